@@ -1,0 +1,167 @@
+"""Analytic bispectrum shot noise (section "Bispectrum Shot Noise from
+Triangle-Constrained Spherical-Harmonic Integrals": Lemma 2 / eq. lemma2 and
+eq. g_ell, the Scoccimarro, Sugiyama (eqs. Q_ell, H_ell, sugi_shot) and
+new-estimator shot-noise results; appendix on the derivation of g_l).
+
+g_l(t) = 1/(2t) int_{|t-1|}^{t+1} x L_l((x^2 + t^2 - 1)/(2 x t)) dx   (practical form)
+evaluated with a 64-point Gauss-Legendre rule; the closed forms of
+eq. g_first_five are kept as an independent cross-check.
+
+Shell averages used by every shot-noise term (even l, Re parts):
+    s_l(k) = < sum_m y_l^m(qhat) Sbar_l^m C(q) / W(q)^2 >_k
+    Q_l(k) = < Re F_l(q) N(q)* >_k - s_l(k)       (eq. Q_ell; N = F_0 of the N mesh)
+    H_l(k) = < Re F_0(q) F_l^N(q)* >_k - s_l(k)   (eq. H_ell; F_l^N = F_l of the N mesh)
+
+Readings where the paper defers or is garbled:
+* C(q): alias sum of the squared window, C = prod_i c(q_i) without interlacing,
+  C = 1/2 [prod_i c(q_i) + prod_i c~(q_i)] with interlacing, where
+  c = sum_n W1^2(q + 2 k_N n), c~ = sum_n (-1)^n W1^2(q + 2 k_N n), |n| <= 64.
+* Scoccimarro (l-leg i, other legs j, k; four coincidence cases, with the
+  ring average of eq. I_l0l giving the Legendre factors):
+  N^(l) = (2l+1)/I33 [Q_l(k_i) + L_l(mu_ij) H_l(k_j) + L_l(mu_ik) H_l(k_k) + delta_l0 Sbar]
+  with mu from bin centres, mu_ij = (k_k^2 - k_i^2 - k_j^2)/(2 k_i k_j), clipped.
+* New estimator, B_l0l(k_i, k_j), t = k_i / k_j at bin centres:
+  N_l0l = 1/I33 { delta_l0 Sbar + (-1)^l (2l+1) [g_l(t) H_l(k_i) + g_l(1/t) H_l(k_j)]
+                  + (2l+1) sum_c N_c Q_l(k_c)/k_c / sum_c N_c/k_c },
+  c running over bins |i-j| .. i+j; the i=j=k term carries 1/I33.
+"""
+
+from __future__ import annotations
+
+import math
+
+import numpy as np
+from numpy.polynomial.legendre import leggauss
+
+from .mesh import freq_index
+from .spectra import Bins, kvectors
+from .ylm import legendre, ylm_racah
+
+_GL_NODES, _GL_WEIGHTS = leggauss(64)
+
+
+def g_ell(ell: int, t: float) -> float:
+    """g_l(t) from the practical integral form (64-point Gauss-Legendre)."""
+    if t == 0.0:
+        return 1.0 if ell == 0 else 0.0
+    a, b = abs(t - 1.0), t + 1.0
+    x = 0.5 * (b - a) * _GL_NODES + 0.5 * (b + a)
+    arg = np.clip((x * x + t * t - 1.0) / (2.0 * x * t), -1.0, 1.0)
+    return float(0.5 * (b - a) * np.sum(_GL_WEIGHTS * x * legendre(ell, arg)) / (2.0 * t))
+
+
+def g_ell_closed(ell: int, t: float) -> float:
+    """Closed forms of eq. g_first_five (l = 0..4)."""
+    if ell == 0:
+        return 1.0
+    if ell == 1:
+        return 2.0 * t / 3.0 if t < 1.0 else 1.0 - 1.0 / (3.0 * t * t)
+    if ell == 2:
+        if t == 0.0:
+            return 0.0
+        if t == 1.0:
+            return 0.25
+        lg = math.log((t + 1.0) / abs(t - 1.0))
+        return (2.0 * t * (5.0 * t * t - 3.0) + 3.0 * (t * t - 1.0) ** 2 * lg) / (16.0 * t ** 3)
+    if ell == 3:
+        return 0.0 if t < 1.0 else (t * t - 1.0) ** 2 / t ** 4
+    if ell == 4:
+        if t == 0.0:
+            return 0.0
+        if t == 1.0:
+            return -1.0 / 24.0
+        lg = math.log((t + 1.0) / abs(t - 1.0))
+        return (2.0 * t * (81.0 * t ** 4 - 190.0 * t * t + 105.0)
+                + 15.0 * (t * t - 7.0) * (t * t - 1.0) ** 2 * lg) / (192.0 * t ** 5)
+    raise ValueError("closed forms exist for l <= 4")
+
+
+_KAPPA_RULE = {}
+
+
+def g_ell_kappa(ell: int, t: float, npts: int = 2000) -> float:
+    """g_l(t) from the kappa-integral form of eq. g_ell (independent quadrature)."""
+    if npts not in _KAPPA_RULE:
+        _KAPPA_RULE[npts] = leggauss(npts)
+    nodes, weights = _KAPPA_RULE[npts]
+
+    def integrand(k):
+        c = np.cos(k)
+        val = np.sqrt(np.clip((c * c + t * t + 2 * t * c) / (1 + t * t + 2 * t * c), 0.0, 1.0))
+        return 0.5 * np.sin(k) * legendre(ell, val)
+
+    def quad(a, b):
+        if b <= a:
+            return 0.0
+        k = 0.5 * (b - a) * nodes + 0.5 * (b + a)
+        return 0.5 * (b - a) * float(np.sum(weights * integrand(k)))
+
+    if t > 1.0:
+        return quad(0.0, math.pi)
+    k0 = math.acos(-t)
+    return quad(0.0, k0) + (-1) ** ell * quad(k0, math.pi)
+
+
+def alias_tables(nmesh: int, scheme: int, images: int = 64):
+    """(c, c~) per FFT-ordered index, FP64 image sums of W1^2 = sinc^(2p)."""
+    n = freq_index(nmesh).astype(np.float64)
+    c = np.zeros(nmesh)
+    ct = np.zeros(nmesh)
+    for j in range(-images, images + 1):
+        s = np.sinc(n / nmesh + j) ** (2 * scheme)
+        c += s
+        ct += (-1) ** (j & 1) * s
+    return c, ct
+
+
+def c_shot(nmesh: int, scheme: int, interlace: bool) -> np.ndarray:
+    c, ct = alias_tables(nmesh, scheme)
+    full = c[:, None, None] * c[None, :, None] * c[None, None, :]
+    if not interlace:
+        return full
+    return 0.5 * (full + ct[:, None, None] * ct[None, :, None] * ct[None, None, :])
+
+
+def self_term(ell: int, Sbar_lm, bins: Bins, W: np.ndarray, C: np.ndarray) -> np.ndarray:
+    """s_l(k): shell mean of sum_m y_l^m(qhat) Sbar_l^m C / W^2 (real part)."""
+    kvec = kvectors(bins.nmesh, bins.boxsize)
+    acc = np.zeros(W.shape, dtype=np.complex128)
+    for m in range(-ell, ell + 1):
+        acc += ylm_racah(ell, m, kvec) * Sbar_lm[(ell, m)]
+    return bins.shell_mean(np.real(acc) * C / (W * W))
+
+
+def scoccimarro_shot(ell, configs, Q, H, centres, I33, Sbar):
+    """N^(l)(i; j, k) per configuration (see module docstring).
+
+    l = 0 is pinned statistically (Poisson catalogs); l > 0: parity unpinned
+    beyond its ingredients."""
+    out = np.empty(len(configs))
+    for t, (i, j, k) in enumerate(configs):
+        ki, kj, kk = centres[i], centres[j], centres[k]
+        mu_ij = np.clip((kk * kk - ki * ki - kj * kj) / (2 * ki * kj), -1.0, 1.0)
+        mu_ik = np.clip((kj * kj - ki * ki - kk * kk) / (2 * ki * kk), -1.0, 1.0)
+        val = Q[i] + legendre(ell, mu_ij) * H[j] + legendre(ell, mu_ik) * H[k]
+        if ell == 0:
+            val += Sbar
+        out[t] = (2 * ell + 1) / I33 * val
+    return out
+
+
+def triposh_shot(ell, pairs, Q_ext, H, counts_ext, centres_ext, I33, Sbar):
+    """N_l0l(k_i, k_j) per pair (i <= j); Q_ext etc. extend to bin 2 nbins - 2.
+
+    l = 0 is pinned statistically (Poisson catalogs); l > 0: parity unpinned
+    beyond its ingredients."""
+    out = np.empty(len(pairs))
+    sign = -1.0 if ell % 2 else 1.0
+    for t, (i, j) in enumerate(pairs):
+        tt = centres_ext[i] / centres_ext[j]
+        term = sign * (2 * ell + 1) * (g_ell(ell, tt) * H[i] + g_ell(ell, 1.0 / tt) * H[j])
+        cs = np.arange(abs(i - j), i + j + 1)
+        wgt = counts_ext[cs] / centres_ext[cs]
+        term += (2 * ell + 1) * float(np.sum(wgt * Q_ext[cs]) / np.sum(wgt))
+        if ell == 0:
+            term += Sbar
+        out[t] = term / I33
+    return out
