@@ -1,0 +1,275 @@
+/*
+ * cnpc.h -- C ABI of the MI355X (gfx950) FFT clustering-estimator library.
+ *
+ * Computes the Yamamoto power-spectrum multipoles, the modified high-order
+ * multipoles, the Scoccimarro bispectrum multipoles and the compressed TripoSH
+ * bispectrum B_l0l with analytic shot noise, following "Efficient estimators
+ * for power spectrum and bispectrum multipole measurements" (Xie et al.).
+ * Section and equation names below refer to that paper.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - All data pointers are DEVICE pointers unless a parameter says "host".
+ *    The caller owns every buffer; no call allocates device memory.  Scratch
+ *    space is passed in as `ws` / `ws_bytes`, sized by the matching
+ *    *_workspace_size query.
+ *  - Every call is asynchronous on `stream` (a hipStream_t, NULL = default
+ *    stream).  Outputs are valid once the stream has synchronised.
+ *  - Return value: CNPC_OK (0) or a negative status.  Arguments are validated
+ *    on the host before anything is launched; on error nothing is launched and
+ *    cnpc_last_error() (thread-local) describes the problem.
+ *  - Positions are 3 x uint32 fixed point p = floor(x / L * 2^32), stored
+ *    structure-of-arrays: pos[0..n) = x, pos[n..2n) = y, pos[2n..3n) = z.
+ *  - Weights w are FP32 (NULL means w = 1 for every particle).
+ *  - Real meshes are N^3 values, index (ix * N + iy) * N + iz, node j at x = jH
+ *    (H = L/N).  With interlacing a second mesh B (nodes at (j + 1/2) H)
+ *    follows mesh A contiguously.
+ *  - Full half spectra ("half layout") hold N * N * (N/2) complex values
+ *    (re, im interleaved), index (ix * N + iy) * (N/2) + kz, kz = 0..N/2-1.
+ *    The kz = N/2 plane is not stored: every estimator zeroes modes with a
+ *    Nyquist component.  Wavenumber index n = i for i < N/2, i - N otherwise.
+ *  - Band spectra ("band layout", band half-width M, a power of two <= N/2)
+ *    hold only modes with |nx|, |ny| < M and 0 <= nz < M:
+ *    (2M) * (2M) * M complex values, index (jx * 2M + jy) * M + kz with
+ *    n = j for j < M and j - 2M otherwise.  Every binned mode lies in the band
+ *    when M > k_max / k_f (k_f = 2 pi / L); cnpc_band_for() returns the
+ *    smallest such M.
+ *  - Element type follows desc->dtype: float / float2 (CNPC_F32) or
+ *    double / double2 (CNPC_F64).  Shell accumulators, catalog sums,
+ *    normalisations and shot-noise terms are always FP64.
+ *  - Forward transforms use exp(-i k.x) (the sign of eq. key1); inverse
+ *    transforms use exp(+i k.x) and are unnormalised.
+ */
+#ifndef CNPC_H
+#define CNPC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t cnpc_status;
+#define CNPC_OK 0
+#define CNPC_EINVAL (-1)       /* invalid argument (null pointer, bad size, ...) */
+#define CNPC_EWORKSPACE (-2)   /* workspace smaller than the query returned */
+#define CNPC_EHIP (-3)         /* a HIP runtime call failed */
+#define CNPC_EUNSUPPORTED (-4) /* valid but not supported (e.g. N > 1024) */
+
+#define CNPC_F32 0
+#define CNPC_F64 1
+#define CNPC_CIC 2
+#define CNPC_TSC 3
+#define CNPC_LOS_LOCAL 0  /* xhat = unit vector from the observer to the node */
+#define CNPC_LOS_GLOBAL 1 /* xhat = desc->los for every node */
+
+/* Mesh / catalog geometry.  n: power of two in [16, 1024].  observer: used
+ * with CNPC_LOS_LOCAL; must lie outside the box.  los: unit vector used with
+ * CNPC_LOS_GLOBAL. */
+typedef struct {
+  int32_t n;
+  int32_t assign;    /* CNPC_CIC or CNPC_TSC */
+  int32_t interlace; /* 0 or 1 */
+  int32_t dtype;     /* CNPC_F32 or CNPC_F64 */
+  int32_t los_mode;  /* CNPC_LOS_LOCAL or CNPC_LOS_GLOBAL */
+  int32_t reserved;
+  double boxsize; /* L */
+  double observer[3];
+  double los[3];
+} cnpc_mesh_desc;
+
+/* k bins: half-open [kmin + b dk, kmin + (b+1) dk), b = 0..nbins-1.  Mode
+ * membership is decided on the integer |n|^2 with thresholds
+ * T_b = ceil(((kmin + b dk) / k_f)^2) computed in FP64 (this reading of the
+ * binning mask of the Sugiyama section is documented in the design notes).
+ * The k = 0 mode and modes with a Nyquist component are excluded.  The top
+ * edge must not exceed the Nyquist wavenumber. */
+typedef struct {
+  double kmin;
+  double dk;
+  int32_t nbins;
+  int32_t reserved;
+} cnpc_kbins;
+
+/* ---- catalog sums (sections on the Yamamoto and Scoccimarro estimators) ----
+ * Per catalog FP64 sums: [0] sum w, [1] sum w^2, [2] sum w^3, then for
+ * (l, m) in (0,0),(2,0),(2,1),(2,2),(4,0),...,(4,4): re, im of
+ * sum w^3 y_l^m*(xhat) (Racah-normalised harmonics, xhat from the observer to
+ * the particle, or desc->los).  CNPC_SUMS_LEN doubles. */
+#define CNPC_NYLM_SUMS 9
+#define CNPC_SUMS_LEN (3 + 2 * CNPC_NYLM_SUMS)
+size_t cnpc_catalog_sums_workspace_size(void);
+cnpc_status cnpc_catalog_sums(const cnpc_mesh_desc* desc, const uint32_t* pos, const float* w,
+                              int64_t n, double* sums, void* ws, size_t ws_bytes, void* stream);
+
+/* Normalisations from the galaxy and random sums (under eq. Hand17 and
+ * eq. bi_sco; the Sbar terms of eq. Q_ell): CNPC_NORMS_LEN doubles
+ *   [0] alpha = sum_g w / sum_r w      [1] nbar = ngal / L^3
+ *   [2] I22 = alpha nbar sum_r w^2     [3] I33 = alpha nbar^2 sum_r w^3
+ *   [4] N0 = (sum_g w^2 + alpha^2 sum_r w^2) / I22
+ *   [5] Sbar = sum_g w^3 - alpha^3 sum_r w^3
+ *   [6 + 2q], [7 + 2q]: re, im of Sbar_l^m for the q-th (l, m) listed above
+ * Computed on the device (no host synchronisation). */
+#define CNPC_NORM_ALPHA 0
+#define CNPC_NORM_NBAR 1
+#define CNPC_NORM_I22 2
+#define CNPC_NORM_I33 3
+#define CNPC_NORM_N0 4
+#define CNPC_NORM_SBAR 5
+#define CNPC_NORM_SBARLM 6
+#define CNPC_NORMS_LEN (6 + 2 * CNPC_NYLM_SUMS)
+cnpc_status cnpc_norms(const cnpc_mesh_desc* desc, const double* gal_sums, const double* ran_sums,
+                       int64_t ngal, double* norms, void* stream);
+
+/* ---- paint: mass assignment of the FKP field (section on modified high-order
+ * multipoles, TSC assignment) ----
+ * delta = n_g - alpha n_r (weights w) and, when noise != NULL, the shot-noise
+ * mesh N = n_g(w^2) + alpha^2 n_r(w^2) (definition of N_l^m under
+ * eq. generic_noise).  alpha is read from norms[CNPC_NORM_ALPHA] on the device.
+ * CIC: nodes floor(u), floor(u)+1; TSC: nodes floor(u+1/2)+{-1,0,1}, with
+ * u = p N / 2^32 (mesh B: u - 1/2).  Outputs are overwritten (not accumulated):
+ * delta and noise each hold (1 + interlace) N^3 elements of desc->dtype.
+ * Particles are bucketed by 16^3-node tiles and accumulated in LDS; sums inside
+ * a tile are order dependent at FP32 rounding. */
+size_t cnpc_paint_workspace_size(const cnpc_mesh_desc* desc, int64_t ngal, int64_t nran);
+cnpc_status cnpc_paint(const cnpc_mesh_desc* desc, const uint32_t* gpos, const float* gw,
+                       int64_t ngal, const uint32_t* rpos, const float* rw, int64_t nran,
+                       const double* norms, void* delta, void* noise, void* ws, size_t ws_bytes,
+                       void* stream);
+
+/* ---- fft: batched 3-D real transforms (all hot-path transforms) ----
+ * Full r2c: `batch` real meshes -> half-layout spectra.  Full c2r: half-layout
+ * spectra (kz = N/2 plane taken as zero) -> real meshes.  Band r2c: real
+ * meshes -> band-layout spectra (half-width M); band c2r: band spectra (modes
+ * outside the band taken as zero) -> real meshes.  in and out must not
+ * overlap; out of a c2r may alias nothing else.  Scratch: ws of
+ * cnpc_fft_workspace_size bytes. */
+size_t cnpc_fft_workspace_size(const cnpc_mesh_desc* desc, int32_t batch, int32_t band);
+cnpc_status cnpc_fft_r2c(const cnpc_mesh_desc* desc, int32_t batch, int32_t band, const void* in,
+                         void* out, void* ws, size_t ws_bytes, void* stream);
+cnpc_status cnpc_fft_c2r(const cnpc_mesh_desc* desc, int32_t batch, int32_t band, const void* in,
+                         void* out, void* ws, size_t ws_bytes, void* stream);
+int32_t cnpc_band_for(const cnpc_mesh_desc* desc, double kmax);
+
+/* ---- interlacing and de-aliasing (design reading; not in the paper) ----
+ * From the painted meshes A (and B): D(k) = 1/2 [D_A(k) + exp(-i k.(1,1,1)H/2) D_B(k)]
+ * with every Nyquist-component mode zeroed (without interlacing D = D_A).
+ * Writes D in band layout (half-width `band`) to spec_band and, when
+ * delta_int != NULL, the de-aliased real mesh IDFT(D) / N^3 (without
+ * interlacing: a copy of A). */
+size_t cnpc_deinterlace_workspace_size(const cnpc_mesh_desc* desc);
+cnpc_status cnpc_deinterlace(const cnpc_mesh_desc* desc, int32_t band, const void* meshes,
+                             void* spec_band, void* delta_int, void* ws, size_t ws_bytes,
+                             void* stream);
+
+/* ---- ylm_fields: Y_lm-weighted real fields (eq. key1, eq. hand, eq. F_lm_SIC) ----
+ * Materialised form: out = (2l+1) real meshes delta(x) * [Re y_l^0, Re y_l^1,
+ * Im y_l^1, ..., Re y_l^l, Im y_l^l](xhat) (Racah-normalised, m >= 0 only; the
+ * m < 0 fields follow from the conjugation symmetry).  l in 0..4. */
+cnpc_status cnpc_ylm_fields(const cnpc_mesh_desc* desc, int32_t ell, const void* delta, void* out,
+                            void* stream);
+/* Fused form: the same fields for every l in ells[0..nells) (host array,
+ * each l in {1,2,3,4}) transformed straight to band spectra without being
+ * materialised: out holds sum(2l+1) band spectra in that order. */
+size_t cnpc_ylm_r2c_workspace_size(const cnpc_mesh_desc* desc, int32_t nfields, int32_t band);
+cnpc_status cnpc_ylm_r2c(const cnpc_mesh_desc* desc, int32_t band, int32_t nells,
+                         const int32_t* ells, const void* delta, void* out, void* ws,
+                         size_t ws_bytes, void* stream);
+
+/* ---- F_l assembly (eq. hand with eq. F_lm_SIC on the r2c half spectrum) ----
+ * F_l(k) = [c_0 A_0 + 2 sum_{m>=1} (c_m A_m + s_m B_m)](k) / W(k), with
+ * c_m + i s_m = y_l^m(khat), A_m, B_m the band spectra of the Re / Im fields,
+ * W(k) = prod_i sinc(pi n_i / N)^p (eq. compensation), F_l(0) = 0.
+ * l = 0: F_0 = D / W from the de-interlaced spectrum alone (ylm may be NULL).
+ * Output: one band spectrum. */
+cnpc_status cnpc_assemble_F(const cnpc_mesh_desc* desc, int32_t band, int32_t ell,
+                            const void* spec0, const void* ylm, void* F_out, void* stream);
+
+/* ---- bin_pk: shell means (eqs. Hand17, pk_final, Pllp; eqs. Q_ell, H_ell) ----
+ * For each of npairs products (a, b) (host arrays pa, pb of band-spectrum
+ * pointers, device), accumulates in FP64 over the modes of every bin
+ *   sum Re F_a(k) F_b(k)^*        (Hermitian half-grid weights 1 / 2)
+ * and, per bin, N_mode (int64, exact) and sum |k|.  With self_ells != NULL
+ * (host, nself entries), also the shell mean of the self-pair term
+ *   s_l(k) = < sum_m y_l^m(khat) Sbar_l^m C(k) / W(k)^2 >
+ * where C is the alias sum of the squared window (interlaced: half the sum of
+ * the plain and the alternating image sums), reading Sbar_l^m from norms.
+ * Output (device, FP64): means[npairs][nbins] = shell means, selfterm[nself][nbins],
+ * nmodes[nbins], keff[nbins] (mean |k|).  No normalisation is applied here.
+ * Limits: nbins <= 128, npairs <= 16, nself <= 4 with self_ells in {0, 2, 4}.
+ * pa, pb, self_ells are host arrays; the spectra they point to are device
+ * band spectra (half-width `band`). */
+size_t cnpc_bin_pk_workspace_size(const cnpc_kbins* bins, int32_t npairs, int32_t nself);
+cnpc_status cnpc_bin_pk(const cnpc_mesh_desc* desc, const cnpc_kbins* bins, int32_t band,
+                        int32_t npairs, const void* const* pa, const void* const* pb,
+                        int32_t nself, const int32_t* self_ells, const double* norms,
+                        double* means, double* selfterm, int64_t* nmodes, double* keff,
+                        void* ws, size_t ws_bytes, void* stream);
+
+/* Yamamoto multipoles from the shell means (eq. Hand17 / eq. Pllp / eq. Plnew):
+ * P_l = (2l+1)/I22 <Re F_0 F_l*> - delta_l0 N0, P_ll' = (2(l+l')+1)/I22
+ * <Re F_l F_l'*> - N_ll' (N_22 = 9 N0/5, N_44 = 17 N0/9, N_42 = 0), and
+ * P_4b, P_6b, P_8b.  means_* are the bin_pk outputs for the listed products
+ * (NULL when not wanted).  out: [P0, P2, P4, P22, P42, P44, P4b, P6b, P8b][nbins]. */
+cnpc_status cnpc_pk_finalize(const cnpc_kbins* bins, const double* mean00, const double* mean02,
+                             const double* mean04, const double* mean22, const double* mean42,
+                             const double* mean44, const double* norms, double* out, void* stream);
+
+/* ---- bispectrum (eq. bi_sco; eq. new_bispec for B_l0l) ----
+ * Shell fields X_i^(l)(x) = sum_{q in bin i} F_l(q) exp(i q.x) by band c2r,
+ * G_l = sum_{all q} F_l(q) exp(i q.x), then the grid contraction
+ *   C[(a,b), c] = sum_x X_a^(0) X_b^(0) Y_c,  a <= b,
+ * with columns Y = [X^(0) shells, X^(l) shells (Scoccimarro, l > 0), G_l
+ * (TripoSH)], cast as a GEMM over grid points.  Then
+ *   B_l(i; j, k)   = (2l+1)/I33 C / (N^3 N_T) - N^(l)        (Scoccimarro)
+ *   BB_l0l(i, j)   = (2l+1)/I33 C / (N^3 N_i N_j) - N_l0l    (TripoSH)
+ * with the analytic shot noise of the shot-noise section (Lemma 1 special
+ * case eq. I_l0l, Lemma 2 / eq. g_ell, eqs. Q_ell, H_ell).  Configurations:
+ * Scoccimarro l = 0: i <= j <= k; l > 0: any i, j <= k; all closed
+ * (largest index <= sum of the other two) with N_T > 0; TripoSH: i <= j.
+ * precision: CNPC_PREC_F64 / CNPC_PREC_F32 (VALU contraction in the field
+ * type) or CNPC_PREC_BF16X3 (split-BF16 hi+lo MFMA, FP32 accumulation inside a
+ * tile, FP64 across tiles; FP32 fields only).
+ * See cnpc_bispec_plan for the host-side configuration tables. */
+#define CNPC_PREC_F64 0
+#define CNPC_PREC_F32 1
+#define CNPC_PREC_BF16X3 2
+#define CNPC_EST_SCOCCIMARRO 0
+#define CNPC_EST_TRIPOSH 1
+
+typedef struct cnpc_bispec_plan cnpc_bispec_plan;
+/* Creates the plan (host tables: configurations, triangle counts N_T computed
+ * once in FP64 from shell indicator fields on the device, g_l(t) by FP64
+ * Gauss-Legendre, alias sums).  Synchronises `stream`.  ws: scratch of
+ * cnpc_bispec_workspace_size bytes for the N_T computation and later calls. */
+cnpc_status cnpc_bispec_plan_create(cnpc_bispec_plan** plan, const cnpc_mesh_desc* desc,
+                                    const cnpc_kbins* bins, int32_t estimator, int32_t ell,
+                                    int32_t precision, void* ws, size_t ws_bytes, void* stream);
+void cnpc_bispec_plan_destroy(cnpc_bispec_plan* plan);
+int32_t cnpc_bispec_nconfigs(const cnpc_bispec_plan* plan);
+/* Host copy of the configurations (3 ints each: i, j, k; TripoSH k = -1) and N_T. */
+cnpc_status cnpc_bispec_configs(const cnpc_bispec_plan* plan, int32_t* ijk, int64_t* ntri);
+size_t cnpc_bispec_workspace_size(const cnpc_mesh_desc* desc, const cnpc_kbins* bins,
+                                  int32_t estimator, int32_t ell);
+/* F0, Fl: band spectra (half-width cnpc_bispec_band) of F_0 and F_l.
+ * noise_means: device FP64 [4][nbins_ext] rows (Q_l, H_l raw shell means
+ * <Re F_l N*>, <Re F_0 F_l^N*> and the self term s_l, then N_mode of the
+ * extended binning) from cnpc_bin_pk on the extended binning of
+ * cnpc_bispec_ext_bins (NULL: no shot noise).  Outputs (device FP64, one value
+ * per configuration): raw estimator, shot noise, shot-subtracted estimator. */
+int32_t cnpc_bispec_band(const cnpc_bispec_plan* plan);
+cnpc_status cnpc_bispec_ext_bins(const cnpc_bispec_plan* plan, cnpc_kbins* ext);
+cnpc_status cnpc_bispectrum(const cnpc_bispec_plan* plan, const void* F0, const void* Fl,
+                            const double* noise_means, const double* norms, double* raw,
+                            double* shot, double* value, void* ws, size_t ws_bytes, void* stream);
+
+/* Last error message of the calling thread ("" when none). */
+const char* cnpc_last_error(void);
+/* Library version string. */
+const char* cnpc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CNPC_H */

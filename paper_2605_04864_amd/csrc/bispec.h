@@ -1,0 +1,58 @@
+// Host-side pieces of the bispectrum: plan, shell c2r, contraction, finalize.
+#pragma once
+
+#include <vector>
+
+#include "spectra.h"
+
+namespace cnpc {
+
+constexpr int MAX_COLS = 40;
+
+struct ContractCols {
+  int ncols;
+  int field[MAX_COLS];  // field index of each column
+};
+
+struct FinArgs {
+  int est, ell, nb, next, ncols, nconf;
+  double n3;
+  const int* cfg;
+  const int64_t* ntri;
+  const double* aux;     // per config: L(mu_ij), L(mu_ik) (Scoccimarro) or g(t), g(1/t)
+  const double* counts;  // N_mode per shell
+  const double* wq;      // N_c / k_c per extended bin
+};
+
+double g_ell_host(int l, double t);
+size_t bispec_ws_bytes(const cnpc_mesh_desc* d, int nb, int band, int nfields, int ncols);
+template <typename T>
+cnpc_status contract_valu(const T* fields, int64_t npts, int nf, int nshell, const ContractCols& cc,
+                          double* partial, double* out, hipStream_t s);
+
+}  // namespace cnpc
+
+struct cnpc_bispec_plan {
+  cnpc_mesh_desc desc;
+  cnpc_kbins bins, ext;
+  int est, ell, prec;
+  int nb, next, band, nfields, nconf;
+  cnpc::ContractCols cc;
+  std::vector<int64_t> thr, counts, counts_ext, ntri;
+  std::vector<int> cfg;
+  std::vector<double> aux, wq;
+  int* d_cfg = nullptr;
+  int64_t* d_ntri = nullptr;
+  double* d_aux = nullptr;
+  double* d_counts = nullptr;
+  double* d_wq = nullptr;
+};
+
+namespace cnpc {
+cnpc_status bispec_plan_create(cnpc_bispec_plan** out, const cnpc_mesh_desc* d, const cnpc_kbins* b,
+                               int est, int ell, int prec, void* ws, size_t ws_bytes, hipStream_t s);
+void bispec_plan_destroy(cnpc_bispec_plan* P);
+cnpc_status bispec_run(const cnpc_bispec_plan* P, const void* F0, const void* Fl,
+                       const double* noise, const double* norms, double* raw, double* shot,
+                       double* value, void* ws, size_t ws_bytes, hipStream_t s);
+}  // namespace cnpc

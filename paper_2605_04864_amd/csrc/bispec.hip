@@ -1,0 +1,523 @@
+// Bispectrum: shell-filtered band c2r, grid contraction C[(a,b),c] = sum_x X_a X_b Y_c,
+// normalisation and analytic shot noise (Scoccimarro B_l and TripoSH B_l0l).
+#include <cmath>
+#include <vector>
+
+#include "bispec.h"
+
+namespace cnpc {
+
+// ------------------------------------------------------------ host maths --
+static double legendre_host(int l, double x) {
+  if (l == 0) return 1.0;
+  double p0 = 1.0, p1 = x;
+  for (int k = 2; k <= l; ++k) {
+    const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+    p0 = p1;
+    p1 = p2;
+  }
+  return p1;
+}
+
+// Gauss-Legendre nodes / weights on [-1, 1] by Newton iteration on P_n
+static void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.resize(n);
+  w.resize(n);
+  for (int i = 0; i < n; ++i) {
+    double z = cos(M_PI * (i + 0.75) / (n + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      const double dp = n * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (fabs(dz) < 1e-16) break;
+    }
+    double p0 = 1.0, p1 = z;
+    for (int k = 2; k <= n; ++k) {
+      const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    const double dp = n * (z * p1 - p0) / (z * z - 1.0);
+    x[i] = z;
+    w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+// g_l(t) of Lemma 2 from the integral over x in [|t-1|, t+1] of
+// x L_l((x^2 + t^2 - 1)/(2 x t)) / (2t), 64-point Gauss-Legendre.
+double g_ell_host(int l, double t) {
+  if (t == 0.0) return l == 0 ? 1.0 : 0.0;
+  static std::vector<double> gx, gw;
+  if (gx.empty()) gauss_legendre(64, gx, gw);
+  const double a = fabs(t - 1.0), b = t + 1.0;
+  double s = 0.0;
+  for (size_t i = 0; i < gx.size(); ++i) {
+    const double x = 0.5 * (b - a) * gx[i] + 0.5 * (b + a);
+    double c = (x * x + t * t - 1.0) / (2.0 * x * t);
+    c = c > 1.0 ? 1.0 : (c < -1.0 ? -1.0 : c);
+    s += gw[i] * x * legendre_host(l, c);
+  }
+  return 0.5 * (b - a) * s / (2.0 * t);
+}
+
+// exact mode counts per bin over the band (host integer loop)
+static std::vector<int64_t> mode_counts(const cnpc_mesh_desc* d, const std::vector<int64_t>& thr,
+                                        int nb) {
+  std::vector<int64_t> c(nb, 0);
+  const int n = d->n, h = n / 2;
+  const int64_t tmax = thr[nb];
+  int r = 0;
+  while ((int64_t)r * r < tmax) ++r;
+  for (int nx = -r; nx <= r; ++nx)
+    for (int ny = -r; ny <= r; ++ny)
+      for (int nz = -r; nz <= r; ++nz) {
+        if (nx <= -h || nx >= h || ny <= -h || ny >= h || nz <= -h || nz >= h) continue;
+        const int64_t n2 = (int64_t)nx * nx + (int64_t)ny * ny + (int64_t)nz * nz;
+        if (n2 == 0 || n2 < thr[0] || n2 >= tmax) continue;
+        int b = 0;
+        while (b + 1 <= nb && n2 >= thr[b + 1]) ++b;
+        c[b]++;
+      }
+  return c;
+}
+
+static bool closed(int i, int j, int k) {
+  int a = i, b = j, c = k;
+  if (a > b) std::swap(a, b);
+  if (b > c) std::swap(b, c);
+  if (a > b) std::swap(a, b);
+  return c <= a + b;
+}
+
+static inline int pair_index(int a, int b, int nb) {  // a <= b
+  return a * nb - a * (a - 1) / 2 + (b - a);
+}
+
+// ---------------------------------------------------------- contraction --
+template <typename T>
+__global__ void __launch_bounds__(256) k_contract(const T* __restrict__ fields, int64_t npts, int nf,
+                                                  int nshell, int npairs, int p0, ContractCols cc,
+                                                  double* __restrict__ partial) {
+  constexpr int KT = 128;  // points per LDS tile
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* tile = reinterpret_cast<T*>(smem_raw);  // [nf][KT]
+  const int p = p0 + threadIdx.x;
+  int fa = 0, fb = 0;
+  if (p < npairs) {  // decode pair index -> (a, b), a <= b
+    int a = 0, rem = p;
+    while (rem >= nshell - a) { rem -= nshell - a; ++a; }
+    fa = a;
+    fb = a + rem;
+  }
+  double tot[MAX_COLS];
+  T acc[MAX_COLS];
+#pragma unroll
+  for (int c = 0; c < MAX_COLS; ++c) { tot[c] = 0.0; acc[c] = T(0); }
+  const int64_t per_block = (npts + gridDim.x - 1) / gridDim.x;
+  const int64_t x0 = (int64_t)blockIdx.x * per_block;
+  const int64_t x1 = min(npts, x0 + per_block);
+  int tiles_since_flush = 0;
+  for (int64_t xb = x0; xb < x1; xb += KT) {
+    const int kt = (int)min((int64_t)KT, x1 - xb);
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < nf * KT; idx += blockDim.x) {
+      const int f = idx / KT, k = idx - f * KT;
+      tile[idx] = k < kt ? fields[(int64_t)f * npts + xb + k] : T(0);
+    }
+    __syncthreads();
+    if (p < npairs) {
+      const T* ta = tile + fa * KT;
+      const T* tb = tile + fb * KT;
+      for (int k = 0; k < KT; ++k) {
+        const T av = ta[k] * tb[k];
+#pragma unroll
+        for (int c = 0; c < MAX_COLS; ++c)
+          if (c < cc.ncols) acc[c] += av * tile[cc.field[c] * KT + k];
+      }
+    }
+    if (++tiles_since_flush == 16) {  // FP32 inside 2048 points, FP64 across
+#pragma unroll
+      for (int c = 0; c < MAX_COLS; ++c) { tot[c] += (double)acc[c]; acc[c] = T(0); }
+      tiles_since_flush = 0;
+    }
+  }
+  if (p < npairs) {
+    double* out = partial + ((int64_t)blockIdx.x * npairs + p) * cc.ncols;
+#pragma unroll
+    for (int c = 0; c < MAX_COLS; ++c)
+      if (c < cc.ncols) out[c] = tot[c] + (double)acc[c];
+  }
+}
+
+__global__ void k_reduce_blocks(const double* __restrict__ partial, int nblocks, int64_t len,
+                                double* __restrict__ out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < len;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int b = 0; b < nblocks; ++b) s += partial[(int64_t)b * len + i];
+    out[i] = s;
+  }
+}
+
+constexpr int CONTRACT_BLOCKS = 512;
+
+template <typename T>
+cnpc_status contract_valu(const T* fields, int64_t npts, int nf, int nshell, const ContractCols& cc,
+                          double* partial, double* out, hipStream_t s) {
+  const int npairs = nshell * (nshell + 1) / 2;
+  const size_t lds = (size_t)nf * 128 * sizeof(T);
+  if (lds > lds_limit()) {
+    set_error("too many fields for the contraction tile (%d)", nf);
+    return CNPC_EUNSUPPORTED;
+  }
+  for (int p0 = 0; p0 < npairs; p0 += 256) {
+    // each launch covers 256 pairs; partials of all launches share the layout
+    hipLaunchKernelGGL((k_contract<T>), dim3(CONTRACT_BLOCKS), dim3(256), lds, s, fields, npts, nf,
+                       nshell, npairs, p0, cc, partial);
+    CNPC_HIP(hipGetLastError());
+  }
+  const int64_t len = (int64_t)npairs * cc.ncols;
+  const unsigned g = (unsigned)std::min<int64_t>((len + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_reduce_blocks, dim3(g), dim3(256), 0, s, partial, CONTRACT_BLOCKS, len, out);
+  CNPC_HIP(hipGetLastError());
+  return CNPC_OK;
+}
+
+size_t contract_partial_doubles(int nshell, int ncols) {
+  return (size_t)CONTRACT_BLOCKS * nshell * (nshell + 1) / 2 * ncols;
+}
+
+// --------------------------------------------------- shell-filtered c2r --
+// X_b = c2r[Phi_b F] for the shells b0..b0+nsh-1 (mask != 0), or G = c2r[F]
+// (mask == 0, nsh = 1).  F: band spectrum (half-width m).
+template <typename T>
+cnpc_status shell_c2r(const cnpc_mesh_desc* d, int m, const cx<T>* F, const int64_t* thr, int nthr,
+                      int b0, int nsh, bool mask, T* out, cx<T>* ws, hipStream_t s) {
+  const int n = d->n, dt = d->dtype;
+  const int64_t nn = (int64_t)n * n;
+  cx<T>* w1 = ws;                            // [nsh][n][n][m]
+  cx<T>* w2 = ws + (int64_t)nsh * nn * m;    // [nsh][n][2m][m]
+  ColArgs ax = make_col(n, dt, 0, (int64_t)n * 2 * m * m, (int64_t)2 * m * m, (int64_t)2 * m * m,
+                        2 * m * m, m, 0);
+  if (mask) {
+    ax.mask_m = m;
+    ax.mask_b0 = b0;
+    for (int i = 0; i < nthr; ++i) ax.thr[i] = thr[i];
+  }
+  CNPC_TRY(colpass<T>(n, 1, F, w2, ax, nsh, s));
+  ColArgs ay = make_col(n, dt, (int64_t)2 * m * m, (int64_t)n * m, m, m, m, m, 0);
+  CNPC_TRY(colpass<T>(n, 1, w2, w1, ay, (int64_t)nsh * n, s));
+  CNPC_TRY(zpass_c2r<T>(n, w1, out, (int64_t)nsh * nn, m, s));
+  return CNPC_OK;
+}
+
+size_t shell_c2r_ws_elems(int n, int m, int nsh) {
+  const size_t nn = (size_t)n * n;
+  return (size_t)nsh * (nn * m + (size_t)n * 2 * m * m);
+}
+
+// ------------------------------------------------------------- finalize --
+__global__ void k_finalize(FinArgs f, const double* __restrict__ C, const double* __restrict__ noise,
+                           const double* __restrict__ nm, double* __restrict__ raw,
+                           double* __restrict__ shot, double* __restrict__ value) {
+  const double I33 = nm[CNPC_NORM_I33], Sbar = nm[CNPC_NORM_SBAR];
+  const double pre = (2.0 * f.ell + 1.0) / I33;
+  const int ne = f.next;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < f.nconf; t += gridDim.x * blockDim.x) {
+    const int i = f.cfg[3 * t], j = f.cfg[3 * t + 1], k = f.cfg[3 * t + 2];
+    double r, sh = 0.0;
+    if (f.est == CNPC_EST_SCOCCIMARRO) {
+      const int p = j * f.nb - j * (j - 1) / 2 + (k - j);
+      const double c = C[(int64_t)p * f.ncols + i];
+      r = pre * c / (f.n3 * (double)f.ntri[t]);
+      if (noise) {
+        const double* Q = noise;
+        const double* H = noise + ne;
+        const double* S = noise + 2 * ne;
+        double v = (Q[i] - S[i]) + f.aux[2 * t] * (H[j] - S[j]) + f.aux[2 * t + 1] * (H[k] - S[k]);
+        if (f.ell == 0) v += Sbar;
+        sh = pre * v;
+      }
+    } else {
+      const int p = i * f.nb - i * (i - 1) / 2 + (j - i);
+      const double c = C[(int64_t)p * f.ncols + 0];
+      r = pre * c / (f.n3 * f.counts[i] * f.counts[j]);
+      if (noise) {
+        const double* Q = noise;
+        const double* H = noise + ne;
+        const double* S = noise + 2 * ne;
+        const double sgn = (f.ell & 1) ? -1.0 : 1.0;
+        double v = sgn * (2.0 * f.ell + 1.0) *
+                   (f.aux[2 * t] * (H[i] - S[i]) + f.aux[2 * t + 1] * (H[j] - S[j]));
+        const int c0 = i > j ? i - j : j - i, c1 = i + j;
+        double num = 0.0, den = 0.0;
+        for (int q = c0; q <= c1; ++q) {
+          num += f.wq[q] * (Q[q] - S[q]);
+          den += f.wq[q];
+        }
+        v += (2.0 * f.ell + 1.0) * num / den;
+        if (f.ell == 0) v += Sbar;
+        sh = v / I33;
+      }
+    }
+    raw[t] = r;
+    shot[t] = sh;
+    value[t] = r - sh;
+  }
+}
+
+// ---------------------------------------------------------------- plan --
+static cnpc_status device_tables(cnpc_bispec_plan* P) {
+  const int nc = P->nconf;
+  CNPC_HIP(hipMalloc(&P->d_cfg, sizeof(int) * 3 * (nc > 0 ? nc : 1)));
+  CNPC_HIP(hipMalloc(&P->d_ntri, sizeof(int64_t) * (nc > 0 ? nc : 1)));
+  CNPC_HIP(hipMalloc(&P->d_aux, sizeof(double) * 2 * (nc > 0 ? nc : 1)));
+  CNPC_HIP(hipMalloc(&P->d_counts, sizeof(double) * (P->nb > 0 ? P->nb : 1)));
+  CNPC_HIP(hipMalloc(&P->d_wq, sizeof(double) * (P->next > 0 ? P->next : 1)));
+  return CNPC_OK;
+}
+
+static cnpc_status upload_tables(cnpc_bispec_plan* P) {
+  const int nc = P->nconf;
+  std::vector<double> cnt(P->nb);
+  for (int b = 0; b < P->nb; ++b) cnt[b] = (double)P->counts[b];
+  CNPC_HIP(hipMemcpy(P->d_cfg, P->cfg.data(), sizeof(int) * 3 * nc, hipMemcpyHostToDevice));
+  CNPC_HIP(hipMemcpy(P->d_ntri, P->ntri.data(), sizeof(int64_t) * nc, hipMemcpyHostToDevice));
+  CNPC_HIP(hipMemcpy(P->d_aux, P->aux.data(), sizeof(double) * 2 * nc, hipMemcpyHostToDevice));
+  CNPC_HIP(hipMemcpy(P->d_counts, cnt.data(), sizeof(double) * P->nb, hipMemcpyHostToDevice));
+  CNPC_HIP(hipMemcpy(P->d_wq, P->wq.data(), sizeof(double) * P->next, hipMemcpyHostToDevice));
+  return CNPC_OK;
+}
+
+__global__ void k_fill_ones(cx<double>* p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = cx<double>{1.0, 0.0};
+}
+
+size_t bispec_ws_bytes(const cnpc_mesh_desc* d, int nb, int band, int nfields, int ncols) {
+  const size_t n3 = (size_t)d->n * d->n * d->n;
+  const size_t es = esize(d->dtype);
+  // run time: fields + c2r scratch for all of them + contraction partials/result
+  const size_t run = nfields * n3 * es + shell_c2r_ws_elems(d->n, band, nfields) * 2 * es +
+                     (contract_partial_doubles(nb, ncols) + (size_t)nb * (nb + 1) / 2 * ncols) * 8;
+  // plan time (FP64 indicator fields): ones + fields + scratch + partials
+  const size_t bsz = (size_t)4 * band * band * band;
+  const size_t plan = bsz * 16 + (size_t)nb * n3 * 8 + shell_c2r_ws_elems(d->n, band, nb) * 16 +
+                      (contract_partial_doubles(nb, nb) + (size_t)nb * (nb + 1) / 2 * nb) * 8;
+  return (run > plan ? run : plan) + 4096;
+}
+
+static void fields_for(int est, int ell, int nb, int* nfields, ContractCols* cc) {
+  if (est == CNPC_EST_TRIPOSH) {
+    *nfields = nb + 1;
+    cc->ncols = 1;
+    cc->field[0] = nb;
+  } else if (ell == 0) {
+    *nfields = nb;
+    cc->ncols = nb;
+    for (int c = 0; c < nb; ++c) cc->field[c] = c;
+  } else {
+    *nfields = 2 * nb;
+    cc->ncols = nb;
+    for (int c = 0; c < nb; ++c) cc->field[c] = nb + c;
+  }
+}
+
+static unsigned char* align256(unsigned char* p) {
+  return reinterpret_cast<unsigned char*>((reinterpret_cast<uintptr_t>(p) + 255) & ~(uintptr_t)255);
+}
+
+cnpc_status bispec_plan_create(cnpc_bispec_plan** out, const cnpc_mesh_desc* d, const cnpc_kbins* b,
+                               int est, int ell, int prec, void* ws, size_t ws_bytes,
+                               hipStream_t s) {
+  auto* P = new cnpc_bispec_plan();
+  P->desc = *d;
+  P->bins = *b;
+  P->est = est;
+  P->ell = ell;
+  P->prec = prec;
+  P->nb = b->nbins;
+  P->thr.resize(P->nb + 1);
+  bin_thresholds(d, b, P->thr.data());
+  const double kf = 2.0 * M_PI / d->boxsize;
+  const double ktop = b->kmin + b->nbins * b->dk;
+  // noise spectra binning: TripoSH needs k3 bins up to |i + j| <= 2 nb - 2
+  P->ext = *b;
+  if (est == CNPC_EST_TRIPOSH) P->ext.nbins = 2 * P->nb - 1;
+  P->next = P->ext.nbins;
+  const double kneed = est == CNPC_EST_TRIPOSH ? b->kmin + P->ext.nbins * b->dk : ktop;
+  int m = 1;
+  while (m < d->n / 2 && (double)m * kf <= kneed) m <<= 1;
+  P->band = m;
+  if ((double)m * kf <= kneed && m >= d->n / 2) {
+    // band = N/2 covers every mode below Nyquist
+  }
+  P->counts = mode_counts(d, P->thr, P->nb);
+  std::vector<int64_t> thr_ext(P->next + 1);
+  bin_thresholds(d, &P->ext, thr_ext.data());
+  P->counts_ext = mode_counts(d, thr_ext, P->next);
+  P->wq.resize(P->next);
+  for (int c = 0; c < P->next; ++c) {
+    const double kc = b->kmin + (c + 0.5) * b->dk;
+    P->wq[c] = (double)P->counts_ext[c] / kc;
+  }
+  fields_for(est, ell, P->nb, &P->nfields, &P->cc);
+  // configurations
+  const int nb = P->nb;
+  std::vector<int> cfg;
+  if (est == CNPC_EST_TRIPOSH) {
+    for (int i = 0; i < nb; ++i)
+      for (int j = i; j < nb; ++j) {
+        cfg.push_back(i); cfg.push_back(j); cfg.push_back(-1);
+      }
+  } else {
+    for (int i = 0; i < nb; ++i)
+      for (int j = (ell == 0 ? i : 0); j < nb; ++j)
+        for (int k = j; k < nb; ++k)
+          if (closed(i, j, k)) { cfg.push_back(i); cfg.push_back(j); cfg.push_back(k); }
+  }
+  const int ncand = (int)cfg.size() / 3;
+  std::vector<int64_t> ntri(ncand, 0);
+  if (est == CNPC_EST_SCOCCIMARRO) {
+    // N_T from FP64 indicator fields, once per binning
+    unsigned char* w = align256(reinterpret_cast<unsigned char*>(ws));
+    const int64_t n3 = (int64_t)d->n * d->n * d->n;
+    const int64_t bsz = (int64_t)4 * m * m * m;
+    cx<double>* ones = reinterpret_cast<cx<double>*>(w);
+    double* ind = reinterpret_cast<double*>(align256(reinterpret_cast<unsigned char*>(ones + bsz)));
+    cx<double>* scr = reinterpret_cast<cx<double>*>(align256(reinterpret_cast<unsigned char*>(ind + (int64_t)nb * n3)));
+    double* partial = reinterpret_cast<double*>(align256(reinterpret_cast<unsigned char*>(scr + shell_c2r_ws_elems(d->n, m, nb))));
+    double* Cm = partial + contract_partial_doubles(nb, nb);
+    const size_t need = (reinterpret_cast<unsigned char*>(Cm + (size_t)nb * (nb + 1) / 2 * nb) -
+                         reinterpret_cast<unsigned char*>(ws));
+    if (need > ws_bytes) {
+      delete P;
+      set_error("bispectrum plan workspace too small: need %zu, got %zu", need, ws_bytes);
+      return CNPC_EWORKSPACE;
+    }
+    cnpc_mesh_desc d64 = *d;
+    d64.dtype = CNPC_F64;
+    hipLaunchKernelGGL(k_fill_ones, dim3(256), dim3(256), 0, s, ones, bsz);
+    CNPC_HIP(hipGetLastError());
+    CNPC_TRY(ensure_twiddles());
+    CNPC_TRY(shell_c2r<double>(&d64, m, ones, P->thr.data(), nb + 1, 0, nb, true, ind, scr, s));
+    ContractCols c2;
+    c2.ncols = nb;
+    for (int c = 0; c < nb; ++c) c2.field[c] = c;
+    CNPC_TRY(contract_valu<double>(ind, n3, nb, nb, c2, partial, Cm, s));
+    std::vector<double> hC((size_t)nb * (nb + 1) / 2 * nb);
+    CNPC_HIP(hipMemcpyAsync(hC.data(), Cm, sizeof(double) * hC.size(), hipMemcpyDeviceToHost, s));
+    CNPC_HIP(hipStreamSynchronize(s));
+    for (int t = 0; t < ncand; ++t) {
+      const int i = cfg[3 * t], j = cfg[3 * t + 1], k = cfg[3 * t + 2];
+      const double v = hC[(size_t)pair_index(j, k, nb) * nb + i] / (double)n3;
+      ntri[t] = (int64_t)llround(v);
+    }
+  }
+  // keep configurations with triangles (Scoccimarro) and fill per-config factors
+  const double* dummy = nullptr;
+  (void)dummy;
+  for (int t = 0; t < ncand; ++t) {
+    const int i = cfg[3 * t], j = cfg[3 * t + 1], k = cfg[3 * t + 2];
+    if (est == CNPC_EST_SCOCCIMARRO && ntri[t] <= 0) continue;
+    P->cfg.push_back(i); P->cfg.push_back(j); P->cfg.push_back(k);
+    P->ntri.push_back(est == CNPC_EST_SCOCCIMARRO ? ntri[t] : 0);
+    const double ki = b->kmin + (i + 0.5) * b->dk, kj = b->kmin + (j + 0.5) * b->dk;
+    if (est == CNPC_EST_SCOCCIMARRO) {
+      const double kk = b->kmin + (k + 0.5) * b->dk;
+      double mij = (kk * kk - ki * ki - kj * kj) / (2.0 * ki * kj);
+      double mik = (kj * kj - ki * ki - kk * kk) / (2.0 * ki * kk);
+      mij = mij > 1 ? 1 : (mij < -1 ? -1 : mij);
+      mik = mik > 1 ? 1 : (mik < -1 ? -1 : mik);
+      P->aux.push_back(legendre_host(ell, mij));
+      P->aux.push_back(legendre_host(ell, mik));
+    } else {
+      const double t_ = ki / kj;
+      P->aux.push_back(g_ell_host(ell, t_));
+      P->aux.push_back(g_ell_host(ell, 1.0 / t_));
+    }
+  }
+  P->nconf = (int)P->ntri.size();
+  cnpc_status st = device_tables(P);
+  if (st == CNPC_OK) st = upload_tables(P);
+  if (st != CNPC_OK) {
+    bispec_plan_destroy(P);
+    return st;
+  }
+  *out = P;
+  return CNPC_OK;
+}
+
+void bispec_plan_destroy(cnpc_bispec_plan* P) {
+  if (!P) return;
+  if (P->d_cfg) (void)hipFree(P->d_cfg);
+  if (P->d_ntri) (void)hipFree(P->d_ntri);
+  if (P->d_aux) (void)hipFree(P->d_aux);
+  if (P->d_counts) (void)hipFree(P->d_counts);
+  if (P->d_wq) (void)hipFree(P->d_wq);
+  delete P;
+}
+
+template <typename T>
+static cnpc_status bispec_run_t(const cnpc_bispec_plan* P, const cx<T>* F0, const cx<T>* Fl,
+                                const double* noise, const double* norms, double* raw, double* shot,
+                                double* value, void* ws, size_t ws_bytes, hipStream_t s) {
+  const cnpc_mesh_desc* d = &P->desc;
+  const int n = d->n, m = P->band, nb = P->nb;
+  const int64_t n3 = (int64_t)n * n * n;
+  unsigned char* w = align256(reinterpret_cast<unsigned char*>(ws));
+  T* fields = reinterpret_cast<T*>(w);
+  cx<T>* scr = reinterpret_cast<cx<T>*>(align256(reinterpret_cast<unsigned char*>(fields + (int64_t)P->nfields * n3)));
+  double* partial = reinterpret_cast<double*>(align256(reinterpret_cast<unsigned char*>(scr + shell_c2r_ws_elems(n, m, P->nfields))));
+  double* Cm = partial + contract_partial_doubles(nb, P->cc.ncols);
+  const size_t need = reinterpret_cast<unsigned char*>(Cm + (size_t)nb * (nb + 1) / 2 * P->cc.ncols) -
+                      reinterpret_cast<unsigned char*>(ws);
+  if (need > ws_bytes) {
+    set_error("bispectrum workspace too small: need %zu, got %zu", need, ws_bytes);
+    return CNPC_EWORKSPACE;
+  }
+  CNPC_TRY(ensure_twiddles());
+  const int nthr = nb + 1;
+  CNPC_TRY(shell_c2r<T>(d, m, F0, P->thr.data(), nthr, 0, nb, true, fields, scr, s));
+  if (P->est == CNPC_EST_SCOCCIMARRO && P->ell > 0)
+    CNPC_TRY(shell_c2r<T>(d, m, Fl, P->thr.data(), nthr, 0, nb, true, fields + (int64_t)nb * n3, scr, s));
+  if (P->est == CNPC_EST_TRIPOSH)
+    CNPC_TRY(shell_c2r<T>(d, m, Fl, P->thr.data(), nthr, 0, 1, false, fields + (int64_t)nb * n3, scr, s));
+  CNPC_TRY(contract_valu<T>(fields, n3, P->nfields, nb, P->cc, partial, Cm, s));
+  FinArgs f;
+  f.est = P->est;
+  f.ell = P->ell;
+  f.nb = nb;
+  f.next = P->next;
+  f.ncols = P->cc.ncols;
+  f.nconf = P->nconf;
+  f.n3 = (double)n3;
+  f.cfg = P->d_cfg;
+  f.ntri = P->d_ntri;
+  f.aux = P->d_aux;
+  f.counts = P->d_counts;
+  f.wq = P->d_wq;
+  const unsigned g = (unsigned)std::max(1, (P->nconf + 255) / 256);
+  hipLaunchKernelGGL(k_finalize, dim3(g), dim3(256), 0, s, f, Cm, noise, norms, raw, shot, value);
+  CNPC_HIP(hipGetLastError());
+  return CNPC_OK;
+}
+
+cnpc_status bispec_run(const cnpc_bispec_plan* P, const void* F0, const void* Fl,
+                       const double* noise, const double* norms, double* raw, double* shot,
+                       double* value, void* ws, size_t ws_bytes, hipStream_t s) {
+  if (P->desc.dtype == CNPC_F64)
+    return bispec_run_t<double>(P, (const cx<double>*)F0, (const cx<double>*)Fl, noise, norms, raw, shot,
+                                value, ws, ws_bytes, s);
+  return bispec_run_t<float>(P, (const cx<float>*)F0, (const cx<float>*)Fl, noise, norms, raw, shot,
+                             value, ws, ws_bytes, s);
+}
+
+}  // namespace cnpc

@@ -1,0 +1,350 @@
+// Batched 3-D real FFTs for gfx950: z-row passes (two real rows packed in one
+// complex transform), strided column passes (x and y), band pruning.
+#include <mutex>
+#include <vector>
+#include <cmath>
+
+#include "fft.h"
+
+namespace cnpc {
+
+__device__ cx<double> g_twiddle1024[1024];
+
+cnpc_status ensure_twiddles() {
+  static std::mutex mu;
+  static bool ready[64] = {false};
+  int dev = 0;
+  CNPC_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) {
+    set_error("device index %d out of range", dev);
+    return CNPC_EUNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lk(mu);
+  if (ready[dev]) return CNPC_OK;
+  std::vector<cx<double>> h(1024);
+  for (int t = 0; t < 1024; ++t) {
+    // exp(-2 pi i t / 1024) via exact octant symmetry of the angle
+    const long double a = 2.0L * 3.14159265358979323846264338327950288L * t / 1024.0L;
+    h[t] = cx<double>{(double)cosl(a), (double)(-sinl(a))};
+  }
+  CNPC_HIP(hipMemcpyToSymbol(HIP_SYMBOL(g_twiddle1024), h.data(), sizeof(cx<double>) * 1024));
+  ready[dev] = true;
+  return CNPC_OK;
+}
+
+// ------------------------------------------------------------------ sizes --
+template <typename T, int N>
+struct ZCfg {
+  // sequences per workgroup so that the two ping-pong buffers take <= 32 KiB
+  static constexpr int bytes = 16384;
+  static constexpr int nseq_raw = bytes / (N * (int)sizeof(cx<T>));
+  static constexpr int NSEQ = nseq_raw < 1 ? 1 : nseq_raw;
+};
+
+int col_tile_width(int n, int dtype) {
+  // 128-byte row segments when LDS allows: twiddles + two buffers of N x W elements
+  const size_t es = dtype == CNPC_F64 ? 16 : 8;
+  const size_t lim = lds_limit();
+  int w = (int)(128 / es);
+  while (w > 1 && (2 * (size_t)n * w + n) * es > lim) w >>= 1;
+  return w;
+}
+
+// ---------------------------------------------------------- z-pass r2c --
+// rows r = 0..nrows-1 of length N (real, in + r*N); pairs (2q, 2q+1) packed as
+// one complex sequence z = a + i b.  Output row r: kz = 0..kz_keep-1 complex at
+// out + r * kz_keep.
+template <typename T, int N>
+__global__ void __launch_bounds__(256) k_zpass_r2c(const T* __restrict__ in, cx<T>* __restrict__ out,
+                                                   int64_t npairs, int kz_keep) {
+  constexpr int NSEQ = ZCfg<T, N>::NSEQ;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* A = tw + N;
+  cx<T>* B = A + NSEQ * N;
+  load_twiddles<T, N, -1>(tw);
+  const int64_t q0 = (int64_t)blockIdx.x * NSEQ;
+  const int nq = (int)((npairs - q0) < NSEQ ? (npairs - q0) : NSEQ);
+  for (int idx = threadIdx.x; idx < nq * N; idx += blockDim.x) {
+    const int s = idx / N, e = idx - s * N;
+    const T* r0 = in + (2 * (q0 + s)) * (int64_t)N;
+    A[s * N + e] = cx<T>{r0[e], r0[N + e]};
+  }
+  __syncthreads();
+  cx<T>* Z = fft_lds<T, N, -1, false>(A, B, nq, 0, N, 1, tw);
+  for (int idx = threadIdx.x; idx < nq * kz_keep; idx += blockDim.x) {
+    const int s = idx / kz_keep, k = idx - s * kz_keep;
+    const cx<T> zk = Z[s * N + k];
+    const cx<T> zm = cconj(Z[s * N + ((N - k) & (N - 1))]);
+    const cx<T> a = cscale(cadd(zk, zm), T(0.5));
+    const cx<T> d = csub(zk, zm);
+    const cx<T> b = {T(0.5) * d.y, T(-0.5) * d.x};  // (zk - zm) / (2 i)
+    cx<T>* o = out + (2 * (q0 + s)) * (int64_t)kz_keep;
+    o[k] = a;
+    o[kz_keep + k] = b;
+  }
+}
+
+// ---------------------------------------------------------- z-pass c2r --
+// input rows r: kz = 0..kz_in-1 complex at in + r * kz_in (higher kz, and
+// kz = N/2, taken as zero); output real rows at out + r * N.  in and out may
+// alias when kz_in == N/2 (the workgroup reads all its rows first).
+template <typename T, int N>
+__global__ void __launch_bounds__(256) k_zpass_c2r(const cx<T>* in, T* out, int64_t npairs,
+                                                   int kz_in) {
+  constexpr int NSEQ = ZCfg<T, N>::NSEQ;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* A = tw + N;
+  cx<T>* B = A + NSEQ * N;
+  load_twiddles<T, N, 1>(tw);
+  const int64_t q0 = (int64_t)blockIdx.x * NSEQ;
+  const int nq = (int)((npairs - q0) < NSEQ ? (npairs - q0) : NSEQ);
+  for (int idx = threadIdx.x; idx < nq * N; idx += blockDim.x) {
+    const int s = idx / N, k = idx - s * N;
+    const cx<T>* r0 = in + (2 * (q0 + s)) * (int64_t)kz_in;
+    cx<T> z = {T(0), T(0)};
+    if (k < (N >> 1)) {
+      if (k < kz_in) {
+        const cx<T> a = r0[k], b = r0[kz_in + k];
+        z = cx<T>{a.x - b.y, a.y + b.x};
+      }
+    } else if (k > (N >> 1)) {
+      const int kk = N - k;
+      if (kk < kz_in) {
+        const cx<T> a = r0[kk], b = r0[kz_in + kk];
+        z = cx<T>{a.x + b.y, b.x - a.y};
+      }
+    }
+    A[s * N + k] = z;
+  }
+  __syncthreads();
+  cx<T>* Z = fft_lds<T, N, 1, false>(A, B, nq, 0, N, 1, tw);
+  for (int idx = threadIdx.x; idx < nq * N; idx += blockDim.x) {
+    const int s = idx / N, e = idx - s * N;
+    T* o = out + (2 * (q0 + s)) * (int64_t)N;
+    const cx<T> z = Z[s * N + e];
+    o[e] = z.x;
+    o[N + e] = z.y;
+  }
+}
+
+// ---------------------------------------------------------- column pass --
+// For each plane p and each tile of W consecutive columns: transform along the
+// row index (length N).  Input rows: all N (band_in == 0) or the 2*band_in band
+// rows (others zero).  Output rows likewise with band_out.
+template <typename T, int N, int DIR>
+__global__ void __launch_bounds__(256) k_colpass(const cx<T>* in, cx<T>* out, ColArgs a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* A = tw + N;
+  cx<T>* B = A + N * a.W;
+  load_twiddles<T, N, DIR>(tw);
+  const int tiles = a.ncols >> a.logW;
+  const int64_t p = blockIdx.x / tiles;
+  const int c0 = (blockIdx.x - (int)(p * tiles)) << a.logW;
+  const cx<T>* src = in + p * a.plane_in + c0;
+  for (int idx = threadIdx.x; idx < N * a.W; idx += blockDim.x) {
+    const int r = idx >> a.logW, c = idx & (a.W - 1);
+    int j = r;
+    bool ok = true;
+    if (a.band_in) {
+      if (r < a.band_in) j = r;
+      else if (r >= N - a.band_in) j = r - N + 2 * a.band_in;
+      else ok = false;
+    }
+    if (ok && a.mask_m) {
+      const int col = c0 + c;
+      const int jy = col / a.mask_m, kz = col - jy * a.mask_m;
+      const int nx = freq_of(r, N), ny = band_freq(jy, a.mask_m);
+      const int64_t n2 = (int64_t)nx * nx + (int64_t)ny * ny + (int64_t)kz * kz;
+      const int b = a.mask_b0 + (int)p;
+      ok = n2 > 0 && n2 >= a.thr[b] && n2 < a.thr[b + 1] && nx != -(N / 2) && ny != -(N / 2);
+    }
+    A[idx] = ok ? src[(int64_t)j * a.row_in + c] : cx<T>{T(0), T(0)};
+  }
+  __syncthreads();
+  cx<T>* R = fft_lds<T, N, DIR, true>(A, B, a.W, a.logW, 1, a.W, tw);
+  cx<T>* dst = out + p * a.plane_out + c0;
+  for (int idx = threadIdx.x; idx < N * a.W; idx += blockDim.x) {
+    const int r = idx >> a.logW, c = idx & (a.W - 1);
+    int j = r;
+    if (a.band_out) {
+      if (r < a.band_out) j = r;
+      else if (r >= N - a.band_out) j = r - N + 2 * a.band_out;
+      else continue;
+    }
+    dst[(int64_t)j * a.row_out + c] = R[idx];
+  }
+}
+
+// ------------------------------------------------------------- launchers --
+template <typename T, int N>
+static cnpc_status zr2c_n(const T* in, cx<T>* out, int64_t nrows, int kz, hipStream_t s) {
+  const int64_t npairs = nrows / 2;
+  constexpr int NSEQ = ZCfg<T, N>::NSEQ;
+  const int64_t blocks = (npairs + NSEQ - 1) / NSEQ;
+  const size_t lds = sizeof(cx<T>) * (N + 2 * NSEQ * N);
+  hipLaunchKernelGGL((k_zpass_r2c<T, N>), dim3((unsigned)blocks), dim3(256), lds, s, in, out, npairs,
+                     kz);
+  CNPC_HIP(hipGetLastError());
+  return CNPC_OK;
+}
+
+template <typename T, int N>
+static cnpc_status zc2r_n(const cx<T>* in, T* out, int64_t nrows, int kz, hipStream_t s) {
+  const int64_t npairs = nrows / 2;
+  constexpr int NSEQ = ZCfg<T, N>::NSEQ;
+  const int64_t blocks = (npairs + NSEQ - 1) / NSEQ;
+  const size_t lds = sizeof(cx<T>) * (N + 2 * NSEQ * N);
+  hipLaunchKernelGGL((k_zpass_c2r<T, N>), dim3((unsigned)blocks), dim3(256), lds, s, in, out, npairs,
+                     kz);
+  CNPC_HIP(hipGetLastError());
+  return CNPC_OK;
+}
+
+template <typename T, int N, int DIR>
+static cnpc_status col_n(const cx<T>* in, cx<T>* out, const ColArgs& a, int64_t nplanes,
+                         hipStream_t s) {
+  const int64_t blocks = nplanes * (a.ncols >> a.logW);
+  if (blocks <= 0) return CNPC_OK;
+  if (blocks > 0x7fffffffLL) {
+    set_error("column pass grid too large");
+    return CNPC_EUNSUPPORTED;
+  }
+  const size_t lds = sizeof(cx<T>) * (N + 2 * N * a.W);
+  hipLaunchKernelGGL((k_colpass<T, N, DIR>), dim3((unsigned)blocks), dim3(256), lds, s, in, out, a);
+  CNPC_HIP(hipGetLastError());
+  return CNPC_OK;
+}
+
+#define CNPC_DISPATCH_N(n, CALL)          \
+  switch (n) {                            \
+    case 16: { constexpr int NN = 16; return CALL; }     \
+    case 32: { constexpr int NN = 32; return CALL; }     \
+    case 64: { constexpr int NN = 64; return CALL; }     \
+    case 128: { constexpr int NN = 128; return CALL; }   \
+    case 256: { constexpr int NN = 256; return CALL; }   \
+    case 512: { constexpr int NN = 512; return CALL; }   \
+    case 1024: { constexpr int NN = 1024; return CALL; } \
+    default: set_error("unsupported mesh size %d", n); return CNPC_EUNSUPPORTED; \
+  }
+
+template <typename T>
+cnpc_status zpass_r2c(int n, const T* in, cx<T>* out, int64_t nrows, int kz, hipStream_t s) {
+  CNPC_DISPATCH_N(n, (zr2c_n<T, NN>(in, out, nrows, kz, s)));
+}
+template <typename T>
+cnpc_status zpass_c2r(int n, const cx<T>* in, T* out, int64_t nrows, int kz, hipStream_t s) {
+  CNPC_DISPATCH_N(n, (zc2r_n<T, NN>(in, out, nrows, kz, s)));
+}
+template <typename T>
+cnpc_status colpass(int n, int dir, const cx<T>* in, cx<T>* out, const ColArgs& a, int64_t nplanes,
+                    hipStream_t s) {
+  if (dir < 0) {
+    CNPC_DISPATCH_N(n, (col_n<T, NN, -1>(in, out, a, nplanes, s)));
+  }
+  CNPC_DISPATCH_N(n, (col_n<T, NN, 1>(in, out, a, nplanes, s)));
+}
+
+ColArgs make_col(int n, int dtype, int64_t plane_in, int64_t plane_out, int64_t row_in,
+                 int64_t row_out, int ncols, int band_in, int band_out) {
+  ColArgs a;
+  a.plane_in = plane_in;
+  a.plane_out = plane_out;
+  a.row_in = row_in;
+  a.row_out = row_out;
+  a.ncols = ncols;
+  int w = col_tile_width(n, dtype);
+  while (w > 1 && (ncols % w) != 0) w >>= 1;
+  a.W = w;
+  a.logW = ilog2_host(w);
+  a.band_in = band_in;
+  a.band_out = band_out;
+  a.mask_m = 0;
+  a.mask_b0 = 0;
+  return a;
+}
+
+// ------------------------------------------------------- 3-D transforms --
+template <typename T>
+cnpc_status fft3d_r2c(int n, int batch, int band, const T* in, cx<T>* out, cx<T>* ws,
+                      hipStream_t s) {
+  CNPC_TRY(ensure_twiddles());
+  const int dt = sizeof(T) == 8 ? CNPC_F64 : CNPC_F32;
+  const int64_t nn = (int64_t)n * n;
+  if (band == 0) {
+    const int h = n / 2;
+    CNPC_TRY(zpass_r2c<T>(n, in, out, (int64_t)batch * nn, h, s));
+    // y: planes (b, ix), rows iy (stride h), columns kz
+    ColArgs ay = make_col(n, dt, (int64_t)n * h, (int64_t)n * h, h, h, h, 0, 0);
+    CNPC_TRY(colpass<T>(n, -1, out, out, ay, (int64_t)batch * n, s));
+    // x: planes b, rows ix (stride n*h), columns (iy, kz)
+    ColArgs ax = make_col(n, dt, nn * h, nn * h, (int64_t)n * h, (int64_t)n * h, n * h, 0, 0);
+    CNPC_TRY(colpass<T>(n, -1, out, out, ax, batch, s));
+    return CNPC_OK;
+  }
+  const int m = band;
+  cx<T>* w1 = ws;                              // [batch][n][n][m]
+  cx<T>* w2 = ws + (int64_t)batch * nn * m;    // [batch][n][2m][m]
+  CNPC_TRY(zpass_r2c<T>(n, in, w1, (int64_t)batch * nn, m, s));
+  ColArgs ay = make_col(n, dt, (int64_t)n * m, (int64_t)2 * m * m, m, m, m, 0, m);
+  CNPC_TRY(colpass<T>(n, -1, w1, w2, ay, (int64_t)batch * n, s));
+  ColArgs ax = make_col(n, dt, (int64_t)n * 2 * m * m, (int64_t)4 * m * m * m, (int64_t)2 * m * m,
+                        (int64_t)2 * m * m, 2 * m * m, 0, m);
+  CNPC_TRY(colpass<T>(n, -1, w2, out, ax, batch, s));
+  return CNPC_OK;
+}
+
+template <typename T>
+cnpc_status fft3d_c2r(int n, int batch, int band, const cx<T>* in, T* out, cx<T>* ws,
+                      hipStream_t s) {
+  CNPC_TRY(ensure_twiddles());
+  const int dt = sizeof(T) == 8 ? CNPC_F64 : CNPC_F32;
+  const int64_t nn = (int64_t)n * n;
+  if (band == 0) {
+    const int h = n / 2;
+    cx<T>* o = reinterpret_cast<cx<T>*>(out);
+    ColArgs ax = make_col(n, dt, nn * h, nn * h, (int64_t)n * h, (int64_t)n * h, n * h, 0, 0);
+    CNPC_TRY(colpass<T>(n, 1, in, o, ax, batch, s));
+    ColArgs ay = make_col(n, dt, (int64_t)n * h, (int64_t)n * h, h, h, h, 0, 0);
+    CNPC_TRY(colpass<T>(n, 1, o, o, ay, (int64_t)batch * n, s));
+    CNPC_TRY(zpass_c2r<T>(n, o, out, (int64_t)batch * nn, h, s));
+    return CNPC_OK;
+  }
+  const int m = band;
+  cx<T>* w1 = ws;                            // [batch][n][n][m]
+  cx<T>* w2 = ws + (int64_t)batch * nn * m;  // [batch][n][2m][m]
+  ColArgs ax = make_col(n, dt, (int64_t)4 * m * m * m, (int64_t)n * 2 * m * m, (int64_t)2 * m * m,
+                        (int64_t)2 * m * m, 2 * m * m, m, 0);
+  CNPC_TRY(colpass<T>(n, 1, in, w2, ax, batch, s));
+  ColArgs ay = make_col(n, dt, (int64_t)2 * m * m, (int64_t)n * m, m, m, m, m, 0);
+  CNPC_TRY(colpass<T>(n, 1, w2, w1, ay, (int64_t)batch * n, s));
+  CNPC_TRY(zpass_c2r<T>(n, w1, out, (int64_t)batch * nn, m, s));
+  return CNPC_OK;
+}
+
+size_t fft_ws_elems(int n, int batch, int band) {
+  if (band == 0) return 0;
+  const size_t nn = (size_t)n * n;
+  return (size_t)batch * (nn * band + (size_t)n * 2 * band * band);
+}
+
+template cnpc_status zpass_r2c<float>(int, const float*, cx<float>*, int64_t, int, hipStream_t);
+template cnpc_status zpass_r2c<double>(int, const double*, cx<double>*, int64_t, int, hipStream_t);
+template cnpc_status zpass_c2r<float>(int, const cx<float>*, float*, int64_t, int, hipStream_t);
+template cnpc_status zpass_c2r<double>(int, const cx<double>*, double*, int64_t, int, hipStream_t);
+template cnpc_status colpass<float>(int, int, const cx<float>*, cx<float>*, const ColArgs&, int64_t,
+                                    hipStream_t);
+template cnpc_status colpass<double>(int, int, const cx<double>*, cx<double>*, const ColArgs&,
+                                     int64_t, hipStream_t);
+template cnpc_status fft3d_r2c<float>(int, int, int, const float*, cx<float>*, cx<float>*,
+                                      hipStream_t);
+template cnpc_status fft3d_r2c<double>(int, int, int, const double*, cx<double>*, cx<double>*,
+                                       hipStream_t);
+template cnpc_status fft3d_c2r<float>(int, int, int, const cx<float>*, float*, cx<float>*,
+                                      hipStream_t);
+template cnpc_status fft3d_c2r<double>(int, int, int, const cx<double>*, double*, cx<double>*,
+                                       hipStream_t);
+
+}  // namespace cnpc

@@ -1,0 +1,158 @@
+// LDS-staged radix-8/4 Stockham FFT building blocks for 64-wide wavefronts.
+//
+// A workgroup transforms `nseq` independent length-N sequences that sit in
+// LDS (element e of sequence s at buf[s * sstride + e * estride]).  Each stage
+// reads R strided values per task into registers, applies the twiddles
+// w^(r k), does an R-point DFT in registers and writes the autosorted result
+// to the other LDS buffer (ping-pong, one barrier per stage).  Radix-8 stages
+// first, then radix-4: N = 8^a 4^b.
+#pragma once
+
+#include "common.h"
+
+namespace cnpc {
+
+// exp(-2 pi i t / 1024), t = 0..1023, FP64; set once per device by the host.
+extern __device__ cx<double> g_twiddle1024[1024];
+
+template <int N>
+struct Radix {
+  static constexpr int L = (N <= 1) ? 0 : 1 + Radix<N / 2>::L;
+  static constexpr int n8 = (L % 3 == 0) ? L / 3 : ((L % 3 == 1) ? (L - 4) / 3 : (L - 2) / 3);
+  static constexpr int n4 = (L - 3 * n8) / 2;
+};
+template <>
+struct Radix<1> {
+  static constexpr int L = 0;
+  static constexpr int n8 = 0;
+  static constexpr int n4 = 0;
+};
+
+// multiply by DIR * i (DIR = -1: forward, -i; DIR = +1: inverse, +i)
+template <typename T, int DIR>
+__device__ __forceinline__ cx<T> mul_i(cx<T> a) {
+  return DIR < 0 ? cx<T>{a.y, -a.x} : cx<T>{-a.y, a.x};
+}
+
+template <typename T, int DIR>
+__device__ __forceinline__ void dft4(cx<T>& a0, cx<T>& a1, cx<T>& a2, cx<T>& a3) {
+  const cx<T> t0 = cadd(a0, a2), t1 = csub(a0, a2), t2 = cadd(a1, a3);
+  const cx<T> t3 = mul_i<T, DIR>(csub(a1, a3));
+  a0 = cadd(t0, t2);
+  a2 = csub(t0, t2);
+  a1 = cadd(t1, t3);
+  a3 = csub(t1, t3);
+}
+
+template <typename T, int DIR>
+__device__ __forceinline__ void dft8(cx<T>* v) {
+  dft4<T, DIR>(v[0], v[2], v[4], v[6]);  // E0..E3
+  dft4<T, DIR>(v[1], v[3], v[5], v[7]);  // O0..O3
+  const T r = T(0.70710678118654752440);
+  const cx<T> o0 = v[1];
+  cx<T> o1 = v[3], o2 = v[5], o3 = v[7];
+  if (DIR < 0) {  // W = exp(-i pi/4)
+    o1 = {r * (o1.x + o1.y), r * (o1.y - o1.x)};
+    o2 = {o2.y, -o2.x};
+    o3 = {r * (o3.y - o3.x), -r * (o3.x + o3.y)};
+  } else {  // W = exp(+i pi/4)
+    o1 = {r * (o1.x - o1.y), r * (o1.x + o1.y)};
+    o2 = {-o2.y, o2.x};
+    o3 = {-r * (o3.x + o3.y), r * (o3.x - o3.y)};
+  }
+  const cx<T> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+  v[0] = cadd(e0, o0);
+  v[4] = csub(e0, o0);
+  v[1] = cadd(e1, o1);
+  v[5] = csub(e1, o1);
+  v[2] = cadd(e2, o2);
+  v[6] = csub(e2, o2);
+  v[3] = cadd(e3, o3);
+  v[7] = csub(e3, o3);
+}
+
+template <typename T, int R, int DIR>
+__device__ __forceinline__ void dftR(cx<T>* v) {
+  if constexpr (R == 8) {
+    dft8<T, DIR>(v);
+  } else {
+    dft4<T, DIR>(v[0], v[1], v[2], v[3]);
+  }
+}
+
+// Twiddle table tw[t] = exp(DIR 2 pi i t / N) into LDS.
+template <typename T, int N, int DIR>
+__device__ __forceinline__ void load_twiddles(cx<T>* tw) {
+  constexpr int step = 1024 / N;
+  for (int t = threadIdx.x; t < N; t += blockDim.x) {
+    const cx<double> w = g_twiddle1024[t * step];
+    tw[t] = cx<T>{T(w.x), DIR < 0 ? T(w.y) : T(-w.y)};
+  }
+}
+
+// One Stockham stage, src -> dst.  SEQ_FAST: consecutive tasks walk the
+// sequences (column layouts, nseq a power of two = 1 << lognseq); otherwise
+// they walk the elements of one sequence (row layouts).
+template <typename T, int N, int R, int DIR, bool SEQ_FAST>
+__device__ __forceinline__ void fft_stage(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst,
+                                          int nseq, int lognseq, int sstride, int estride,
+                                          const cx<T>* __restrict__ tw, int Ns) {
+  constexpr int per = N / R;
+  const int tasks = nseq * per;
+  for (int task = threadIdx.x; task < tasks; task += blockDim.x) {
+    int s, j;
+    if constexpr (SEQ_FAST) {
+      s = task & (nseq - 1);
+      j = task >> lognseq;
+    } else {
+      s = task / per;
+      j = task - s * per;
+    }
+    const cx<T>* in = src + s * sstride;
+    cx<T> v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = in[(j + r * per) * estride];
+    const int k = j & (Ns - 1);
+    if (Ns > 1) {
+      const int step = (N / (Ns * R)) * k;
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw[r * step]);
+    }
+    dftR<T, R, DIR>(v);
+    const int base = (j - k) * R + k;
+    cx<T>* out = dst + s * sstride;
+#pragma unroll
+    for (int r = 0; r < R; ++r) out[(base + r * Ns) * estride] = v[r];
+  }
+}
+
+// Full FFT of all sequences; data must be in `a` and visible (barrier done).
+// Returns the buffer that holds the result; ends with a barrier.
+template <typename T, int N, int DIR, bool SEQ_FAST>
+__device__ __forceinline__ cx<T>* fft_lds(cx<T>* a, cx<T>* b, int nseq, int lognseq, int sstride,
+                                          int estride, const cx<T>* tw) {
+  cx<T>* src = a;
+  cx<T>* dst = b;
+  int Ns = 1;
+#pragma unroll
+  for (int i = 0; i < Radix<N>::n8; ++i) {
+    fft_stage<T, N, 8, DIR, SEQ_FAST>(src, dst, nseq, lognseq, sstride, estride, tw, Ns);
+    __syncthreads();
+    cx<T>* t = src;
+    src = dst;
+    dst = t;
+    Ns *= 8;
+  }
+#pragma unroll
+  for (int i = 0; i < Radix<N>::n4; ++i) {
+    fft_stage<T, N, 4, DIR, SEQ_FAST>(src, dst, nseq, lognseq, sstride, estride, tw, Ns);
+    __syncthreads();
+    cx<T>* t = src;
+    src = dst;
+    dst = t;
+    Ns *= 4;
+  }
+  return src;
+}
+
+}  // namespace cnpc

@@ -1,0 +1,40 @@
+// Host-side entry points of the catalog sums and the painter.
+#pragma once
+
+#include "common.h"
+
+namespace cnpc {
+
+struct SumsArgs {
+  double boxsize;
+  double obs[3];
+  double los[3];
+  int global_los;
+};
+
+template <typename T>
+struct FoldArgs {
+  const T* blocks[4];
+  int n, nt, nphase, nsets;
+};
+
+struct PaintLayout {
+  int nt, ntiles, nphase, nsets;
+  size_t off_spos[2], off_sw[2], off_count[2], off_start[2], off_cursor[2];
+  size_t off_blocks[4];
+  size_t total;
+};
+
+PaintLayout paint_layout(const cnpc_mesh_desc* d, int64_t ngal, int64_t nran, bool weighted);
+cnpc_status launch_catalog_sums(const cnpc_mesh_desc* d, const uint32_t* pos, const float* w,
+                                int64_t n, double* sums, void* ws, size_t ws_bytes, hipStream_t s);
+cnpc_status launch_norms(const cnpc_mesh_desc* d, const double* gs, const double* rs, int64_t ngal,
+                         double* norms, hipStream_t s);
+cnpc_status launch_paint(const cnpc_mesh_desc* d, const uint32_t* gpos, const float* gw,
+                         int64_t ngal, const uint32_t* rpos, const float* rw, int64_t nran,
+                         const double* norms, void* delta, void* noise, void* ws, size_t ws_bytes,
+                         hipStream_t s);
+// per-workgroup LDS limit of the current device (bytes)
+size_t lds_limit();
+
+}  // namespace cnpc

@@ -1,0 +1,547 @@
+// Y_lm-weighted transforms, de-interlacing, F_l assembly and FP64 shell binning.
+#include "spectra.h"
+
+namespace cnpc {
+
+// --------------------------------------------------------------- geometry --
+struct Geo {
+  double h;        // mesh spacing L / N
+  double obs[3];   // observer (local line of sight)
+  double los[3];   // fixed line of sight
+  int global_los;
+};
+
+static Geo make_geo(const cnpc_mesh_desc* d) {
+  Geo g;
+  g.h = d->boxsize / d->n;
+  for (int i = 0; i < 3; ++i) { g.obs[i] = d->observer[i]; g.los[i] = d->los[i]; }
+  g.global_los = d->los_mode == CNPC_LOS_GLOBAL;
+  return g;
+}
+
+struct FieldTable {
+  int nf;
+  signed char ell[32], m[32], part[32];
+};
+
+static int field_table(int nells, const int32_t* ells, FieldTable* ft) {
+  int f = 0;
+  for (int q = 0; q < nells; ++q) {
+    const int l = ells[q];
+    for (int m = 0; m <= l; ++m) {
+      for (int p = 0; p < (m == 0 ? 1 : 2); ++p) {
+        if (f >= 32) return -1;
+        ft->ell[f] = (signed char)l;
+        ft->m[f] = (signed char)m;
+        ft->part[f] = (signed char)p;
+        ++f;
+      }
+    }
+  }
+  ft->nf = f;
+  return f;
+}
+
+template <typename T>
+__device__ __forceinline__ void node_dir(const Geo& g, int ix, int iy, int iz, T* u) {
+  if (g.global_los) {
+    u[0] = T(g.los[0]); u[1] = T(g.los[1]); u[2] = T(g.los[2]);
+    return;
+  }
+  const T rx = T(ix * g.h - g.obs[0]), ry = T(iy * g.h - g.obs[1]), rz = T(iz * g.h - g.obs[2]);
+  const T inv = T(1) / sqrt(rx * rx + ry * ry + rz * rz);
+  u[0] = rx * inv; u[1] = ry * inv; u[2] = rz * inv;
+}
+
+// ------------------------------------------------ materialised ylm fields --
+template <typename T>
+__global__ void __launch_bounds__(256) k_ylm_fields(const T* __restrict__ delta, T* __restrict__ out,
+                                                    int n, int ell, Geo g) {
+  const int64_t n3 = (int64_t)n * n * n;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n3;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int iz = (int)(i % n), iy = (int)((i / n) % n), ix = (int)(i / ((int64_t)n * n));
+    T u[3];
+    node_dir<T>(g, ix, iy, iz, u);
+    T re[5], im[5];
+    racah_ylm<T>(ell, u[0], u[1], u[2], re, im);
+    const T dv = delta[i];
+    out[i] = dv * re[0];
+    for (int m = 1; m <= ell; ++m) {
+      out[(2 * m - 1) * n3 + i] = dv * re[m];
+      out[(2 * m) * n3 + i] = dv * im[m];
+    }
+  }
+}
+
+// ------------------------------------------ fused ylm prologue z-pass r2c --
+// One row pair (ix, 2j), (ix, 2j+1) of delta per workgroup; fields [f0, f0+nfc)
+// are formed in LDS and transformed; kz < kz_keep is written for each field.
+template <typename T, int N>
+__global__ void __launch_bounds__(256) k_zpass_ylm(const T* __restrict__ delta, cx<T>* __restrict__ out,
+                                                   FieldTable ft, int f0, int nfc, int kz_keep,
+                                                   int64_t fstride, Geo g) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* A = tw + N;
+  cx<T>* B = A + nfc * N;
+  load_twiddles<T, N, -1>(tw);
+  const int q = blockIdx.x;
+  const int ix = q / (N / 2), iy0 = 2 * (q - ix * (N / 2));
+  const T* r0 = delta + ((int64_t)ix * N + iy0) * N;
+  for (int e = threadIdx.x; e < N; e += blockDim.x) {
+    const T d0 = r0[e], d1 = r0[N + e];
+    T u0[3], u1[3];
+    node_dir<T>(g, ix, iy0, e, u0);
+    node_dir<T>(g, ix, iy0 + 1, e, u1);
+    int cur = -1;
+    T re0[5], im0[5], re1[5], im1[5];
+    for (int f = 0; f < nfc; ++f) {
+      const int l = ft.ell[f0 + f], m = ft.m[f0 + f], p = ft.part[f0 + f];
+      if (l != cur) {
+        racah_ylm<T>(l, u0[0], u0[1], u0[2], re0, im0);
+        racah_ylm<T>(l, u1[0], u1[1], u1[2], re1, im1);
+        cur = l;
+      }
+      const T w0 = p ? im0[m] : re0[m];
+      const T w1 = p ? im1[m] : re1[m];
+      A[f * N + e] = cx<T>{d0 * w0, d1 * w1};
+    }
+  }
+  __syncthreads();
+  cx<T>* Z = fft_lds<T, N, -1, false>(A, B, nfc, 0, N, 1, tw);
+  for (int idx = threadIdx.x; idx < nfc * kz_keep; idx += blockDim.x) {
+    const int f = idx / kz_keep, k = idx - f * kz_keep;
+    const cx<T> zk = Z[f * N + k];
+    const cx<T> zm = cconj(Z[f * N + ((N - k) & (N - 1))]);
+    const cx<T> a = cscale(cadd(zk, zm), T(0.5));
+    const cx<T> dd = csub(zk, zm);
+    const cx<T> b = {T(0.5) * dd.y, T(-0.5) * dd.x};
+    cx<T>* o = out + (int64_t)(f0 + f) * fstride + ((int64_t)ix * N + iy0) * kz_keep;
+    o[k] = a;
+    o[kz_keep + k] = b;
+  }
+}
+
+template <typename T, int N>
+static cnpc_status zylm_n(const T* delta, cx<T>* out, const FieldTable& ft, int kz,
+                          int64_t fstride, const Geo& g, hipStream_t s) {
+  // fields per launch: two ping-pong buffers of nfc * N elements within the LDS limit
+  const size_t per = 2 * N * sizeof(cx<T>);
+  int nfc = (int)((lds_limit() - N * sizeof(cx<T>)) / per);
+  if (nfc < 1) nfc = 1;
+  if (nfc > ft.nf) nfc = ft.nf;
+  for (int f0 = 0; f0 < ft.nf; f0 += nfc) {
+    const int c = std::min(nfc, ft.nf - f0);
+    const size_t lds = sizeof(cx<T>) * (N + 2 * c * N);
+    hipLaunchKernelGGL((k_zpass_ylm<T, N>), dim3(N * (N / 2)), dim3(256), lds, s, delta, out, ft, f0, c,
+                       kz, fstride, g);
+    CNPC_HIP(hipGetLastError());
+  }
+  return CNPC_OK;
+}
+
+template <typename T>
+static cnpc_status zpass_ylm(int n, const T* delta, cx<T>* out, const FieldTable& ft, int kz,
+                             int64_t fstride, const Geo& g, hipStream_t s) {
+  switch (n) {
+    case 16: return zylm_n<T, 16>(delta, out, ft, kz, fstride, g, s);
+    case 32: return zylm_n<T, 32>(delta, out, ft, kz, fstride, g, s);
+    case 64: return zylm_n<T, 64>(delta, out, ft, kz, fstride, g, s);
+    case 128: return zylm_n<T, 128>(delta, out, ft, kz, fstride, g, s);
+    case 256: return zylm_n<T, 256>(delta, out, ft, kz, fstride, g, s);
+    case 512: return zylm_n<T, 512>(delta, out, ft, kz, fstride, g, s);
+    case 1024: return zylm_n<T, 1024>(delta, out, ft, kz, fstride, g, s);
+    default: set_error("unsupported mesh size %d", n); return CNPC_EUNSUPPORTED;
+  }
+}
+
+// y then x column passes of a band-pruned forward transform:
+// w1 [batch][n][n][m] -> w2 [batch][n][2m][m] -> out [batch][2m][2m][m]
+template <typename T>
+cnpc_status band_forward_yx(int n, int dt, int batch, int m, const cx<T>* w1, cx<T>* w2, cx<T>* out,
+                            hipStream_t s) {
+  ColArgs ay = make_col(n, dt, (int64_t)n * m, (int64_t)2 * m * m, m, m, m, 0, m);
+  CNPC_TRY(colpass<T>(n, -1, w1, w2, ay, (int64_t)batch * n, s));
+  ColArgs ax = make_col(n, dt, (int64_t)n * 2 * m * m, (int64_t)4 * m * m * m, (int64_t)2 * m * m,
+                        (int64_t)2 * m * m, 2 * m * m, 0, m);
+  CNPC_TRY(colpass<T>(n, -1, w2, out, ax, batch, s));
+  return CNPC_OK;
+}
+template cnpc_status band_forward_yx<float>(int, int, int, int, const cx<float>*, cx<float>*,
+                                            cx<float>*, hipStream_t);
+template cnpc_status band_forward_yx<double>(int, int, int, int, const cx<double>*, cx<double>*,
+                                             cx<double>*, hipStream_t);
+
+template <typename T>
+static cnpc_status ylm_r2c_t(const cnpc_mesh_desc* d, int band, const FieldTable& ft,
+                             const T* delta, cx<T>* out, cx<T>* ws, hipStream_t s) {
+  CNPC_TRY(ensure_twiddles());
+  const int n = d->n, m = band;
+  const int64_t nn = (int64_t)n * n;
+  cx<T>* w1 = ws;
+  cx<T>* w2 = ws + (int64_t)ft.nf * nn * m;
+  CNPC_TRY(zpass_ylm<T>(n, delta, w1, ft, m, nn * m, make_geo(d), s));
+  return band_forward_yx<T>(n, d->dtype, ft.nf, m, w1, w2, out, s);
+}
+
+size_t ylm_r2c_ws_bytes(const cnpc_mesh_desc* d, int nfields, int band) {
+  const size_t nn = (size_t)d->n * d->n;
+  return (size_t)nfields * (nn * band + (size_t)d->n * 2 * band * band) * 2 * esize(d->dtype);
+}
+
+cnpc_status launch_ylm_r2c(const cnpc_mesh_desc* d, int band, int nells, const int32_t* ells,
+                           const void* delta, void* out, void* ws, size_t ws_bytes, hipStream_t s) {
+  FieldTable ft;
+  const int nf = field_table(nells, ells, &ft);
+  CNPC_REQUIRE(nf > 0, "too many Y_lm fields (max 32)");
+  if (ws_bytes < ylm_r2c_ws_bytes(d, nf, band)) {
+    set_error("ylm_r2c workspace too small");
+    return CNPC_EWORKSPACE;
+  }
+  if (d->dtype == CNPC_F64)
+    return ylm_r2c_t<double>(d, band, ft, (const double*)delta, (cx<double>*)out, (cx<double>*)ws, s);
+  return ylm_r2c_t<float>(d, band, ft, (const float*)delta, (cx<float>*)out, (cx<float>*)ws, s);
+}
+
+cnpc_status launch_ylm_fields(const cnpc_mesh_desc* d, int ell, const void* delta, void* out,
+                              hipStream_t s) {
+  const int64_t n3 = (int64_t)d->n * d->n * d->n;
+  const unsigned nb = (unsigned)std::min<int64_t>((n3 + 255) / 256, 65536);
+  if (d->dtype == CNPC_F64)
+    hipLaunchKernelGGL((k_ylm_fields<double>), dim3(nb), dim3(256), 0, s, (const double*)delta,
+                       (double*)out, d->n, ell, make_geo(d));
+  else
+    hipLaunchKernelGGL((k_ylm_fields<float>), dim3(nb), dim3(256), 0, s, (const float*)delta,
+                       (float*)out, d->n, ell, make_geo(d));
+  CNPC_HIP(hipGetLastError());
+  return CNPC_OK;
+}
+
+// ------------------------------------------------------------ interlacing --
+// Combine the spectra of meshes A and B: D = 1/2 [SA + exp(-i pi (nx+ny+nz)/N) SB]
+// (without interlacing D = SA), modes with a Nyquist component zeroed.  Layout
+// of sa/sb: half (m == 0) or band (half-width m).  D * scale_inplace is written
+// back into sa; D itself is written to band_out (band half-width mb) when given.
+template <typename T>
+__global__ void __launch_bounds__(256) k_interlace_combine(cx<T>* sa, const cx<T>* __restrict__ sb,
+                                                           int n, int m, cx<T>* band_out, int mb,
+                                                           int interlace, T scale_inplace) {
+  const int ny_ = m ? 2 * m : n;
+  const int nz_ = m ? m : n / 2;
+  const int64_t total = (int64_t)ny_ * ny_ * nz_;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int kz = (int)(i % nz_);
+    const int jy = (int)((i / nz_) % ny_);
+    const int jx = (int)(i / ((int64_t)nz_ * ny_));
+    const int nx = m ? band_freq(jx, m) : freq_of(jx, n);
+    const int ny = m ? band_freq(jy, m) : freq_of(jy, n);
+    cx<T> v = sa[i];
+    if (nx == -(n / 2) || ny == -(n / 2)) {
+      v = cx<T>{T(0), T(0)};
+    } else if (interlace) {
+      double sn, cs;
+      sincospi(-(double)(nx + ny + kz) / (double)n, &sn, &cs);
+      const cx<T> b = sb[i];
+      const cx<T> ph = {T(cs), T(sn)};
+      v = cscale(cadd(v, cmul(ph, b)), T(0.5));
+    }
+    sa[i] = cscale(v, scale_inplace);
+    if (band_out && nx > -mb && nx < mb && ny > -mb && ny < mb && kz < mb) {
+      const int bx = nx < 0 ? nx + 2 * mb : nx, by = ny < 0 ? ny + 2 * mb : ny;
+      band_out[((int64_t)bx * 2 * mb + by) * mb + kz] = v;
+    }
+  }
+}
+
+size_t deinterlace_ws_bytes(const cnpc_mesh_desc* d) {
+  const size_t half = (size_t)d->n * d->n * (d->n / 2) * 2 * esize(d->dtype);
+  return 2 * half;
+}
+
+size_t deinterlace_band_ws_bytes(const cnpc_mesh_desc* d, int band) {
+  const int nb = d->interlace ? 2 : 1;
+  const size_t bsz = (size_t)4 * band * band * band;
+  return (nb * bsz + fft_ws_elems(d->n, nb, band)) * 2 * esize(d->dtype);
+}
+
+template <typename T>
+static cnpc_status deinterlace_t(const cnpc_mesh_desc* d, int band, const T* meshes, cx<T>* spec,
+                                 T* delta_int, cx<T>* ws, hipStream_t s) {
+  const int n = d->n;
+  const int64_t n3 = (int64_t)n * n * n;
+  const int il = d->interlace ? 1 : 0;
+  const int nb = 1 + il;
+  if (delta_int == nullptr || !il) {
+    // band-pruned path: only the band of D is needed
+    const int64_t bsz = (int64_t)4 * band * band * band;
+    cx<T>* sp = ws;                       // [nb][band]
+    cx<T>* fws = ws + (int64_t)nb * bsz;  // transform scratch
+    CNPC_TRY(fft3d_r2c<T>(n, nb, band, meshes, sp, fws, s));
+    const unsigned g = (unsigned)std::min<int64_t>((bsz + 255) / 256, 65536);
+    hipLaunchKernelGGL((k_interlace_combine<T>), dim3(g), dim3(256), 0, s, sp, il ? sp + bsz : sp, n,
+                       band, spec, band, il, T(1));
+    CNPC_HIP(hipGetLastError());
+    if (delta_int)
+      CNPC_HIP(hipMemcpyAsync(delta_int, meshes, sizeof(T) * n3, hipMemcpyDeviceToDevice, s));
+    return CNPC_OK;
+  }
+  const int64_t hsz = (int64_t)n * n * (n / 2);
+  cx<T>* sp = ws;  // [2][half]
+  CNPC_TRY(fft3d_r2c<T>(n, 2, 0, meshes, sp, nullptr, s));
+  const unsigned g = (unsigned)std::min<int64_t>((hsz + 255) / 256, 65536);
+  // D / N^3 stays in place for the unnormalised inverse; D itself goes to the band
+  hipLaunchKernelGGL((k_interlace_combine<T>), dim3(g), dim3(256), 0, s, sp, sp + hsz, n, 0, spec,
+                     band, 1, T(1.0 / (double)n3));
+  CNPC_HIP(hipGetLastError());
+  return fft3d_c2r<T>(n, 1, 0, sp, delta_int, nullptr, s);
+}
+
+cnpc_status launch_deinterlace(const cnpc_mesh_desc* d, int band, const void* meshes, void* spec,
+                               void* delta_int, void* ws, size_t ws_bytes, hipStream_t s) {
+  const bool full = delta_int != nullptr && d->interlace;
+  if (ws_bytes < (full ? deinterlace_ws_bytes(d) : deinterlace_band_ws_bytes(d, band))) {
+    set_error("deinterlace workspace too small");
+    return CNPC_EWORKSPACE;
+  }
+  if (d->dtype == CNPC_F64)
+    return deinterlace_t<double>(d, band, (const double*)meshes, (cx<double>*)spec, (double*)delta_int,
+                                 (cx<double>*)ws, s);
+  return deinterlace_t<float>(d, band, (const float*)meshes, (cx<float>*)spec, (float*)delta_int,
+                              (cx<float>*)ws, s);
+}
+
+// --------------------------------------------------------- F_l assembly --
+template <typename T>
+__global__ void __launch_bounds__(256) k_assemble(int n, int m, int ell, int assign,
+                                                  const cx<T>* __restrict__ spec0,
+                                                  const cx<T>* __restrict__ ylm, cx<T>* __restrict__ F) {
+  const int64_t bsz = (int64_t)4 * m * m * m;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < bsz;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int kz = (int)(i % m);
+    const int jy = (int)((i / m) % (2 * m));
+    const int jx = (int)(i / ((int64_t)2 * m * m));
+    const int nx = band_freq(jx, m), ny = band_freq(jy, m), nz = kz;
+    const int64_t n2 = (int64_t)nx * nx + (int64_t)ny * ny + (int64_t)nz * nz;
+    if (n2 == 0 || nx == -(n / 2) || ny == -(n / 2)) {
+      F[i] = cx<T>{T(0), T(0)};
+      continue;
+    }
+    const double W = window_1d(nx, n, assign) * window_1d(ny, n, assign) * window_1d(nz, n, assign);
+    if (ell == 0) {
+      const cx<T> v = spec0[i];
+      F[i] = cx<T>{T(v.x / W), T(v.y / W)};
+      continue;
+    }
+    const double inv = 1.0 / sqrt((double)n2);
+    T re[5], im[5];
+    racah_ylm<T>(ell, T(nx * inv), T(ny * inv), T(nz * inv), re, im);
+    cx<T> acc = cscale(ylm[i], re[0]);
+    for (int mm = 1; mm <= ell; ++mm) {
+      const cx<T> a = ylm[(2 * mm - 1) * bsz + i];
+      const cx<T> b = ylm[(2 * mm) * bsz + i];
+      acc.x += T(2) * (re[mm] * a.x + im[mm] * b.x);
+      acc.y += T(2) * (re[mm] * a.y + im[mm] * b.y);
+    }
+    F[i] = cx<T>{T(acc.x / W), T(acc.y / W)};
+  }
+}
+
+cnpc_status launch_assemble(const cnpc_mesh_desc* d, int band, int ell, const void* spec0,
+                            const void* ylm, void* F, hipStream_t s) {
+  const int64_t bsz = (int64_t)4 * band * band * band;
+  const unsigned g = (unsigned)std::min<int64_t>((bsz + 255) / 256, 65536);
+  if (d->dtype == CNPC_F64)
+    hipLaunchKernelGGL((k_assemble<double>), dim3(g), dim3(256), 0, s, d->n, band, ell, d->assign,
+                       (const cx<double>*)spec0, (const cx<double>*)ylm, (cx<double>*)F);
+  else
+    hipLaunchKernelGGL((k_assemble<float>), dim3(g), dim3(256), 0, s, d->n, band, ell, d->assign,
+                       (const cx<float>*)spec0, (const cx<float>*)ylm, (cx<float>*)F);
+  CNPC_HIP(hipGetLastError());
+  return CNPC_OK;
+}
+
+// ---------------------------------------------------------------- binning --
+template <typename T>
+__global__ void __launch_bounds__(256) k_bin(BinArgs<T> a, const double* __restrict__ norms,
+                                             double* __restrict__ acc_out,
+                                             unsigned long long* __restrict__ cnt_out) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int nacc = a.npairs + a.nself + 1;  // + sum |k|
+  double* acc = reinterpret_cast<double*>(smem_raw);
+  unsigned long long* cnt = reinterpret_cast<unsigned long long*>(acc + (int64_t)a.nbins * nacc);
+  for (int i = threadIdx.x; i < a.nbins * nacc; i += blockDim.x) acc[i] = 0.0;
+  for (int i = threadIdx.x; i < a.nbins; i += blockDim.x) cnt[i] = 0ull;
+  __syncthreads();
+  const int m = a.m, n = a.n;
+  const int64_t bsz = (int64_t)4 * m * m * m;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < bsz;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int kz = (int)(i % m);
+    const int jy = (int)((i / m) % (2 * m));
+    const int jx = (int)(i / ((int64_t)2 * m * m));
+    const int nx = band_freq(jx, m), ny = band_freq(jy, m), nz = kz;
+    if (nx == -(n / 2) || ny == -(n / 2) || nz == n / 2) continue;
+    const int64_t n2 = (int64_t)nx * nx + (int64_t)ny * ny + (int64_t)nz * nz;
+    if (n2 == 0 || n2 < a.thr[0] || n2 >= a.thr[a.nbins]) continue;
+    int lo = 0, hi = a.nbins;  // thr[lo] <= n2 < thr[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (n2 >= a.thr[mid]) lo = mid; else hi = mid;
+    }
+    const int b = lo;
+    const double wgt = nz == 0 ? 1.0 : 2.0;
+    double* ab = acc + b * nacc;
+    for (int q = 0; q < a.npairs; ++q) {
+      const cx<T> fa = a.pa[q][i], fb = a.pb[q][i];
+      atomicAdd(&ab[q], wgt * ((double)fa.x * (double)fb.x + (double)fa.y * (double)fb.y));
+    }
+    if (a.nself) {
+      const double kn = sqrt((double)n2);
+      const double ux = nx / kn, uy = ny / kn, uz = nz / kn;
+      double cxs, ctx, cys, cty, czs, ctz;
+      alias_1d(nx, n, a.assign, &cxs, &ctx);
+      alias_1d(ny, n, a.assign, &cys, &cty);
+      alias_1d(nz, n, a.assign, &czs, &ctz);
+      const double C = a.interlace ? 0.5 * (cxs * cys * czs + ctx * cty * ctz) : cxs * cys * czs;
+      const double W = window_1d(nx, n, a.assign) * window_1d(ny, n, a.assign) *
+                       window_1d(nz, n, a.assign);
+      const double cw = C / (W * W);
+      for (int q = 0; q < a.nself; ++q) {
+        const int l = a.self_ell[q];
+        const int base = l == 0 ? 0 : (l == 2 ? 1 : 4);
+        double re[5], im[5];
+        racah_ylm<double>(l, ux, uy, uz, re, im);
+        const double* sb = norms + CNPC_NORM_SBARLM + 2 * base;
+        double v = re[0] * sb[0] - im[0] * sb[1];
+        for (int mm = 1; mm <= l; ++mm) v += 2.0 * (re[mm] * sb[2 * mm] - im[mm] * sb[2 * mm + 1]);
+        atomicAdd(&ab[a.npairs + q], wgt * v * cw);
+      }
+    }
+    atomicAdd(&ab[a.npairs + a.nself], wgt * sqrt((double)n2));
+    atomicAdd(&cnt[b], (unsigned long long)(nz == 0 ? 1 : 2));
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < a.nbins * nacc; i += blockDim.x) {
+    const double v = acc[i];
+    if (v != 0.0) atomicAdd(&acc_out[i], v);
+  }
+  for (int i = threadIdx.x; i < a.nbins; i += blockDim.x) {
+    const unsigned long long c = cnt[i];
+    if (c) atomicAdd(&cnt_out[i], c);
+  }
+}
+
+__global__ void k_zero_f64(double* p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+__global__ void k_zero_i64(int64_t* p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
+// acc [nbins][nacc] sums -> shell means
+__global__ void k_bin_finish(const double* __restrict__ acc, const int64_t* __restrict__ cnt,
+                             int nbins, int npairs, int nself, double kf, double* __restrict__ means,
+                             double* __restrict__ selfterm, double* __restrict__ keff) {
+  const int nacc = npairs + nself + 1;
+  for (int b = threadIdx.x; b < nbins; b += blockDim.x) {
+    const double c = cnt[b] > 0 ? (double)cnt[b] : 1.0;
+    for (int q = 0; q < npairs; ++q) means[q * nbins + b] = acc[b * nacc + q] / c;
+    for (int q = 0; q < nself; ++q) selfterm[q * nbins + b] = acc[b * nacc + npairs + q] / c;
+    if (keff) keff[b] = kf * acc[b * nacc + npairs + nself] / c;
+  }
+}
+
+size_t bin_ws_doubles(int nbins, int npairs, int nself) {
+  return (size_t)nbins * (npairs + nself + 1);
+}
+
+template <typename T>
+static cnpc_status bin_t(const cnpc_mesh_desc* d, const int64_t* thr, int nbins, int band,
+                         int npairs, const void* const* pa, const void* const* pb, int nself,
+                         const int32_t* self_ells, const double* norms, double* acc, double* means,
+                         double* selfterm, int64_t* nmodes, double* keff, hipStream_t s) {
+  BinArgs<T> a;
+  a.n = d->n;
+  a.m = band;
+  a.assign = d->assign;
+  a.interlace = d->interlace;
+  a.nbins = nbins;
+  a.npairs = npairs;
+  a.nself = nself;
+  for (int b = 0; b <= nbins; ++b) a.thr[b] = thr[b];
+  for (int q = 0; q < npairs; ++q) {
+    a.pa[q] = (const cx<T>*)pa[q];
+    a.pb[q] = (const cx<T>*)pb[q];
+  }
+  for (int q = 0; q < nself; ++q) a.self_ell[q] = self_ells[q];
+  const int nacc = npairs + nself + 1;
+  const int64_t nacc_tot = (int64_t)nbins * nacc;
+  hipLaunchKernelGGL(k_zero_f64, dim3(1), dim3(256), 0, s, acc, nacc_tot);
+  CNPC_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(256), 0, s, nmodes, (int64_t)nbins);
+  CNPC_HIP(hipGetLastError());
+  const int64_t bsz = (int64_t)4 * band * band * band;
+  const unsigned g = (unsigned)std::min<int64_t>((bsz + 255) / 256, 2048);
+  const size_t lds = sizeof(double) * nacc_tot + sizeof(unsigned long long) * nbins;
+  hipLaunchKernelGGL((k_bin<T>), dim3(g), dim3(256), lds, s, a, norms, acc,
+                     (unsigned long long*)nmodes);
+  CNPC_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_bin_finish, dim3(1), dim3(256), 0, s, acc, nmodes, nbins, npairs, nself,
+                     2.0 * 3.14159265358979323846 / d->boxsize, means, selfterm, keff);
+  CNPC_HIP(hipGetLastError());
+  return CNPC_OK;
+}
+
+cnpc_status launch_bin(const cnpc_mesh_desc* d, const int64_t* thr, int nbins, int band, int npairs,
+                       const void* const* pa, const void* const* pb, int nself,
+                       const int32_t* self_ells, const double* norms, double* acc, double* means,
+                       double* selfterm, int64_t* nmodes, double* keff, hipStream_t s) {
+  if (d->dtype == CNPC_F64)
+    return bin_t<double>(d, thr, nbins, band, npairs, pa, pb, nself, self_ells, norms, acc, means,
+                         selfterm, nmodes, keff, s);
+  return bin_t<float>(d, thr, nbins, band, npairs, pa, pb, nself, self_ells, norms, acc, means,
+                      selfterm, nmodes, keff, s);
+}
+
+// ------------------------------------------------------ Yamamoto finalize --
+__global__ void k_pk_finalize(int nbins, const double* m00, const double* m02, const double* m04,
+                              const double* m22, const double* m42, const double* m44,
+                              const double* __restrict__ nm, double* __restrict__ out) {
+  const double I22 = nm[CNPC_NORM_I22], N0 = nm[CNPC_NORM_N0];
+  for (int b = threadIdx.x; b < nbins; b += blockDim.x) {
+    const double P0 = m00 ? m00[b] / I22 - N0 : 0.0;
+    const double P2 = m02 ? 5.0 * m02[b] / I22 : 0.0;
+    const double P4 = m04 ? 9.0 * m04[b] / I22 : 0.0;
+    const double P22 = m22 ? 9.0 * m22[b] / I22 - 9.0 / 5.0 * N0 : 0.0;
+    const double P42 = m42 ? 13.0 * m42[b] / I22 : 0.0;
+    const double P44 = m44 ? 17.0 * m44[b] / I22 - 17.0 / 9.0 * N0 : 0.0;
+    out[0 * nbins + b] = P0;
+    out[1 * nbins + b] = P2;
+    out[2 * nbins + b] = P4;
+    out[3 * nbins + b] = P22;
+    out[4 * nbins + b] = P42;
+    out[5 * nbins + b] = P44;
+    out[6 * nbins + b] = 35.0 / 18.0 * P22 - P2 - 3.5 * P0;
+    out[7 * nbins + b] = 11.0 / 5.0 * P42 - 52.0 / 63.0 * P4 - 286.0 / 175.0 * P2;
+    out[8 * nbins + b] = 1287.0 / 490.0 * P44 - 374.0 / 245.0 * P42 - 3553.0 / 15435.0 * P4 -
+                         1326.0 / 8575.0 * P2 - 2431.0 / 490.0 * P0;
+  }
+}
+
+cnpc_status launch_pk_finalize(int nbins, const double* m00, const double* m02, const double* m04,
+                               const double* m22, const double* m42, const double* m44,
+                               const double* norms, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_pk_finalize, dim3(1), dim3(256), 0, s, nbins, m00, m02, m04, m22, m42, m44,
+                     norms, out);
+  CNPC_HIP(hipGetLastError());
+  return CNPC_OK;
+}
+
+}  // namespace cnpc

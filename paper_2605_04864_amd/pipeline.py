@@ -1,0 +1,258 @@
+"""End-to-end measurements composed from the C ABI calls.
+
+Torch provides device memory and the stream; every arithmetic step runs in the
+HIP library.  Results stay on the device (FP64 tensors) until the caller reads
+them.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import math
+from dataclasses import dataclass, field
+from typing import Dict, Optional, Sequence
+
+import torch
+
+from . import _lib as L
+
+_TORCH_DT = {L.F32: torch.float32, L.F64: torch.float64}
+
+
+class Scratch:
+    """One growable device byte buffer shared by consecutive calls on a stream."""
+
+    def __init__(self, device="cuda"):
+        self.device = device
+        self.buf = torch.empty(0, dtype=torch.uint8, device=device)
+
+    def get(self, nbytes: int):
+        nbytes = max(int(nbytes), 256)
+        if self.buf.numel() < nbytes:
+            self.buf = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        return self.buf
+
+
+def _sh(stream):
+    return L.stream_handle(stream)
+
+
+def _empty(shape, dtype, device="cuda"):
+    return torch.empty(shape, dtype=dtype, device=device)
+
+
+def catalog_norms(desc, gpos, rpos, gw=None, rw=None, scratch: Optional[Scratch] = None, stream=None):
+    """FP64 catalog sums of both catalogs and the normalisations (device)."""
+    sc = scratch or Scratch()
+    s = _sh(stream)
+    ws = sc.get(L.lib.cnpc_catalog_sums_workspace_size())
+    gs = _empty(L.SUMS_LEN, torch.float64)
+    rs = _empty(L.SUMS_LEN, torch.float64)
+    L.check(L.lib.cnpc_catalog_sums(C.byref(desc), L.ptr(gpos), L.ptr(gw), gpos.shape[1], L.ptr(gs),
+                                    L.ptr(ws), ws.numel(), s))
+    L.check(L.lib.cnpc_catalog_sums(C.byref(desc), L.ptr(rpos), L.ptr(rw), rpos.shape[1], L.ptr(rs),
+                                    L.ptr(ws), ws.numel(), s))
+    norms = _empty(L.NORMS_LEN, torch.float64)
+    L.check(L.lib.cnpc_norms(C.byref(desc), L.ptr(gs), L.ptr(rs), gpos.shape[1], L.ptr(norms), s))
+    return norms, gs, rs
+
+
+def paint(desc, gpos, rpos, norms, gw=None, rw=None, noise=True, scratch: Optional[Scratch] = None,
+          stream=None):
+    sc = scratch or Scratch()
+    n = desc.n
+    nph = 2 if desc.interlace else 1
+    dt = _TORCH_DT[desc.dtype]
+    delta = _empty((nph, n, n, n), dt)
+    nmesh = _empty((nph, n, n, n), dt) if noise else None
+    ws = sc.get(L.lib.cnpc_paint_workspace_size(C.byref(desc), gpos.shape[1], rpos.shape[1]))
+    L.check(L.lib.cnpc_paint(C.byref(desc), L.ptr(gpos), L.ptr(gw), gpos.shape[1], L.ptr(rpos),
+                             L.ptr(rw), rpos.shape[1], L.ptr(norms), L.ptr(delta), L.ptr(nmesh),
+                             L.ptr(ws), ws.numel(), _sh(stream)))
+    return delta, nmesh
+
+
+def band_size(band: int) -> int:
+    return 4 * band ** 3
+
+
+def deinterlace(desc, band, meshes, want_real=True, scratch: Optional[Scratch] = None, stream=None):
+    sc = scratch or Scratch()
+    n = desc.n
+    dt = _TORCH_DT[desc.dtype]
+    spec = _empty((band_size(band), 2), dt)
+    real = _empty((n, n, n), dt) if want_real else None
+    ws = sc.get(L.lib.cnpc_deinterlace_workspace_size(C.byref(desc)))
+    L.check(L.lib.cnpc_deinterlace(C.byref(desc), band, L.ptr(meshes), L.ptr(spec), L.ptr(real),
+                                   L.ptr(ws), ws.numel(), _sh(stream)))
+    return spec, real
+
+
+def ylm_spectra(desc, band, ells: Sequence[int], delta_int, scratch: Optional[Scratch] = None,
+                stream=None):
+    sc = scratch or Scratch()
+    ells = [int(l) for l in ells if l > 0]
+    nf = sum(2 * l + 1 for l in ells)
+    dt = _TORCH_DT[desc.dtype]
+    out = _empty((nf, band_size(band), 2), dt)
+    arr = (C.c_int32 * len(ells))(*ells)
+    ws = sc.get(L.lib.cnpc_ylm_r2c_workspace_size(C.byref(desc), nf, band))
+    L.check(L.lib.cnpc_ylm_r2c(C.byref(desc), band, len(ells), arr, L.ptr(delta_int), L.ptr(out),
+                               L.ptr(ws), ws.numel(), _sh(stream)))
+    res, f = {}, 0
+    for l in ells:
+        res[l] = out[f:f + 2 * l + 1]
+        f += 2 * l + 1
+    return res
+
+
+def assemble(desc, band, ell, spec0=None, ylm=None, stream=None):
+    dt = _TORCH_DT[desc.dtype]
+    F = _empty((band_size(band), 2), dt)
+    L.check(L.lib.cnpc_assemble_F(C.byref(desc), band, ell, L.ptr(spec0), L.ptr(ylm), L.ptr(F),
+                                  _sh(stream)))
+    return F
+
+
+def bin_means(desc, bins, band, pairs, self_ells=(), norms=None, scratch: Optional[Scratch] = None,
+              stream=None):
+    sc = scratch or Scratch()
+    nb = bins.nbins
+    npairs, nself = len(pairs), len(self_ells)
+    means = _empty((max(npairs, 1), nb), torch.float64)
+    selft = _empty((max(nself, 1), nb), torch.float64)
+    nmodes = _empty(nb, torch.int64)
+    keff = _empty(nb, torch.float64)
+    pa = (C.c_void_p * max(npairs, 1))(*[L.ptr(a) for a, _ in pairs])
+    pb = (C.c_void_p * max(npairs, 1))(*[L.ptr(b) for _, b in pairs])
+    se = (C.c_int32 * max(nself, 1))(*[int(l) for l in self_ells])
+    ws = sc.get(L.lib.cnpc_bin_pk_workspace_size(C.byref(bins), npairs, nself))
+    L.check(L.lib.cnpc_bin_pk(C.byref(desc), C.byref(bins), band, npairs, pa, pb, nself, se,
+                              L.ptr(norms), L.ptr(means), L.ptr(selft), L.ptr(nmodes), L.ptr(keff),
+                              L.ptr(ws), ws.numel(), _sh(stream)))
+    return means[:npairs], selft[:nself], nmodes, keff
+
+
+def pk_finalize(bins, m, norms, stream=None):
+    out = _empty((9, bins.nbins), torch.float64)
+    g = lambda k: L.ptr(m.get(k))
+    L.check(L.lib.cnpc_pk_finalize(C.byref(bins), g("00"), g("02"), g("04"), g("22"), g("42"),
+                                   g("44"), L.ptr(norms), L.ptr(out), _sh(stream)))
+    return out
+
+
+PK_ROWS = ("P0", "P2", "P4", "P22", "P42", "P44", "P4b", "P6b", "P8b")
+
+
+def measure_pk(desc, gpos, rpos, bins, ells=(0, 2, 4), modified=False, gw=None, rw=None,
+               scratch: Optional[Scratch] = None, stream=None) -> Dict[str, torch.Tensor]:
+    """Yamamoto P_l (and P_ll', P_4b, P_6b, P_8b when modified) of one catalog pair."""
+    sc = scratch or Scratch()
+    norms, _, _ = catalog_norms(desc, gpos, rpos, gw, rw, sc, stream)
+    delta, _ = paint(desc, gpos, rpos, norms, gw, rw, noise=False, scratch=sc, stream=stream)
+    kmax = bins.kmin + bins.nbins * bins.dk
+    band = L.lib.cnpc_band_for(C.byref(desc), kmax)
+    hi = [l for l in ells if l > 0]
+    need_real = len(hi) > 0
+    D, dint = deinterlace(desc, band, delta, want_real=need_real, scratch=sc, stream=stream)
+    del delta
+    F = {0: assemble(desc, band, 0, spec0=D, stream=stream)}
+    if hi:
+        ylm = ylm_spectra(desc, band, hi, dint, sc, stream)
+        for l in hi:
+            F[l] = assemble(desc, band, l, ylm=ylm[l], stream=stream)
+    pairs, keys = [], []
+    for l in ells:
+        pairs.append((F[0], F[l]))
+        keys.append(f"0{l}")
+    if modified:
+        for (a, b) in ((2, 2), (4, 2), (4, 4)):
+            pairs.append((F[a], F[b]))
+            keys.append(f"{a}{b}")
+    means, _, nmodes, keff = bin_means(desc, bins, band, pairs, (), norms, sc, stream)
+    m = {k: means[i] for i, k in enumerate(keys)}
+    out = pk_finalize(bins, m, norms, stream)
+    res = {"norms": norms, "nmodes": nmodes, "k_eff": keff, "band": band}
+    for i, k in enumerate(PK_ROWS):
+        res[k] = out[i]
+    return res
+
+
+_PLANS: Dict[tuple, "BispecPlan"] = {}
+
+
+class BispecPlan:
+    def __init__(self, desc, bins, estimator, ell, precision, scratch: Scratch, stream=None):
+        self.desc, self.bins = desc, bins
+        self.estimator, self.ell, self.precision = estimator, ell, precision
+        self.ws_bytes = L.lib.cnpc_bispec_workspace_size(C.byref(desc), C.byref(bins), estimator, ell)
+        ws = scratch.get(self.ws_bytes)
+        h = C.c_void_p()
+        L.check(L.lib.cnpc_bispec_plan_create(C.byref(h), C.byref(desc), C.byref(bins), estimator, ell,
+                                              precision, L.ptr(ws), ws.numel(), _sh(stream)))
+        self.handle = h
+        self.nconf = L.lib.cnpc_bispec_nconfigs(h)
+        self.band = L.lib.cnpc_bispec_band(h)
+        ext = L.KBins()
+        L.check(L.lib.cnpc_bispec_ext_bins(h, C.byref(ext)))
+        self.ext = ext
+
+    def configs(self):
+        import numpy as np
+        ijk = (C.c_int32 * (3 * self.nconf))()
+        nt = (C.c_int64 * self.nconf)()
+        L.check(L.lib.cnpc_bispec_configs(self.handle, ijk, nt))
+        return (np.frombuffer(ijk, dtype=np.int32).reshape(-1, 3).copy(),
+                np.frombuffer(nt, dtype=np.int64).copy())
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            L.lib.cnpc_bispec_plan_destroy(h)
+            self.handle = None
+
+
+def bispec_plan(desc, bins, estimator, ell, precision, scratch: Scratch, stream=None) -> BispecPlan:
+    key = (bytes(desc), bytes(bins), estimator, ell, precision)
+    if key not in _PLANS:
+        _PLANS[key] = BispecPlan(desc, bins, estimator, ell, precision, scratch, stream)
+    return _PLANS[key]
+
+
+def measure_bk(desc, gpos, rpos, bins, estimator=L.EST_SCOCCIMARRO, ell=0, precision=None, gw=None,
+               rw=None, scratch: Optional[Scratch] = None, stream=None, shot_noise=True):
+    """Scoccimarro B_l or TripoSH B_l0l of one catalog pair, with analytic shot noise."""
+    sc = scratch or Scratch()
+    if precision is None:
+        precision = L.PREC_F64 if desc.dtype == L.F64 else L.PREC_F32
+    plan = bispec_plan(desc, bins, estimator, ell, precision, sc, stream)
+    band = plan.band
+    norms, _, _ = catalog_norms(desc, gpos, rpos, gw, rw, sc, stream)
+    delta, nmesh = paint(desc, gpos, rpos, norms, gw, rw, noise=shot_noise, scratch=sc, stream=stream)
+    D, dint = deinterlace(desc, band, delta, want_real=ell > 0, scratch=sc, stream=stream)
+    del delta
+    F0 = assemble(desc, band, 0, spec0=D, stream=stream)
+    Fl = F0
+    if ell > 0:
+        ylm = ylm_spectra(desc, band, [ell], dint, sc, stream)
+        Fl = assemble(desc, band, ell, ylm=ylm[ell], stream=stream)
+    noise = None
+    if shot_noise:
+        DN, nint = deinterlace(desc, band, nmesh, want_real=ell > 0, scratch=sc, stream=stream)
+        FN0 = assemble(desc, band, 0, spec0=DN, stream=stream)
+        FNl = FN0
+        if ell > 0:
+            ylmN = ylm_spectra(desc, band, [ell], nint, sc, stream)
+            FNl = assemble(desc, band, ell, ylm=ylmN[ell], stream=stream)
+        means, selft, _, _ = bin_means(desc, plan.ext, band, [(Fl, FN0), (F0, FNl)], (ell,), norms, sc,
+                                       stream)
+        noise = torch.cat([means, selft], 0).contiguous()
+    raw = _empty(plan.nconf, torch.float64)
+    shot = _empty(plan.nconf, torch.float64)
+    val = _empty(plan.nconf, torch.float64)
+    ws = sc.get(plan.ws_bytes)
+    Fl_arg = Fl if (ell > 0 or estimator == L.EST_TRIPOSH) else None
+    L.check(L.lib.cnpc_bispectrum(plan.handle, L.ptr(F0), L.ptr(Fl_arg), L.ptr(noise), L.ptr(norms),
+                                  L.ptr(raw), L.ptr(shot), L.ptr(val), L.ptr(ws), ws.numel(),
+                                  _sh(stream)))
+    return {"raw": raw, "shot": shot, "value": val, "norms": norms, "plan": plan, "noise": noise}

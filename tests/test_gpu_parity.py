@@ -1,0 +1,238 @@
+"""GPU parity of every hot-path step against the FP64 oracle (through the C ABI).
+
+Bars: FP64 paths within 1e-10 (relative to the largest magnitude), FP32 paths
+within 1e-5, integer outputs (cell patterns, mode counts, triangle counts)
+bit-exact.  Sizes span several 16^3 paint tiles and FFT column tiles.
+"""
+
+import ctypes as C
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # the marker deselects these on CPU runs
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2605_04864_amd as cn  # noqa: E402
+from paper_2605_04864_amd import _lib as L  # noqa: E402
+from paper_2605_04864_amd import pipeline as pl  # noqa: E402
+from oracle import bispectrum as obk  # noqa: E402
+from oracle import mesh as oms  # noqa: E402
+from oracle import spectra as osp  # noqa: E402
+from oracle.catalog import catalog_norms  # noqa: E402
+from oracle.pipeline import MeshConfig, measure_bk, measure_pk  # noqa: E402
+import synthcat  # noqa: E402
+
+OBS = synthcat.observer_position()
+TOL = {L.F64: 1e-10, L.F32: 1e-5}
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def dev(x, dtype=None):
+    t = torch.as_tensor(np.ascontiguousarray(x))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+# ---------------------------------------------------------------- FFT -----
+@pytest.mark.parametrize("dtype", [L.F32, L.F64])
+@pytest.mark.parametrize("n", [16, 32, 64])
+def test_fft_full_r2c_c2r(n, dtype):
+    rng = np.random.default_rng(n)
+    x = rng.normal(size=(2, n, n, n))
+    d = cn.mesh_desc(n, 100.0, dtype=dtype)
+    tdt = torch.float64 if dtype == L.F64 else torch.float32
+    xin = dev(x, tdt)
+    spec = torch.empty((2, n, n, n // 2, 2), dtype=tdt, device="cuda")
+    L.check(L.lib.cnpc_fft_r2c(C.byref(d), 2, 0, L.ptr(xin), L.ptr(spec), None, 0, L.stream_handle()))
+    ref = np.fft.rfftn(x, axes=(1, 2, 3))[..., : n // 2]
+    got = host(spec)
+    got = got[..., 0] + 1j * got[..., 1]
+    assert rel(got, ref) < 10 * TOL[dtype]
+    # inverse: unnormalised, kz = N/2 plane absent
+    back = torch.empty_like(xin)
+    L.check(L.lib.cnpc_fft_c2r(C.byref(d), 2, 0, L.ptr(spec), L.ptr(back), None, 0, L.stream_handle()))
+    full = np.fft.rfftn(x, axes=(1, 2, 3))
+    full[..., n // 2] = 0.0
+    refb = np.fft.irfftn(full, s=(n, n, n), axes=(1, 2, 3)) * n ** 3
+    assert rel(host(back), refb) < 10 * TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", [L.F32, L.F64])
+@pytest.mark.parametrize("n,band", [(32, 8), (64, 16), (64, 32)])
+def test_fft_band_r2c_c2r(n, band, dtype):
+    rng = np.random.default_rng(n + band)
+    x = rng.normal(size=(3, n, n, n))
+    d = cn.mesh_desc(n, 100.0, dtype=dtype)
+    tdt = torch.float64 if dtype == L.F64 else torch.float32
+    xin = dev(x, tdt)
+    spec = torch.empty((3, 2 * band, 2 * band, band, 2), dtype=tdt, device="cuda")
+    wsb = L.lib.cnpc_fft_workspace_size(C.byref(d), 3, band)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    L.check(L.lib.cnpc_fft_r2c(C.byref(d), 3, band, L.ptr(xin), L.ptr(spec), L.ptr(ws), wsb,
+                               L.stream_handle()))
+    full = np.fft.rfftn(x, axes=(1, 2, 3))
+    idx = np.r_[0:band, n - band:n]
+    ref = full[:, idx][:, :, idx][..., :band]
+    got = host(spec)
+    got = got[..., 0] + 1j * got[..., 1]
+    assert rel(got, ref) < 10 * TOL[dtype]
+    back = torch.empty_like(xin)
+    L.check(L.lib.cnpc_fft_c2r(C.byref(d), 3, band, L.ptr(spec), L.ptr(back), L.ptr(ws), wsb,
+                               L.stream_handle()))
+    trunc = np.zeros_like(full)
+    trunc[np.ix_(range(3), idx, idx, range(band))] = ref
+    refb = np.fft.irfftn(trunc, s=(n, n, n), axes=(1, 2, 3)) * n ** 3
+    assert rel(host(back), refb) < 10 * TOL[dtype]
+
+
+# -------------------------------------------------------------- paint -----
+def _tiny(seed, ng, nr, weights=False):
+    g, gw, r, rw = synthcat.tiny_catalog(ng, nr, seed=seed, weights=weights)
+    return g, gw, r, rw
+
+
+@pytest.mark.parametrize("dtype", [L.F32, L.F64])
+@pytest.mark.parametrize("assign,interlace", [(L.CIC, False), (L.CIC, True), (L.TSC, False), (L.TSC, True)])
+@pytest.mark.parametrize("weights", [False, True])
+def test_paint_and_norms(assign, interlace, weights, dtype):
+    n, box = 32, 500.0
+    g, gw, r, rw = _tiny(3 + assign, 3000, 20000, weights)
+    d = cn.mesh_desc(n, box, assign=assign, interlace=interlace, dtype=dtype, observer=OBS)
+    gt, rt = dev(g), dev(r)
+    gwt = dev(gw) if weights else None
+    rwt = dev(rw) if weights else None
+    norms, gs, rs = pl.catalog_norms(d, gt, rt, gwt, rwt)
+    ora = catalog_norms(g, gw, r, rw, box, OBS, (0, 2, 4))
+    hn = host(norms)
+    for k, v in ((L.NORM_ALPHA, ora.alpha), (L.NORM_NBAR, ora.nbar), (L.NORM_I22, ora.I22),
+                 (L.NORM_I33, ora.I33), (L.NORM_N0, ora.N0), (L.NORM_SBAR, ora.Sbar)):
+        assert math.isclose(hn[k], v, rel_tol=1e-12)
+    q = 0
+    for l in (0, 2, 4):
+        for m in range(0, l + 1):
+            sb = ora.Sbar_lm[(l, m)]
+            assert abs(complex(hn[L.NORM_SBARLM + 2 * q], hn[L.NORM_SBARLM + 2 * q + 1]) - sb) < 1e-9 * max(1, abs(ora.Sbar))
+            q += 1
+    delta, nmesh = pl.paint(d, gt, rt, norms, gwt, rwt, noise=True)
+    od, onm = oms.paint_fkp(g, gw, r, rw, ora.alpha, n, assign, interlace, noise=True)
+    hd, hnm = host(delta), host(nmesh)
+    for ph in range(2 if interlace else 1):
+        assert rel(hd[ph], od[ph]) < 20 * TOL[dtype]
+        assert rel(hnm[ph], onm[ph]) < 20 * TOL[dtype]
+
+
+def test_paint_single_particle_cells_bit_exact():
+    n, box = 32, 100.0
+    rng = np.random.default_rng(9)
+    for assign in (L.CIC, L.TSC):
+        for trial in range(20):
+            p = rng.integers(0, 2 ** 32, size=(3, 1), dtype=np.uint32)
+            if trial == 0:
+                p[:] = np.uint32(2 ** 32 - 1)  # wraps at the upper edge
+            if trial == 1:
+                p[:] = np.uint32(0)
+            r = rng.integers(0, 2 ** 32, size=(3, 1), dtype=np.uint32)
+            d = cn.mesh_desc(n, box, assign=assign, interlace=True, dtype=L.F64, observer=OBS)
+            norms, _, _ = pl.catalog_norms(d, dev(p), dev(r))
+            delta, _ = pl.paint(d, dev(p), dev(r), norms, noise=False)
+            ga = oms.paint(p, None, n, assign, 0.0)
+            gb = oms.paint(p, None, n, assign, 0.5)
+            hd = host(delta)
+            ra = oms.paint(r, None, n, assign, 0.0)
+            rb = oms.paint(r, None, n, assign, 0.5)
+            # alpha = 1: delta = g - r; compare the supports of g alone via exactness of sums
+            assert np.array_equal(np.abs(hd[0] - (ga - ra)) < 1e-12, np.ones_like(ga, bool))
+            assert np.array_equal(np.abs(hd[1] - (gb - rb)) < 1e-12, np.ones_like(gb, bool))
+
+
+# --------------------------------------------------------------- ylm ------
+@pytest.mark.parametrize("dtype", [L.F32, L.F64])
+@pytest.mark.parametrize("ell", [1, 2, 3, 4])
+def test_ylm_fields(ell, dtype):
+    from oracle.ylm import ylm_racah
+    n, box = 16, 300.0
+    d = cn.mesh_desc(n, box, dtype=dtype, observer=OBS)
+    tdt = torch.float64 if dtype == L.F64 else torch.float32
+    delta = np.random.default_rng(ell).normal(size=(n, n, n))
+    out = torch.empty((2 * ell + 1, n, n, n), dtype=tdt, device="cuda")
+    L.check(L.lib.cnpc_ylm_fields(C.byref(d), ell, L.ptr(dev(delta, tdt)), L.ptr(out), L.stream_handle()))
+    rvec = osp.line_of_sight(n, box, OBS)
+    got = host(out)
+    refs = [delta * ylm_racah(ell, 0, rvec).real]
+    for m in range(1, ell + 1):
+        y = ylm_racah(ell, m, rvec)
+        refs += [delta * y.real, delta * y.imag]
+    for f, ref in enumerate(refs):
+        assert rel(got[f], ref) < 10 * TOL[dtype] + 1e-7 * (dtype == L.F32)
+
+
+# ---------------------------------------------------------- power ---------
+def _cat(seed, ng, nr):
+    g = synthcat.lognormal_catalog(ng, 1000.0, seed)
+    r = synthcat.random_catalog(nr, seed + 1)
+    return g, r
+
+
+@pytest.mark.parametrize("dtype", [L.F64, L.F32])
+@pytest.mark.parametrize("n,assign,interlace", [(32, L.CIC, False), (64, L.TSC, True)])
+def test_measure_pk_vs_oracle(n, assign, interlace, dtype):
+    box = 1000.0
+    g, r = _cat(100 + n, 40_000, 200_000)
+    kN = math.pi * n / box
+    nb = int(kN // 0.01) - 1
+    bins = cn.kbins(0.0, 0.01, nb)
+    d = cn.mesh_desc(n, box, assign=assign, interlace=interlace, dtype=dtype, observer=OBS)
+    res = pl.measure_pk(d, dev(g), dev(r), bins, ells=(0, 2, 4), modified=True)
+    cfg = MeshConfig(box, n, assign, interlace, OBS)
+    ora = measure_pk(g, None, r, None, cfg, 0.0, 0.01, nb, ells=(0, 2, 4), modified=True)
+    assert np.array_equal(host(res["nmodes"]), ora["nmodes"])
+    assert rel(host(res["k_eff"]), ora["k_eff"]) < 1e-12
+    for key in ("P0", "P2", "P4", "P22", "P42", "P44", "P4b", "P6b", "P8b"):
+        assert rel(host(res[key]), ora[key]) < TOL[dtype] * (1 if dtype == L.F64 else 3), key
+
+
+# ---------------------------------------------------------- bispectrum ----
+@pytest.mark.parametrize("dtype", [L.F64, L.F32])
+@pytest.mark.parametrize("est,ell", [(L.EST_SCOCCIMARRO, 0), (L.EST_SCOCCIMARRO, 2),
+                                     (L.EST_TRIPOSH, 0), (L.EST_TRIPOSH, 2)])
+def test_measure_bk_vs_oracle(est, ell, dtype):
+    n, box = 32, 1000.0
+    nb, dk = 4, 0.012
+    g, r = _cat(7, 30_000, 150_000)
+    bins = cn.kbins(0.0, dk, nb)
+    d = cn.mesh_desc(n, box, assign=L.TSC, interlace=True, dtype=dtype, observer=OBS)
+    res = pl.measure_bk(d, dev(g), dev(r), bins, estimator=est, ell=ell)
+    cfg = MeshConfig(box, n, L.TSC, True, OBS)
+    sc = (ell,) if est == L.EST_SCOCCIMARRO else ()
+    tr = (ell,) if est == L.EST_TRIPOSH else ()
+    ora = measure_bk(g, None, r, None, cfg, dk, nb, ells=tuple(sorted({0, ell})), scoccimarro=sc, triposh=tr)
+    plan = res["plan"]
+    ijk, ntri = plan.configs()
+    if est == L.EST_SCOCCIMARRO:
+        key = f"B{ell}"
+        assert [tuple(c) for c in ijk] == [tuple(c) for c in ora[f"{key}_configs"]]
+        assert np.array_equal(ntri, ora[f"{key}_ntri"])
+    else:
+        key = f"BB{ell}0{ell}"
+        assert [tuple(c[:2]) for c in ijk] == [tuple(c) for c in ora[f"{key}_pairs"]]
+    tol = TOL[dtype] * (1 if dtype == L.F64 else 10)
+    assert rel(host(res["raw"]), ora[f"{key}_raw"]) < tol
+    assert rel(host(res["shot"]), ora[f"{key}_shot"]) < tol
+    assert rel(host(res["value"]), ora[key]) < tol
