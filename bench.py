@@ -1,0 +1,293 @@
+#!/usr/bin/env python3
+"""Throughput of the P_l + B_l hot path on one MI355X.
+
+Workload (one "step"): a batch of 64 synthetic lognormal mock catalogs of
+uneven size (N_g log-uniform in [1e6, 8e6], 10x randoms), 256^3 TSC mesh with
+interlacing, L = 1000 Mpc/h, observer 1500 Mpc/h from the box corner; per mock
+the Yamamoto P_0, P_2, P_4 and the Scoccimarro B_0 (20 bins of dk = 0.01,
+825 closed triangles) with analytic shot noise.  Catalogs are resident in HBM
+before timing.  Prints one JSON line.
+
+Also measured: the plain FP64 GPU path (same algorithm, FP64 fields and
+contraction) on a few mocks, per-kernel HIP-event timings of the dominant
+kernel for the roofline, and the FP64 CPU oracle on a bounded sample.
+"""
+
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import ctypes as C
+import json
+import math
+import os
+import sys
+import time
+
+os.environ.setdefault("OPENBLAS_NUM_THREADS", "1")  # the CPU oracle runs single-threaded
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0
+PEAKS_TFLOPS = {"fp32": 157.3, "fp64": 78.6, "bf16": 2500.0}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--mocks", type=int, default=64)
+    ap.add_argument("--precision", choices=["f32", "bf16x3"], default="bf16x3")
+    ap.add_argument("--no-graph", action="store_true", help="launch eagerly instead of one hipGraph")
+    ap.add_argument("--fp64-mocks", type=int, default=2, help="mocks timed on the plain FP64 path")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--quiet", action="store_true")
+    return ap.parse_args()
+
+
+def log(args, *msg):
+    if not args.quiet:
+        print("[bench]", *msg, file=sys.stderr, flush=True)
+
+
+def make_mocks(nmocks: int, workers: int = 16):
+    import synthcat
+    sizes = synthcat.mock_sizes_c4(64)[:nmocks]
+
+    def one(k):
+        ng = int(sizes[k])
+        g = synthcat.lognormal_catalog(ng, 1000.0, 4000 + 2 * k)
+        r = synthcat.random_catalog(10 * ng, 4000 + 2 * k + 1)
+        return g, r
+
+    with cf.ThreadPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(one, range(nmocks))), sizes
+
+
+def algorithmic_bytes(ng, nr, es, n=256):
+    """Per-mock bytes of the staged pipeline: 12 (N_g + N_r) + 50 R + 34 C."""
+    R = n ** 3 * es
+    Cb = n * n * (n // 2 + 1) * 2 * es
+    return 12 * (ng + nr) + 50 * R + 34 * Cb
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU; the mocks are independent and "
+                          "shard across GPUs without communication, but multi-GPU runs are not "
+                          "part of it", "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    import paper_2605_04864_amd as cn
+    from paper_2605_04864_amd import _lib as L
+    from paper_2605_04864_amd import pipeline as pl
+    import synthcat
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t0 = time.time()
+    mocks, sizes = make_mocks(args.mocks)
+    log(args, f"generated {args.mocks} mocks in {time.time() - t0:.1f}s")
+    gpu_mocks = [(torch.from_numpy(g).to(dev), torch.from_numpy(r).to(dev)) for g, r in mocks]
+    torch.cuda.synchronize()
+    log(args, f"uploaded in {time.time() - t0:.1f}s")
+    obs = synthcat.observer_position()
+    bins = cn.kbins(0.0, 0.01, 20)
+    prec = L.PREC_BF16X3 if args.precision == "bf16x3" else L.PREC_F32
+    desc = cn.mesh_desc(256, 1000.0, assign=L.TSC, interlace=True, dtype=L.F32, observer=obs)
+    sc = pl.Scratch()
+    plan = pl.bispec_plan(desc, bins, L.EST_SCOCCIMARRO, 0, prec, sc)
+    outs = [{"pk": torch.empty((9, 20), dtype=torch.float64, device=dev),
+             "bk": torch.empty((3, plan.nconf), dtype=torch.float64, device=dev)} for _ in gpu_mocks]
+
+    def step():
+        for (g, r), o in zip(gpu_mocks, outs):
+            pl.measure_pk_bk(desc, g, r, bins, plan, scratch=sc, out=o)
+
+    step()  # eager pass: plans, twiddles and scratch reach their final size
+    torch.cuda.synchronize()
+    run = step
+    if not args.no_graph:
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            step()
+        run = graph.replay
+        log(args, "captured the batch as one graph")
+    for _ in range(args.warmup):
+        run()
+    torch.cuda.synchronize()
+    log(args, f"warmup done {time.time() - t0:.1f}s")
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    ev0.record()
+    for _ in range(args.steps):
+        run()
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms_step = ev0.elapsed_time(ev1) / args.steps
+    value = args.mocks / (ms_step / 1e3)
+    log(args, f"timed {args.steps} steps: {ms_step:.1f} ms/step (wall {wall:.2f}s)")
+
+    # per-kernel timings of one instrumented step (HIP events on the launch stream)
+    mask = sum(1 << v for v in L.KT.values())
+    L.check(L.lib.cnpc_ktimer_start(mask, 1 << 16))
+    step()
+    ms_cls = (C.c_double * 16)()
+    n_cls = (C.c_int64 * 16)()
+    L.check(L.lib.cnpc_ktimer_stop(ms_cls, n_cls))
+    kern = {k: {"ms": ms_cls[v], "launches": n_cls[v]} for k, v in L.KT.items()}
+    dom = max(kern, key=lambda k: kern[k]["ms"])
+    ntot = int(np.sum(sizes) * 11)
+    es = 4
+    roof = roofline(dom, kern[dom], args.mocks, sizes, es, plan)
+
+    # plain FP64 GPU path: one mock at a time
+    fp64 = None
+    if args.fp64_mocks > 0:
+        d64 = cn.mesh_desc(256, 1000.0, assign=L.TSC, interlace=True, dtype=L.F64, observer=obs)
+        sc64 = pl.Scratch()
+        plan64 = pl.bispec_plan(d64, bins, L.EST_SCOCCIMARRO, 0, L.PREC_F64, sc64)
+        order = np.argsort(sizes)
+        pick = [int(order[len(order) // 2])] + [int(order[0])][: max(0, args.fp64_mocks - 1)]
+        g, r = gpu_mocks[pick[0]]
+        pl.measure_pk_bk(d64, g, r, bins, plan64, scratch=sc64)  # warm
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for k in pick:
+            g, r = gpu_mocks[k]
+            pl.measure_pk_bk(d64, g, r, bins, plan64, scratch=sc64)
+        torch.cuda.synchronize()
+        per = (time.perf_counter() - t) / len(pick)
+        fp64 = {"catalogs_per_s": 1.0 / per, "mocks_timed": [int(sizes[k]) for k in pick],
+                "speedup_fp32_batched": value * per}
+        del sc64
+    cpu = None if args.no_cpu else cpu_baseline(mocks, sizes, log=lambda *m: log(args, *m))
+
+    mean_bytes = np.mean([algorithmic_bytes(int(s), 10 * int(s), es) for s in sizes[: args.mocks]])
+    line = {
+        "metric": "P_l/B_l catalogs/s at 256^3 (batched FP32)",
+        "value": value,
+        "unit": "catalogs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == L.PREC_F32 else "f32+bf16x3",
+        "graph": not args.no_graph,
+        "data": "synthetic lognormal mocks (seeded), resident in HBM",
+        "config": {"workload": "64 uneven lognormal mocks (N_g 1e6-8e6 log-uniform, 10x randoms), "
+                               "256^3 TSC + interlacing, L=1000, P_0,2,4 + Scoccimarro B_0 (20 bins, "
+                               "dk=0.01) with analytic shot noise",
+                   "global_batch": args.mocks, "nmesh": 256, "particles_total": ntot},
+        "pipeline_hbm_frac": (mean_bytes * args.mocks / (ms_step / 1e3)) / (HBM_PEAK_GBS * 1e9),
+        "kernels_ms_per_step": {k: round(v["ms"], 3) for k, v in kern.items()},
+        "roofline": roof,
+        "fp64_plain": fp64,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+def roofline(name, k, nmocks, sizes, es, plan):
+    """Algorithmic traffic / flops of one launch of the dominant kernel class."""
+    n3 = 256 ** 3
+    avg_ms = k["ms"] / max(k["launches"], 1)
+    launches_per_mock = k["launches"] / nmocks
+    mean_np = float(np.mean(sizes[:nmocks])) * 11
+    if name == "contract":
+        nb = 20
+        npairs = nb * (nb + 1) // 2
+        ncols = nb
+        flops = 2.0 * npairs * ncols * n3 / launches_per_mock
+        achieved = flops / (avg_ms * 1e-3) / 1e12
+        return {"kernel": "k_contract", "bound": "alu", "achieved": achieved,
+                "peak": PEAKS_TFLOPS["fp32"], "unit": "TFLOP/s", "frac": achieved / PEAKS_TFLOPS["fp32"],
+                "traffic": None, "avg_launch_ms": avg_ms, "per_launch": f"{flops:.3e} flop"}
+    per_launch_bytes = {
+        "paint": (mean_np * 12) / launches_per_mock,
+        "sort": (mean_np * 12 * 1.5) / launches_per_mock,
+        "fold": (4 * n3 * es + 2 * 4096 * 6859 * es * 2) / launches_per_mock,
+        "zr2c": None, "col": None, "zc2r": None, "bin": None, "sums": mean_np * 12 / launches_per_mock,
+    }
+    b = per_launch_bytes.get(name)
+    if b is None:
+        return {"kernel": name, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": None, "traffic": None, "avg_launch_ms": avg_ms}
+    achieved = b / (avg_ms * 1e-3) / 1e9
+    return {"kernel": name, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "avg_launch_ms": avg_ms}
+
+
+def cpu_baseline(mocks, sizes, log=print):
+    """FP64 oracle on a bounded sample of the smallest mock, extrapolated to one mock.
+
+    Each oracle step is timed on a slice and scaled by the number of times the
+    whole computation repeats it; the sum estimates seconds per catalog."""
+    import synthcat
+    from oracle import bispectrum as obk
+    from oracle import mesh as oms
+    from oracle import spectra as osp
+    from oracle.catalog import catalog_norms
+    from oracle.ylm import Ylm
+    k = int(np.argmin(sizes))
+    g, r = mocks[k]
+    ng, nr = g.shape[1], r.shape[1]
+    n, box = 256, 1000.0
+    obs = synthcat.observer_position()
+    parts = {}
+    frac = 50
+    t = time.perf_counter()
+    catalog_norms(g[:, : ng // frac], None, r[:, : nr // frac], None, box, obs, (0, 2, 4))
+    parts["catalog_sums"] = (time.perf_counter() - t) * frac
+    t = time.perf_counter()
+    oms.paint(r[:, : nr // 20], None, n, oms.TSC, 0.0)
+    # 8 paintings (2 catalogs x 2 interlacing phases x {w, w^2}) of all particles
+    parts["paint"] = (time.perf_counter() - t) * 20 * 8 * (ng + nr) / nr
+    mesh = np.random.default_rng(0).normal(size=(n, n, n))
+    t = time.perf_counter()
+    D = np.fft.fftn(mesh)
+    one_fft = time.perf_counter() - t
+    parts["deinterlace_ffts"] = one_fft * 6  # (A, B, inverse) for delta and N
+    rvec = osp.line_of_sight(n, box, obs)
+    kvec = osp.kvectors(n, box)
+    t = time.perf_counter()
+    S = np.fft.fftn(mesh * Ylm(2, 1, rvec))
+    acc = np.conj(Ylm(2, 1, kvec)) * S
+    one_m = time.perf_counter() - t
+    parts["ylm_weighted_ffts"] = one_m * 14  # 5 (l=2) + 9 (l=4) m values
+    del S, acc, rvec, kvec
+    bins = osp.Bins(0.0, 0.01, 20, box, n)
+    t = time.perf_counter()
+    shells = bins.shell_index()
+    X = obk.shell_field(D, shells, 10)
+    one_shell = time.perf_counter() - t
+    parts["shell_and_indicator_iffts"] = one_shell * 40
+    t = time.perf_counter()
+    for _ in range(8):
+        obk.triple_sum(X, X, X)
+    parts["triple_sums"] = (time.perf_counter() - t) / 8 * 825 * 2  # signal + triangle counts
+    t = time.perf_counter()
+    bins.shell_mean(np.real(D * np.conj(D)))
+    parts["binning"] = (time.perf_counter() - t) * 6
+    total = sum(parts.values())
+    threads = int(os.environ.get("OMP_NUM_THREADS", "1"))
+    log(f"cpu oracle estimate {total:.1f}s per catalog: " +
+        ", ".join(f"{k}={v:.1f}" for k, v in parts.items()))
+    return {"value": 1.0 / total, "unit": "catalogs/s", "cores": 1, "kind": "oracle",
+            "sample": f"smallest mock (N_g={ng}, N_r={nr}), 256^3: each oracle step timed on a "
+                      f"slice (1/50 of the catalog sums, 1/20 of one painting, one 256^3 FFT, one "
+                      f"Y_lm-weighted FFT, one shell inverse FFT, 8 triple sums) and scaled by its "
+                      f"repeat count; numpy FFT single-threaded",
+            "seconds_per_catalog": total, "parts_s": {k: round(v, 2) for k, v in parts.items()},
+            "omp_threads_env": threads}
+
+
+if __name__ == "__main__":
+    main()

@@ -33,7 +33,8 @@
  *    (2M) * (2M) * M complex values, index (jx * 2M + jy) * M + kz with
  *    n = j for j < M and j - 2M otherwise.  Every binned mode lies in the band
  *    when M > k_max / k_f (k_f = 2 pi / L); cnpc_band_for() returns the
- *    smallest such M.
+ *    smallest such M.  Forward band transforms fill the n = -M rows; inverse
+ *    band transforms read them as zero (they have no +M partner).
  *  - Element type follows desc->dtype: float / float2 (CNPC_F32) or
  *    double / double2 (CNPC_F64).  Shell accumulators, catalog sums,
  *    normalisations and shot-noise terms are always FP64.
@@ -263,6 +264,25 @@ cnpc_status cnpc_bispec_ext_bins(const cnpc_bispec_plan* plan, cnpc_kbins* ext);
 cnpc_status cnpc_bispectrum(const cnpc_bispec_plan* plan, const void* F0, const void* Fl,
                             const double* noise_means, const double* norms, double* raw,
                             double* shot, double* value, void* ws, size_t ws_bytes, void* stream);
+
+/* ---- kernel timer (measurement hook for benchmarks and profilers) ----
+ * While started, every launch of a kernel class selected by class_mask (bit
+ * 1 << class) is bracketed by HIP events recorded on its launch stream (at
+ * most max_launches launches in total; later ones are not timed).
+ * cnpc_ktimer_stop synchronises those events and writes, per class (arrays of
+ * 16), the summed kernel time in ms and the number of timed launches.  Not for
+ * use under stream capture.  Host-side state: one timer per process. */
+#define CNPC_KT_PAINT 1    /* tile accumulation */
+#define CNPC_KT_SORT 2     /* tile counting + scatter */
+#define CNPC_KT_FOLD 3     /* block fold into meshes */
+#define CNPC_KT_ZR2C 4     /* z-row r2c passes (plain and Y_lm prologue) */
+#define CNPC_KT_COL 5      /* x / y column passes */
+#define CNPC_KT_ZC2R 6     /* z-row c2r passes */
+#define CNPC_KT_CONTRACT 7 /* bispectrum grid contraction */
+#define CNPC_KT_BIN 8      /* shell binning */
+#define CNPC_KT_SUMS 9     /* catalog sums */
+cnpc_status cnpc_ktimer_start(uint32_t class_mask, int32_t max_launches);
+cnpc_status cnpc_ktimer_stop(double* ms_per_class, int64_t* launches_per_class);
 
 /* Last error message of the calling thread ("" when none). */
 const char* cnpc_last_error(void);

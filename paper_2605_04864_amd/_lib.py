@@ -83,7 +83,12 @@ _PROTOS = {
     "cnpc_bispec_band": (_i32, [_vp]),
     "cnpc_bispec_ext_bins": (_i32, [_vp, _PB]),
     "cnpc_bispectrum": (_i32, [_vp, _cvp, _cvp, _cvp, _cvp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "cnpc_ktimer_start": (_i32, [C.c_uint32, _i32]),
+    "cnpc_ktimer_stop": (_i32, [C.POINTER(_d), C.POINTER(_i64)]),
 }
+
+KT = {"paint": 1, "sort": 2, "fold": 3, "zr2c": 4, "col": 5, "zc2r": 6, "contract": 7, "bin": 8,
+      "sums": 9}
 
 EXPORTED = tuple(_PROTOS)
 

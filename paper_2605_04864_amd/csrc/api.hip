@@ -3,6 +3,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "bispec.h"
 
@@ -36,6 +37,31 @@ size_t lds_limit() {
 }
 
 static bool pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+// ----------------------------------------------------------- kernel timer --
+struct KTimer {
+  uint32_t mask = 0;
+  int used = 0;
+  int open_cls = -1;
+  std::vector<hipEvent_t> ev;
+  std::vector<int> cls;
+};
+static KTimer g_kt;
+
+void kt_begin(int c, hipStream_t s) {
+  if (((g_kt.mask >> c) & 1u) && g_kt.used + 2 <= (int)g_kt.ev.size()) {
+    (void)hipEventRecord(g_kt.ev[g_kt.used], s);
+    g_kt.open_cls = c;
+  }
+}
+void kt_end(int c, hipStream_t s) {
+  if (g_kt.open_cls == c && g_kt.used + 2 <= (int)g_kt.ev.size()) {
+    (void)hipEventRecord(g_kt.ev[g_kt.used + 1], s);
+    g_kt.cls[g_kt.used / 2] = c;
+    g_kt.used += 2;
+    g_kt.open_cls = -1;
+  }
+}
 
 cnpc_status check_desc(const cnpc_mesh_desc* d) {
   CNPC_REQUIRE(d != nullptr, "null mesh descriptor");
@@ -87,6 +113,48 @@ extern "C" {
 
 const char* cnpc_last_error(void) { return g_err.c_str(); }
 const char* cnpc_version(void) { return "cnpc 0.1 (gfx950)"; }
+
+cnpc_status cnpc_ktimer_start(uint32_t class_mask, int32_t max_launches) {
+  API_BEGIN;
+  CNPC_REQUIRE(class_mask != 0 && (class_mask >> 16) == 0, "class mask must select classes 0..15");
+  CNPC_REQUIRE(max_launches >= 1 && max_launches <= (1 << 20), "max_launches out of range");
+  for (hipEvent_t e : g_kt.ev) (void)hipEventDestroy(e);
+  g_kt.ev.assign(2 * (size_t)max_launches, nullptr);
+  g_kt.cls.assign((size_t)max_launches, -1);
+  for (auto& e : g_kt.ev) CNPC_HIP(hipEventCreate(&e));
+  g_kt.used = 0;
+  g_kt.open_cls = -1;
+  g_kt.mask = class_mask;
+  return CNPC_OK;
+}
+
+cnpc_status cnpc_ktimer_stop(double* ms_per_class, int64_t* launches_per_class) {
+  API_BEGIN;
+  double tot[16] = {0};
+  int64_t cnt[16] = {0};
+  cnpc_status st = CNPC_OK;
+  for (int i = 0; i + 1 < g_kt.used; i += 2) {
+    float ms = 0.f;
+    if (hipEventSynchronize(g_kt.ev[i + 1]) != hipSuccess ||
+        hipEventElapsedTime(&ms, g_kt.ev[i], g_kt.ev[i + 1]) != hipSuccess) {
+      set_error("kernel timer events failed");
+      st = CNPC_EHIP;
+      break;
+    }
+    const int c = g_kt.cls[i / 2];
+    if (c >= 0 && c < 16) { tot[c] += ms; cnt[c]++; }
+  }
+  for (int c = 0; c < 16; ++c) {
+    if (ms_per_class) ms_per_class[c] = tot[c];
+    if (launches_per_class) launches_per_class[c] = cnt[c];
+  }
+  for (hipEvent_t e : g_kt.ev) (void)hipEventDestroy(e);
+  g_kt.ev.clear();
+  g_kt.cls.clear();
+  g_kt.used = 0;
+  g_kt.mask = 0;
+  return st;
+}
 
 size_t cnpc_catalog_sums_workspace_size(void) { return (size_t)1024 * CNPC_SUMS_LEN * sizeof(double); }
 
@@ -349,7 +417,6 @@ cnpc_status cnpc_bispectrum(const cnpc_bispec_plan* p, const void* F0, const voi
   CNPC_REQUIRE(F0 && norms && raw && shot && value && ws, "null pointer argument");
   CNPC_REQUIRE(p->ell == 0 || p->est == CNPC_EST_TRIPOSH || Fl != nullptr, "B_l with l > 0 needs F_l");
   CNPC_REQUIRE(p->est != CNPC_EST_TRIPOSH || Fl != nullptr, "TripoSH needs F_l (F_0 for l = 0)");
-  CNPC_REQUIRE(p->prec != CNPC_PREC_BF16X3, "split-BF16 contraction not available in this build");
   return bispec_run(p, F0, Fl, noise_means, norms, raw, shot, value, ws, ws_bytes, as_stream(stream));
 }
 

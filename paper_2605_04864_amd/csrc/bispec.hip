@@ -178,8 +178,10 @@ cnpc_status contract_valu(const T* fields, int64_t npts, int nf, int nshell, con
   }
   for (int p0 = 0; p0 < npairs; p0 += 256) {
     // each launch covers 256 pairs; partials of all launches share the layout
+    kt_begin(CNPC_KT_CONTRACT, s);
     hipLaunchKernelGGL((k_contract<T>), dim3(CONTRACT_BLOCKS), dim3(256), lds, s, fields, npts, nf,
                        nshell, npairs, p0, cc, partial);
+    kt_end(CNPC_KT_CONTRACT, s);
     CNPC_HIP(hipGetLastError());
   }
   const int64_t len = (int64_t)npairs * cc.ncols;
@@ -191,6 +193,158 @@ cnpc_status contract_valu(const T* fields, int64_t npts, int nf, int nshell, con
 
 size_t contract_partial_doubles(int nshell, int ncols) {
   return (size_t)CONTRACT_BLOCKS * nshell * (nshell + 1) / 2 * ncols;
+}
+
+// ------------------------------------------------ split-BF16 MFMA contraction --
+// C[(a,b), c] = sum_x A[x,(a,b)] B[x,c] with A = X_a X_b formed in FP32 and both
+// operands split into bf16 hi + lo; each 32x32 output tile accumulates
+// hi*hi + hi*lo + lo*hi with v_mfma_f32_32x32x16_bf16 in FP32 over the
+// workgroup's slice of grid points, then the slices are summed in FP64.
+// Operand layout of the 32x32x16 bf16 MFMA (64 lanes): lane l holds
+// A[l % 32][8 (l / 32) + e] and B[8 (l / 32) + e][l % 32], e = 0..7; the result
+// register v of lane l is D[8 (v / 4) + 4 (l / 32) + (v % 4)][l % 32].
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ void split_bf16(const float* v, bf16x8_t& hi, bf16x8_t& lo) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const __bf16 h = (__bf16)v[e];
+    hi[e] = h;
+    lo[e] = (__bf16)(v[e] - (float)h);
+  }
+}
+
+constexpr int MF_KC = 64;        // grid points per LDS chunk
+constexpr int MF_PAD = 4;        // row padding (floats) against bank conflicts
+constexpr int MF_ROW = MF_KC + MF_PAD;
+
+template <int TPW>
+__global__ void __launch_bounds__(256) k_contract_mfma(const float* __restrict__ fields, int64_t npts,
+                                                       int nf, int nshell, int npairs, ContractCols cc,
+                                                       int mtiles, int ntiles,
+                                                       double* __restrict__ partial) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  float* tile = reinterpret_cast<float*>(smem_raw);                      // [nf + 1][MF_ROW]
+  unsigned char* pa = reinterpret_cast<unsigned char*>(tile + (nf + 1) * MF_ROW);  // [mtiles*32]
+  unsigned char* pb = pa + mtiles * 32;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int zero_row = nf;  // an all-zero LDS row for padded pairs / columns
+  for (int p = threadIdx.x; p < mtiles * 32; p += blockDim.x) {
+    int a = zero_row, bb = zero_row;
+    if (p < npairs) {
+      int x = 0, rem = p;
+      while (rem >= nshell - x) { rem -= nshell - x; ++x; }
+      a = x;
+      bb = x + rem;
+    }
+    pa[p] = (unsigned char)a;
+    pb[p] = (unsigned char)bb;
+  }
+  for (int i = threadIdx.x; i < MF_ROW; i += blockDim.x) tile[zero_row * MF_ROW + i] = 0.f;
+  // output tiles of this wave: t = wave, wave + 4, ... over mtiles x ntiles
+  const int ntot = mtiles * ntiles;
+  f32x16_t acc[TPW];
+#pragma unroll
+  for (int q = 0; q < TPW; ++q)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[q][v] = 0.f;
+  const int grp = lane >> 5, row = lane & 31;
+  const int64_t per_block = ((npts + gridDim.x - 1) / gridDim.x + MF_KC - 1) / MF_KC * MF_KC;
+  const int64_t x0 = (int64_t)blockIdx.x * per_block;
+  const int64_t x1 = min(npts, x0 + per_block);
+  for (int64_t xb = x0; xb < x1; xb += MF_KC) {
+    const int kt = (int)min((int64_t)MF_KC, x1 - xb);
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < nf * MF_KC; idx += blockDim.x) {
+      const int f = idx / MF_KC, k = idx - f * MF_KC;
+      tile[f * MF_ROW + k] = k < kt ? fields[(int64_t)f * npts + xb + k] : 0.f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < MF_KC / 16; ++ks) {
+      const int k0 = ks * 16 + grp * 8;
+      int cur_m = -1, cur_n = -1;
+      bf16x8_t ahi, alo, bhi, blo;
+#pragma unroll
+      for (int q = 0; q < TPW; ++q) {
+        const int t = wave + 4 * q;
+        if (t < ntot) {
+          const int mt = t / ntiles, nt = t - mt * ntiles;
+          if (mt != cur_m) {
+            const int p = mt * 32 + row;
+            const float* ra = tile + pa[p] * MF_ROW + k0;
+            const float* rb = tile + pb[p] * MF_ROW + k0;
+            float v[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] = ra[e] * rb[e];
+            split_bf16(v, ahi, alo);
+            cur_m = mt;
+          }
+          if (nt != cur_n) {
+            const int j = nt * 32 + row;
+            const int f = j < cc.ncols ? cc.field[j] : zero_row;
+            const float* rc = tile + f * MF_ROW + k0;
+            float v[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] = rc[e];
+            split_bf16(v, bhi, blo);
+            cur_n = nt;
+          }
+          acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, bhi, acc[q], 0, 0, 0);
+          acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, blo, acc[q], 0, 0, 0);
+          acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bhi, acc[q], 0, 0, 0);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < TPW; ++q) {
+    const int t = wave + 4 * q;
+    if (t < ntot) {
+      const int mt = t / ntiles, nt = t - mt * ntiles;
+      const int j = nt * 32 + row;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int p = mt * 32 + 8 * (v / 4) + 4 * grp + (v % 4);
+        if (p < npairs && j < cc.ncols)
+          partial[((int64_t)blockIdx.x * npairs + p) * cc.ncols + j] = (double)acc[q][v];
+      }
+    }
+  }
+}
+
+cnpc_status contract_mfma(const float* fields, int64_t npts, int nf, int nshell, const ContractCols& cc,
+                          double* partial, double* out, hipStream_t s) {
+  const int npairs = nshell * (nshell + 1) / 2;
+  const int mtiles = (npairs + 31) / 32, ntiles = (cc.ncols + 31) / 32;
+  const int tpw = (mtiles * ntiles + 3) / 4;
+  if (nf + 1 > 255 || ntiles > 2) {
+    set_error("split-BF16 contraction supports at most 254 fields and 64 columns");
+    return CNPC_EUNSUPPORTED;
+  }
+  const size_t lds = sizeof(float) * (nf + 1) * MF_ROW + 2 * (size_t)mtiles * 32;
+  kt_begin(CNPC_KT_CONTRACT, s);
+  if (tpw <= 2)
+    hipLaunchKernelGGL((k_contract_mfma<2>), dim3(CONTRACT_BLOCKS), dim3(256), lds, s, fields, npts, nf,
+                       nshell, npairs, cc, mtiles, ntiles, partial);
+  else if (tpw <= 4)
+    hipLaunchKernelGGL((k_contract_mfma<4>), dim3(CONTRACT_BLOCKS), dim3(256), lds, s, fields, npts, nf,
+                       nshell, npairs, cc, mtiles, ntiles, partial);
+  else if (tpw <= 8)
+    hipLaunchKernelGGL((k_contract_mfma<8>), dim3(CONTRACT_BLOCKS), dim3(256), lds, s, fields, npts, nf,
+                       nshell, npairs, cc, mtiles, ntiles, partial);
+  else {
+    set_error("split-BF16 contraction: too many output tiles (%d)", mtiles * ntiles);
+    return CNPC_EUNSUPPORTED;
+  }
+  kt_end(CNPC_KT_CONTRACT, s);
+  CNPC_HIP(hipGetLastError());
+  const int64_t len = (int64_t)npairs * cc.ncols;
+  const unsigned g = (unsigned)std::min<int64_t>((len + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_reduce_blocks, dim3(g), dim3(256), 0, s, partial, CONTRACT_BLOCKS, len, out);
+  CNPC_HIP(hipGetLastError());
+  return CNPC_OK;
 }
 
 // --------------------------------------------------- shell-filtered c2r --
@@ -490,7 +644,14 @@ static cnpc_status bispec_run_t(const cnpc_bispec_plan* P, const cx<T>* F0, cons
     CNPC_TRY(shell_c2r<T>(d, m, Fl, P->thr.data(), nthr, 0, nb, true, fields + (int64_t)nb * n3, scr, s));
   if (P->est == CNPC_EST_TRIPOSH)
     CNPC_TRY(shell_c2r<T>(d, m, Fl, P->thr.data(), nthr, 0, 1, false, fields + (int64_t)nb * n3, scr, s));
-  CNPC_TRY(contract_valu<T>(fields, n3, P->nfields, nb, P->cc, partial, Cm, s));
+  if constexpr (sizeof(T) == 4) {
+    if (P->prec == CNPC_PREC_BF16X3)
+      CNPC_TRY(contract_mfma(fields, n3, P->nfields, nb, P->cc, partial, Cm, s));
+    else
+      CNPC_TRY(contract_valu<T>(fields, n3, P->nfields, nb, P->cc, partial, Cm, s));
+  } else {
+    CNPC_TRY(contract_valu<T>(fields, n3, P->nfields, nb, P->cc, partial, Cm, s));
+  }
   FinArgs f;
   f.est = P->est;
   f.ell = P->ell;

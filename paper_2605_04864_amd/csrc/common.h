@@ -39,6 +39,10 @@ void clear_error();
     if (s_ != CNPC_OK) return s_;   \
   } while (0)
 
+// kernel timer hooks (no-ops unless cnpc_ktimer_start selected the class)
+void kt_begin(int cls, hipStream_t s);
+void kt_end(int cls, hipStream_t s);
+
 cnpc_status check_desc(const cnpc_mesh_desc* d);
 cnpc_status check_bins(const cnpc_mesh_desc* d, const cnpc_kbins* b);
 inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
@@ -127,7 +131,7 @@ __device__ __forceinline__ void racah_ylm(int ell, T x, T y, T z, T* re, T* im) 
       re[2] = c2 * s2r; im[2] = c2 * s2i;
       const T c3 = T(-1.47901994577490951707) * z;  // -sqrt(35)/4
       re[3] = c3 * s3r; im[3] = c3 * s3i;
-      const T c4 = T(0.73950997288745475853);  // sqrt(35/2)/8
+      const T c4 = T(0.52291251658379721749);  // sqrt(35/2)/8
       re[4] = c4 * s4r; im[4] = c4 * s4i;
       break;
     }

@@ -149,8 +149,10 @@ __global__ void __launch_bounds__(256) k_colpass(const cx<T>* in, cx<T>* out, Co
     int j = r;
     bool ok = true;
     if (a.band_in) {
+      // band rows n = -(M-1) .. M-1; the unpaired n = -M row is read as zero so
+      // that inverse transforms see a Hermitian-consistent kz = 0 plane
       if (r < a.band_in) j = r;
-      else if (r >= N - a.band_in) j = r - N + 2 * a.band_in;
+      else if (r > N - a.band_in) j = r - N + 2 * a.band_in;
       else ok = false;
     }
     if (ok && a.mask_m) {
@@ -159,7 +161,8 @@ __global__ void __launch_bounds__(256) k_colpass(const cx<T>* in, cx<T>* out, Co
       const int nx = freq_of(r, N), ny = band_freq(jy, a.mask_m);
       const int64_t n2 = (int64_t)nx * nx + (int64_t)ny * ny + (int64_t)kz * kz;
       const int b = a.mask_b0 + (int)p;
-      ok = n2 > 0 && n2 >= a.thr[b] && n2 < a.thr[b + 1] && nx != -(N / 2) && ny != -(N / 2);
+      ok = n2 > 0 && n2 >= a.thr[b] && n2 < a.thr[b + 1] && nx != -(N / 2) && ny != -(N / 2) &&
+           ny != -a.mask_m;
     }
     A[idx] = ok ? src[(int64_t)j * a.row_in + c] : cx<T>{T(0), T(0)};
   }
@@ -185,8 +188,10 @@ static cnpc_status zr2c_n(const T* in, cx<T>* out, int64_t nrows, int kz, hipStr
   constexpr int NSEQ = ZCfg<T, N>::NSEQ;
   const int64_t blocks = (npairs + NSEQ - 1) / NSEQ;
   const size_t lds = sizeof(cx<T>) * (N + 2 * NSEQ * N);
+  kt_begin(CNPC_KT_ZR2C, s);
   hipLaunchKernelGGL((k_zpass_r2c<T, N>), dim3((unsigned)blocks), dim3(256), lds, s, in, out, npairs,
                      kz);
+  kt_end(CNPC_KT_ZR2C, s);
   CNPC_HIP(hipGetLastError());
   return CNPC_OK;
 }
@@ -197,8 +202,10 @@ static cnpc_status zc2r_n(const cx<T>* in, T* out, int64_t nrows, int kz, hipStr
   constexpr int NSEQ = ZCfg<T, N>::NSEQ;
   const int64_t blocks = (npairs + NSEQ - 1) / NSEQ;
   const size_t lds = sizeof(cx<T>) * (N + 2 * NSEQ * N);
+  kt_begin(CNPC_KT_ZC2R, s);
   hipLaunchKernelGGL((k_zpass_c2r<T, N>), dim3((unsigned)blocks), dim3(256), lds, s, in, out, npairs,
                      kz);
+  kt_end(CNPC_KT_ZC2R, s);
   CNPC_HIP(hipGetLastError());
   return CNPC_OK;
 }
@@ -213,7 +220,9 @@ static cnpc_status col_n(const cx<T>* in, cx<T>* out, const ColArgs& a, int64_t 
     return CNPC_EUNSUPPORTED;
   }
   const size_t lds = sizeof(cx<T>) * (N + 2 * N * a.W);
+  kt_begin(CNPC_KT_COL, s);
   hipLaunchKernelGGL((k_colpass<T, N, DIR>), dim3((unsigned)blocks), dim3(256), lds, s, in, out, a);
+  kt_end(CNPC_KT_COL, s);
   CNPC_HIP(hipGetLastError());
   return CNPC_OK;
 }

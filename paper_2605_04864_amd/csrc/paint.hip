@@ -353,7 +353,9 @@ cnpc_status launch_catalog_sums(const cnpc_mesh_desc* d, const uint32_t* pos, co
   for (int i = 0; i < 3; ++i) { a.obs[i] = d->observer[i]; a.los[i] = d->los[i]; }
   a.global_los = d->los_mode == CNPC_LOS_GLOBAL;
   double* partial = reinterpret_cast<double*>(ws);
+  kt_begin(CNPC_KT_SUMS, s);
   hipLaunchKernelGGL(k_catalog_sums, dim3(nblocks), dim3(256), 0, s, pos, w, n, a, partial);
+  kt_end(CNPC_KT_SUMS, s);
   CNPC_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(64), 0, s, partial, nblocks, sums);
   CNPC_HIP(hipGetLastError());
@@ -432,15 +434,19 @@ static cnpc_status paint_t(const cnpc_mesh_desc* d, const uint32_t* gpos, const 
     const int64_t chunk = (int64_t)SORT_BLOCK * SORT_PER_THREAD;
     const int64_t nblk = (n + chunk - 1) / chunk;
     if (nblk > 0) {
+      kt_begin(CNPC_KT_SORT, s);
       hipLaunchKernelGGL(k_tile_count, dim3((unsigned)nblk), dim3(SORT_BLOCK), lds_sort, s, cpos[c], n,
                          shift, L.nt, L.ntiles, count);
+      kt_end(CNPC_KT_SORT, s);
       CNPC_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, count, L.ntiles, start, cursor);
     CNPC_HIP(hipGetLastError());
     if (nblk > 0) {
+      kt_begin(CNPC_KT_SORT, s);
       hipLaunchKernelGGL(k_tile_scatter, dim3((unsigned)nblk), dim3(SORT_BLOCK), lds_scatter, s,
                          cpos[c], cw[c], n, shift, L.nt, L.ntiles, cursor, spos, sw);
+      kt_end(CNPC_KT_SORT, s);
       CNPC_HIP(hipGetLastError());
     }
     const int npow = weighted ? 2 : 1;
@@ -448,8 +454,10 @@ static cnpc_status paint_t(const cnpc_mesh_desc* d, const uint32_t* gpos, const 
       const int set = weighted ? (pw * 2 + c) : c;
       T* blocks = reinterpret_cast<T*>(ws + L.off_blocks[set]);
       for (int ph0 = 0; ph0 < L.nphase; ph0 += nph) {
+        kt_begin(CNPC_KT_PAINT, s);
         hipLaunchKernelGGL((k_paint_tiles<T>), dim3(L.ntiles), dim3(256), lds_paint, s, spos, sw, n,
                            start, count, shift, L.nt, d->assign, L.nphase, ph0, nph, pw + 1, blocks);
+        kt_end(CNPC_KT_PAINT, s);
         CNPC_HIP(hipGetLastError());
       }
       fa.blocks[set] = blocks;
@@ -457,7 +465,9 @@ static cnpc_status paint_t(const cnpc_mesh_desc* d, const uint32_t* gpos, const 
   }
   const int64_t total = (int64_t)d->n * d->n * d->n * L.nphase;
   const int64_t nb = std::min<int64_t>((total + 255) / 256, 65536);
+  kt_begin(CNPC_KT_FOLD, s);
   hipLaunchKernelGGL((k_fold<T>), dim3((unsigned)nb), dim3(256), 0, s, fa, norms, delta, noise);
+  kt_end(CNPC_KT_FOLD, s);
   CNPC_HIP(hipGetLastError());
   return CNPC_OK;
 }

@@ -134,8 +134,10 @@ static cnpc_status zylm_n(const T* delta, cx<T>* out, const FieldTable& ft, int 
   for (int f0 = 0; f0 < ft.nf; f0 += nfc) {
     const int c = std::min(nfc, ft.nf - f0);
     const size_t lds = sizeof(cx<T>) * (N + 2 * c * N);
+    kt_begin(CNPC_KT_ZR2C, s);
     hipLaunchKernelGGL((k_zpass_ylm<T, N>), dim3(N * (N / 2)), dim3(256), lds, s, delta, out, ft, f0, c,
                        kz, fstride, g);
+    kt_end(CNPC_KT_ZR2C, s);
     CNPC_HIP(hipGetLastError());
   }
   return CNPC_OK;
@@ -490,8 +492,10 @@ static cnpc_status bin_t(const cnpc_mesh_desc* d, const int64_t* thr, int nbins,
   const int64_t bsz = (int64_t)4 * band * band * band;
   const unsigned g = (unsigned)std::min<int64_t>((bsz + 255) / 256, 2048);
   const size_t lds = sizeof(double) * nacc_tot + sizeof(unsigned long long) * nbins;
+  kt_begin(CNPC_KT_BIN, s);
   hipLaunchKernelGGL((k_bin<T>), dim3(g), dim3(256), lds, s, a, norms, acc,
                      (unsigned long long*)nmodes);
+  kt_end(CNPC_KT_BIN, s);
   CNPC_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_bin_finish, dim3(1), dim3(256), 0, s, acc, nmodes, nbins, npairs, nself,
                      2.0 * 3.14159265358979323846 / d->boxsize, means, selfterm, keff);

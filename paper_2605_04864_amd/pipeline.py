@@ -256,3 +256,41 @@ def measure_bk(desc, gpos, rpos, bins, estimator=L.EST_SCOCCIMARRO, ell=0, preci
                                   L.ptr(raw), L.ptr(shot), L.ptr(val), L.ptr(ws), ws.numel(),
                                   _sh(stream)))
     return {"raw": raw, "shot": shot, "value": val, "norms": norms, "plan": plan, "noise": noise}
+
+
+def measure_pk_bk(desc, gpos, rpos, bins, plan: "BispecPlan", ells=(0, 2, 4), gw=None, rw=None,
+                  scratch: Optional[Scratch] = None, stream=None, out=None):
+    """One catalog pair through the whole hot path: P_l (l in ells) and the
+    Scoccimarro B_0 of `plan`, sharing the painting, the de-interlaced F_0 and
+    the shot-noise spectra.  `out` (optional): dict of preallocated result
+    tensors to write into ("pk": [9, nbins], "bk": [3, nconf])."""
+    sc = scratch or Scratch()
+    band = plan.band
+    norms, _, _ = catalog_norms(desc, gpos, rpos, gw, rw, sc, stream)
+    delta, nmesh = paint(desc, gpos, rpos, norms, gw, rw, noise=True, scratch=sc, stream=stream)
+    hi = [l for l in ells if l > 0]
+    D, dint = deinterlace(desc, band, delta, want_real=len(hi) > 0, scratch=sc, stream=stream)
+    DN, _ = deinterlace(desc, band, nmesh, want_real=False, scratch=sc, stream=stream)
+    F = {0: assemble(desc, band, 0, spec0=D, stream=stream)}
+    FN0 = assemble(desc, band, 0, spec0=DN, stream=stream)
+    if hi:
+        ylm = ylm_spectra(desc, band, hi, dint, sc, stream)
+        for l in hi:
+            F[l] = assemble(desc, band, l, ylm=ylm[l], stream=stream)
+    pairs = [(F[0], F[l]) for l in ells] + [(F[0], FN0)]
+    means, selft, nmodes, keff = bin_means(desc, bins, band, pairs, (0,), norms, sc, stream)
+    m = {f"0{l}": means[i] for i, l in enumerate(ells)}
+    pk = pk_finalize(bins, m, norms, stream)
+    q = means[len(ells)]
+    noise = torch.stack([q, q, selft[0]], 0).contiguous()
+    res = out if out is not None else {
+        "pk": _empty((9, bins.nbins), torch.float64),
+        "bk": _empty((3, plan.nconf), torch.float64)}
+    res["pk"].copy_(pk)
+    ws = sc.get(plan.ws_bytes)
+    bk = res["bk"]
+    L.check(L.lib.cnpc_bispectrum(plan.handle, L.ptr(F[0]), None, L.ptr(noise), L.ptr(norms),
+                                  L.ptr(bk[0]), L.ptr(bk[1]), L.ptr(bk[2]), L.ptr(ws), ws.numel(),
+                                  _sh(stream)))
+    res["nmodes"] = nmodes
+    return res
