@@ -192,7 +192,8 @@ cnpc_status contract_valu(const T* fields, int64_t npts, int nf, int nshell, con
 }
 
 size_t contract_partial_doubles(int nshell, int ncols) {
-  return (size_t)CONTRACT_BLOCKS * nshell * (nshell + 1) / 2 * ncols;
+  // room for the split-BF16 kernel's partials (up to 4 point groups per workgroup)
+  return (size_t)CONTRACT_BLOCKS * 4 * nshell * (nshell + 1) / 2 * ncols;
 }
 
 // ------------------------------------------------ split-BF16 MFMA contraction --
@@ -215,22 +216,31 @@ __device__ __forceinline__ void split_bf16(const float* v, bf16x8_t& hi, bf16x8_
   }
 }
 
-constexpr int MF_KC = 64;        // grid points per LDS chunk
+constexpr int MF_KC = 256;       // grid points per LDS chunk (= threads per workgroup)
 constexpr int MF_PAD = 4;        // row padding (floats) against bank conflicts
 constexpr int MF_ROW = MF_KC + MF_PAD;
 
-template <int TPW>
+// The 4 waves of a workgroup form MG = 4 / KG pair groups x KG point groups:
+// wave (mg, kg) owns the m-tiles mg*MTW .. mg*MTW+MTW-1 (32 pairs each) and all
+// NT n-tiles (32 columns each) for the points kg, kg + KG, ... (16-point steps)
+// of every 256-point chunk staged in LDS; the next chunk is prefetched into
+// registers meanwhile.  Splitting the points (KG > 1) keeps each operand split
+// computed once; splitting the pairs (KG = 1) bounds the accumulators per wave.
+template <int MTW, int NT, int KG, int MAXF>
 __global__ void __launch_bounds__(256) k_contract_mfma(const float* __restrict__ fields, int64_t npts,
                                                        int nf, int nshell, int npairs, ContractCols cc,
-                                                       int mtiles, int ntiles,
                                                        double* __restrict__ partial) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  float* tile = reinterpret_cast<float*>(smem_raw);                      // [nf + 1][MF_ROW]
-  unsigned char* pa = reinterpret_cast<unsigned char*>(tile + (nf + 1) * MF_ROW);  // [mtiles*32]
-  unsigned char* pb = pa + mtiles * 32;
+  float* tile = reinterpret_cast<float*>(smem_raw);  // [nf + 1][MF_ROW]
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int zero_row = nf;  // an all-zero LDS row for padded pairs / columns
-  for (int p = threadIdx.x; p < mtiles * 32; p += blockDim.x) {
+  const int mg = wave / KG, kg = wave - mg * KG;
+  const int zero_row = nf;  // all-zero LDS row for padded pairs / columns
+  for (int i = threadIdx.x; i < MF_ROW; i += blockDim.x) tile[zero_row * MF_ROW + i] = 0.f;
+  const int grp = lane >> 5, row = lane & 31;
+  int offa[MTW], offb[MTW];
+#pragma unroll
+  for (int i = 0; i < MTW; ++i) {
+    const int p = (mg * MTW + i) * 32 + row;
     int a = zero_row, bb = zero_row;
     if (p < npairs) {
       int x = 0, rem = p;
@@ -238,111 +248,154 @@ __global__ void __launch_bounds__(256) k_contract_mfma(const float* __restrict__
       a = x;
       bb = x + rem;
     }
-    pa[p] = (unsigned char)a;
-    pb[p] = (unsigned char)bb;
+    offa[i] = a * MF_ROW + grp * 8;
+    offb[i] = bb * MF_ROW + grp * 8;
   }
-  for (int i = threadIdx.x; i < MF_ROW; i += blockDim.x) tile[zero_row * MF_ROW + i] = 0.f;
-  // output tiles of this wave: t = wave, wave + 4, ... over mtiles x ntiles
-  const int ntot = mtiles * ntiles;
-  f32x16_t acc[TPW];
+  int offc[NT];
 #pragma unroll
-  for (int q = 0; q < TPW; ++q)
+  for (int nt = 0; nt < NT; ++nt) {
+    const int j = nt * 32 + row;
+    int f = zero_row;
 #pragma unroll
-    for (int v = 0; v < 16; ++v) acc[q][v] = 0.f;
-  const int grp = lane >> 5, row = lane & 31;
+    for (int c = 0; c < MAX_COLS; ++c)
+      if (c == j && c < cc.ncols) f = cc.field[c];
+    offc[nt] = f * MF_ROW + grp * 8;
+  }
+  f32x16_t acc[MTW][NT];
+#pragma unroll
+  for (int i = 0; i < MTW; ++i)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[i][nt][v] = 0.f;
   const int64_t per_block = ((npts + gridDim.x - 1) / gridDim.x + MF_KC - 1) / MF_KC * MF_KC;
   const int64_t x0 = (int64_t)blockIdx.x * per_block;
   const int64_t x1 = min(npts, x0 + per_block);
+  const float* src = fields + threadIdx.x;
+  float pre[MAXF];
+  {
+    const bool ok = x0 + threadIdx.x < x1;
+#pragma unroll
+    for (int f = 0; f < MAXF; ++f)
+      if (f < nf) pre[f] = ok ? src[(int64_t)f * npts + x0] : 0.f;
+  }
   for (int64_t xb = x0; xb < x1; xb += MF_KC) {
-    const int kt = (int)min((int64_t)MF_KC, x1 - xb);
     __syncthreads();
-    for (int idx = threadIdx.x; idx < nf * MF_KC; idx += blockDim.x) {
-      const int f = idx / MF_KC, k = idx - f * MF_KC;
-      tile[f * MF_ROW + k] = k < kt ? fields[(int64_t)f * npts + xb + k] : 0.f;
+#pragma unroll
+    for (int f = 0; f < MAXF; ++f)
+      if (f < nf) tile[f * MF_ROW + threadIdx.x] = pre[f];
+    __syncthreads();
+    if (xb + MF_KC < x1) {
+      const int64_t xn = xb + MF_KC;
+      const bool ok = xn + threadIdx.x < x1;
+#pragma unroll
+      for (int f = 0; f < MAXF; ++f)
+        if (f < nf) pre[f] = ok ? src[(int64_t)f * npts + xn] : 0.f;
     }
-    __syncthreads();
+    for (int ks = kg * 16; ks < MF_KC; ks += 16 * KG) {
+      bf16x8_t bhi[NT], blo[NT];
 #pragma unroll
-    for (int ks = 0; ks < MF_KC / 16; ++ks) {
-      const int k0 = ks * 16 + grp * 8;
-      int cur_m = -1, cur_n = -1;
-      bf16x8_t ahi, alo, bhi, blo;
+      for (int nt = 0; nt < NT; ++nt) {
+        float v[8];
+        const float* rc = tile + offc[nt] + ks;
 #pragma unroll
-      for (int q = 0; q < TPW; ++q) {
-        const int t = wave + 4 * q;
-        if (t < ntot) {
-          const int mt = t / ntiles, nt = t - mt * ntiles;
-          if (mt != cur_m) {
-            const int p = mt * 32 + row;
-            const float* ra = tile + pa[p] * MF_ROW + k0;
-            const float* rb = tile + pb[p] * MF_ROW + k0;
-            float v[8];
+        for (int e = 0; e < 8; ++e) v[e] = rc[e];
+        split_bf16(v, bhi[nt], blo[nt]);
+      }
+      // no branches: tiles past the last pair read the zero row, so the
+      // accumulators stay in AGPRs across the whole loop
 #pragma unroll
-            for (int e = 0; e < 8; ++e) v[e] = ra[e] * rb[e];
-            split_bf16(v, ahi, alo);
-            cur_m = mt;
-          }
-          if (nt != cur_n) {
-            const int j = nt * 32 + row;
-            const int f = j < cc.ncols ? cc.field[j] : zero_row;
-            const float* rc = tile + f * MF_ROW + k0;
-            float v[8];
+      for (int i = 0; i < MTW; ++i) {
+        float v[8];
+        const float* ra = tile + offa[i] + ks;
+        const float* rb = tile + offb[i] + ks;
 #pragma unroll
-            for (int e = 0; e < 8; ++e) v[e] = rc[e];
-            split_bf16(v, bhi, blo);
-            cur_n = nt;
-          }
-          acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, bhi, acc[q], 0, 0, 0);
-          acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, blo, acc[q], 0, 0, 0);
-          acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bhi, acc[q], 0, 0, 0);
+        for (int e = 0; e < 8; ++e) v[e] = ra[e] * rb[e];
+        bf16x8_t ahi, alo;
+        split_bf16(v, ahi, alo);
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          acc[i][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, bhi[nt], acc[i][nt], 0, 0, 0);
+          acc[i][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, blo[nt], acc[i][nt], 0, 0, 0);
+          acc[i][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bhi[nt], acc[i][nt], 0, 0, 0);
         }
       }
     }
   }
+  // one partial per (workgroup, point group)
+  double* out = partial + ((int64_t)blockIdx.x * KG + kg) * npairs * cc.ncols;
 #pragma unroll
-  for (int q = 0; q < TPW; ++q) {
-    const int t = wave + 4 * q;
-    if (t < ntot) {
-      const int mt = t / ntiles, nt = t - mt * ntiles;
+  for (int i = 0; i < MTW; ++i) {
+    const int mt = mg * MTW + i;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
       const int j = nt * 32 + row;
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const int p = mt * 32 + 8 * (v / 4) + 4 * grp + (v % 4);
-        if (p < npairs && j < cc.ncols)
-          partial[((int64_t)blockIdx.x * npairs + p) * cc.ncols + j] = (double)acc[q][v];
+        if (p < npairs && j < cc.ncols) out[(int64_t)p * cc.ncols + j] = (double)acc[i][nt][v];
       }
     }
   }
+}
+
+template <int MTW, int NT, int KG>
+static cnpc_status launch_mfma(const float* fields, int64_t npts, int nf, int nshell, int npairs,
+                               const ContractCols& cc, double* partial, size_t lds, hipStream_t s) {
+  if (nf <= 24)
+    hipLaunchKernelGGL((k_contract_mfma<MTW, NT, KG, 24>), dim3(CONTRACT_BLOCKS), dim3(256), lds, s,
+                       fields, npts, nf, nshell, npairs, cc, partial);
+  else if (nf <= 48)
+    hipLaunchKernelGGL((k_contract_mfma<MTW, NT, KG, 48>), dim3(CONTRACT_BLOCKS), dim3(256), lds, s,
+                       fields, npts, nf, nshell, npairs, cc, partial);
+  else {
+    set_error("split-BF16 contraction supports at most 48 fields");
+    return CNPC_EUNSUPPORTED;
+  }
+  CNPC_HIP(hipGetLastError());
+  return CNPC_OK;
+}
+
+// partial doubles needed by contract_mfma (4 point groups per workgroup at most)
+size_t contract_mfma_partial_doubles(int nshell, int ncols) {
+  return (size_t)CONTRACT_BLOCKS * 4 * nshell * (nshell + 1) / 2 * ncols;
 }
 
 cnpc_status contract_mfma(const float* fields, int64_t npts, int nf, int nshell, const ContractCols& cc,
                           double* partial, double* out, hipStream_t s) {
   const int npairs = nshell * (nshell + 1) / 2;
   const int mtiles = (npairs + 31) / 32, ntiles = (cc.ncols + 31) / 32;
-  const int tpw = (mtiles * ntiles + 3) / 4;
-  if (nf + 1 > 255 || ntiles > 2) {
-    set_error("split-BF16 contraction supports at most 254 fields and 64 columns");
+  if (ntiles > 2 || mtiles > 32) {
+    set_error("split-BF16 contraction supports at most 64 columns and 1024 pairs");
     return CNPC_EUNSUPPORTED;
   }
-  const size_t lds = sizeof(float) * (nf + 1) * MF_ROW + 2 * (size_t)mtiles * 32;
+  const size_t lds = sizeof(float) * (nf + 1) * MF_ROW;
+  int kgroups = 4;
+  cnpc_status st;
   kt_begin(CNPC_KT_CONTRACT, s);
-  if (tpw <= 2)
-    hipLaunchKernelGGL((k_contract_mfma<2>), dim3(CONTRACT_BLOCKS), dim3(256), lds, s, fields, npts, nf,
-                       nshell, npairs, cc, mtiles, ntiles, partial);
-  else if (tpw <= 4)
-    hipLaunchKernelGGL((k_contract_mfma<4>), dim3(CONTRACT_BLOCKS), dim3(256), lds, s, fields, npts, nf,
-                       nshell, npairs, cc, mtiles, ntiles, partial);
-  else if (tpw <= 8)
-    hipLaunchKernelGGL((k_contract_mfma<8>), dim3(CONTRACT_BLOCKS), dim3(256), lds, s, fields, npts, nf,
-                       nshell, npairs, cc, mtiles, ntiles, partial);
-  else {
-    set_error("split-BF16 contraction: too many output tiles (%d)", mtiles * ntiles);
-    return CNPC_EUNSUPPORTED;
+  // accumulators per wave: MTW * NT * 16 <= 128 registers
+  if (mtiles * ntiles <= 8) {
+    if (ntiles == 1) st = launch_mfma<8, 1, 4>(fields, npts, nf, nshell, npairs, cc, partial, lds, s);
+    else st = launch_mfma<4, 2, 4>(fields, npts, nf, nshell, npairs, cc, partial, lds, s);
+  } else if (mtiles * ntiles <= 16) {
+    kgroups = 2;  // two pair groups of up to 8 tiles
+    if (ntiles == 1) st = launch_mfma<8, 1, 2>(fields, npts, nf, nshell, npairs, cc, partial, lds, s);
+    else st = launch_mfma<4, 2, 2>(fields, npts, nf, nshell, npairs, cc, partial, lds, s);
+  } else {
+    kgroups = 1;  // four pair groups
+    if (ntiles == 1) st = launch_mfma<8, 1, 1>(fields, npts, nf, nshell, npairs, cc, partial, lds, s);
+    else if (mtiles <= 16) st = launch_mfma<4, 2, 1>(fields, npts, nf, nshell, npairs, cc, partial, lds, s);
+    else {
+      set_error("split-BF16 contraction: too many output tiles");
+      st = CNPC_EUNSUPPORTED;
+    }
   }
   kt_end(CNPC_KT_CONTRACT, s);
-  CNPC_HIP(hipGetLastError());
+  if (st != CNPC_OK) return st;
   const int64_t len = (int64_t)npairs * cc.ncols;
   const unsigned g = (unsigned)std::min<int64_t>((len + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_reduce_blocks, dim3(g), dim3(256), 0, s, partial, CONTRACT_BLOCKS, len, out);
+  hipLaunchKernelGGL(k_reduce_blocks, dim3(g), dim3(256), 0, s, partial, CONTRACT_BLOCKS * kgroups, len,
+                     out);
   CNPC_HIP(hipGetLastError());
   return CNPC_OK;
 }

@@ -13,7 +13,7 @@ namespace cnpc {
 constexpr int TILE = 16;
 constexpr int BW = TILE + 3;           // block width: nodes c-1 .. c+2 around tile
 constexpr int BVOL = BW * BW * BW;     // 6859
-constexpr int SORT_BLOCK = 256;
+constexpr int SORT_BLOCK = 1024;
 constexpr int SORT_PER_THREAD = 64;    // particles per thread per sort workgroup
 constexpr int LDS_TILES_MAX = 8192;    // LDS-aggregated sort up to this many tiles
 
@@ -72,14 +72,14 @@ __global__ void __launch_bounds__(256) k_catalog_sums(const uint32_t* __restrict
   }
 }
 
-__global__ void k_reduce_partials(const double* __restrict__ partial, int nblocks,
-                                  double* __restrict__ out) {
-  const int q = threadIdx.x;
-  if (q < CNPC_SUMS_LEN) {
-    double v = 0.0;
-    for (int b = 0; b < nblocks; ++b) v += partial[(int64_t)b * CNPC_SUMS_LEN + q];
-    out[q] = v;
-  }
+__global__ void __launch_bounds__(64) k_reduce_partials(const double* __restrict__ partial, int nblocks,
+                                                        double* __restrict__ out) {
+  // block q sums column q over the partials in a fixed order (deterministic)
+  const int q = blockIdx.x;
+  double v = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += 64) v += partial[(int64_t)b * CNPC_SUMS_LEN + q];
+  v = wave_sum(v);
+  if (threadIdx.x == 0) out[q] = v;
 }
 
 __global__ void k_norms(const double* __restrict__ gs, const double* __restrict__ rs, int64_t ngal,
@@ -235,20 +235,27 @@ __device__ __forceinline__ int stencil_1d(uint32_t p, int shift, int assign, int
   return off;
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256) k_paint_tiles(const uint32_t* __restrict__ spos,
+// Contributions are accumulated as 64-bit fixed point (2^-40 units) with
+// integer LDS atomics: on gfx950 integer LDS atomics run at full rate while
+// FP32 LDS atomics are an order of magnitude slower, and integer sums do not
+// depend on the order in which the threads add (bit-reproducible blocks).
+constexpr double FIX_SCALE = 1099511627776.0;  // 2^40
+constexpr double FIX_INV = 1.0 / 1099511627776.0;
+
+template <typename T, int ASSIGN>
+__global__ void __launch_bounds__(512) k_paint_tiles(const uint32_t* __restrict__ spos,
                                                      const float* __restrict__ sw, int64_t n,
                                                      const uint32_t* __restrict__ start,
                                                      const uint32_t* __restrict__ count, int shift,
-                                                     int nt, int assign, int nphase, int ph0,
-                                                     int nph, int power, T* __restrict__ blocks) {
+                                                     int nphase, int ph0, int nph, int power,
+                                                     T* __restrict__ blocks) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* acc = reinterpret_cast<T*>(smem_raw);  // [nph][BVOL]
+  unsigned long long* acc = reinterpret_cast<unsigned long long*>(smem_raw);  // [nph][BVOL]
   const int t = blockIdx.x;
-  for (int i = threadIdx.x; i < nph * BVOL; i += blockDim.x) acc[i] = T(0);
+  for (int i = threadIdx.x; i < nph * BVOL; i += blockDim.x) acc[i] = 0ull;
   __syncthreads();
   const uint32_t s0 = start[t], cnt = count[t];
-  const int np = assign == CNPC_TSC ? 3 : 2;
+  constexpr int NP = ASSIGN == CNPC_TSC ? 3 : 2;
   for (uint32_t k = threadIdx.x; k < cnt; k += blockDim.x) {
     const int64_t i = (int64_t)s0 + k;
     const uint32_t px = spos[i], py = spos[n + i], pz = spos[2 * n + i];
@@ -263,24 +270,30 @@ __global__ void __launch_bounds__(256) k_paint_tiles(const uint32_t* __restrict_
     for (int q = 0; q < nph; ++q) {
       const int ph = ph0 + q;
       T wx[3], wy[3], wz[3];
-      const int ox = stencil_1d<T>(px, shift, assign, ph, wx);
-      const int oy = stencil_1d<T>(py, shift, assign, ph, wy);
-      const int oz = stencil_1d<T>(pz, shift, assign, ph, wz);
-      T* a = acc + q * BVOL;
-      for (int ix = 0; ix < np; ++ix) {
+      const int ox = stencil_1d<T>(px, shift, ASSIGN, ph, wx);
+      const int oy = stencil_1d<T>(py, shift, ASSIGN, ph, wy);
+      const int oz = stencil_1d<T>(pz, shift, ASSIGN, ph, wz);
+      unsigned long long* a =
+          acc + q * BVOL + (bx + ox) * BW * BW + (by + oy) * BW + (bz + oz);
+#pragma unroll
+      for (int ix = 0; ix < NP; ++ix) {
         const T vx = wv * wx[ix];
-        const int lx = (bx + ox + ix) * BW * BW;
-        for (int iy = 0; iy < np; ++iy) {
+#pragma unroll
+        for (int iy = 0; iy < NP; ++iy) {
           const T vxy = vx * wy[iy];
-          const int lxy = lx + (by + oy + iy) * BW + bz + oz;
-          for (int iz = 0; iz < np; ++iz) atomicAdd(&a[lxy + iz], vxy * wz[iz]);
+#pragma unroll
+          for (int iz = 0; iz < NP; ++iz) {
+            const long long fixv = __double2ll_rn((double)(vxy * wz[iz]) * FIX_SCALE);
+            atomicAdd(&a[ix * BW * BW + iy * BW + iz], (unsigned long long)fixv);
+          }
         }
       }
     }
   }
   __syncthreads();
   T* out = blocks + ((int64_t)t * nphase + ph0) * BVOL;
-  for (int i = threadIdx.x; i < nph * BVOL; i += blockDim.x) out[i] = acc[i];
+  for (int i = threadIdx.x; i < nph * BVOL; i += blockDim.x)
+    out[i] = T((double)(long long)acc[i] * FIX_INV);
 }
 
 // sum of the blocks of set `s` covering node (x, y, z), phase ph
@@ -357,7 +370,7 @@ cnpc_status launch_catalog_sums(const cnpc_mesh_desc* d, const uint32_t* pos, co
   hipLaunchKernelGGL(k_catalog_sums, dim3(nblocks), dim3(256), 0, s, pos, w, n, a, partial);
   kt_end(CNPC_KT_SUMS, s);
   CNPC_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(64), 0, s, partial, nblocks, sums);
+  hipLaunchKernelGGL(k_reduce_partials, dim3(CNPC_SUMS_LEN), dim3(64), 0, s, partial, nblocks, sums);
   CNPC_HIP(hipGetLastError());
   return CNPC_OK;
 }
@@ -414,9 +427,9 @@ static cnpc_status paint_t(const cnpc_mesh_desc* d, const uint32_t* gpos, const 
   const int64_t cn[2] = {ngal, nran};
   const size_t lds_sort = L.ntiles <= LDS_TILES_MAX ? (size_t)L.ntiles * 4 : 0;
   const size_t lds_scatter = L.ntiles <= LDS_TILES_MAX ? (size_t)L.ntiles * 8 : 0;
-  // phases per launch so that the LDS block fits the workgroup limit
-  const int nph = ((size_t)L.nphase * BVOL * sizeof(T) <= lds_limit()) ? L.nphase : 1;
-  const size_t lds_paint = (size_t)nph * BVOL * sizeof(T);
+  // phases per launch so that the 64-bit LDS blocks fit the workgroup limit
+  const int nph = ((size_t)L.nphase * BVOL * 8 <= lds_limit()) ? L.nphase : 1;
+  const size_t lds_paint = (size_t)nph * BVOL * 8;
   FoldArgs<T> fa;
   fa.n = d->n;
   fa.nt = L.nt;
@@ -455,8 +468,12 @@ static cnpc_status paint_t(const cnpc_mesh_desc* d, const uint32_t* gpos, const 
       T* blocks = reinterpret_cast<T*>(ws + L.off_blocks[set]);
       for (int ph0 = 0; ph0 < L.nphase; ph0 += nph) {
         kt_begin(CNPC_KT_PAINT, s);
-        hipLaunchKernelGGL((k_paint_tiles<T>), dim3(L.ntiles), dim3(256), lds_paint, s, spos, sw, n,
-                           start, count, shift, L.nt, d->assign, L.nphase, ph0, nph, pw + 1, blocks);
+        if (d->assign == CNPC_TSC)
+          hipLaunchKernelGGL((k_paint_tiles<T, CNPC_TSC>), dim3(L.ntiles), dim3(512), lds_paint, s, spos,
+                             sw, n, start, count, shift, L.nphase, ph0, nph, pw + 1, blocks);
+        else
+          hipLaunchKernelGGL((k_paint_tiles<T, CNPC_CIC>), dim3(L.ntiles), dim3(512), lds_paint, s, spos,
+                             sw, n, start, count, shift, L.nphase, ph0, nph, pw + 1, blocks);
         kt_end(CNPC_KT_PAINT, s);
         CNPC_HIP(hipGetLastError());
       }
