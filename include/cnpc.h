@@ -223,8 +223,14 @@ cnpc_status cnpc_pk_finalize(const cnpc_kbins* bins, const double* mean00, const
  *   C[(a,b), c] = sum_x X_a^(0) X_b^(0) Y_c,  a <= b,
  * with columns Y = [X^(0) shells, X^(l) shells (Scoccimarro, l > 0), G_l
  * (TripoSH)], cast as a GEMM over grid points.  Then
- *   B_l(i; j, k)   = (2l+1)/I33 C / (N^3 N_T) - N^(l)        (Scoccimarro)
- *   BB_l0l(i, j)   = (2l+1)/I33 C / (N^3 N_i N_j) - N_l0l    (TripoSH)
+ *   B_l(i; j, k)   = (2l+1)/I33 C / (G^3 N_T) - N^(l)        (Scoccimarro)
+ *   BB_l0l(i, j)   = (2l+1)/I33 C / (G^3 N_i N_j) - N_l0l    (TripoSH)
+ * The fields and the sum over x live on a G^3 grid (cnpc_bispec_grid), the
+ * smallest power of two >= 2M with G > c1 + c2 + c3, where c is the largest
+ * |wavevector component| a field holds (shells: below the top bin edge; the
+ * unfiltered TripoSH field: M - 1), capped at the mesh size N.  Below N this
+ * sum over x has no aliased (q1 + q2 + q3 = G) terms, so it equals G^3 times
+ * the sum over exactly closed triangles, as the N^3 sum does.
  * with the analytic shot noise of the shot-noise section (Lemma 1 special
  * case eq. I_l0l, Lemma 2 / eq. g_ell, eqs. Q_ell, H_ell).  Configurations:
  * Scoccimarro l = 0: i <= j <= k; l > 0: any i, j <= k; all closed
@@ -260,6 +266,8 @@ size_t cnpc_bispec_workspace_size(const cnpc_mesh_desc* desc, const cnpc_kbins* 
  * cnpc_bispec_ext_bins (NULL: no shot noise).  Outputs (device FP64, one value
  * per configuration): raw estimator, shot noise, shot-subtracted estimator. */
 int32_t cnpc_bispec_band(const cnpc_bispec_plan* plan);
+/* Side G of the grid the shell fields and the contraction use (<= N). */
+int32_t cnpc_bispec_grid(const cnpc_bispec_plan* plan);
 cnpc_status cnpc_bispec_ext_bins(const cnpc_bispec_plan* plan, cnpc_kbins* ext);
 cnpc_status cnpc_bispectrum(const cnpc_bispec_plan* plan, const void* F0, const void* Fl,
                             const double* noise_means, const double* norms, double* raw,

@@ -81,6 +81,7 @@ _PROTOS = {
     "cnpc_bispec_nconfigs": (_i32, [_vp]),
     "cnpc_bispec_configs": (_i32, [_vp, C.POINTER(_i32), C.POINTER(_i64)]),
     "cnpc_bispec_band": (_i32, [_vp]),
+    "cnpc_bispec_grid": (_i32, [_vp]),
     "cnpc_bispec_ext_bins": (_i32, [_vp, _PB]),
     "cnpc_bispectrum": (_i32, [_vp, _cvp, _cvp, _cvp, _cvp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "cnpc_ktimer_start": (_i32, [C.c_uint32, _i32]),

@@ -354,16 +354,7 @@ cnpc_status cnpc_pk_finalize(const cnpc_kbins* b, const double* m00, const doubl
 
 size_t cnpc_bispec_workspace_size(const cnpc_mesh_desc* d, const cnpc_kbins* b, int32_t est, int32_t ell) {
   if (check_desc(d) != CNPC_OK || check_bins(d, b) != CNPC_OK) return 0;
-  const double kf = 2.0 * M_PI / d->boxsize;
-  const int nb = b->nbins;
-  const double kneed = b->kmin + (est == CNPC_EST_TRIPOSH ? (2 * nb - 1) : nb) * b->dk;
-  int m = 1;
-  while (m < d->n / 2 && (double)m * kf <= kneed) m <<= 1;
-  int nf, nc;
-  if (est == CNPC_EST_TRIPOSH) { nf = nb + 1; nc = 1; }
-  else if (ell == 0) { nf = nb; nc = nb; }
-  else { nf = 2 * nb; nc = nb; }
-  return bispec_ws_bytes(d, nb, m, nf, nc);
+  return bispec_ws_bytes(d, b, est, ell);
 }
 
 cnpc_status cnpc_bispec_plan_create(cnpc_bispec_plan** plan, const cnpc_mesh_desc* d, const cnpc_kbins* b,
@@ -401,6 +392,8 @@ cnpc_status cnpc_bispec_configs(const cnpc_bispec_plan* p, int32_t* ijk, int64_t
 }
 
 int32_t cnpc_bispec_band(const cnpc_bispec_plan* p) { return p ? p->band : 0; }
+
+int32_t cnpc_bispec_grid(const cnpc_bispec_plan* p) { return p ? p->grid : 0; }
 
 cnpc_status cnpc_bispec_ext_bins(const cnpc_bispec_plan* p, cnpc_kbins* ext) {
   API_BEGIN;

@@ -24,8 +24,16 @@ struct FinArgs {
   const double* wq;      // N_c / k_c per extended bin
 };
 
+struct BispecGeom {
+  int band;     // band half-width M of F_0 / F_l
+  int grid;     // side G of the grid the shell fields and the contraction use
+  int nfields;  // real fields per catalog
+  int ncols;    // contraction columns
+};
+
 double g_ell_host(int l, double t);
-size_t bispec_ws_bytes(const cnpc_mesh_desc* d, int nb, int band, int nfields, int ncols);
+BispecGeom bispec_geometry(const cnpc_mesh_desc* d, const cnpc_kbins* b, int est, int ell);
+size_t bispec_ws_bytes(const cnpc_mesh_desc* d, const cnpc_kbins* b, int est, int ell);
 template <typename T>
 cnpc_status contract_valu(const T* fields, int64_t npts, int nf, int nshell, const ContractCols& cc,
                           double* partial, double* out, hipStream_t s);
@@ -36,7 +44,7 @@ struct cnpc_bispec_plan {
   cnpc_mesh_desc desc;
   cnpc_kbins bins, ext;
   int est, ell, prec;
-  int nb, next, band, nfields, nconf;
+  int nb, next, band, grid, nfields, nconf;
   cnpc::ContractCols cc;
   std::vector<int64_t> thr, counts, counts_ext, ntri;
   std::vector<int> cfg;

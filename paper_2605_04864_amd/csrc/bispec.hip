@@ -508,30 +508,60 @@ __global__ void k_fill_ones(cx<double>* p, int64_t n) {
     p[i] = cx<double>{1.0, 0.0};
 }
 
-size_t bispec_ws_bytes(const cnpc_mesh_desc* d, int nb, int band, int nfields, int ncols) {
-  const size_t n3 = (size_t)d->n * d->n * d->n;
+// Band half-width and contraction grid of a bispectrum binning.  Every shell
+// field holds modes with |component| <= c_s = floor(sqrt(T_nb - 1)); the
+// unfiltered TripoSH field F_l holds the band, |component| <= M - 1.  A sum over
+// a G^3 grid of a product of three such fields equals G^3 times the sum over
+// exactly closed triangles q1 + q2 + q3 = 0 as soon as no component of
+// q1 + q2 + q3 can reach +-G, i.e. G > c1 + c2 + c3; the band layout needs
+// G >= 2M.  G is the smallest power of two meeting both, capped at the mesh
+// size (where the sum is the mesh's own, as in the plain estimator).
+BispecGeom bispec_geometry(const cnpc_mesh_desc* d, const cnpc_kbins* b, int est, int ell) {
+  BispecGeom g;
+  const double kf = 2.0 * M_PI / d->boxsize;
+  const int nb = b->nbins;
+  const double kneed = b->kmin + (est == CNPC_EST_TRIPOSH ? (2 * nb - 1) : nb) * b->dk;
+  int m = 1;
+  while (m < d->n / 2 && (double)m * kf <= kneed) m <<= 1;
+  g.band = m;
+  std::vector<int64_t> thr(nb + 1);
+  bin_thresholds(d, b, thr.data());
+  int64_t cs = 0;
+  while ((cs + 1) * (cs + 1) <= thr[nb] - 1) ++cs;
+  const int64_t c3 = est == CNPC_EST_TRIPOSH ? (int64_t)m - 1 : cs;
+  const int64_t need = 2 * cs + c3 + 1;
+  int G = 16;
+  while (G < d->n && (G < need || G < 2 * m)) G <<= 1;
+  g.grid = G;
+  if (est == CNPC_EST_TRIPOSH) { g.nfields = nb + 1; g.ncols = 1; }
+  else if (ell == 0) { g.nfields = nb; g.ncols = nb; }
+  else { g.nfields = 2 * nb; g.ncols = nb; }
+  return g;
+}
+
+size_t bispec_ws_bytes(const cnpc_mesh_desc* d, const cnpc_kbins* b, int est, int ell) {
+  const BispecGeom g = bispec_geometry(d, b, est, ell);
+  const int nb = b->nbins, band = g.band;
+  const size_t g3 = (size_t)g.grid * g.grid * g.grid;
   const size_t es = esize(d->dtype);
   // run time: fields + c2r scratch for all of them + contraction partials/result
-  const size_t run = nfields * n3 * es + shell_c2r_ws_elems(d->n, band, nfields) * 2 * es +
-                     (contract_partial_doubles(nb, ncols) + (size_t)nb * (nb + 1) / 2 * ncols) * 8;
+  const size_t run = g.nfields * g3 * es + shell_c2r_ws_elems(g.grid, band, g.nfields) * 2 * es +
+                     (contract_partial_doubles(nb, g.ncols) + (size_t)nb * (nb + 1) / 2 * g.ncols) * 8;
   // plan time (FP64 indicator fields): ones + fields + scratch + partials
   const size_t bsz = (size_t)4 * band * band * band;
-  const size_t plan = bsz * 16 + (size_t)nb * n3 * 8 + shell_c2r_ws_elems(d->n, band, nb) * 16 +
+  const size_t plan = bsz * 16 + (size_t)nb * g3 * 8 + shell_c2r_ws_elems(g.grid, band, nb) * 16 +
                       (contract_partial_doubles(nb, nb) + (size_t)nb * (nb + 1) / 2 * nb) * 8;
   return (run > plan ? run : plan) + 4096;
 }
 
-static void fields_for(int est, int ell, int nb, int* nfields, ContractCols* cc) {
+static void fields_for(int est, int ell, int nb, ContractCols* cc) {
   if (est == CNPC_EST_TRIPOSH) {
-    *nfields = nb + 1;
     cc->ncols = 1;
     cc->field[0] = nb;
   } else if (ell == 0) {
-    *nfields = nb;
     cc->ncols = nb;
     for (int c = 0; c < nb; ++c) cc->field[c] = c;
   } else {
-    *nfields = 2 * nb;
     cc->ncols = nb;
     for (int c = 0; c < nb; ++c) cc->field[c] = nb + c;
   }
@@ -553,19 +583,15 @@ cnpc_status bispec_plan_create(cnpc_bispec_plan** out, const cnpc_mesh_desc* d, 
   P->nb = b->nbins;
   P->thr.resize(P->nb + 1);
   bin_thresholds(d, b, P->thr.data());
-  const double kf = 2.0 * M_PI / d->boxsize;
-  const double ktop = b->kmin + b->nbins * b->dk;
   // noise spectra binning: TripoSH needs k3 bins up to |i + j| <= 2 nb - 2
   P->ext = *b;
   if (est == CNPC_EST_TRIPOSH) P->ext.nbins = 2 * P->nb - 1;
   P->next = P->ext.nbins;
-  const double kneed = est == CNPC_EST_TRIPOSH ? b->kmin + P->ext.nbins * b->dk : ktop;
-  int m = 1;
-  while (m < d->n / 2 && (double)m * kf <= kneed) m <<= 1;
+  const BispecGeom geo = bispec_geometry(d, b, est, ell);
+  const int m = geo.band, G = geo.grid;
   P->band = m;
-  if ((double)m * kf <= kneed && m >= d->n / 2) {
-    // band = N/2 covers every mode below Nyquist
-  }
+  P->grid = G;
+  P->nfields = geo.nfields;
   P->counts = mode_counts(d, P->thr, P->nb);
   std::vector<int64_t> thr_ext(P->next + 1);
   bin_thresholds(d, &P->ext, thr_ext.data());
@@ -575,7 +601,7 @@ cnpc_status bispec_plan_create(cnpc_bispec_plan** out, const cnpc_mesh_desc* d, 
     const double kc = b->kmin + (c + 0.5) * b->dk;
     P->wq[c] = (double)P->counts_ext[c] / kc;
   }
-  fields_for(est, ell, P->nb, &P->nfields, &P->cc);
+  fields_for(est, ell, P->nb, &P->cc);
   // configurations
   const int nb = P->nb;
   std::vector<int> cfg;
@@ -595,12 +621,12 @@ cnpc_status bispec_plan_create(cnpc_bispec_plan** out, const cnpc_mesh_desc* d, 
   if (est == CNPC_EST_SCOCCIMARRO) {
     // N_T from FP64 indicator fields, once per binning
     unsigned char* w = align256(reinterpret_cast<unsigned char*>(ws));
-    const int64_t n3 = (int64_t)d->n * d->n * d->n;
+    const int64_t g3 = (int64_t)G * G * G;
     const int64_t bsz = (int64_t)4 * m * m * m;
     cx<double>* ones = reinterpret_cast<cx<double>*>(w);
     double* ind = reinterpret_cast<double*>(align256(reinterpret_cast<unsigned char*>(ones + bsz)));
-    cx<double>* scr = reinterpret_cast<cx<double>*>(align256(reinterpret_cast<unsigned char*>(ind + (int64_t)nb * n3)));
-    double* partial = reinterpret_cast<double*>(align256(reinterpret_cast<unsigned char*>(scr + shell_c2r_ws_elems(d->n, m, nb))));
+    cx<double>* scr = reinterpret_cast<cx<double>*>(align256(reinterpret_cast<unsigned char*>(ind + (int64_t)nb * g3)));
+    double* partial = reinterpret_cast<double*>(align256(reinterpret_cast<unsigned char*>(scr + shell_c2r_ws_elems(G, m, nb))));
     double* Cm = partial + contract_partial_doubles(nb, nb);
     const size_t need = (reinterpret_cast<unsigned char*>(Cm + (size_t)nb * (nb + 1) / 2 * nb) -
                          reinterpret_cast<unsigned char*>(ws));
@@ -611,6 +637,7 @@ cnpc_status bispec_plan_create(cnpc_bispec_plan** out, const cnpc_mesh_desc* d, 
     }
     cnpc_mesh_desc d64 = *d;
     d64.dtype = CNPC_F64;
+    d64.n = G;
     hipLaunchKernelGGL(k_fill_ones, dim3(256), dim3(256), 0, s, ones, bsz);
     CNPC_HIP(hipGetLastError());
     CNPC_TRY(ensure_twiddles());
@@ -618,13 +645,13 @@ cnpc_status bispec_plan_create(cnpc_bispec_plan** out, const cnpc_mesh_desc* d, 
     ContractCols c2;
     c2.ncols = nb;
     for (int c = 0; c < nb; ++c) c2.field[c] = c;
-    CNPC_TRY(contract_valu<double>(ind, n3, nb, nb, c2, partial, Cm, s));
+    CNPC_TRY(contract_valu<double>(ind, g3, nb, nb, c2, partial, Cm, s));
     std::vector<double> hC((size_t)nb * (nb + 1) / 2 * nb);
     CNPC_HIP(hipMemcpyAsync(hC.data(), Cm, sizeof(double) * hC.size(), hipMemcpyDeviceToHost, s));
     CNPC_HIP(hipStreamSynchronize(s));
     for (int t = 0; t < ncand; ++t) {
       const int i = cfg[3 * t], j = cfg[3 * t + 1], k = cfg[3 * t + 2];
-      const double v = hC[(size_t)pair_index(j, k, nb) * nb + i] / (double)n3;
+      const double v = hC[(size_t)pair_index(j, k, nb) * nb + i] / (double)g3;
       ntri[t] = (int64_t)llround(v);
     }
   }
@@ -676,7 +703,10 @@ template <typename T>
 static cnpc_status bispec_run_t(const cnpc_bispec_plan* P, const cx<T>* F0, const cx<T>* Fl,
                                 const double* noise, const double* norms, double* raw, double* shot,
                                 double* value, void* ws, size_t ws_bytes, hipStream_t s) {
-  const cnpc_mesh_desc* d = &P->desc;
+  // shell fields live on the contraction grid (P->grid)^3, not on the mesh
+  cnpc_mesh_desc dg = P->desc;
+  dg.n = P->grid;
+  const cnpc_mesh_desc* d = &dg;
   const int n = d->n, m = P->band, nb = P->nb;
   const int64_t n3 = (int64_t)n * n * n;
   unsigned char* w = align256(reinterpret_cast<unsigned char*>(ws));

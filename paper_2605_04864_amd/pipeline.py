@@ -193,6 +193,7 @@ class BispecPlan:
         self.handle = h
         self.nconf = L.lib.cnpc_bispec_nconfigs(h)
         self.band = L.lib.cnpc_bispec_band(h)
+        self.grid = L.lib.cnpc_bispec_grid(h)
         ext = L.KBins()
         L.check(L.lib.cnpc_bispec_ext_bins(h, C.byref(ext)))
         self.ext = ext

@@ -259,6 +259,33 @@ def test_measure_bk_split_bf16_vs_oracle(est, ell):
     assert rel(host(res["value"]), ora[key]) < 1e-3
 
 
+@pytest.mark.parametrize("est,ell,prec", [(L.EST_SCOCCIMARRO, 0, L.PREC_F64), (L.EST_SCOCCIMARRO, 2, L.PREC_BF16X3),
+                                          (L.EST_TRIPOSH, 2, L.PREC_F64), (L.EST_TRIPOSH, 0, L.PREC_BF16X3)])
+def test_measure_bk_reduced_grid_vs_oracle(est, ell, prec):
+    """Shell fields on a 32^3 contraction grid for a 64^3 mesh (k_max far below
+    Nyquist) against the oracle's sum over the full 64^3 mesh."""
+    n, box = 64, 1000.0
+    nb, dk = 4, 0.012
+    g, r = _cat(11, 40_000, 200_000)
+    bins = cn.kbins(0.0, dk, nb)
+    dtype = L.F64 if prec == L.PREC_F64 else L.F32
+    d = cn.mesh_desc(n, box, assign=L.TSC, interlace=True, dtype=dtype, observer=OBS)
+    res = pl.measure_bk(d, dev(g), dev(r), bins, estimator=est, ell=ell, precision=prec)
+    plan = res["plan"]
+    assert plan.grid == 32
+    cfg = MeshConfig(box, n, L.TSC, True, OBS)
+    sc = (ell,) if est == L.EST_SCOCCIMARRO else ()
+    tr = (ell,) if est == L.EST_TRIPOSH else ()
+    ora = measure_bk(g, None, r, None, cfg, dk, nb, ells=tuple(sorted({0, ell})), scoccimarro=sc, triposh=tr)
+    key = f"B{ell}" if est == L.EST_SCOCCIMARRO else f"BB{ell}0{ell}"
+    if est == L.EST_SCOCCIMARRO:
+        ijk, ntri = plan.configs()
+        assert np.array_equal(ntri, ora[f"{key}_ntri"])
+    tol = TOL[L.F64] if prec == L.PREC_F64 else 1e-3
+    assert rel(host(res["raw"]), ora[f"{key}_raw"]) < tol
+    assert rel(host(res["value"]), ora[key]) < tol
+
+
 def test_graph_replay_matches_eager():
     """The batch captured as one graph gives the eager results on every replay."""
     n, box = 32, 1000.0
