@@ -19,8 +19,9 @@ struct FoldArgs {
 };
 
 struct PaintLayout {
-  int nt, ntiles, nphase, nsets;
-  size_t off_spos[2], off_sw[2], off_count[2], off_start[2], off_cursor[2];
+  int nt, ntiles, nphase, nsets, nbuckets;
+  size_t off_rec, off_tmp;  // sorted records, bucket-ordered records (shared by both catalogs)
+  size_t off_count, off_start, off_cursor, off_bcur;
   size_t off_blocks[4];
   size_t total;
 };

@@ -1,7 +1,7 @@
 // Catalog sums, normalisations and FKP mass assignment (CIC / TSC, interlacing).
 //
-// Painting: particles are counting-sorted by 16^3-node tile (LDS-aggregated
-// counts, one global atomic per (workgroup, tile)), each tile's particles are
+// Painting: particles are counting-sorted by 16^3-node tile (two LDS-staged
+// steps: by bucket of tiles, then by tile), each tile's particles are
 // accumulated into a 19^3-node LDS block (the tile plus the stencil halo) with
 // LDS atomics, blocks are written out without atomics, and a fold pass sums
 // the <= 8 blocks covering every node while forming delta = n_g - alpha n_r and
@@ -100,14 +100,38 @@ __global__ void k_norms(const double* __restrict__ gs, const double* __restrict_
 }
 
 // ------------------------------------------------------------------- sort --
-__device__ __forceinline__ int tile_of(uint32_t px, uint32_t py, uint32_t pz, int shift, int nt) {
-  const int tx = (int)(px >> shift) >> 4, ty = (int)(py >> shift) >> 4, tz = (int)(pz >> shift) >> 4;
-  return (tx * nt + ty) * nt + tz;
+// Tiles are numbered bucket-major: a bucket is a cube of S^3 tiles (S = min(4,
+// nt)), key = bucket * S^3 + tile-in-bucket.  The particles of a catalog are
+// moved twice, each time by a counting sort whose workgroups stage their chunk
+// in LDS ordered by key and then store it in per-key runs: first by bucket
+// (few keys, long runs), then by tile inside the bucket.  Records are AoS:
+// (px, py, pz) or (px, py, pz, w bits).
+struct TileGeom {
+  int shift;  // 32 - log2(n): node index = p >> shift
+  int nt;     // tiles per side
+  int ls;     // log2(S)
+  int lnb;    // log2(buckets per side)
+};
+
+template <int RS>
+struct Rec {
+  uint32_t v[RS];
+};
+
+__device__ __forceinline__ int key_of(int tx, int ty, int tz, const TileGeom& g) {
+  const int m = (1 << g.ls) - 1;
+  const int b = ((((tx >> g.ls) << g.lnb) | (ty >> g.ls)) << g.lnb) | (tz >> g.ls);
+  const int l = ((((tx & m) << g.ls) | (ty & m)) << g.ls) | (tz & m);
+  return (b << (3 * g.ls)) | l;
 }
 
-// count[t] += number of particles in tile t (LDS aggregation when it fits)
+__device__ __forceinline__ int tile_key(uint32_t px, uint32_t py, uint32_t pz, const TileGeom& g) {
+  return key_of((int)(px >> g.shift) >> 4, (int)(py >> g.shift) >> 4, (int)(pz >> g.shift) >> 4, g);
+}
+
+// count[key] += number of particles in the tile (LDS aggregation when it fits)
 __global__ void __launch_bounds__(SORT_BLOCK) k_tile_count(const uint32_t* __restrict__ pos, int64_t n,
-                                                           int shift, int nt, int ntiles,
+                                                           TileGeom g, int ntiles,
                                                            uint32_t* __restrict__ count) {
   extern __shared__ uint32_t lcount[];
   const bool lds = ntiles <= LDS_TILES_MAX;
@@ -119,7 +143,7 @@ __global__ void __launch_bounds__(SORT_BLOCK) k_tile_count(const uint32_t* __res
     __syncthreads();
   }
   for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-    const int t = tile_of(pos[i], pos[n + i], pos[2 * n + i], shift, nt);
+    const int t = tile_key(pos[i], pos[n + i], pos[2 * n + i], g);
     if (lds) atomicAdd(&lcount[t], 1u);
     else atomicAdd(&count[t], 1u);
   }
@@ -132,65 +156,147 @@ __global__ void __launch_bounds__(SORT_BLOCK) k_tile_count(const uint32_t* __res
   }
 }
 
-// exclusive scan of count -> start, cursor = start (one workgroup)
-__global__ void __launch_bounds__(1024) k_tile_scan(const uint32_t* __restrict__ count, int ntiles,
-                                                    uint32_t* __restrict__ start,
-                                                    uint32_t* __restrict__ cursor) {
-  __shared__ uint32_t part[1024];
-  const int per = (ntiles + 1023) / 1024;
-  const int t0 = threadIdx.x * per;
+// Exclusive scan of R values by a workgroup of NT threads: emit(r, sum_{q < r}
+// in[q]) for every r, each thread handling a run of consecutive r.  Wave
+// prefix sums plus one LDS slot per wave (wsum, NT / 64 entries).
+template <int NT, typename Emit>
+__device__ void block_exclusive_scan(const uint32_t* in, int R, uint32_t* wsum, Emit emit) {
+  const int per = (R + NT - 1) / NT;
+  const int t0 = threadIdx.x * per, t1 = min(R, t0 + per);
   uint32_t s = 0;
-  for (int t = t0; t < min(ntiles, t0 + per); ++t) s += count[t];
-  part[threadIdx.x] = s;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    const uint32_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
-    __syncthreads();
-    part[threadIdx.x] += v;
-    __syncthreads();
+  for (int t = t0; t < t1; ++t) s += in[t];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint32_t v = s;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t u = __shfl_up(v, off, 64);
+    if (lane >= off) v += u;
   }
-  uint32_t run = part[threadIdx.x] - s;
-  for (int t = t0; t < min(ntiles, t0 + per); ++t) {
-    start[t] = run;
-    cursor[t] = run;
-    run += count[t];
+  if (lane == 63) wsum[wv] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (int k = 0; k < NT / 64; ++k) {
+      const uint32_t c = wsum[k];
+      wsum[k] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+  uint32_t run = wsum[wv] + v - s;
+  for (int t = t0; t < t1; ++t) {
+    emit(t, run);
+    run += in[t];
   }
 }
 
-__global__ void __launch_bounds__(SORT_BLOCK) k_tile_scatter(const uint32_t* __restrict__ pos,
-                                                             const float* __restrict__ w, int64_t n,
-                                                             int shift, int nt, int ntiles,
-                                                             uint32_t* __restrict__ cursor,
-                                                             uint32_t* __restrict__ spos,
-                                                             float* __restrict__ sw) {
-  extern __shared__ uint32_t lmem[];
-  const bool lds = ntiles <= LDS_TILES_MAX;
-  uint32_t* lcount = lmem;
-  uint32_t* lbase = lmem + (lds ? ntiles : 0);
-  const int64_t chunk = (int64_t)SORT_BLOCK * SORT_PER_THREAD;
-  const int64_t i0 = (int64_t)blockIdx.x * chunk;
-  const int64_t i1 = min(n, i0 + chunk);
-  if (lds) {
-    for (int t = threadIdx.x; t < ntiles; t += blockDim.x) lcount[t] = 0;
-    __syncthreads();
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x)
-      atomicAdd(&lcount[tile_of(pos[i], pos[n + i], pos[2 * n + i], shift, nt)], 1u);
-    __syncthreads();
-    for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
-      const uint32_t c = lcount[t];
-      lbase[t] = c ? atomicAdd(&cursor[t], c) : 0u;
-      lcount[t] = 0;
-    }
-    __syncthreads();
+// start[key] = exclusive scan of count, cursor = start, bucket cursor
+// bcur[b] = start[b * S^3] (one workgroup)
+__global__ void __launch_bounds__(1024) k_tile_scan(const uint32_t* __restrict__ count, int ntiles,
+                                                    int per_bucket, uint32_t* __restrict__ start,
+                                                    uint32_t* __restrict__ cursor,
+                                                    uint32_t* __restrict__ bcur) {
+  __shared__ uint32_t wsum[16];
+  block_exclusive_scan<1024>(count, ntiles, wsum, [&](int t, uint32_t v) {
+    start[t] = v;
+    cursor[t] = v;
+    if (t % per_bucket == 0) bcur[t / per_bucket] = v;
+  });
+}
+
+constexpr int PART_THREADS = 1024;
+
+// Size in bytes of the LDS layout of k_partition.
+__host__ __device__ constexpr size_t partition_lds(int per, int rs, int rcap) {
+  return (size_t)PART_THREADS * per * (rs * 4 + 2) + (size_t)3 * rcap * 4 + 64;
+}
+
+// One counting-sort step over a chunk of PART_THREADS * PER particles.
+// SOA: input is the catalog (pos [3][n], optional w), else records.
+// FINE == false: key = bucket (rcap = number of buckets).
+// FINE == true, SOA: key = tile key (rcap = number of tiles, one bucket).
+// FINE == true, records in bucket order: key = tile key; the chunk's keys lie
+// in [bucket(first) S^3, (bucket(last) + 1) S^3); if that range is wider than
+// rcap the chunk takes one global atomic per particle instead.
+// cursor[key] hands out output slots (initialised to the key's start).
+template <bool SOA, bool FINE, int RS, int PER>
+__global__ void __launch_bounds__(PART_THREADS) k_partition(const uint32_t* __restrict__ pos,
+                                                            const float* __restrict__ w,
+                                                            const Rec<RS>* __restrict__ rin,
+                                                            int64_t n, TileGeom g, int rcap,
+                                                            uint32_t* __restrict__ cursor,
+                                                            Rec<RS>* __restrict__ rout) {
+  constexpr int CH = PART_THREADS * PER;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  Rec<RS>* stage = reinterpret_cast<Rec<RS>*>(smem_raw);                        // [CH]
+  uint16_t* skey = reinterpret_cast<uint16_t*>(smem_raw + (size_t)CH * RS * 4);  // [CH]
+  uint32_t* hist = reinterpret_cast<uint32_t*>(smem_raw + (size_t)CH * (RS * 4 + 2));
+  uint32_t* lstart = hist + rcap;
+  uint32_t* gbase = lstart + rcap;
+  uint32_t* wsum = gbase + rcap;  // 16 slots
+  const int64_t c0 = (int64_t)blockIdx.x * CH;
+  const int bshift = 3 * g.ls;
+  int klo = 0, R;
+  if (FINE && !SOA) {
+    const Rec<RS> a = rin[c0], b = rin[min(n, c0 + CH) - 1];
+    const int kb0 = tile_key(a.v[0], a.v[1], a.v[2], g) >> bshift;
+    const int kb1 = tile_key(b.v[0], b.v[1], b.v[2], g) >> bshift;
+    klo = kb0 << bshift;
+    R = (kb1 - kb0 + 1) << bshift;
+  } else {
+    R = rcap;
   }
-  for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-    const uint32_t px = pos[i], py = pos[n + i], pz = pos[2 * n + i];
-    const int t = tile_of(px, py, pz, shift, nt);
-    const uint32_t slot = lds ? lbase[t] + atomicAdd(&lcount[t], 1u) : atomicAdd(&cursor[t], 1u);
-    spos[slot] = px;
-    spos[n + slot] = py;
-    spos[2 * n + slot] = pz;
-    if (w) sw[slot] = w[i];
+  Rec<RS> r[PER];
+  int key[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int64_t i = c0 + (int64_t)k * PART_THREADS + threadIdx.x;
+    key[k] = -1;
+    if (i < n) {
+      if (!SOA) {
+        r[k] = rin[i];
+      } else {
+        r[k].v[0] = pos[i];
+        r[k].v[1] = pos[n + i];
+        r[k].v[2] = pos[2 * n + i];
+        if constexpr (RS == 4) r[k].v[3] = __float_as_uint(w[i]);
+      }
+      const int t = tile_key(r[k].v[0], r[k].v[1], r[k].v[2], g);
+      key[k] = FINE ? t - klo : (t >> bshift);
+    }
+  }
+  if (FINE && !SOA && R > rcap) {
+    // wide key range: one global slot per particle
+#pragma unroll
+    for (int k = 0; k < PER; ++k)
+      if (key[k] >= 0) rout[atomicAdd(&cursor[klo + key[k]], 1u)] = r[k];
+    return;
+  }
+  for (int t = threadIdx.x; t < R; t += PART_THREADS) hist[t] = 0u;
+  __syncthreads();
+  uint32_t rank[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k)
+    if (key[k] >= 0) rank[k] = atomicAdd(&hist[key[k]], 1u);
+  __syncthreads();
+  block_exclusive_scan<PART_THREADS>(hist, R, wsum, [&](int t, uint32_t v) {
+    lstart[t] = v;
+    const uint32_t c = hist[t];
+    gbase[t] = c ? atomicAdd(&cursor[klo + t], c) : 0u;
+  });
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < PER; ++k)
+    if (key[k] >= 0) {
+      const uint32_t slot = lstart[key[k]] + rank[k];
+      stage[slot] = r[k];
+      skey[slot] = (uint16_t)key[k];
+    }
+  __syncthreads();
+  const int cnt = (int)min((int64_t)CH, n - c0);
+  for (int j = threadIdx.x; j < cnt; j += PART_THREADS) {
+    const int kk = skey[j];
+    rout[gbase[kk] + (j - lstart[kk])] = stage[j];
   }
 }
 
@@ -235,36 +341,43 @@ __device__ __forceinline__ int stencil_1d(uint32_t p, int shift, int assign, int
   return off;
 }
 
-// Contributions are accumulated as 64-bit fixed point (2^-40 units) with
-// integer LDS atomics: on gfx950 integer LDS atomics run at full rate while
-// FP32 LDS atomics are an order of magnitude slower, and integer sums do not
-// depend on the order in which the threads add (bit-reproducible blocks).
+// Contributions are accumulated as 64-bit fixed point with integer LDS
+// atomics: on gfx950 integer LDS atomics run at full rate while FP32 LDS
+// atomics are an order of magnitude slower, and integer sums do not depend on
+// the order in which the threads add (bit-reproducible blocks).  Units: 2^-40
+// in general; 2^-30 for unit-weight FP32 painting, where every contribution
+// lies in [0, 1] and converts with one 32-bit instruction (its rounding,
+// <= 2^-31 absolute, is far below the FP32 resolution of the mesh values).
 constexpr double FIX_SCALE = 1099511627776.0;  // 2^40
 constexpr double FIX_INV = 1.0 / 1099511627776.0;
+constexpr float FIX32_SCALE = 1073741824.0f;  // 2^30
+constexpr double FIX32_INV = 1.0 / 1073741824.0;
 
-template <typename T, int ASSIGN>
-__global__ void __launch_bounds__(512) k_paint_tiles(const uint32_t* __restrict__ spos,
-                                                     const float* __restrict__ sw, int64_t n,
+template <typename T, int ASSIGN, int RS>
+__global__ void __launch_bounds__(1024) k_paint_tiles(const Rec<RS>* __restrict__ rec,
                                                      const uint32_t* __restrict__ start,
-                                                     const uint32_t* __restrict__ count, int shift,
+                                                     const uint32_t* __restrict__ count, TileGeom g,
                                                      int nphase, int ph0, int nph, int power,
                                                      T* __restrict__ blocks) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   unsigned long long* acc = reinterpret_cast<unsigned long long*>(smem_raw);  // [nph][BVOL]
-  const int t = blockIdx.x;
+  const int t = blockIdx.x;  // tile (tx * nt + ty) * nt + tz
+  const int shift = g.shift;
   for (int i = threadIdx.x; i < nph * BVOL; i += blockDim.x) acc[i] = 0ull;
   __syncthreads();
-  const uint32_t s0 = start[t], cnt = count[t];
+  const int key = key_of(t / (g.nt * g.nt), (t / g.nt) % g.nt, t % g.nt, g);
+  const uint32_t s0 = start[key], cnt = count[key];
   constexpr int NP = ASSIGN == CNPC_TSC ? 3 : 2;
+  constexpr bool FIX32 = sizeof(T) == 4 && RS == 3;
   for (uint32_t k = threadIdx.x; k < cnt; k += blockDim.x) {
-    const int64_t i = (int64_t)s0 + k;
-    const uint32_t px = spos[i], py = spos[n + i], pz = spos[2 * n + i];
+    const Rec<RS> p = rec[(int64_t)s0 + k];
+    const uint32_t px = p.v[0], py = p.v[1], pz = p.v[2];
     T wv = T(1);
-    if (sw) {
-      wv = T(sw[i]);
+    if constexpr (RS == 4) {
+      wv = T(__uint_as_float(p.v[3]));
       if (power == 2) wv *= wv;
     }
-    const int bx = ((int)(px >> shift) & 15) + 1;
+  const int bx = ((int)(px >> shift) & 15) + 1;
     const int by = ((int)(py >> shift) & 15) + 1;
     const int bz = ((int)(pz >> shift) & 15) + 1;
     for (int q = 0; q < nph; ++q) {
@@ -283,7 +396,11 @@ __global__ void __launch_bounds__(512) k_paint_tiles(const uint32_t* __restrict_
           const T vxy = vx * wy[iy];
 #pragma unroll
           for (int iz = 0; iz < NP; ++iz) {
-            const long long fixv = __double2ll_rn((double)(vxy * wz[iz]) * FIX_SCALE);
+            long long fixv;
+            if constexpr (FIX32)
+              fixv = __float2int_rn(vxy * wz[iz] * FIX32_SCALE);
+            else
+              fixv = __double2ll_rn((double)(vxy * wz[iz]) * FIX_SCALE);
             atomicAdd(&a[ix * BW * BW + iy * BW + iz], (unsigned long long)fixv);
           }
         }
@@ -293,7 +410,7 @@ __global__ void __launch_bounds__(512) k_paint_tiles(const uint32_t* __restrict_
   __syncthreads();
   T* out = blocks + ((int64_t)t * nphase + ph0) * BVOL;
   for (int i = threadIdx.x; i < nph * BVOL; i += blockDim.x)
-    out[i] = T((double)(long long)acc[i] * FIX_INV);
+    out[i] = T((double)(long long)acc[i] * (FIX32 ? FIX32_INV : FIX_INV));
 }
 
 // sum of the blocks of set `s` covering node (x, y, z), phase ph
@@ -384,6 +501,16 @@ cnpc_status launch_norms(const cnpc_mesh_desc* d, const double* gs, const double
 
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
+static TileGeom tile_geom(const cnpc_mesh_desc* d) {
+  TileGeom g;
+  g.shift = 32 - ilog2_host(d->n);
+  g.nt = d->n / TILE;
+  const int S = g.nt < 4 ? g.nt : 4;
+  g.ls = ilog2_host(S);
+  g.lnb = ilog2_host(g.nt / S);
+  return g;
+}
+
 PaintLayout paint_layout(const cnpc_mesh_desc* d, int64_t ngal, int64_t nran, bool weighted) {
   PaintLayout L;
   const int nt = d->n / TILE;
@@ -391,16 +518,18 @@ PaintLayout paint_layout(const cnpc_mesh_desc* d, int64_t ngal, int64_t nran, bo
   L.ntiles = nt * nt * nt;
   L.nphase = d->interlace ? 2 : 1;
   L.nsets = weighted ? 4 : 2;
+  const TileGeom g = tile_geom(d);
+  L.nbuckets = 1 << (3 * g.lnb);
   const size_t es = esize(d->dtype);
+  const int64_t np = ngal > nran ? ngal : nran;
+  const size_t rec = (size_t)np * (weighted ? 16 : 12);
   size_t off = 0;
-  for (int c = 0; c < 2; ++c) {
-    const int64_t np = c == 0 ? ngal : nran;
-    L.off_spos[c] = off; off = align_up(off + (size_t)np * 3 * 4);
-    L.off_sw[c] = off; off = align_up(off + (weighted ? (size_t)np * 4 : 0));
-    L.off_count[c] = off; off = align_up(off + (size_t)L.ntiles * 4);
-    L.off_start[c] = off; off = align_up(off + (size_t)L.ntiles * 4);
-    L.off_cursor[c] = off; off = align_up(off + (size_t)L.ntiles * 4);
-  }
+  L.off_rec = off; off = align_up(off + rec);
+  L.off_tmp = off; off = align_up(off + (L.nbuckets > 1 ? rec : 0));
+  L.off_count = off; off = align_up(off + (size_t)L.ntiles * 4);
+  L.off_start = off; off = align_up(off + (size_t)L.ntiles * 4);
+  L.off_cursor = off; off = align_up(off + (size_t)L.ntiles * 4);
+  L.off_bcur = off; off = align_up(off + (size_t)L.nbuckets * 4);
   for (int k = 0; k < L.nsets; ++k) {
     L.off_blocks[k] = off;
     off = align_up(off + (size_t)L.ntiles * L.nphase * BVOL * es);
@@ -415,70 +544,118 @@ __global__ void k_zero_u32(uint32_t* p, int64_t n) {
     p[i] = 0u;
 }
 
+constexpr int FINE_RCAP = 512;  // LDS key range of the second sort step
+
+// Largest particles-per-thread (4, 2, 1) whose LDS layout lets two
+// workgroups share a CU, else the largest that fits one.
+static int partition_per(int rs, int rcap) {
+  const size_t lim = lds_limit();
+  for (int per = 4; per >= 1; per >>= 1)
+    if (2 * partition_lds(per, rs, rcap) <= lim) return per;
+  for (int per = 4; per >= 1; per >>= 1)
+    if (partition_lds(per, rs, rcap) <= lim) return per;
+  return 0;
+}
+
+template <bool SOA, bool FINE, int RS>
+static cnpc_status launch_partition(const uint32_t* pos, const float* w, const Rec<RS>* rin, int64_t n,
+                                    const TileGeom& g, int rcap, uint32_t* cursor, Rec<RS>* rout,
+                                    hipStream_t s) {
+  const int per = partition_per(RS, rcap);
+  if (per == 0) {
+    set_error("sort: %d keys do not fit the LDS of a workgroup", rcap);
+    return CNPC_EINVAL;
+  }
+  const int64_t ch = (int64_t)PART_THREADS * per;
+  const unsigned nblk = (unsigned)((n + ch - 1) / ch);
+  const size_t lds = partition_lds(per, RS, rcap);
+  kt_begin(CNPC_KT_SORT, s);
+  if (per == 4)
+    hipLaunchKernelGGL((k_partition<SOA, FINE, RS, 4>), dim3(nblk), dim3(PART_THREADS), lds, s, pos, w, rin,
+                       n, g, rcap, cursor, rout);
+  else if (per == 2)
+    hipLaunchKernelGGL((k_partition<SOA, FINE, RS, 2>), dim3(nblk), dim3(PART_THREADS), lds, s, pos, w, rin,
+                       n, g, rcap, cursor, rout);
+  else
+    hipLaunchKernelGGL((k_partition<SOA, FINE, RS, 1>), dim3(nblk), dim3(PART_THREADS), lds, s, pos, w, rin,
+                       n, g, rcap, cursor, rout);
+  kt_end(CNPC_KT_SORT, s);
+  CNPC_HIP(hipGetLastError());
+  return CNPC_OK;
+}
+
+template <typename T, int RS>
+static cnpc_status sort_and_paint(const cnpc_mesh_desc* d, const uint32_t* pos, const float* w, int64_t n,
+                                  int set0, bool weighted, unsigned char* ws, const PaintLayout& L,
+                                  hipStream_t s) {
+  const TileGeom g = tile_geom(d);
+  uint32_t* count = reinterpret_cast<uint32_t*>(ws + L.off_count);
+  uint32_t* start = reinterpret_cast<uint32_t*>(ws + L.off_start);
+  uint32_t* cursor = reinterpret_cast<uint32_t*>(ws + L.off_cursor);
+  uint32_t* bcur = reinterpret_cast<uint32_t*>(ws + L.off_bcur);
+  Rec<RS>* rec = reinterpret_cast<Rec<RS>*>(ws + L.off_rec);
+  Rec<RS>* tmp = reinterpret_cast<Rec<RS>*>(ws + L.off_tmp);
+  hipLaunchKernelGGL(k_zero_u32, dim3(64), dim3(256), 0, s, count, (int64_t)L.ntiles);
+  CNPC_HIP(hipGetLastError());
+  const size_t lds_count = L.ntiles <= LDS_TILES_MAX ? (size_t)L.ntiles * 4 : 0;
+  const int64_t chunk = (int64_t)SORT_BLOCK * SORT_PER_THREAD;
+  const int64_t nblk = (n + chunk - 1) / chunk;
+  kt_begin(CNPC_KT_SORT, s);
+  hipLaunchKernelGGL(k_tile_count, dim3((unsigned)nblk), dim3(SORT_BLOCK), lds_count, s, pos, n, g, L.ntiles,
+                     count);
+  kt_end(CNPC_KT_SORT, s);
+  CNPC_HIP(hipGetLastError());
+  const int per_bucket = 1 << (3 * g.ls);
+  hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, count, L.ntiles, per_bucket, start, cursor, bcur);
+  CNPC_HIP(hipGetLastError());
+  if (L.nbuckets > 1) {
+    CNPC_TRY((launch_partition<true, false, RS>(pos, w, nullptr, n, g, L.nbuckets, bcur, tmp, s)));
+    CNPC_TRY((launch_partition<false, true, RS>(nullptr, nullptr, tmp, n, g, FINE_RCAP, cursor, rec, s)));
+  } else {
+    CNPC_TRY((launch_partition<true, true, RS>(pos, w, nullptr, n, g, L.ntiles, cursor, rec, s)));
+  }
+  // phases per launch so that the 64-bit LDS blocks fit the workgroup limit
+  const int nph = ((size_t)L.nphase * BVOL * 8 <= lds_limit()) ? L.nphase : 1;
+  const size_t lds_paint = (size_t)nph * BVOL * 8;
+  const int npow = weighted ? 2 : 1;
+  for (int pw = 0; pw < npow; ++pw) {
+    T* blocks = reinterpret_cast<T*>(ws + L.off_blocks[set0 + 2 * pw]);
+    for (int ph0 = 0; ph0 < L.nphase; ph0 += nph) {
+      kt_begin(CNPC_KT_PAINT, s);
+      if (d->assign == CNPC_TSC)
+        hipLaunchKernelGGL((k_paint_tiles<T, CNPC_TSC, RS>), dim3(L.ntiles), dim3(1024), lds_paint, s, rec, start,
+                           count, g, L.nphase, ph0, nph, pw + 1, blocks);
+      else
+        hipLaunchKernelGGL((k_paint_tiles<T, CNPC_CIC, RS>), dim3(L.ntiles), dim3(1024), lds_paint, s, rec, start,
+                           count, g, L.nphase, ph0, nph, pw + 1, blocks);
+      kt_end(CNPC_KT_PAINT, s);
+      CNPC_HIP(hipGetLastError());
+    }
+  }
+  return CNPC_OK;
+}
+
 template <typename T>
 static cnpc_status paint_t(const cnpc_mesh_desc* d, const uint32_t* gpos, const float* gw,
                            int64_t ngal, const uint32_t* rpos, const float* rw, int64_t nran,
                            const double* norms, T* delta, T* noise, unsigned char* ws,
                            const PaintLayout& L, hipStream_t s) {
-  const int shift = 32 - ilog2_host(d->n);
   const bool weighted = (gw != nullptr) || (rw != nullptr);
   const uint32_t* cpos[2] = {gpos, rpos};
   const float* cw[2] = {gw, rw};
   const int64_t cn[2] = {ngal, nran};
-  const size_t lds_sort = L.ntiles <= LDS_TILES_MAX ? (size_t)L.ntiles * 4 : 0;
-  const size_t lds_scatter = L.ntiles <= LDS_TILES_MAX ? (size_t)L.ntiles * 8 : 0;
-  // phases per launch so that the 64-bit LDS blocks fit the workgroup limit
-  const int nph = ((size_t)L.nphase * BVOL * 8 <= lds_limit()) ? L.nphase : 1;
-  const size_t lds_paint = (size_t)nph * BVOL * 8;
   FoldArgs<T> fa;
   fa.n = d->n;
   fa.nt = L.nt;
   fa.nphase = L.nphase;
   fa.nsets = L.nsets;
   for (int c = 0; c < 2; ++c) {
-    const int64_t n = cn[c];
-    uint32_t* count = reinterpret_cast<uint32_t*>(ws + L.off_count[c]);
-    uint32_t* start = reinterpret_cast<uint32_t*>(ws + L.off_start[c]);
-    uint32_t* cursor = reinterpret_cast<uint32_t*>(ws + L.off_cursor[c]);
-    uint32_t* spos = reinterpret_cast<uint32_t*>(ws + L.off_spos[c]);
-    float* sw = cw[c] ? reinterpret_cast<float*>(ws + L.off_sw[c]) : nullptr;
-    hipLaunchKernelGGL(k_zero_u32, dim3(64), dim3(256), 0, s, count, (int64_t)L.ntiles);
-    CNPC_HIP(hipGetLastError());
-    const int64_t chunk = (int64_t)SORT_BLOCK * SORT_PER_THREAD;
-    const int64_t nblk = (n + chunk - 1) / chunk;
-    if (nblk > 0) {
-      kt_begin(CNPC_KT_SORT, s);
-      hipLaunchKernelGGL(k_tile_count, dim3((unsigned)nblk), dim3(SORT_BLOCK), lds_sort, s, cpos[c], n,
-                         shift, L.nt, L.ntiles, count);
-      kt_end(CNPC_KT_SORT, s);
-      CNPC_HIP(hipGetLastError());
-    }
-    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, count, L.ntiles, start, cursor);
-    CNPC_HIP(hipGetLastError());
-    if (nblk > 0) {
-      kt_begin(CNPC_KT_SORT, s);
-      hipLaunchKernelGGL(k_tile_scatter, dim3((unsigned)nblk), dim3(SORT_BLOCK), lds_scatter, s,
-                         cpos[c], cw[c], n, shift, L.nt, L.ntiles, cursor, spos, sw);
-      kt_end(CNPC_KT_SORT, s);
-      CNPC_HIP(hipGetLastError());
-    }
-    const int npow = weighted ? 2 : 1;
-    for (int pw = 0; pw < npow; ++pw) {
-      const int set = weighted ? (pw * 2 + c) : c;
-      T* blocks = reinterpret_cast<T*>(ws + L.off_blocks[set]);
-      for (int ph0 = 0; ph0 < L.nphase; ph0 += nph) {
-        kt_begin(CNPC_KT_PAINT, s);
-        if (d->assign == CNPC_TSC)
-          hipLaunchKernelGGL((k_paint_tiles<T, CNPC_TSC>), dim3(L.ntiles), dim3(512), lds_paint, s, spos,
-                             sw, n, start, count, shift, L.nphase, ph0, nph, pw + 1, blocks);
-        else
-          hipLaunchKernelGGL((k_paint_tiles<T, CNPC_CIC>), dim3(L.ntiles), dim3(512), lds_paint, s, spos,
-                             sw, n, start, count, shift, L.nphase, ph0, nph, pw + 1, blocks);
-        kt_end(CNPC_KT_PAINT, s);
-        CNPC_HIP(hipGetLastError());
-      }
-      fa.blocks[set] = blocks;
-    }
+    for (int pw = 0; pw < (weighted ? 2 : 1); ++pw)
+      fa.blocks[c + 2 * pw] = reinterpret_cast<T*>(ws + L.off_blocks[c + 2 * pw]);
+    if (cw[c])
+      CNPC_TRY((sort_and_paint<T, 4>(d, cpos[c], cw[c], cn[c], c, weighted, ws, L, s)));
+    else
+      CNPC_TRY((sort_and_paint<T, 3>(d, cpos[c], nullptr, cn[c], c, weighted, ws, L, s)));
   }
   const int64_t total = (int64_t)d->n * d->n * d->n * L.nphase;
   const int64_t nb = std::min<int64_t>((total + 255) / 256, 65536);

@@ -141,6 +141,39 @@ def test_paint_and_norms(assign, interlace, weights, dtype):
         assert rel(hnm[ph], onm[ph]) < 20 * TOL[dtype]
 
 
+@pytest.mark.parametrize("case", ["dense128", "sparse256_weighted", "one_tile256"])
+def test_paint_bucketed_sort(case):
+    """Meshes with several tile buckets: bucket step, tile step (LDS runs and
+    the per-particle path for chunks spanning many buckets), against the oracle."""
+    rng = np.random.default_rng(21)
+    if case == "dense128":
+        n, box, assign, interlace, dtype = 128, 1000.0, L.TSC, True, L.F32
+        g = synthcat.lognormal_catalog(200_000, box, 5)
+        r = synthcat.random_catalog(1_000_000, 6)
+        gw = rw = None
+    elif case == "sparse256_weighted":
+        n, box, assign, interlace, dtype = 256, 1000.0, L.CIC, False, L.F64
+        g, gw, r, rw = _tiny(8, 5000, 30000, True)
+    else:
+        n, box, assign, interlace, dtype = 256, 1000.0, L.TSC, True, L.F32
+        # every particle inside one 16^3-node tile (plus its stencil halo)
+        g = (rng.integers(0, 2 ** 32 // 16, size=(3, 20000), dtype=np.uint32) + np.uint32(2 ** 31))
+        r = (rng.integers(0, 2 ** 32 // 16, size=(3, 90000), dtype=np.uint32) + np.uint32(2 ** 31))
+        gw = rw = None
+    g, r = np.ascontiguousarray(g), np.ascontiguousarray(r)
+    d = cn.mesh_desc(n, box, assign=assign, interlace=interlace, dtype=dtype, observer=OBS)
+    gwt = dev(gw) if gw is not None else None
+    rwt = dev(rw) if rw is not None else None
+    norms, _, _ = pl.catalog_norms(d, dev(g), dev(r), gwt, rwt)
+    delta, nmesh = pl.paint(d, dev(g), dev(r), norms, gwt, rwt, noise=True)
+    alpha = float(host(norms)[L.NORM_ALPHA])
+    od, onm = oms.paint_fkp(g, gw, r, rw, alpha, n, assign, interlace, noise=True)
+    hd, hnm = host(delta), host(nmesh)
+    for ph in range(2 if interlace else 1):
+        assert rel(hd[ph], od[ph]) < 20 * TOL[dtype]
+        assert rel(hnm[ph], onm[ph]) < 20 * TOL[dtype]
+
+
 def test_paint_single_particle_cells_bit_exact():
     n, box = 32, 100.0
     rng = np.random.default_rng(9)
