@@ -155,14 +155,38 @@ __global__ void __launch_bounds__(256) k_contract(const T* __restrict__ fields, 
   }
 }
 
-__global__ void k_reduce_blocks(const double* __restrict__ partial, int nblocks, int64_t len,
-                                double* __restrict__ out) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < len;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    double s = 0.0;
-    for (int b = 0; b < nblocks; ++b) s += partial[(int64_t)b * len + i];
-    out[i] = s;
+// out[i] = sum_b partial[b][i]: a workgroup owns 64 consecutive outputs, its 16
+// waves sum interleaved quarters of the rows (four independent chains each),
+// then the wave sums are added in a fixed order (deterministic result).
+__global__ void __launch_bounds__(1024) k_reduce_blocks(const double* __restrict__ partial, int nblocks,
+                                                        int64_t len, double* __restrict__ out) {
+  __shared__ double red[16][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  if (i < len) {
+    int b = wv;
+    for (; b + 48 < nblocks; b += 64) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) s[u] += partial[(int64_t)(b + 16 * u) * len + i];
+    }
+    for (int u = 0; b < nblocks; b += 16, ++u) s[u & 3] += partial[(int64_t)b * len + i];
   }
+  red[wv][lane] = (s[0] + s[1]) + (s[2] + s[3]);
+  __syncthreads();
+  if (wv == 0 && i < len) {
+    double t = 0.0;
+    for (int k = 0; k < 16; ++k) t += red[k][lane];
+    out[i] = t;
+  }
+}
+
+static cnpc_status reduce_blocks(const double* partial, int nblocks, int64_t len, double* out,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_blocks, dim3((unsigned)((len + 63) / 64)), dim3(1024), 0, s, partial, nblocks,
+                     len, out);
+  CNPC_HIP(hipGetLastError());
+  return CNPC_OK;
 }
 
 constexpr int CONTRACT_BLOCKS = 512;
@@ -184,11 +208,7 @@ cnpc_status contract_valu(const T* fields, int64_t npts, int nf, int nshell, con
     kt_end(CNPC_KT_CONTRACT, s);
     CNPC_HIP(hipGetLastError());
   }
-  const int64_t len = (int64_t)npairs * cc.ncols;
-  const unsigned g = (unsigned)std::min<int64_t>((len + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_reduce_blocks, dim3(g), dim3(256), 0, s, partial, CONTRACT_BLOCKS, len, out);
-  CNPC_HIP(hipGetLastError());
-  return CNPC_OK;
+  return reduce_blocks(partial, CONTRACT_BLOCKS, (int64_t)npairs * cc.ncols, out, s);
 }
 
 size_t contract_partial_doubles(int nshell, int ncols) {
@@ -392,12 +412,7 @@ cnpc_status contract_mfma(const float* fields, int64_t npts, int nf, int nshell,
   }
   kt_end(CNPC_KT_CONTRACT, s);
   if (st != CNPC_OK) return st;
-  const int64_t len = (int64_t)npairs * cc.ncols;
-  const unsigned g = (unsigned)std::min<int64_t>((len + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_reduce_blocks, dim3(g), dim3(256), 0, s, partial, CONTRACT_BLOCKS * kgroups, len,
-                     out);
-  CNPC_HIP(hipGetLastError());
-  return CNPC_OK;
+  return reduce_blocks(partial, CONTRACT_BLOCKS * kgroups, (int64_t)npairs * cc.ncols, out, s);
 }
 
 // --------------------------------------------------- shell-filtered c2r --

@@ -129,6 +129,95 @@ __global__ void __launch_bounds__(256) k_zpass_c2r(const cx<T>* in, T* out, int6
   }
 }
 
+// ------------------------------------------------- register z-passes --
+// N = R^2: a group of R lanes transforms one row pair with row_fft_rr
+// (256 / R row pairs per workgroup); same layouts and semantics as
+// k_zpass_r2c / k_zpass_c2r.
+template <typename T, int R>
+__global__ void __launch_bounds__(256) k_zpass_r2c_rr(const T* __restrict__ in, cx<T>* __restrict__ out,
+                                                      int64_t npairs, int kz_keep) {
+  constexpr int N = R * R, GR = 256 / R;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
+  load_twiddles<T, N, -1>(tw);
+  const int grp = threadIdx.x / R, rank = threadIdx.x % R;
+  cx<T>* buf = tw + N + grp * (R * (R + 1));
+  const int64_t q = (int64_t)blockIdx.x * GR + grp;
+  const bool live = q < npairs;
+  const T* r0 = in + 2 * q * (int64_t)N;
+  cx<T> v[R];
+#pragma unroll
+  for (int n2 = 0; n2 < R; ++n2) {
+    const int z = rank + R * n2;
+    v[n2] = live ? cx<T>{r0[z], r0[N + z]} : cx<T>{T(0), T(0)};
+  }
+  __syncthreads();
+  row_fft_rr<T, R, -1>(v, rank, buf, tw);
+  const int src = (R - rank) & (R - 1);
+  const int K2 = (kz_keep + R - 1) / R;
+  cx<T>* o = out + 2 * q * (int64_t)kz_keep;
+#pragma unroll
+  for (int k2 = 0; k2 < R / 2; ++k2) {
+    if (k2 < K2) {
+      const cx<T> a = v[R - 1 - k2];
+      const cx<T> sh = {__shfl(a.x, src, R), __shfl(a.y, src, R)};
+      const cx<T> zm = cconj(rank ? sh : v[(R - k2) & (R - 1)]);
+      const cx<T> zk = v[k2];
+      const int k = rank + R * k2;
+      if (live && k < kz_keep) {
+        const cx<T> dd = csub(zk, zm);
+        o[k] = cscale(cadd(zk, zm), T(0.5));
+        o[kz_keep + k] = cx<T>{T(0.5) * dd.y, T(-0.5) * dd.x};
+      }
+    }
+  }
+}
+
+template <typename T, int R>
+__global__ void __launch_bounds__(256) k_zpass_c2r_rr(const cx<T>* in, T* out, int64_t npairs, int kz_in) {
+  constexpr int N = R * R, GR = 256 / R;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
+  load_twiddles<T, N, 1>(tw);
+  const int grp = threadIdx.x / R, rank = threadIdx.x % R;
+  cx<T>* buf = tw + N + grp * (R * (R + 1));
+  const int64_t q = (int64_t)blockIdx.x * GR + grp;
+  const bool live = q < npairs;
+  const cx<T>* r0 = in + 2 * q * (int64_t)kz_in;
+  cx<T> v[R];
+#pragma unroll
+  for (int n2 = 0; n2 < R; ++n2) {
+    const int k = rank + R * n2;
+    cx<T> z = {T(0), T(0)};
+    if (live) {
+      if (k < (N >> 1)) {
+        if (k < kz_in) {
+          const cx<T> a = r0[k], b = r0[kz_in + k];
+          z = cx<T>{a.x - b.y, a.y + b.x};
+        }
+      } else if (k > (N >> 1)) {
+        const int kk = N - k;
+        if (kk < kz_in) {
+          const cx<T> a = r0[kk], b = r0[kz_in + kk];
+          z = cx<T>{a.x + b.y, b.x - a.y};
+        }
+      }
+    }
+    v[n2] = z;
+  }
+  __syncthreads();
+  row_fft_rr<T, R, 1>(v, rank, buf, tw);
+  if (live) {
+    T* o = out + 2 * q * (int64_t)N;
+#pragma unroll
+    for (int k2 = 0; k2 < R; ++k2) {
+      const int e = rank + R * k2;
+      o[e] = v[k2].x;
+      o[N + e] = v[k2].y;
+    }
+  }
+}
+
 // ---------------------------------------------------------- column pass --
 // For each plane p and each tile of W consecutive columns: transform along the
 // row index (length N).  Input rows: all N (band_in == 0) or the 2*band_in band
@@ -181,10 +270,92 @@ __global__ void __launch_bounds__(256) k_colpass(const cx<T>* in, cx<T>* out, Co
   }
 }
 
+// Register column pass for N = R^2: 256 threads = W = 256 / R columns x R
+// ranks.  Lane (c, rank) loads rows rank + R n2 of column c, does the first
+// R-point DFT in registers, exchanges through LDS (layout [k1][n1][c] with 16
+// elements of padding per k1 block, so that the stage-1 writes and the stage-2
+// reads of a half wavefront hit distinct banks) and does the second R-point
+// DFT; it then holds output rows rank + R k2.  Same arguments and band / mask
+// semantics as k_colpass.
+template <typename T, int R, int DIR>
+__global__ void __launch_bounds__(256) k_colpass_rr(const cx<T>* in, cx<T>* out, ColArgs a) {
+  constexpr int N = R * R, W = 256 / R, LOGW = (W == 8 ? 3 : W == 16 ? 4 : W == 32 ? 5 : 6);
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* buf = tw + N;
+  load_twiddles<T, N, DIR>(tw);
+  const int c = threadIdx.x & (W - 1), rank = threadIdx.x >> LOGW;
+  const int tiles = a.ncols >> LOGW;
+  const int64_t p = blockIdx.x / tiles;
+  const int c0 = (blockIdx.x - (int)(p * tiles)) << LOGW;
+  const cx<T>* src = in + p * a.plane_in + c0 + c;
+  int jy = 0, kz = 0;
+  if (a.mask_m) {
+    jy = (c0 + c) / a.mask_m;
+    kz = (c0 + c) - jy * a.mask_m;
+  }
+  cx<T> v[R];
+#pragma unroll
+  for (int n2 = 0; n2 < R; ++n2) {
+    const int r = rank + R * n2;
+    int j = r;
+    bool ok = true;
+    if (a.band_in) {
+      // band rows n = -(M-1) .. M-1; the unpaired n = -M row is read as zero
+      if (r < a.band_in) j = r;
+      else if (r > N - a.band_in) j = r - N + 2 * a.band_in;
+      else ok = false;
+    }
+    if (ok && a.mask_m) {
+      const int nx = freq_of(r, N), ny = band_freq(jy, a.mask_m);
+      const int64_t n2s = (int64_t)nx * nx + (int64_t)ny * ny + (int64_t)kz * kz;
+      const int b = a.mask_b0 + (int)p;
+      ok = n2s > 0 && n2s >= a.thr[b] && n2s < a.thr[b + 1] && nx != -(N / 2) && ny != -(N / 2) &&
+           ny != -a.mask_m;
+    }
+    v[n2] = ok ? src[(int64_t)j * a.row_in] : cx<T>{T(0), T(0)};
+  }
+  __syncthreads();  // twiddles
+  dft_reg<T, R, DIR>(v);
+#pragma unroll
+  for (int k1 = 0; k1 < R; ++k1)
+    buf[(k1 * R + rank) * W + c + 16 * k1] = k1 == 0 ? v[k1] : cmul(v[k1], tw[rank * k1]);
+  __syncthreads();
+#pragma unroll
+  for (int n1 = 0; n1 < R; ++n1) v[n1] = buf[(rank * R + n1) * W + c + 16 * rank];
+  dft_reg<T, R, DIR>(v);
+  cx<T>* dst = out + p * a.plane_out + c0 + c;
+#pragma unroll
+  for (int k2 = 0; k2 < R; ++k2) {
+    const int r = rank + R * k2;
+    int j = r;
+    if (a.band_out) {
+      if (r < a.band_out) j = r;
+      else if (r >= N - a.band_out) j = r - N + 2 * a.band_out;
+      else continue;
+    }
+    dst[(int64_t)j * a.row_out] = v[k2];
+  }
+}
+
 // ------------------------------------------------------------- launchers --
+// side R of the register passes for N = R^2 (0: LDS Stockham passes)
+constexpr int rr_radix(int n) { return n == 64 ? 8 : n == 256 ? 16 : 0; }
+
 template <typename T, int N>
 static cnpc_status zr2c_n(const T* in, cx<T>* out, int64_t nrows, int kz, hipStream_t s) {
   const int64_t npairs = nrows / 2;
+  constexpr int R = rr_radix(N);
+  if constexpr (R > 0) {
+    constexpr int GR = 256 / R;
+    const size_t lds = sizeof(cx<T>) * (N + (size_t)GR * R * (R + 1));
+    kt_begin(CNPC_KT_ZR2C, s);
+    hipLaunchKernelGGL((k_zpass_r2c_rr<T, R>), dim3((unsigned)((npairs + GR - 1) / GR)), dim3(256), lds, s, in,
+                       out, npairs, kz);
+    kt_end(CNPC_KT_ZR2C, s);
+    CNPC_HIP(hipGetLastError());
+    return CNPC_OK;
+  }
   constexpr int NSEQ = ZCfg<T, N>::NSEQ;
   const int64_t blocks = (npairs + NSEQ - 1) / NSEQ;
   const size_t lds = sizeof(cx<T>) * (N + 2 * NSEQ * N);
@@ -199,6 +370,17 @@ static cnpc_status zr2c_n(const T* in, cx<T>* out, int64_t nrows, int kz, hipStr
 template <typename T, int N>
 static cnpc_status zc2r_n(const cx<T>* in, T* out, int64_t nrows, int kz, hipStream_t s) {
   const int64_t npairs = nrows / 2;
+  constexpr int R = rr_radix(N);
+  if constexpr (R > 0) {
+    constexpr int GR = 256 / R;
+    const size_t lds = sizeof(cx<T>) * (N + (size_t)GR * R * (R + 1));
+    kt_begin(CNPC_KT_ZC2R, s);
+    hipLaunchKernelGGL((k_zpass_c2r_rr<T, R>), dim3((unsigned)((npairs + GR - 1) / GR)), dim3(256), lds, s, in,
+                       out, npairs, kz);
+    kt_end(CNPC_KT_ZC2R, s);
+    CNPC_HIP(hipGetLastError());
+    return CNPC_OK;
+  }
   constexpr int NSEQ = ZCfg<T, N>::NSEQ;
   const int64_t blocks = (npairs + NSEQ - 1) / NSEQ;
   const size_t lds = sizeof(cx<T>) * (N + 2 * NSEQ * N);
@@ -213,6 +395,24 @@ static cnpc_status zc2r_n(const cx<T>* in, T* out, int64_t nrows, int kz, hipStr
 template <typename T, int N, int DIR>
 static cnpc_status col_n(const cx<T>* in, cx<T>* out, const ColArgs& a, int64_t nplanes,
                          hipStream_t s) {
+  constexpr int R = rr_radix(N);
+  if constexpr (R > 0) {
+    constexpr int W = 256 / R;
+    if (a.ncols % W == 0) {
+      const int64_t blocks = nplanes * (a.ncols / W);
+      if (blocks <= 0) return CNPC_OK;
+      if (blocks > 0x7fffffffLL) {
+        set_error("column pass grid too large");
+        return CNPC_EUNSUPPORTED;
+      }
+      const size_t lds = sizeof(cx<T>) * (N + (size_t)N * W + 16 * R);
+      kt_begin(CNPC_KT_COL, s);
+      hipLaunchKernelGGL((k_colpass_rr<T, R, DIR>), dim3((unsigned)blocks), dim3(256), lds, s, in, out, a);
+      kt_end(CNPC_KT_COL, s);
+      CNPC_HIP(hipGetLastError());
+      return CNPC_OK;
+    }
+  }
   const int64_t blocks = nplanes * (a.ncols >> a.logW);
   if (blocks <= 0) return CNPC_OK;
   if (blocks > 0x7fffffffLL) {

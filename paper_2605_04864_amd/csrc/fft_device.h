@@ -80,6 +80,96 @@ __device__ __forceinline__ void dftR(cx<T>* v) {
   }
 }
 
+// cos(2 pi j / 32) from the first-octant values and quadrant symmetry.
+__host__ __device__ constexpr double cos_frac32(int j) {
+  j &= 31;
+  constexpr double c8[9] = {1.0,
+                            0.98078528040323044913,
+                            0.92387953251128675613,
+                            0.83146961230254523708,
+                            0.70710678118654752440,
+                            0.55557023301960222474,
+                            0.38268343236508977173,
+                            0.19509032201612826785,
+                            0.0};
+  return j <= 8 ? c8[j] : (j <= 16 ? -c8[16 - j] : (j <= 24 ? -c8[j - 16] : c8[32 - j]));
+}
+
+// W_R^j = exp(DIR 2 pi i j / R) for R dividing 32
+template <typename T, int R, int DIR>
+__device__ __forceinline__ cx<T> wR(int j) {
+  const int q = (j * (32 / R)) & 31;
+  return cx<T>{T(cos_frac32(q)), T(DIR * cos_frac32(q - 8))};
+}
+
+template <typename T, int R, int DIR>
+__device__ __forceinline__ void dft_reg(cx<T>* v);
+
+// R = P Q point DFT of registers, natural order in and out: n = a + P b,
+// k = c + Q d; Q-point DFTs over b, twiddles W_R^(a c), P-point DFTs over a.
+template <typename T, int P, int Q, int DIR>
+__device__ __forceinline__ void dft_composite(cx<T>* v) {
+  constexpr int R = P * Q;
+#pragma unroll
+  for (int a = 0; a < P; ++a) {
+    cx<T> t[Q];
+#pragma unroll
+    for (int b = 0; b < Q; ++b) t[b] = v[a + P * b];
+    dft_reg<T, Q, DIR>(t);
+#pragma unroll
+    for (int c = 0; c < Q; ++c) v[a + P * c] = (a * c == 0) ? t[c] : cmul(t[c], wR<T, R, DIR>(a * c));
+  }
+  cx<T> o[R];
+#pragma unroll
+  for (int c = 0; c < Q; ++c) {
+    cx<T> t[P];
+#pragma unroll
+    for (int a = 0; a < P; ++a) t[a] = v[a + P * c];
+    dft_reg<T, P, DIR>(t);
+#pragma unroll
+    for (int d = 0; d < P; ++d) o[c + Q * d] = t[d];
+  }
+#pragma unroll
+  for (int k = 0; k < R; ++k) v[k] = o[k];
+}
+
+template <typename T, int R, int DIR>
+__device__ __forceinline__ void dft_reg(cx<T>* v) {
+  if constexpr (R == 2) {
+    const cx<T> a = v[0];
+    v[0] = cadd(a, v[1]);
+    v[1] = csub(a, v[1]);
+  } else if constexpr (R == 4) {
+    dft4<T, DIR>(v[0], v[1], v[2], v[3]);
+  } else if constexpr (R == 8) {
+    dft8<T, DIR>(v);
+  } else if constexpr (R == 16) {
+    dft_composite<T, 4, 4, DIR>(v);
+  } else {
+    static_assert(R == 32, "register DFT sizes: 2, 4, 8, 16, 32");
+    dft_composite<T, 4, 8, DIR>(v);
+  }
+}
+
+// Length N = R * R transform of one sequence by a group of R lanes (rank =
+// lane within the group): on entry lane n1 holds x[n1 + R n2] in v[n2]; on
+// exit it holds X[n1 + R k2] in v[k2].  Two register DFTs with one LDS
+// transpose in between (buffer of R (R + 1) elements per group, padded so that
+// both the row writes and the column reads are bank-conflict free); tw is the
+// N-entry table W_N^t.  Contains two workgroup barriers: every lane of the
+// workgroup must call it.
+template <typename T, int R, int DIR>
+__device__ __forceinline__ void row_fft_rr(cx<T>* v, int rank, cx<T>* buf, const cx<T>* tw) {
+  dft_reg<T, R, DIR>(v);  // lane n1: Y[n1][k1] in v[k1]
+#pragma unroll
+  for (int k1 = 0; k1 < R; ++k1) buf[k1 * (R + 1) + rank] = k1 == 0 ? v[k1] : cmul(v[k1], tw[rank * k1]);
+  __syncthreads();
+#pragma unroll
+  for (int n1 = 0; n1 < R; ++n1) v[n1] = buf[rank * (R + 1) + n1];
+  __syncthreads();
+  dft_reg<T, R, DIR>(v);
+}
+
 // Twiddle table tw[t] = exp(DIR 2 pi i t / N) into LDS.
 template <typename T, int N, int DIR>
 __device__ __forceinline__ void load_twiddles(cx<T>* tw) {

@@ -123,6 +123,126 @@ __global__ void __launch_bounds__(256) k_zpass_ylm(const T* __restrict__ delta, 
   }
 }
 
+// One Racah-normalised harmonic component: Re (part 0) or Im (part 1) of
+// y_l^m(u) for the unit vector u = (x, y, z) (same polynomials as racah_ylm).
+template <typename T>
+__device__ __forceinline__ T ylm_one(int l, int m, int part, T x, T y, T z) {
+  T sr = T(1), si = T(0);  // (x + i y)^m
+  for (int k = 0; k < m; ++k) {
+    const T t = sr * x - si * y;
+    si = sr * y + si * x;
+    sr = t;
+  }
+  const T z2 = z * z;
+  T c;
+  switch (l * 8 + m) {
+    case 0: c = T(1); break;
+    case 8: c = z; break;
+    case 9: c = T(-0.70710678118654752440); break;
+    case 16: c = T(0.5) * (T(3) * z2 - T(1)); break;
+    case 17: c = T(-1.22474487139158904910) * z; break;
+    case 18: c = T(0.61237243569579452455); break;
+    case 24: c = T(0.5) * z * (T(5) * z2 - T(3)); break;
+    case 25: c = T(-0.43301270189221932338) * (T(5) * z2 - T(1)); break;
+    case 26: c = T(1.36930639376291528364) * z; break;
+    case 27: c = T(-0.55901699437494742410); break;
+    case 32: c = T(0.125) * (T(35) * z2 * z2 - T(30) * z2 + T(3)); break;
+    case 33: c = T(-0.55901699437494742410) * z * (T(7) * z2 - T(3)); break;
+    case 34: c = T(0.39528470752104741650) * (T(7) * z2 - T(1)); break;
+    case 35: c = T(-1.47901994577490951707) * z; break;
+    default: c = T(0.52291251658379721749); break;  // l = 4, m = 4
+  }
+  return c * (part ? si : sr);
+}
+
+// Weight of field (l, m, part) at the node with observer-relative position
+// (rx, ry, rz) (local line of sight) or for the fixed line of sight.
+template <typename T>
+__device__ __forceinline__ T node_weight(const Geo& g, int l, int m, int part, T rx, T ry, T rz) {
+  if (g.global_los) return ylm_one<T>(l, m, part, T(g.los[0]), T(g.los[1]), T(g.los[2]));
+  const T inv = T(1) / sqrt(rx * rx + ry * ry + rz * rz);
+  return ylm_one<T>(l, m, part, rx * inv, ry * inv, rz * inv);
+}
+
+// Register z-pass for N = R^2: a group of R lanes owns one row pair (ix, 2j),
+// (ix, 2j+1) of delta, keeps its 2R samples in registers and, field after
+// field, forms the weighted pair as one complex row, transforms it with
+// row_fft_rr and writes kz < kz_keep of both real rows (two-for-one split).
+template <typename T, int R>
+__global__ void __launch_bounds__(256) k_zpass_ylm_rr(const T* __restrict__ delta, cx<T>* __restrict__ out,
+                                                      FieldTable ft, int kz_keep, int64_t fstride, Geo g) {
+  constexpr int N = R * R;
+  constexpr int GR = 256 / R;  // row pairs per workgroup
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
+  load_twiddles<T, N, -1>(tw);
+  const int grp = threadIdx.x / R, rank = threadIdx.x % R;
+  cx<T>* buf = tw + N + grp * (R * (R + 1));
+  const int q = blockIdx.x * GR + grp;
+  const int ix = q / (N / 2), iy0 = 2 * (q - ix * (N / 2));
+  const T* r0 = delta + ((int64_t)ix * N + iy0) * N;
+  T d0[R], d1[R], rz[R];
+#pragma unroll
+  for (int n2 = 0; n2 < R; ++n2) {
+    const int z = rank + R * n2;
+    d0[n2] = r0[z];
+    d1[n2] = r0[N + z];
+    rz[n2] = T(z * g.h - g.obs[2]);
+  }
+  const T rx = T(ix * g.h - g.obs[0]);
+  const T ry0 = T(iy0 * g.h - g.obs[1]), ry1 = T((iy0 + 1) * g.h - g.obs[1]);
+  __syncthreads();
+  const int src = (R - rank) & (R - 1);
+  const int K2 = (kz_keep + R - 1) / R;
+  cx<T>* orow = out + ((int64_t)ix * N + iy0) * kz_keep;
+  for (int f = 0; f < ft.nf; ++f) {
+    const int l = ft.ell[f], m = ft.m[f], p = ft.part[f];
+    cx<T> v[R];
+#pragma unroll
+    for (int n2 = 0; n2 < R; ++n2) {
+      // the directions are recomputed per field: an opaque copy of rz keeps
+      // the compiler from hoisting 2R unit vectors out of the field loop
+      T z = rz[n2];
+      asm volatile("" : "+v"(z));
+      const T w0 = node_weight<T>(g, l, m, p, rx, ry0, z);
+      const T w1 = node_weight<T>(g, l, m, p, rx, ry1, z);
+      v[n2] = cx<T>{d0[n2] * w0, d1[n2] * w1};
+    }
+    row_fft_rr<T, R, -1>(v, rank, buf, tw);
+    // lane k1 holds Z[k1 + R k2]; Z[N - k] sits in lane (R - k1) & (R - 1),
+    // register R - 1 - k2 (k1 > 0) or in this lane, register (R - k2) & (R - 1)
+    cx<T>* o = orow + (int64_t)f * fstride;
+#pragma unroll
+    for (int k2 = 0; k2 < R / 2; ++k2) {
+      if (k2 < K2) {
+        const cx<T> a = v[R - 1 - k2];
+        const cx<T> sh = {__shfl(a.x, src, R), __shfl(a.y, src, R)};
+        const cx<T> zm = cconj(rank ? sh : v[(R - k2) & (R - 1)]);
+        const cx<T> zk = v[k2];
+        const int k = rank + R * k2;
+        if (k < kz_keep) {
+          const cx<T> dd = csub(zk, zm);
+          o[k] = cscale(cadd(zk, zm), T(0.5));
+          o[kz_keep + k] = cx<T>{T(0.5) * dd.y, T(-0.5) * dd.x};
+        }
+      }
+    }
+  }
+}
+
+template <typename T, int R>
+static cnpc_status zylm_rr(const T* delta, cx<T>* out, const FieldTable& ft, int kz, int64_t fstride,
+                           const Geo& g, hipStream_t s) {
+  constexpr int N = R * R, GR = 256 / R;
+  const size_t lds = sizeof(cx<T>) * (N + (size_t)GR * R * (R + 1));
+  kt_begin(CNPC_KT_ZR2C, s);
+  hipLaunchKernelGGL((k_zpass_ylm_rr<T, R>), dim3(N * (N / 2) / GR), dim3(256), lds, s, delta, out, ft, kz,
+                     fstride, g);
+  kt_end(CNPC_KT_ZR2C, s);
+  CNPC_HIP(hipGetLastError());
+  return CNPC_OK;
+}
+
 template <typename T, int N>
 static cnpc_status zylm_n(const T* delta, cx<T>* out, const FieldTable& ft, int kz,
                           int64_t fstride, const Geo& g, hipStream_t s) {
@@ -147,11 +267,11 @@ template <typename T>
 static cnpc_status zpass_ylm(int n, const T* delta, cx<T>* out, const FieldTable& ft, int kz,
                              int64_t fstride, const Geo& g, hipStream_t s) {
   switch (n) {
-    case 16: return zylm_n<T, 16>(delta, out, ft, kz, fstride, g, s);
+    case 16: return zylm_rr<T, 4>(delta, out, ft, kz, fstride, g, s);
     case 32: return zylm_n<T, 32>(delta, out, ft, kz, fstride, g, s);
-    case 64: return zylm_n<T, 64>(delta, out, ft, kz, fstride, g, s);
+    case 64: return zylm_rr<T, 8>(delta, out, ft, kz, fstride, g, s);
     case 128: return zylm_n<T, 128>(delta, out, ft, kz, fstride, g, s);
-    case 256: return zylm_n<T, 256>(delta, out, ft, kz, fstride, g, s);
+    case 256: return zylm_rr<T, 16>(delta, out, ft, kz, fstride, g, s);
     case 512: return zylm_n<T, 512>(delta, out, ft, kz, fstride, g, s);
     case 1024: return zylm_n<T, 1024>(delta, out, ft, kz, fstride, g, s);
     default: set_error("unsupported mesh size %d", n); return CNPC_EUNSUPPORTED;

@@ -52,7 +52,7 @@ def host(t):
 
 # ---------------------------------------------------------------- FFT -----
 @pytest.mark.parametrize("dtype", [L.F32, L.F64])
-@pytest.mark.parametrize("n", [16, 32, 64])
+@pytest.mark.parametrize("n", [16, 32, 64, 256])
 def test_fft_full_r2c_c2r(n, dtype):
     rng = np.random.default_rng(n)
     x = rng.normal(size=(2, n, n, n))
@@ -75,7 +75,7 @@ def test_fft_full_r2c_c2r(n, dtype):
 
 
 @pytest.mark.parametrize("dtype", [L.F32, L.F64])
-@pytest.mark.parametrize("n,band", [(32, 8), (64, 16), (64, 32)])
+@pytest.mark.parametrize("n,band", [(32, 8), (64, 16), (64, 32), (256, 32)])
 def test_fft_band_r2c_c2r(n, band, dtype):
     rng = np.random.default_rng(n + band)
     x = rng.normal(size=(3, n, n, n))
@@ -217,6 +217,30 @@ def test_ylm_fields(ell, dtype):
         refs += [delta * y.real, delta * y.imag]
     for f, ref in enumerate(refs):
         assert rel(got[f], ref) < 10 * TOL[dtype] + 1e-7 * (dtype == L.F32)
+
+
+@pytest.mark.parametrize("n,band,dtype", [(64, 16, L.F64), (128, 32, L.F32), (256, 32, L.F32), (256, 64, L.F64)])
+def test_ylm_r2c_band(n, band, dtype):
+    """Y_lm-weighted band transforms (fused prologue z-pass + band column
+    passes) against numpy FFTs of the explicitly weighted fields."""
+    from oracle.ylm import ylm_racah
+    box = 1000.0
+    d = cn.mesh_desc(n, box, dtype=dtype, observer=OBS)
+    tdt = torch.float64 if dtype == L.F64 else torch.float32
+    delta = np.random.default_rng(n + band).normal(size=(n, n, n))
+    got = pl.ylm_spectra(d, band, (2, 4), dev(delta, tdt))
+    rvec = osp.line_of_sight(n, box, OBS)
+    idx = np.r_[0:band, n - band:n]
+    for ell in (2, 4):
+        fields = [ylm_racah(ell, 0, rvec).real]
+        for m in range(1, ell + 1):
+            y = ylm_racah(ell, m, rvec)
+            fields += [y.real, y.imag]
+        g = host(got[ell])
+        for f, w in enumerate(fields):
+            ref = np.fft.rfftn(delta * w)[np.ix_(idx, idx, range(band))]
+            gf = g[f, ..., 0] + 1j * g[f, ..., 1]
+            assert rel(gf.reshape(ref.shape), ref) < 20 * TOL[dtype], (ell, f)
 
 
 # ---------------------------------------------------------- power ---------
