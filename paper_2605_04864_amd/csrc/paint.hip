@@ -341,17 +341,12 @@ __device__ __forceinline__ int stencil_1d(uint32_t p, int shift, int assign, int
   return off;
 }
 
-// Contributions are accumulated as 64-bit fixed point with integer LDS
-// atomics: on gfx950 integer LDS atomics run at full rate while FP32 LDS
-// atomics are an order of magnitude slower, and integer sums do not depend on
-// the order in which the threads add (bit-reproducible blocks).  Units: 2^-40
-// in general; 2^-30 for unit-weight FP32 painting, where every contribution
-// lies in [0, 1] and converts with one 32-bit instruction (its rounding,
-// <= 2^-31 absolute, is far below the FP32 resolution of the mesh values).
+// Contributions are accumulated as 64-bit fixed point (2^-40 units) with
+// integer LDS atomics: on gfx950 integer LDS atomics run at full rate while
+// FP32 LDS atomics are an order of magnitude slower, and integer sums do not
+// depend on the order in which the threads add (bit-reproducible blocks).
 constexpr double FIX_SCALE = 1099511627776.0;  // 2^40
 constexpr double FIX_INV = 1.0 / 1099511627776.0;
-constexpr float FIX32_SCALE = 1073741824.0f;  // 2^30
-constexpr double FIX32_INV = 1.0 / 1073741824.0;
 
 template <typename T, int ASSIGN, int RS>
 __global__ void __launch_bounds__(1024) k_paint_tiles(const Rec<RS>* __restrict__ rec,
@@ -368,7 +363,6 @@ __global__ void __launch_bounds__(1024) k_paint_tiles(const Rec<RS>* __restrict_
   const int key = key_of(t / (g.nt * g.nt), (t / g.nt) % g.nt, t % g.nt, g);
   const uint32_t s0 = start[key], cnt = count[key];
   constexpr int NP = ASSIGN == CNPC_TSC ? 3 : 2;
-  constexpr bool FIX32 = sizeof(T) == 4 && RS == 3;
   for (uint32_t k = threadIdx.x; k < cnt; k += blockDim.x) {
     const Rec<RS> p = rec[(int64_t)s0 + k];
     const uint32_t px = p.v[0], py = p.v[1], pz = p.v[2];
@@ -396,11 +390,7 @@ __global__ void __launch_bounds__(1024) k_paint_tiles(const Rec<RS>* __restrict_
           const T vxy = vx * wy[iy];
 #pragma unroll
           for (int iz = 0; iz < NP; ++iz) {
-            long long fixv;
-            if constexpr (FIX32)
-              fixv = __float2int_rn(vxy * wz[iz] * FIX32_SCALE);
-            else
-              fixv = __double2ll_rn((double)(vxy * wz[iz]) * FIX_SCALE);
+            const long long fixv = __double2ll_rn((double)(vxy * wz[iz]) * FIX_SCALE);
             atomicAdd(&a[ix * BW * BW + iy * BW + iz], (unsigned long long)fixv);
           }
         }
@@ -410,60 +400,143 @@ __global__ void __launch_bounds__(1024) k_paint_tiles(const Rec<RS>* __restrict_
   __syncthreads();
   T* out = blocks + ((int64_t)t * nphase + ph0) * BVOL;
   for (int i = threadIdx.x; i < nph * BVOL; i += blockDim.x)
-    out[i] = T((double)(long long)acc[i] * (FIX32 ? FIX32_INV : FIX_INV));
+    out[i] = T((double)(long long)acc[i] * FIX_INV);
 }
 
-// sum of the blocks of set `s` covering node (x, y, z), phase ph
-template <typename T>
-__device__ __forceinline__ T gather_node(const T* __restrict__ blocks, int nt, int nphase, int ph,
-                                         int x, int y, int z) {
-  int tx[2], lx[2], nx = 0, ty[2], ly[2], ny = 0, tz[2], lz[2], nz = 0;
-  auto cover = [nt](int c, int* tt, int* ll, int& k) {
-    const int t = c >> 4, r = c & 15;
-    tt[k] = t; ll[k] = r + 1; ++k;
-    if (r <= 1) { tt[k] = (t - 1 + nt) % nt; ll[k] = r + 17; ++k; }
-    else if (r == 15) { tt[k] = (t + 1) % nt; ll[k] = 0; ++k; }
-  };
-  cover(x, tx, lx, nx);
-  cover(y, ty, ly, ny);
-  cover(z, tz, lz, nz);
-  T v = T(0);
-  for (int a = 0; a < nx; ++a)
-    for (int b = 0; b < ny; ++b)
-      for (int c = 0; c < nz; ++c) {
-        const int64_t tile = ((int64_t)tx[a] * nt + ty[b]) * nt + tz[c];
-        v += blocks[(tile * nphase + ph) * BVOL + (lx[a] * BW + ly[b]) * BW + lz[c]];
+// Unit-weight FP32 painting with 32-bit LDS atomics.  Each round of the
+// workgroup paints one particle per thread; a node then gains at most
+// PPF * max node weight per flush interval (PPF = particles per flush), which
+// at the chosen scale stays below 2^32 (TSC: 2048 * 0.421875 * 2^22; CIC:
+// 1024 * 1 * 2^21), so the 32-bit sums are exact.  After every interval each
+// thread moves the nodes it owns into 64-bit registers and clears them.  The
+// result equals the 64-bit fixed-point sum of the contributions rounded to
+// 2^-22 (TSC) or 2^-21 (CIC), independent of the order of the additions.
+constexpr int PAINT32_THREADS = 1024;
+constexpr int PAINT32_OWN = (2 * BVOL + PAINT32_THREADS - 1) / PAINT32_THREADS;  // nodes per thread
+
+template <int ASSIGN>
+__global__ void __launch_bounds__(PAINT32_THREADS) k_paint_tiles_u32(const Rec<3>* __restrict__ rec,
+                                                                     const uint32_t* __restrict__ start,
+                                                                     const uint32_t* __restrict__ count,
+                                                                     TileGeom g, int nphase,
+                                                                     float* __restrict__ blocks) {
+  constexpr float SCALE = ASSIGN == CNPC_TSC ? 4194304.0f : 2097152.0f;  // 2^22, 2^21
+  constexpr int ROUNDS_PER_FLUSH = ASSIGN == CNPC_TSC ? 2 : 1;
+  constexpr int NP = ASSIGN == CNPC_TSC ? 3 : 2;
+  __shared__ uint32_t acc[2 * BVOL];
+  const int t = blockIdx.x;
+  const int shift = g.shift;
+  const int nv = nphase * BVOL;
+  for (int i = threadIdx.x; i < nv; i += PAINT32_THREADS) acc[i] = 0u;
+  unsigned long long own[PAINT32_OWN];
+#pragma unroll
+  for (int j = 0; j < PAINT32_OWN; ++j) own[j] = 0ull;
+  __syncthreads();
+  const int key = key_of(t / (g.nt * g.nt), (t / g.nt) % g.nt, t % g.nt, g);
+  const uint32_t s0 = start[key], cnt = count[key];
+  int round = 0;
+  for (uint32_t base = 0; base < cnt; base += PAINT32_THREADS) {
+    const uint32_t k = base + threadIdx.x;
+    if (k < cnt) {
+      const Rec<3> p = rec[(int64_t)s0 + k];
+      const uint32_t px = p.v[0], py = p.v[1], pz = p.v[2];
+      const int bx = ((int)(px >> shift) & 15) + 1;
+      const int by = ((int)(py >> shift) & 15) + 1;
+      const int bz = ((int)(pz >> shift) & 15) + 1;
+      for (int ph = 0; ph < nphase; ++ph) {
+        float wx[3], wy[3], wz[3];
+        const int ox = stencil_1d<float>(px, shift, ASSIGN, ph, wx);
+        const int oy = stencil_1d<float>(py, shift, ASSIGN, ph, wy);
+        const int oz = stencil_1d<float>(pz, shift, ASSIGN, ph, wz);
+        uint32_t* a = acc + ph * BVOL + (bx + ox) * BW * BW + (by + oy) * BW + (bz + oz);
+#pragma unroll
+        for (int ix = 0; ix < NP; ++ix)
+#pragma unroll
+          for (int iy = 0; iy < NP; ++iy) {
+            const float vxy = wx[ix] * wy[iy] * SCALE;
+#pragma unroll
+            for (int iz = 0; iz < NP; ++iz)
+              atomicAdd(&a[ix * BW * BW + iy * BW + iz], __float2uint_rn(vxy * wz[iz]));
+          }
       }
-  return v;
+    }
+    if (++round == ROUNDS_PER_FLUSH || base + PAINT32_THREADS >= cnt) {
+      round = 0;
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < PAINT32_OWN; ++j) {
+        const int i = threadIdx.x + j * PAINT32_THREADS;
+        if (i < nv) {
+          own[j] += acc[i];
+          acc[i] = 0u;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  float* out = blocks + (int64_t)t * nphase * BVOL;
+#pragma unroll
+  for (int j = 0; j < PAINT32_OWN; ++j) {
+    const int i = threadIdx.x + j * PAINT32_THREADS;
+    if (i < nv) out[i] = (float)((double)own[j] * (1.0 / (double)SCALE));
+  }
 }
 
-// out_delta = sum_s cd[s] blocks_s, out_noise = sum_s cn[s] blocks_s; coefficients
-// come from alpha on the device: sets (g, r) for unit weights, (g w, r w, g w^2,
-// r w^2) for weighted catalogs.
+// Fold of the tile blocks into meshes: a workgroup owns Z2 tiles along z
+// (16 x 16 Z2 threads, lane = node (y, z) of the tiles) and walks x; every
+// node sums the <= 8 blocks covering it (own block plus the halos of the
+// lower / upper neighbours) for each set and forms
+// delta = sum_s cd[s] v_s and N = sum_s cn[s] v_s.
 template <typename T>
-__global__ void __launch_bounds__(256) k_fold(FoldArgs<T> fa, const double* __restrict__ norms,
-                                              T* __restrict__ delta, T* __restrict__ noise) {
-  const int n = fa.n;
-  const int64_t n3 = (int64_t)n * n * n;
+__global__ void __launch_bounds__(512) k_fold_tiles(FoldArgs<T> fa, const double* __restrict__ norms,
+                                                    T* __restrict__ delta, T* __restrict__ noise) {
+  const int n = fa.n, nt = fa.nt, z2 = nt >= 2 ? 2 : 1;
+  const int nzp = nt / z2;
+  int b = blockIdx.x;
+  const int tzp = b % nzp; b /= nzp;
+  const int ty = b % nt; b /= nt;
+  const int tx = b % nt;
+  const int ph = b / nt;
+  const int ly = threadIdx.x >> (z2 == 2 ? 5 : 4);
+  const int lzz = threadIdx.x & (16 * z2 - 1);
+  const int tz = tzp * z2 + (lzz >> 4), lz = lzz & 15;
   const double alpha = norms[CNPC_NORM_ALPHA];
-  double cd[4], cn[4];
+  T cd[4], cn[4];
   if (fa.nsets == 2) {
-    cd[0] = 1.0; cd[1] = -alpha; cn[0] = 1.0; cn[1] = alpha * alpha;
+    cd[0] = T(1); cd[1] = T(-alpha); cn[0] = T(1); cn[1] = T(alpha * alpha);
   } else {
-    cd[0] = 1.0; cd[1] = -alpha; cd[2] = 0.0; cd[3] = 0.0;
-    cn[0] = 0.0; cn[1] = 0.0; cn[2] = 1.0; cn[3] = alpha * alpha;
+    cd[0] = T(1); cd[1] = T(-alpha); cd[2] = T(0); cd[3] = T(0);
+    cn[0] = T(0); cn[1] = T(0); cn[2] = T(1); cn[3] = T(alpha * alpha);
   }
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n3 * fa.nphase;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int ph = (int)(idx / n3);
-    const int64_t cell = idx - ph * n3;
-    const int z = (int)(cell % n), y = (int)((cell / n) % n), x = (int)(cell / ((int64_t)n * n));
+  // y and z covers: (tile, local index) pairs
+  int cy = 1, cz = 1, tyc[2], lyc[2], tzc[2], lzc[2];
+  tyc[0] = ty; lyc[0] = ly + 1;
+  if (ly <= 1) { tyc[1] = (ty - 1 + nt) % nt; lyc[1] = ly + 17; cy = 2; }
+  else if (ly == 15) { tyc[1] = (ty + 1) % nt; lyc[1] = 0; cy = 2; }
+  tzc[0] = tz; lzc[0] = lz + 1;
+  if (lz <= 1) { tzc[1] = (tz - 1 + nt) % nt; lzc[1] = lz + 17; cz = 2; }
+  else if (lz == 15) { tzc[1] = (tz + 1) % nt; lzc[1] = 0; cz = 2; }
+  const int64_t n3 = (int64_t)n * n * n;
+  const int y = ty * 16 + ly, z = tz * 16 + lz;
+  for (int lx = 0; lx < 16; ++lx) {
+    int cx = 1, txc[2], lxc[2];
+    txc[0] = tx; lxc[0] = lx + 1;
+    if (lx <= 1) { txc[1] = (tx - 1 + nt) % nt; lxc[1] = lx + 17; cx = 2; }
+    else if (lx == 15) { txc[1] = (tx + 1) % nt; lxc[1] = 0; cx = 2; }
     T d = T(0), q = T(0);
     for (int s = 0; s < fa.nsets; ++s) {
-      const T v = gather_node<T>(fa.blocks[s], fa.nt, fa.nphase, ph, x, y, z);
-      d += T(cd[s]) * v;
-      q += T(cn[s]) * v;
+      const T* bl = fa.blocks[s];
+      T v = T(0);
+      for (int a = 0; a < cx; ++a)
+        for (int bb = 0; bb < cy; ++bb)
+          for (int c = 0; c < cz; ++c) {
+            const int64_t tile = ((int64_t)txc[a] * nt + tyc[bb]) * nt + tzc[c];
+            v += bl[(tile * fa.nphase + ph) * BVOL + (lxc[a] * BW + lyc[bb]) * BW + lzc[c]];
+          }
+      d += cd[s] * v;
+      q += cn[s] * v;
     }
+    const int64_t idx = ph * n3 + ((int64_t)(tx * 16 + lx) * n + y) * n + z;
     delta[idx] = d;
     if (noise) noise[idx] = q;
   }
@@ -620,6 +693,18 @@ static cnpc_status sort_and_paint(const cnpc_mesh_desc* d, const uint32_t* pos, 
   const int npow = weighted ? 2 : 1;
   for (int pw = 0; pw < npow; ++pw) {
     T* blocks = reinterpret_cast<T*>(ws + L.off_blocks[set0 + 2 * pw]);
+    if constexpr (sizeof(T) == 4 && RS == 3) {
+      kt_begin(CNPC_KT_PAINT, s);
+      if (d->assign == CNPC_TSC)
+        hipLaunchKernelGGL((k_paint_tiles_u32<CNPC_TSC>), dim3(L.ntiles), dim3(PAINT32_THREADS), 0, s, rec, start,
+                           count, g, L.nphase, reinterpret_cast<float*>(blocks));
+      else
+        hipLaunchKernelGGL((k_paint_tiles_u32<CNPC_CIC>), dim3(L.ntiles), dim3(PAINT32_THREADS), 0, s, rec, start,
+                           count, g, L.nphase, reinterpret_cast<float*>(blocks));
+      kt_end(CNPC_KT_PAINT, s);
+      CNPC_HIP(hipGetLastError());
+      continue;
+    }
     for (int ph0 = 0; ph0 < L.nphase; ph0 += nph) {
       kt_begin(CNPC_KT_PAINT, s);
       if (d->assign == CNPC_TSC)
@@ -657,10 +742,10 @@ static cnpc_status paint_t(const cnpc_mesh_desc* d, const uint32_t* gpos, const 
     else
       CNPC_TRY((sort_and_paint<T, 3>(d, cpos[c], nullptr, cn[c], c, weighted, ws, L, s)));
   }
-  const int64_t total = (int64_t)d->n * d->n * d->n * L.nphase;
-  const int64_t nb = std::min<int64_t>((total + 255) / 256, 65536);
+  const int z2 = L.nt >= 2 ? 2 : 1;
+  const int64_t nb = (int64_t)L.nphase * L.nt * L.nt * (L.nt / z2);
   kt_begin(CNPC_KT_FOLD, s);
-  hipLaunchKernelGGL((k_fold<T>), dim3((unsigned)nb), dim3(256), 0, s, fa, norms, delta, noise);
+  hipLaunchKernelGGL((k_fold_tiles<T>), dim3((unsigned)nb), dim3(256 * z2), 0, s, fa, norms, delta, noise);
   kt_end(CNPC_KT_FOLD, s);
   CNPC_HIP(hipGetLastError());
   return CNPC_OK;
