@@ -414,6 +414,46 @@ __global__ void __launch_bounds__(1024) k_paint_tiles(const Rec<RS>* __restrict_
 constexpr int PAINT32_THREADS = 1024;
 constexpr int PAINT32_OWN = (2 * BVOL + PAINT32_THREADS - 1) / PAINT32_THREADS;  // nodes per thread
 
+// 1-D stencil in 32-bit integer arithmetic (shift <= 28): same nodes and
+// weights as stencil_1d<float>.
+template <int ASSIGN>
+__device__ __forceinline__ int stencil32(uint32_t p, int shift, int phase, float* wt) {
+  const uint32_t one = 1u << shift, half = one >> 1;
+  const int f = (int)(p & (one - 1u));
+  const float inv = 1.0f / (float)one;
+  if constexpr (ASSIGN == CNPC_TSC) {
+    int off, dfix;
+    if (phase == 0) {
+      const bool up = f >= (int)half;
+      off = up ? 1 : 0;
+      dfix = up ? f - (int)one : f;
+    } else {
+      off = 0;
+      dfix = f - (int)half;
+    }
+    const float d = (float)dfix * inv;
+    const float a = 0.5f - d, b = 0.5f + d;
+    wt[0] = 0.5f * a * a;
+    wt[1] = 0.75f - d * d;
+    wt[2] = 0.5f * b * b;
+    return off - 1;
+  } else {
+    if (phase == 0) {
+      const float d = (float)f * inv;
+      wt[0] = 1.0f - d;
+      wt[1] = d;
+      return 0;
+    }
+    const bool up = f >= (int)half;
+    const int off = up ? 0 : -1;
+    const int dfix = up ? f - (int)half : f + (int)half;
+    const float d = (float)dfix * inv;
+    wt[0] = 1.0f - d;
+    wt[1] = d;
+    return off;
+  }
+}
+
 template <int ASSIGN>
 __global__ void __launch_bounds__(PAINT32_THREADS) k_paint_tiles_u32(const Rec<3>* __restrict__ rec,
                                                                      const uint32_t* __restrict__ start,
@@ -423,7 +463,7 @@ __global__ void __launch_bounds__(PAINT32_THREADS) k_paint_tiles_u32(const Rec<3
   constexpr float SCALE = ASSIGN == CNPC_TSC ? 4194304.0f : 2097152.0f;  // 2^22, 2^21
   constexpr int ROUNDS_PER_FLUSH = ASSIGN == CNPC_TSC ? 2 : 1;
   constexpr int NP = ASSIGN == CNPC_TSC ? 3 : 2;
-  __shared__ uint32_t acc[2 * BVOL];
+  __shared__ __align__(16) uint32_t acc[2 * BVOL];
   const int t = blockIdx.x;
   const int shift = g.shift;
   const int nv = nphase * BVOL;
@@ -445,18 +485,18 @@ __global__ void __launch_bounds__(PAINT32_THREADS) k_paint_tiles_u32(const Rec<3
       const int bz = ((int)(pz >> shift) & 15) + 1;
       for (int ph = 0; ph < nphase; ++ph) {
         float wx[3], wy[3], wz[3];
-        const int ox = stencil_1d<float>(px, shift, ASSIGN, ph, wx);
-        const int oy = stencil_1d<float>(py, shift, ASSIGN, ph, wy);
-        const int oz = stencil_1d<float>(pz, shift, ASSIGN, ph, wz);
-        uint32_t* a = acc + ph * BVOL + (bx + ox) * BW * BW + (by + oy) * BW + (bz + oz);
+        const int ox = stencil32<ASSIGN>(px, shift, ph, wx);
+        const int oy = stencil32<ASSIGN>(py, shift, ph, wy);
+        const int oz = stencil32<ASSIGN>(pz, shift, ph, wz);
+        const int a0 = ph * BVOL + (bx + ox) * BW * BW + (by + oy) * BW + (bz + oz);
 #pragma unroll
         for (int ix = 0; ix < NP; ++ix)
 #pragma unroll
           for (int iy = 0; iy < NP; ++iy) {
             const float vxy = wx[ix] * wy[iy] * SCALE;
+            const int ai = a0 + ix * BW * BW + iy * BW;
 #pragma unroll
-            for (int iz = 0; iz < NP; ++iz)
-              atomicAdd(&a[ix * BW * BW + iy * BW + iz], __float2uint_rn(vxy * wz[iz]));
+            for (int iz = 0; iz < NP; ++iz) atomicAdd(&acc[ai + iz], __float2uint_rn(vxy * wz[iz]));
           }
       }
     }

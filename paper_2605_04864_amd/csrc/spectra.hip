@@ -155,19 +155,80 @@ __device__ __forceinline__ T ylm_one(int l, int m, int part, T x, T y, T z) {
   return c * (part ? si : sr);
 }
 
-// Weight of field (l, m, part) at the node with observer-relative position
-// (rx, ry, rz) (local line of sight) or for the fixed line of sight.
+// Solid-harmonic form of y_l^m: with r the observer-relative node position,
+// R = |r| and s = r_x + i r_y,  y_l^m(r / R) = Q_lm(r_z, R^2) s^m / R^l, where
+// Q_lm = c_lm(u_z) R^(l-m) (c_lm: the z factor of ylm_one) written as
+// z^odd (A z^4 + B z^2 R^2 + C R^4 + D z^2 + E R^2 + F) with z = r_z.
+struct SolidQ {
+  double A, B, C, D, E, F;
+  int odd;
+};
+
+__device__ __forceinline__ SolidQ solid_coef(int l, int m) {
+  SolidQ q = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0};
+  switch (l * 8 + m) {
+    case 0: q.F = 1.f; break;
+    case 8: q.odd = 1; q.F = 1.f; break;
+    case 9: q.F = -0.70710678118654752440; break;
+    case 16: q.D = 1.5; q.E = -0.5; break;
+    case 17: q.odd = 1; q.F = -1.22474487139158904910; break;
+    case 18: q.F = 0.61237243569579452455; break;
+    case 24: q.odd = 1; q.D = 2.5; q.E = -1.5; break;
+    case 25: q.D = -2.16506350946109661690; q.E = 0.43301270189221932338; break;
+    case 26: q.odd = 1; q.F = 1.36930639376291528364; break;
+    case 27: q.F = -0.55901699437494742410; break;
+    case 32: q.A = 4.375; q.B = -3.75; q.C = 0.375; break;
+    case 33: q.odd = 1; q.D = -3.91311896062463196870; q.E = 1.67705098312484227230; break;
+    case 34: q.D = 2.76699295264733191550; q.E = -0.39528470752104741650; break;
+    case 35: q.odd = 1; q.F = -1.47901994577490951707; break;
+    default: q.F = 0.52291251658379721749; break;  // l = 4, m = 4
+  }
+  return q;
+}
+
 template <typename T>
-__device__ __forceinline__ T node_weight(const Geo& g, int l, int m, int part, T rx, T ry, T rz) {
-  if (g.global_los) return ylm_one<T>(l, m, part, T(g.los[0]), T(g.los[1]), T(g.los[2]));
-  const T inv = T(1) / sqrt(rx * rx + ry * ry + rz * rz);
-  return ylm_one<T>(l, m, part, rx * inv, ry * inv, rz * inv);
+__device__ __forceinline__ T solid_eval(const SolidQ& q, T z, T r2) {
+  const T z2 = z * z;
+  const T v = (T(q.A) * z2 + T(q.B) * r2 + T(q.D)) * z2 + (T(q.C) * r2 + T(q.E)) * r2 + T(q.F);
+  return q.odd ? v * z : v;
+}
+
+// R^k for R^2 = q and a small integer k; FP32 uses the hardware reciprocal and
+// reciprocal square root (about 1 ulp), FP64 exact division and sqrt.
+template <typename T>
+__device__ __forceinline__ T pow_r(T q, int k) {
+  const int a = k < 0 ? -k : k;
+  T r = T(1);
+  if constexpr (sizeof(T) == 4) {
+    const T b = k < 0 ? __builtin_amdgcn_rcpf(q) : q;
+    if (a & 1) r = k < 0 ? __builtin_amdgcn_rsqf(q) : __builtin_sqrtf(q);
+    for (int i = 0; i < a / 2; ++i) r *= b;
+  } else {
+    if (a & 1) r = sqrt(q);
+    for (int i = 0; i < a / 2; ++i) r *= q;
+    if (k < 0) r = T(1) / r;
+  }
+  return r;
+}
+
+// Re (part 0) or Im (part 1) of (x + i y)^m
+template <typename T>
+__device__ __forceinline__ T cpow_part(T x, T y, int m, int part) {
+  T sr = T(1), si = T(0);
+  for (int k = 0; k < m; ++k) {
+    const T t = sr * x - si * y;
+    si = sr * y + si * x;
+    sr = t;
+  }
+  return part ? si : sr;
 }
 
 // Register z-pass for N = R^2: a group of R lanes owns one row pair (ix, 2j),
-// (ix, 2j+1) of delta, keeps its 2R samples in registers and, field after
-// field, forms the weighted pair as one complex row, transforms it with
-// row_fft_rr and writes kz < kz_keep of both real rows (two-for-one split).
+// (ix, 2j+1) of delta and, field after field (fields ordered by l), forms the
+// weighted pair as one complex row, transforms it with row_fft_rr and writes
+// kz < kz_keep of both real rows (two-for-one split).  Local line of sight:
+// the lanes keep e = delta / R^l for the current l and multiply by
+// Q_lm(r_z, R^2) and the row constant Re / Im (r_x + i r_y)^m.
 template <typename T, int R>
 __global__ void __launch_bounds__(256) k_zpass_ylm_rr(const T* __restrict__ delta, cx<T>* __restrict__ out,
                                                       FieldTable ft, int kz_keep, int64_t fstride, Geo g) {
@@ -181,52 +242,79 @@ __global__ void __launch_bounds__(256) k_zpass_ylm_rr(const T* __restrict__ delt
   const int q = blockIdx.x * GR + grp;
   const int ix = q / (N / 2), iy0 = 2 * (q - ix * (N / 2));
   const T* r0 = delta + ((int64_t)ix * N + iy0) * N;
-  T d0[R], d1[R], rz[R];
+  T e0[R], e1[R], rz[R];
 #pragma unroll
   for (int n2 = 0; n2 < R; ++n2) {
     const int z = rank + R * n2;
-    d0[n2] = r0[z];
-    d1[n2] = r0[N + z];
+    e0[n2] = r0[z];
+    e1[n2] = r0[N + z];
     rz[n2] = T(z * g.h - g.obs[2]);
   }
   const T rx = T(ix * g.h - g.obs[0]);
   const T ry0 = T(iy0 * g.h - g.obs[1]), ry1 = T((iy0 + 1) * g.h - g.obs[1]);
+  const T rho0 = rx * rx + ry0 * ry0, rho1 = rx * rx + ry1 * ry1;
   __syncthreads();
   const int src = (R - rank) & (R - 1);
   const int K2 = (kz_keep + R - 1) / R;
   cx<T>* orow = out + ((int64_t)ix * N + iy0) * kz_keep;
-  for (int f = 0; f < ft.nf; ++f) {
-    const int l = ft.ell[f], m = ft.m[f], p = ft.part[f];
-    cx<T> v[R];
+  int lcur = 0;
+  for (int f0 = 0; f0 < ft.nf;) {
+    // fields come in runs of equal l: rescale e = delta / R^l once per run
+    const int l = ft.ell[f0];
+    int f1 = f0 + 1;
+    while (f1 < ft.nf && ft.ell[f1] == l) ++f1;
+    if (!g.global_los && l != lcur) {
+      const int dl = lcur - l;
 #pragma unroll
-    for (int n2 = 0; n2 < R; ++n2) {
-      // the directions are recomputed per field: an opaque copy of rz keeps
-      // the compiler from hoisting 2R unit vectors out of the field loop
-      T z = rz[n2];
-      asm volatile("" : "+v"(z));
-      const T w0 = node_weight<T>(g, l, m, p, rx, ry0, z);
-      const T w1 = node_weight<T>(g, l, m, p, rx, ry1, z);
-      v[n2] = cx<T>{d0[n2] * w0, d1[n2] * w1};
+      for (int n2 = 0; n2 < R; ++n2) {
+        const T za = rz[n2];
+        e0[n2] *= pow_r<T>(rho0 + za * za, dl);
+        e1[n2] *= pow_r<T>(rho1 + za * za, dl);
+      }
+      lcur = l;
     }
-    row_fft_rr<T, R, -1>(v, rank, buf, tw);
-    // lane k1 holds Z[k1 + R k2]; Z[N - k] sits in lane (R - k1) & (R - 1),
-    // register R - 1 - k2 (k1 > 0) or in this lane, register (R - k2) & (R - 1)
-    cx<T>* o = orow + (int64_t)f * fstride;
+    for (int f = f0; f < f1; ++f) {
+      const int m = ft.m[f], p = ft.part[f];
+      cx<T> v[R];
+      if (g.global_los) {
+        const T w = ylm_one<T>(l, m, p, T(g.los[0]), T(g.los[1]), T(g.los[2]));
 #pragma unroll
-    for (int k2 = 0; k2 < R / 2; ++k2) {
-      if (k2 < K2) {
-        const cx<T> a = v[R - 1 - k2];
-        const cx<T> sh = {__shfl(a.x, src, R), __shfl(a.y, src, R)};
-        const cx<T> zm = cconj(rank ? sh : v[(R - k2) & (R - 1)]);
-        const cx<T> zk = v[k2];
-        const int k = rank + R * k2;
-        if (k < kz_keep) {
-          const cx<T> dd = csub(zk, zm);
-          o[k] = cscale(cadd(zk, zm), T(0.5));
-          o[kz_keep + k] = cx<T>{T(0.5) * dd.y, T(-0.5) * dd.x};
+        for (int n2 = 0; n2 < R; ++n2) v[n2] = cx<T>{e0[n2] * w, e1[n2] * w};
+      } else {
+        const T s0 = cpow_part<T>(rx, ry0, m, p), s1 = cpow_part<T>(rx, ry1, m, p);
+        const SolidQ qc = solid_coef(l, m);
+#pragma unroll
+        for (int n2 = 0; n2 < R; ++n2) {
+          // opaque copy: keeps r_z^2 and R^2 of all nodes from being hoisted
+          // out of the field loop into registers
+          T za = rz[n2];
+          asm volatile("" : "+v"(za));
+          const T w0 = solid_eval<T>(qc, za, rho0 + za * za) * s0;
+          const T w1 = solid_eval<T>(qc, za, rho1 + za * za) * s1;
+          v[n2] = cx<T>{e0[n2] * w0, e1[n2] * w1};
+        }
+      }
+      row_fft_rr<T, R, -1>(v, rank, buf, tw);
+      // lane k1 holds Z[k1 + R k2]; Z[N - k] sits in lane (R - k1) & (R - 1),
+      // register R - 1 - k2 (k1 > 0) or in this lane, register (R - k2) & (R - 1)
+      cx<T>* o = orow + (int64_t)f * fstride;
+#pragma unroll
+      for (int k2 = 0; k2 < R / 2; ++k2) {
+        if (k2 < K2) {
+          const cx<T> a = v[R - 1 - k2];
+          const cx<T> sh = {__shfl(a.x, src, R), __shfl(a.y, src, R)};
+          const cx<T> zm = cconj(rank ? sh : v[(R - k2) & (R - 1)]);
+          const cx<T> zk = v[k2];
+          const int k = rank + R * k2;
+          if (k < kz_keep) {
+            const cx<T> dd = csub(zk, zm);
+            o[k] = cscale(cadd(zk, zm), T(0.5));
+            o[kz_keep + k] = cx<T>{T(0.5) * dd.y, T(-0.5) * dd.x};
+          }
         }
       }
     }
+    f0 = f1;
   }
 }
 
