@@ -455,7 +455,7 @@ __device__ __forceinline__ int stencil32(uint32_t p, int shift, int phase, float
 }
 
 template <int ASSIGN>
-__global__ void __launch_bounds__(PAINT32_THREADS) k_paint_tiles_u32(const Rec<3>* __restrict__ rec,
+__global__ void __launch_bounds__(PAINT32_THREADS, 8) k_paint_tiles_u32(const Rec<3>* __restrict__ rec,
                                                                      const uint32_t* __restrict__ start,
                                                                      const uint32_t* __restrict__ count,
                                                                      TileGeom g, int nphase,
@@ -541,44 +541,71 @@ __global__ void __launch_bounds__(512) k_fold_tiles(FoldArgs<T> fa, const double
   const int lzz = threadIdx.x & (16 * z2 - 1);
   const int tz = tzp * z2 + (lzz >> 4), lz = lzz & 15;
   const double alpha = norms[CNPC_NORM_ALPHA];
-  T cd[4], cn[4];
+  T cd[4] = {T(0), T(0), T(0), T(0)}, cn[4] = {T(0), T(0), T(0), T(0)};
   if (fa.nsets == 2) {
     cd[0] = T(1); cd[1] = T(-alpha); cn[0] = T(1); cn[1] = T(alpha * alpha);
   } else {
     cd[0] = T(1); cd[1] = T(-alpha); cd[2] = T(0); cd[3] = T(0);
     cn[0] = T(0); cn[1] = T(0); cn[2] = T(1); cn[3] = T(alpha * alpha);
   }
-  // y and z covers: (tile, local index) pairs
-  int cy = 1, cz = 1, tyc[2], lyc[2], tzc[2], lzc[2];
-  tyc[0] = ty; lyc[0] = ly + 1;
-  if (ly <= 1) { tyc[1] = (ty - 1 + nt) % nt; lyc[1] = ly + 17; cy = 2; }
-  else if (ly == 15) { tyc[1] = (ty + 1) % nt; lyc[1] = 0; cy = 2; }
-  tzc[0] = tz; lzc[0] = lz + 1;
-  if (lz <= 1) { tzc[1] = (tz - 1 + nt) % nt; lzc[1] = lz + 17; cz = 2; }
-  else if (lz == 15) { tzc[1] = (tz + 1) % nt; lzc[1] = 0; cz = 2; }
+  // y and z covers: own block (local index + 1) and, near the tile faces, the
+  // lower (local + 17) or upper (local 0) neighbour; a second entry with
+  // valid flag off contributes nothing
+  const int tyo = ly <= 1 ? (ty - 1 + nt) % nt : (ty + 1) % nt;
+  const int lyo = ly <= 1 ? ly + 17 : 0;
+  const bool hy = ly <= 1 || ly == 15;
+  const int tzo = lz <= 1 ? (tz - 1 + nt) % nt : (tz + 1) % nt;
+  const int lzo = lz <= 1 ? lz + 17 : 0;
+  const bool hz = lz <= 1 || lz == 15;
   const int64_t n3 = (int64_t)n * n * n;
   const int y = ty * 16 + ly, z = tz * 16 + lz;
-  for (int lx = 0; lx < 16; ++lx) {
-    int cx = 1, txc[2], lxc[2];
-    txc[0] = tx; lxc[0] = lx + 1;
-    if (lx <= 1) { txc[1] = (tx - 1 + nt) % nt; lxc[1] = lx + 17; cx = 2; }
-    else if (lx == 15) { txc[1] = (tx + 1) % nt; lxc[1] = 0; cx = 2; }
-    T d = T(0), q = T(0);
-    for (int s = 0; s < fa.nsets; ++s) {
-      const T* bl = fa.blocks[s];
-      T v = T(0);
-      for (int a = 0; a < cx; ++a)
-        for (int bb = 0; bb < cy; ++bb)
-          for (int c = 0; c < cz; ++c) {
-            const int64_t tile = ((int64_t)txc[a] * nt + tyc[bb]) * nt + tzc[c];
-            v += bl[(tile * fa.nphase + ph) * BVOL + (lxc[a] * BW + lyc[bb]) * BW + lzc[c]];
+  const int64_t tstride = (int64_t)fa.nphase * BVOL;
+  // offsets (elements) of the four (y, z) cover combinations within a tile
+  // column x: tile index (tx' nt + ty') nt + tz' times tstride plus local part
+  const int64_t cyz[4] = {((int64_t)ty * nt + tz) * tstride + (ly + 1) * BW + (lz + 1),
+                          ((int64_t)tyo * nt + tz) * tstride + lyo * BW + (lz + 1),
+                          ((int64_t)ty * nt + tzo) * tstride + (ly + 1) * BW + lzo,
+                          ((int64_t)tyo * nt + tzo) * tstride + lyo * BW + lzo};
+  const bool vyz[4] = {true, hy, hz, hy && hz};
+  const int64_t xstride = (int64_t)nt * nt * tstride;
+  // groups of XG nodes along x: every load of the group is issued before any
+  // store (the block reads cannot alias the mesh writes)
+  constexpr int XG = 4;
+  for (int lx0 = 0; lx0 < 16; lx0 += XG) {
+    T v[XG][4];
+#pragma unroll
+    for (int u = 0; u < XG; ++u) {
+      const int lx = lx0 + u;
+      const bool hx = lx <= 1 || lx == 15;
+      const int txo = lx <= 1 ? (tx - 1 + nt) % nt : (tx + 1) % nt;
+      const int64_t cx0 = tx * xstride + (int64_t)ph * BVOL + (lx + 1) * BW * BW;
+      const int64_t cx1 = txo * xstride + (int64_t)ph * BVOL + (lx <= 1 ? lx + 17 : 0) * BW * BW;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        T acc = T(0);
+        if (s < fa.nsets) {
+          const T* __restrict__ bl = fa.blocks[s];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            if (vyz[k]) acc += bl[cx0 + cyz[k]];
+            if (hx && vyz[k]) acc += bl[cx1 + cyz[k]];
           }
-      d += cd[s] * v;
-      q += cn[s] * v;
+        }
+        v[u][s] = acc;
+      }
     }
-    const int64_t idx = ph * n3 + ((int64_t)(tx * 16 + lx) * n + y) * n + z;
-    delta[idx] = d;
-    if (noise) noise[idx] = q;
+#pragma unroll
+    for (int u = 0; u < XG; ++u) {
+      T d = T(0), q = T(0);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        d += cd[s] * v[u][s];
+        q += cn[s] * v[u][s];
+      }
+      const int64_t idx = ph * n3 + ((int64_t)(tx * 16 + lx0 + u) * n + y) * n + z;
+      delta[idx] = d;
+      if (noise) noise[idx] = q;
+    }
   }
 }
 
