@@ -131,13 +131,25 @@ cnpc_status cnpc_norms(const cnpc_mesh_desc* desc, const double* gal_sums, const
  * CIC: nodes floor(u), floor(u)+1; TSC: nodes floor(u+1/2)+{-1,0,1}, with
  * u = p N / 2^32 (mesh B: u - 1/2).  Outputs are overwritten (not accumulated):
  * delta and noise each hold (1 + interlace) N^3 elements of desc->dtype.
- * Particles are bucketed by 16^3-node tiles and accumulated in LDS; sums inside
- * a tile are order dependent at FP32 rounding. */
+ * Particles are counting-sorted by 16^3-node tiles and accumulated in LDS as
+ * integer fixed point (2^-40 units; 2^-22 for unit-weight FP32 TSC, 2^-21
+ * for CIC), so the meshes do not depend on the order of the additions.
+ * Workspace: cnpc_paint_workspace_size bytes (an upper bound for weighted and
+ * unweighted catalogs), owned by the caller, not retained after the call. */
 size_t cnpc_paint_workspace_size(const cnpc_mesh_desc* desc, int64_t ngal, int64_t nran);
 cnpc_status cnpc_paint(const cnpc_mesh_desc* desc, const uint32_t* gpos, const float* gw,
                        int64_t ngal, const uint32_t* rpos, const float* rw, int64_t nran,
                        const double* norms, void* delta, void* noise, void* ws, size_t ws_bytes,
                        void* stream);
+/* cnpc_catalog_sums of both catalogs, cnpc_norms and cnpc_paint in one call:
+ * the tile histogram of the sort is taken during the catalog-sum pass, which
+ * saves one read of every particle.  gal_sums, ran_sums: CNPC_SUMS_LEN device
+ * doubles each, or NULL when not wanted; norms: CNPC_NORMS_LEN device doubles
+ * (output).  Same meshes and workspace size as cnpc_paint. */
+cnpc_status cnpc_paint_fkp(const cnpc_mesh_desc* desc, const uint32_t* gpos, const float* gw,
+                           int64_t ngal, const uint32_t* rpos, const float* rw, int64_t nran,
+                           double* gal_sums, double* ran_sums, double* norms, void* delta,
+                           void* noise, void* ws, size_t ws_bytes, void* stream);
 
 /* ---- fft: batched 3-D real transforms (all hot-path transforms) ----
  * Full r2c: `batch` real meshes -> half-layout spectra.  Full c2r: half-layout

@@ -194,6 +194,20 @@ cnpc_status cnpc_paint(const cnpc_mesh_desc* d, const uint32_t* gpos, const floa
                       as_stream(stream));
 }
 
+cnpc_status cnpc_paint_fkp(const cnpc_mesh_desc* d, const uint32_t* gpos, const float* gw, int64_t ngal,
+                           const uint32_t* rpos, const float* rw, int64_t nran, double* gal_sums,
+                           double* ran_sums, double* norms, void* delta, void* noise, void* ws,
+                           size_t ws_bytes, void* stream) {
+  API_BEGIN;
+  CNPC_TRY(check_desc(d));
+  CNPC_REQUIRE(ngal >= 1 && ngal < ((int64_t)1 << 32), "ngal must be in [1, 2^32)");
+  CNPC_REQUIRE(nran >= 1 && nran < ((int64_t)1 << 32), "nran must be in [1, 2^32)");
+  CNPC_REQUIRE(gpos && rpos && norms && delta && ws, "null pointer argument");
+  CNPC_REQUIRE((gw == nullptr) == (rw == nullptr), "give weights for both catalogs or for neither");
+  return launch_paint_fkp(d, gpos, gw, ngal, rpos, rw, nran, gal_sums, ran_sums, norms, delta, noise, ws,
+                          ws_bytes, as_stream(stream));
+}
+
 static cnpc_status check_band(const cnpc_mesh_desc* d, int band) {
   CNPC_REQUIRE(band == 0 || (pow2(band) && band >= 1 && band <= d->n / 2),
                "band must be 0 (full) or a power of two <= n/2 (got %d)", band);

@@ -247,7 +247,7 @@ constexpr int MF_ROW = MF_KC + MF_PAD;
 // registers meanwhile.  Splitting the points (KG > 1) keeps each operand split
 // computed once; splitting the pairs (KG = 1) bounds the accumulators per wave.
 template <int MTW, int NT, int KG, int MAXF>
-__global__ void __launch_bounds__(256) k_contract_mfma(const float* __restrict__ fields, int64_t npts,
+__global__ void __launch_bounds__(256, 2) k_contract_mfma(const float* __restrict__ fields, int64_t npts,
                                                        int nf, int nshell, int npairs, ContractCols cc,
                                                        double* __restrict__ partial) {
   extern __shared__ __align__(16) unsigned char smem_raw[];

@@ -21,7 +21,9 @@ struct FoldArgs {
 struct PaintLayout {
   int nt, ntiles, nphase, nsets, nbuckets;
   size_t off_rec, off_tmp;  // sorted records, bucket-ordered records (shared by both catalogs)
-  size_t off_count, off_start, off_cursor, off_bcur;
+  size_t off_count[2];           // tile counts of the galaxy / random catalog
+  size_t off_partial, off_sums;  // catalog-sum partials and sums (fused entry point)
+  size_t off_start, off_cursor, off_bcur;
   size_t off_blocks[4];
   size_t total;
 };
@@ -35,6 +37,10 @@ cnpc_status launch_paint(const cnpc_mesh_desc* d, const uint32_t* gpos, const fl
                          int64_t ngal, const uint32_t* rpos, const float* rw, int64_t nran,
                          const double* norms, void* delta, void* noise, void* ws, size_t ws_bytes,
                          hipStream_t s);
+cnpc_status launch_paint_fkp(const cnpc_mesh_desc* d, const uint32_t* gpos, const float* gw,
+                             int64_t ngal, const uint32_t* rpos, const float* rw, int64_t nran,
+                             double* gsums, double* rsums, double* norms, void* delta, void* noise,
+                             void* ws, size_t ws_bytes, hipStream_t s);
 // per-workgroup LDS limit of the current device (bytes)
 size_t lds_limit();
 

@@ -17,21 +17,67 @@ constexpr int SORT_BLOCK = 1024;
 constexpr int SORT_PER_THREAD = 64;    // particles per thread per sort workgroup
 constexpr int LDS_TILES_MAX = 8192;    // LDS-aggregated sort up to this many tiles
 
+// ------------------------------------------------------------ tile keys --
+struct TileGeom {
+  int shift;  // 32 - log2(n): node index = p >> shift
+  int nt;     // tiles per side
+  int ls;     // log2(S)
+  int lnb;    // log2(buckets per side)
+};
+
+template <int RS>
+struct Rec {
+  uint32_t v[RS];
+};
+
+__device__ __forceinline__ int key_of(int tx, int ty, int tz, const TileGeom& g) {
+  const int m = (1 << g.ls) - 1;
+  const int b = ((((tx >> g.ls) << g.lnb) | (ty >> g.ls)) << g.lnb) | (tz >> g.ls);
+  const int l = ((((tx & m) << g.ls) | (ty & m)) << g.ls) | (tz & m);
+  return (b << (3 * g.ls)) | l;
+}
+
+__device__ __forceinline__ int tile_key(uint32_t px, uint32_t py, uint32_t pz, const TileGeom& g) {
+  return key_of((int)(px >> g.shift) >> 4, (int)(py >> g.shift) >> 4, (int)(pz >> g.shift) >> 4, g);
+}
+
+struct CountArgs {
+  TileGeom g;
+  int ntiles;
+  uint32_t* count;  // nullptr: sums only
+};
+
 // ------------------------------------------------------------ catalog sums --
 __device__ __forceinline__ double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
   return v;
 }
 
-__global__ void __launch_bounds__(256) k_catalog_sums(const uint32_t* __restrict__ pos,
+constexpr int SUMS_THREADS = 1024;
+constexpr int SUMS_BLOCKS = 256;
+
+__global__ void __launch_bounds__(SUMS_THREADS) k_catalog_sums(const uint32_t* __restrict__ pos,
                                                       const float* __restrict__ w, int64_t n,
-                                                      SumsArgs a, double* __restrict__ partial) {
+                                                      SumsArgs a, double* __restrict__ partial,
+                                                      CountArgs ca) {
+  extern __shared__ uint32_t lcount[];
+  const bool count = ca.count != nullptr;
+  const bool lds = count && ca.ntiles <= LDS_TILES_MAX;
+  if (lds) {
+    for (int t = threadIdx.x; t < ca.ntiles; t += blockDim.x) lcount[t] = 0;
+    __syncthreads();
+  }
   double acc[CNPC_SUMS_LEN];
 #pragma unroll
   for (int q = 0; q < CNPC_SUMS_LEN; ++q) acc[q] = 0.0;
   const double scale = a.boxsize / 4294967296.0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
+    if (count) {
+      const int t = tile_key(pos[i], pos[n + i], pos[2 * n + i], ca.g);
+      if (lds) atomicAdd(&lcount[t], 1u);
+      else atomicAdd(&ca.count[t], 1u);
+    }
     const double wi = w ? (double)w[i] : 1.0;
     const double w2 = wi * wi, w3 = w2 * wi;
     acc[0] += wi;
@@ -57,7 +103,7 @@ __global__ void __launch_bounds__(256) k_catalog_sums(const uint32_t* __restrict
     racah_ylm<double>(4, ux, uy, uz, re, im);
     for (int m = 0; m <= 4; ++m) { acc[q++] += w3 * re[m]; acc[q++] -= w3 * im[m]; }
   }
-  __shared__ double red[4][CNPC_SUMS_LEN];
+  __shared__ double red[SUMS_THREADS / 64][CNPC_SUMS_LEN];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
   for (int q = 0; q < CNPC_SUMS_LEN; ++q) {
@@ -69,6 +115,12 @@ __global__ void __launch_bounds__(256) k_catalog_sums(const uint32_t* __restrict
     double v = 0.0;
     for (int k = 0; k < (int)(blockDim.x >> 6); ++k) v += red[k][threadIdx.x];
     partial[(int64_t)blockIdx.x * CNPC_SUMS_LEN + threadIdx.x] = v;
+  }
+  if (lds) {
+    for (int t = threadIdx.x; t < ca.ntiles; t += blockDim.x) {
+      const uint32_t c = lcount[t];
+      if (c) atomicAdd(&ca.count[t], c);
+    }
   }
 }
 
@@ -106,29 +158,6 @@ __global__ void k_norms(const double* __restrict__ gs, const double* __restrict_
 // in LDS ordered by key and then store it in per-key runs: first by bucket
 // (few keys, long runs), then by tile inside the bucket.  Records are AoS:
 // (px, py, pz) or (px, py, pz, w bits).
-struct TileGeom {
-  int shift;  // 32 - log2(n): node index = p >> shift
-  int nt;     // tiles per side
-  int ls;     // log2(S)
-  int lnb;    // log2(buckets per side)
-};
-
-template <int RS>
-struct Rec {
-  uint32_t v[RS];
-};
-
-__device__ __forceinline__ int key_of(int tx, int ty, int tz, const TileGeom& g) {
-  const int m = (1 << g.ls) - 1;
-  const int b = ((((tx >> g.ls) << g.lnb) | (ty >> g.ls)) << g.lnb) | (tz >> g.ls);
-  const int l = ((((tx & m) << g.ls) | (ty & m)) << g.ls) | (tz & m);
-  return (b << (3 * g.ls)) | l;
-}
-
-__device__ __forceinline__ int tile_key(uint32_t px, uint32_t py, uint32_t pz, const TileGeom& g) {
-  return key_of((int)(px >> g.shift) >> 4, (int)(py >> g.shift) >> 4, (int)(pz >> g.shift) >> 4, g);
-}
-
 // count[key] += number of particles in the tile (LDS aggregation when it fits)
 __global__ void __launch_bounds__(SORT_BLOCK) k_tile_count(const uint32_t* __restrict__ pos, int64_t n,
                                                            TileGeom g, int ntiles,
@@ -610,26 +639,37 @@ __global__ void __launch_bounds__(512) k_fold_tiles(FoldArgs<T> fa, const double
 }
 
 // ------------------------------------------------------------------- host --
-cnpc_status launch_catalog_sums(const cnpc_mesh_desc* d, const uint32_t* pos, const float* w,
-                                int64_t n, double* sums, void* ws, size_t ws_bytes,
-                                hipStream_t s) {
-  const int nblocks = 1024;
-  if (ws_bytes < (size_t)nblocks * CNPC_SUMS_LEN * sizeof(double)) {
-    set_error("catalog_sums workspace too small");
-    return CNPC_EWORKSPACE;
-  }
+static TileGeom tile_geom(const cnpc_mesh_desc* d);
+
+static cnpc_status sums_counted(const cnpc_mesh_desc* d, const uint32_t* pos, const float* w, int64_t n,
+                                double* sums, double* partial, const CountArgs& ca, hipStream_t s) {
+  const int nblocks = SUMS_BLOCKS;
   SumsArgs a;
   a.boxsize = d->boxsize;
   for (int i = 0; i < 3; ++i) { a.obs[i] = d->observer[i]; a.los[i] = d->los[i]; }
   a.global_los = d->los_mode == CNPC_LOS_GLOBAL;
-  double* partial = reinterpret_cast<double*>(ws);
+  const size_t lds = (ca.count && ca.ntiles <= LDS_TILES_MAX) ? (size_t)ca.ntiles * 4 : 0;
   kt_begin(CNPC_KT_SUMS, s);
-  hipLaunchKernelGGL(k_catalog_sums, dim3(nblocks), dim3(256), 0, s, pos, w, n, a, partial);
+  hipLaunchKernelGGL(k_catalog_sums, dim3(nblocks), dim3(SUMS_THREADS), lds, s, pos, w, n, a, partial, ca);
   kt_end(CNPC_KT_SUMS, s);
   CNPC_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_reduce_partials, dim3(CNPC_SUMS_LEN), dim3(64), 0, s, partial, nblocks, sums);
   CNPC_HIP(hipGetLastError());
   return CNPC_OK;
+}
+
+cnpc_status launch_catalog_sums(const cnpc_mesh_desc* d, const uint32_t* pos, const float* w,
+                                int64_t n, double* sums, void* ws, size_t ws_bytes,
+                                hipStream_t s) {
+  const int nblocks = SUMS_BLOCKS;
+  if (ws_bytes < (size_t)nblocks * CNPC_SUMS_LEN * sizeof(double)) {
+    set_error("catalog_sums workspace too small");
+    return CNPC_EWORKSPACE;
+  }
+  CountArgs ca;
+  ca.ntiles = 0;
+  ca.count = nullptr;
+  return sums_counted(d, pos, w, n, sums, reinterpret_cast<double*>(ws), ca, s);
 }
 
 cnpc_status launch_norms(const cnpc_mesh_desc* d, const double* gs, const double* rs, int64_t ngal,
@@ -666,7 +706,10 @@ PaintLayout paint_layout(const cnpc_mesh_desc* d, int64_t ngal, int64_t nran, bo
   size_t off = 0;
   L.off_rec = off; off = align_up(off + rec);
   L.off_tmp = off; off = align_up(off + (L.nbuckets > 1 ? rec : 0));
-  L.off_count = off; off = align_up(off + (size_t)L.ntiles * 4);
+  L.off_count[0] = off; off = align_up(off + (size_t)L.ntiles * 4);
+  L.off_count[1] = off; off = align_up(off + (size_t)L.ntiles * 4);
+  L.off_partial = off; off = align_up(off + (size_t)SUMS_BLOCKS * CNPC_SUMS_LEN * 8);
+  L.off_sums = off; off = align_up(off + (size_t)2 * CNPC_SUMS_LEN * 8);
   L.off_start = off; off = align_up(off + (size_t)L.ntiles * 4);
   L.off_cursor = off; off = align_up(off + (size_t)L.ntiles * 4);
   L.off_bcur = off; off = align_up(off + (size_t)L.nbuckets * 4);
@@ -726,25 +769,27 @@ static cnpc_status launch_partition(const uint32_t* pos, const float* w, const R
 
 template <typename T, int RS>
 static cnpc_status sort_and_paint(const cnpc_mesh_desc* d, const uint32_t* pos, const float* w, int64_t n,
-                                  int set0, bool weighted, unsigned char* ws, const PaintLayout& L,
-                                  hipStream_t s) {
+                                  int set0, bool weighted, bool counted, unsigned char* ws,
+                                  const PaintLayout& L, hipStream_t s) {
   const TileGeom g = tile_geom(d);
-  uint32_t* count = reinterpret_cast<uint32_t*>(ws + L.off_count);
+  uint32_t* count = reinterpret_cast<uint32_t*>(ws + L.off_count[set0]);
   uint32_t* start = reinterpret_cast<uint32_t*>(ws + L.off_start);
   uint32_t* cursor = reinterpret_cast<uint32_t*>(ws + L.off_cursor);
   uint32_t* bcur = reinterpret_cast<uint32_t*>(ws + L.off_bcur);
   Rec<RS>* rec = reinterpret_cast<Rec<RS>*>(ws + L.off_rec);
   Rec<RS>* tmp = reinterpret_cast<Rec<RS>*>(ws + L.off_tmp);
-  hipLaunchKernelGGL(k_zero_u32, dim3(64), dim3(256), 0, s, count, (int64_t)L.ntiles);
-  CNPC_HIP(hipGetLastError());
-  const size_t lds_count = L.ntiles <= LDS_TILES_MAX ? (size_t)L.ntiles * 4 : 0;
-  const int64_t chunk = (int64_t)SORT_BLOCK * SORT_PER_THREAD;
-  const int64_t nblk = (n + chunk - 1) / chunk;
-  kt_begin(CNPC_KT_SORT, s);
-  hipLaunchKernelGGL(k_tile_count, dim3((unsigned)nblk), dim3(SORT_BLOCK), lds_count, s, pos, n, g, L.ntiles,
-                     count);
-  kt_end(CNPC_KT_SORT, s);
-  CNPC_HIP(hipGetLastError());
+  if (!counted) {
+    hipLaunchKernelGGL(k_zero_u32, dim3(64), dim3(256), 0, s, count, (int64_t)L.ntiles);
+    CNPC_HIP(hipGetLastError());
+    const size_t lds_count = L.ntiles <= LDS_TILES_MAX ? (size_t)L.ntiles * 4 : 0;
+    const int64_t chunk = (int64_t)SORT_BLOCK * SORT_PER_THREAD;
+    const int64_t nblk = (n + chunk - 1) / chunk;
+    kt_begin(CNPC_KT_SORT, s);
+    hipLaunchKernelGGL(k_tile_count, dim3((unsigned)nblk), dim3(SORT_BLOCK), lds_count, s, pos, n, g, L.ntiles,
+                       count);
+    kt_end(CNPC_KT_SORT, s);
+    CNPC_HIP(hipGetLastError());
+  }
   const int per_bucket = 1 << (3 * g.ls);
   hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, count, L.ntiles, per_bucket, start, cursor, bcur);
   CNPC_HIP(hipGetLastError());
@@ -791,7 +836,7 @@ template <typename T>
 static cnpc_status paint_t(const cnpc_mesh_desc* d, const uint32_t* gpos, const float* gw,
                            int64_t ngal, const uint32_t* rpos, const float* rw, int64_t nran,
                            const double* norms, T* delta, T* noise, unsigned char* ws,
-                           const PaintLayout& L, hipStream_t s) {
+                           const PaintLayout& L, bool counted, hipStream_t s) {
   const bool weighted = (gw != nullptr) || (rw != nullptr);
   const uint32_t* cpos[2] = {gpos, rpos};
   const float* cw[2] = {gw, rw};
@@ -805,9 +850,9 @@ static cnpc_status paint_t(const cnpc_mesh_desc* d, const uint32_t* gpos, const 
     for (int pw = 0; pw < (weighted ? 2 : 1); ++pw)
       fa.blocks[c + 2 * pw] = reinterpret_cast<T*>(ws + L.off_blocks[c + 2 * pw]);
     if (cw[c])
-      CNPC_TRY((sort_and_paint<T, 4>(d, cpos[c], cw[c], cn[c], c, weighted, ws, L, s)));
+      CNPC_TRY((sort_and_paint<T, 4>(d, cpos[c], cw[c], cn[c], c, weighted, counted, ws, L, s)));
     else
-      CNPC_TRY((sort_and_paint<T, 3>(d, cpos[c], nullptr, cn[c], c, weighted, ws, L, s)));
+      CNPC_TRY((sort_and_paint<T, 3>(d, cpos[c], nullptr, cn[c], c, weighted, counted, ws, L, s)));
   }
   const int z2 = L.nt >= 2 ? 2 : 1;
   const int64_t nb = (int64_t)L.nphase * L.nt * L.nt * (L.nt / z2);
@@ -831,9 +876,43 @@ cnpc_status launch_paint(const cnpc_mesh_desc* d, const uint32_t* gpos, const fl
   unsigned char* w = reinterpret_cast<unsigned char*>(ws);
   if (d->dtype == CNPC_F64)
     return paint_t<double>(d, gpos, gw, ngal, rpos, rw, nran, norms, (double*)delta, (double*)noise, w,
-                           L, s);
+                           L, false, s);
   return paint_t<float>(d, gpos, gw, ngal, rpos, rw, nran, norms, (float*)delta, (float*)noise, w, L,
-                        s);
+                        false, s);
+}
+
+cnpc_status launch_paint_fkp(const cnpc_mesh_desc* d, const uint32_t* gpos, const float* gw,
+                             int64_t ngal, const uint32_t* rpos, const float* rw, int64_t nran,
+                             double* gsums, double* rsums, double* norms, void* delta, void* noise,
+                             void* ws, size_t ws_bytes, hipStream_t s) {
+  const bool weighted = (gw != nullptr) || (rw != nullptr);
+  PaintLayout L = paint_layout(d, ngal, nran, weighted);
+  if (ws_bytes < L.total) {
+    set_error("paint workspace too small: need %zu bytes, got %zu", L.total, ws_bytes);
+    return CNPC_EWORKSPACE;
+  }
+  unsigned char* w = reinterpret_cast<unsigned char*>(ws);
+  uint32_t* count0 = reinterpret_cast<uint32_t*>(w + L.off_count[0]);
+  uint32_t* count1 = reinterpret_cast<uint32_t*>(w + L.off_count[1]);
+  double* partial = reinterpret_cast<double*>(w + L.off_partial);
+  double* gs = gsums ? gsums : reinterpret_cast<double*>(w + L.off_sums);
+  double* rs = rsums ? rsums : reinterpret_cast<double*>(w + L.off_sums) + CNPC_SUMS_LEN;
+  hipLaunchKernelGGL(k_zero_u32, dim3(64), dim3(256), 0, s, count0, (int64_t)L.ntiles);
+  hipLaunchKernelGGL(k_zero_u32, dim3(64), dim3(256), 0, s, count1, (int64_t)L.ntiles);
+  CNPC_HIP(hipGetLastError());
+  CountArgs ca;
+  ca.g = tile_geom(d);
+  ca.ntiles = L.ntiles;
+  ca.count = count0;
+  CNPC_TRY(sums_counted(d, gpos, gw, ngal, gs, partial, ca, s));
+  ca.count = count1;
+  CNPC_TRY(sums_counted(d, rpos, rw, nran, rs, partial, ca, s));
+  CNPC_TRY(launch_norms(d, gs, rs, ngal, norms, s));
+  if (d->dtype == CNPC_F64)
+    return paint_t<double>(d, gpos, gw, ngal, rpos, rw, nran, norms, (double*)delta, (double*)noise, w,
+                           L, true, s);
+  return paint_t<float>(d, gpos, gw, ngal, rpos, rw, nran, norms, (float*)delta, (float*)noise, w, L,
+                        true, s);
 }
 
 }  // namespace cnpc

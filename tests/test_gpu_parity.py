@@ -174,6 +174,27 @@ def test_paint_bucketed_sort(case):
         assert rel(hnm[ph], onm[ph]) < 20 * TOL[dtype]
 
 
+@pytest.mark.parametrize("n,weights,dtype", [(32, False, L.F32), (32, True, L.F64), (128, False, L.F32)])
+def test_paint_fkp_matches_separate_calls(n, weights, dtype):
+    """The fused entry point (sums + tile counts in one pass) gives bit-identical
+    sums, normalisations and meshes to cnpc_catalog_sums + cnpc_norms + cnpc_paint."""
+    if n == 32:
+        g, gw, r, rw = _tiny(12, 4000, 30000, weights)
+    else:
+        g = synthcat.lognormal_catalog(100_000, 1000.0, 13)
+        r = synthcat.random_catalog(500_000, 14)
+        gw = rw = None
+    d = cn.mesh_desc(n, 1000.0, assign=L.TSC, interlace=True, dtype=dtype, observer=OBS)
+    gt, rt = dev(g), dev(r)
+    gwt = dev(gw) if gw is not None else None
+    rwt = dev(rw) if rw is not None else None
+    norms, gs, rs = pl.catalog_norms(d, gt, rt, gwt, rwt)
+    delta, nmesh = pl.paint(d, gt, rt, norms, gwt, rwt, noise=True)
+    norms2, delta2, nmesh2, gs2, rs2 = pl.paint_fkp(d, gt, rt, gwt, rwt, noise=True)
+    for a, b in ((norms, norms2), (gs, gs2), (rs, rs2), (delta, delta2), (nmesh, nmesh2)):
+        assert np.array_equal(host(a), host(b))
+
+
 def test_paint_single_particle_cells_bit_exact():
     n, box = 32, 100.0
     rng = np.random.default_rng(9)
