@@ -65,11 +65,33 @@ def make_mocks(nmocks: int, workers: int = 16):
         return list(ex.map(one, range(nmocks))), sizes
 
 
-def algorithmic_bytes(ng, nr, es, n=256):
-    """Per-mock bytes of the staged pipeline: 12 (N_g + N_r) + 50 R + 34 C."""
-    R = n ** 3 * es
-    Cb = n * n * (n // 2 + 1) * 2 * es
-    return 12 * (ng + nr) + 50 * R + 34 * Cb
+def class_model(ng, nr, n=256, es=4, band=32, grid=128, nb=20, nfields=14, nphase=2):
+    """Algorithmic HBM bytes (or MFMA flops) of one mock per kernel class of the
+    path: every array read or written once by the kernels of that class."""
+    ntiles, bvol = (n // 16) ** 3, 19 ** 3
+    npart = ng + nr
+    blocks = ntiles * nphase * bvol * es            # one catalog's tile blocks
+    mesh = n ** 3 * es                               # one real mesh
+    half = n * n * (n // 2) * 2 * es                 # one half-layout spectrum
+    zb = n * n * band * 2 * es                       # one z-pruned band plane stack
+    yb = n * 2 * band * band * 2 * es                # after the y pass
+    xb = 4 * band ** 3 * 2 * es                      # band spectrum
+    g3 = grid ** 3 * es
+    gz = grid * grid * band * 2 * es
+    gy = grid * 2 * band * band * 2 * es
+    npairs = nb * (nb + 1) // 2
+    return {
+        "sums": 12 * npart,
+        "sort": 2 * 24 * npart,
+        "paint": 12 * npart + 2 * blocks,
+        "fold": 2 * blocks + 2 * nphase * mesh,
+        "zr2c": nphase * (mesh + half) + nphase * (mesh + zb) + (mesh + nfields * zb),
+        "col": (nphase * 4 * half + nphase * (zb + 2 * yb + xb) + nfields * (zb + 2 * yb + xb)
+                + 4 * half + nb * (xb + 2 * gy + gz)),
+        "zc2r": (half + mesh) + nb * (gz + g3),
+        "bin": (nfields + 4) * xb,
+        "contract": 3 * 2.0 * npairs * nb * grid ** 3,   # MFMA flops (split bf16: 3 products)
+    }
 
 
 def main():
@@ -141,9 +163,29 @@ def main():
     L.check(L.lib.cnpc_ktimer_stop(ms_cls, n_cls))
     kern = {k: {"ms": ms_cls[v], "launches": n_cls[v]} for k, v in L.KT.items()}
     dom = max(kern, key=lambda k: kern[k]["ms"])
-    ntot = int(np.sum(sizes) * 11)
-    es = 4
-    roof = roofline(dom, kern[dom], args.mocks, sizes, es, plan)
+    ntot = int(np.sum(sizes[: args.mocks]) * 11)
+    models = [class_model(int(sz), 10 * int(sz), band=plan.band, grid=plan.grid)
+              for sz in sizes[: args.mocks]]
+    model = {k: float(np.sum([m[k] for m in models])) for k in models[0]}  # per step
+    classes = {}
+    for name, kv in kern.items():
+        if kv["launches"] == 0 or kv["ms"] <= 0:
+            continue
+        per_launch = model[name] / kv["launches"]
+        avg_ms = kv["ms"] / kv["launches"]
+        if name == "contract":
+            ach = per_launch / (avg_ms * 1e-3) / 1e12
+            classes[name] = {"bound": "mfma", "achieved": ach, "peak": PEAKS_TFLOPS["bf16"],
+                             "unit": "TFLOP/s", "frac": ach / PEAKS_TFLOPS["bf16"],
+                             "avg_launch_ms": avg_ms, "per_launch": per_launch}
+        else:
+            ach = per_launch / (avg_ms * 1e-3) / 1e9
+            classes[name] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": ach / HBM_PEAK_GBS, "avg_launch_ms": avg_ms,
+                             "per_launch": per_launch}
+    roof = dict(classes[dom])
+    roof["kernel"] = KERNEL_OF_CLASS.get(dom, dom)
+    roof["traffic"] = measured_traffic(roof["kernel"])
 
     # plain FP64 GPU path: one mock at a time
     fp64 = None
@@ -167,7 +209,7 @@ def main():
         del sc64
     cpu = None if args.no_cpu else cpu_baseline(mocks, sizes, log=lambda *m: log(args, *m))
 
-    mean_bytes = np.mean([algorithmic_bytes(int(s), 10 * int(s), es) for s in sizes[: args.mocks]])
+    hbm_bytes = sum(v for k, v in model.items() if k != "contract")
     line = {
         "metric": "P_l/B_l catalogs/s at 256^3 (batched FP32)",
         "value": value,
@@ -186,47 +228,49 @@ def main():
                                "256^3 TSC + interlacing, L=1000, P_0,2,4 + Scoccimarro B_0 (20 bins, "
                                "dk=0.01) with analytic shot noise",
                    "global_batch": args.mocks, "nmesh": 256, "particles_total": ntot},
-        "pipeline_hbm_frac": (mean_bytes * args.mocks / (ms_step / 1e3)) / (HBM_PEAK_GBS * 1e9),
+        "pipeline_hbm_frac": (hbm_bytes / (ms_step / 1e3)) / (HBM_PEAK_GBS * 1e9),
         "kernels_ms_per_step": {k: round(v["ms"], 3) for k, v in kern.items()},
         "roofline": roof,
+        "roofline_by_class": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv)
+                                  for kk, vv in v.items()} for k, v in classes.items()},
         "fp64_plain": fp64,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))
 
 
-def roofline(name, k, nmocks, sizes, es, plan):
-    """Algorithmic traffic / flops of one launch of the dominant kernel class."""
-    n3 = 256 ** 3
-    avg_ms = k["ms"] / max(k["launches"], 1)
-    launches_per_mock = k["launches"] / nmocks
-    mean_np = float(np.mean(sizes[:nmocks])) * 11
-    if name == "contract":
-        nb = 20
-        npairs = nb * (nb + 1) // 2
-        ncols = nb
-        flops = 2.0 * npairs * ncols * n3 / launches_per_mock
-        achieved = flops / (avg_ms * 1e-3) / 1e12
-        return {"kernel": "k_contract", "bound": "alu", "achieved": achieved,
-                "peak": PEAKS_TFLOPS["fp32"], "unit": "TFLOP/s", "frac": achieved / PEAKS_TFLOPS["fp32"],
-                "traffic": None, "avg_launch_ms": avg_ms, "per_launch": f"{flops:.3e} flop"}
-    per_launch_bytes = {
-        "paint": (mean_np * 12) / launches_per_mock,
-        "sort": (mean_np * 12 * 1.5) / launches_per_mock,
-        "fold": (4 * n3 * es + 2 * 4096 * 6859 * es * 2) / launches_per_mock,
-        "zr2c": None, "col": None, "zc2r": None, "bin": None, "sums": mean_np * 12 / launches_per_mock,
-    }
-    b = per_launch_bytes.get(name)
-    if b is None:
-        return {"kernel": name, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": None, "traffic": None, "avg_launch_ms": avg_ms}
-    achieved = b / (avg_ms * 1e-3) / 1e9
-    return {"kernel": name, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "avg_launch_ms": avg_ms}
+# kernel behind each timer class (the dominant one is named in the roofline)
+KERNEL_OF_CLASS = {"paint": "k_paint_tiles_u32", "sort": "k_partition", "fold": "k_fold_tiles",
+                   "zr2c": "k_zpass_ylm_rr", "col": "k_colpass_rr", "zc2r": "k_zpass_c2r",
+                   "contract": "k_contract_mfma", "bin": "k_bin", "sums": "k_catalog_sums"}
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of
+    `kernel` (FETCH_SIZE + WRITE_SIZE, copy-kernel calibrated), or None when
+    there is none or the kernel source changed since it was taken."""
+    import hashlib
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                        f"{kernel}_traffic_256c_64mocks.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if "=" in line and not line.startswith("#"):
+                k, v = line.split("=", 1)
+                vals[k.strip()] = v.strip()
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), vals.get("source", ""))
+    if not os.path.exists(src):
+        return None
+    with open(src, "rb") as fh:
+        if hashlib.sha256(fh.read()).hexdigest() != vals.get("source_sha256"):
+            return None
+    return float(vals["bytes_per_launch"])
 
 
 def cpu_baseline(mocks, sizes, log=print):
-    """FP64 oracle on a bounded sample of the smallest mock, extrapolated to one mock.
+    """FP64 oracle on a bounded sample of the smallest mock, extrapolated to the mean mock.
 
     Each oracle step is timed on a slice and scaled by the number of times the
     whole computation repeats it; the sum estimates seconds per catalog."""
@@ -276,6 +320,10 @@ def cpu_baseline(mocks, sizes, log=print):
     t = time.perf_counter()
     bins.shell_mean(np.real(D * np.conj(D)))
     parts["binning"] = (time.perf_counter() - t) * 6
+    # particle-proportional steps scaled from the sampled mock to the mean mock
+    scale = float(np.mean(sizes)) / float(sizes[k])
+    parts["catalog_sums"] *= scale
+    parts["paint"] *= scale
     total = sum(parts.values())
     threads = int(os.environ.get("OMP_NUM_THREADS", "1"))
     log(f"cpu oracle estimate {total:.1f}s per catalog: " +
@@ -284,7 +332,8 @@ def cpu_baseline(mocks, sizes, log=print):
             "sample": f"smallest mock (N_g={ng}, N_r={nr}), 256^3: each oracle step timed on a "
                       f"slice (1/50 of the catalog sums, 1/20 of one painting, one 256^3 FFT, one "
                       f"Y_lm-weighted FFT, one shell inverse FFT, 8 triple sums) and scaled by its "
-                      f"repeat count; numpy FFT single-threaded",
+                      f"repeat count; sums and painting then scaled to the mean mock "
+                      f"(N_g={float(np.mean(sizes)):.3g}); numpy FFT single-threaded",
             "seconds_per_catalog": total, "parts_s": {k: round(v, 2) for k, v in parts.items()},
             "omp_threads_env": threads}
 
