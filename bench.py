@@ -40,6 +40,7 @@ def parse():
     ap.add_argument("--mocks", type=int, default=64)
     ap.add_argument("--precision", choices=["f32", "bf16x3"], default="bf16x3")
     ap.add_argument("--no-graph", action="store_true", help="launch eagerly instead of one hipGraph")
+    ap.add_argument("--streams", type=int, default=2, help="concurrent streams inside a step")
     ap.add_argument("--fp64-mocks", type=int, default=2, help="mocks timed on the plain FP64 path")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--quiet", action="store_true")
@@ -123,13 +124,19 @@ def main():
     plan = pl.bispec_plan(desc, bins, L.EST_SCOCCIMARRO, 0, prec, sc)
     outs = [{"pk": torch.empty((9, 20), dtype=torch.float64, device=dev),
              "bk": torch.empty((3, plan.nconf), dtype=torch.float64, device=dev)} for _ in gpu_mocks]
+    batch = pl.Batch(args.streams)
 
     def step():
-        for (g, r), o in zip(gpu_mocks, outs):
-            pl.measure_pk_bk(desc, g, r, bins, plan, scratch=sc, out=o)
+        batch.run(desc, gpu_mocks, bins, plan, outs)
 
     step()  # eager pass: plans, twiddles and scratch reach their final size
     torch.cuda.synchronize()
+
+    ntot = int(np.sum(sizes[: args.mocks]) * 11)
+    models = [class_model(int(sz), 10 * int(sz), band=plan.band, grid=plan.grid)
+              for sz in sizes[: args.mocks]]
+    model = {k: float(np.sum([m[k] for m in models])) for k in models[0]}  # per step
+
     run = step
     if not args.no_graph:
         graph = torch.cuda.CUDAGraph()
@@ -154,38 +161,26 @@ def main():
     value = args.mocks / (ms_step / 1e3)
     log(args, f"timed {args.steps} steps: {ms_step:.1f} ms/step (wall {wall:.2f}s)")
 
-    # per-kernel timings of one instrumented step (HIP events on the launch stream)
+    # kernel times: the same step (same streams and schedule) launched eagerly
+    # with every launch of the timed classes bracketed by HIP events on its
+    # launch stream; the step time of this pass is reported beside the graph's
     mask = sum(1 << v for v in L.KT.values())
     L.check(L.lib.cnpc_ktimer_start(mask, 1 << 16))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
     step()
-    ms_cls = (C.c_double * 16)()
-    n_cls = (C.c_int64 * 16)()
-    L.check(L.lib.cnpc_ktimer_stop(ms_cls, n_cls))
-    kern = {k: {"ms": ms_cls[v], "launches": n_cls[v]} for k, v in L.KT.items()}
+    e1.record()
+    kern = ktimer_read(L)
+    ms_instr = e0.elapsed_time(e1)
     dom = max(kern, key=lambda k: kern[k]["ms"])
-    ntot = int(np.sum(sizes[: args.mocks]) * 11)
-    models = [class_model(int(sz), 10 * int(sz), band=plan.band, grid=plan.grid)
-              for sz in sizes[: args.mocks]]
-    model = {k: float(np.sum([m[k] for m in models])) for k in models[0]}  # per step
-    classes = {}
-    for name, kv in kern.items():
-        if kv["launches"] == 0 or kv["ms"] <= 0:
-            continue
-        per_launch = model[name] / kv["launches"]
-        avg_ms = kv["ms"] / kv["launches"]
-        if name == "contract":
-            ach = per_launch / (avg_ms * 1e-3) / 1e12
-            classes[name] = {"bound": "mfma", "achieved": ach, "peak": PEAKS_TFLOPS["bf16"],
-                             "unit": "TFLOP/s", "frac": ach / PEAKS_TFLOPS["bf16"],
-                             "avg_launch_ms": avg_ms, "per_launch": per_launch}
-        else:
-            ach = per_launch / (avg_ms * 1e-3) / 1e9
-            classes[name] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                             "frac": ach / HBM_PEAK_GBS, "avg_launch_ms": avg_ms,
-                             "per_launch": per_launch}
+    classes = {name: class_roofline(name, kv, model) for name, kv in kern.items()
+               if kv["launches"] > 0 and kv["ms"] > 0}
     roof = dict(classes[dom])
     roof["kernel"] = KERNEL_OF_CLASS.get(dom, dom)
     roof["traffic"] = measured_traffic(roof["kernel"])
+    roof["durations_from"] = (f"HIP events around each launch of an eager pass of the timed step "
+                              f"({args.streams} streams, {ms_instr:.1f} ms)")
+    kern_ms = {k: round(v["ms"], 3) for k, v in kern.items()}
 
     # plain FP64 GPU path: one mock at a time
     fp64 = None
@@ -223,13 +218,14 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if prec == L.PREC_F32 else "f32+bf16x3",
         "graph": not args.no_graph,
+        "streams": args.streams,
         "data": "synthetic lognormal mocks (seeded), resident in HBM",
         "config": {"workload": "64 uneven lognormal mocks (N_g 1e6-8e6 log-uniform, 10x randoms), "
                                "256^3 TSC + interlacing, L=1000, P_0,2,4 + Scoccimarro B_0 (20 bins, "
                                "dk=0.01) with analytic shot noise",
                    "global_batch": args.mocks, "nmesh": 256, "particles_total": ntot},
         "pipeline_hbm_frac": (hbm_bytes / (ms_step / 1e3)) / (HBM_PEAK_GBS * 1e9),
-        "kernels_ms_per_step": {k: round(v["ms"], 3) for k, v in kern.items()},
+        "kernels_ms_per_step": kern_ms,
         "roofline": roof,
         "roofline_by_class": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv)
                                   for kk, vv in v.items()} for k, v in classes.items()},
@@ -237,6 +233,28 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))
+
+
+def ktimer_read(L):
+    """Stop the library's kernel timer: {class: {"ms": total, "launches": n}}."""
+    ms_cls = (C.c_double * 16)()
+    n_cls = (C.c_int64 * 16)()
+    L.check(L.lib.cnpc_ktimer_stop(ms_cls, n_cls))
+    return {k: {"ms": ms_cls[v], "launches": n_cls[v]} for k, v in L.KT.items()}
+
+
+def class_roofline(name, kv, model):
+    """Achieved rate of one kernel class: algorithmic bytes (or MFMA flops) per
+    launch from the per-step model over the average launch duration."""
+    per_launch = model[name] / kv["launches"]
+    avg_ms = kv["ms"] / kv["launches"]
+    if name == "contract":
+        ach = per_launch / (avg_ms * 1e-3) / 1e12
+        return {"bound": "mfma", "achieved": ach, "peak": PEAKS_TFLOPS["bf16"], "unit": "TFLOP/s",
+                "frac": ach / PEAKS_TFLOPS["bf16"], "avg_launch_ms": avg_ms, "per_launch": per_launch}
+    ach = per_launch / (avg_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS, "avg_launch_ms": avg_ms, "per_launch": per_launch}
 
 
 # kernel behind each timer class (the dominant one is named in the roofline)

@@ -293,7 +293,7 @@ cnpc_status cnpc_bispectrum(const cnpc_bispec_plan* plan, const void* F0, const 
  * 16), the summed kernel time in ms and the number of timed launches.  Not for
  * use under stream capture.  Host-side state: one timer per process. */
 #define CNPC_KT_PAINT 1    /* tile accumulation */
-#define CNPC_KT_SORT 2     /* tile counting + scatter */
+#define CNPC_KT_SORT 2     /* tile counting (standalone paint) + bucket / tile scatter */
 #define CNPC_KT_FOLD 3     /* block fold into meshes */
 #define CNPC_KT_ZR2C 4     /* z-row r2c passes (plain and Y_lm prologue) */
 #define CNPC_KT_COL 5      /* x / y column passes */

@@ -314,3 +314,26 @@ def measure_pk_bk(desc, gpos, rpos, bins, plan: "BispecPlan", ells=(0, 2, 4), gw
                                   _sh(stream)))
     res["nmodes"] = nmodes
     return res
+
+
+class Batch:
+    """Many catalog pairs through measure_pk_bk, spread round-robin over
+    `nstreams` streams (each with its own scratch), so that the small and the
+    tail-end kernels of one catalog overlap the work of another.  The caller's
+    current stream is forked at the start and joined at the end, so a batch can
+    be captured into one graph."""
+
+    def __init__(self, nstreams: int = 2, device="cuda"):
+        self.streams = [torch.cuda.Stream(device=device) for _ in range(max(1, nstreams))]
+        self.scratch = [Scratch(device) for _ in self.streams]
+
+    def run(self, desc, catalogs, bins, plan, outs, ells=(0, 2, 4)):
+        cur = torch.cuda.current_stream()
+        for s in self.streams:
+            s.wait_stream(cur)
+        for i, ((g, r), o) in enumerate(zip(catalogs, outs)):
+            k = i % len(self.streams)
+            with torch.cuda.stream(self.streams[k]):
+                measure_pk_bk(desc, g, r, bins, plan, ells=ells, scratch=self.scratch[k], out=o)
+        for s in self.streams:
+            cur.wait_stream(s)

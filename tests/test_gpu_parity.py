@@ -364,24 +364,32 @@ def test_measure_bk_reduced_grid_vs_oracle(est, ell, prec):
     assert rel(host(res["value"]), ora[key]) < tol
 
 
-def test_graph_replay_matches_eager():
-    """The batch captured as one graph gives the eager results on every replay."""
+@pytest.mark.parametrize("nstreams", [1, 3])
+def test_graph_replay_matches_eager(nstreams):
+    """The batch captured as one graph (catalogs spread over nstreams streams)
+    gives the eager single-stream results on every replay."""
     n, box = 32, 1000.0
     bins = cn.kbins(0.0, 0.012, 4)
     d = cn.mesh_desc(n, box, assign=L.TSC, interlace=True, dtype=L.F32, observer=OBS)
-    cats = [_cat(21 + 2 * k, 10_000 * (k + 1), 60_000 * (k + 1)) for k in range(2)]
+    cats = [_cat(21 + 2 * k, 10_000 * (k + 1), 60_000 * (k + 1)) for k in range(4)]
     cats = [(dev(g), dev(r)) for g, r in cats]
     sc = pl.Scratch()
     plan = pl.bispec_plan(d, bins, L.EST_SCOCCIMARRO, 0, L.PREC_F32, sc)
     outs = [{"pk": torch.empty((9, 4), dtype=torch.float64, device="cuda"),
              "bk": torch.empty((3, plan.nconf), dtype=torch.float64, device="cuda")} for _ in cats]
+    for (g, r), o in zip(cats, outs):
+        pl.measure_pk_bk(d, g, r, bins, plan, scratch=sc, out=o)
+    batch = pl.Batch(nstreams)
 
     def step():
-        for (g, r), o in zip(cats, outs):
-            pl.measure_pk_bk(d, g, r, bins, plan, scratch=sc, out=o)
+        batch.run(d, cats, bins, plan, outs)
 
-    step()
     eager = [(host(o["pk"]).copy(), host(o["bk"]).copy()) for o in outs]
+    step()  # eager multi-stream pass: scratch buffers reach their size
+    torch.cuda.synchronize()
+    for (pk, bk), o in zip(eager, outs):
+        assert rel(host(o["pk"]), pk) < 1e-5
+        assert rel(host(o["bk"]), bk) < 1e-5
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
         step()
