@@ -83,25 +83,46 @@ __global__ void __launch_bounds__(SUMS_THREADS) k_catalog_sums(const uint32_t* _
     acc[0] += wi;
     acc[1] += w2;
     acc[2] += w3;
-    double ux, uy, uz;
-    if (a.global_los) {
-      ux = a.los[0]; uy = a.los[1]; uz = a.los[2];
-    } else {
-      const double rx = (double)pos[i] * scale - a.obs[0];
-      const double ry = (double)pos[n + i] * scale - a.obs[1];
-      const double rz = (double)pos[2 * n + i] * scale - a.obs[2];
-      const double inv = 1.0 / sqrt(rx * rx + ry * ry + rz * rz);
-      ux = rx * inv; uy = ry * inv; uz = rz * inv;
-    }
-    double re[5], im[5];
     int q = 3;
     // (l, m) order: (0,0), (2,0..2), (4,0..4); accumulate w^3 conj(y_l^m)
     acc[q++] += w3;  // y_0^0 = 1
     acc[q++] += 0.0;
-    racah_ylm<double>(2, ux, uy, uz, re, im);
-    for (int m = 0; m <= 2; ++m) { acc[q++] += w3 * re[m]; acc[q++] -= w3 * im[m]; }
-    racah_ylm<double>(4, ux, uy, uz, re, im);
-    for (int m = 0; m <= 4; ++m) { acc[q++] += w3 * re[m]; acc[q++] -= w3 * im[m]; }
+    if (a.global_los) {
+      double re[5], im[5];
+      racah_ylm<double>(2, a.los[0], a.los[1], a.los[2], re, im);
+      for (int m = 0; m <= 2; ++m) { acc[q++] += w3 * re[m]; acc[q++] -= w3 * im[m]; }
+      racah_ylm<double>(4, a.los[0], a.los[1], a.los[2], re, im);
+      for (int m = 0; m <= 4; ++m) { acc[q++] += w3 * re[m]; acc[q++] -= w3 * im[m]; }
+    } else {
+      // solid harmonics: y_l^m(r / R) = Q_lm(r_z, R^2) (r_x + i r_y)^m / R^l,
+      // the Q_lm of solid_coef written out for l = 2, 4
+      const double rx = (double)pos[i] * scale - a.obs[0];
+      const double ry = (double)pos[n + i] * scale - a.obs[1];
+      const double rz = (double)pos[2 * n + i] * scale - a.obs[2];
+      const double z2 = rz * rz;
+      const double r2 = rx * rx + ry * ry + z2;
+      const double i2 = 1.0 / r2;
+      const double c2 = w3 * i2, c4 = c2 * i2;
+      const double s2r = rx * rx - ry * ry, s2i = 2.0 * rx * ry;
+      const double s3r = s2r * rx - s2i * ry, s3i = s2r * ry + s2i * rx;
+      const double s4r = s2r * s2r - s2i * s2i, s4i = 2.0 * s2r * s2i;
+      const double q20 = c2 * (1.5 * z2 - 0.5 * r2);
+      const double q21 = c2 * -1.22474487139158904910 * rz;
+      const double q22 = c2 * 0.61237243569579452455;
+      acc[5] += q20;
+      acc[7] += q21 * rx; acc[8] -= q21 * ry;
+      acc[9] += q22 * s2r; acc[10] -= q22 * s2i;
+      const double q40 = c4 * ((4.375 * z2 - 3.75 * r2) * z2 + 0.375 * r2 * r2);
+      const double q41 = c4 * rz * (-3.91311896062463196870 * z2 + 1.67705098312484227230 * r2);
+      const double q42 = c4 * (2.76699295264733191550 * z2 - 0.39528470752104741650 * r2);
+      const double q43 = c4 * -1.47901994577490951707 * rz;
+      const double q44 = c4 * 0.52291251658379721749;
+      acc[11] += q40;
+      acc[13] += q41 * rx; acc[14] -= q41 * ry;
+      acc[15] += q42 * s2r; acc[16] -= q42 * s2i;
+      acc[17] += q43 * s3r; acc[18] -= q43 * s3i;
+      acc[19] += q44 * s4r; acc[20] -= q44 * s4i;
+    }
   }
   __shared__ double red[SUMS_THREADS / 64][CNPC_SUMS_LEN];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;

@@ -155,44 +155,6 @@ __device__ __forceinline__ T ylm_one(int l, int m, int part, T x, T y, T z) {
   return c * (part ? si : sr);
 }
 
-// Solid-harmonic form of y_l^m: with r the observer-relative node position,
-// R = |r| and s = r_x + i r_y,  y_l^m(r / R) = Q_lm(r_z, R^2) s^m / R^l, where
-// Q_lm = c_lm(u_z) R^(l-m) (c_lm: the z factor of ylm_one) written as
-// z^odd (A z^4 + B z^2 R^2 + C R^4 + D z^2 + E R^2 + F) with z = r_z.
-struct SolidQ {
-  double A, B, C, D, E, F;
-  int odd;
-};
-
-__device__ __forceinline__ SolidQ solid_coef(int l, int m) {
-  SolidQ q = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0};
-  switch (l * 8 + m) {
-    case 0: q.F = 1.f; break;
-    case 8: q.odd = 1; q.F = 1.f; break;
-    case 9: q.F = -0.70710678118654752440; break;
-    case 16: q.D = 1.5; q.E = -0.5; break;
-    case 17: q.odd = 1; q.F = -1.22474487139158904910; break;
-    case 18: q.F = 0.61237243569579452455; break;
-    case 24: q.odd = 1; q.D = 2.5; q.E = -1.5; break;
-    case 25: q.D = -2.16506350946109661690; q.E = 0.43301270189221932338; break;
-    case 26: q.odd = 1; q.F = 1.36930639376291528364; break;
-    case 27: q.F = -0.55901699437494742410; break;
-    case 32: q.A = 4.375; q.B = -3.75; q.C = 0.375; break;
-    case 33: q.odd = 1; q.D = -3.91311896062463196870; q.E = 1.67705098312484227230; break;
-    case 34: q.D = 2.76699295264733191550; q.E = -0.39528470752104741650; break;
-    case 35: q.odd = 1; q.F = -1.47901994577490951707; break;
-    default: q.F = 0.52291251658379721749; break;  // l = 4, m = 4
-  }
-  return q;
-}
-
-template <typename T>
-__device__ __forceinline__ T solid_eval(const SolidQ& q, T z, T r2) {
-  const T z2 = z * z;
-  const T v = (T(q.A) * z2 + T(q.B) * r2 + T(q.D)) * z2 + (T(q.C) * r2 + T(q.E)) * r2 + T(q.F);
-  return q.odd ? v * z : v;
-}
-
 // R^k for R^2 = q and a small integer k; FP32 uses the hardware reciprocal and
 // reciprocal square root (about 1 ulp), FP64 exact division and sqrt.
 template <typename T>
@@ -209,18 +171,6 @@ __device__ __forceinline__ T pow_r(T q, int k) {
     if (k < 0) r = T(1) / r;
   }
   return r;
-}
-
-// Re (part 0) or Im (part 1) of (x + i y)^m
-template <typename T>
-__device__ __forceinline__ T cpow_part(T x, T y, int m, int part) {
-  T sr = T(1), si = T(0);
-  for (int k = 0; k < m; ++k) {
-    const T t = sr * x - si * y;
-    si = sr * y + si * x;
-    sr = t;
-  }
-  return part ? si : sr;
 }
 
 // Register z-pass for N = R^2: a group of R lanes owns one row pair (ix, 2j),
