@@ -66,6 +66,15 @@ def make_mocks(nmocks: int, workers: int = 16):
         return list(ex.map(one, range(nmocks))), sizes
 
 
+def pipeline_bytes(ng, nr, es=4, n=256):
+    """Minimal HBM bytes of one mock when every stage reads its inputs and
+    writes its outputs once: 12 (N_g + N_r) + 50 R + 34 C (R: real mesh, C:
+    half-complex spectrum)."""
+    R = n ** 3 * es
+    Cb = n * n * (n // 2 + 1) * 2 * es
+    return 12 * (ng + nr) + 50 * R + 34 * Cb
+
+
 def class_model(ng, nr, n=256, es=4, band=32, grid=128, nb=20, nfields=14, nphase=2):
     """Algorithmic HBM bytes (or MFMA flops) of one mock per kernel class of the
     path: every array read or written once by the kernels of that class."""
@@ -204,7 +213,7 @@ def main():
         del sc64
     cpu = None if args.no_cpu else cpu_baseline(mocks, sizes, log=lambda *m: log(args, *m))
 
-    hbm_bytes = sum(v for k, v in model.items() if k != "contract")
+    hbm_bytes = float(np.sum([pipeline_bytes(int(sz), 10 * int(sz)) for sz in sizes[: args.mocks]]))
     line = {
         "metric": "P_l/B_l catalogs/s at 256^3 (batched FP32)",
         "value": value,

@@ -180,7 +180,7 @@ __device__ __forceinline__ T pow_r(T q, int k) {
 // the lanes keep e = delta / R^l for the current l and multiply by
 // Q_lm(r_z, R^2) and the row constant Re / Im (r_x + i r_y)^m.
 template <typename T, int R>
-__global__ void __launch_bounds__(256) k_zpass_ylm_rr(const T* __restrict__ delta, cx<T>* __restrict__ out,
+__global__ void __launch_bounds__(256, 2) k_zpass_ylm_rr(const T* __restrict__ delta, cx<T>* __restrict__ out,
                                                       FieldTable ft, int kz_keep, int64_t fstride, Geo g) {
   constexpr int N = R * R;
   constexpr int GR = 256 / R;  // row pairs per workgroup
