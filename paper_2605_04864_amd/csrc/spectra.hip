@@ -155,32 +155,47 @@ __device__ __forceinline__ T ylm_one(int l, int m, int part, T x, T y, T z) {
   return c * (part ? si : sr);
 }
 
-// R^k for R^2 = q and a small integer k; FP32 uses the hardware reciprocal and
-// reciprocal square root (about 1 ulp), FP64 exact division and sqrt.
-template <typename T>
-__device__ __forceinline__ T pow_r(T q, int k) {
-  const int a = k < 0 ? -k : k;
-  T r = T(1);
-  if constexpr (sizeof(T) == 4) {
-    const T b = k < 0 ? __builtin_amdgcn_rcpf(q) : q;
-    if (a & 1) r = k < 0 ? __builtin_amdgcn_rsqf(q) : __builtin_sqrtf(q);
-    for (int i = 0; i < a / 2; ++i) r *= b;
-  } else {
-    if (a & 1) r = sqrt(q);
-    for (int i = 0; i < a / 2; ++i) r *= q;
-    if (k < 0) r = T(1) / r;
+// R^-L for R^2 = q (FP32: hardware reciprocal / reciprocal square root).
+template <typename T, int L>
+__device__ __forceinline__ T inv_pow_r(T q) {
+  if constexpr (L == 0) return T(1);
+  T i2;
+  if constexpr (sizeof(T) == 4) i2 = __builtin_amdgcn_rcpf(q);
+  else i2 = T(1) / q;
+  T r = (L & 2) ? i2 : T(1);
+  if constexpr (L >= 4) r *= i2 * i2;
+  if constexpr (L & 1) {
+    if constexpr (sizeof(T) == 4) r *= __builtin_amdgcn_rsqf(q);
+    else r /= sqrt(q);
   }
   return r;
 }
 
+// v[n2] = (e0 w(row 0), e1 w(row 1)) for the nodes z = rank + R n2 of a row
+// pair; w = Q_lm(r_z, R^2) R^-L s, r_z = rz0 + n2 dz, R^2 = rho + r_z^2.
+template <typename T, int R, int L>
+__device__ __forceinline__ void weigh_rows(cx<T>* v, const T* e0, const T* e1, T rz0, T dz, T rho0, T rho1,
+                                           const SolidQ& qc, T s0, T s1) {
+#pragma unroll
+  for (int n2 = 0; n2 < R; ++n2) {
+    // opaque copy: keeps r_z^2 and R^2 of all nodes from being hoisted out of
+    // the field loop into registers
+    T za = rz0 + T(n2) * dz;
+    asm volatile("" : "+v"(za));
+    const T q0 = rho0 + za * za, q1 = rho1 + za * za;
+    const T w0 = solid_eval<T>(qc, za, q0) * s0 * inv_pow_r<T, L>(q0);
+    const T w1 = solid_eval<T>(qc, za, q1) * s1 * inv_pow_r<T, L>(q1);
+    v[n2] = cx<T>{e0[n2] * w0, e1[n2] * w1};
+  }
+}
+
 // Register z-pass for N = R^2: a group of R lanes owns one row pair (ix, 2j),
-// (ix, 2j+1) of delta and, field after field (fields ordered by l), forms the
-// weighted pair as one complex row, transforms it with row_fft_rr and writes
-// kz < kz_keep of both real rows (two-for-one split).  Local line of sight:
-// the lanes keep e = delta / R^l for the current l and multiply by
-// Q_lm(r_z, R^2) and the row constant Re / Im (r_x + i r_y)^m.
+// (ix, 2j+1) of delta and, field after field, forms the weighted pair as one
+// complex row, transforms it with row_fft_rr and writes kz < kz_keep of both
+// real rows (two-for-one split).  Local line of sight: the weight of a node is
+// Q_lm(r_z, R^2) R^-l times the row constant Re / Im (r_x + i r_y)^m.
 template <typename T, int R>
-__global__ void __launch_bounds__(256, 2) k_zpass_ylm_rr(const T* __restrict__ delta, cx<T>* __restrict__ out,
+__global__ void __launch_bounds__(256, 3) k_zpass_ylm_rr(const T* __restrict__ delta, cx<T>* __restrict__ out,
                                                       FieldTable ft, int kz_keep, int64_t fstride, Geo g) {
   constexpr int N = R * R;
   constexpr int GR = 256 / R;  // row pairs per workgroup
@@ -192,14 +207,15 @@ __global__ void __launch_bounds__(256, 2) k_zpass_ylm_rr(const T* __restrict__ d
   const int q = blockIdx.x * GR + grp;
   const int ix = q / (N / 2), iy0 = 2 * (q - ix * (N / 2));
   const T* r0 = delta + ((int64_t)ix * N + iy0) * N;
-  T e0[R], e1[R], rz[R];
+  T e0[R], e1[R];  // delta of the two rows
 #pragma unroll
   for (int n2 = 0; n2 < R; ++n2) {
     const int z = rank + R * n2;
     e0[n2] = r0[z];
     e1[n2] = r0[N + z];
-    rz[n2] = T(z * g.h - g.obs[2]);
   }
+  // r_z of node z = rank + R n2 is rz0 + n2 dz (recomputed where needed)
+  const T rz0 = T(rank * g.h - g.obs[2]), dz = T(R * g.h);
   const T rx = T(ix * g.h - g.obs[0]);
   const T ry0 = T(iy0 * g.h - g.obs[1]), ry1 = T((iy0 + 1) * g.h - g.obs[1]);
   const T rho0 = rx * rx + ry0 * ry0, rho1 = rx * rx + ry1 * ry1;
@@ -207,22 +223,10 @@ __global__ void __launch_bounds__(256, 2) k_zpass_ylm_rr(const T* __restrict__ d
   const int src = (R - rank) & (R - 1);
   const int K2 = (kz_keep + R - 1) / R;
   cx<T>* orow = out + ((int64_t)ix * N + iy0) * kz_keep;
-  int lcur = 0;
   for (int f0 = 0; f0 < ft.nf;) {
-    // fields come in runs of equal l: rescale e = delta / R^l once per run
     const int l = ft.ell[f0];
     int f1 = f0 + 1;
     while (f1 < ft.nf && ft.ell[f1] == l) ++f1;
-    if (!g.global_los && l != lcur) {
-      const int dl = lcur - l;
-#pragma unroll
-      for (int n2 = 0; n2 < R; ++n2) {
-        const T za = rz[n2];
-        e0[n2] *= pow_r<T>(rho0 + za * za, dl);
-        e1[n2] *= pow_r<T>(rho1 + za * za, dl);
-      }
-      lcur = l;
-    }
     for (int f = f0; f < f1; ++f) {
       const int m = ft.m[f], p = ft.part[f];
       cx<T> v[R];
@@ -233,15 +237,12 @@ __global__ void __launch_bounds__(256, 2) k_zpass_ylm_rr(const T* __restrict__ d
       } else {
         const T s0 = cpow_part<T>(rx, ry0, m, p), s1 = cpow_part<T>(rx, ry1, m, p);
         const SolidQ qc = solid_coef(l, m);
-#pragma unroll
-        for (int n2 = 0; n2 < R; ++n2) {
-          // opaque copy: keeps r_z^2 and R^2 of all nodes from being hoisted
-          // out of the field loop into registers
-          T za = rz[n2];
-          asm volatile("" : "+v"(za));
-          const T w0 = solid_eval<T>(qc, za, rho0 + za * za) * s0;
-          const T w1 = solid_eval<T>(qc, za, rho1 + za * za) * s1;
-          v[n2] = cx<T>{e0[n2] * w0, e1[n2] * w1};
+        switch (l) {
+          case 0: weigh_rows<T, R, 0>(v, e0, e1, rz0, dz, rho0, rho1, qc, s0, s1); break;
+          case 1: weigh_rows<T, R, 1>(v, e0, e1, rz0, dz, rho0, rho1, qc, s0, s1); break;
+          case 2: weigh_rows<T, R, 2>(v, e0, e1, rz0, dz, rho0, rho1, qc, s0, s1); break;
+          case 3: weigh_rows<T, R, 3>(v, e0, e1, rz0, dz, rho0, rho1, qc, s0, s1); break;
+          default: weigh_rows<T, R, 4>(v, e0, e1, rz0, dz, rho0, rho1, qc, s0, s1); break;
         }
       }
       row_fft_rr<T, R, -1>(v, rank, buf, tw);
