@@ -143,13 +143,16 @@ cnpc_status cnpc_paint(const cnpc_mesh_desc* desc, const uint32_t* gpos, const f
                        void* stream);
 /* cnpc_catalog_sums of both catalogs, cnpc_norms and cnpc_paint in one call:
  * the tile histogram of the sort is taken during the catalog-sum pass, which
- * saves one read of every particle.  gal_sums, ran_sums: CNPC_SUMS_LEN device
+ * saves one read of every particle.  sums_lmax (0, 2 or 4): the Y_l^m sums
+ * (and Sbar_l^m) are formed for l <= sums_lmax only, the others are zero; the
+ * l = 0 sums are always formed.  gal_sums, ran_sums: CNPC_SUMS_LEN device
  * doubles each, or NULL when not wanted; norms: CNPC_NORMS_LEN device doubles
- * (output).  Same meshes and workspace size as cnpc_paint. */
+ * (output).  Same meshes and workspace size as cnpc_paint; sums_lmax = 4
+ * gives the sums of cnpc_catalog_sums bit for bit. */
 cnpc_status cnpc_paint_fkp(const cnpc_mesh_desc* desc, const uint32_t* gpos, const float* gw,
                            int64_t ngal, const uint32_t* rpos, const float* rw, int64_t nran,
-                           double* gal_sums, double* ran_sums, double* norms, void* delta,
-                           void* noise, void* ws, size_t ws_bytes, void* stream);
+                           int32_t sums_lmax, double* gal_sums, double* ran_sums, double* norms,
+                           void* delta, void* noise, void* ws, size_t ws_bytes, void* stream);
 
 /* ---- fft: batched 3-D real transforms (all hot-path transforms) ----
  * Full r2c: `batch` real meshes -> half-layout spectra.  Full c2r: half-layout

@@ -61,8 +61,8 @@ _PROTOS = {
     "cnpc_norms": (_i32, [_PD, _cvp, _cvp, _i64, _vp, _vp]),
     "cnpc_paint_workspace_size": (_sz, [_PD, _i64, _i64]),
     "cnpc_paint": (_i32, [_PD, _cvp, _cvp, _i64, _cvp, _cvp, _i64, _cvp, _vp, _vp, _vp, _sz, _vp]),
-    "cnpc_paint_fkp": (_i32, [_PD, _cvp, _cvp, _i64, _cvp, _cvp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _sz,
-                              _vp]),
+    "cnpc_paint_fkp": (_i32, [_PD, _cvp, _cvp, _i64, _cvp, _cvp, _i64, _i32, _vp, _vp, _vp, _vp, _vp, _vp,
+                              _sz, _vp]),
     "cnpc_fft_workspace_size": (_sz, [_PD, _i32, _i32]),
     "cnpc_fft_r2c": (_i32, [_PD, _i32, _i32, _cvp, _vp, _vp, _sz, _vp]),
     "cnpc_fft_c2r": (_i32, [_PD, _i32, _i32, _cvp, _vp, _vp, _sz, _vp]),

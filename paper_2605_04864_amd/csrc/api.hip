@@ -195,17 +195,18 @@ cnpc_status cnpc_paint(const cnpc_mesh_desc* d, const uint32_t* gpos, const floa
 }
 
 cnpc_status cnpc_paint_fkp(const cnpc_mesh_desc* d, const uint32_t* gpos, const float* gw, int64_t ngal,
-                           const uint32_t* rpos, const float* rw, int64_t nran, double* gal_sums,
-                           double* ran_sums, double* norms, void* delta, void* noise, void* ws,
-                           size_t ws_bytes, void* stream) {
+                           const uint32_t* rpos, const float* rw, int64_t nran, int32_t sums_lmax,
+                           double* gal_sums, double* ran_sums, double* norms, void* delta, void* noise,
+                           void* ws, size_t ws_bytes, void* stream) {
   API_BEGIN;
+  CNPC_REQUIRE(sums_lmax == 0 || sums_lmax == 2 || sums_lmax == 4, "sums_lmax must be 0, 2 or 4");
   CNPC_TRY(check_desc(d));
   CNPC_REQUIRE(ngal >= 1 && ngal < ((int64_t)1 << 32), "ngal must be in [1, 2^32)");
   CNPC_REQUIRE(nran >= 1 && nran < ((int64_t)1 << 32), "nran must be in [1, 2^32)");
   CNPC_REQUIRE(gpos && rpos && norms && delta && ws, "null pointer argument");
   CNPC_REQUIRE((gw == nullptr) == (rw == nullptr), "give weights for both catalogs or for neither");
-  return launch_paint_fkp(d, gpos, gw, ngal, rpos, rw, nran, gal_sums, ran_sums, norms, delta, noise, ws,
-                          ws_bytes, as_stream(stream));
+  return launch_paint_fkp(d, gpos, gw, ngal, rpos, rw, nran, sums_lmax, gal_sums, ran_sums, norms, delta,
+                          noise, ws, ws_bytes, as_stream(stream));
 }
 
 static cnpc_status check_band(const cnpc_mesh_desc* d, int band) {

@@ -6,6 +6,7 @@
 namespace cnpc {
 
 struct SumsArgs {
+  int lmax;  // Y_lm sums for l <= lmax (0, 2 or 4); the others stay zero
   double boxsize;
   double obs[3];
   double los[3];
@@ -39,8 +40,8 @@ cnpc_status launch_paint(const cnpc_mesh_desc* d, const uint32_t* gpos, const fl
                          hipStream_t s);
 cnpc_status launch_paint_fkp(const cnpc_mesh_desc* d, const uint32_t* gpos, const float* gw,
                              int64_t ngal, const uint32_t* rpos, const float* rw, int64_t nran,
-                             double* gsums, double* rsums, double* norms, void* delta, void* noise,
-                             void* ws, size_t ws_bytes, hipStream_t s);
+                             int sums_lmax, double* gsums, double* rsums, double* norms, void* delta,
+                             void* noise, void* ws, size_t ws_bytes, hipStream_t s);
 // per-workgroup LDS limit of the current device (bytes)
 size_t lds_limit();
 

@@ -87,10 +87,12 @@ __global__ void __launch_bounds__(SUMS_THREADS) k_catalog_sums(const uint32_t* _
     // (l, m) order: (0,0), (2,0..2), (4,0..4); accumulate w^3 conj(y_l^m)
     acc[q++] += w3;  // y_0^0 = 1
     acc[q++] += 0.0;
+    if (a.lmax < 2) continue;
     if (a.global_los) {
       double re[5], im[5];
       racah_ylm<double>(2, a.los[0], a.los[1], a.los[2], re, im);
       for (int m = 0; m <= 2; ++m) { acc[q++] += w3 * re[m]; acc[q++] -= w3 * im[m]; }
+      if (a.lmax < 4) continue;
       racah_ylm<double>(4, a.los[0], a.los[1], a.los[2], re, im);
       for (int m = 0; m <= 4; ++m) { acc[q++] += w3 * re[m]; acc[q++] -= w3 * im[m]; }
     } else {
@@ -112,6 +114,7 @@ __global__ void __launch_bounds__(SUMS_THREADS) k_catalog_sums(const uint32_t* _
       acc[5] += q20;
       acc[7] += q21 * rx; acc[8] -= q21 * ry;
       acc[9] += q22 * s2r; acc[10] -= q22 * s2i;
+      if (a.lmax < 4) continue;
       const double q40 = c4 * ((4.375 * z2 - 3.75 * r2) * z2 + 0.375 * r2 * r2);
       const double q41 = c4 * rz * (-3.91311896062463196870 * z2 + 1.67705098312484227230 * r2);
       const double q42 = c4 * (2.76699295264733191550 * z2 - 0.39528470752104741650 * r2);
@@ -663,9 +666,10 @@ __global__ void __launch_bounds__(512) k_fold_tiles(FoldArgs<T> fa, const double
 static TileGeom tile_geom(const cnpc_mesh_desc* d);
 
 static cnpc_status sums_counted(const cnpc_mesh_desc* d, const uint32_t* pos, const float* w, int64_t n,
-                                double* sums, double* partial, const CountArgs& ca, hipStream_t s) {
+                                int lmax, double* sums, double* partial, const CountArgs& ca, hipStream_t s) {
   const int nblocks = SUMS_BLOCKS;
   SumsArgs a;
+  a.lmax = lmax;
   a.boxsize = d->boxsize;
   for (int i = 0; i < 3; ++i) { a.obs[i] = d->observer[i]; a.los[i] = d->los[i]; }
   a.global_los = d->los_mode == CNPC_LOS_GLOBAL;
@@ -690,7 +694,7 @@ cnpc_status launch_catalog_sums(const cnpc_mesh_desc* d, const uint32_t* pos, co
   CountArgs ca;
   ca.ntiles = 0;
   ca.count = nullptr;
-  return sums_counted(d, pos, w, n, sums, reinterpret_cast<double*>(ws), ca, s);
+  return sums_counted(d, pos, w, n, 4, sums, reinterpret_cast<double*>(ws), ca, s);
 }
 
 cnpc_status launch_norms(const cnpc_mesh_desc* d, const double* gs, const double* rs, int64_t ngal,
@@ -904,8 +908,8 @@ cnpc_status launch_paint(const cnpc_mesh_desc* d, const uint32_t* gpos, const fl
 
 cnpc_status launch_paint_fkp(const cnpc_mesh_desc* d, const uint32_t* gpos, const float* gw,
                              int64_t ngal, const uint32_t* rpos, const float* rw, int64_t nran,
-                             double* gsums, double* rsums, double* norms, void* delta, void* noise,
-                             void* ws, size_t ws_bytes, hipStream_t s) {
+                             int sums_lmax, double* gsums, double* rsums, double* norms, void* delta,
+                             void* noise, void* ws, size_t ws_bytes, hipStream_t s) {
   const bool weighted = (gw != nullptr) || (rw != nullptr);
   PaintLayout L = paint_layout(d, ngal, nran, weighted);
   if (ws_bytes < L.total) {
@@ -925,9 +929,9 @@ cnpc_status launch_paint_fkp(const cnpc_mesh_desc* d, const uint32_t* gpos, cons
   ca.g = tile_geom(d);
   ca.ntiles = L.ntiles;
   ca.count = count0;
-  CNPC_TRY(sums_counted(d, gpos, gw, ngal, gs, partial, ca, s));
+  CNPC_TRY(sums_counted(d, gpos, gw, ngal, sums_lmax, gs, partial, ca, s));
   ca.count = count1;
-  CNPC_TRY(sums_counted(d, rpos, rw, nran, rs, partial, ca, s));
+  CNPC_TRY(sums_counted(d, rpos, rw, nran, sums_lmax, rs, partial, ca, s));
   CNPC_TRY(launch_norms(d, gs, rs, ngal, norms, s));
   if (d->dtype == CNPC_F64)
     return paint_t<double>(d, gpos, gw, ngal, rpos, rw, nran, norms, (double*)delta, (double*)noise, w,

@@ -72,10 +72,11 @@ def paint(desc, gpos, rpos, norms, gw=None, rw=None, noise=True, scratch: Option
     return delta, nmesh
 
 
-def paint_fkp(desc, gpos, rpos, gw=None, rw=None, noise=True, scratch: Optional[Scratch] = None,
-              stream=None):
-    """Catalog sums, normalisations and painting in one library call.
-    Returns (norms, delta, noise mesh or None, galaxy sums, random sums)."""
+def paint_fkp(desc, gpos, rpos, gw=None, rw=None, noise=True, sums_lmax=4,
+              scratch: Optional[Scratch] = None, stream=None):
+    """Catalog sums (Y_lm sums for l <= sums_lmax), normalisations and painting
+    in one library call.  Returns (norms, delta, noise mesh or None, galaxy sums,
+    random sums)."""
     sc = scratch or Scratch()
     n = desc.n
     nph = 2 if desc.interlace else 1
@@ -87,8 +88,8 @@ def paint_fkp(desc, gpos, rpos, gw=None, rw=None, noise=True, scratch: Optional[
     rs = _empty(L.SUMS_LEN, torch.float64)
     ws = sc.get(L.lib.cnpc_paint_workspace_size(C.byref(desc), gpos.shape[1], rpos.shape[1]))
     L.check(L.lib.cnpc_paint_fkp(C.byref(desc), L.ptr(gpos), L.ptr(gw), gpos.shape[1], L.ptr(rpos),
-                                 L.ptr(rw), rpos.shape[1], L.ptr(gs), L.ptr(rs), L.ptr(norms), L.ptr(delta),
-                                 L.ptr(nmesh), L.ptr(ws), ws.numel(), _sh(stream)))
+                                 L.ptr(rw), rpos.shape[1], int(sums_lmax), L.ptr(gs), L.ptr(rs), L.ptr(norms),
+                                 L.ptr(delta), L.ptr(nmesh), L.ptr(ws), ws.numel(), _sh(stream)))
     return norms, delta, nmesh, gs, rs
 
 
@@ -287,7 +288,10 @@ def measure_pk_bk(desc, gpos, rpos, bins, plan: "BispecPlan", ells=(0, 2, 4), gw
     tensors to write into ("pk": [9, nbins], "bk": [3, nconf])."""
     sc = scratch or Scratch()
     band = plan.band
-    norms, delta, nmesh, _, _ = paint_fkp(desc, gpos, rpos, gw, rw, noise=True, scratch=sc, stream=stream)
+    # the B_0 shot noise and P_l need only the l = 0 catalog sums
+    lmax = 0 if plan.ell == 0 else 4
+    norms, delta, nmesh, _, _ = paint_fkp(desc, gpos, rpos, gw, rw, noise=True, sums_lmax=lmax, scratch=sc,
+                                          stream=stream)
     hi = [l for l in ells if l > 0]
     D, dint = deinterlace(desc, band, delta, want_real=len(hi) > 0, scratch=sc, stream=stream)
     DN, _ = deinterlace(desc, band, nmesh, want_real=False, scratch=sc, stream=stream)

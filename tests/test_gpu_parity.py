@@ -193,6 +193,13 @@ def test_paint_fkp_matches_separate_calls(n, weights, dtype):
     norms2, delta2, nmesh2, gs2, rs2 = pl.paint_fkp(d, gt, rt, gwt, rwt, noise=True)
     for a, b in ((norms, norms2), (gs, gs2), (rs, rs2), (delta, delta2), (nmesh, nmesh2)):
         assert np.array_equal(host(a), host(b))
+    # l = 0 sums only: the same w sums, meshes and l = 0 normalisations, zero Y_lm sums
+    norms0, delta0, nmesh0, gs0, rs0 = pl.paint_fkp(d, gt, rt, gwt, rwt, noise=True, sums_lmax=0)
+    for a, b in ((delta, delta0), (nmesh, nmesh0)):
+        assert np.array_equal(host(a), host(b))
+    assert np.array_equal(host(gs)[:5], host(gs0)[:5]) and not np.any(host(gs0)[5:])
+    assert np.array_equal(host(rs)[:5], host(rs0)[:5]) and not np.any(host(rs0)[5:])
+    assert np.array_equal(host(norms)[:L.NORM_SBARLM + 2], host(norms0)[:L.NORM_SBARLM + 2])
 
 
 def test_paint_single_particle_cells_bit_exact():
