@@ -40,7 +40,9 @@ def parse():
     ap.add_argument("--mocks", type=int, default=64)
     ap.add_argument("--precision", choices=["f32", "bf16x3"], default="bf16x3")
     ap.add_argument("--no-graph", action="store_true", help="launch eagerly instead of one hipGraph")
-    ap.add_argument("--streams", type=int, default=2, help="concurrent streams inside a step")
+    ap.add_argument("--streams", type=int, default=4, help="concurrent streams inside a step")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (calibrates HBM counters)")
     ap.add_argument("--fp64-mocks", type=int, default=2, help="mocks timed on the plain FP64 path")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--quiet", action="store_true")
@@ -104,8 +106,24 @@ def class_model(ng, nr, n=256, es=4, band=32, grid=128, nb=20, nfields=14, nphas
     }
 
 
+def copy_probe(mib: int):
+    """A plain copy kernel of known size (5 launches): under rocprofv3 --pmc its
+    FETCH_SIZE / WRITE_SIZE per dispatch calibrate the counters against bytes."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.rand(n, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4, "launches": 5}))
+
+
 def main():
     args = parse()
+    if args.copy_probe_mib > 0:
+        copy_probe(args.copy_probe_mib)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; the mocks are independent and "
                           "shard across GPUs without communication, but multi-GPU runs are not "
