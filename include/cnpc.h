@@ -132,8 +132,8 @@ cnpc_status cnpc_norms(const cnpc_mesh_desc* desc, const double* gal_sums, const
  * u = p N / 2^32 (mesh B: u - 1/2).  Outputs are overwritten (not accumulated):
  * delta and noise each hold (1 + interlace) N^3 elements of desc->dtype.
  * Particles are counting-sorted by 16^3-node tiles and accumulated in LDS as
- * integer fixed point (2^-40 units; 2^-22 for unit-weight FP32 TSC, 2^-21
- * for CIC), so the meshes do not depend on the order of the additions.
+ * integer fixed point (2^-40 units; 2^-21 for unit-weight FP32), so the
+ * meshes do not depend on the order of the additions.
  * Workspace: cnpc_paint_workspace_size bytes (an upper bound for weighted and
  * unweighted catalogs), owned by the caller, not retained after the call. */
 size_t cnpc_paint_workspace_size(const cnpc_mesh_desc* desc, int64_t ngal, int64_t nran);

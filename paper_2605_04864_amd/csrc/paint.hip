@@ -459,11 +459,11 @@ __global__ void __launch_bounds__(1024) k_paint_tiles(const Rec<RS>* __restrict_
 // Unit-weight FP32 painting with 32-bit LDS atomics.  Each round of the
 // workgroup paints one particle per thread; a node then gains at most
 // PPF * max node weight per flush interval (PPF = particles per flush), which
-// at the chosen scale stays below 2^32 (TSC: 2048 * 0.421875 * 2^22; CIC:
+// at 2^21 units stays below 2^32 (TSC: 4096 * 0.421875 * 2^21; CIC:
 // 1024 * 1 * 2^21), so the 32-bit sums are exact.  After every interval each
 // thread moves the nodes it owns into 64-bit registers and clears them.  The
 // result equals the 64-bit fixed-point sum of the contributions rounded to
-// 2^-22 (TSC) or 2^-21 (CIC), independent of the order of the additions.
+// 2^-21 (half up), independent of the order of the additions.
 constexpr int PAINT32_THREADS = 1024;
 constexpr int PAINT32_OWN = (2 * BVOL + PAINT32_THREADS - 1) / PAINT32_THREADS;  // nodes per thread
 
@@ -513,8 +513,8 @@ __global__ void __launch_bounds__(PAINT32_THREADS, 8) k_paint_tiles_u32(const Re
                                                                      const uint32_t* __restrict__ count,
                                                                      TileGeom g, int nphase,
                                                                      float* __restrict__ blocks) {
-  constexpr float SCALE = ASSIGN == CNPC_TSC ? 4194304.0f : 2097152.0f;  // 2^22, 2^21
-  constexpr int ROUNDS_PER_FLUSH = ASSIGN == CNPC_TSC ? 2 : 1;
+  constexpr float SCALE = 2097152.0f;  // 2^21
+  constexpr int ROUNDS_PER_FLUSH = ASSIGN == CNPC_TSC ? 4 : 1;
   constexpr int NP = ASSIGN == CNPC_TSC ? 3 : 2;
   __shared__ __align__(16) uint32_t acc[2 * BVOL];
   const int t = blockIdx.x;
@@ -549,7 +549,8 @@ __global__ void __launch_bounds__(PAINT32_THREADS, 8) k_paint_tiles_u32(const Re
             const float vxy = wx[ix] * wy[iy] * SCALE;
             const int ai = a0 + ix * BW * BW + iy * BW;
 #pragma unroll
-            for (int iz = 0; iz < NP; ++iz) atomicAdd(&acc[ai + iz], __float2uint_rn(vxy * wz[iz]));
+            for (int iz = 0; iz < NP; ++iz)
+              atomicAdd(&acc[ai + iz], (uint32_t)__builtin_fmaf(vxy, wz[iz], 0.5f));
           }
       }
     }
@@ -585,7 +586,11 @@ __global__ void __launch_bounds__(512) k_fold_tiles(FoldArgs<T> fa, const double
                                                     T* __restrict__ delta, T* __restrict__ noise) {
   const int n = fa.n, nt = fa.nt, z2 = nt >= 2 ? 2 : 1;
   const int nzp = nt / z2;
+  // workgroups are dealt round-robin to the 8 XCDs: give each XCD a contiguous
+  // run of tiles so that the halo rows a tile reads from its neighbours are
+  // mostly in the same XCD's L2
   int b = blockIdx.x;
+  if ((gridDim.x & 7) == 0) b = (b & 7) * (gridDim.x >> 3) + (b >> 3);
   const int tzp = b % nzp; b /= nzp;
   const int ty = b % nt; b /= nt;
   const int tx = b % nt;
