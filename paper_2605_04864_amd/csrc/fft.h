@@ -37,6 +37,11 @@ template <typename T>
 cnpc_status fft3d_r2c(int n, int batch, int band, const T* in, cx<T>* out, cx<T>* ws, hipStream_t s);
 template <typename T>
 cnpc_status fft3d_c2r(int n, int batch, int band, const cx<T>* in, T* out, cx<T>* ws, hipStream_t s);
+// fused x pass of the interlaced full transform (N = 64 or 256; see fft.hip)
+template <typename T>
+cnpc_status xpass_interlace(int n, const cx<T>* in, cx<T>* out, cx<T>* band_out, int mb, T scale,
+                            hipStream_t s);
+constexpr bool has_xpass_interlace(int n) { return n == 64 || n == 256; }
 // complex elements of scratch needed by fft3d_* (0 for full transforms)
 size_t fft_ws_elems(int n, int batch, int band);
 

@@ -1,6 +1,7 @@
 // Batched 3-D real FFTs for gfx950: z-row passes (two real rows packed in one
 // complex transform), strided column passes (x and y), band pruning.
 #include <mutex>
+#include <type_traits>
 #include <vector>
 #include <cmath>
 
@@ -270,6 +271,26 @@ __global__ void __launch_bounds__(256) k_colpass(const cx<T>* in, cx<T>* out, Co
   }
 }
 
+// Length N = R^2 transform of W = 256 / R columns by a workgroup: lane (c,
+// rank) holds rows rank + R n2 of column c in v[n2] on entry and rows
+// rank + R k2 of the transform in v[k2] on exit.  One LDS exchange (layout
+// [k1][n1][c], 16 elements of padding per k1 block, conflict free for the
+// stage-1 writes and the stage-2 reads of a half wavefront); contains one
+// workgroup barrier before the exchange reads and one after them.
+template <typename T, int R, int DIR>
+__device__ __forceinline__ void col_fft_rr(cx<T>* v, int c, int rank, cx<T>* buf, const cx<T>* tw) {
+  constexpr int W = 256 / R;
+  dft_reg<T, R, DIR>(v);
+#pragma unroll
+  for (int k1 = 0; k1 < R; ++k1)
+    buf[(k1 * R + rank) * W + c + 16 * k1] = k1 == 0 ? v[k1] : cmul(v[k1], tw[rank * k1]);
+  __syncthreads();
+#pragma unroll
+  for (int n1 = 0; n1 < R; ++n1) v[n1] = buf[(rank * R + n1) * W + c + 16 * rank];
+  __syncthreads();
+  dft_reg<T, R, DIR>(v);
+}
+
 // Register column pass for N = R^2: 256 threads = W = 256 / R columns x R
 // ranks.  Lane (c, rank) loads rows rank + R n2 of column c, does the first
 // R-point DFT in registers, exchanges through LDS (layout [k1][n1][c] with 16
@@ -316,14 +337,7 @@ __global__ void __launch_bounds__(256) k_colpass_rr(const cx<T>* in, cx<T>* out,
     v[n2] = ok ? src[(int64_t)j * a.row_in] : cx<T>{T(0), T(0)};
   }
   __syncthreads();  // twiddles
-  dft_reg<T, R, DIR>(v);
-#pragma unroll
-  for (int k1 = 0; k1 < R; ++k1)
-    buf[(k1 * R + rank) * W + c + 16 * k1] = k1 == 0 ? v[k1] : cmul(v[k1], tw[rank * k1]);
-  __syncthreads();
-#pragma unroll
-  for (int n1 = 0; n1 < R; ++n1) v[n1] = buf[(rank * R + n1) * W + c + 16 * rank];
-  dft_reg<T, R, DIR>(v);
+  col_fft_rr<T, R, DIR>(v, c, rank, buf, tw);
   cx<T>* dst = out + p * a.plane_out + c0 + c;
 #pragma unroll
   for (int k2 = 0; k2 < R; ++k2) {
@@ -337,6 +351,84 @@ __global__ void __launch_bounds__(256) k_colpass_rr(const cx<T>* in, cx<T>* out,
     dst[(int64_t)j * a.row_out] = v[k2];
   }
 }
+
+// Fused x pass of the interlaced full transform (N = R^2): for W columns
+// (iy, kz) of both phase spectra (after their z and y passes, layout
+// [phase][x][y][kz < N/2]) the forward x transforms of A and B, the combination
+// D = 1/2 [A + e^{-i pi (nx + ny + kz) / N} B] (D = 0 on a Nyquist row or
+// column), the band copy of D (|nx|, |ny| < mb, kz < mb), and the inverse x
+// transform of scale * D, written to out (layout [x][y][kz]).
+template <typename T, int R>
+__global__ void __launch_bounds__(256) k_xpass_interlace_rr(const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
+                                                            cx<T>* __restrict__ band_out, int mb, T scale) {
+  constexpr int N = R * R, W = 256 / R, H = N / 2;
+  constexpr int LOGW = (W == 8 ? 3 : W == 16 ? 4 : W == 32 ? 5 : 6);
+  constexpr int64_t ROW = (int64_t)N * H, PHASE = (int64_t)N * N * H;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* twf = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* twi = twf + N;
+  cx<T>* buf = twi + N;
+  load_twiddles<T, N, -1>(twf);
+  load_twiddles<T, N, 1>(twi);
+  const int c = threadIdx.x & (W - 1), rank = threadIdx.x >> LOGW;
+  const int col = blockIdx.x * W + c;
+  cx<T> va[R], vb[R];
+#pragma unroll
+  for (int n2 = 0; n2 < R; ++n2) {
+    const int64_t o = (int64_t)(rank + R * n2) * ROW + col;
+    va[n2] = in[o];
+    vb[n2] = in[PHASE + o];
+  }
+  __syncthreads();  // twiddles
+  col_fft_rr<T, R, -1>(va, c, rank, buf, twf);
+  col_fft_rr<T, R, -1>(vb, c, rank, buf, twf);
+  const int iy = col / H, kz = col - iy * H;
+  const int ny = iy < H ? iy : iy - N;
+#pragma unroll
+  for (int k2 = 0; k2 < R; ++k2) {
+    const int row = rank + R * k2;
+    const int nx = row < H ? row : row - N;
+    cx<T> d = {T(0), T(0)};
+    if (nx != -H && ny != -H) {
+      T sn, cs;
+      if constexpr (sizeof(T) == 4) sincospif(-(float)(nx + ny + kz) / (float)N, &sn, &cs);
+      else sincospi(-(double)(nx + ny + kz) / (double)N, &sn, &cs);
+      d = cscale(cadd(va[k2], cmul(cx<T>{cs, sn}, vb[k2])), T(0.5));
+    }
+    if (band_out && nx > -mb && nx < mb && ny > -mb && ny < mb && kz < mb) {
+      const int bx = nx < 0 ? nx + 2 * mb : nx, by = ny < 0 ? ny + 2 * mb : ny;
+      band_out[((int64_t)bx * 2 * mb + by) * mb + kz] = d;
+    }
+    va[k2] = cscale(d, scale);
+  }
+  col_fft_rr<T, R, 1>(va, c, rank, buf, twi);
+#pragma unroll
+  for (int k2 = 0; k2 < R; ++k2) out[(int64_t)(rank + R * k2) * ROW + col] = va[k2];
+}
+
+template <typename T>
+cnpc_status xpass_interlace(int n, const cx<T>* in, cx<T>* out, cx<T>* band_out, int mb, T scale,
+                            hipStream_t s) {
+  auto go = [&](auto rc) -> cnpc_status {
+    constexpr int R = decltype(rc)::value, N = R * R, W = 256 / R;
+    const int64_t cols = (int64_t)N * (N / 2);
+    const size_t lds = sizeof(cx<T>) * (2 * N + (size_t)N * W + 16 * R);
+    kt_begin(CNPC_KT_COL, s);
+    hipLaunchKernelGGL((k_xpass_interlace_rr<T, R>), dim3((unsigned)(cols / W)), dim3(256), lds, s, in, out,
+                       band_out, mb, scale);
+    kt_end(CNPC_KT_COL, s);
+    CNPC_HIP(hipGetLastError());
+    return CNPC_OK;
+  };
+  if (n == 64) return go(std::integral_constant<int, 8>());
+  if (n == 256) return go(std::integral_constant<int, 16>());
+  set_error("fused interlace pass needs N = 64 or 256 (got %d)", n);
+  return CNPC_EUNSUPPORTED;
+}
+template cnpc_status xpass_interlace<float>(int, const cx<float>*, cx<float>*, cx<float>*, int, float,
+                                            hipStream_t);
+template cnpc_status xpass_interlace<double>(int, const cx<double>*, cx<double>*, cx<double>*, int, double,
+                                             hipStream_t);
 
 // ------------------------------------------------------------- launchers --
 // side R of the register passes for N = R^2 (0: LDS Stockham passes)

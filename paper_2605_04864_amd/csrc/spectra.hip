@@ -450,6 +450,22 @@ static cnpc_status deinterlace_t(const cnpc_mesh_desc* d, int band, const T* mes
   }
   const int64_t hsz = (int64_t)n * n * (n / 2);
   cx<T>* sp = ws;  // [2][half]
+  if (has_xpass_interlace(n)) {
+    // z and y passes of both phases, then one pass doing their x transforms,
+    // the combination, the band copy and the inverse x transform of D / N^3;
+    // inverse y and z passes into delta_int (complex view of its N^3 reals)
+    CNPC_TRY(ensure_twiddles());
+    const int dt = sizeof(T) == 8 ? CNPC_F64 : CNPC_F32;
+    const int h = n / 2;
+    const int64_t nn = (int64_t)n * n;
+    CNPC_TRY(zpass_r2c<T>(n, meshes, sp, 2 * nn, h, s));
+    ColArgs ay = make_col(n, dt, (int64_t)n * h, (int64_t)n * h, h, h, h, 0, 0);
+    CNPC_TRY(colpass<T>(n, -1, sp, sp, ay, 2 * (int64_t)n, s));
+    cx<T>* o = reinterpret_cast<cx<T>*>(delta_int);
+    CNPC_TRY(xpass_interlace<T>(n, sp, o, spec, band, T(1.0 / (double)n3), s));
+    CNPC_TRY(colpass<T>(n, 1, o, o, ay, (int64_t)n, s));
+    return zpass_c2r<T>(n, o, delta_int, nn, h, s);
+  }
   CNPC_TRY(fft3d_r2c<T>(n, 2, 0, meshes, sp, nullptr, s));
   const unsigned g = (unsigned)std::min<int64_t>((hsz + 255) / 256, 65536);
   // D / N^3 stays in place for the unnormalised inverse; D itself goes to the band
