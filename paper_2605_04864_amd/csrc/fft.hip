@@ -291,6 +291,136 @@ __device__ __forceinline__ void col_fft_rr(cx<T>* v, int c, int rank, cx<T>* buf
   dft_reg<T, R, DIR>(v);
 }
 
+// Column analogue of row_fft_q for N = R1 R2 (R2 = Q R1): W = 256 / R1
+// columns x R1 ranks; lane (c, rank) holds rows rank + R1 n2 (n2 < R2) on
+// entry and rows (rank + R1 i) + R2 k2 in v[i R1 + k2] on exit.  LDS layout
+// [k1][n1][c] with 16 elements of padding per k1 block; two barriers.
+template <typename T, int R1, int R2, int DIR>
+__device__ __forceinline__ void col_fft_q(cx<T>* v, int c, int rank, cx<T>* buf, const cx<T>* tw) {
+  constexpr int W = 256 / R1, Q = R2 / R1;
+  dft_reg<T, R2, DIR>(v);
+#pragma unroll
+  for (int k1 = 0; k1 < R2; ++k1)
+    buf[(k1 * R1 + rank) * W + c + 16 * k1] = k1 == 0 ? v[k1] : cmul(v[k1], tw[rank * k1]);
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const int k1 = rank + R1 * i;
+#pragma unroll
+    for (int n1 = 0; n1 < R1; ++n1) v[i * R1 + n1] = buf[(k1 * R1 + n1) * W + c + 16 * k1];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < Q; ++i) dft_reg<T, R1, DIR>(v + i * R1);
+}
+
+// Column pass for N = R1 R2 with R2 = 2 R1 (N = 128, 512): same arguments,
+// band and mask semantics as k_colpass.
+template <typename T, int R1, int R2, int DIR>
+__global__ void __launch_bounds__(256) k_colpass_q(const cx<T>* in, cx<T>* out, ColArgs a) {
+  constexpr int N = R1 * R2, W = 256 / R1, Q = R2 / R1;
+  constexpr int LOGW = (W == 8 ? 3 : W == 16 ? 4 : W == 32 ? 5 : 6);
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* buf = tw + N;
+  load_twiddles<T, N, DIR>(tw);
+  const int c = threadIdx.x & (W - 1), rank = threadIdx.x >> LOGW;
+  const int tiles = a.ncols >> LOGW;
+  const int64_t p = blockIdx.x / tiles;
+  const int c0 = (blockIdx.x - (int)(p * tiles)) << LOGW;
+  const cx<T>* src = in + p * a.plane_in + c0 + c;
+  int jy = 0, kz = 0;
+  if (a.mask_m) {
+    jy = (c0 + c) / a.mask_m;
+    kz = (c0 + c) - jy * a.mask_m;
+  }
+  cx<T> v[R2];
+#pragma unroll
+  for (int n2 = 0; n2 < R2; ++n2) {
+    const int r = rank + R1 * n2;
+    int j = r;
+    bool ok = true;
+    if (a.band_in) {
+      if (r < a.band_in) j = r;
+      else if (r > N - a.band_in) j = r - N + 2 * a.band_in;
+      else ok = false;
+    }
+    if (ok && a.mask_m) {
+      const int nx = freq_of(r, N), ny = band_freq(jy, a.mask_m);
+      const int64_t n2s = (int64_t)nx * nx + (int64_t)ny * ny + (int64_t)kz * kz;
+      const int b = a.mask_b0 + (int)p;
+      ok = n2s > 0 && n2s >= a.thr[b] && n2s < a.thr[b + 1] && nx != -(N / 2) && ny != -(N / 2) &&
+           ny != -a.mask_m;
+    }
+    v[n2] = ok ? src[(int64_t)j * a.row_in] : cx<T>{T(0), T(0)};
+  }
+  __syncthreads();  // twiddles
+  col_fft_q<T, R1, R2, DIR>(v, c, rank, buf, tw);
+  cx<T>* dst = out + p * a.plane_out + c0 + c;
+#pragma unroll
+  for (int i = 0; i < Q; ++i)
+#pragma unroll
+    for (int k2 = 0; k2 < R1; ++k2) {
+      const int r = rank + R1 * i + R2 * k2;
+      int j = r;
+      if (a.band_out) {
+        if (r < a.band_out) j = r;
+        else if (r >= N - a.band_out) j = r - N + 2 * a.band_out;
+        else continue;
+      }
+      dst[(int64_t)j * a.row_out] = v[i * R1 + k2];
+    }
+}
+
+// z-row c2r for N = R1 R2 (R2 = 2 R1): a group of R1 lanes per row pair;
+// same layouts and semantics as k_zpass_c2r.
+template <typename T, int R1, int R2>
+__global__ void __launch_bounds__(256) k_zpass_c2r_q(const cx<T>* in, T* out, int64_t npairs, int kz_in) {
+  constexpr int N = R1 * R2, GR = 256 / R1, Q = R2 / R1;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
+  load_twiddles<T, N, 1>(tw);
+  const int grp = threadIdx.x / R1, rank = threadIdx.x % R1;
+  cx<T>* buf = tw + N + grp * (R2 * (R1 + 1));
+  const int64_t q = (int64_t)blockIdx.x * GR + grp;
+  const bool live = q < npairs;
+  const cx<T>* r0 = in + 2 * q * (int64_t)kz_in;
+  cx<T> v[R2];
+#pragma unroll
+  for (int n2 = 0; n2 < R2; ++n2) {
+    const int k = rank + R1 * n2;
+    cx<T> z = {T(0), T(0)};
+    if (live) {
+      if (k < (N >> 1)) {
+        if (k < kz_in) {
+          const cx<T> a = r0[k], b = r0[kz_in + k];
+          z = cx<T>{a.x - b.y, a.y + b.x};
+        }
+      } else if (k > (N >> 1)) {
+        const int kk = N - k;
+        if (kk < kz_in) {
+          const cx<T> a = r0[kk], b = r0[kz_in + kk];
+          z = cx<T>{a.x + b.y, b.x - a.y};
+        }
+      }
+    }
+    v[n2] = z;
+  }
+  __syncthreads();
+  row_fft_q<T, R1, R2, 1>(v, rank, buf, tw);
+  if (live) {
+    T* o = out + 2 * q * (int64_t)N;
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+#pragma unroll
+      for (int k2 = 0; k2 < R1; ++k2) {
+        const int e = rank + R1 * i + R2 * k2;
+        o[e] = v[i * R1 + k2].x;
+        o[N + e] = v[i * R1 + k2].y;
+      }
+  }
+}
+
 // Register column pass for N = R^2: 256 threads = W = 256 / R columns x R
 // ranks.  Lane (c, rank) loads rows rank + R n2 of column c, does the first
 // R-point DFT in registers, exchanges through LDS (layout [k1][n1][c] with 16
@@ -459,9 +589,23 @@ static cnpc_status zr2c_n(const T* in, cx<T>* out, int64_t nrows, int kz, hipStr
   return CNPC_OK;
 }
 
+// R1 of the N = R1 (2 R1) register passes (0: none)
+constexpr int q_radix(int n) { return n == 128 ? 8 : n == 512 ? 16 : 0; }
+
 template <typename T, int N>
 static cnpc_status zc2r_n(const cx<T>* in, T* out, int64_t nrows, int kz, hipStream_t s) {
   const int64_t npairs = nrows / 2;
+  constexpr int R1 = q_radix(N);
+  if constexpr (R1 > 0) {
+    constexpr int R2 = 2 * R1, GR = 256 / R1;
+    const size_t lds = sizeof(cx<T>) * (N + (size_t)GR * R2 * (R1 + 1));
+    kt_begin(CNPC_KT_ZC2R, s);
+    hipLaunchKernelGGL((k_zpass_c2r_q<T, R1, R2>), dim3((unsigned)((npairs + GR - 1) / GR)), dim3(256), lds, s,
+                       in, out, npairs, kz);
+    kt_end(CNPC_KT_ZC2R, s);
+    CNPC_HIP(hipGetLastError());
+    return CNPC_OK;
+  }
   constexpr int R = rr_radix(N);
   if constexpr (R > 0) {
     constexpr int GR = 256 / R;
@@ -487,6 +631,24 @@ static cnpc_status zc2r_n(const cx<T>* in, T* out, int64_t nrows, int kz, hipStr
 template <typename T, int N, int DIR>
 static cnpc_status col_n(const cx<T>* in, cx<T>* out, const ColArgs& a, int64_t nplanes,
                          hipStream_t s) {
+  constexpr int R1 = q_radix(N);
+  if constexpr (R1 > 0) {
+    constexpr int R2 = 2 * R1, W = 256 / R1;
+    if (a.ncols % W == 0) {
+      const int64_t blocks = nplanes * (a.ncols / W);
+      if (blocks <= 0) return CNPC_OK;
+      if (blocks > 0x7fffffffLL) {
+        set_error("column pass grid too large");
+        return CNPC_EUNSUPPORTED;
+      }
+      const size_t lds = sizeof(cx<T>) * (N + (size_t)N * W + 16 * R2);
+      kt_begin(CNPC_KT_COL, s);
+      hipLaunchKernelGGL((k_colpass_q<T, R1, R2, DIR>), dim3((unsigned)blocks), dim3(256), lds, s, in, out, a);
+      kt_end(CNPC_KT_COL, s);
+      CNPC_HIP(hipGetLastError());
+      return CNPC_OK;
+    }
+  }
   constexpr int R = rr_radix(N);
   if constexpr (R > 0) {
     constexpr int W = 256 / R;

@@ -170,6 +170,27 @@ __device__ __forceinline__ void row_fft_rr(cx<T>* v, int rank, cx<T>* buf, const
   dft_reg<T, R, DIR>(v);
 }
 
+// Length N = R1 R2 transform (R2 = Q R1) of one sequence by a group of R1
+// lanes: on entry lane n1 holds x[n1 + R1 n2] in v[n2] (n2 < R2); on exit it
+// holds X[(n1 + R1 i) + R2 k2] in v[i R1 + k2] (i < Q, k2 < R1).  R2-point
+// register DFTs, one padded LDS exchange (R2 (R1 + 1) elements per group), Q
+// R1-point register DFTs per lane.  Two workgroup barriers.
+template <typename T, int R1, int R2, int DIR>
+__device__ __forceinline__ void row_fft_q(cx<T>* v, int rank, cx<T>* buf, const cx<T>* tw) {
+  constexpr int Q = R2 / R1;
+  dft_reg<T, R2, DIR>(v);  // lane n1: Y[n1][k1] in v[k1]
+#pragma unroll
+  for (int k1 = 0; k1 < R2; ++k1) buf[k1 * (R1 + 1) + rank] = k1 == 0 ? v[k1] : cmul(v[k1], tw[rank * k1]);
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < Q; ++i)
+#pragma unroll
+    for (int n1 = 0; n1 < R1; ++n1) v[i * R1 + n1] = buf[(rank + R1 * i) * (R1 + 1) + n1];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < Q; ++i) dft_reg<T, R1, DIR>(v + i * R1);
+}
+
 // Twiddle table tw[t] = exp(DIR 2 pi i t / N) into LDS.
 template <typename T, int N, int DIR>
 __device__ __forceinline__ void load_twiddles(cx<T>* tw) {

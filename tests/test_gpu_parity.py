@@ -52,7 +52,7 @@ def host(t):
 
 # ---------------------------------------------------------------- FFT -----
 @pytest.mark.parametrize("dtype", [L.F32, L.F64])
-@pytest.mark.parametrize("n", [16, 32, 64, 256])
+@pytest.mark.parametrize("n", [16, 32, 64, 128, 256])
 def test_fft_full_r2c_c2r(n, dtype):
     rng = np.random.default_rng(n)
     x = rng.normal(size=(2, n, n, n))
@@ -75,7 +75,7 @@ def test_fft_full_r2c_c2r(n, dtype):
 
 
 @pytest.mark.parametrize("dtype", [L.F32, L.F64])
-@pytest.mark.parametrize("n,band", [(32, 8), (64, 16), (64, 32), (256, 32)])
+@pytest.mark.parametrize("n,band", [(32, 8), (64, 16), (64, 32), (128, 32), (256, 32)])
 def test_fft_band_r2c_c2r(n, band, dtype):
     rng = np.random.default_rng(n + band)
     x = rng.normal(size=(3, n, n, n))
@@ -103,6 +103,36 @@ def test_fft_band_r2c_c2r(n, band, dtype):
     trunc[:, :, n - band] = 0.0
     refb = np.fft.irfftn(trunc, s=(n, n, n), axes=(1, 2, 3)) * n ** 3
     assert rel(host(back), refb) < 10 * TOL[dtype]
+
+
+def test_fft_band_512():
+    """Band transforms at 512^3 (register column and z-row passes, N = 16 x 32)."""
+    n, band = 512, 64
+    rng = np.random.default_rng(5)
+    x = rng.normal(size=(1, n, n, n)).astype(np.float32)
+    d = cn.mesh_desc(n, 100.0, dtype=L.F32)
+    xin = dev(x)
+    spec = torch.empty((1, 2 * band, 2 * band, band, 2), dtype=torch.float32, device="cuda")
+    wsb = L.lib.cnpc_fft_workspace_size(C.byref(d), 1, band)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    L.check(L.lib.cnpc_fft_r2c(C.byref(d), 1, band, L.ptr(xin), L.ptr(spec), L.ptr(ws), wsb,
+                               L.stream_handle()))
+    full = np.fft.rfftn(x[0].astype(np.float64))
+    idx = np.r_[0:band, n - band:n]
+    ref = full[idx][:, idx][..., :band]
+    del full
+    got = host(spec)[0]
+    got = got[..., 0] + 1j * got[..., 1]
+    assert rel(got, ref) < 10 * TOL[L.F32]
+    back = torch.empty_like(xin)
+    L.check(L.lib.cnpc_fft_c2r(C.byref(d), 1, band, L.ptr(spec), L.ptr(back), L.ptr(ws), wsb,
+                               L.stream_handle()))
+    trunc = np.zeros((n, n, n // 2 + 1), dtype=np.complex128)
+    trunc[np.ix_(idx, idx, range(band))] = ref
+    trunc[n - band] = 0.0
+    trunc[:, n - band] = 0.0
+    refb = np.fft.irfftn(trunc, s=(n, n, n), axes=(0, 1, 2)) * n ** 3
+    assert rel(host(back)[0], refb) < 10 * TOL[L.F32]
 
 
 # -------------------------------------------------------------- paint -----
