@@ -40,7 +40,10 @@ def parse():
     ap.add_argument("--mocks", type=int, default=64)
     ap.add_argument("--precision", choices=["f32", "bf16x3"], default="bf16x3")
     ap.add_argument("--no-graph", action="store_true", help="launch eagerly instead of one hipGraph")
-    ap.add_argument("--streams", type=int, default=4, help="concurrent streams inside a step")
+    ap.add_argument("--streams", type=int, default=0,
+                    help="concurrent streams inside a step (0: the autotuner's choice, else 4)")
+    ap.add_argument("--no-tune", action="store_true", help="library defaults, no autotuning")
+    ap.add_argument("--tune-mocks", type=int, default=16, help="mocks per autotuner trial batch")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (calibrates HBM counters)")
     ap.add_argument("--fp64-mocks", type=int, default=2, help="mocks timed on the plain FP64 path")
@@ -151,7 +154,20 @@ def main():
     plan = pl.bispec_plan(desc, bins, L.EST_SCOCCIMARRO, 0, prec, sc)
     outs = [{"pk": torch.empty((9, 20), dtype=torch.float64, device=dev),
              "bk": torch.empty((3, plan.nconf), dtype=torch.float64, device=dev)} for _ in gpu_mocks]
-    batch = pl.Batch(args.streams)
+    tuning = None
+    nstreams = args.streams or 4
+    if not args.no_tune:
+        from paper_2605_04864_amd import autotune
+        tcat = gpu_mocks[: max(1, min(args.tune_mocks, len(gpu_mocks)))]
+        res = autotune.tune_batch(desc, tcat, bins, plan, use_cache=False,
+                                  streams=(args.streams,) if args.streams else (1, 2, 3, 4, 6),
+                                  log=lambda m: log(args, m))
+        nstreams = res.streams
+        tuning = res.as_dict()
+        tuning["batch_mocks"] = len(tcat)
+        log(args, f"autotuned in {res.seconds:.1f}s: streams {res.streams}, knobs {res.knobs}, "
+                  f"{res.default_ms:.2f} -> {res.ms:.2f} ms per {len(tcat)} mocks")
+    batch = pl.Batch(nstreams)
 
     def step():
         batch.run(desc, gpu_mocks, bins, plan, outs)
@@ -251,7 +267,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if prec == L.PREC_F32 else "f32+bf16x3",
         "graph": not args.no_graph,
-        "streams": args.streams,
+        "streams": nstreams,
+        "tuning": tuning,
         "data": "synthetic lognormal mocks (seeded), resident in HBM",
         "config": {"workload": "64 uneven lognormal mocks (N_g 1e6-8e6 log-uniform, 10x randoms), "
                                "256^3 TSC + interlacing, L=1000, P_0,2,4 + Scoccimarro B_0 (20 bins, "

@@ -307,6 +307,28 @@ cnpc_status cnpc_bispectrum(const cnpc_bispec_plan* plan, const void* F0, const 
 cnpc_status cnpc_ktimer_start(uint32_t class_mask, int32_t max_launches);
 cnpc_status cnpc_ktimer_stop(double* ms_per_class, int64_t* launches_per_class);
 
+/* ---- tuning knobs (read by an autotuner; results within each kernel's
+ * tolerance whatever the setting, bit-identical paint and binning) ----
+ * Process-wide launch choices, read when a call enqueues its kernels (a
+ * captured graph keeps the choices made during capture).  Value 0 restores the
+ * library's own choice; a value that does not fit a launch (LDS, tile counts)
+ * falls back to that choice for that launch.
+ *   CNPC_TUNE_FFT_PASSES   1: LDS Stockham passes only; 0: register passes for
+ *                          N = 64, 128, 256, 512 where the tile divides.
+ *   CNPC_TUNE_FFT_COL_W    columns per workgroup of the LDS column passes
+ *                          (power of two 1..64).
+ *   CNPC_TUNE_CONTRACT_KG  point groups per contraction workgroup (1, 2, 4).
+ *   CNPC_TUNE_SORT_PER     particles per thread of the sort scatter (1, 2, 4).
+ * cnpc_tune_set rejects unknown knobs and values outside those ranges;
+ * cnpc_tune_get returns the current value (-1 for an unknown knob). */
+#define CNPC_TUNE_FFT_PASSES 0
+#define CNPC_TUNE_FFT_COL_W 1
+#define CNPC_TUNE_CONTRACT_KG 2
+#define CNPC_TUNE_SORT_PER 3
+#define CNPC_TUNE_COUNT 4
+cnpc_status cnpc_tune_set(int32_t knob, int32_t value);
+int32_t cnpc_tune_get(int32_t knob);
+
 /* Last error message of the calling thread ("" when none). */
 const char* cnpc_last_error(void);
 /* Library version string. */

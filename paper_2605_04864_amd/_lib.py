@@ -88,10 +88,16 @@ _PROTOS = {
     "cnpc_bispectrum": (_i32, [_vp, _cvp, _cvp, _cvp, _cvp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "cnpc_ktimer_start": (_i32, [C.c_uint32, _i32]),
     "cnpc_ktimer_stop": (_i32, [C.POINTER(_d), C.POINTER(_i64)]),
+    "cnpc_tune_set": (_i32, [_i32, _i32]),
+    "cnpc_tune_get": (_i32, [_i32]),
 }
 
 KT = {"paint": 1, "sort": 2, "fold": 3, "zr2c": 4, "col": 5, "zc2r": 6, "contract": 7, "bin": 8,
       "sums": 9}
+
+# tuning knobs (cnpc_tune_set / cnpc_tune_get): name -> (index, allowed values)
+TUNE = {"fft_passes": (0, (0, 1)), "fft_col_w": (1, (0, 1, 2, 4, 8, 16, 32, 64)),
+        "contract_kg": (2, (0, 1, 2, 4)), "sort_per": (3, (0, 1, 2, 4))}
 
 EXPORTED = tuple(_PROTOS)
 

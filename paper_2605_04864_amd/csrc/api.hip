@@ -1,4 +1,5 @@
 // C ABI: host-side argument validation and dispatch (see include/cnpc.h).
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -63,6 +64,13 @@ void kt_end(int c, hipStream_t s) {
   }
 }
 
+// -------------------------------------------------------- tuning knobs --
+static std::atomic<int> g_tune[CNPC_TUNE_COUNT];
+
+int tune_value(int knob) {
+  return knob >= 0 && knob < CNPC_TUNE_COUNT ? g_tune[knob].load(std::memory_order_relaxed) : 0;
+}
+
 cnpc_status check_desc(const cnpc_mesh_desc* d) {
   CNPC_REQUIRE(d != nullptr, "null mesh descriptor");
   CNPC_REQUIRE(pow2(d->n) && d->n >= 16 && d->n <= 1024, "n must be a power of two in [16, 1024] (got %d)", d->n);
@@ -113,6 +121,25 @@ extern "C" {
 
 const char* cnpc_last_error(void) { return g_err.c_str(); }
 const char* cnpc_version(void) { return "cnpc 0.1 (gfx950)"; }
+
+cnpc_status cnpc_tune_set(int32_t knob, int32_t value) {
+  API_BEGIN;
+  CNPC_REQUIRE(knob >= 0 && knob < CNPC_TUNE_COUNT, "unknown tuning knob %d", knob);
+  bool ok = value == 0;
+  switch (knob) {
+    case CNPC_TUNE_FFT_PASSES: ok = value == 0 || value == 1; break;
+    case CNPC_TUNE_FFT_COL_W: ok = ok || (value > 0 && value <= 64 && (value & (value - 1)) == 0); break;
+    case CNPC_TUNE_CONTRACT_KG:
+    case CNPC_TUNE_SORT_PER: ok = ok || value == 1 || value == 2 || value == 4; break;
+  }
+  CNPC_REQUIRE(ok, "value %d out of range for tuning knob %d", value, knob);
+  g_tune[knob].store(value, std::memory_order_relaxed);
+  return CNPC_OK;
+}
+
+int32_t cnpc_tune_get(int32_t knob) {
+  return knob >= 0 && knob < CNPC_TUNE_COUNT ? g_tune[knob].load(std::memory_order_relaxed) : -1;
+}
 
 cnpc_status cnpc_ktimer_start(uint32_t class_mask, int32_t max_launches) {
   API_BEGIN;

@@ -381,6 +381,17 @@ size_t contract_mfma_partial_doubles(int nshell, int ncols) {
   return (size_t)CONTRACT_BLOCKS * 4 * nshell * (nshell + 1) / 2 * ncols;
 }
 
+// dispatch of launch_mfma over MTW = 1..MAXMTW for fixed NT, KG
+template <int NT, int KG, int MTW>
+static cnpc_status launch_mfma_mtw(int mtw, const float* fields, int64_t npts, int nf, int nshell, int npairs,
+                                   const ContractCols& cc, double* partial, size_t lds, hipStream_t s) {
+  if (mtw == MTW) return launch_mfma<MTW, NT, KG>(fields, npts, nf, nshell, npairs, cc, partial, lds, s);
+  if constexpr (MTW > 1)
+    return launch_mfma_mtw<NT, KG, MTW - 1>(mtw, fields, npts, nf, nshell, npairs, cc, partial, lds, s);
+  set_error("split-BF16 contraction: no kernel for %d tiles per wave", mtw);
+  return CNPC_EUNSUPPORTED;
+}
+
 cnpc_status contract_mfma(const float* fields, int64_t npts, int nf, int nshell, const ContractCols& cc,
                           double* partial, double* out, hipStream_t s) {
   const int npairs = nshell * (nshell + 1) / 2;
@@ -390,29 +401,36 @@ cnpc_status contract_mfma(const float* fields, int64_t npts, int nf, int nshell,
     return CNPC_EUNSUPPORTED;
   }
   const size_t lds = sizeof(float) * (nf + 1) * MF_ROW;
-  int kgroups = 4;
+  // The 4 waves of a workgroup are KG point groups x (4 / KG) pair groups; a
+  // wave holds MTW x NT accumulator tiles (<= 8, i.e. <= 128 registers).
+  // Default: the most point groups for which the tiles fit (each operand
+  // split computed once); tuning knob CNPC_TUNE_CONTRACT_KG overrides.
+  auto mtw_for = [&](int kg) { return (mtiles + (4 / kg) - 1) / (4 / kg); };
+  int kg = tune_value(CNPC_TUNE_CONTRACT_KG);
+  if (kg != 1 && kg != 2 && kg != 4) {
+    kg = 4;
+    while (kg > 1 && mtw_for(kg) * ntiles > 8) kg >>= 1;
+  }
+  const int mtw = mtw_for(kg);
+  if (mtw * ntiles > 8) {
+    set_error("split-BF16 contraction: %d pair tiles x %d column tiles do not fit %d point groups", mtiles,
+              ntiles, kg);
+    return CNPC_EUNSUPPORTED;
+  }
   cnpc_status st;
   kt_begin(CNPC_KT_CONTRACT, s);
-  // accumulators per wave: MTW * NT * 16 <= 128 registers
-  if (mtiles * ntiles <= 8) {
-    if (ntiles == 1) st = launch_mfma<8, 1, 4>(fields, npts, nf, nshell, npairs, cc, partial, lds, s);
-    else st = launch_mfma<4, 2, 4>(fields, npts, nf, nshell, npairs, cc, partial, lds, s);
-  } else if (mtiles * ntiles <= 16) {
-    kgroups = 2;  // two pair groups of up to 8 tiles
-    if (ntiles == 1) st = launch_mfma<8, 1, 2>(fields, npts, nf, nshell, npairs, cc, partial, lds, s);
-    else st = launch_mfma<4, 2, 2>(fields, npts, nf, nshell, npairs, cc, partial, lds, s);
+  if (ntiles == 1) {
+    if (kg == 4) st = launch_mfma_mtw<1, 4, 8>(mtw, fields, npts, nf, nshell, npairs, cc, partial, lds, s);
+    else if (kg == 2) st = launch_mfma_mtw<1, 2, 8>(mtw, fields, npts, nf, nshell, npairs, cc, partial, lds, s);
+    else st = launch_mfma_mtw<1, 1, 8>(mtw, fields, npts, nf, nshell, npairs, cc, partial, lds, s);
   } else {
-    kgroups = 1;  // four pair groups
-    if (ntiles == 1) st = launch_mfma<8, 1, 1>(fields, npts, nf, nshell, npairs, cc, partial, lds, s);
-    else if (mtiles <= 16) st = launch_mfma<4, 2, 1>(fields, npts, nf, nshell, npairs, cc, partial, lds, s);
-    else {
-      set_error("split-BF16 contraction: too many output tiles");
-      st = CNPC_EUNSUPPORTED;
-    }
+    if (kg == 4) st = launch_mfma_mtw<2, 4, 4>(mtw, fields, npts, nf, nshell, npairs, cc, partial, lds, s);
+    else if (kg == 2) st = launch_mfma_mtw<2, 2, 4>(mtw, fields, npts, nf, nshell, npairs, cc, partial, lds, s);
+    else st = launch_mfma_mtw<2, 1, 4>(mtw, fields, npts, nf, nshell, npairs, cc, partial, lds, s);
   }
   kt_end(CNPC_KT_CONTRACT, s);
   if (st != CNPC_OK) return st;
-  return reduce_blocks(partial, CONTRACT_BLOCKS * kgroups, (int64_t)npairs * cc.ncols, out, s);
+  return reduce_blocks(partial, CONTRACT_BLOCKS * kg, (int64_t)npairs * cc.ncols, out, s);
 }
 
 // --------------------------------------------------- shell-filtered c2r --

@@ -43,6 +43,11 @@ void clear_error();
 void kt_begin(int cls, hipStream_t s);
 void kt_end(int cls, hipStream_t s);
 
+// current value of a tuning knob (0: library default)
+int tune_value(int knob);
+// register FFT passes allowed (CNPC_TUNE_FFT_PASSES != 1)
+inline bool fft_register_passes() { return tune_value(CNPC_TUNE_FFT_PASSES) != 1; }
+
 cnpc_status check_desc(const cnpc_mesh_desc* d);
 cnpc_status check_bins(const cnpc_mesh_desc* d, const cnpc_kbins* b);
 inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }

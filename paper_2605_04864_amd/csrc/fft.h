@@ -41,7 +41,7 @@ cnpc_status fft3d_c2r(int n, int batch, int band, const cx<T>* in, T* out, cx<T>
 template <typename T>
 cnpc_status xpass_interlace(int n, const cx<T>* in, cx<T>* out, cx<T>* band_out, int mb, T scale,
                             hipStream_t s);
-constexpr bool has_xpass_interlace(int n) { return n == 64 || n == 256; }
+inline bool has_xpass_interlace(int n) { return (n == 64 || n == 256) && fft_register_passes(); }
 // complex elements of scratch needed by fft3d_* (0 for full transforms)
 size_t fft_ws_elems(int n, int batch, int band);
 

@@ -43,10 +43,12 @@ struct ZCfg {
 };
 
 int col_tile_width(int n, int dtype) {
-  // 128-byte row segments when LDS allows: twiddles + two buffers of N x W elements
+  // 128-byte row segments (or the tuned width) when LDS allows: twiddles +
+  // two buffers of N x W elements
   const size_t es = dtype == CNPC_F64 ? 16 : 8;
   const size_t lim = lds_limit();
-  int w = (int)(128 / es);
+  const int tw = tune_value(CNPC_TUNE_FFT_COL_W);
+  int w = tw > 0 ? tw : (int)(128 / es);
   while (w > 1 && (2 * (size_t)n * w + n) * es > lim) w >>= 1;
   return w;
 }
@@ -568,7 +570,7 @@ template <typename T, int N>
 static cnpc_status zr2c_n(const T* in, cx<T>* out, int64_t nrows, int kz, hipStream_t s) {
   const int64_t npairs = nrows / 2;
   constexpr int R = rr_radix(N);
-  if constexpr (R > 0) {
+  if constexpr (R > 0) if (fft_register_passes()) {
     constexpr int GR = 256 / R;
     const size_t lds = sizeof(cx<T>) * (N + (size_t)GR * R * (R + 1));
     kt_begin(CNPC_KT_ZR2C, s);
@@ -596,7 +598,7 @@ template <typename T, int N>
 static cnpc_status zc2r_n(const cx<T>* in, T* out, int64_t nrows, int kz, hipStream_t s) {
   const int64_t npairs = nrows / 2;
   constexpr int R1 = q_radix(N);
-  if constexpr (R1 > 0) {
+  if constexpr (R1 > 0) if (fft_register_passes()) {
     constexpr int R2 = 2 * R1, GR = 256 / R1;
     const size_t lds = sizeof(cx<T>) * (N + (size_t)GR * R2 * (R1 + 1));
     kt_begin(CNPC_KT_ZC2R, s);
@@ -607,7 +609,7 @@ static cnpc_status zc2r_n(const cx<T>* in, T* out, int64_t nrows, int kz, hipStr
     return CNPC_OK;
   }
   constexpr int R = rr_radix(N);
-  if constexpr (R > 0) {
+  if constexpr (R > 0) if (fft_register_passes()) {
     constexpr int GR = 256 / R;
     const size_t lds = sizeof(cx<T>) * (N + (size_t)GR * R * (R + 1));
     kt_begin(CNPC_KT_ZC2R, s);
@@ -634,7 +636,7 @@ static cnpc_status col_n(const cx<T>* in, cx<T>* out, const ColArgs& a, int64_t 
   constexpr int R1 = q_radix(N);
   if constexpr (R1 > 0) {
     constexpr int R2 = 2 * R1, W = 256 / R1;
-    if (a.ncols % W == 0) {
+    if (a.ncols % W == 0 && fft_register_passes()) {
       const int64_t blocks = nplanes * (a.ncols / W);
       if (blocks <= 0) return CNPC_OK;
       if (blocks > 0x7fffffffLL) {
@@ -652,7 +654,7 @@ static cnpc_status col_n(const cx<T>* in, cx<T>* out, const ColArgs& a, int64_t 
   constexpr int R = rr_radix(N);
   if constexpr (R > 0) {
     constexpr int W = 256 / R;
-    if (a.ncols % W == 0) {
+    if (a.ncols % W == 0 && fft_register_passes()) {
       const int64_t blocks = nplanes * (a.ncols / W);
       if (blocks <= 0) return CNPC_OK;
       if (blocks > 0x7fffffffLL) {

@@ -759,10 +759,13 @@ __global__ void k_zero_u32(uint32_t* p, int64_t n) {
 
 constexpr int FINE_RCAP = 512;  // LDS key range of the second sort step
 
-// Largest particles-per-thread (4, 2, 1) whose LDS layout lets two
-// workgroups share a CU, else the largest that fits one.
+// Particles per thread: the tuned value when its LDS layout fits, else the
+// largest (4, 2, 1) whose layout lets two workgroups share a CU, else the
+// largest that fits one.
 static int partition_per(int rs, int rcap) {
   const size_t lim = lds_limit();
+  const int tp = tune_value(CNPC_TUNE_SORT_PER);
+  if (tp > 0 && partition_lds(tp, rs, rcap) <= lim) return tp;
   for (int per = 4; per >= 1; per >>= 1)
     if (2 * partition_lds(per, rs, rcap) <= lim) return per;
   for (int per = 4; per >= 1; per >>= 1)

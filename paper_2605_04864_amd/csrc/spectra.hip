@@ -308,9 +308,13 @@ static cnpc_status zpass_ylm(int n, const T* delta, cx<T>* out, const FieldTable
   switch (n) {
     case 16: return zylm_rr<T, 4>(delta, out, ft, kz, fstride, g, s);
     case 32: return zylm_n<T, 32>(delta, out, ft, kz, fstride, g, s);
-    case 64: return zylm_rr<T, 8>(delta, out, ft, kz, fstride, g, s);
+    case 64:
+      if (fft_register_passes()) return zylm_rr<T, 8>(delta, out, ft, kz, fstride, g, s);
+      return zylm_n<T, 64>(delta, out, ft, kz, fstride, g, s);
     case 128: return zylm_n<T, 128>(delta, out, ft, kz, fstride, g, s);
-    case 256: return zylm_rr<T, 16>(delta, out, ft, kz, fstride, g, s);
+    case 256:
+      if (fft_register_passes()) return zylm_rr<T, 16>(delta, out, ft, kz, fstride, g, s);
+      return zylm_n<T, 256>(delta, out, ft, kz, fstride, g, s);
     case 512: return zylm_n<T, 512>(delta, out, ft, kz, fstride, g, s);
     case 1024: return zylm_n<T, 1024>(delta, out, ft, kz, fstride, g, s);
     default: set_error("unsupported mesh size %d", n); return CNPC_EUNSUPPORTED;

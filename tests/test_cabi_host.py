@@ -97,3 +97,61 @@ def test_paint_and_bispec_validation():
     assert st == -1 and "FP64" in L.last_error()
     assert L.lib.cnpc_paint_workspace_size(C.byref(d), 1000, 10000) > 0
     assert L.lib.cnpc_bispec_workspace_size(C.byref(d), C.byref(b), 0, 0) > 0
+
+
+def test_tuning_knobs_validation():
+    from paper_2605_04864_amd import _lib as L
+    try:
+        for name, (idx, values) in L.TUNE.items():
+            for v in values:
+                assert L.lib.cnpc_tune_set(idx, v) == 0, (name, v)
+                assert L.lib.cnpc_tune_get(idx) == v
+            for bad in (-1, 3, 128):
+                if bad in values:
+                    continue
+                assert L.lib.cnpc_tune_set(idx, bad) == -1, (name, bad)
+                assert "out of range" in L.last_error()
+                assert L.lib.cnpc_tune_get(idx) == values[-1]  # rejected values change nothing
+        assert L.lib.cnpc_tune_set(len(L.TUNE), 0) == -1 and "unknown tuning knob" in L.last_error()
+        assert L.lib.cnpc_tune_get(len(L.TUNE)) == -1
+        assert L.lib.cnpc_tune_get(-1) == -1
+    finally:
+        for idx, _ in L.TUNE.values():
+            L.lib.cnpc_tune_set(idx, 0)
+
+
+def test_autotune_coordinate_descent():
+    from paper_2605_04864_amd.autotune import coordinate_descent
+    # separable cost with a known optimum; start elsewhere
+    opt = {"a": 3, "b": 1, "c": 2}
+    cost = lambda s: 10.0 + sum((s[k] - opt[k]) ** 2 for k in opt)
+    calls = []
+
+    def measure(s):
+        calls.append(dict(s))
+        return cost(s)
+
+    space = {"a": [0, 1, 2, 3, 4], "b": [0, 1], "c": [0, 1, 2]}
+    best, t, trials = coordinate_descent(space, {"a": 0, "b": 0, "c": 0}, measure)
+    assert best == opt and t == 10.0
+    # one sweep: the start, then every value not equal to the incumbent
+    assert len(calls) == 1 + 4 + 1 + 2 and len(trials) == len(calls)
+    # gains below min_gain keep the incumbent
+    flat = lambda s: 100.0 - 0.5 * s["a"]
+    best, _, _ = coordinate_descent({"a": [0, 1]}, {"a": 0}, flat, min_gain=0.01)
+    assert best == {"a": 0}
+
+
+def test_autotune_cache_roundtrip(tmp_path):
+    from paper_2605_04864_amd import autotune as at
+    path = str(tmp_path / "sub" / "tune.json")
+    assert at._cache_load(path) == {"version": 1, "entries": {}}
+    e1 = {"streams": 3, "knobs": {"fft_passes": 0, "fft_col_w": 8, "contract_kg": 2, "sort_per": 4},
+          "ms": 1.5, "default_ms": 2.0}
+    at._cache_store(path, "sig1", e1)
+    at._cache_store(path, "sig2", dict(e1, streams=1))
+    d = at._cache_load(path)
+    assert d["entries"]["sig1"] == e1 and d["entries"]["sig2"]["streams"] == 1
+    with open(path, "w") as f:
+        f.write("{not json")
+    assert at._cache_load(path)["entries"] == {}
