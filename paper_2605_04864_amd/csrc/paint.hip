@@ -13,6 +13,17 @@ namespace cnpc {
 constexpr int TILE = 16;
 constexpr int BW = TILE + 3;           // block width: nodes c-1 .. c+2 around tile
 constexpr int BVOL = BW * BW * BW;     // 6859
+constexpr int BSTRIDE = 6880;          // elements per (tile, phase) block: BVOL rounded to 32
+
+// Layout of a block (LDS accumulator and memory).  Local node l = 0..18 along
+// an axis is node 16 t - 1 + l of the mesh: l = 1..16 are the tile's own
+// nodes, l = 17..18 nodes 0..1 of the upper neighbour, l = 0 node 15 of the
+// lower one.  Rows (lx, ly) of 19 nodes are stored in row-major order, and
+// within a row node lz sits at (lz + 18) mod 19: the 16 own nodes first, then
+// the two of the upper neighbour, then the one of the lower neighbour.  So a
+// fold reads every row as one run of 16 own values and short runs for the z
+// neighbours, and the stencil addresses of a particle stay affine except for
+// a node l = 0, which moves to the end of its row.
 constexpr int SORT_BLOCK = 1024;
 constexpr int SORT_PER_THREAD = 64;    // particles per thread per sort workgroup
 constexpr int LDS_TILES_MAX = 8192;    // LDS-aggregated sort up to this many tiles
@@ -433,8 +444,9 @@ __global__ void __launch_bounds__(1024) k_paint_tiles(const Rec<RS>* __restrict_
       const int ox = stencil_1d<T>(px, shift, ASSIGN, ph, wx);
       const int oy = stencil_1d<T>(py, shift, ASSIGN, ph, wy);
       const int oz = stencil_1d<T>(pz, shift, ASSIGN, ph, wz);
-      unsigned long long* a =
-          acc + q * BVOL + (bx + ox) * BW * BW + (by + oy) * BW + (bz + oz);
+      // node lz = bz + oz + iz sits at lz - 1 in its row, lz = 0 at 18
+      const int a1 = q * BVOL + (bx + ox) * BW * BW + (by + oy) * BW + (bz + oz - 1);
+      const int a0 = a1 + (bz + oz == 0 ? BW : 0);
 #pragma unroll
       for (int ix = 0; ix < NP; ++ix) {
         const T vx = wv * wx[ix];
@@ -444,16 +456,18 @@ __global__ void __launch_bounds__(1024) k_paint_tiles(const Rec<RS>* __restrict_
 #pragma unroll
           for (int iz = 0; iz < NP; ++iz) {
             const long long fixv = __double2ll_rn((double)(vxy * wz[iz]) * FIX_SCALE);
-            atomicAdd(&a[ix * BW * BW + iy * BW + iz], (unsigned long long)fixv);
+            atomicAdd(&acc[(iz == 0 ? a0 : a1) + ix * BW * BW + iy * BW + iz], (unsigned long long)fixv);
           }
         }
       }
     }
   }
   __syncthreads();
-  T* out = blocks + ((int64_t)t * nphase + ph0) * BVOL;
-  for (int i = threadIdx.x; i < nph * BVOL; i += blockDim.x)
-    out[i] = T((double)(long long)acc[i] * FIX_INV);
+  T* out = blocks + ((int64_t)t * nphase + ph0) * BSTRIDE;
+  for (int i = threadIdx.x; i < nph * BVOL; i += blockDim.x) {
+    const int q = i >= BVOL ? 1 : 0;
+    out[q * BSTRIDE + i - q * BVOL] = T((double)(long long)acc[i] * FIX_INV);
+  }
 }
 
 // Unit-weight FP32 painting with 32-bit LDS atomics.  Each round of the
@@ -541,16 +555,18 @@ __global__ void __launch_bounds__(PAINT32_THREADS, 8) k_paint_tiles_u32(const Re
         const int ox = stencil32<ASSIGN>(px, shift, ph, wx);
         const int oy = stencil32<ASSIGN>(py, shift, ph, wy);
         const int oz = stencil32<ASSIGN>(pz, shift, ph, wz);
-        const int a0 = ph * BVOL + (bx + ox) * BW * BW + (by + oy) * BW + (bz + oz);
+        // node lz = bz + oz + iz sits at lz - 1 in its row, lz = 0 at 18
+        const int a1 = ph * BVOL + (bx + ox) * BW * BW + (by + oy) * BW + (bz + oz - 1);
+        const int a0 = a1 + (bz + oz == 0 ? BW : 0);
 #pragma unroll
         for (int ix = 0; ix < NP; ++ix)
 #pragma unroll
           for (int iy = 0; iy < NP; ++iy) {
             const float vxy = wx[ix] * wy[iy] * SCALE;
-            const int ai = a0 + ix * BW * BW + iy * BW;
+            const int o = ix * BW * BW + iy * BW;
 #pragma unroll
             for (int iz = 0; iz < NP; ++iz)
-              atomicAdd(&acc[ai + iz], (uint32_t)__builtin_fmaf(vxy, wz[iz], 0.5f));
+              atomicAdd(&acc[(iz == 0 ? a0 : a1) + o + iz], (uint32_t)__builtin_fmaf(vxy, wz[iz], 0.5f));
           }
       }
     }
@@ -568,103 +584,139 @@ __global__ void __launch_bounds__(PAINT32_THREADS, 8) k_paint_tiles_u32(const Re
       __syncthreads();
     }
   }
-  float* out = blocks + (int64_t)t * nphase * BVOL;
+  float* out = blocks + (int64_t)t * nphase * BSTRIDE;
 #pragma unroll
   for (int j = 0; j < PAINT32_OWN; ++j) {
     const int i = threadIdx.x + j * PAINT32_THREADS;
-    if (i < nv) out[i] = (float)((double)own[j] * (1.0 / (double)SCALE));
+    if (i < nv) {
+      const int q = i >= BVOL ? 1 : 0;
+      out[q * BSTRIDE + i - q * BVOL] = (float)((double)own[j] * (1.0 / (double)SCALE));
+    }
   }
 }
 
-// Fold of the tile blocks into meshes: a workgroup owns Z2 tiles along z
-// (16 x 16 Z2 threads, lane = node (y, z) of the tiles) and walks x; every
-// node sums the <= 8 blocks covering it (own block plus the halos of the
-// lower / upper neighbours) for each set and forms
-// delta = sum_s cd[s] v_s and N = sum_s cn[s] v_s.
+// 16 consecutive elements from an address aligned to the element size
+// (gfx950 takes 16-byte loads at 4-byte alignment)
+template <typename T>
+__device__ __forceinline__ void load16(const T* __restrict__ p, T* v) {
+  struct __attribute__((aligned(sizeof(T)))) V2 { T a, b; };
+  struct __attribute__((aligned(sizeof(T)))) V4 { T a, b, c, d; };
+  if constexpr (sizeof(T) == 4) {
+    const V4* q = reinterpret_cast<const V4*>(p);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const V4 u = q[k];
+      v[4 * k] = u.a; v[4 * k + 1] = u.b; v[4 * k + 2] = u.c; v[4 * k + 3] = u.d;
+    }
+  } else {
+    const V2* q = reinterpret_cast<const V2*>(p);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const V2 u = q[k];
+      v[2 * k] = u.a; v[2 * k + 1] = u.b;
+    }
+  }
+}
+
+// 16 consecutive elements to a 16 * sizeof(T)-aligned address
+template <typename T>
+__device__ __forceinline__ void store16(T* __restrict__ p, const T* v) {
+  if constexpr (sizeof(T) == 4) {
+    float4* q = reinterpret_cast<float4*>(p);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) q[k] = make_float4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
+  } else {
+    double2* q = reinterpret_cast<double2*>(p);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) q[k] = make_double2(v[2 * k], v[2 * k + 1]);
+  }
+}
+
+// Fold of the tile blocks into meshes.  A workgroup covers Z2 tiles along z
+// of one (x, y) tile column and one phase; a thread owns the 16-node z-row
+// (x, y) of one tile.  Along x (and y) the row gathers from its own tile
+// (local row l = c + 1) and, for c = 0, 1 (15), from the lower neighbour's
+// row l = c + 17 (the upper neighbour's row 0); from each of these <= 4 (x, y)
+// sources it reads the 16 own values of the row in the same z tile, values
+// 16..17 of the row in the lower z tile (nodes 0, 1) and value 18 of the row
+// in the upper z tile (node 15): every block element is read exactly once.
+// Per set the sum is formed first, then delta = sum_s cd[s] v_s and
+// N = sum_s cn[s] v_s.
 template <typename T>
 __global__ void __launch_bounds__(512) k_fold_tiles(FoldArgs<T> fa, const double* __restrict__ norms,
                                                     T* __restrict__ delta, T* __restrict__ noise) {
   const int n = fa.n, nt = fa.nt, z2 = nt >= 2 ? 2 : 1;
   const int nzp = nt / z2;
-  // workgroups are dealt round-robin to the 8 XCDs: give each XCD a contiguous
-  // run of tiles so that the halo rows a tile reads from its neighbours are
-  // mostly in the same XCD's L2
   int b = blockIdx.x;
-  if ((gridDim.x & 7) == 0) b = (b & 7) * (gridDim.x >> 3) + (b >> 3);
   const int tzp = b % nzp; b /= nzp;
   const int ty = b % nt; b /= nt;
   const int tx = b % nt;
   const int ph = b / nt;
-  const int ly = threadIdx.x >> (z2 == 2 ? 5 : 4);
-  const int lzz = threadIdx.x & (16 * z2 - 1);
-  const int tz = tzp * z2 + (lzz >> 4), lz = lzz & 15;
+  const int zt = threadIdx.x % z2, row = threadIdx.x / z2;
+  const int cx = row >> 4, cy = row & 15;
+  const int tz = tzp * z2 + zt;
   const double alpha = norms[CNPC_NORM_ALPHA];
   T cd[4] = {T(0), T(0), T(0), T(0)}, cn[4] = {T(0), T(0), T(0), T(0)};
   if (fa.nsets == 2) {
     cd[0] = T(1); cd[1] = T(-alpha); cn[0] = T(1); cn[1] = T(alpha * alpha);
   } else {
-    cd[0] = T(1); cd[1] = T(-alpha); cd[2] = T(0); cd[3] = T(0);
-    cn[0] = T(0); cn[1] = T(0); cn[2] = T(1); cn[3] = T(alpha * alpha);
+    cd[0] = T(1); cd[1] = T(-alpha); cn[2] = T(1); cn[3] = T(alpha * alpha);
   }
-  // y and z covers: own block (local index + 1) and, near the tile faces, the
-  // lower (local + 17) or upper (local 0) neighbour; a second entry with
-  // valid flag off contributes nothing
-  const int tyo = ly <= 1 ? (ty - 1 + nt) % nt : (ty + 1) % nt;
-  const int lyo = ly <= 1 ? ly + 17 : 0;
-  const bool hy = ly <= 1 || ly == 15;
-  const int tzo = lz <= 1 ? (tz - 1 + nt) % nt : (tz + 1) % nt;
-  const int lzo = lz <= 1 ? lz + 17 : 0;
-  const bool hz = lz <= 1 || lz == 15;
-  const int64_t n3 = (int64_t)n * n * n;
-  const int y = ty * 16 + ly, z = tz * 16 + lz;
-  const int64_t tstride = (int64_t)fa.nphase * BVOL;
-  // offsets (elements) of the four (y, z) cover combinations within a tile
-  // column x: tile index (tx' nt + ty') nt + tz' times tstride plus local part
-  const int64_t cyz[4] = {((int64_t)ty * nt + tz) * tstride + (ly + 1) * BW + (lz + 1),
-                          ((int64_t)tyo * nt + tz) * tstride + lyo * BW + (lz + 1),
-                          ((int64_t)ty * nt + tzo) * tstride + (ly + 1) * BW + lzo,
-                          ((int64_t)tyo * nt + tzo) * tstride + lyo * BW + lzo};
-  const bool vyz[4] = {true, hy, hz, hy && hz};
-  const int64_t xstride = (int64_t)nt * nt * tstride;
-  // groups of XG nodes along x: every load of the group is issued before any
-  // store (the block reads cannot alias the mesh writes)
-  constexpr int XG = 4;
-  for (int lx0 = 0; lx0 < 16; lx0 += XG) {
-    T v[XG][4];
+  // x / y sources: own tile (row c + 1) or, near the faces, the neighbour
+  const bool hx = cx <= 1 || cx == 15, hy = cy <= 1 || cy == 15;
+  const int txn = cx <= 1 ? (tx - 1 + nt) % nt : (tx + 1) % nt;
+  const int tyn = cy <= 1 ? (ty - 1 + nt) % nt : (ty + 1) % nt;
+  const int lxn = cx <= 1 ? cx + 17 : 0, lyn = cy <= 1 ? cy + 17 : 0;
+  const int tzl = (tz - 1 + nt) % nt, tzu = (tz + 1) % nt;
+  const int64_t bst = (int64_t)fa.nphase * BSTRIDE;  // per tile
+  // element offsets of the row of source k = 2 a + c (a: x neighbour, c: y
+  // neighbour) in the same, lower and upper z tile; source k is used when ok[k]
+  int64_t o0[4], o1[4], o2[4];
+  bool ok[4];
 #pragma unroll
-    for (int u = 0; u < XG; ++u) {
-      const int lx = lx0 + u;
-      const bool hx = lx <= 1 || lx == 15;
-      const int txo = lx <= 1 ? (tx - 1 + nt) % nt : (tx + 1) % nt;
-      const int64_t cx0 = tx * xstride + (int64_t)ph * BVOL + (lx + 1) * BW * BW;
-      const int64_t cx1 = txo * xstride + (int64_t)ph * BVOL + (lx <= 1 ? lx + 17 : 0) * BW * BW;
+  for (int k = 0; k < 4; ++k) {
+    const int a = k >> 1, c = k & 1;
+    ok[k] = (!a || hx) && (!c || hy);
+    const int txs = a ? txn : tx, tys = c ? tyn : ty;
+    const int r = ((a ? lxn : cx + 1) * BW + (c ? lyn : cy + 1)) * BW;
+    const int64_t col = ((int64_t)txs * nt + tys) * nt;
+    o0[k] = (col + tz) * bst + (int64_t)ph * BSTRIDE + r;
+    o1[k] = (col + tzl) * bst + (int64_t)ph * BSTRIDE + r + 16;
+    o2[k] = (col + tzu) * bst + (int64_t)ph * BSTRIDE + r + 18;
+  }
+  T d[16], q[16];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        T acc = T(0);
-        if (s < fa.nsets) {
-          const T* __restrict__ bl = fa.blocks[s];
+  for (int e = 0; e < 16; ++e) d[e] = q[e] = T(0);
 #pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            if (vyz[k]) acc += bl[cx0 + cyz[k]];
-            if (hx && vyz[k]) acc += bl[cx1 + cyz[k]];
-          }
-        }
-        v[u][s] = acc;
-      }
+  for (int s = 0; s < 4; ++s) {
+    if (s >= fa.nsets) break;
+    const T* __restrict__ bl = fa.blocks[s];
+    T v[16];
+    load16<T>(bl + o0[0], v);
+    T lo0 = bl[o1[0]], lo1 = bl[o1[0] + 1], up = bl[o2[0]];
+#pragma unroll
+    for (int k = 1; k < 4; ++k) {
+      if (!ok[k]) continue;
+      T u[16];
+      load16<T>(bl + o0[k], u);
+#pragma unroll
+      for (int e = 0; e < 16; ++e) v[e] += u[e];
+      lo0 += bl[o1[k]];
+      lo1 += bl[o1[k] + 1];
+      up += bl[o2[k]];
     }
+    v[0] += lo0;
+    v[1] += lo1;
+    v[15] += up;
 #pragma unroll
-    for (int u = 0; u < XG; ++u) {
-      T d = T(0), q = T(0);
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        d += cd[s] * v[u][s];
-        q += cn[s] * v[u][s];
-      }
-      const int64_t idx = ph * n3 + ((int64_t)(tx * 16 + lx0 + u) * n + y) * n + z;
-      delta[idx] = d;
-      if (noise) noise[idx] = q;
+    for (int e = 0; e < 16; ++e) {
+      d[e] += cd[s] * v[e];
+      q[e] += cn[s] * v[e];
     }
   }
+  const int64_t idx = (int64_t)ph * n * n * n + ((int64_t)(tx * 16 + cx) * n + ty * 16 + cy) * n + tz * 16;
+  store16<T>(delta + idx, d);
+  if (noise) store16<T>(noise + idx, q);
 }
 
 // ------------------------------------------------------------------- host --
@@ -745,7 +797,7 @@ PaintLayout paint_layout(const cnpc_mesh_desc* d, int64_t ngal, int64_t nran, bo
   L.off_bcur = off; off = align_up(off + (size_t)L.nbuckets * 4);
   for (int k = 0; k < L.nsets; ++k) {
     L.off_blocks[k] = off;
-    off = align_up(off + (size_t)L.ntiles * L.nphase * BVOL * es);
+    off = align_up(off + (size_t)L.ntiles * L.nphase * BSTRIDE * es);
   }
   L.total = off;
   return L;
