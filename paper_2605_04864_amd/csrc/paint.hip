@@ -67,6 +67,61 @@ __device__ __forceinline__ double wave_sum(double v) {
 constexpr int SUMS_THREADS = 1024;
 constexpr int SUMS_BLOCKS = 256;
 
+// adds the catalog sums of one particle (weight wi) to acc
+template <int LMAX>
+__device__ __forceinline__ void sums_add(double* acc, uint32_t px, uint32_t py, uint32_t pz, double wi,
+                                       double scale, const SumsArgs& a) {
+  const double w2 = wi * wi, w3 = w2 * wi;
+  acc[0] += wi;
+  acc[1] += w2;
+  acc[2] += w3;
+  int q = 3;
+  // (l, m) order: (0,0), (2,0..2), (4,0..4); accumulate w^3 conj(y_l^m)
+  acc[q++] += w3;  // y_0^0 = 1
+  acc[q++] += 0.0;
+  if constexpr (LMAX < 2) return;
+  if (a.global_los) {
+    double re[5], im[5];
+    racah_ylm<double>(2, a.los[0], a.los[1], a.los[2], re, im);
+    for (int m = 0; m <= 2; ++m) { acc[q++] += w3 * re[m]; acc[q++] -= w3 * im[m]; }
+    if constexpr (LMAX < 4) return;
+    racah_ylm<double>(4, a.los[0], a.los[1], a.los[2], re, im);
+    for (int m = 0; m <= 4; ++m) { acc[q++] += w3 * re[m]; acc[q++] -= w3 * im[m]; }
+  } else {
+    // solid harmonics: y_l^m(r / R) = Q_lm(r_z, R^2) (r_x + i r_y)^m / R^l,
+    // the Q_lm of solid_coef written out for l = 2, 4
+    const double rx = (double)px * scale - a.obs[0];
+    const double ry = (double)py * scale - a.obs[1];
+    const double rz = (double)pz * scale - a.obs[2];
+    const double z2 = rz * rz;
+    const double r2 = rx * rx + ry * ry + z2;
+    const double i2 = 1.0 / r2;
+    const double c2 = w3 * i2, c4 = c2 * i2;
+    const double s2r = rx * rx - ry * ry, s2i = 2.0 * rx * ry;
+    const double s3r = s2r * rx - s2i * ry, s3i = s2r * ry + s2i * rx;
+    const double s4r = s2r * s2r - s2i * s2i, s4i = 2.0 * s2r * s2i;
+    const double q20 = c2 * (1.5 * z2 - 0.5 * r2);
+    const double q21 = c2 * -1.22474487139158904910 * rz;
+    const double q22 = c2 * 0.61237243569579452455;
+    acc[5] += q20;
+    acc[7] += q21 * rx; acc[8] -= q21 * ry;
+    acc[9] += q22 * s2r; acc[10] -= q22 * s2i;
+    if constexpr (LMAX < 4) return;
+    const double q40 = c4 * ((4.375 * z2 - 3.75 * r2) * z2 + 0.375 * r2 * r2);
+    const double q41 = c4 * rz * (-3.91311896062463196870 * z2 + 1.67705098312484227230 * r2);
+    const double q42 = c4 * (2.76699295264733191550 * z2 - 0.39528470752104741650 * r2);
+    const double q43 = c4 * -1.47901994577490951707 * rz;
+    const double q44 = c4 * 0.52291251658379721749;
+    acc[11] += q40;
+    acc[13] += q41 * rx; acc[14] -= q41 * ry;
+    acc[15] += q42 * s2r; acc[16] -= q42 * s2i;
+    acc[17] += q43 * s3r; acc[18] -= q43 * s3i;
+    acc[19] += q44 * s4r; acc[20] -= q44 * s4i;
+  }
+}
+
+// LMAX: Y_lm sums for l <= LMAX (0, 2 or 4); the others stay zero
+template <int LMAX>
 __global__ void __launch_bounds__(SUMS_THREADS) k_catalog_sums(const uint32_t* __restrict__ pos,
                                                       const float* __restrict__ w, int64_t n,
                                                       SumsArgs a, double* __restrict__ partial,
@@ -82,60 +137,34 @@ __global__ void __launch_bounds__(SUMS_THREADS) k_catalog_sums(const uint32_t* _
 #pragma unroll
   for (int q = 0; q < CNPC_SUMS_LEN; ++q) acc[q] = 0.0;
   const double scale = a.boxsize / 4294967296.0;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    if (count) {
-      const int t = tile_key(pos[i], pos[n + i], pos[2 * n + i], ca.g);
-      if (lds) atomicAdd(&lcount[t], 1u);
-      else atomicAdd(&ca.count[t], 1u);
+  // U particles per thread and trip: all their loads are issued before any of
+  // them is used (fewer for the larger register sets of l > 0)
+  constexpr int U = LMAX == 0 ? 4 : (LMAX == 2 ? 2 : 1);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i0 < n; i0 += U * stride) {
+    uint32_t px[U], py[U], pz[U];
+    float wv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = i0 + u * stride;
+      px[u] = py[u] = pz[u] = 0u;
+      wv[u] = 1.0f;
+      if (i < n) {
+        px[u] = pos[i];
+        py[u] = pos[n + i];
+        pz[u] = pos[2 * n + i];
+        if (w) wv[u] = w[i];
+      }
     }
-    const double wi = w ? (double)w[i] : 1.0;
-    const double w2 = wi * wi, w3 = w2 * wi;
-    acc[0] += wi;
-    acc[1] += w2;
-    acc[2] += w3;
-    int q = 3;
-    // (l, m) order: (0,0), (2,0..2), (4,0..4); accumulate w^3 conj(y_l^m)
-    acc[q++] += w3;  // y_0^0 = 1
-    acc[q++] += 0.0;
-    if (a.lmax < 2) continue;
-    if (a.global_los) {
-      double re[5], im[5];
-      racah_ylm<double>(2, a.los[0], a.los[1], a.los[2], re, im);
-      for (int m = 0; m <= 2; ++m) { acc[q++] += w3 * re[m]; acc[q++] -= w3 * im[m]; }
-      if (a.lmax < 4) continue;
-      racah_ylm<double>(4, a.los[0], a.los[1], a.los[2], re, im);
-      for (int m = 0; m <= 4; ++m) { acc[q++] += w3 * re[m]; acc[q++] -= w3 * im[m]; }
-    } else {
-      // solid harmonics: y_l^m(r / R) = Q_lm(r_z, R^2) (r_x + i r_y)^m / R^l,
-      // the Q_lm of solid_coef written out for l = 2, 4
-      const double rx = (double)pos[i] * scale - a.obs[0];
-      const double ry = (double)pos[n + i] * scale - a.obs[1];
-      const double rz = (double)pos[2 * n + i] * scale - a.obs[2];
-      const double z2 = rz * rz;
-      const double r2 = rx * rx + ry * ry + z2;
-      const double i2 = 1.0 / r2;
-      const double c2 = w3 * i2, c4 = c2 * i2;
-      const double s2r = rx * rx - ry * ry, s2i = 2.0 * rx * ry;
-      const double s3r = s2r * rx - s2i * ry, s3i = s2r * ry + s2i * rx;
-      const double s4r = s2r * s2r - s2i * s2i, s4i = 2.0 * s2r * s2i;
-      const double q20 = c2 * (1.5 * z2 - 0.5 * r2);
-      const double q21 = c2 * -1.22474487139158904910 * rz;
-      const double q22 = c2 * 0.61237243569579452455;
-      acc[5] += q20;
-      acc[7] += q21 * rx; acc[8] -= q21 * ry;
-      acc[9] += q22 * s2r; acc[10] -= q22 * s2i;
-      if (a.lmax < 4) continue;
-      const double q40 = c4 * ((4.375 * z2 - 3.75 * r2) * z2 + 0.375 * r2 * r2);
-      const double q41 = c4 * rz * (-3.91311896062463196870 * z2 + 1.67705098312484227230 * r2);
-      const double q42 = c4 * (2.76699295264733191550 * z2 - 0.39528470752104741650 * r2);
-      const double q43 = c4 * -1.47901994577490951707 * rz;
-      const double q44 = c4 * 0.52291251658379721749;
-      acc[11] += q40;
-      acc[13] += q41 * rx; acc[14] -= q41 * ry;
-      acc[15] += q42 * s2r; acc[16] -= q42 * s2i;
-      acc[17] += q43 * s3r; acc[18] -= q43 * s3i;
-      acc[19] += q44 * s4r; acc[20] -= q44 * s4i;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (i0 + u * stride >= n) break;
+      if (count) {
+        const int t = tile_key(px[u], py[u], pz[u], ca.g);
+        if (lds) atomicAdd(&lcount[t], 1u);
+        else atomicAdd(&ca.count[t], 1u);
+      }
+      sums_add<LMAX>(acc, px[u], py[u], pz[u], (double)wv[u], scale, a);
     }
   }
   __shared__ double red[SUMS_THREADS / 64][CNPC_SUMS_LEN];
@@ -732,7 +761,12 @@ static cnpc_status sums_counted(const cnpc_mesh_desc* d, const uint32_t* pos, co
   a.global_los = d->los_mode == CNPC_LOS_GLOBAL;
   const size_t lds = (ca.count && ca.ntiles <= LDS_TILES_MAX) ? (size_t)ca.ntiles * 4 : 0;
   kt_begin(CNPC_KT_SUMS, s);
-  hipLaunchKernelGGL(k_catalog_sums, dim3(nblocks), dim3(SUMS_THREADS), lds, s, pos, w, n, a, partial, ca);
+  if (lmax >= 4)
+    hipLaunchKernelGGL(k_catalog_sums<4>, dim3(nblocks), dim3(SUMS_THREADS), lds, s, pos, w, n, a, partial, ca);
+  else if (lmax >= 2)
+    hipLaunchKernelGGL(k_catalog_sums<2>, dim3(nblocks), dim3(SUMS_THREADS), lds, s, pos, w, n, a, partial, ca);
+  else
+    hipLaunchKernelGGL(k_catalog_sums<0>, dim3(nblocks), dim3(SUMS_THREADS), lds, s, pos, w, n, a, partial, ca);
   kt_end(CNPC_KT_SUMS, s);
   CNPC_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_reduce_partials, dim3(CNPC_SUMS_LEN), dim3(64), 0, s, partial, nblocks, sums);

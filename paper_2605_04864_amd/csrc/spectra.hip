@@ -171,21 +171,56 @@ __device__ __forceinline__ T inv_pow_r(T q) {
   return r;
 }
 
-// v[n2] = (e0 w(row 0), e1 w(row 1)) for the nodes z = rank + R n2 of a row
-// pair; w = Q_lm(r_z, R^2) R^-L s, r_z = rz0 + n2 dz, R^2 = rho + r_z^2.
-template <typename T, int R, int L>
-__device__ __forceinline__ void weigh_rows(cx<T>* v, const T* e0, const T* e1, T rz0, T dz, T rho0, T rho1,
-                                           const SolidQ& qc, T s0, T s1) {
+// d0, d1 *= R^-K at the nodes z = rank + R n2 of the two rows (R^2 = rho + r_z^2)
+template <typename T, int R, int K>
+__device__ __forceinline__ void scale_rows(T* d0, T* d1, T rz0, T dz, T rho0, T rho1) {
 #pragma unroll
   for (int n2 = 0; n2 < R; ++n2) {
-    // opaque copy: keeps r_z^2 and R^2 of all nodes from being hoisted out of
+    T za = rz0 + T(n2) * dz;
+    asm volatile("" : "+v"(za));
+    d0[n2] *= inv_pow_r<T, K>(rho0 + za * za);
+    d1[n2] *= inv_pow_r<T, K>(rho1 + za * za);
+  }
+}
+
+// Q_lm(z, rho^2 + z^2) s = (c4 z^2 + c2) z^2 + c0, times z when Q_lm is odd:
+// the solid-harmonic polynomial along one row (rho^2 = r_x^2 + r_y^2), with
+// the row factor s = Re / Im (r_x + i r_y)^m folded in.
+template <typename T>
+struct ZPoly {
+  T c4, c2, c0;
+};
+
+template <typename T>
+__device__ __forceinline__ ZPoly<T> zpoly(const SolidQ& q, T rho2, T s) {
+  // Q = (A z^2 + B R^2 + D) z^2 + (C R^2 + E) R^2 + F with R^2 = rho^2 + z^2
+  const T r = rho2;
+  ZPoly<T> c;
+  c.c4 = T(q.A + q.B + q.C) * s;
+  c.c2 = (T(q.B + 2.0 * q.C) * r + T(q.D + q.E)) * s;
+  c.c0 = ((T(q.C) * r + T(q.E)) * r + T(q.F)) * s;
+  return c;
+}
+
+// v[n2] = (d0 w(row 0), d1 w(row 1)) at the nodes z = rank + R n2, with
+// w = Q_lm s along each row and d = delta R^-l
+template <typename T, int R, bool ODD>
+__device__ __forceinline__ void weigh_z(cx<T>* v, const T* d0, const T* d1, T rz0, T dz, const ZPoly<T>& a,
+                                       const ZPoly<T>& b) {
+#pragma unroll
+  for (int n2 = 0; n2 < R; ++n2) {
+    // opaque copy: keeps r_z and r_z^2 of all nodes from being hoisted out of
     // the field loop into registers
     T za = rz0 + T(n2) * dz;
     asm volatile("" : "+v"(za));
-    const T q0 = rho0 + za * za, q1 = rho1 + za * za;
-    const T w0 = solid_eval<T>(qc, za, q0) * s0 * inv_pow_r<T, L>(q0);
-    const T w1 = solid_eval<T>(qc, za, q1) * s1 * inv_pow_r<T, L>(q1);
-    v[n2] = cx<T>{e0[n2] * w0, e1[n2] * w1};
+    const T z2 = za * za;
+    T w0 = (a.c4 * z2 + a.c2) * z2 + a.c0;
+    T w1 = (b.c4 * z2 + b.c2) * z2 + b.c0;
+    if constexpr (ODD) {
+      w0 *= za;
+      w1 *= za;
+    }
+    v[n2] = cx<T>{d0[n2] * w0, d1[n2] * w1};
   }
 }
 
@@ -207,12 +242,15 @@ __global__ void __launch_bounds__(256, 3) k_zpass_ylm_rr(const T* __restrict__ d
   const int q = blockIdx.x * GR + grp;
   const int ix = q / (N / 2), iy0 = 2 * (q - ix * (N / 2));
   const T* r0 = delta + ((int64_t)ix * N + iy0) * N;
-  T e0[R], e1[R];  // delta of the two rows
+  // delta R^-pw of the two rows; pw follows the l of the current field run
+  // (local line of sight), from delta itself whenever l drops
+  T d0[R], d1[R];
+  int pw = 0;
 #pragma unroll
   for (int n2 = 0; n2 < R; ++n2) {
     const int z = rank + R * n2;
-    e0[n2] = r0[z];
-    e1[n2] = r0[N + z];
+    d0[n2] = r0[z];
+    d1[n2] = r0[N + z];
   }
   // r_z of node z = rank + R n2 is rz0 + n2 dz (recomputed where needed)
   const T rz0 = T(rank * g.h - g.obs[2]), dz = T(R * g.h);
@@ -227,23 +265,38 @@ __global__ void __launch_bounds__(256, 3) k_zpass_ylm_rr(const T* __restrict__ d
     const int l = ft.ell[f0];
     int f1 = f0 + 1;
     while (f1 < ft.nf && ft.ell[f1] == l) ++f1;
+    if (!g.global_los && l != pw) {
+      if (l < pw) {
+#pragma unroll
+        for (int n2 = 0; n2 < R; ++n2) {
+          const int z = rank + R * n2;
+          d0[n2] = r0[z];
+          d1[n2] = r0[N + z];
+        }
+        pw = 0;
+      }
+      switch (l - pw) {
+        case 1: scale_rows<T, R, 1>(d0, d1, rz0, dz, rho0, rho1); break;
+        case 2: scale_rows<T, R, 2>(d0, d1, rz0, dz, rho0, rho1); break;
+        case 3: scale_rows<T, R, 3>(d0, d1, rz0, dz, rho0, rho1); break;
+        case 4: scale_rows<T, R, 4>(d0, d1, rz0, dz, rho0, rho1); break;
+        default: break;
+      }
+      pw = l;
+    }
     for (int f = f0; f < f1; ++f) {
       const int m = ft.m[f], p = ft.part[f];
       cx<T> v[R];
       if (g.global_los) {
         const T w = ylm_one<T>(l, m, p, T(g.los[0]), T(g.los[1]), T(g.los[2]));
 #pragma unroll
-        for (int n2 = 0; n2 < R; ++n2) v[n2] = cx<T>{e0[n2] * w, e1[n2] * w};
+        for (int n2 = 0; n2 < R; ++n2) v[n2] = cx<T>{d0[n2] * w, d1[n2] * w};
       } else {
         const T s0 = cpow_part<T>(rx, ry0, m, p), s1 = cpow_part<T>(rx, ry1, m, p);
         const SolidQ qc = solid_coef(l, m);
-        switch (l) {
-          case 0: weigh_rows<T, R, 0>(v, e0, e1, rz0, dz, rho0, rho1, qc, s0, s1); break;
-          case 1: weigh_rows<T, R, 1>(v, e0, e1, rz0, dz, rho0, rho1, qc, s0, s1); break;
-          case 2: weigh_rows<T, R, 2>(v, e0, e1, rz0, dz, rho0, rho1, qc, s0, s1); break;
-          case 3: weigh_rows<T, R, 3>(v, e0, e1, rz0, dz, rho0, rho1, qc, s0, s1); break;
-          default: weigh_rows<T, R, 4>(v, e0, e1, rz0, dz, rho0, rho1, qc, s0, s1); break;
-        }
+        const ZPoly<T> a = zpoly<T>(qc, rho0, s0), b = zpoly<T>(qc, rho1, s1);
+        if (qc.odd) weigh_z<T, R, true>(v, d0, d1, rz0, dz, a, b);
+        else weigh_z<T, R, false>(v, d0, d1, rz0, dz, a, b);
       }
       row_fft_rr<T, R, -1>(v, rank, buf, tw);
       // lane k1 holds Z[k1 + R k2]; Z[N - k] sits in lane (R - k1) & (R - 1),
