@@ -35,7 +35,7 @@ PEAKS_TFLOPS = {"fp32": 157.3, "fp64": 78.6, "bf16": 2500.0}
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--mocks", type=int, default=64)
     ap.add_argument("--precision", choices=["f32", "bf16x3"], default="bf16x3")
@@ -159,7 +159,7 @@ def main():
     if not args.no_tune:
         from paper_2605_04864_amd import autotune
         tcat = gpu_mocks[: max(1, min(args.tune_mocks, len(gpu_mocks)))]
-        res = autotune.tune_batch(desc, tcat, bins, plan, use_cache=False,
+        res = autotune.tune_batch(desc, tcat, bins, plan, use_cache=False, reps=5,
                                   streams=(args.streams,) if args.streams else (1, 2, 3, 4, 6),
                                   log=lambda m: log(args, m))
         nstreams = res.streams
@@ -191,16 +191,17 @@ def main():
         run()
     torch.cuda.synchronize()
     log(args, f"warmup done {time.time() - t0:.1f}s")
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     w0 = time.perf_counter()
-    ev0.record()
-    for _ in range(args.steps):
+    evs[0].record()
+    for k in range(args.steps):
         run()
-    ev1.record()
+        evs[k + 1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
-    ms_step = ev0.elapsed_time(ev1) / args.steps
+    step_ms = [evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)]
+    ms_step = evs[0].elapsed_time(evs[-1]) / args.steps
     value = args.mocks / (ms_step / 1e3)
     log(args, f"timed {args.steps} steps: {ms_step:.1f} ms/step (wall {wall:.2f}s)")
 
@@ -262,6 +263,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_step,
+        "step_ms_median": float(np.median(step_ms)),
+        "step_ms_min": float(np.min(step_ms)),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

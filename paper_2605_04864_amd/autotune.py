@@ -156,7 +156,7 @@ def time_batch(desc, catalogs, bins, plan, ells=(0, 2, 4), nstreams: int = DEFAU
 
 
 def tune_batch(desc, catalogs, bins, plan, ells=(0, 2, 4), streams: Sequence[int] = (1, 2, 3, 4, 6),
-               reps: int = 3, min_gain: float = 0.01, cache: Optional[str] = None,
+               reps: int = 3, min_gain: float = 0.02, cache: Optional[str] = None,
                use_cache: bool = True, log: Optional[Callable[[str], None]] = None) -> TuneResult:
     """Pick the stream count and knob values for batches like `catalogs` and
     leave the knobs set to the choice."""
