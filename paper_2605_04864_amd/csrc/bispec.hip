@@ -342,6 +342,35 @@ __global__ void __launch_bounds__(256, 2) k_contract_mfma(const float* __restric
       }
     }
   }
+  if constexpr (KG == 4) {
+    // the four point groups hold the same tiles: sum them in FP64 through LDS
+    // (fixed order) and write one partial per workgroup, coalesced
+    __syncthreads();
+    double* red = reinterpret_cast<double*>(smem_raw);  // [MTW][NT][16][64]
+#pragma unroll
+    for (int k = 0; k < KG; ++k) {
+      if (kg == k) {
+#pragma unroll
+        for (int i = 0; i < MTW; ++i)
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+              const int idx = ((i * NT + nt) * 16 + v) * 64 + lane;
+              red[idx] = (k == 0 ? 0.0 : red[idx]) + (double)acc[i][nt][v];
+            }
+      }
+      __syncthreads();
+    }
+    double* out = partial + (int64_t)blockIdx.x * npairs * cc.ncols;
+    for (int e = threadIdx.x; e < npairs * cc.ncols; e += blockDim.x) {
+      const int p = e / cc.ncols, j = e - p * cc.ncols;
+      const int r = p & 31;
+      const int v = (r >> 3) * 4 + (r & 3), ln = ((r >> 2) & 1) * 32 + (j & 31);
+      out[e] = red[(((p >> 5) * NT + (j >> 5)) * 16 + v) * 64 + ln];
+    }
+    return;
+  }
   // one partial per (workgroup, point group)
   double* out = partial + ((int64_t)blockIdx.x * KG + kg) * npairs * cc.ncols;
 #pragma unroll
@@ -400,7 +429,8 @@ cnpc_status contract_mfma(const float* fields, int64_t npts, int nf, int nshell,
     set_error("split-BF16 contraction supports at most 64 columns and 1024 pairs");
     return CNPC_EUNSUPPORTED;
   }
-  const size_t lds = sizeof(float) * (nf + 1) * MF_ROW;
+  // staging tile; with 4 point groups also the FP64 reduction of the tiles
+  const size_t lds_tile = sizeof(float) * (nf + 1) * MF_ROW;
   // The 4 waves of a workgroup are KG point groups x (4 / KG) pair groups; a
   // wave holds MTW x NT accumulator tiles (<= 8, i.e. <= 128 registers).
   // Default: the most point groups for which the tiles fit (each operand
@@ -417,6 +447,8 @@ cnpc_status contract_mfma(const float* fields, int64_t npts, int nf, int nshell,
               ntiles, kg);
     return CNPC_EUNSUPPORTED;
   }
+  const size_t lds_red = kg == 4 ? (size_t)mtw * ntiles * 16 * 64 * sizeof(double) : 0;
+  const size_t lds = lds_tile > lds_red ? lds_tile : lds_red;
   cnpc_status st;
   kt_begin(CNPC_KT_CONTRACT, s);
   if (ntiles == 1) {
@@ -430,7 +462,8 @@ cnpc_status contract_mfma(const float* fields, int64_t npts, int nf, int nshell,
   }
   kt_end(CNPC_KT_CONTRACT, s);
   if (st != CNPC_OK) return st;
-  return reduce_blocks(partial, CONTRACT_BLOCKS * kg, (int64_t)npairs * cc.ncols, out, s);
+  return reduce_blocks(partial, kg == 4 ? CONTRACT_BLOCKS : CONTRACT_BLOCKS * kg, (int64_t)npairs * cc.ncols,
+                       out, s);
 }
 
 // --------------------------------------------------- shell-filtered c2r --
