@@ -49,6 +49,10 @@ def parse():
     ap.add_argument("--fp64-mocks", type=int, default=2, help="mocks timed on the plain FP64 path")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--config", type=int, default=4, choices=[1, 2, 3, 4, 5],
+                    help="4: the batched headline; 1, 2, 3, 5: one catalog of that configuration "
+                         "timed per precision form, with cross-precision errors")
+    ap.add_argument("--reps", type=int, default=2, help="timed repetitions per form (--config != 4)")
     return ap.parse_args()
 
 
@@ -132,6 +136,9 @@ def main():
                           "shard across GPUs without communication, but multi-GPU runs are not "
                           "part of it", "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.config != 4:
+        single_config(args)
+        return
     import torch
     import paper_2605_04864_amd as cn
     from paper_2605_04864_amd import _lib as L
@@ -284,6 +291,92 @@ def main():
                                   for kk, vv in v.items()} for k, v in classes.items()},
         "fp64_plain": fp64,
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+def rel_err(a, b):
+    """max |a - b| / max |b| over a multipole vector."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.max(np.abs(a - b)) / max(float(np.max(np.abs(b))), 1e-300))
+
+
+def single_config(args):
+    """One catalog of configuration c1, c2, c3 or c5 (seeded lognormal galaxies
+    and uniform randoms of the configuration's size): seconds per catalog of
+    every precision form (catalogs resident in HBM, plans built beforehand) and
+    the relative errors of FP32 and split-BF16 against the FP64 path."""
+    import torch
+    import paper_2605_04864_amd as cn
+    from paper_2605_04864_amd import _lib as L
+    from paper_2605_04864_amd import pipeline as pl
+    import synthcat
+
+    spec = synthcat.config_spec(args.config)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t0 = time.time()
+    g = synthcat.lognormal_catalog(spec.ngal, spec.boxsize, 1000 * args.config)
+    r = synthcat.random_catalog(spec.nran, 1000 * args.config + 1)
+    log(args, f"generated c{args.config} catalogs in {time.time() - t0:.1f}s")
+    gd, rd = torch.from_numpy(g).to(dev), torch.from_numpy(r).to(dev)
+    del g, r
+    obs = synthcat.observer_position()
+    bins = cn.kbins(0.0, spec.dk, spec.nbins)
+    descs = {dt: cn.mesh_desc(spec.nmesh, spec.boxsize, assign=spec.assign, interlace=spec.interlace,
+                              dtype=dt, observer=obs) for dt in (L.F32, L.F64)}
+    # (name, precision form, callable returning {output: tensor})
+    jobs = []
+    if args.config in (1, 2):
+        modified = args.config == 2
+
+        def pk(dt):
+            def run():
+                res = pl.measure_pk(descs[dt], gd, rd, bins, ells=spec.ells, modified=modified)
+                keys = pl.PK_ROWS if modified else ("P0", "P2", "P4")
+                return {k: res[k] for k in keys}
+            return run
+        jobs += [("pk", "f64", pk(L.F64)), ("pk", "f32", pk(L.F32))]
+    else:
+        ests = ([("B0", L.EST_SCOCCIMARRO, 0), ("B2", L.EST_SCOCCIMARRO, 2), ("B202", L.EST_TRIPOSH, 2)]
+                if args.config == 3 else [("B202", L.EST_TRIPOSH, 2)])
+        forms = [("f64", L.F64, L.PREC_F64), ("f32", L.F32, L.PREC_F32), ("bf16x3", L.F32, L.PREC_BF16X3)]
+
+        def bk(dt, prec, est, ell):
+            def run():
+                res = pl.measure_bk(descs[dt], gd, rd, bins, estimator=est, ell=ell, precision=prec)
+                return {"raw": res["raw"], "value": res["value"]}
+            return run
+        for name, est, ell in ests:
+            jobs += [(name, f, bk(dt, prec, est, ell)) for f, dt, prec in forms]
+    times, outs = {}, {}
+    for name, form, run in jobs:
+        outs[(name, form)] = {k: v.detach().cpu().numpy() for k, v in run().items()}  # warm: plans, scratch
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.reps):
+            run()
+        e1.record()
+        torch.cuda.synchronize()
+        times.setdefault(name, {})[form] = e0.elapsed_time(e1) / 1e3 / args.reps
+        log(args, f"c{args.config} {name} {form}: {times[name][form]:.4f} s per catalog")
+    errors = {}
+    for (name, form), o in outs.items():
+        if form == "f64":
+            continue
+        ref = outs[(name, "f64")]
+        errors.setdefault(name, {})[form] = {k: rel_err(o[k], ref[k]) for k in o}
+    line = {
+        "metric": "seconds per catalog",
+        "config": {"workload": spec.name, "ngal": spec.ngal, "nran": spec.nran, "nmesh": spec.nmesh,
+                   "boxsize": spec.boxsize, "nbins": spec.nbins, "dk": spec.dk},
+        "n_gpus": 1,
+        "data": "synthetic lognormal galaxies + uniform randoms (seeded), resident in HBM",
+        "reps": args.reps,
+        "seconds_per_catalog": times,
+        "rel_error_vs_fp64": errors,
     }
     print(json.dumps(line))
 
