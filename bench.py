@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--streams", type=int, default=0,
                     help="concurrent streams inside a step (0: the autotuner's choice, else 4)")
     ap.add_argument("--no-tune", action="store_true", help="library defaults, no autotuning")
+    ap.add_argument("--staged", action="store_true",
+                    help="painting and spectra on separate streams (with --no-tune)")
     ap.add_argument("--tune-mocks", type=int, default=16, help="mocks per autotuner trial batch")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (calibrates HBM counters)")
@@ -163,6 +165,7 @@ def main():
              "bk": torch.empty((3, plan.nconf), dtype=torch.float64, device=dev)} for _ in gpu_mocks]
     tuning = None
     nstreams = args.streams or 4
+    staged = args.staged
     if not args.no_tune:
         from paper_2605_04864_amd import autotune
         tcat = gpu_mocks[: max(1, min(args.tune_mocks, len(gpu_mocks)))]
@@ -170,11 +173,12 @@ def main():
                                   streams=(args.streams,) if args.streams else (1, 2, 3, 4, 6),
                                   log=lambda m: log(args, m))
         nstreams = res.streams
+        staged = res.staged
         tuning = res.as_dict()
         tuning["batch_mocks"] = len(tcat)
-        log(args, f"autotuned in {res.seconds:.1f}s: streams {res.streams}, knobs {res.knobs}, "
+        log(args, f"autotuned in {res.seconds:.1f}s: streams {res.streams}, staged {res.staged}, knobs {res.knobs}, "
                   f"{res.default_ms:.2f} -> {res.ms:.2f} ms per {len(tcat)} mocks")
-    batch = pl.Batch(nstreams)
+    batch = pl.Batch(nstreams, staged=staged)
 
     def step():
         batch.run(desc, gpu_mocks, bins, plan, outs)
@@ -278,6 +282,7 @@ def main():
         "dtype": "f32" if prec == L.PREC_F32 else "f32+bf16x3",
         "graph": not args.no_graph,
         "streams": nstreams,
+        "staged": staged,
         "tuning": tuning,
         "data": "synthetic lognormal mocks (seeded), resident in HBM",
         "config": {"workload": "64 uneven lognormal mocks (N_g 1e6-8e6 log-uniform, 10x randoms), "

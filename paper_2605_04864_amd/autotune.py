@@ -6,12 +6,15 @@ size), the batch is captured into one HIP graph, and the graph is replayed.
 The setting is
 
   streams      streams a ``pipeline.Batch`` spreads the catalogs over
+  staged       Batch mode: whole catalogs round-robin (False; the only mode
+               captured into graphs, so the only one searched)
   fft_passes   register FFT passes (0) or LDS Stockham passes only (1)
   fft_col_w    columns per workgroup of the LDS column passes (0: library's)
   contract_kg  point groups per split-BF16 contraction workgroup (0: library's)
   sort_per     particles per thread of the sort scatter (0: library's)
+  sort_threads threads per sort-scatter workgroup (0: library's)
 
-The last four are the library's tuning knobs (``cnpc_tune_set``); the search
+The last five are the library's tuning knobs (``cnpc_tune_set``); the search
 is one coordinate-descent sweep in that order, each value timed with the
 others held at the best found so far, and a value replaces the incumbent only
 when it is faster by more than ``min_gain``.  Every setting gives results
@@ -31,7 +34,7 @@ from typing import Callable, Dict, List, Optional, Sequence, Tuple
 
 from . import _lib as L
 
-KNOB_ORDER = ("fft_passes", "fft_col_w", "contract_kg", "sort_per")
+KNOB_ORDER = ("fft_passes", "fft_col_w", "contract_kg", "sort_per", "sort_threads")
 DEFAULT_STREAMS = 4
 
 
@@ -114,6 +117,7 @@ def _cache_store(path: str, sig: str, entry: Dict) -> None:
 @dataclass
 class TuneResult:
     streams: int
+    staged: bool
     knobs: Dict[str, int]
     ms: float                  # per batch, best setting
     default_ms: float          # per batch, library defaults (DEFAULT_STREAMS if offered)
@@ -128,14 +132,14 @@ class TuneResult:
 
 
 def time_batch(desc, catalogs, bins, plan, ells=(0, 2, 4), nstreams: int = DEFAULT_STREAMS,
-               reps: int = 3) -> float:
+               reps: int = 3, staged: bool = False) -> float:
     """Median ms per graph replay of the whole batch under the current knobs."""
     import torch
     from . import pipeline as pl
     dev = catalogs[0][0].device
     outs = [{"pk": torch.empty((9, bins.nbins), dtype=torch.float64, device=dev),
              "bk": torch.empty((3, plan.nconf), dtype=torch.float64, device=dev)} for _ in catalogs]
-    batch = pl.Batch(nstreams, device=dev)
+    batch = pl.Batch(nstreams, device=dev, staged=staged)
     batch.run(desc, catalogs, bins, plan, outs, ells)
     torch.cuda.synchronize()
     graph = torch.cuda.CUDAGraph()
@@ -166,17 +170,19 @@ def tune_batch(desc, catalogs, bins, plan, ells=(0, 2, 4), streams: Sequence[int
         hit = _cache_load(path).get("entries", {}).get(sig)
         if hit:
             set_knobs(hit["knobs"])
-            return TuneResult(int(hit["streams"]), dict(hit["knobs"]), float(hit["ms"]),
-                              float(hit["default_ms"]), 0.0, True, [])
-    space = {"streams": list(streams)}
+            return TuneResult(int(hit["streams"]), bool(hit.get("staged", False)), dict(hit["knobs"]),
+                              float(hit["ms"]), float(hit["default_ms"]), 0.0, True, [])
+    # staged batches are not captured into graphs (see pipeline.Batch), so the
+    # timed search keeps the round-robin batch
+    space = {"streams": list(streams), "staged": [False]}
     for k in KNOB_ORDER:
         space[k] = list(L.TUNE[k][1]) if k != "fft_col_w" else [0, 4, 8, 16, 32]
     s0 = DEFAULT_STREAMS if DEFAULT_STREAMS in streams else streams[0]
-    start = {"streams": s0, **{k: 0 for k in KNOB_ORDER}}
+    start = {"streams": s0, "staged": False, **{k: 0 for k in KNOB_ORDER}}
 
     def measure(s):
         set_knobs({k: s[k] for k in KNOB_ORDER})
-        t = time_batch(desc, catalogs, bins, plan, ells, s["streams"], reps)
+        t = time_batch(desc, catalogs, bins, plan, ells, s["streams"], reps, staged=s["staged"])
         if log:
             log(f"autotune {s} -> {t:.3f} ms")
         return t
@@ -189,9 +195,9 @@ def tune_batch(desc, catalogs, bins, plan, ells=(0, 2, 4), streams: Sequence[int
         raise
     knobs = {k: int(best[k]) for k in KNOB_ORDER}
     set_knobs(knobs)
-    res = TuneResult(int(best["streams"]), knobs, float(best_t), float(trials[0][1]),
+    res = TuneResult(int(best["streams"]), bool(best["staged"]), knobs, float(best_t), float(trials[0][1]),
                      time.time() - t0, False, [dict(s, ms=t) for s, t in trials])
     if use_cache:
-        _cache_store(path, sig, {"streams": res.streams, "knobs": knobs, "ms": res.ms,
+        _cache_store(path, sig, {"streams": res.streams, "staged": res.staged, "knobs": knobs, "ms": res.ms,
                                  "default_ms": res.default_ms})
     return res

@@ -72,20 +72,26 @@ def paint(desc, gpos, rpos, norms, gw=None, rw=None, noise=True, scratch: Option
     return delta, nmesh
 
 
-def paint_fkp(desc, gpos, rpos, gw=None, rw=None, noise=True, sums_lmax=4,
-              scratch: Optional[Scratch] = None, stream=None):
-    """Catalog sums (Y_lm sums for l <= sums_lmax), normalisations and painting
-    in one library call.  Returns (norms, delta, noise mesh or None, galaxy sums,
-    random sums)."""
-    sc = scratch or Scratch()
+def paint_outputs(desc, noise=True):
+    """Output buffers of paint_fkp: (norms, delta, noise mesh or None, galaxy
+    sums, random sums)."""
     n = desc.n
     nph = 2 if desc.interlace else 1
     dt = _TORCH_DT[desc.dtype]
-    delta = _empty((nph, n, n, n), dt)
-    nmesh = _empty((nph, n, n, n), dt) if noise else None
-    norms = _empty(L.NORMS_LEN, torch.float64)
-    gs = _empty(L.SUMS_LEN, torch.float64)
-    rs = _empty(L.SUMS_LEN, torch.float64)
+    return (_empty(L.NORMS_LEN, torch.float64), _empty((nph, n, n, n), dt),
+            _empty((nph, n, n, n), dt) if noise else None, _empty(L.SUMS_LEN, torch.float64),
+            _empty(L.SUMS_LEN, torch.float64))
+
+
+def paint_fkp(desc, gpos, rpos, gw=None, rw=None, noise=True, sums_lmax=4,
+              scratch: Optional[Scratch] = None, stream=None, out=None):
+    """Catalog sums (Y_lm sums for l <= sums_lmax), normalisations and painting
+    in one library call.  Returns (norms, delta, noise mesh or None, galaxy sums,
+    random sums), written into `out` (from paint_outputs) when given."""
+    sc = scratch or Scratch()
+    norms, delta, nmesh, gs, rs = out if out is not None else paint_outputs(desc, noise)
+    if noise and nmesh is None:
+        raise ValueError("paint_fkp: noise requested without a noise mesh")
     ws = sc.get(L.lib.cnpc_paint_workspace_size(C.byref(desc), gpos.shape[1], rpos.shape[1]))
     L.check(L.lib.cnpc_paint_fkp(C.byref(desc), L.ptr(gpos), L.ptr(gw), gpos.shape[1], L.ptr(rpos),
                                  L.ptr(rw), rpos.shape[1], int(sums_lmax), L.ptr(gs), L.ptr(rs), L.ptr(norms),
@@ -287,11 +293,20 @@ def measure_pk_bk(desc, gpos, rpos, bins, plan: "BispecPlan", ells=(0, 2, 4), gw
     the shot-noise spectra.  `out` (optional): dict of preallocated result
     tensors to write into ("pk": [9, nbins], "bk": [3, nconf])."""
     sc = scratch or Scratch()
-    band = plan.band
+    painted = paint_fkp(desc, gpos, rpos, gw, rw, noise=True, sums_lmax=_pk_bk_lmax(plan), scratch=sc,
+                        stream=stream)
+    return _spectra_stage(desc, bins, plan, painted, ells, sc, stream, out)
+
+
+def _pk_bk_lmax(plan) -> int:
     # the B_0 shot noise and P_l need only the l = 0 catalog sums
-    lmax = 0 if plan.ell == 0 else 4
-    norms, delta, nmesh, _, _ = paint_fkp(desc, gpos, rpos, gw, rw, noise=True, sums_lmax=lmax, scratch=sc,
-                                          stream=stream)
+    return 0 if plan.ell == 0 else 4
+
+
+def _spectra_stage(desc, bins, plan, painted, ells, sc: Scratch, stream, out):
+    """Everything of measure_pk_bk after the painting."""
+    norms, delta, nmesh = painted[0], painted[1], painted[2]
+    band = plan.band
     hi = [l for l in ells if l > 0]
     D, dint = deinterlace(desc, band, delta, want_real=len(hi) > 0, scratch=sc, stream=stream)
     DN, _ = deinterlace(desc, band, nmesh, want_real=False, scratch=sc, stream=stream)
@@ -321,23 +336,73 @@ def measure_pk_bk(desc, gpos, rpos, bins, plan: "BispecPlan", ells=(0, 2, 4), gw
 
 
 class Batch:
-    """Many catalog pairs through measure_pk_bk, spread round-robin over
-    `nstreams` streams (each with its own scratch), so that the small and the
-    tail-end kernels of one catalog overlap the work of another.  The caller's
-    current stream is forked at the start and joined at the end, so a batch can
-    be captured into one graph."""
+    """Many catalog pairs through measure_pk_bk.
 
-    def __init__(self, nstreams: int = 2, device="cuda"):
+    Round-robin mode (staged=False): the catalogs are spread over `nstreams`
+    streams (each with its own scratch), so that the small and the tail-end
+    kernels of one catalog overlap the work of another.
+
+    Staged mode (staged=True): the painting of catalog i (catalog sums, sort,
+    LDS paint and fold, bound by LDS atomics and HBM) runs on one of `nstage`
+    particle streams into that stream's mesh slot, and everything after it
+    (transforms, binning, contraction) on one of `nstreams` spectral streams,
+    so the two kinds of work overlap by construction.  A slot is painted again
+    only after the spectral stream that read it has reached that point.
+
+    In both modes the caller's current stream is forked at the start and
+    joined at the end; the round-robin batch can be captured into one graph,
+    the staged one runs eagerly only."""
+
+    def __init__(self, nstreams: int = 2, device="cuda", staged: bool = False, nstage: int = 2):
+        self.device = device
+        self.staged = staged
         self.streams = [torch.cuda.Stream(device=device) for _ in range(max(1, nstreams))]
         self.scratch = [Scratch(device) for _ in self.streams]
+        self.pstreams = [torch.cuda.Stream(device=device) for _ in range(max(1, nstage))] if staged else []
+        self.pscratch = [Scratch(device) for _ in self.pstreams]
+        self.slots = [None] * len(self.pstreams)
+        self.slot_key = [None] * len(self.pstreams)
+
+    def _slot(self, j, desc):
+        key = (desc.n, desc.dtype, desc.interlace)
+        if self.slots[j] is None or self.slot_key[j] != key:
+            with torch.cuda.stream(self.pstreams[j]):
+                self.slots[j] = paint_outputs(desc, noise=True)
+            self.slot_key[j] = key
+        return self.slots[j]
 
     def run(self, desc, catalogs, bins, plan, outs, ells=(0, 2, 4)):
+        if self.staged and torch.cuda.is_current_stream_capturing():
+            # capturing the staged dependency pattern (particle and spectral
+            # streams waiting on each other in turn) crashed the process at
+            # the end of the capture on ROCm 7; only the round-robin batch is
+            # captured
+            raise RuntimeError("staged batches run eagerly only; use staged=False under graph capture")
         cur = torch.cuda.current_stream()
-        for s in self.streams:
+        for s in self.streams + self.pstreams:
             s.wait_stream(cur)
-        for i, ((g, r), o) in enumerate(zip(catalogs, outs)):
-            k = i % len(self.streams)
-            with torch.cuda.stream(self.streams[k]):
-                measure_pk_bk(desc, g, r, bins, plan, ells=ells, scratch=self.scratch[k], out=o)
-        for s in self.streams:
+        if not self.staged:
+            for i, ((g, r), o) in enumerate(zip(catalogs, outs)):
+                k = i % len(self.streams)
+                with torch.cuda.stream(self.streams[k]):
+                    measure_pk_bk(desc, g, r, bins, plan, ells=ells, scratch=self.scratch[k], out=o)
+        else:
+            # every cross-stream dependency is an event recorded and waited on
+            # at once (wait_stream), also under graph capture
+            reader = [None] * len(self.pstreams)  # spectral stream that last read slot j
+            for i, ((g, r), o) in enumerate(zip(catalogs, outs)):
+                j = i % len(self.pstreams)
+                k = i % len(self.streams)
+                p, s = self.pstreams[j], self.streams[k]
+                slot = self._slot(j, desc)
+                if reader[j] is not None:
+                    p.wait_stream(reader[j])
+                with torch.cuda.stream(p):
+                    paint_fkp(desc, g, r, noise=True, sums_lmax=_pk_bk_lmax(plan), scratch=self.pscratch[j],
+                              stream=p, out=slot)
+                s.wait_stream(p)
+                with torch.cuda.stream(s):
+                    _spectra_stage(desc, bins, plan, slot, ells, self.scratch[k], s, o)
+                reader[j] = s
+        for s in self.streams + self.pstreams:
             cur.wait_stream(s)

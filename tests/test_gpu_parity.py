@@ -401,10 +401,16 @@ def test_measure_bk_reduced_grid_vs_oracle(est, ell, prec):
     assert rel(host(res["value"]), ora[key]) < tol
 
 
-@pytest.mark.parametrize("nstreams", [1, 3])
-def test_graph_replay_matches_eager(nstreams):
-    """The batch captured as one graph (catalogs spread over nstreams streams)
-    gives the eager single-stream results on every replay."""
+_STAGED_SKIP = pytest.mark.skip(reason="capturing a staged batch crashed the process at the end of the "
+                                        "capture; Batch.run now refuses staged batches under capture")
+
+
+@pytest.mark.parametrize("nstreams,staged", [(1, False), (3, False), pytest.param(2, True, marks=_STAGED_SKIP),
+                                             pytest.param(1, True, marks=_STAGED_SKIP)])
+def test_graph_replay_matches_eager(nstreams, staged):
+    """The batch captured as one graph (catalogs spread over nstreams streams,
+    or painting and spectra on separate streams) gives the eager single-stream
+    results on every replay."""
     n, box = 32, 1000.0
     bins = cn.kbins(0.0, 0.012, 4)
     d = cn.mesh_desc(n, box, assign=L.TSC, interlace=True, dtype=L.F32, observer=OBS)
@@ -416,7 +422,7 @@ def test_graph_replay_matches_eager(nstreams):
              "bk": torch.empty((3, plan.nconf), dtype=torch.float64, device="cuda")} for _ in cats]
     for (g, r), o in zip(cats, outs):
         pl.measure_pk_bk(d, g, r, bins, plan, scratch=sc, out=o)
-    batch = pl.Batch(nstreams)
+    batch = pl.Batch(nstreams, staged=staged)
 
     def step():
         batch.run(d, cats, bins, plan, outs)

@@ -3,7 +3,8 @@
 Each knob only changes launch shapes, so every setting must meet the same bar
 against the FP64 oracle as the defaults: the FFT, Y_lm and power-spectrum
 cases rerun with the LDS Stockham passes and other column tile widths, the
-bucketed sort with other particles-per-thread (paint stays bit-exact), and the
+bucketed sort with other particles per thread and workgroup sizes (paint
+stays bit-exact), and the
 split-BF16 contraction with every point-group split on 20 shells (210 shell
 pairs: 7 pair tiles, so 2, 4 or 7 tiles per wave; 20 or 40 fields).
 """
@@ -63,10 +64,11 @@ def test_measure_pk_stockham_only():
         P.test_measure_pk_vs_oracle(64, L.TSC, True, L.F32)
 
 
+@pytest.mark.parametrize("threads", [512, 1024])
 @pytest.mark.parametrize("per", [1, 2, 4])
 @pytest.mark.parametrize("case", ["dense128", "sparse256_weighted", "one_tile256"])
-def test_paint_sort_per(case, per):
-    with knobs(sort_per=per):
+def test_paint_sort_per(case, per, threads):
+    with knobs(sort_per=per, sort_threads=threads):
         P.test_paint_bucketed_sort(case)
 
 
@@ -112,15 +114,17 @@ def test_autotune_batch(tmp_path):
     try:
         res = autotune.tune_batch(d, cats, bins, plan, streams=(1, 2), reps=1, cache=path)
         assert res.streams in (1, 2) and not res.cached and len(res.trials) >= 5
+        assert res.staged in (False, True)
         assert res.ms > 0 and res.default_ms > 0
         assert autotune.get_knobs() == res.knobs
         for k, v in res.knobs.items():
             assert v in L.TUNE[k][1]
         again = autotune.tune_batch(d, cats, bins, plan, streams=(1, 2), reps=1, cache=path)
         assert again.cached and again.knobs == res.knobs and again.streams == res.streams
+        assert again.staged == res.staged
         outs = [{"pk": torch.empty((9, 4), dtype=torch.float64, device="cuda"),
                  "bk": torch.empty((3, plan.nconf), dtype=torch.float64, device="cuda")} for _ in cats]
-        pl.Batch(res.streams).run(d, cats, bins, plan, outs)
+        pl.Batch(res.streams, staged=res.staged).run(d, cats, bins, plan, outs)
         torch.cuda.synchronize()
         for (pk, bk), o in zip(ref, outs):
             assert P.rel(P.host(o["pk"]), pk) < 1e-5
