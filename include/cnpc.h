@@ -319,13 +319,15 @@ cnpc_status cnpc_ktimer_stop(double* ms_per_class, int64_t* launches_per_class);
  *                          (power of two 1..64).
  *   CNPC_TUNE_CONTRACT_KG  point groups per contraction workgroup (1, 2, 4).
  *   CNPC_TUNE_SORT_PER     particles per thread of the sort scatter (1, 2, 4).
+ *   CNPC_TUNE_SORT_THREADS threads per sort-scatter workgroup (512, 1024).
  * cnpc_tune_set rejects unknown knobs and values outside those ranges;
  * cnpc_tune_get returns the current value (-1 for an unknown knob). */
 #define CNPC_TUNE_FFT_PASSES 0
 #define CNPC_TUNE_FFT_COL_W 1
 #define CNPC_TUNE_CONTRACT_KG 2
 #define CNPC_TUNE_SORT_PER 3
-#define CNPC_TUNE_COUNT 4
+#define CNPC_TUNE_SORT_THREADS 4
+#define CNPC_TUNE_COUNT 5
 cnpc_status cnpc_tune_set(int32_t knob, int32_t value);
 int32_t cnpc_tune_get(int32_t knob);
 

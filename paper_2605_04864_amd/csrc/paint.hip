@@ -297,14 +297,12 @@ __global__ void __launch_bounds__(1024) k_tile_scan(const uint32_t* __restrict__
   });
 }
 
-constexpr int PART_THREADS = 1024;
-
-// Size in bytes of the LDS layout of k_partition.
-__host__ __device__ constexpr size_t partition_lds(int per, int rs, int rcap) {
-  return (size_t)PART_THREADS * per * (rs * 4 + 2) + (size_t)3 * rcap * 4 + 64;
+// Size in bytes of the LDS layout of k_partition with nt threads.
+__host__ __device__ constexpr size_t partition_lds(int per, int rs, int rcap, int nt) {
+  return (size_t)nt * per * (rs * 4 + 2) + (size_t)3 * rcap * 4 + 64;
 }
 
-// One counting-sort step over a chunk of PART_THREADS * PER particles.
+// One counting-sort step over a chunk of NT * PER particles.
 // SOA: input is the catalog (pos [3][n], optional w), else records.
 // FINE == false: key = bucket (rcap = number of buckets).
 // FINE == true, SOA: key = tile key (rcap = number of tiles, one bucket).
@@ -312,14 +310,14 @@ __host__ __device__ constexpr size_t partition_lds(int per, int rs, int rcap) {
 // in [bucket(first) S^3, (bucket(last) + 1) S^3); if that range is wider than
 // rcap the chunk takes one global atomic per particle instead.
 // cursor[key] hands out output slots (initialised to the key's start).
-template <bool SOA, bool FINE, int RS, int PER>
-__global__ void __launch_bounds__(PART_THREADS) k_partition(const uint32_t* __restrict__ pos,
+template <bool SOA, bool FINE, int RS, int PER, int NT>
+__global__ void __launch_bounds__(NT) k_partition(const uint32_t* __restrict__ pos,
                                                             const float* __restrict__ w,
                                                             const Rec<RS>* __restrict__ rin,
                                                             int64_t n, TileGeom g, int rcap,
                                                             uint32_t* __restrict__ cursor,
                                                             Rec<RS>* __restrict__ rout) {
-  constexpr int CH = PART_THREADS * PER;
+  constexpr int CH = NT * PER;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   Rec<RS>* stage = reinterpret_cast<Rec<RS>*>(smem_raw);                        // [CH]
   uint16_t* skey = reinterpret_cast<uint16_t*>(smem_raw + (size_t)CH * RS * 4);  // [CH]
@@ -343,7 +341,7 @@ __global__ void __launch_bounds__(PART_THREADS) k_partition(const uint32_t* __re
   int key[PER];
 #pragma unroll
   for (int k = 0; k < PER; ++k) {
-    const int64_t i = c0 + (int64_t)k * PART_THREADS + threadIdx.x;
+    const int64_t i = c0 + (int64_t)k * NT + threadIdx.x;
     key[k] = -1;
     if (i < n) {
       if (!SOA) {
@@ -365,14 +363,14 @@ __global__ void __launch_bounds__(PART_THREADS) k_partition(const uint32_t* __re
       if (key[k] >= 0) rout[atomicAdd(&cursor[klo + key[k]], 1u)] = r[k];
     return;
   }
-  for (int t = threadIdx.x; t < R; t += PART_THREADS) hist[t] = 0u;
+  for (int t = threadIdx.x; t < R; t += NT) hist[t] = 0u;
   __syncthreads();
   uint32_t rank[PER];
 #pragma unroll
   for (int k = 0; k < PER; ++k)
     if (key[k] >= 0) rank[k] = atomicAdd(&hist[key[k]], 1u);
   __syncthreads();
-  block_exclusive_scan<PART_THREADS>(hist, R, wsum, [&](int t, uint32_t v) {
+  block_exclusive_scan<NT>(hist, R, wsum, [&](int t, uint32_t v) {
     lstart[t] = v;
     const uint32_t c = hist[t];
     gbase[t] = c ? atomicAdd(&cursor[klo + t], c) : 0u;
@@ -387,7 +385,7 @@ __global__ void __launch_bounds__(PART_THREADS) k_partition(const uint32_t* __re
     }
   __syncthreads();
   const int cnt = (int)min((int64_t)CH, n - c0);
-  for (int j = threadIdx.x; j < cnt; j += PART_THREADS) {
+  for (int j = threadIdx.x; j < cnt; j += NT) {
     const int kk = skey[j];
     rout[gbase[kk] + (j - lstart[kk])] = stage[j];
   }
@@ -845,42 +843,54 @@ __global__ void k_zero_u32(uint32_t* p, int64_t n) {
 
 constexpr int FINE_RCAP = 512;  // LDS key range of the second sort step
 
-// Particles per thread: the tuned value when its LDS layout fits, else the
-// largest (4, 2, 1) whose layout lets two workgroups share a CU, else the
-// largest that fits one.
-static int partition_per(int rs, int rcap) {
+// Particles per thread for nt-thread workgroups: the tuned value when its LDS
+// layout fits, else the largest (4, 2, 1) whose layout lets 32 waves' worth
+// of workgroups share a CU, else the largest that fits one.
+static int partition_per(int rs, int rcap, int nt) {
   const size_t lim = lds_limit();
   const int tp = tune_value(CNPC_TUNE_SORT_PER);
-  if (tp > 0 && partition_lds(tp, rs, rcap) <= lim) return tp;
+  if (tp > 0 && partition_lds(tp, rs, rcap, nt) <= lim) return tp;
+  const size_t wgs = (size_t)(2048 / nt);
   for (int per = 4; per >= 1; per >>= 1)
-    if (2 * partition_lds(per, rs, rcap) <= lim) return per;
+    if (wgs * partition_lds(per, rs, rcap, nt) <= lim) return per;
   for (int per = 4; per >= 1; per >>= 1)
-    if (partition_lds(per, rs, rcap) <= lim) return per;
+    if (partition_lds(per, rs, rcap, nt) <= lim) return per;
   return 0;
+}
+
+template <bool SOA, bool FINE, int RS, int NT>
+static void launch_partition_nt(int per, unsigned nblk, size_t lds, const uint32_t* pos, const float* w,
+                                const Rec<RS>* rin, int64_t n, const TileGeom& g, int rcap, uint32_t* cursor,
+                                Rec<RS>* rout, hipStream_t s) {
+  if (per == 4)
+    hipLaunchKernelGGL((k_partition<SOA, FINE, RS, 4, NT>), dim3(nblk), dim3(NT), lds, s, pos, w, rin, n, g,
+                       rcap, cursor, rout);
+  else if (per == 2)
+    hipLaunchKernelGGL((k_partition<SOA, FINE, RS, 2, NT>), dim3(nblk), dim3(NT), lds, s, pos, w, rin, n, g,
+                       rcap, cursor, rout);
+  else
+    hipLaunchKernelGGL((k_partition<SOA, FINE, RS, 1, NT>), dim3(nblk), dim3(NT), lds, s, pos, w, rin, n, g,
+                       rcap, cursor, rout);
 }
 
 template <bool SOA, bool FINE, int RS>
 static cnpc_status launch_partition(const uint32_t* pos, const float* w, const Rec<RS>* rin, int64_t n,
                                     const TileGeom& g, int rcap, uint32_t* cursor, Rec<RS>* rout,
                                     hipStream_t s) {
-  const int per = partition_per(RS, rcap);
+  const int nt = tune_value(CNPC_TUNE_SORT_THREADS) == 512 ? 512 : 1024;
+  const int per = partition_per(RS, rcap, nt);
   if (per == 0) {
     set_error("sort: %d keys do not fit the LDS of a workgroup", rcap);
     return CNPC_EINVAL;
   }
-  const int64_t ch = (int64_t)PART_THREADS * per;
+  const int64_t ch = (int64_t)nt * per;
   const unsigned nblk = (unsigned)((n + ch - 1) / ch);
-  const size_t lds = partition_lds(per, RS, rcap);
+  const size_t lds = partition_lds(per, RS, rcap, nt);
   kt_begin(CNPC_KT_SORT, s);
-  if (per == 4)
-    hipLaunchKernelGGL((k_partition<SOA, FINE, RS, 4>), dim3(nblk), dim3(PART_THREADS), lds, s, pos, w, rin,
-                       n, g, rcap, cursor, rout);
-  else if (per == 2)
-    hipLaunchKernelGGL((k_partition<SOA, FINE, RS, 2>), dim3(nblk), dim3(PART_THREADS), lds, s, pos, w, rin,
-                       n, g, rcap, cursor, rout);
+  if (nt == 512)
+    launch_partition_nt<SOA, FINE, RS, 512>(per, nblk, lds, pos, w, rin, n, g, rcap, cursor, rout, s);
   else
-    hipLaunchKernelGGL((k_partition<SOA, FINE, RS, 1>), dim3(nblk), dim3(PART_THREADS), lds, s, pos, w, rin,
-                       n, g, rcap, cursor, rout);
+    launch_partition_nt<SOA, FINE, RS, 1024>(per, nblk, lds, pos, w, rin, n, g, rcap, cursor, rout, s);
   kt_end(CNPC_KT_SORT, s);
   CNPC_HIP(hipGetLastError());
   return CNPC_OK;
