@@ -42,9 +42,11 @@ class CnpcError(RuntimeError):
 
 
 def _load():
-    if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is missing: build it with python -m paper_2605_04864_amd.build")
-    return C.CDLL(LIB_PATH)
+    # CNPC_LIBRARY selects another build of the library (e.g. to compare two builds)
+    path = os.environ.get("CNPC_LIBRARY") or LIB_PATH
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with python -m paper_2605_04864_amd.build")
+    return C.CDLL(path)
 
 
 lib = _load()

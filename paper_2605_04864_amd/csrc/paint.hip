@@ -41,6 +41,9 @@ struct Rec {
   uint32_t v[RS];
 };
 
+// catalog positions read once by the sums pass: non-temporal loads
+__device__ __forceinline__ uint32_t ld_stream(const uint32_t* p) { return __builtin_nontemporal_load(p); }
+
 __device__ __forceinline__ int key_of(int tx, int ty, int tz, const TileGeom& g) {
   const int m = (1 << g.ls) - 1;
   const int b = ((((tx >> g.ls) << g.lnb) | (ty >> g.ls)) << g.lnb) | (tz >> g.ls);
@@ -150,9 +153,9 @@ __global__ void __launch_bounds__(SUMS_THREADS) k_catalog_sums(const uint32_t* _
       px[u] = py[u] = pz[u] = 0u;
       wv[u] = 1.0f;
       if (i < n) {
-        px[u] = pos[i];
-        py[u] = pos[n + i];
-        pz[u] = pos[2 * n + i];
+        px[u] = ld_stream(pos + i);
+        py[u] = ld_stream(pos + n + i);
+        pz[u] = ld_stream(pos + 2 * n + i);
         if (w) wv[u] = w[i];
       }
     }
