@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--no-tune", action="store_true", help="library defaults, no autotuning")
     ap.add_argument("--staged", action="store_true",
                     help="painting and spectra on separate streams (with --no-tune)")
+    ap.add_argument("--balance", choices=["rr", "lpt", "mixed"], default="rr",
+                    help="placement of the catalogs on the streams (see pipeline.Batch.assignment)")
     ap.add_argument("--tune-mocks", type=int, default=16, help="mocks per autotuner trial batch")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (calibrates HBM counters)")
@@ -178,13 +180,14 @@ def main():
         tuning["batch_mocks"] = len(tcat)
         log(args, f"autotuned in {res.seconds:.1f}s: streams {res.streams}, staged {res.staged}, knobs {res.knobs}, "
                   f"{res.default_ms:.2f} -> {res.ms:.2f} ms per {len(tcat)} mocks")
-    batch = pl.Batch(nstreams, staged=staged)
+    batch = pl.Batch(nstreams, staged=staged, balance=args.balance)
 
     def step():
         batch.run(desc, gpu_mocks, bins, plan, outs)
 
     step()  # eager pass: plans, twiddles and scratch reach their final size
     torch.cuda.synchronize()
+    eager = [(o["pk"].clone(), o["bk"].clone()) for o in outs]
 
     ntot = int(np.sum(sizes[: args.mocks]) * 11)
     models = [class_model(int(sz), 10 * int(sz), band=plan.band, grid=plan.grid)
@@ -213,6 +216,12 @@ def main():
     wall = time.perf_counter() - w0
     step_ms = [evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)]
     ms_step = evs[0].elapsed_time(evs[-1]) / args.steps
+    # the timed replays recompute every output: they must match the eager pass
+    replay_err = 0.0
+    for (pk, bk), o in zip(eager, outs):
+        for a, b in ((o["pk"], pk), (o["bk"], bk)):
+            replay_err = max(replay_err, float((a - b).abs().max() / b.abs().max().clamp_min(1e-300)))
+    del eager
     value = args.mocks / (ms_step / 1e3)
     log(args, f"timed {args.steps} steps: {ms_step:.1f} ms/step (wall {wall:.2f}s)")
 
@@ -275,6 +284,7 @@ def main():
         "warmup": args.warmup,
         "ms_per_step": ms_step,
         "step_ms_median": float(np.median(step_ms)),
+        "timed_outputs_vs_eager": replay_err,
         "step_ms_min": float(np.min(step_ms)),
         "higher_is_better": True,
         "scaling": "weak",
@@ -283,6 +293,7 @@ def main():
         "graph": not args.no_graph,
         "streams": nstreams,
         "staged": staged,
+        "placement": args.balance,
         "tuning": tuning,
         "data": "synthetic lognormal mocks (seeded), resident in HBM",
         "config": {"workload": "64 uneven lognormal mocks (N_g 1e6-8e6 log-uniform, 10x randoms), "

@@ -42,6 +42,9 @@ class CnpcError(RuntimeError):
 
 
 def _load():
+    # torch first: its HIP runtime is then the one the library binds to, whatever
+    # the caller imported first (two runtimes in one process do not see the GPU)
+    import torch  # noqa: F401
     # CNPC_LIBRARY selects another build of the library (e.g. to compare two builds)
     path = os.environ.get("CNPC_LIBRARY") or LIB_PATH
     if not os.path.exists(path):

@@ -335,12 +335,40 @@ def _spectra_stage(desc, bins, plan, painted, ells, sc: Scratch, stream, out):
     return res
 
 
+def balanced_assignment(sizes: Sequence[int], nstreams: int, mixed: bool = False):
+    """Longest-first greedy placement: items by decreasing size (ties: index),
+    each on the stream with the smallest total so far (ties: lowest stream).
+    Returns (item, stream) pairs in launch order: placement order, or with
+    mixed=True the streams' lists interleaved with odd streams reversed
+    (smallest first), so that streams running side by side hold catalogs of
+    different sizes."""
+    load = [0] * nstreams
+    out = []
+    for i in sorted(range(len(sizes)), key=lambda c: (-sizes[c], c)):
+        k = min(range(nstreams), key=lambda q: (load[q], q))
+        load[k] += sizes[i]
+        out.append((i, k))
+    if not mixed:
+        return out
+    lists = [[i for i, q in out if q == k] for k in range(nstreams)]
+    for k in range(1, nstreams, 2):
+        lists[k].reverse()
+    mixed_out = []
+    for step in range(max((len(x) for x in lists), default=0)):
+        for k in range(nstreams):
+            if step < len(lists[k]):
+                mixed_out.append((lists[k][step], k))
+    return mixed_out
+
+
 class Batch:
     """Many catalog pairs through measure_pk_bk.
 
-    Round-robin mode (staged=False): the catalogs are spread over `nstreams`
+    Stream mode (staged=False): the catalogs are spread over `nstreams`
     streams (each with its own scratch), so that the small and the tail-end
-    kernels of one catalog overlap the work of another.
+    kernels of one catalog overlap the work of another; `balance` picks the
+    placement ("rr" round-robin, "lpt" or "mixed" by particle count, see
+    assignment).
 
     Staged mode (staged=True): the painting of catalog i (catalog sums, sort,
     LDS paint and fold, bound by LDS atomics and HBM) runs on one of `nstage`
@@ -353,15 +381,28 @@ class Batch:
     joined at the end; the round-robin batch can be captured into one graph,
     the staged one runs eagerly only."""
 
-    def __init__(self, nstreams: int = 2, device="cuda", staged: bool = False, nstage: int = 2):
+    def __init__(self, nstreams: int = 2, device="cuda", staged: bool = False, nstage: int = 2,
+                 balance: str = "rr"):
         self.device = device
         self.staged = staged
+        self.balance = balance
         self.streams = [torch.cuda.Stream(device=device) for _ in range(max(1, nstreams))]
         self.scratch = [Scratch(device) for _ in self.streams]
         self.pstreams = [torch.cuda.Stream(device=device) for _ in range(max(1, nstage))] if staged else []
         self.pscratch = [Scratch(device) for _ in self.pstreams]
         self.slots = [None] * len(self.pstreams)
         self.slot_key = [None] * len(self.pstreams)
+
+    def assignment(self, catalogs):
+        """(catalog, stream) pairs in launch order.  balance "rr": catalog i
+        on stream i mod nstreams; "lpt": by decreasing particle count, each on
+        the stream with the fewest particles so far; "mixed": the same
+        placement with odd streams running their catalogs smallest first."""
+        ns = len(self.streams)
+        if self.balance == "rr":
+            return [(i, i % ns) for i in range(len(catalogs))]
+        return balanced_assignment([int(g.shape[1]) + int(r.shape[1]) for g, r in catalogs], ns,
+                                   mixed=self.balance == "mixed")
 
     def _slot(self, j, desc):
         key = (desc.n, desc.dtype, desc.interlace)
@@ -382,8 +423,8 @@ class Batch:
         for s in self.streams + self.pstreams:
             s.wait_stream(cur)
         if not self.staged:
-            for i, ((g, r), o) in enumerate(zip(catalogs, outs)):
-                k = i % len(self.streams)
+            for i, k in self.assignment(catalogs):
+                (g, r), o = catalogs[i], outs[i]
                 with torch.cuda.stream(self.streams[k]):
                     measure_pk_bk(desc, g, r, bins, plan, ells=ells, scratch=self.scratch[k], out=o)
         else:

@@ -156,3 +156,24 @@ def test_autotune_cache_roundtrip(tmp_path):
     with open(path, "w") as f:
         f.write("{not json")
     assert at._cache_load(path)["entries"] == {}
+
+
+def test_balanced_stream_assignment():
+    from paper_2605_04864_amd.pipeline import balanced_assignment
+    import numpy as np
+    sizes = [int(x) for x in np.random.default_rng(3).integers(1_000_000, 8_000_000, 64)]
+    asg = balanced_assignment(sizes, 4)
+    assert sorted(i for i, _ in asg) == list(range(64))          # every catalog placed once
+    assert [sizes[i] for i, _ in asg] == sorted(sizes, reverse=True)  # largest first
+    load = [0] * 4
+    for i, k in asg:
+        load[k] += sizes[i]
+    assert max(load) - min(load) <= max(sizes)                    # greedy bound
+    assert (max(load) - min(load)) / (sum(load) / 4) < 0.02
+    assert balanced_assignment([5, 5, 5], 2) == [(0, 0), (1, 1), (2, 0)]  # deterministic ties
+    assert balanced_assignment([], 3) == []
+    mix = balanced_assignment(sizes, 4, mixed=True)
+    assert sorted(mix) == sorted(asg)                               # same placement
+    for k in range(4):
+        seq = [sizes[i] for i, q in mix if q == k]
+        assert seq == sorted(seq, reverse=(k % 2 == 0))             # odd streams smallest first
