@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--mocks", type=int, default=64)
     ap.add_argument("--precision", choices=["f32", "bf16x3"], default="bf16x3")
     ap.add_argument("--no-graph", action="store_true", help="launch eagerly instead of one hipGraph")
+    ap.add_argument("--graph-per-stream", action="store_true",
+                    help="one single-stream graph per stream instead of one multi-stream graph")
     ap.add_argument("--streams", type=int, default=0,
                     help="concurrent streams inside a step (0: the autotuner's choice, else 4)")
     ap.add_argument("--no-tune", action="store_true", help="library defaults, no autotuning")
@@ -195,7 +197,26 @@ def main():
     model = {k: float(np.sum([m[k] for m in models])) for k in models[0]}  # per step
 
     run = step
-    if not args.no_graph:
+    if args.graph_per_stream and not args.no_graph and not staged:
+        # one single-stream graph per stream, replayed side by side
+        graphs = []
+        for k, s in enumerate(batch.streams):
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=s):
+                batch.run_stream(k, desc, gpu_mocks, bins, plan, outs)
+            graphs.append(g)
+
+        def run():
+            cur = torch.cuda.current_stream()
+            for s in batch.streams:
+                s.wait_stream(cur)
+            for g, s in zip(graphs, batch.streams):
+                with torch.cuda.stream(s):
+                    g.replay()
+            for s in batch.streams:
+                cur.wait_stream(s)
+        log(args, f"captured {len(graphs)} single-stream graphs")
+    elif not args.no_graph:
         graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(graph):
             step()
@@ -290,7 +311,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32" if prec == L.PREC_F32 else "f32+bf16x3",
-        "graph": not args.no_graph,
+        "graph": "none" if args.no_graph else ("per-stream" if args.graph_per_stream else "one"),
         "streams": nstreams,
         "staged": staged,
         "placement": args.balance,

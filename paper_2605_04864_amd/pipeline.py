@@ -404,6 +404,14 @@ class Batch:
         return balanced_assignment([int(g.shape[1]) + int(r.shape[1]) for g, r in catalogs], ns,
                                    mixed=self.balance == "mixed")
 
+    def run_stream(self, k, desc, catalogs, bins, plan, outs, ells=(0, 2, 4)):
+        """The catalogs that the placement puts on stream k, on the caller's
+        current stream (used to capture one single-stream graph per stream)."""
+        for i, q in self.assignment(catalogs):
+            if q == k:
+                measure_pk_bk(desc, catalogs[i][0], catalogs[i][1], bins, plan, ells=ells,
+                              scratch=self.scratch[k], out=outs[i])
+
     def _slot(self, j, desc):
         key = (desc.n, desc.dtype, desc.interlace)
         if self.slots[j] is None or self.slot_key[j] != key:
