@@ -28,7 +28,7 @@ class MeshConfig:
 def fkp_spectra(gpos, gw, rpos, rw, cfg: MeshConfig, ells=(0, 2, 4), noise_ells=()):
     """Norms, W, and F_l of the FKP field (and of the N mesh for noise_ells)."""
     obs = cfg.observer
-    sbar_ells = sorted(set(ells) | set(noise_ells) | {0})
+    sbar_ells = sorted({l for l in set(ells) | set(noise_ells) | {0} if l % 2 == 0})
     norms = catalog_norms(gpos, gw, rpos, rw, cfg.boxsize, obs, sbar_ells, cfg.los)
     want_noise = len(noise_ells) > 0
     delta, nm = ms.paint_fkp(gpos, gw, rpos, rw, norms.alpha, cfg.nmesh, cfg.assign,
@@ -50,6 +50,9 @@ def measure_pk(gpos, gw, rpos, rw, cfg: MeshConfig, kmin, dk, nbins, ells=(0, 2,
     bins = sp.Bins(kmin, dk, nbins, cfg.boxsize, cfg.nmesh)
     out = {"norms": norms, "nmodes": bins.counts(), "k_eff": bins.k_eff()}
     for l in ells:
+        if l % 2:
+            out[f"P{l}_raw"] = out[f"P{l}"] = sp.pk_multipole_odd(F[0], F[l], l, bins, norms.I22)
+            continue
         raw, sub = sp.pk_multipole(F[0], F[l], l, bins, norms.I22, norms.N0)
         out[f"P{l}_raw"], out[f"P{l}"] = raw, sub
     if modified:
@@ -60,6 +63,22 @@ def measure_pk(gpos, gw, rpos, rw, cfg: MeshConfig, kmin, dk, nbins, ells=(0, 2,
             pp[(a, b)] = sub
         out["P4b"], out["P6b"], out["P8b"] = sp.modified_multipoles(
             out["P0"], out["P2"], out["P4"], pp[(2, 2)], pp[(4, 2)], pp[(4, 4)])
+    return out
+
+
+def measure_pk_cross(gA, wA, rA, wrA, gB, wB, rB, wrB, cfg: MeshConfig, kmin, dk, nbins, ells=(0, 2, 4)):
+    """Cross multipoles of two tracers A and B (each with its own randoms):
+    (2l+1)/I22^AB <F_0^A F_l^B*> per bin, the real part for even l and the
+    imaginary part for odd l, with I22^AB = sqrt(I22^A I22^B) and no shot
+    noise (distinct samples share no galaxy)."""
+    nA, _, FA, _ = fkp_spectra(gA, wA, rA, wrA, cfg, (0,))
+    nB, _, FB, _ = fkp_spectra(gB, wB, rB, wrB, cfg, ells)
+    I22 = float(np.sqrt(nA.I22 * nB.I22))
+    bins = sp.Bins(kmin, dk, nbins, cfg.boxsize, cfg.nmesh)
+    out = {"I22": I22, "nmodes": bins.counts()}
+    for l in ells:
+        part = sp.power_raw_imag if l % 2 else sp.power_raw
+        out[f"P{l}"] = (2 * l + 1) / I22 * part(FA[0], FB[l], bins)
     return out
 
 

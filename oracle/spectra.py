@@ -146,6 +146,17 @@ def power_raw(Fa, Fb, bins: Bins) -> np.ndarray:
     return bins.shell_mean(np.real(Fa * np.conj(Fb)))
 
 
+def power_raw_imag(Fa, Fb, bins: Bins) -> np.ndarray:
+    """<Im F_a F_b*> per bin."""
+    return bins.shell_mean(np.imag(Fa * np.conj(Fb)))
+
+
+def pk_multipole_odd(F0, Fl, ell, bins, I22):
+    """Odd l: eq. pk_final with the imaginary part taken in place of the real
+    part (the sentence after eq. pk_final); the shot noise is zero for l > 0."""
+    return (2 * ell + 1) / I22 * power_raw_imag(F0, Fl, bins)
+
+
 def pk_multipole(F0, Fl, ell, bins, I22, N0):
     """eq. Hand17: (raw, shot-subtracted)."""
     raw = (2 * ell + 1) / I22 * power_raw(F0, Fl, bins)

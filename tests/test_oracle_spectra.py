@@ -13,6 +13,11 @@
   of (2l+1) L_l(mu) P(k)(b + f mu^2)^2, whose ratios approach the Kaiser values.
 * Catalog norms: closed forms for unit weights.
 * Poisson: unclustered galaxies give a shot-subtracted P_0 consistent with zero.
+* Odd multipoles (imaginary part of eq. pk_final): F_1, F_3 equal the brute-
+  force Legendre-kernel DFT; the G_l route gives the same Im shell means; with
+  a global line of sight they vanish; F_l is anti-Hermitian for odd l.
+* Cross multipoles of two tracers: a tracer crossed with itself gives its auto
+  multipoles without shot noise; the l = 0 cross is symmetric in A, B.
 """
 
 import math
@@ -57,7 +62,7 @@ def test_F_ell_matches_bruteforce_legendre_dft():
     rhat = r / np.linalg.norm(r, axis=1)[:, None]
     nidx = ms.freq_index(n)
     kf = 2 * math.pi / L
-    for ell in (2, 4):
+    for ell in (1, 2, 3, 4):
         F = sp.yamamoto_F(delta, D, ell, L, obs, W)
         for k in [(1, 0, 0), (1, 2, -3), (-2, 3, 1), (3, -1, 2), (0, 0, 2)]:
             kv = np.array(k, float) * kf
@@ -262,3 +267,62 @@ def test_poisson_catalog_pk_consistent_with_shot_noise():
     z = out["P0"] / sigma
     assert np.all(np.abs(z[1:]) < 5.0)
     assert abs(np.mean(out["P0_raw"][2:]) / N0 - 1.0) < 0.05
+
+
+def test_odd_multipoles_G_route_and_global_los():
+    n, L = 16, 400.0
+    obs = np.array([-200.0, -210.0, -190.0])
+    delta = _random_field(n, 5)
+    D = np.fft.fftn(delta)
+    W = ms.compensation(n, ms.TSC)
+    bins = sp.Bins(0.0, 2 * math.pi / L * 1.5, 5, L, n)
+    F0 = sp.yamamoto_F(delta, D, 0, L, obs, W)
+    for ell in (1, 3):
+        F = sp.yamamoto_F(delta, D, ell, L, obs, W)
+        G = sp.calG(delta, D, ell, L, obs, W)
+        p_F = sp.power_raw_imag(F0, F, bins)
+        p_G = bins.shell_mean(np.imag(F0 * np.conj(G)))
+        assert np.max(np.abs(p_F)) > 0
+        assert np.allclose(p_F, p_G, rtol=1e-11, atol=1e-11 * np.max(np.abs(p_F)))
+        # the real part of the full-grid shell sum vanishes for odd l (anti-Hermitian F_l)
+        assert np.max(np.abs(sp.power_raw(F0, F, bins))) < 1e-11 * np.max(np.abs(p_F))
+        # global line of sight: F_l = D L_l(khat . n) / W, so F_0 F_l* is real
+        los = np.array([0.6, 0.0, 0.8])
+        Fg = sp.yamamoto_F(delta, D, ell, L, obs, W, los=los)
+        assert np.max(np.abs(sp.pk_multipole_odd(F0, Fg, ell, bins, 1.0))) < 1e-11 * np.max(np.abs(p_F))
+
+
+def test_odd_multipoles_from_catalog_pipeline():
+    """measure_pk returns P_1, P_3 as the imaginary-part estimator; they vanish
+    for a global line of sight and not for the local one."""
+    L, n = 1000.0, 32
+    g = synthcat.lognormal_catalog(20_000, L, 61)
+    r = synthcat.random_catalog(100_000, 62)
+    obs = synthcat.observer_position()
+    loc = measure_pk(g, None, r, None, MeshConfig(L, n, ms.TSC, True, obs), 0.0, 0.012, 6, ells=(0, 1, 3))
+    glob = measure_pk(g, None, r, None, MeshConfig(L, n, ms.TSC, True, obs, los=np.ones(3) / math.sqrt(3)),
+                      0.0, 0.012, 6, ells=(0, 1, 3))
+    scale = np.max(np.abs(loc["P0"]))
+    for l in (1, 3):
+        assert np.max(np.abs(glob[f"P{l}"])) < 1e-10 * scale
+        assert np.max(np.abs(loc[f"P{l}"])) > 1e-6 * scale
+
+
+def test_cross_multipoles_self_and_symmetry():
+    from oracle.pipeline import measure_pk_cross
+    L, n = 1000.0, 32
+    cfg = MeshConfig(L, n, ms.TSC, True, synthcat.observer_position())
+    gA = synthcat.lognormal_catalog(15_000, L, 71)
+    rA = synthcat.random_catalog(80_000, 72)
+    gB = synthcat.lognormal_catalog(9_000, L, 73)
+    rB = synthcat.random_catalog(60_000, 74)
+    ells = (0, 1, 2, 3, 4)
+    auto = measure_pk(gA, None, rA, None, cfg, 0.0, 0.012, 6, ells=ells)
+    self_cross = measure_pk_cross(gA, None, rA, None, gA, None, rA, None, cfg, 0.0, 0.012, 6, ells=ells)
+    for l in ells:
+        assert np.allclose(self_cross[f"P{l}"], auto[f"P{l}_raw"], rtol=1e-12, atol=0), l
+    ab = measure_pk_cross(gA, None, rA, None, gB, None, rB, None, cfg, 0.0, 0.012, 6, ells=(0,))
+    ba = measure_pk_cross(gB, None, rB, None, gA, None, rA, None, cfg, 0.0, 0.012, 6, ells=(0,))
+    assert np.allclose(ab["P0"], ba["P0"], rtol=1e-12)
+    assert np.isclose(ab["I22"], math.sqrt(auto["norms"].I22 *
+                                           measure_pk(gB, None, rB, None, cfg, 0.0, 0.012, 6, ells=(0,))["norms"].I22))
