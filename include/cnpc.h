@@ -223,6 +223,28 @@ cnpc_status cnpc_bin_pk(const cnpc_mesh_desc* desc, const cnpc_kbins* bins, int3
                         double* means, double* selfterm, int64_t* nmodes, double* keff,
                         void* ws, size_t ws_bytes, void* stream);
 
+/* Shell means of Im F_a(k) F_b(k)^* (odd multipoles: the imaginary-part form
+ * of eq. pk_final).  Same arguments, limits and workspace as cnpc_bin_pk with
+ * no self terms; for anti-Hermitian products (F_0 F_l^*, l odd) the half-grid
+ * weights apply unchanged. */
+cnpc_status cnpc_bin_pk_im(const cnpc_mesh_desc* desc, const cnpc_kbins* bins, int32_t band,
+                           int32_t npairs, const void* const* pa, const void* const* pb,
+                           double* means, int64_t* nmodes, double* keff, void* ws, size_t ws_bytes,
+                           void* stream);
+
+/* One multipole from its shell mean: out = (2l+1) mean / I22 - delta_l0 N0
+ * (eq. Hand17; odd l with the Im mean of cnpc_bin_pk_im; no shot noise for
+ * l > 0).  l in [0, 8]; mean, norms, out device, nbins values. */
+cnpc_status cnpc_pk_multipole(const cnpc_kbins* bins, int32_t ell, const double* mean,
+                              const double* norms, double* out, void* stream);
+
+/* Normalisations of the cross multipoles of two tracers A, B (auto and cross
+ * spectra of several tracers): the norms of A with I22 = sqrt(I22_A I22_B)
+ * and N0 = 0 (distinct samples share no galaxy).  All device, CNPC_NORMS_LEN
+ * doubles. */
+cnpc_status cnpc_cross_norms(const double* norms_a, const double* norms_b, double* norms_out,
+                             void* stream);
+
 /* Yamamoto multipoles from the shell means (eq. Hand17 / eq. Pllp / eq. Plnew):
  * P_l = (2l+1)/I22 <Re F_0 F_l*> - delta_l0 N0, P_ll' = (2(l+l')+1)/I22
  * <Re F_l F_l'*> - N_ll' (N_22 = 9 N0/5, N_44 = 17 N0/9, N_42 = 0), and

@@ -93,6 +93,10 @@ _PROTOS = {
     "cnpc_bispectrum": (_i32, [_vp, _cvp, _cvp, _cvp, _cvp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "cnpc_ktimer_start": (_i32, [C.c_uint32, _i32]),
     "cnpc_ktimer_stop": (_i32, [C.POINTER(_d), C.POINTER(_i64)]),
+    "cnpc_bin_pk_im": (_i32, [_PD, _PB, _i32, _i32, C.POINTER(_vp), C.POINTER(_vp), _vp, _vp, _vp, _vp,
+                              _sz, _vp]),
+    "cnpc_pk_multipole": (_i32, [_PB, _i32, _vp, _vp, _vp, _vp]),
+    "cnpc_cross_norms": (_i32, [_vp, _vp, _vp, _vp]),
     "cnpc_tune_set": (_i32, [_i32, _i32]),
     "cnpc_tune_get": (_i32, [_i32]),
 }

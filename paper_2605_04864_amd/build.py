@@ -1,6 +1,7 @@
 """Build libcnpc.so (all HIP kernels + the C ABI) for gfx950 with hipcc.
 
-Usage: python -m paper_2605_04864_amd.build [--jobs J]
+Usage: python paper_2605_04864_amd/build.py [--jobs J] (as a script: importing the
+package needs a library that exports every declared call)
 The library is written next to this file (in-tree), objects go to _build/.
 """
 

@@ -352,11 +352,11 @@ size_t cnpc_bin_pk_workspace_size(const cnpc_kbins* b, int32_t npairs, int32_t n
   return bin_ws_doubles(b->nbins, npairs, nself) * sizeof(double);
 }
 
-cnpc_status cnpc_bin_pk(const cnpc_mesh_desc* d, const cnpc_kbins* b, int32_t band, int32_t npairs,
-                        const void* const* pa, const void* const* pb, int32_t nself,
-                        const int32_t* self_ells, const double* norms, double* means, double* selfterm,
-                        int64_t* nmodes, double* keff, void* ws, size_t ws_bytes, void* stream) {
-  API_BEGIN;
+static cnpc_status bin_pk_common(const cnpc_mesh_desc* d, const cnpc_kbins* b, int32_t band, int32_t npairs,
+                                 const void* const* pa, const void* const* pb, uint32_t imag, int32_t nself,
+                                 const int32_t* self_ells, const double* norms, double* means,
+                                 double* selfterm, int64_t* nmodes, double* keff, void* ws, size_t ws_bytes,
+                                 void* stream) {
   CNPC_TRY(check_desc(d));
   CNPC_TRY(check_bins(d, b));
   CNPC_REQUIRE(band >= 1, "band must be >= 1");
@@ -382,8 +382,41 @@ cnpc_status cnpc_bin_pk(const cnpc_mesh_desc* d, const cnpc_kbins* b, int32_t ba
   }
   int64_t thr[MAX_BINS + 1];
   bin_thresholds(d, b, thr);
-  return launch_bin(d, thr, b->nbins, band, npairs, pa, pb, nself, self_ells, norms, (double*)ws, means,
+  return launch_bin(d, thr, b->nbins, band, npairs, pa, pb, imag, nself, self_ells, norms, (double*)ws, means,
                     selfterm, nmodes, keff, as_stream(stream));
+}
+
+cnpc_status cnpc_bin_pk(const cnpc_mesh_desc* d, const cnpc_kbins* b, int32_t band, int32_t npairs,
+                        const void* const* pa, const void* const* pb, int32_t nself,
+                        const int32_t* self_ells, const double* norms, double* means, double* selfterm,
+                        int64_t* nmodes, double* keff, void* ws, size_t ws_bytes, void* stream) {
+  API_BEGIN;
+  return bin_pk_common(d, b, band, npairs, pa, pb, 0u, nself, self_ells, norms, means, selfterm, nmodes, keff,
+                       ws, ws_bytes, stream);
+}
+
+cnpc_status cnpc_bin_pk_im(const cnpc_mesh_desc* d, const cnpc_kbins* b, int32_t band, int32_t npairs,
+                           const void* const* pa, const void* const* pb, double* means, int64_t* nmodes,
+                           double* keff, void* ws, size_t ws_bytes, void* stream) {
+  API_BEGIN;
+  const uint32_t all = npairs >= 32 ? 0xffffffffu : ((1u << (npairs > 0 ? npairs : 0)) - 1u);
+  return bin_pk_common(d, b, band, npairs, pa, pb, all, 0, nullptr, nullptr, means, nullptr, nmodes, keff,
+                       ws, ws_bytes, stream);
+}
+
+cnpc_status cnpc_pk_multipole(const cnpc_kbins* b, int32_t ell, const double* mean, const double* norms,
+                              double* out, void* stream) {
+  API_BEGIN;
+  CNPC_REQUIRE(b && b->nbins >= 1 && b->nbins <= MAX_BINS, "bad bins");
+  CNPC_REQUIRE(ell >= 0 && ell <= 8, "ell must be in [0, 8]");
+  CNPC_REQUIRE(mean && norms && out, "null pointer argument");
+  return launch_pk_multipole(b->nbins, ell, mean, norms, out, as_stream(stream));
+}
+
+cnpc_status cnpc_cross_norms(const double* norms_a, const double* norms_b, double* norms_out, void* stream) {
+  API_BEGIN;
+  CNPC_REQUIRE(norms_a && norms_b && norms_out, "null pointer argument");
+  return launch_cross_norms(norms_a, norms_b, norms_out, as_stream(stream));
 }
 
 cnpc_status cnpc_pk_finalize(const cnpc_kbins* b, const double* m00, const double* m02, const double* m04,

@@ -19,6 +19,7 @@ struct BinArgs {
   int64_t thr[MAX_BINS + 1];
   const cx<T>* pa[MAX_PAIRS];
   const cx<T>* pb[MAX_PAIRS];
+  uint32_t imag;  // bit q: pair q accumulates Im F_a F_b^* instead of Re
 };
 
 template <typename T>
@@ -37,9 +38,12 @@ cnpc_status launch_assemble(const cnpc_mesh_desc* d, int band, int ell, const vo
                             const void* ylm, void* F, hipStream_t s);
 size_t bin_ws_doubles(int nbins, int npairs, int nself);
 cnpc_status launch_bin(const cnpc_mesh_desc* d, const int64_t* thr, int nbins, int band, int npairs,
-                       const void* const* pa, const void* const* pb, int nself,
+                       const void* const* pa, const void* const* pb, uint32_t imag, int nself,
                        const int32_t* self_ells, const double* norms, double* acc, double* means,
                        double* selfterm, int64_t* nmodes, double* keff, hipStream_t s);
+cnpc_status launch_pk_multipole(int nbins, int ell, const double* mean, const double* norms, double* out,
+                                hipStream_t s);
+cnpc_status launch_cross_norms(const double* na, const double* nb, double* out, hipStream_t s);
 cnpc_status launch_pk_finalize(int nbins, const double* m00, const double* m02, const double* m04,
                                const double* m22, const double* m42, const double* m44,
                                const double* norms, double* out, hipStream_t s);

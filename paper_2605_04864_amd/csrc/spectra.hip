@@ -630,7 +630,12 @@ __global__ void __launch_bounds__(256) k_bin(BinArgs<T> a, const double* __restr
     double* ab = acc + b * nacc;
     for (int q = 0; q < a.npairs; ++q) {
       const cx<T> fa = a.pa[q][i], fb = a.pb[q][i];
-      atomicAdd(&ab[q], wgt * ((double)fa.x * (double)fb.x + (double)fa.y * (double)fb.y));
+      // Re or Im of F_a F_b^*; for an anti-Hermitian product (odd l) the
+      // k and -k halves carry the same imaginary part, so the half-grid
+      // weights apply to both
+      const double v = ((a.imag >> q) & 1u) ? (double)fa.y * (double)fb.x - (double)fa.x * (double)fb.y
+                                            : (double)fa.x * (double)fb.x + (double)fa.y * (double)fb.y;
+      atomicAdd(&ab[q], wgt * v);
     }
     if (a.nself) {
       const double kn = sqrt((double)n2);
@@ -698,7 +703,7 @@ size_t bin_ws_doubles(int nbins, int npairs, int nself) {
 
 template <typename T>
 static cnpc_status bin_t(const cnpc_mesh_desc* d, const int64_t* thr, int nbins, int band,
-                         int npairs, const void* const* pa, const void* const* pb, int nself,
+                         int npairs, const void* const* pa, const void* const* pb, uint32_t imag, int nself,
                          const int32_t* self_ells, const double* norms, double* acc, double* means,
                          double* selfterm, int64_t* nmodes, double* keff, hipStream_t s) {
   BinArgs<T> a;
@@ -709,6 +714,7 @@ static cnpc_status bin_t(const cnpc_mesh_desc* d, const int64_t* thr, int nbins,
   a.nbins = nbins;
   a.npairs = npairs;
   a.nself = nself;
+  a.imag = imag;
   for (int b = 0; b <= nbins; ++b) a.thr[b] = thr[b];
   for (int q = 0; q < npairs; ++q) {
     a.pa[q] = (const cx<T>*)pa[q];
@@ -736,13 +742,13 @@ static cnpc_status bin_t(const cnpc_mesh_desc* d, const int64_t* thr, int nbins,
 }
 
 cnpc_status launch_bin(const cnpc_mesh_desc* d, const int64_t* thr, int nbins, int band, int npairs,
-                       const void* const* pa, const void* const* pb, int nself,
+                       const void* const* pa, const void* const* pb, uint32_t imag, int nself,
                        const int32_t* self_ells, const double* norms, double* acc, double* means,
                        double* selfterm, int64_t* nmodes, double* keff, hipStream_t s) {
   if (d->dtype == CNPC_F64)
-    return bin_t<double>(d, thr, nbins, band, npairs, pa, pb, nself, self_ells, norms, acc, means,
+    return bin_t<double>(d, thr, nbins, band, npairs, pa, pb, imag, nself, self_ells, norms, acc, means,
                          selfterm, nmodes, keff, s);
-  return bin_t<float>(d, thr, nbins, band, npairs, pa, pb, nself, self_ells, norms, acc, means,
+  return bin_t<float>(d, thr, nbins, band, npairs, pa, pb, imag, nself, self_ells, norms, acc, means,
                       selfterm, nmodes, keff, s);
 }
 
@@ -769,6 +775,39 @@ __global__ void k_pk_finalize(int nbins, const double* m00, const double* m02, c
     out[8 * nbins + b] = 1287.0 / 490.0 * P44 - 374.0 / 245.0 * P42 - 3553.0 / 15435.0 * P4 -
                          1326.0 / 8575.0 * P2 - 2431.0 / 490.0 * P0;
   }
+}
+
+// one multipole from its shell mean: (2l+1) mean / I22 - delta_l0 N0 (odd l:
+// the mean of Im F_0 F_l^*, no shot noise)
+__global__ void k_pk_multipole(int nbins, int ell, const double* __restrict__ mean,
+                               const double* __restrict__ nm, double* __restrict__ out) {
+  const double I22 = nm[CNPC_NORM_I22], N0 = ell == 0 ? nm[CNPC_NORM_N0] : 0.0;
+  for (int b = threadIdx.x; b < nbins; b += blockDim.x) out[b] = (2.0 * ell + 1.0) * mean[b] / I22 - N0;
+}
+
+cnpc_status launch_pk_multipole(int nbins, int ell, const double* mean, const double* norms, double* out,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(k_pk_multipole, dim3(1), dim3(128), 0, s, nbins, ell, mean, norms, out);
+  CNPC_HIP(hipGetLastError());
+  return CNPC_OK;
+}
+
+// normalisations of the cross spectrum of tracers A and B: those of A with
+// I22 = sqrt(I22_A I22_B) and N0 = 0 (distinct samples share no galaxy)
+__global__ void k_cross_norms(const double* __restrict__ na, const double* __restrict__ nb,
+                              double* __restrict__ out) {
+  for (int i = threadIdx.x; i < CNPC_NORMS_LEN; i += blockDim.x) out[i] = na[i];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    out[CNPC_NORM_I22] = sqrt(na[CNPC_NORM_I22] * nb[CNPC_NORM_I22]);
+    out[CNPC_NORM_N0] = 0.0;
+  }
+}
+
+cnpc_status launch_cross_norms(const double* na, const double* nb, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_cross_norms, dim3(1), dim3(64), 0, s, na, nb, out);
+  CNPC_HIP(hipGetLastError());
+  return CNPC_OK;
 }
 
 cnpc_status launch_pk_finalize(int nbins, const double* m00, const double* m02, const double* m04,

@@ -142,8 +142,12 @@ def assemble(desc, band, ell, spec0=None, ylm=None, stream=None):
 
 
 def bin_means(desc, bins, band, pairs, self_ells=(), norms=None, scratch: Optional[Scratch] = None,
-              stream=None):
+              stream=None, imag=False):
+    """Shell means of Re F_a F_b^* (imag=False) or Im F_a F_b^* (imag=True,
+    no self terms) for the (a, b) in pairs; self terms s_l; mode counts; k_eff."""
     sc = scratch or Scratch()
+    if imag and self_ells:
+        raise ValueError("self terms go with the real-part means")
     nb = bins.nbins
     npairs, nself = len(pairs), len(self_ells)
     means = _empty((max(npairs, 1), nb), torch.float64)
@@ -154,10 +158,29 @@ def bin_means(desc, bins, band, pairs, self_ells=(), norms=None, scratch: Option
     pb = (C.c_void_p * max(npairs, 1))(*[L.ptr(b) for _, b in pairs])
     se = (C.c_int32 * max(nself, 1))(*[int(l) for l in self_ells])
     ws = sc.get(L.lib.cnpc_bin_pk_workspace_size(C.byref(bins), npairs, nself))
-    L.check(L.lib.cnpc_bin_pk(C.byref(desc), C.byref(bins), band, npairs, pa, pb, nself, se,
-                              L.ptr(norms), L.ptr(means), L.ptr(selft), L.ptr(nmodes), L.ptr(keff),
-                              L.ptr(ws), ws.numel(), _sh(stream)))
+    if imag:
+        L.check(L.lib.cnpc_bin_pk_im(C.byref(desc), C.byref(bins), band, npairs, pa, pb, L.ptr(means),
+                                     L.ptr(nmodes), L.ptr(keff), L.ptr(ws), ws.numel(), _sh(stream)))
+    else:
+        L.check(L.lib.cnpc_bin_pk(C.byref(desc), C.byref(bins), band, npairs, pa, pb, nself, se,
+                                  L.ptr(norms), L.ptr(means), L.ptr(selft), L.ptr(nmodes), L.ptr(keff),
+                                  L.ptr(ws), ws.numel(), _sh(stream)))
     return means[:npairs], selft[:nself], nmodes, keff
+
+
+def pk_multipole(bins, ell, mean, norms, stream=None):
+    """(2l+1) mean / I22 - delta_l0 N0 for one shell-mean vector (device)."""
+    out = _empty(bins.nbins, torch.float64)
+    L.check(L.lib.cnpc_pk_multipole(C.byref(bins), int(ell), L.ptr(mean), L.ptr(norms), L.ptr(out),
+                                    _sh(stream)))
+    return out
+
+
+def cross_norms(norms_a, norms_b, stream=None):
+    """Normalisations of the cross multipoles of tracers A and B (device)."""
+    out = _empty(L.NORMS_LEN, torch.float64)
+    L.check(L.lib.cnpc_cross_norms(L.ptr(norms_a), L.ptr(norms_b), L.ptr(out), _sh(stream)))
+    return out
 
 
 def pk_finalize(bins, m, norms, stream=None):
@@ -173,7 +196,8 @@ PK_ROWS = ("P0", "P2", "P4", "P22", "P42", "P44", "P4b", "P6b", "P8b")
 
 def measure_pk(desc, gpos, rpos, bins, ells=(0, 2, 4), modified=False, gw=None, rw=None,
                scratch: Optional[Scratch] = None, stream=None) -> Dict[str, torch.Tensor]:
-    """Yamamoto P_l (and P_ll', P_4b, P_6b, P_8b when modified) of one catalog pair."""
+    """Yamamoto P_l (and P_ll', P_4b, P_6b, P_8b when modified) of one catalog pair.
+    Odd l in ells (1, 3) give the imaginary-part multipoles, with no shot noise."""
     sc = scratch or Scratch()
     norms, _, _ = catalog_norms(desc, gpos, rpos, gw, rw, sc, stream)
     delta, _ = paint(desc, gpos, rpos, norms, gw, rw, noise=False, scratch=sc, stream=stream)
@@ -188,6 +212,8 @@ def measure_pk(desc, gpos, rpos, bins, ells=(0, 2, 4), modified=False, gw=None, 
         ylm = ylm_spectra(desc, band, hi, dint, sc, stream)
         for l in hi:
             F[l] = assemble(desc, band, l, ylm=ylm[l], stream=stream)
+    odd = [l for l in ells if l % 2]
+    ells = [l for l in ells if l % 2 == 0]
     pairs, keys = [], []
     for l in ells:
         pairs.append((F[0], F[l]))
@@ -202,6 +228,51 @@ def measure_pk(desc, gpos, rpos, bins, ells=(0, 2, 4), modified=False, gw=None, 
     res = {"norms": norms, "nmodes": nmodes, "k_eff": keff, "band": band}
     for i, k in enumerate(PK_ROWS):
         res[k] = out[i]
+    if odd:
+        # odd multipoles: the imaginary part of the same shell average
+        mi, _, _, _ = bin_means(desc, bins, band, [(F[0], F[l]) for l in odd], (), norms, sc, stream, imag=True)
+        for i, l in enumerate(odd):
+            res[f"P{l}"] = pk_multipole(bins, l, mi[i], norms, stream)
+    return res
+
+
+def measure_pk_cross(desc, cat_a, cat_b, bins, ells=(0, 2, 4), scratch: Optional[Scratch] = None,
+                     stream=None) -> Dict[str, torch.Tensor]:
+    """Cross multipoles of two tracers A and B, each a (galaxies, randoms[,
+    galaxy weights, random weights]) tuple: (2l+1)/I22^AB <F_0^A F_l^B*>, the
+    real part for even l and the imaginary part for odd l, I22^AB = sqrt(I22^A
+    I22^B), no shot noise."""
+    sc = scratch or Scratch()
+    kmax = bins.kmin + bins.nbins * bins.dk
+    band = L.lib.cnpc_band_for(C.byref(desc), kmax)
+    F = {}
+    norms = {}
+    for tag, cat, want in (("a", cat_a, (0,)), ("b", cat_b, tuple(ells))):
+        g, r = cat[0], cat[1]
+        gw = cat[2] if len(cat) > 2 else None
+        rw = cat[3] if len(cat) > 3 else None
+        nm, _, _ = catalog_norms(desc, g, r, gw, rw, sc, stream)
+        delta, _ = paint(desc, g, r, nm, gw, rw, noise=False, scratch=sc, stream=stream)
+        hi = [l for l in want if l > 0]
+        D, dint = deinterlace(desc, band, delta, want_real=len(hi) > 0, scratch=sc, stream=stream)
+        del delta
+        F[(tag, 0)] = assemble(desc, band, 0, spec0=D, stream=stream)
+        if hi:
+            ylm = ylm_spectra(desc, band, hi, dint, sc, stream)
+            for l in hi:
+                F[(tag, l)] = assemble(desc, band, l, ylm=ylm[l], stream=stream)
+        norms[tag] = nm
+    nab = cross_norms(norms["a"], norms["b"], stream)
+    res = {"norms": nab}
+    for imag in (False, True):
+        sel = [l for l in ells if (l % 2 == 1) == imag]
+        if not sel:
+            continue
+        m, _, nmodes, keff = bin_means(desc, bins, band, [(F[("a", 0)], F[("b", l)]) for l in sel], (), nab,
+                                       sc, stream, imag=imag)
+        res["nmodes"], res["k_eff"] = nmodes, keff
+        for i, l in enumerate(sel):
+            res[f"P{l}"] = pk_multipole(bins, l, m[i], nab, stream)
     return res
 
 
