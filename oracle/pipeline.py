@@ -92,8 +92,10 @@ def noise_terms(F, FN, ell, bins_ext, norms, W, cfg):
 
 
 def measure_bk(gpos, gw, rpos, rw, cfg: MeshConfig, dk, nbins, ells=(0, 2),
-               scoccimarro=(0, 2), triposh=(0, 2)):
-    """Scoccimarro B_l and TripoSH BB_l0l with analytic shot noise (kmin = 0)."""
+               scoccimarro=(0, 2), triposh=(0, 2), fft_noise=False):
+    """Scoccimarro B_l and TripoSH BB_l0l with analytic shot noise (kmin = 0);
+    fft_noise adds BB_l0l with the FFT-method i = j != k term ("BBl0l_shot_fft",
+    "BBl0l_fft")."""
     norms, W, F, FN = fkp_spectra(gpos, gw, rpos, rw, cfg, ells, noise_ells=ells)
     bins = sp.Bins(0.0, dk, nbins, cfg.boxsize, cfg.nmesh)
     ext = sp.Bins(0.0, dk, 2 * nbins - 1, cfg.boxsize, cfg.nmesh)
@@ -118,4 +120,12 @@ def measure_bk(gpos, gw, rpos, rw, cfg: MeshConfig, dk, nbins, ells=(0, 2),
         out[f"BB{l}0{l}_pairs"] = pairs
         out[f"BB{l}0{l}_raw"], out[f"BB{l}0{l}_shot"] = raw, shot
         out[f"BB{l}0{l}"] = raw - shot
+        if fft_noise:
+            C = sn.c_shot(cfg.nmesh, cfg.assign, cfg.interlace)
+            s_modes = sn.self_term_modes(l, norms.Sbar_lm, cfg.nmesh, cfg.boxsize, W, C)
+            P = sn.noise_product(F[l], FN[0], s_modes)
+            T = sn.exact_pair_sums(P, bins, pairs)
+            sf = sn.triposh_shot_fft(l, pairs, T, H, bins.counts(), centres, norms.I33, norms.Sbar)
+            out[f"BB{l}0{l}_pairsum"] = T
+            out[f"BB{l}0{l}_shot_fft"], out[f"BB{l}0{l}_fft"] = sf, raw - sf
     return out

@@ -24,6 +24,16 @@ Readings where the paper defers or is garbled:
   N_l0l = 1/I33 { delta_l0 Sbar + (-1)^l (2l+1) [g_l(t) H_l(k_i) + g_l(1/t) H_l(k_j)]
                   + (2l+1) sum_c N_c Q_l(k_c)/k_c / sum_c N_c/k_c },
   c running over bins |i-j| .. i+j; the i=j=k term carries 1/I33.
+* FFT method for the i = j != k term of B_l0l (the two l = 0 legs share a
+  particle; section "Validation of the analytical method ...", the FFT
+  reference, applied to the new estimator as its shot-noise subsection
+  derives that term): no thin-shell step.  With the per-mode product
+      P(q) = F_l(q) N(q)^* - s_l(q)        (s_l(q): the summand of s_l above)
+  the term is (2l+1)/I33 * T(i, j) / (N_i N_j), where
+      T(i, j) = sum_{q1 in shell i, q2 in shell j} Re P(q1 + q2)
+  is the grid sum sum_x I_i(x) I_j(x) p(x) / N^3 of the shell indicator fields
+  and p = sum_q P(q) e^{iq.x}.  P(0) := 0 (F_l(0) = 0, so the q3 = 0 pairs
+  carry neither signal nor noise) and modes with a Nyquist component are zero.
 """
 
 from __future__ import annotations
@@ -33,7 +43,7 @@ import math
 import numpy as np
 from numpy.polynomial.legendre import leggauss
 
-from .mesh import freq_index
+from .mesh import freq_index, nyquist_mask
 from .spectra import Bins, kvectors
 from .ylm import legendre, ylm_racah
 
@@ -161,6 +171,52 @@ def triposh_shot(ell, pairs, Q_ext, H, counts_ext, centres_ext, I33, Sbar):
         cs = np.arange(abs(i - j), i + j + 1)
         wgt = counts_ext[cs] / centres_ext[cs]
         term += (2 * ell + 1) * float(np.sum(wgt * Q_ext[cs]) / np.sum(wgt))
+        if ell == 0:
+            term += Sbar
+        out[t] = term / I33
+    return out
+
+
+def self_term_modes(ell: int, Sbar_lm, nmesh: int, boxsize: float, W: np.ndarray,
+                    C: np.ndarray) -> np.ndarray:
+    """s_l(q) per mode: Re sum_m y_l^m(qhat) Sbar_l^m C(q) / W(q)^2; 0 at q = 0."""
+    kvec = kvectors(nmesh, boxsize)
+    zero = np.all(kvec == 0.0, axis=-1)
+    safe = np.where(zero[..., None], 1.0, kvec)
+    acc = np.zeros(W.shape, dtype=np.complex128)
+    for m in range(-ell, ell + 1):
+        acc += ylm_racah(ell, m, safe) * Sbar_lm[(ell, m)]
+    return np.where(zero, 0.0, np.real(acc) * C / (W * W))
+
+
+def noise_product(Fl: np.ndarray, FN0: np.ndarray, s_modes: np.ndarray) -> np.ndarray:
+    """P(q) = F_l(q) N(q)^* - s_l(q), zero at q = 0 and on Nyquist-component modes."""
+    P = Fl * np.conj(FN0) - s_modes
+    P = np.where(nyquist_mask(Fl.shape[0]), 0.0, P)
+    P[0, 0, 0] = 0.0
+    return P
+
+
+def exact_pair_sums(P: np.ndarray, bins: Bins, pairs) -> np.ndarray:
+    """T(i, j) = sum_{q1 in i, q2 in j} Re P(q1 + q2) via sum_x I_i I_j p / N^3."""
+    from .bispectrum import indicator_field, triple_sum
+    n = P.shape[0]
+    n3 = float(n) ** 3
+    p = np.fft.ifftn(P).real * n3
+    shells = bins.shell_index()
+    ind = {b: indicator_field(shells, b) for b in sorted({x for q in pairs for x in q})}
+    return np.array([triple_sum(ind[i], ind[j], p) / n3 for i, j in pairs])
+
+
+def triposh_shot_fft(ell, pairs, T, H, counts, centres, I33, Sbar):
+    """N_l0l(k_i, k_j) with the i = j != k term from the exact pair sums T (the
+    other terms as in triposh_shot)."""
+    out = np.empty(len(pairs))
+    sign = -1.0 if ell % 2 else 1.0
+    for t, (i, j) in enumerate(pairs):
+        tt = centres[i] / centres[j]
+        term = sign * (2 * ell + 1) * (g_ell(ell, tt) * H[i] + g_ell(ell, 1.0 / tt) * H[j])
+        term += (2 * ell + 1) * T[t] / (float(counts[i]) * float(counts[j]))
         if ell == 0:
             term += Sbar
         out[t] = term / I33
