@@ -44,6 +44,9 @@ def parse():
                     help="one single-stream graph per stream instead of one multi-stream graph")
     ap.add_argument("--streams", type=int, default=0,
                     help="concurrent streams inside a step (0: the autotuner's choice, else 4)")
+    ap.add_argument("--engine", choices=["native", "torch"], default="native",
+                    help="batch runner: the library's cnpc_batch (HIP graph captured by the library) "
+                         "or the Python Batch captured with torch.cuda.CUDAGraph")
     ap.add_argument("--no-tune", action="store_true", help="library defaults, no autotuning")
     ap.add_argument("--staged", action="store_true",
                     help="painting and spectra on separate streams (with --no-tune)")
@@ -175,17 +178,26 @@ def main():
         tcat = gpu_mocks[: max(1, min(args.tune_mocks, len(gpu_mocks)))]
         res = autotune.tune_batch(desc, tcat, bins, plan, use_cache=False, reps=5,
                                   streams=(args.streams,) if args.streams else (1, 2, 3, 4, 6),
-                                  log=lambda m: log(args, m))
+                                  log=lambda m: log(args, m), engine=args.engine)
         nstreams = res.streams
         staged = res.staged
         tuning = res.as_dict()
         tuning["batch_mocks"] = len(tcat)
         log(args, f"autotuned in {res.seconds:.1f}s: streams {res.streams}, staged {res.staged}, knobs {res.knobs}, "
                   f"{res.default_ms:.2f} -> {res.ms:.2f} ms per {len(tcat)} mocks")
-    batch = pl.Batch(nstreams, staged=staged, balance=args.balance)
+    native = args.engine == "native" and not staged and not args.graph_per_stream and args.balance == "rr"
+    if native:
+        batch = pl.NativeBatch(desc, bins, plan, nstreams=nstreams,
+                               max_ngal=max(int(g.shape[1]) for g, _ in gpu_mocks),
+                               max_nran=max(int(r.shape[1]) for _, r in gpu_mocks))
 
-    def step():
-        batch.run(desc, gpu_mocks, bins, plan, outs)
+        def step():
+            batch.run(gpu_mocks, outs)
+    else:
+        batch = pl.Batch(nstreams, staged=staged, balance=args.balance)
+
+        def step():
+            batch.run(desc, gpu_mocks, bins, plan, outs)
 
     step()  # eager pass: plans, twiddles and scratch reach their final size
     torch.cuda.synchronize()
@@ -216,6 +228,10 @@ def main():
             for s in batch.streams:
                 cur.wait_stream(s)
         log(args, f"captured {len(graphs)} single-stream graphs")
+    elif not args.no_graph and native:
+        batch.capture(gpu_mocks, outs)
+        run = batch.replay
+        log(args, "captured the batch as one graph (cnpc_batch_capture)")
     elif not args.no_graph:
         graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(graph):
@@ -312,6 +328,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if prec == L.PREC_F32 else "f32+bf16x3",
         "graph": "none" if args.no_graph else ("per-stream" if args.graph_per_stream else "one"),
+        "engine": "cnpc_batch" if native else "python Batch",
         "streams": nstreams,
         "staged": staged,
         "placement": args.balance,
@@ -375,18 +392,39 @@ def single_config(args):
                 return {k: res[k] for k in keys}
             return run
         jobs += [("pk", "f64", pk(L.F64)), ("pk", "f32", pk(L.F32))]
+        # odd multipoles alongside the even ones, and the cross multipoles of
+        # two tracers (alternate galaxies, each with alternate randoms)
+        ga, gb = gd[:, 0::2].contiguous(), gd[:, 1::2].contiguous()
+        ra, rb = rd[:, 0::2].contiguous(), rd[:, 1::2].contiguous()
+
+        def pk_odd(dt):
+            def run():
+                res = pl.measure_pk(descs[dt], gd, rd, bins, ells=(0, 1, 2, 3, 4))
+                return {k: res[k] for k in ("P0", "P1", "P2", "P3", "P4")}
+            return run
+
+        def pk_cross(dt):
+            def run():
+                res = pl.measure_pk_cross(descs[dt], (ga, ra), (gb, rb), bins, ells=(0, 1, 2, 3, 4))
+                return {k: res[k] for k in ("P0", "P1", "P2", "P3", "P4")}
+            return run
+        jobs += [("pk_odd", "f64", pk_odd(L.F64)), ("pk_odd", "f32", pk_odd(L.F32)),
+                 ("pk_cross", "f64", pk_cross(L.F64)), ("pk_cross", "f32", pk_cross(L.F32))]
     else:
         ests = ([("B0", L.EST_SCOCCIMARRO, 0), ("B2", L.EST_SCOCCIMARRO, 2), ("B202", L.EST_TRIPOSH, 2)]
                 if args.config == 3 else [("B202", L.EST_TRIPOSH, 2)])
         forms = [("f64", L.F64, L.PREC_F64), ("f32", L.F32, L.PREC_F32), ("bf16x3", L.F32, L.PREC_BF16X3)]
 
-        def bk(dt, prec, est, ell):
+        def bk(dt, prec, est, ell, noise="analytic"):
             def run():
-                res = pl.measure_bk(descs[dt], gd, rd, bins, estimator=est, ell=ell, precision=prec)
-                return {"raw": res["raw"], "value": res["value"]}
+                res = pl.measure_bk(descs[dt], gd, rd, bins, estimator=est, ell=ell, precision=prec,
+                                    noise=noise)
+                return {"raw": res["raw"], "shot": res["shot"], "value": res["value"]}
             return run
         for name, est, ell in ests:
             jobs += [(name, f, bk(dt, prec, est, ell)) for f, dt, prec in forms]
+        # TripoSH with the FFT-method i = j != k noise term
+        jobs += [("B202_fft_noise", f, bk(dt, prec, L.EST_TRIPOSH, 2, "fft")) for f, dt, prec in forms]
     times, outs = {}, {}
     for name, form, run in jobs:
         outs[(name, form)] = {k: v.detach().cpu().numpy() for k, v in run().items()}  # warm: plans, scratch

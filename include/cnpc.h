@@ -310,6 +310,82 @@ cnpc_status cnpc_bispectrum(const cnpc_bispec_plan* plan, const void* F0, const 
                             const double* noise_means, const double* norms, double* raw,
                             double* shot, double* value, void* ws, size_t ws_bytes, void* stream);
 
+/* ---- FFT-method shot noise of the TripoSH BB_l0l (the reference method of
+ * the section validating the analytic shot noise, applied to the i = j != k
+ * term that the new estimator's shot-noise subsection derives) ----
+ * The i = j != k term (the two l = 0 legs on one particle) becomes exact:
+ *   (2l+1)/I33 T(i, j) / (N_i N_j),
+ *   T(i, j) = sum_{q1 in shell i, q2 in shell j} Re P(q1 + q2),
+ *   P(q) = F_l(q) N(q)^* - s_l(q)   (s_l(q): the per-mode self-pair term),
+ * with P(0) = 0 and P = 0 on modes with a Nyquist component, computed as the
+ * contraction sum_x I_i I_j p of the shell indicator fields I_b = c2r[Phi_b]
+ * with p = c2r[P] on the plan's grid (no thin-shell step).  The other terms
+ * are those of cnpc_bispectrum.
+ * cnpc_bispec_indicator_bytes: size of the indicator fields (nbins fields of
+ * G^3 values in the plan's field type; 0 for a Scoccimarro plan).
+ * cnpc_bispec_indicators: fills them (caller-owned device buffer, computed
+ * once per plan and read-only afterwards; ws as for cnpc_bispectrum).
+ * cnpc_bispectrum_fft_noise: cnpc_bispectrum of a TripoSH plan with that
+ * term exact; FN0 is the band spectrum of F_0 of the N mesh (as F0), ind the
+ * filled indicator fields; noise_means as for cnpc_bispectrum (required).
+ * Costs a second contraction, one more band c2r and a copy of the indicators
+ * into ws.  Errors: CNPC_EINVAL for a Scoccimarro plan or a null pointer,
+ * CNPC_EWORKSPACE for a short ws. */
+size_t cnpc_bispec_indicator_bytes(const cnpc_bispec_plan* plan);
+cnpc_status cnpc_bispec_indicators(const cnpc_bispec_plan* plan, void* ind, void* ws, size_t ws_bytes,
+                                   void* stream);
+cnpc_status cnpc_bispectrum_fft_noise(const cnpc_bispec_plan* plan, const void* F0, const void* Fl,
+                                      const void* FN0, const void* ind, const double* noise_means,
+                                      const double* norms, double* raw, double* shot, double* value,
+                                      void* ws, size_t ws_bytes, void* stream);
+
+/* ---- batched measurement (the 64-mock workload of P_l and B_0) ----
+ * A batch runs many catalog pairs through the whole hot path: catalog sums,
+ * painting (cnpc_paint_fkp), de-interlacing of delta and N, the Y_lm r2c
+ * transforms of the l > 0 multipoles in ells, F_l assembly, the shell means of
+ * F_0 F_l^* and F_0 N^* with the l = 0 self term, P_l (cnpc_pk_finalize rows)
+ * and the Scoccimarro B_0 of plan with its analytic shot noise (cnpc_bispectrum
+ * rows) -- the same calls, in the same order, as the single-catalog entry
+ * points.  Catalog i runs on batch stream i mod nstreams; each stream owns a
+ * slab of the caller's workspace for its intermediates, so catalogs on
+ * different streams overlap.
+ * cnpc_batch_create: plan must be a Scoccimarro l = 0 plan made for desc and
+ * bins; ells: 1 to 3 distinct values of {0, 2, 4}, including 0; nstreams in
+ * [1, 16]; max_ngal / max_nran bound every later catalog (they size the
+ * painting scratch).  The batch owns its streams (default priority), events
+ * and a captured graph; it keeps a pointer to plan, which must outlive it.
+ * cnpc_batch_workspace_size: bytes of device workspace a run needs.
+ * cnpc_batch_run: enqueues ncat catalogs.  Host arrays of ncat device
+ * pointers: gpos / rpos (3 x n uint32 positions), pk_out (9 x nbins FP64, the
+ * cnpc_pk_finalize rows), bk_out (3 x nconf FP64: raw, shot, value); host
+ * arrays ngal / nran; gw / rw: NULL, or arrays of per-catalog FP32 weight
+ * pointers (NULL entries: unit weights).  The batch streams wait for the work
+ * already on `stream`, and `stream` waits for them at the end.
+ * cnpc_batch_capture: captures the same enqueue into a HIP graph held by the
+ * batch (replacing an earlier one); nothing runs.  Every pointer is baked
+ * into the graph: inputs, outputs and ws must stay allocated, at the same
+ * addresses, for as long as the graph is replayed (refill the inputs in place
+ * to measure other catalogs of the same sizes).
+ * cnpc_batch_replay: launches the captured graph on `stream`.
+ * Calls on one batch must not overlap (they share its streams, events and
+ * workspace slabs).  Errors: CNPC_EINVAL (arguments, sizes above the maxima,
+ * replay before capture), CNPC_EWORKSPACE, CNPC_EHIP. */
+typedef struct cnpc_batch cnpc_batch;
+cnpc_status cnpc_batch_create(cnpc_batch** batch, const cnpc_mesh_desc* desc, const cnpc_kbins* bins,
+                              const cnpc_bispec_plan* plan, int32_t nells, const int32_t* ells,
+                              int32_t nstreams, int64_t max_ngal, int64_t max_nran);
+size_t cnpc_batch_workspace_size(const cnpc_batch* batch);
+cnpc_status cnpc_batch_run(cnpc_batch* batch, int32_t ncat, const uint32_t* const* gpos,
+                           const float* const* gw, const int64_t* ngal, const uint32_t* const* rpos,
+                           const float* const* rw, const int64_t* nran, double* const* pk_out,
+                           double* const* bk_out, void* ws, size_t ws_bytes, void* stream);
+cnpc_status cnpc_batch_capture(cnpc_batch* batch, int32_t ncat, const uint32_t* const* gpos,
+                               const float* const* gw, const int64_t* ngal, const uint32_t* const* rpos,
+                               const float* const* rw, const int64_t* nran, double* const* pk_out,
+                               double* const* bk_out, void* ws, size_t ws_bytes);
+cnpc_status cnpc_batch_replay(cnpc_batch* batch, void* stream);
+void cnpc_batch_destroy(cnpc_batch* batch);
+
 /* ---- kernel timer (measurement hook for benchmarks and profilers) ----
  * While started, every launch of a kernel class selected by class_mask (bit
  * 1 << class) is bracketed by HIP events recorded on its launch stream (at

@@ -91,6 +91,18 @@ _PROTOS = {
     "cnpc_bispec_grid": (_i32, [_vp]),
     "cnpc_bispec_ext_bins": (_i32, [_vp, _PB]),
     "cnpc_bispectrum": (_i32, [_vp, _cvp, _cvp, _cvp, _cvp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "cnpc_batch_create": (_i32, [C.POINTER(_vp), _PD, _PB, _vp, _i32, C.POINTER(_i32), _i32, _i64, _i64]),
+    "cnpc_batch_workspace_size": (_sz, [_vp]),
+    "cnpc_batch_run": (_i32, [_vp, _i32, C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_i64), C.POINTER(_vp),
+                              C.POINTER(_vp), C.POINTER(_i64), C.POINTER(_vp), C.POINTER(_vp), _vp, _sz, _vp]),
+    "cnpc_batch_capture": (_i32, [_vp, _i32, C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_i64), C.POINTER(_vp),
+                                  C.POINTER(_vp), C.POINTER(_i64), C.POINTER(_vp), C.POINTER(_vp), _vp, _sz]),
+    "cnpc_batch_replay": (_i32, [_vp, _vp]),
+    "cnpc_batch_destroy": (None, [_vp]),
+    "cnpc_bispec_indicator_bytes": (_sz, [_vp]),
+    "cnpc_bispec_indicators": (_i32, [_vp, _vp, _vp, _sz, _vp]),
+    "cnpc_bispectrum_fft_noise": (_i32, [_vp, _cvp, _cvp, _cvp, _cvp, _cvp, _cvp, _vp, _vp, _vp, _vp, _sz,
+                                         _vp]),
     "cnpc_ktimer_start": (_i32, [C.c_uint32, _i32]),
     "cnpc_ktimer_stop": (_i32, [C.POINTER(_d), C.POINTER(_i64)]),
     "cnpc_bin_pk_im": (_i32, [_PD, _PB, _i32, _i32, C.POINTER(_vp), C.POINTER(_vp), _vp, _vp, _vp, _vp,

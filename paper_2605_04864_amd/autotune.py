@@ -132,40 +132,53 @@ class TuneResult:
 
 
 def time_batch(desc, catalogs, bins, plan, ells=(0, 2, 4), nstreams: int = DEFAULT_STREAMS,
-               reps: int = 3, staged: bool = False) -> float:
-    """Median ms per graph replay of the whole batch under the current knobs."""
+               reps: int = 3, staged: bool = False, engine: str = "torch") -> float:
+    """Median ms per graph replay of the whole batch under the current knobs
+    (engine "native": the library's cnpc_batch graph; "torch": pipeline.Batch
+    captured with torch.cuda.CUDAGraph)."""
     import torch
     from . import pipeline as pl
     dev = catalogs[0][0].device
     outs = [{"pk": torch.empty((9, bins.nbins), dtype=torch.float64, device=dev),
              "bk": torch.empty((3, plan.nconf), dtype=torch.float64, device=dev)} for _ in catalogs]
-    batch = pl.Batch(nstreams, device=dev, staged=staged)
-    batch.run(desc, catalogs, bins, plan, outs, ells)
-    torch.cuda.synchronize()
-    graph = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(graph):
+    if engine == "native" and not staged:
+        batch = pl.NativeBatch(desc, bins, plan, ells=ells, nstreams=nstreams,
+                               max_ngal=max(int(g.shape[1]) for g, _ in catalogs),
+                               max_nran=max(int(r.shape[1]) for _, r in catalogs), device=dev)
+        batch.run(catalogs, outs)
+        torch.cuda.synchronize()
+        batch.capture(catalogs, outs)
+        replay = batch.replay
+    else:
+        batch = pl.Batch(nstreams, device=dev, staged=staged)
         batch.run(desc, catalogs, bins, plan, outs, ells)
-    graph.replay()
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            batch.run(desc, catalogs, bins, plan, outs, ells)
+        replay = graph.replay
+    replay()
     torch.cuda.synchronize()
     times = []
     for _ in range(max(1, reps)):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        graph.replay()
+        replay()
         e1.record()
         torch.cuda.synchronize()
         times.append(e0.elapsed_time(e1))
-    del graph, batch, outs
+    del replay, batch, outs
     return statistics.median(times)
 
 
 def tune_batch(desc, catalogs, bins, plan, ells=(0, 2, 4), streams: Sequence[int] = (1, 2, 3, 4, 6),
                reps: int = 3, min_gain: float = 0.02, cache: Optional[str] = None,
-               use_cache: bool = True, log: Optional[Callable[[str], None]] = None) -> TuneResult:
+               use_cache: bool = True, log: Optional[Callable[[str], None]] = None,
+               engine: str = "torch") -> TuneResult:
     """Pick the stream count and knob values for batches like `catalogs` and
     leave the knobs set to the choice."""
     path = _cache_path(cache)
-    sig = signature(desc, plan, len(catalogs), ells)
+    sig = signature(desc, plan, len(catalogs), ells) + "|" + engine
     if use_cache:
         hit = _cache_load(path).get("entries", {}).get(sig)
         if hit:
@@ -182,7 +195,7 @@ def tune_batch(desc, catalogs, bins, plan, ells=(0, 2, 4), streams: Sequence[int
 
     def measure(s):
         set_knobs({k: s[k] for k in KNOB_ORDER})
-        t = time_batch(desc, catalogs, bins, plan, ells, s["streams"], reps, staged=s["staged"])
+        t = time_batch(desc, catalogs, bins, plan, ells, s["streams"], reps, staged=s["staged"], engine=engine)
         if log:
             log(f"autotune {s} -> {t:.3f} ms")
         return t

@@ -486,7 +486,35 @@ cnpc_status cnpc_bispectrum(const cnpc_bispec_plan* p, const void* F0, const voi
   CNPC_REQUIRE(F0 && norms && raw && shot && value && ws, "null pointer argument");
   CNPC_REQUIRE(p->ell == 0 || p->est == CNPC_EST_TRIPOSH || Fl != nullptr, "B_l with l > 0 needs F_l");
   CNPC_REQUIRE(p->est != CNPC_EST_TRIPOSH || Fl != nullptr, "TripoSH needs F_l (F_0 for l = 0)");
-  return bispec_run(p, F0, Fl, noise_means, norms, raw, shot, value, ws, ws_bytes, as_stream(stream));
+  return bispec_run(p, F0, Fl, nullptr, nullptr, noise_means, norms, raw, shot, value, ws, ws_bytes,
+                    as_stream(stream));
+}
+
+size_t cnpc_bispec_indicator_bytes(const cnpc_bispec_plan* p) {
+  if (p == nullptr || p->est != CNPC_EST_TRIPOSH) return 0;
+  return bispec_indicator_bytes(p);
+}
+
+cnpc_status cnpc_bispec_indicators(const cnpc_bispec_plan* p, void* ind, void* ws, size_t ws_bytes,
+                                   void* stream) {
+  API_BEGIN;
+  CNPC_REQUIRE(p != nullptr, "null plan");
+  CNPC_REQUIRE(p->est == CNPC_EST_TRIPOSH, "shell indicator fields serve the TripoSH FFT-method noise");
+  CNPC_REQUIRE(ind && ws, "null pointer argument");
+  return bispec_indicators(p, ind, ws, ws_bytes, as_stream(stream));
+}
+
+cnpc_status cnpc_bispectrum_fft_noise(const cnpc_bispec_plan* p, const void* F0, const void* Fl,
+                                      const void* FN0, const void* ind, const double* noise_means,
+                                      const double* norms, double* raw, double* shot, double* value, void* ws,
+                                      size_t ws_bytes, void* stream) {
+  API_BEGIN;
+  CNPC_REQUIRE(p != nullptr, "null plan");
+  CNPC_REQUIRE(p->est == CNPC_EST_TRIPOSH, "the FFT-method shot noise is implemented for TripoSH plans");
+  CNPC_REQUIRE(F0 && Fl && FN0 && ind && noise_means && norms && raw && shot && value && ws,
+               "null pointer argument");
+  return bispec_run(p, F0, Fl, FN0, ind, noise_means, norms, raw, shot, value, ws, ws_bytes,
+                    as_stream(stream));
 }
 
 }  // extern "C"

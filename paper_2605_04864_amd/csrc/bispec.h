@@ -60,7 +60,9 @@ namespace cnpc {
 cnpc_status bispec_plan_create(cnpc_bispec_plan** out, const cnpc_mesh_desc* d, const cnpc_kbins* b,
                                int est, int ell, int prec, void* ws, size_t ws_bytes, hipStream_t s);
 void bispec_plan_destroy(cnpc_bispec_plan* P);
-cnpc_status bispec_run(const cnpc_bispec_plan* P, const void* F0, const void* Fl,
-                       const double* noise, const double* norms, double* raw, double* shot,
+cnpc_status bispec_run(const cnpc_bispec_plan* P, const void* F0, const void* Fl, const void* FN0,
+                       const void* ind, const double* noise, const double* norms, double* raw, double* shot,
                        double* value, void* ws, size_t ws_bytes, hipStream_t s);
+size_t bispec_indicator_bytes(const cnpc_bispec_plan* P);
+cnpc_status bispec_indicators(const cnpc_bispec_plan* P, void* out, void* ws, size_t ws_bytes, hipStream_t s);
 }  // namespace cnpc

@@ -496,7 +496,11 @@ size_t shell_c2r_ws_elems(int n, int m, int nsh) {
 }
 
 // ------------------------------------------------------------- finalize --
-__global__ void k_finalize(FinArgs f, const double* __restrict__ C, const double* __restrict__ noise,
+// Cq (TripoSH, optional): exact pair sums of the FFT-method i = j != k term,
+// G^3 sum_{q1 in i, q2 in j} Re P(q1 + q2) per shell pair, in place of the
+// thin-shell weighted mean of Q_l over k3 bins.
+__global__ void k_finalize(FinArgs f, const double* __restrict__ C, const double* __restrict__ Cq,
+                           const double* __restrict__ noise,
                            const double* __restrict__ nm, double* __restrict__ raw,
                            double* __restrict__ shot, double* __restrict__ value) {
   const double I33 = nm[CNPC_NORM_I33], Sbar = nm[CNPC_NORM_SBAR];
@@ -528,13 +532,17 @@ __global__ void k_finalize(FinArgs f, const double* __restrict__ C, const double
         const double sgn = (f.ell & 1) ? -1.0 : 1.0;
         double v = sgn * (2.0 * f.ell + 1.0) *
                    (f.aux[2 * t] * (H[i] - S[i]) + f.aux[2 * t + 1] * (H[j] - S[j]));
-        const int c0 = i > j ? i - j : j - i, c1 = i + j;
-        double num = 0.0, den = 0.0;
-        for (int q = c0; q <= c1; ++q) {
-          num += f.wq[q] * (Q[q] - S[q]);
-          den += f.wq[q];
+        if (Cq) {
+          v += (2.0 * f.ell + 1.0) * Cq[p] / (f.n3 * f.counts[i] * f.counts[j]);
+        } else {
+          const int c0 = i > j ? i - j : j - i, c1 = i + j;
+          double num = 0.0, den = 0.0;
+          for (int q = c0; q <= c1; ++q) {
+            num += f.wq[q] * (Q[q] - S[q]);
+            den += f.wq[q];
+          }
+          v += (2.0 * f.ell + 1.0) * num / den;
         }
-        v += (2.0 * f.ell + 1.0) * num / den;
         if (f.ell == 0) v += Sbar;
         sh = v / I33;
       }
@@ -568,10 +576,53 @@ static cnpc_status upload_tables(cnpc_bispec_plan* P) {
   return CNPC_OK;
 }
 
-__global__ void k_fill_ones(cx<double>* p, int64_t n) {
+template <typename T>
+__global__ void k_fill_ones(cx<T>* p, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = cx<double>{1.0, 0.0};
+    p[i] = cx<T>{T(1), T(0)};
+}
+
+// P(q) = F_l(q) N(q)^* - s_l(q) on the band (half-width m) of an n^3 mesh, with
+// s_l(q) = Re sum_m y_l^m(qhat) Sbar_l^m C(q) / W(q)^2 the self-pair summand;
+// zero at q = 0 and on modes with a Nyquist component.
+template <typename T>
+__global__ void __launch_bounds__(256) k_noise_product(int n, int m, int assign, int interlace, int ell,
+                                                       const cx<T>* __restrict__ Fl,
+                                                       const cx<T>* __restrict__ FN0,
+                                                       const double* __restrict__ norms,
+                                                       cx<T>* __restrict__ P) {
+  const int64_t bsz = (int64_t)4 * m * m * m;
+  const int base = ell == 0 ? 0 : (ell == 2 ? 1 : 4);
+  const double* sb = norms + CNPC_NORM_SBARLM + 2 * base;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < bsz;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int kz = (int)(i % m);
+    const int jy = (int)((i / m) % (2 * m));
+    const int jx = (int)(i / ((int64_t)2 * m * m));
+    const int nx = band_freq(jx, m), ny = band_freq(jy, m), nz = kz;
+    const int64_t n2 = (int64_t)nx * nx + (int64_t)ny * ny + (int64_t)nz * nz;
+    if (n2 == 0 || nx == -(n / 2) || ny == -(n / 2) || nz == n / 2) {
+      P[i] = cx<T>{T(0), T(0)};
+      continue;
+    }
+    const cx<T> a = Fl[i], b = FN0[i];
+    double re = (double)a.x * (double)b.x + (double)a.y * (double)b.y;
+    const double im = (double)a.y * (double)b.x - (double)a.x * (double)b.y;
+    const double kn = sqrt((double)n2);
+    double cxs, ctx, cys, cty, czs, ctz;
+    alias_1d(nx, n, assign, &cxs, &ctx);
+    alias_1d(ny, n, assign, &cys, &cty);
+    alias_1d(nz, n, assign, &czs, &ctz);
+    const double C = interlace ? 0.5 * (cxs * cys * czs + ctx * cty * ctz) : cxs * cys * czs;
+    const double W = window_1d(nx, n, assign) * window_1d(ny, n, assign) * window_1d(nz, n, assign);
+    double yr[5], yi[5];
+    racah_ylm<double>(ell, nx / kn, ny / kn, nz / kn, yr, yi);
+    double sv = yr[0] * sb[0] - yi[0] * sb[1];
+    for (int mm = 1; mm <= ell; ++mm) sv += 2.0 * (yr[mm] * sb[2 * mm] - yi[mm] * sb[2 * mm + 1]);
+    re -= sv * C / (W * W);
+    P[i] = cx<T>{T(re), T(im)};
+  }
 }
 
 // Band half-width and contraction grid of a bispectrum binning.  Every shell
@@ -612,7 +663,7 @@ size_t bispec_ws_bytes(const cnpc_mesh_desc* d, const cnpc_kbins* b, int est, in
   const size_t es = esize(d->dtype);
   // run time: fields + c2r scratch for all of them + contraction partials/result
   const size_t run = g.nfields * g3 * es + shell_c2r_ws_elems(g.grid, band, g.nfields) * 2 * es +
-                     (contract_partial_doubles(nb, g.ncols) + (size_t)nb * (nb + 1) / 2 * g.ncols) * 8;
+                     (contract_partial_doubles(nb, g.ncols) + (size_t)nb * (nb + 1) * g.ncols) * 8;
   // plan time (FP64 indicator fields): ones + fields + scratch + partials
   const size_t bsz = (size_t)4 * band * band * band;
   const size_t plan = bsz * 16 + (size_t)nb * g3 * 8 + shell_c2r_ws_elems(g.grid, band, nb) * 16 +
@@ -704,7 +755,7 @@ cnpc_status bispec_plan_create(cnpc_bispec_plan** out, const cnpc_mesh_desc* d, 
     cnpc_mesh_desc d64 = *d;
     d64.dtype = CNPC_F64;
     d64.n = G;
-    hipLaunchKernelGGL(k_fill_ones, dim3(256), dim3(256), 0, s, ones, bsz);
+    hipLaunchKernelGGL(k_fill_ones<double>, dim3(256), dim3(256), 0, s, ones, bsz);
     CNPC_HIP(hipGetLastError());
     CNPC_TRY(ensure_twiddles());
     CNPC_TRY(shell_c2r<double>(&d64, m, ones, P->thr.data(), nb + 1, 0, nb, true, ind, scr, s));
@@ -766,7 +817,20 @@ void bispec_plan_destroy(cnpc_bispec_plan* P) {
 }
 
 template <typename T>
+static cnpc_status contract_any(const cnpc_bispec_plan* P, const T* fields, int64_t n3, double* partial,
+                                double* out, hipStream_t s) {
+  if constexpr (sizeof(T) == 4) {
+    if (P->prec == CNPC_PREC_BF16X3) return contract_mfma(fields, n3, P->nfields, P->nb, P->cc, partial, out, s);
+  }
+  return contract_valu<T>(fields, n3, P->nfields, P->nb, P->cc, partial, out, s);
+}
+
+// FN0 / ind (TripoSH, both or neither): band spectrum of N and the shell
+// indicator fields of bispec_indicators; with them the i = j != k shot-noise
+// term is the exact pair sum (FFT method) instead of the thin-shell mean.
+template <typename T>
 static cnpc_status bispec_run_t(const cnpc_bispec_plan* P, const cx<T>* F0, const cx<T>* Fl,
+                                const cx<T>* FN0, const T* ind,
                                 const double* noise, const double* norms, double* raw, double* shot,
                                 double* value, void* ws, size_t ws_bytes, hipStream_t s) {
   // shell fields live on the contraction grid (P->grid)^3, not on the mesh
@@ -780,7 +844,8 @@ static cnpc_status bispec_run_t(const cnpc_bispec_plan* P, const cx<T>* F0, cons
   cx<T>* scr = reinterpret_cast<cx<T>*>(align256(reinterpret_cast<unsigned char*>(fields + (int64_t)P->nfields * n3)));
   double* partial = reinterpret_cast<double*>(align256(reinterpret_cast<unsigned char*>(scr + shell_c2r_ws_elems(n, m, P->nfields))));
   double* Cm = partial + contract_partial_doubles(nb, P->cc.ncols);
-  const size_t need = reinterpret_cast<unsigned char*>(Cm + (size_t)nb * (nb + 1) / 2 * P->cc.ncols) -
+  double* Cq = Cm + (size_t)nb * (nb + 1) / 2 * P->cc.ncols;
+  const size_t need = reinterpret_cast<unsigned char*>(Cq + (size_t)nb * (nb + 1) / 2 * P->cc.ncols) -
                       reinterpret_cast<unsigned char*>(ws);
   if (need > ws_bytes) {
     set_error("bispectrum workspace too small: need %zu, got %zu", need, ws_bytes);
@@ -793,13 +858,21 @@ static cnpc_status bispec_run_t(const cnpc_bispec_plan* P, const cx<T>* F0, cons
     CNPC_TRY(shell_c2r<T>(d, m, Fl, P->thr.data(), nthr, 0, nb, true, fields + (int64_t)nb * n3, scr, s));
   if (P->est == CNPC_EST_TRIPOSH)
     CNPC_TRY(shell_c2r<T>(d, m, Fl, P->thr.data(), nthr, 0, 1, false, fields + (int64_t)nb * n3, scr, s));
-  if constexpr (sizeof(T) == 4) {
-    if (P->prec == CNPC_PREC_BF16X3)
-      CNPC_TRY(contract_mfma(fields, n3, P->nfields, nb, P->cc, partial, Cm, s));
-    else
-      CNPC_TRY(contract_valu<T>(fields, n3, P->nfields, nb, P->cc, partial, Cm, s));
-  } else {
-    CNPC_TRY(contract_valu<T>(fields, n3, P->nfields, nb, P->cc, partial, Cm, s));
+  CNPC_TRY(contract_any<T>(P, fields, n3, partial, Cm, s));
+  const bool exact = ind != nullptr;
+  if (exact) {
+    // the signal fields are consumed: P(q) goes to the start of the field
+    // area (4 m^3 complex values <= one G^3 field, G >= 2m), its c2r to the
+    // column slot nb, the cached indicators over slots 0 .. nb-1
+    cx<T>* pq = reinterpret_cast<cx<T>*>(fields);
+    const int64_t bsz = (int64_t)4 * m * m * m;
+    const unsigned gb = (unsigned)std::min<int64_t>((bsz + 255) / 256, 65536);
+    hipLaunchKernelGGL((k_noise_product<T>), dim3(gb), dim3(256), 0, s, P->desc.n, m, P->desc.assign,
+                       P->desc.interlace, P->ell, Fl, FN0, norms, pq);
+    CNPC_HIP(hipGetLastError());
+    CNPC_TRY(shell_c2r<T>(d, m, pq, P->thr.data(), nthr, 0, 1, false, fields + (int64_t)nb * n3, scr, s));
+    CNPC_HIP(hipMemcpyAsync(fields, ind, sizeof(T) * (size_t)nb * n3, hipMemcpyDeviceToDevice, s));
+    CNPC_TRY(contract_any<T>(P, fields, n3, partial, Cq, s));
   }
   FinArgs f;
   f.est = P->est;
@@ -815,19 +888,53 @@ static cnpc_status bispec_run_t(const cnpc_bispec_plan* P, const cx<T>* F0, cons
   f.counts = P->d_counts;
   f.wq = P->d_wq;
   const unsigned g = (unsigned)std::max(1, (P->nconf + 255) / 256);
-  hipLaunchKernelGGL(k_finalize, dim3(g), dim3(256), 0, s, f, Cm, noise, norms, raw, shot, value);
+  hipLaunchKernelGGL(k_finalize, dim3(g), dim3(256), 0, s, f, Cm, exact ? Cq : nullptr, noise, norms, raw,
+                     shot, value);
   CNPC_HIP(hipGetLastError());
   return CNPC_OK;
 }
 
-cnpc_status bispec_run(const cnpc_bispec_plan* P, const void* F0, const void* Fl,
-                       const double* noise, const double* norms, double* raw, double* shot,
+cnpc_status bispec_run(const cnpc_bispec_plan* P, const void* F0, const void* Fl, const void* FN0,
+                       const void* ind, const double* noise, const double* norms, double* raw, double* shot,
                        double* value, void* ws, size_t ws_bytes, hipStream_t s) {
   if (P->desc.dtype == CNPC_F64)
-    return bispec_run_t<double>(P, (const cx<double>*)F0, (const cx<double>*)Fl, noise, norms, raw, shot,
-                                value, ws, ws_bytes, s);
-  return bispec_run_t<float>(P, (const cx<float>*)F0, (const cx<float>*)Fl, noise, norms, raw, shot,
-                             value, ws, ws_bytes, s);
+    return bispec_run_t<double>(P, (const cx<double>*)F0, (const cx<double>*)Fl, (const cx<double>*)FN0,
+                                (const double*)ind, noise, norms, raw, shot, value, ws, ws_bytes, s);
+  return bispec_run_t<float>(P, (const cx<float>*)F0, (const cx<float>*)Fl, (const cx<float>*)FN0,
+                             (const float*)ind, noise, norms, raw, shot, value, ws, ws_bytes, s);
+}
+
+size_t bispec_indicator_bytes(const cnpc_bispec_plan* P) {
+  const size_t g3 = (size_t)P->grid * P->grid * P->grid;
+  return (size_t)P->nb * g3 * esize(P->desc.dtype);
+}
+
+// I_b = c2r[Phi_b] on the contraction grid, b < nb, in the field type.
+template <typename T>
+static cnpc_status bispec_indicators_t(const cnpc_bispec_plan* P, T* out, void* ws, size_t ws_bytes,
+                                       hipStream_t s) {
+  cnpc_mesh_desc dg = P->desc;
+  dg.n = P->grid;
+  const int m = P->band, nb = P->nb;
+  const int64_t bsz = (int64_t)4 * m * m * m;
+  unsigned char* w = align256(reinterpret_cast<unsigned char*>(ws));
+  cx<T>* ones = reinterpret_cast<cx<T>*>(w);
+  cx<T>* scr = reinterpret_cast<cx<T>*>(align256(reinterpret_cast<unsigned char*>(ones + bsz)));
+  const size_t need = reinterpret_cast<unsigned char*>(scr + shell_c2r_ws_elems(P->grid, m, nb)) -
+                      reinterpret_cast<unsigned char*>(ws);
+  if (need > ws_bytes) {
+    set_error("indicator workspace too small: need %zu, got %zu", need, ws_bytes);
+    return CNPC_EWORKSPACE;
+  }
+  CNPC_TRY(ensure_twiddles());
+  hipLaunchKernelGGL(k_fill_ones<T>, dim3(256), dim3(256), 0, s, ones, bsz);
+  CNPC_HIP(hipGetLastError());
+  return shell_c2r<T>(&dg, m, ones, P->thr.data(), nb + 1, 0, nb, true, out, scr, s);
+}
+
+cnpc_status bispec_indicators(const cnpc_bispec_plan* P, void* out, void* ws, size_t ws_bytes, hipStream_t s) {
+  if (P->desc.dtype == CNPC_F64) return bispec_indicators_t<double>(P, (double*)out, ws, ws_bytes, s);
+  return bispec_indicators_t<float>(P, (float*)out, ws, ws_bytes, s);
 }
 
 }  // namespace cnpc

@@ -5,3 +5,4 @@
 #include "spectra.hip"
 #include "bispec.hip"
 #include "api.hip"
+#include "batch.hip"

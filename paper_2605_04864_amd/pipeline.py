@@ -296,6 +296,19 @@ class BispecPlan:
         L.check(L.lib.cnpc_bispec_ext_bins(h, C.byref(ext)))
         self.ext = ext
 
+    def indicators(self, scratch: Scratch, stream=None):
+        """Shell indicator fields of a TripoSH plan (computed once, kept)."""
+        if getattr(self, "_ind", None) is None:
+            nbytes = L.lib.cnpc_bispec_indicator_bytes(self.handle)
+            if nbytes == 0:
+                raise ValueError("indicator fields belong to TripoSH plans")
+            ind = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+            ws = scratch.get(self.ws_bytes)
+            L.check(L.lib.cnpc_bispec_indicators(self.handle, L.ptr(ind), L.ptr(ws), ws.numel(), _sh(stream)))
+            torch.cuda.synchronize()  # read-only from here on, from any stream
+            self._ind = ind
+        return self._ind
+
     def configs(self):
         import numpy as np
         ijk = (C.c_int32 * (3 * self.nconf))()
@@ -319,9 +332,15 @@ def bispec_plan(desc, bins, estimator, ell, precision, scratch: Scratch, stream=
 
 
 def measure_bk(desc, gpos, rpos, bins, estimator=L.EST_SCOCCIMARRO, ell=0, precision=None, gw=None,
-               rw=None, scratch: Optional[Scratch] = None, stream=None, shot_noise=True):
-    """Scoccimarro B_l or TripoSH B_l0l of one catalog pair, with analytic shot noise."""
+               rw=None, scratch: Optional[Scratch] = None, stream=None, shot_noise=True, noise="analytic"):
+    """Scoccimarro B_l or TripoSH B_l0l of one catalog pair, with analytic shot
+    noise; noise="fft" (TripoSH) takes the i = j != k term by the FFT method."""
     sc = scratch or Scratch()
+    method = noise
+    if method not in ("analytic", "fft"):
+        raise ValueError(f"unknown noise method {method!r}")
+    if method == "fft" and (estimator != L.EST_TRIPOSH or not shot_noise):
+        raise ValueError("the FFT-method shot noise is implemented for TripoSH with shot noise on")
     if precision is None:
         precision = L.PREC_F64 if desc.dtype == L.F64 else L.PREC_F32
     plan = bispec_plan(desc, bins, estimator, ell, precision, sc, stream)
@@ -335,7 +354,7 @@ def measure_bk(desc, gpos, rpos, bins, estimator=L.EST_SCOCCIMARRO, ell=0, preci
     if ell > 0:
         ylm = ylm_spectra(desc, band, [ell], dint, sc, stream)
         Fl = assemble(desc, band, ell, ylm=ylm[ell], stream=stream)
-    noise = None
+    rows = None  # noise_means rows of cnpc_bispectrum
     if shot_noise:
         DN, nint = deinterlace(desc, band, nmesh, want_real=ell > 0, scratch=sc, stream=stream)
         FN0 = assemble(desc, band, 0, spec0=DN, stream=stream)
@@ -345,16 +364,23 @@ def measure_bk(desc, gpos, rpos, bins, estimator=L.EST_SCOCCIMARRO, ell=0, preci
             FNl = assemble(desc, band, ell, ylm=ylmN[ell], stream=stream)
         means, selft, _, _ = bin_means(desc, plan.ext, band, [(Fl, FN0), (F0, FNl)], (ell,), norms, sc,
                                        stream)
-        noise = torch.cat([means, selft], 0).contiguous()
+        rows = torch.cat([means, selft], 0).contiguous()
     raw = _empty(plan.nconf, torch.float64)
     shot = _empty(plan.nconf, torch.float64)
     val = _empty(plan.nconf, torch.float64)
-    ws = sc.get(plan.ws_bytes)
     Fl_arg = Fl if (ell > 0 or estimator == L.EST_TRIPOSH) else None
-    L.check(L.lib.cnpc_bispectrum(plan.handle, L.ptr(F0), L.ptr(Fl_arg), L.ptr(noise), L.ptr(norms),
-                                  L.ptr(raw), L.ptr(shot), L.ptr(val), L.ptr(ws), ws.numel(),
-                                  _sh(stream)))
-    return {"raw": raw, "shot": shot, "value": val, "norms": norms, "plan": plan, "noise": noise}
+    if method == "fft":
+        ind = plan.indicators(sc, stream)
+        ws = sc.get(plan.ws_bytes)
+        L.check(L.lib.cnpc_bispectrum_fft_noise(plan.handle, L.ptr(F0), L.ptr(Fl_arg), L.ptr(FN0), L.ptr(ind),
+                                                L.ptr(rows), L.ptr(norms), L.ptr(raw), L.ptr(shot),
+                                                L.ptr(val), L.ptr(ws), ws.numel(), _sh(stream)))
+    else:
+        ws = sc.get(plan.ws_bytes)
+        L.check(L.lib.cnpc_bispectrum(plan.handle, L.ptr(F0), L.ptr(Fl_arg), L.ptr(rows), L.ptr(norms),
+                                      L.ptr(raw), L.ptr(shot), L.ptr(val), L.ptr(ws), ws.numel(),
+                                      _sh(stream)))
+    return {"raw": raw, "shot": shot, "value": val, "norms": norms, "plan": plan, "noise": rows}
 
 
 def measure_pk_bk(desc, gpos, rpos, bins, plan: "BispecPlan", ells=(0, 2, 4), gw=None, rw=None,
@@ -404,6 +430,59 @@ def _spectra_stage(desc, bins, plan, painted, ells, sc: Scratch, stream, out):
                                   _sh(stream)))
     res["nmodes"] = nmodes
     return res
+
+
+class NativeBatch:
+    """The library's own batch (cnpc_batch_*): measure_pk_bk for many catalog
+    pairs, round-robin over `nstreams` streams owned by the library, each with
+    its slab of one workspace; run() enqueues eagerly, capture() records the
+    same work into a HIP graph held by the library and replay() launches it.
+    The captured graph keeps the catalog, output and workspace addresses, so
+    this object holds references to them."""
+
+    def __init__(self, desc, bins, plan: "BispecPlan", ells=(0, 2, 4), nstreams: int = 4,
+                 max_ngal: int = 1, max_nran: int = 1, device="cuda"):
+        ells = [int(l) for l in ells]
+        h = C.c_void_p()
+        arr = (C.c_int32 * len(ells))(*ells)
+        L.check(L.lib.cnpc_batch_create(C.byref(h), C.byref(desc), C.byref(bins), plan.handle, len(ells), arr,
+                                        int(nstreams), int(max_ngal), int(max_nran)))
+        self.handle = h
+        self.plan = plan  # the library keeps a pointer to it
+        self.nstreams = int(nstreams)
+        self.ws = torch.empty(max(256, L.lib.cnpc_batch_workspace_size(h)), dtype=torch.uint8, device=device)
+        self._held = None
+
+    def _args(self, catalogs, outs):
+        n = len(catalogs)
+        if n != len(outs) or n == 0:
+            raise ValueError("need one output dict per catalog and at least one catalog")
+        P = C.c_void_p * n
+        I = C.c_int64 * n
+        weighted = any(len(c) > 2 and c[2] is not None for c in catalogs)
+        gw = P(*[L.ptr(c[2]) if len(c) > 2 else None for c in catalogs]) if weighted else None
+        rw = P(*[L.ptr(c[3]) if len(c) > 3 else None for c in catalogs]) if weighted else None
+        return (n, P(*[L.ptr(c[0]) for c in catalogs]), gw, I(*[int(c[0].shape[1]) for c in catalogs]),
+                P(*[L.ptr(c[1]) for c in catalogs]), rw, I(*[int(c[1].shape[1]) for c in catalogs]),
+                P(*[L.ptr(o["pk"]) for o in outs]), P(*[L.ptr(o["bk"]) for o in outs]))
+
+    def run(self, catalogs, outs, stream=None):
+        a = self._args(catalogs, outs)
+        L.check(L.lib.cnpc_batch_run(self.handle, *a, L.ptr(self.ws), self.ws.numel(), _sh(stream)))
+
+    def capture(self, catalogs, outs):
+        a = self._args(catalogs, outs)
+        L.check(L.lib.cnpc_batch_capture(self.handle, *a, L.ptr(self.ws), self.ws.numel()))
+        self._held = (list(catalogs), list(outs))
+
+    def replay(self, stream=None):
+        L.check(L.lib.cnpc_batch_replay(self.handle, _sh(stream)))
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            L.lib.cnpc_batch_destroy(h)
+            self.handle = None
 
 
 def balanced_assignment(sizes: Sequence[int], nstreams: int, mixed: bool = False):

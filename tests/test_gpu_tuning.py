@@ -98,7 +98,8 @@ def test_contract_point_groups_20_shells(est, ell, kg):
     assert P.rel(val, ora[key]) < 1e-3
 
 
-def test_autotune_batch(tmp_path):
+@pytest.mark.parametrize("engine", ["torch", "native"])
+def test_autotune_batch(tmp_path, engine):
     """The tuner returns a valid setting, leaves the knobs set to it, caches
     it, and the tuned batch gives the default batch's results."""
     n, box = 32, 1000.0
@@ -112,19 +113,23 @@ def test_autotune_batch(tmp_path):
     ref = [(P.host(o["pk"]).copy(), P.host(o["bk"]).copy()) for o in ref]
     path = str(tmp_path / "tune.json")
     try:
-        res = autotune.tune_batch(d, cats, bins, plan, streams=(1, 2), reps=1, cache=path)
+        res = autotune.tune_batch(d, cats, bins, plan, streams=(1, 2), reps=1, cache=path, engine=engine)
         assert res.streams in (1, 2) and not res.cached and len(res.trials) >= 5
         assert res.staged in (False, True)
         assert res.ms > 0 and res.default_ms > 0
         assert autotune.get_knobs() == res.knobs
         for k, v in res.knobs.items():
             assert v in L.TUNE[k][1]
-        again = autotune.tune_batch(d, cats, bins, plan, streams=(1, 2), reps=1, cache=path)
+        again = autotune.tune_batch(d, cats, bins, plan, streams=(1, 2), reps=1, cache=path, engine=engine)
         assert again.cached and again.knobs == res.knobs and again.streams == res.streams
         assert again.staged == res.staged
         outs = [{"pk": torch.empty((9, 4), dtype=torch.float64, device="cuda"),
                  "bk": torch.empty((3, plan.nconf), dtype=torch.float64, device="cuda")} for _ in cats]
-        pl.Batch(res.streams, staged=res.staged).run(d, cats, bins, plan, outs)
+        if engine == "native":
+            pl.NativeBatch(d, bins, plan, nstreams=res.streams, max_ngal=max(g.shape[1] for g, _ in cats),
+                           max_nran=max(r.shape[1] for _, r in cats)).run(cats, outs)
+        else:
+            pl.Batch(res.streams, staged=res.staged).run(d, cats, bins, plan, outs)
         torch.cuda.synchronize()
         for (pk, bk), o in zip(ref, outs):
             assert P.rel(P.host(o["pk"]), pk) < 1e-5
