@@ -238,9 +238,11 @@ cnpc_status cnpc_bin_pk_im(const cnpc_mesh_desc* desc, const cnpc_kbins* bins, i
 cnpc_status cnpc_pk_multipole(const cnpc_kbins* bins, int32_t ell, const double* mean,
                               const double* norms, double* out, void* stream);
 
-/* Normalisations of the cross multipoles of two tracers A, B (auto and cross
- * spectra of several tracers): the norms of A with I22 = sqrt(I22_A I22_B)
- * and N0 = 0 (distinct samples share no galaxy).  All device, CNPC_NORMS_LEN
+/* Normalisations of the cross multipoles of two tracers A, B (the toolkit
+ * section's core functionality: auto and cross correlations of several
+ * tracers; the paper gives no normalisation, this is the library's reading):
+ * the norms of A with I22 = sqrt(I22_A I22_B) and N0 = 0 (distinct samples
+ * share no galaxy).  All device, CNPC_NORMS_LEN
  * doubles. */
 cnpc_status cnpc_cross_norms(const double* norms_a, const double* norms_b, double* norms_out,
                              void* stream);
