@@ -319,8 +319,9 @@ class BispecPlan:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h is not None and h.value:
-            L.lib.cnpc_bispec_plan_destroy(h)
+        lib = getattr(L, "lib", None) if L is not None else None  # None at interpreter exit
+        if h is not None and h.value and lib is not None:
+            lib.cnpc_bispec_plan_destroy(h)
             self.handle = None
 
 
@@ -480,8 +481,9 @@ class NativeBatch:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h is not None and h.value:
-            L.lib.cnpc_batch_destroy(h)
+        lib = getattr(L, "lib", None) if L is not None else None  # None at interpreter exit
+        if h is not None and h.value and lib is not None:
+            lib.cnpc_batch_destroy(h)
             self.handle = None
 
 
