@@ -574,7 +574,18 @@ def cpu_baseline(mocks, sizes, log=print):
                       f"repeat count; sums and painting then scaled to the mean mock "
                       f"(N_g={float(np.mean(sizes)):.3g}); numpy FFT single-threaded",
             "seconds_per_catalog": total, "parts_s": {k: round(v, 2) for k, v in parts.items()},
-            "omp_threads_env": threads}
+            "omp_threads_env": threads, "host_cpus": os.cpu_count(), "cpu_model": _cpu_model()}
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 if __name__ == "__main__":
