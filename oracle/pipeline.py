@@ -129,3 +129,19 @@ def measure_bk(gpos, gw, rpos, rw, cfg: MeshConfig, dk, nbins, ells=(0, 2),
             out[f"BB{l}0{l}_pairsum"] = T
             out[f"BB{l}0{l}_shot_fft"], out[f"BB{l}0{l}_fft"] = sf, raw - sf
     return out
+
+
+def measure_sugiyama(gpos, gw, rpos, rw, cfg: MeshConfig, dk, nbins, l1, l2, L):
+    """Sugiyama B_l1l2L(k_i, k_j) (all i, j) with its analytic shot noise (kmin = 0)."""
+    from . import sugiyama as sg
+    obs = cfg.observer
+    norms, W, F, FN = fkp_spectra(gpos, gw, rpos, rw, cfg, tuple(sorted({0, L})), noise_ells=(L,))
+    delta, _ = ms.paint_fkp(gpos, gw, rpos, rw, norms.alpha, cfg.nmesh, cfg.assign, cfg.interlace,
+                            noise=False)
+    _, dint = ms.deinterlace(delta[0], delta[1] if cfg.interlace else None)
+    bins = sp.Bins(0.0, dk, nbins, cfg.boxsize, cfg.nmesh)
+    ext = sp.Bins(0.0, dk, 2 * nbins - 1, cfg.boxsize, cfg.nmesh)
+    raw = sg.sugiyama_raw(F[0], dint, W, l1, l2, L, bins, norms.I33, cfg.boxsize, obs, cfg.los)
+    Q, H, _ = noise_terms(F, FN, L, ext, norms, W, cfg)
+    shot = sg.sugiyama_shot(l1, l2, L, nbins, Q, H, ext.counts(), ext.centres(), norms.I33, norms.Sbar)
+    return {"norms": norms, "raw": raw, "shot": shot, "value": raw - shot, "nmodes": bins.counts()}
