@@ -283,6 +283,7 @@ cnpc_status cnpc_pk_finalize(const cnpc_kbins* bins, const double* mean00, const
 #define CNPC_PREC_BF16X3 2
 #define CNPC_EST_SCOCCIMARRO 0
 #define CNPC_EST_TRIPOSH 1
+#define CNPC_EST_SUGIYAMA 2 /* plans of cnpc_sugi_plan_create only */
 
 typedef struct cnpc_bispec_plan cnpc_bispec_plan;
 /* Creates the plan (host tables: configurations, triangle counts N_T computed
@@ -311,6 +312,43 @@ cnpc_status cnpc_bispec_ext_bins(const cnpc_bispec_plan* plan, cnpc_kbins* ext);
 cnpc_status cnpc_bispectrum(const cnpc_bispec_plan* plan, const void* F0, const void* Fl,
                             const double* noise_means, const double* norms, double* raw,
                             double* shot, double* value, void* ws, size_t ws_bytes, void* stream);
+
+/* ---- Sugiyama bispectrum multipoles B_l1l2L (section "Sugiyama estimator":
+ * eq. sugi_estimator with eq. F_and_G, the pairing of eq. sym_sugi into
+ * eta Re[...]; shot noise of eqs. S3_sugi_new, q_ells and sugi_shot) ----
+ *   F_l^m(x; k) = 1/N_k sum_{q in shell k} e^{iq.x} y_l^m*(qhat) F_0(q)
+ *   G_L^M(x)    = sum_q e^{iq.x} FFT[delta y_L^M*(xhat)](q) / W(q)
+ *   B(k_i, k_j) = H N / I33 sum_{paired (m1, m2, M)} eta (l1 l2 L; m1 m2 M)
+ *                 Re 1/G^3 sum_x F_l1^m1(x; k_i) F_l2^m2(x; k_j) G_L^M(x)
+ * with y the Racah-normalised harmonics, H = (l1 l2 L; 0 0 0),
+ * N = (2l1+1)(2l2+1)(2L+1); the pairs (m1, m2, M), (-m1, -m2, -M) are taken
+ * once (M < 0, or M = 0 with m1 <= 0), eta = 2 except (0, 0, 0).  Every
+ * field is a real c2r on the plan's grid: F_l^m = c2r[Phi F_0 Re y] +
+ * i c2r[Phi F_0 (-Im y)], G_L^M from the Y_L^M r2c spectra of delta; each
+ * sub-configuration is up to four shell-pair contractions.
+ * Shot noise: delta_l10 delta_l20 delta_L0 Sbar + delta_l1L delta_l20 (2L+1)
+ * H_L(k_i) + delta_l2L delta_l10 (2L+1) H_L(k_j) + H N sum_c q(k_i, k_j, k_c)
+ * (N_c/k_c) Q_L(k_c) / sum_c N_c/k_c, all over I33, with q of eq. q_ells
+ * (Racah-normalised associated Legendre functions, cosines of the closed
+ * triangle of bin centres) and c over the bins |i-j| .. i+j.
+ * cnpc_sugi_plan_create: l1, l2, L in {0, 2, 4} with the triangle rule;
+ * kmin = 0 and (2 nbins - 1) dk below Nyquist; precision as for
+ * cnpc_bispec_plan_create, split BF16 for at most 22 shells.  Destroy with
+ * cnpc_bispec_plan_destroy; cnpc_bispec_band / _grid / _ext_bins /
+ * _nconfigs (nbins^2, every (i, j)) apply.
+ * cnpc_sugiyama: F0 the band spectrum of F_0 (cnpc_assemble_F, l = 0, at the
+ * plan's band); ylm the 2L+1 band spectra of cnpc_ylm_r2c for l = L of the
+ * de-interlaced delta (NULL when L = 0); noise_means the Q_L, H_L, s_L rows
+ * of cnpc_bin_pk on the plan's extended bins (pairs (F_L, N_0), (F_0, F_L^N),
+ * self term L), or NULL for no shot noise; raw, shot, value: nbins x nbins
+ * device FP64, row i = k_1 bin.  ws: cnpc_sugi_workspace_size bytes.  Errors:
+ * CNPC_EINVAL (arguments, a plan of another estimator), CNPC_EWORKSPACE. */
+size_t cnpc_sugi_workspace_size(const cnpc_mesh_desc* desc, const cnpc_kbins* bins);
+cnpc_status cnpc_sugi_plan_create(cnpc_bispec_plan** plan, const cnpc_mesh_desc* desc, const cnpc_kbins* bins,
+                                  int32_t l1, int32_t l2, int32_t L, int32_t precision);
+cnpc_status cnpc_sugiyama(const cnpc_bispec_plan* plan, const void* F0, const void* ylm,
+                          const double* noise_means, const double* norms, double* raw, double* shot,
+                          double* value, void* ws, size_t ws_bytes, void* stream);
 
 /* ---- FFT-method shot noise of the TripoSH BB_l0l (the reference method of
  * the section validating the analytic shot noise, applied to the i = j != k

@@ -17,7 +17,7 @@ F32, F64 = 0, 1
 CIC, TSC = 2, 3
 LOS_LOCAL, LOS_GLOBAL = 0, 1
 PREC_F64, PREC_F32, PREC_BF16X3 = 0, 1, 2
-EST_SCOCCIMARRO, EST_TRIPOSH = 0, 1
+EST_SCOCCIMARRO, EST_TRIPOSH, EST_SUGIYAMA = 0, 1, 2
 NYLM_SUMS = 9
 SUMS_LEN = 3 + 2 * NYLM_SUMS
 NORMS_LEN = 6 + 2 * NYLM_SUMS
@@ -99,6 +99,9 @@ _PROTOS = {
                                   C.POINTER(_vp), C.POINTER(_i64), C.POINTER(_vp), C.POINTER(_vp), _vp, _sz]),
     "cnpc_batch_replay": (_i32, [_vp, _vp]),
     "cnpc_batch_destroy": (None, [_vp]),
+    "cnpc_sugi_workspace_size": (_sz, [_PD, _PB]),
+    "cnpc_sugi_plan_create": (_i32, [C.POINTER(_vp), _PD, _PB, _i32, _i32, _i32, _i32]),
+    "cnpc_sugiyama": (_i32, [_vp, _cvp, _cvp, _cvp, _cvp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "cnpc_bispec_indicator_bytes": (_sz, [_vp]),
     "cnpc_bispec_indicators": (_i32, [_vp, _vp, _vp, _sz, _vp]),
     "cnpc_bispectrum_fft_noise": (_i32, [_vp, _cvp, _cvp, _cvp, _cvp, _cvp, _cvp, _vp, _vp, _vp, _vp, _sz,

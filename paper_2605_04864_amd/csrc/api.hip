@@ -484,6 +484,8 @@ cnpc_status cnpc_bispectrum(const cnpc_bispec_plan* p, const void* F0, const voi
   API_BEGIN;
   CNPC_REQUIRE(p != nullptr, "null plan");
   CNPC_REQUIRE(F0 && norms && raw && shot && value && ws, "null pointer argument");
+  CNPC_REQUIRE(p->est == CNPC_EST_SCOCCIMARRO || p->est == CNPC_EST_TRIPOSH,
+               "a Sugiyama plan runs through cnpc_sugiyama");
   CNPC_REQUIRE(p->ell == 0 || p->est == CNPC_EST_TRIPOSH || Fl != nullptr, "B_l with l > 0 needs F_l");
   CNPC_REQUIRE(p->est != CNPC_EST_TRIPOSH || Fl != nullptr, "TripoSH needs F_l (F_0 for l = 0)");
   return bispec_run(p, F0, Fl, nullptr, nullptr, noise_means, norms, raw, shot, value, ws, ws_bytes,

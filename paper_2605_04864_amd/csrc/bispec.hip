@@ -813,6 +813,7 @@ void bispec_plan_destroy(cnpc_bispec_plan* P) {
   if (P->d_aux) (void)hipFree(P->d_aux);
   if (P->d_counts) (void)hipFree(P->d_counts);
   if (P->d_wq) (void)hipFree(P->d_wq);
+  if (P->d_wq3) (void)hipFree(P->d_wq3);
   delete P;
 }
 

@@ -6,3 +6,4 @@
 #include "bispec.hip"
 #include "api.hip"
 #include "batch.hip"
+#include "sugiyama.hip"

@@ -1,0 +1,440 @@
+// Sugiyama bispectrum multipoles B_l1l2L (tripolar spherical-harmonic
+// expansion; section "Sugiyama estimator", eq. sugi_estimator with eq. F_and_G,
+// the pairing of eq. sym_sugi, and the shot noise of eqs. S3_sugi_new, q_ells
+// and sugi_shot), for even l1, l2, L.
+//
+// Fields on the contraction grid (all real, c2r of Hermitian band spectra):
+//   F_l^m(x; k) = a + i b,  a = c2r[Phi_k F_0 Re y_l^m],  b = c2r[Phi_k F_0 (-Im y_l^m)]
+//   G_L^M(x)    = g + i h,  for M >= 0: g = c2r[A_M / W], h = -c2r[B_M / W]
+//                 (A_M, B_M: r2c of delta Re / Im y_L^M(xhat)); M < 0 by
+//                 G^M = (-1)^M conj(G^-M)
+// (the 1/N_k of F is applied at the end).  Each paired sub-configuration adds
+//   Re[F1 F2 G] = (a1 a2 - b1 b2) g - (a1 b2 + b1 a2) h
+// as up to four contractions sum_x P_i Q_j Z over the shell pairs (i, j),
+// with P, Q the k1 and k2 shell fields and Z = g or h.
+#include "bispec.h"
+
+namespace cnpc {
+
+// ------------------------------------------------------------- host math --
+static double fact(int n) {
+  double f = 1.0;
+  for (int i = 2; i <= n; ++i) f *= i;
+  return f;
+}
+
+// Wigner 3j symbol, Racah formula
+static double wigner3j_host(int j1, int j2, int j3, int m1, int m2, int m3) {
+  if (m1 + m2 + m3 != 0 || j3 < std::abs(j1 - j2) || j3 > j1 + j2) return 0.0;
+  if (std::abs(m1) > j1 || std::abs(m2) > j2 || std::abs(m3) > j3) return 0.0;
+  const double tri = fact(j1 + j2 - j3) * fact(j1 - j2 + j3) * fact(-j1 + j2 + j3) / fact(j1 + j2 + j3 + 1);
+  const double pref = tri * fact(j1 + m1) * fact(j1 - m1) * fact(j2 + m2) * fact(j2 - m2) * fact(j3 + m3) *
+                      fact(j3 - m3);
+  double s = 0.0;
+  for (int k = 0; k <= j1 + j2 + j3; ++k) {
+    const int d[6] = {k, j1 + j2 - j3 - k, j1 - m1 - k, j2 + m2 - k, j3 - j2 + m1 + k, j3 - j1 - m2 + k};
+    bool ok = true;
+    double den = 1.0;
+    for (int t = 0; t < 6; ++t) {
+      if (d[t] < 0) { ok = false; break; }
+      den *= fact(d[t]);
+    }
+    if (ok) s += ((k & 1) ? -1.0 : 1.0) / den;
+  }
+  return (((j1 - j2 - m3) % 2 + 2) % 2 ? -1.0 : 1.0) * std::sqrt(pref) * s;
+}
+
+// Racah-normalised associated Legendre function y_l^n(theta, phi = 0) with
+// cos theta = mu: sqrt((l-n)!/(l+n)!) P_l^n(mu), Condon-Shortley phase in
+// P_l^n, and y_l^-n = (-1)^n y_l^n on phi = 0.
+static double racah_plm_host(int l, int n, double mu) {
+  const int an = std::abs(n);
+  if (an > l) return 0.0;
+  const double st = std::sqrt(std::max(0.0, 1.0 - mu * mu));
+  double pmm = 1.0;  // P_m^m = (-1)^m (2m-1)!! st^m
+  for (int i = 1; i <= an; ++i) pmm *= -(2.0 * i - 1.0) * st;
+  double p = pmm;
+  if (l > an) {
+    double pm1 = mu * (2.0 * an + 1.0) * pmm;  // P_{m+1}^m
+    p = pm1;
+    for (int ll = an + 2; ll <= l; ++ll) {
+      const double pn = ((2.0 * ll - 1.0) * mu * pm1 - (ll + an - 1.0) * pmm) / (ll - an);
+      pmm = pm1;
+      pm1 = pn;
+      p = pn;
+    }
+  }
+  const double y = std::sqrt(fact(l - an) / fact(l + an)) * p;
+  return (n < 0 && (an & 1)) ? -y : y;
+}
+
+// q_l1l2L(k1, k2, k3) with the cosines of the closed triangle
+static double q_factor_host(int l1, int l2, int L, double k1, double k2, double k3) {
+  auto clip = [](double x) { return x > 1.0 ? 1.0 : (x < -1.0 ? -1.0 : x); };
+  const double mu13 = clip((k2 * k2 - k1 * k1 - k3 * k3) / (2.0 * k1 * k3));
+  const double mu23 = clip((k1 * k1 - k2 * k2 - k3 * k3) / (2.0 * k2 * k3));
+  double s = 0.0;
+  const int nm = std::min(l1, l2);
+  for (int n = -nm; n <= nm; ++n) {
+    const double w = wigner3j_host(l1, l2, L, n, -n, 0);
+    if (w == 0.0) continue;
+    s += ((n & 1) ? -1.0 : 1.0) * racah_plm_host(l1, n, mu13) * racah_plm_host(l2, -n, mu23) * w;
+  }
+  return s;
+}
+
+// --------------------------------------------------------------- kernels --
+// out = F0(q) * (part == 0 ? Re y_l^m(qhat) : -Im y_l^m(qhat)) on the band
+template <typename T>
+__global__ void __launch_bounds__(256) k_weight_ylm(int m, int ell, int em, int part,
+                                                    const cx<T>* __restrict__ F0, cx<T>* __restrict__ out) {
+  const int64_t bsz = (int64_t)4 * m * m * m;
+  const int am = em < 0 ? -em : em;
+  const double sg = (em < 0 && (am & 1)) ? -1.0 : 1.0;  // y^-m = (-1)^m conj(y^m)
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < bsz;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int kz = (int)(i % m);
+    const int jy = (int)((i / m) % (2 * m));
+    const int jx = (int)(i / ((int64_t)2 * m * m));
+    const int nx = band_freq(jx, m), ny = band_freq(jy, m), nz = kz;
+    const int64_t n2 = (int64_t)nx * nx + (int64_t)ny * ny + (int64_t)nz * nz;
+    double wgt = 0.0;
+    if (n2 > 0) {
+      const double kn = sqrt((double)n2);
+      double yr[5], yi[5];
+      racah_ylm<double>(ell, nx / kn, ny / kn, nz / kn, yr, yi);
+      const double re = sg * yr[am], im = (em < 0 ? -sg : sg) * yi[am];
+      wgt = part == 0 ? re : -im;
+    }
+    const cx<T> f = F0[i];
+    out[i] = cx<T>{T(wgt * (double)f.x), T(wgt * (double)f.y)};
+  }
+}
+
+// out = scale * in / W(q) on the band of an n^3 mesh; zero at q = 0 and on
+// modes with a Nyquist component
+template <typename T>
+__global__ void __launch_bounds__(256) k_div_window(int n, int m, int assign, double scale,
+                                                    const cx<T>* __restrict__ in, cx<T>* __restrict__ out) {
+  const int64_t bsz = (int64_t)4 * m * m * m;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < bsz;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int kz = (int)(i % m);
+    const int jy = (int)((i / m) % (2 * m));
+    const int jx = (int)(i / ((int64_t)2 * m * m));
+    const int nx = band_freq(jx, m), ny = band_freq(jy, m), nz = kz;
+    const bool zero = (nx == 0 && ny == 0 && nz == 0) || nx == -(n / 2) || ny == -(n / 2) || nz == n / 2;
+    if (zero) {
+      out[i] = cx<T>{T(0), T(0)};
+      continue;
+    }
+    const double W = window_1d(nx, n, assign) * window_1d(ny, n, assign) * window_1d(nz, n, assign);
+    const cx<T> a = in[i];
+    out[i] = cx<T>{T(scale * (double)a.x / W), T(scale * (double)a.y / W)};
+  }
+}
+
+// acc[i][j] += coef * C[pair (i, nb + j) of 2 nb shells]
+__global__ void k_sugi_accum(const double* __restrict__ C, int nb, double coef, double* __restrict__ acc) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nb * nb) return;
+  const int i = t / nb, j = t - i * nb;
+  const int ns = 2 * nb, a = i, b = nb + j;
+  const int p = a * ns - a * (a - 1) / 2 + (b - a);
+  acc[t] += coef * C[p];
+}
+
+struct SugiFin {
+  int l1, l2, L, nb, next;
+  double hn, n3;
+  const double* counts;
+  const double* wq3;
+};
+
+__global__ void k_sugi_finalize(SugiFin f, const double* __restrict__ acc, const double* __restrict__ noise,
+                                const double* __restrict__ nm, double* __restrict__ raw,
+                                double* __restrict__ shot, double* __restrict__ value) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= f.nb * f.nb) return;
+  const int i = t / f.nb, j = t - i * f.nb;
+  const double I33 = nm[CNPC_NORM_I33], Sbar = nm[CNPC_NORM_SBAR];
+  const double r = f.hn / I33 * acc[t] / (f.n3 * f.counts[i] * f.counts[j]);
+  double sh = 0.0;
+  if (noise) {
+    const int ne = f.next;
+    const double* Q = noise;
+    const double* H = noise + ne;
+    const double* S = noise + 2 * ne;
+    double v = 0.0;
+    if (f.l1 == 0 && f.l2 == 0 && f.L == 0) v += Sbar;
+    if (f.l1 == f.L && f.l2 == 0) v += (2.0 * f.L + 1.0) * (H[i] - S[i]);
+    if (f.l2 == f.L && f.l1 == 0) v += (2.0 * f.L + 1.0) * (H[j] - S[j]);
+    const double* w = f.wq3 + (int64_t)t * ne;
+    double q = 0.0;
+    for (int c = 0; c < ne; ++c) q += w[c] * (Q[c] - S[c]);
+    v += f.hn * q;
+    sh = v / I33;
+  }
+  raw[t] = r;
+  shot[t] = sh;
+  value[t] = r - sh;
+}
+
+// ------------------------------------------------------------------ plan --
+static size_t sugi_ws_bytes(const cnpc_mesh_desc* d, const cnpc_kbins* b) {
+  const BispecGeom g = bispec_geometry(d, b, CNPC_EST_TRIPOSH, 0);
+  const int nb = b->nbins, m = g.band;
+  const size_t g3 = (size_t)g.grid * g.grid * g.grid, es = esize(d->dtype);
+  const size_t npairs2 = (size_t)(2 * nb) * (2 * nb + 1) / 2;
+  return (size_t)(2 * nb + 2) * g3 * es + (size_t)4 * m * m * m * 2 * es +
+         shell_c2r_ws_elems(g.grid, m, nb) * 2 * es +
+         (contract_partial_doubles(2 * nb, 1) + npairs2 + (size_t)nb * nb) * 8 + 8192;
+}
+
+static cnpc_status sugi_plan_create(cnpc_bispec_plan** out, const cnpc_mesh_desc* d, const cnpc_kbins* b, int l1,
+                                    int l2, int L, int prec) {
+  auto* P = new cnpc_bispec_plan();
+  P->desc = *d;
+  P->bins = *b;
+  P->est = CNPC_EST_SUGIYAMA;
+  P->ell = L;
+  P->prec = prec;
+  P->l1 = l1;
+  P->l2 = l2;
+  P->L = L;
+  P->nb = b->nbins;
+  P->thr.resize(P->nb + 1);
+  bin_thresholds(d, b, P->thr.data());
+  P->ext = *b;
+  P->ext.nbins = 2 * P->nb - 1;
+  P->next = P->ext.nbins;
+  const BispecGeom geo = bispec_geometry(d, b, CNPC_EST_TRIPOSH, 0);
+  P->band = geo.band;
+  P->grid = geo.grid;
+  P->nfields = 2 * P->nb + 2;
+  P->counts = mode_counts(d, P->thr, P->nb);
+  std::vector<int64_t> thr_ext(P->next + 1);
+  bin_thresholds(d, &P->ext, thr_ext.data());
+  P->counts_ext = mode_counts(d, thr_ext, P->next);
+  P->wq.resize(P->next);
+  for (int c = 0; c < P->next; ++c) P->wq[c] = (double)P->counts_ext[c] / (b->kmin + (c + 0.5) * b->dk);
+  // paired sub-configurations: M < 0, or M = 0 with m1 <= 0; eta = 2 except (0, 0, 0)
+  for (int M = -L; M <= 0; ++M)
+    for (int m1 = -l1; m1 <= l1; ++m1) {
+      const int m2 = -m1 - M;
+      if (std::abs(m2) > l2 || (M == 0 && m1 > 0)) continue;
+      const double w = wigner3j_host(l1, l2, L, m1, m2, M);
+      if (w == 0.0) continue;
+      P->sub.push_back(m1);
+      P->sub.push_back(m2);
+      P->sub.push_back(M);
+      P->subw.push_back((m1 == 0 && m2 == 0 && M == 0) ? w : 2.0 * w);
+    }
+  P->hn = wigner3j_host(l1, l2, L, 0, 0, 0) * (2 * l1 + 1) * (2 * l2 + 1) * (2 * L + 1);
+  // every (k1, k2) pair of shells
+  const int nb = P->nb;
+  for (int i = 0; i < nb; ++i)
+    for (int j = 0; j < nb; ++j) {
+      P->cfg.push_back(i); P->cfg.push_back(j); P->cfg.push_back(-1);
+      P->ntri.push_back(0);
+      P->aux.push_back(0.0); P->aux.push_back(0.0);
+    }
+  P->nconf = nb * nb;
+  // k3 weights of the i = j != k term: q(k1, k2, k_c) N_c/k_c / sum_c N_c/k_c
+  std::vector<double> wq3((size_t)nb * nb * P->next, 0.0);
+  for (int i = 0; i < nb; ++i)
+    for (int j = 0; j < nb; ++j) {
+      const int c0 = std::abs(i - j), c1 = i + j;
+      double den = 0.0;
+      for (int c = c0; c <= c1; ++c) den += P->wq[c];
+      const double ki = b->kmin + (i + 0.5) * b->dk, kj = b->kmin + (j + 0.5) * b->dk;
+      for (int c = c0; c <= c1; ++c) {
+        const double kc = b->kmin + (c + 0.5) * b->dk;
+        wq3[((size_t)i * nb + j) * P->next + c] = q_factor_host(l1, l2, L, ki, kj, kc) * P->wq[c] / den;
+      }
+    }
+  cnpc_status st = device_tables(P);
+  if (st == CNPC_OK) st = upload_tables(P);
+  if (st == CNPC_OK) {
+    if (hipMalloc(&P->d_wq3, sizeof(double) * wq3.size()) != hipSuccess ||
+        hipMemcpy(P->d_wq3, wq3.data(), sizeof(double) * wq3.size(), hipMemcpyHostToDevice) != hipSuccess) {
+      set_error("device tables of the Sugiyama plan failed");
+      st = CNPC_EHIP;
+    }
+  }
+  if (st != CNPC_OK) {
+    bispec_plan_destroy(P);
+    return st;
+  }
+  *out = P;
+  return CNPC_OK;
+}
+
+// ------------------------------------------------------------------- run --
+template <typename T>
+static cnpc_status sugi_run_t(const cnpc_bispec_plan* P, const cx<T>* F0, const cx<T>* ylm, const double* noise,
+                              const double* norms, double* raw, double* shot, double* value, void* ws,
+                              size_t ws_bytes, hipStream_t s) {
+  cnpc_mesh_desc dg = P->desc;
+  dg.n = P->grid;
+  const int G = P->grid, m = P->band, nb = P->nb;
+  const int64_t n3 = (int64_t)G * G * G, bsz = (int64_t)4 * m * m * m;
+  const int npairs2 = (2 * nb) * (2 * nb + 1) / 2;
+  unsigned char* w = align256(reinterpret_cast<unsigned char*>(ws));
+  T* fields = reinterpret_cast<T*>(w);  // [P: nb][Q: nb][g][h]
+  cx<T>* spec = reinterpret_cast<cx<T>*>(align256(reinterpret_cast<unsigned char*>(fields + (int64_t)(2 * nb + 2) * n3)));
+  cx<T>* scr = reinterpret_cast<cx<T>*>(align256(reinterpret_cast<unsigned char*>(spec + bsz)));
+  double* partial = reinterpret_cast<double*>(align256(reinterpret_cast<unsigned char*>(scr + shell_c2r_ws_elems(G, m, nb))));
+  double* Cm = partial + contract_partial_doubles(2 * nb, 1);
+  double* acc = Cm + npairs2;
+  const size_t need = reinterpret_cast<unsigned char*>(acc + (size_t)nb * nb) - reinterpret_cast<unsigned char*>(ws);
+  if (need > ws_bytes) {
+    set_error("Sugiyama workspace too small: need %zu, got %zu", need, ws_bytes);
+    return CNPC_EWORKSPACE;
+  }
+  CNPC_TRY(ensure_twiddles());
+  const unsigned gb = (unsigned)std::min<int64_t>((bsz + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_zero_f64, dim3(1), dim3(256), 0, s, acc, (int64_t)nb * nb);
+  CNPC_HIP(hipGetLastError());
+  T* slotP = fields;
+  T* slotQ = fields + (int64_t)nb * n3;
+  T* slotG = fields + (int64_t)2 * nb * n3;
+  T* slotH = slotG + n3;
+  // leg field (l, m, part) of every shell into a slot
+  auto load_leg = [&](T* slot, int ell, int em, int part) -> cnpc_status {
+    hipLaunchKernelGGL((k_weight_ylm<T>), dim3(gb), dim3(256), 0, s, m, ell, em, part, F0, spec);
+    CNPC_HIP(hipGetLastError());
+    return shell_c2r<T>(&dg, m, spec, P->thr.data(), nb + 1, 0, nb, true, slot, scr, s);
+  };
+  // one unmasked band c2r of scale * in / W into a slot
+  auto load_los = [&](T* slot, const cx<T>* in, double scale) -> cnpc_status {
+    hipLaunchKernelGGL((k_div_window<T>), dim3(gb), dim3(256), 0, s, P->desc.n, m, P->desc.assign, scale, in, spec);
+    CNPC_HIP(hipGetLastError());
+    return shell_c2r<T>(&dg, m, spec, P->thr.data(), nb + 1, 0, 1, false, slot, scr, s);
+  };
+  auto contract_add = [&](int col, double coef) -> cnpc_status {
+    ContractCols cc;
+    cc.ncols = 1;
+    cc.field[0] = 2 * nb + col;
+    if constexpr (sizeof(T) == 4) {
+      if (P->prec == CNPC_PREC_BF16X3) {
+        CNPC_TRY(contract_mfma(fields, n3, 2 * nb + 2, 2 * nb, cc, partial, Cm, s));
+      } else {
+        CNPC_TRY(contract_valu<T>(fields, n3, 2 * nb + 2, 2 * nb, cc, partial, Cm, s));
+      }
+    } else {
+      CNPC_TRY(contract_valu<T>(fields, n3, 2 * nb + 2, 2 * nb, cc, partial, Cm, s));
+    }
+    hipLaunchKernelGGL(k_sugi_accum, dim3((nb * nb + 255) / 256), dim3(256), 0, s, Cm, nb, coef, acc);
+    CNPC_HIP(hipGetLastError());
+    return CNPC_OK;
+  };
+  const int L = P->L;
+  int curM = 1;  // no line-of-sight field loaded yet (loaded M are <= 0)
+  for (size_t q = 0; q < P->subw.size(); ++q) {
+    const int m1 = P->sub[3 * q], m2 = P->sub[3 * q + 1], M = P->sub[3 * q + 2];
+    const double wgt = P->subw[q];
+    if (M != curM) {
+      // G^M = (-1)^M conj(G^|M|) for M < 0: g = (-1)^M c2r[A/W], h = (-1)^M c2r[B/W]
+      const int am = -M;
+      const double sg = (am & 1) ? -1.0 : 1.0;
+      const cx<T>* A = L == 0 ? F0 : ylm + (am == 0 ? 0 : (int64_t)(2 * am - 1) * bsz);
+      if (L == 0) {
+        // G_0^0 = c2r[F_0]: F_0 is already compensated
+        CNPC_TRY(shell_c2r<T>(&dg, m, F0, P->thr.data(), nb + 1, 0, 1, false, slotG, scr, s));
+      } else {
+        CNPC_TRY(load_los(slotG, A, am == 0 ? 1.0 : sg));
+        if (am > 0) CNPC_TRY(load_los(slotH, ylm + (int64_t)(2 * am) * bsz, sg));
+      }
+      curM = M;
+    }
+    // (a1 a2) g, then (a1 b2) h, (b1 b2) g, (b1 a2) h where present
+    int pq[2][3] = {{-99, 0, 0}, {-99, 0, 0}};  // slot contents: (m, part) tags
+    auto ensure = [&](int k, int ell, int em, int part) -> cnpc_status {
+      if (pq[k][0] == 1 && pq[k][1] == em && pq[k][2] == part) return CNPC_OK;
+      CNPC_TRY(load_leg(k == 0 ? slotP : slotQ, ell, em, part));
+      pq[k][0] = 1;
+      pq[k][1] = em;
+      pq[k][2] = part;
+      return CNPC_OK;
+    };
+    CNPC_TRY(ensure(0, P->l1, m1, 0));
+    CNPC_TRY(ensure(1, P->l2, m2, 0));
+    CNPC_TRY(contract_add(0, wgt));
+    if (m2 != 0 && M != 0) {
+      CNPC_TRY(ensure(1, P->l2, m2, 1));
+      CNPC_TRY(contract_add(1, -wgt));
+    }
+    if (m1 != 0) {
+      CNPC_TRY(ensure(0, P->l1, m1, 1));
+      if (m2 != 0) {
+        CNPC_TRY(ensure(1, P->l2, m2, 1));
+        CNPC_TRY(contract_add(0, -wgt));
+      }
+      if (M != 0) {
+        CNPC_TRY(ensure(1, P->l2, m2, 0));
+        CNPC_TRY(contract_add(1, -wgt));
+      }
+    }
+  }
+  SugiFin f;
+  f.l1 = P->l1;
+  f.l2 = P->l2;
+  f.L = P->L;
+  f.nb = nb;
+  f.next = P->next;
+  f.hn = P->hn;
+  f.n3 = (double)n3;
+  f.counts = P->d_counts;
+  f.wq3 = P->d_wq3;
+  hipLaunchKernelGGL(k_sugi_finalize, dim3((nb * nb + 255) / 256), dim3(256), 0, s, f, acc, noise, norms, raw,
+                     shot, value);
+  CNPC_HIP(hipGetLastError());
+  return CNPC_OK;
+}
+
+}  // namespace cnpc
+
+using namespace cnpc;
+
+extern "C" {
+
+size_t cnpc_sugi_workspace_size(const cnpc_mesh_desc* d, const cnpc_kbins* b) {
+  if (check_desc(d) != CNPC_OK || check_bins(d, b) != CNPC_OK) return 0;
+  return sugi_ws_bytes(d, b);
+}
+
+cnpc_status cnpc_sugi_plan_create(cnpc_bispec_plan** plan, const cnpc_mesh_desc* d, const cnpc_kbins* b,
+                                  int32_t l1, int32_t l2, int32_t L, int32_t prec) {
+  API_BEGIN;
+  CNPC_REQUIRE(plan != nullptr, "null plan pointer");
+  *plan = nullptr;
+  CNPC_TRY(check_desc(d));
+  CNPC_TRY(check_bins(d, b));
+  for (int l : {l1, l2, L}) CNPC_REQUIRE(l == 0 || l == 2 || l == 4, "l1, l2, L must be 0, 2 or 4");
+  CNPC_REQUIRE(L >= std::abs(l1 - l2) && L <= l1 + l2, "(l1, l2, L) must satisfy the triangle rule");
+  CNPC_REQUIRE(prec == CNPC_PREC_F64 || prec == CNPC_PREC_F32 || prec == CNPC_PREC_BF16X3, "unknown precision");
+  CNPC_REQUIRE(!(prec == CNPC_PREC_F64 && d->dtype != CNPC_F64), "CNPC_PREC_F64 needs FP64 fields");
+  CNPC_REQUIRE(!(prec != CNPC_PREC_F64 && d->dtype != CNPC_F32), "FP32 / split-BF16 contraction needs FP32 fields");
+  CNPC_REQUIRE(b->kmin == 0.0, "bispectrum bins must start at k = 0 (closure on bin centres)");
+  const double kny = M_PI * d->n / d->boxsize;
+  CNPC_REQUIRE((2 * b->nbins - 1) * b->dk <= kny, "the line-of-sight field needs bins up to 2 k_max below Nyquist");
+  CNPC_REQUIRE(prec != CNPC_PREC_BF16X3 || b->nbins <= 22, "split-BF16 Sugiyama contraction: at most 22 shells");
+  return sugi_plan_create(plan, d, b, l1, l2, L, prec);
+}
+
+cnpc_status cnpc_sugiyama(const cnpc_bispec_plan* p, const void* F0, const void* ylm, const double* noise_means,
+                          const double* norms, double* raw, double* shot, double* value, void* ws, size_t ws_bytes,
+                          void* stream) {
+  API_BEGIN;
+  CNPC_REQUIRE(p != nullptr && p->est == CNPC_EST_SUGIYAMA, "need a plan of cnpc_sugi_plan_create");
+  CNPC_REQUIRE(F0 && norms && raw && shot && value && ws, "null pointer argument");
+  CNPC_REQUIRE(p->L == 0 || ylm != nullptr, "L > 0 needs the Y_L^M spectra of delta");
+  if (p->desc.dtype == CNPC_F64)
+    return sugi_run_t<double>(p, (const cx<double>*)F0, (const cx<double>*)ylm, noise_means, norms, raw, shot,
+                              value, ws, ws_bytes, as_stream(stream));
+  return sugi_run_t<float>(p, (const cx<float>*)F0, (const cx<float>*)ylm, noise_means, norms, raw, shot, value,
+                           ws, ws_bytes, as_stream(stream));
+}
+
+}  // extern "C"

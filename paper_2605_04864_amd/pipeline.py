@@ -384,6 +384,73 @@ def measure_bk(desc, gpos, rpos, bins, estimator=L.EST_SCOCCIMARRO, ell=0, preci
     return {"raw": raw, "shot": shot, "value": val, "norms": norms, "plan": plan, "noise": rows}
 
 
+class SugiPlan:
+    """Plan of the Sugiyama B_l1l2L (cnpc_sugi_plan_create)."""
+
+    def __init__(self, desc, bins, l1, l2, L_, precision):
+        self.desc, self.bins = desc, bins
+        self.l1, self.l2, self.L, self.precision = int(l1), int(l2), int(L_), precision
+        h = C.c_void_p()
+        L.check(L.lib.cnpc_sugi_plan_create(C.byref(h), C.byref(desc), C.byref(bins), self.l1, self.l2, self.L,
+                                            precision))
+        self.handle = h
+        self.band = L.lib.cnpc_bispec_band(h)
+        self.grid = L.lib.cnpc_bispec_grid(h)
+        ext = L.KBins()
+        L.check(L.lib.cnpc_bispec_ext_bins(h, C.byref(ext)))
+        self.ext = ext
+        self.ws_bytes = L.lib.cnpc_sugi_workspace_size(C.byref(desc), C.byref(bins))
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        lib = getattr(L, "lib", None) if L is not None else None  # None at interpreter exit
+        if h is not None and h.value and lib is not None:
+            lib.cnpc_bispec_plan_destroy(h)
+            self.handle = None
+
+
+def sugi_plan(desc, bins, l1, l2, L_, precision) -> SugiPlan:
+    key = ("sugiyama", bytes(desc), bytes(bins), l1, l2, L_, precision)
+    if key not in _PLANS:
+        _PLANS[key] = SugiPlan(desc, bins, l1, l2, L_, precision)
+    return _PLANS[key]
+
+
+def measure_sugiyama(desc, gpos, rpos, bins, l1, l2, L_, precision=None, gw=None, rw=None,
+                     scratch: Optional[Scratch] = None, stream=None, shot_noise=True):
+    """Sugiyama B_l1l2L(k_i, k_j) for every pair of shells (nbins x nbins),
+    with its analytic shot noise."""
+    sc = scratch or Scratch()
+    if precision is None:
+        precision = L.PREC_F64 if desc.dtype == L.F64 else L.PREC_F32
+    plan = sugi_plan(desc, bins, l1, l2, L_, precision)
+    band = plan.band
+    norms, _, _ = catalog_norms(desc, gpos, rpos, gw, rw, sc, stream)
+    delta, nmesh = paint(desc, gpos, rpos, norms, gw, rw, noise=shot_noise, scratch=sc, stream=stream)
+    D, dint = deinterlace(desc, band, delta, want_real=L_ > 0, scratch=sc, stream=stream)
+    del delta
+    F0 = assemble(desc, band, 0, spec0=D, stream=stream)
+    ylmL = ylm_spectra(desc, band, [L_], dint, sc, stream)[L_] if L_ > 0 else None
+    rows = None
+    if shot_noise:
+        FL = assemble(desc, band, L_, ylm=ylmL, stream=stream) if L_ > 0 else F0
+        DN, nint = deinterlace(desc, band, nmesh, want_real=L_ > 0, scratch=sc, stream=stream)
+        FN0 = assemble(desc, band, 0, spec0=DN, stream=stream)
+        FNL = FN0
+        if L_ > 0:
+            FNL = assemble(desc, band, L_, ylm=ylm_spectra(desc, band, [L_], nint, sc, stream)[L_], stream=stream)
+        means, selft, _, _ = bin_means(desc, plan.ext, band, [(FL, FN0), (F0, FNL)], (L_,), norms, sc, stream)
+        rows = torch.cat([means, selft], 0).contiguous()
+    nb = bins.nbins
+    raw = _empty((nb, nb), torch.float64)
+    shot = _empty((nb, nb), torch.float64)
+    val = _empty((nb, nb), torch.float64)
+    ws = sc.get(plan.ws_bytes)
+    L.check(L.lib.cnpc_sugiyama(plan.handle, L.ptr(F0), L.ptr(ylmL), L.ptr(rows), L.ptr(norms), L.ptr(raw),
+                                L.ptr(shot), L.ptr(val), L.ptr(ws), ws.numel(), _sh(stream)))
+    return {"raw": raw, "shot": shot, "value": val, "norms": norms, "plan": plan}
+
+
 def measure_pk_bk(desc, gpos, rpos, bins, plan: "BispecPlan", ells=(0, 2, 4), gw=None, rw=None,
                   scratch: Optional[Scratch] = None, stream=None, out=None):
     """One catalog pair through the whole hot path: P_l (l in ells) and the
