@@ -425,6 +425,15 @@ def single_config(args):
             jobs += [(name, f, bk(dt, prec, est, ell)) for f, dt, prec in forms]
         # TripoSH with the FFT-method i = j != k noise term
         jobs += [("B202_fft_noise", f, bk(dt, prec, L.EST_TRIPOSH, 2, "fft")) for f, dt, prec in forms]
+        if spec.nbins <= 22:
+            # Sugiyama B_l1l2L over every pair of shells (split BF16 holds up to 22 shells)
+            def sugi(dt, prec, l1, l2, Lm):
+                def run():
+                    res = pl.measure_sugiyama(descs[dt], gd, rd, bins, l1, l2, Lm, precision=prec)
+                    return {"raw": res["raw"], "shot": res["shot"], "value": res["value"]}
+                return run
+            for l1, l2, Lm in ((0, 0, 0), (2, 0, 2), (2, 2, 0)):
+                jobs += [(f"Sugiyama_B{l1}{l2}{Lm}", f, sugi(dt, prec, l1, l2, Lm)) for f, dt, prec in forms]
     times, outs = {}, {}
     for name, form, run in jobs:
         outs[(name, form)] = {k: v.detach().cpu().numpy() for k, v in run().items()}  # warm: plans, scratch

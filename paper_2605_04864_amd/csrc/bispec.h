@@ -58,7 +58,7 @@ struct cnpc_bispec_plan {
   // (m1, m2, M) sub-configurations with their weights eta (l1 l2 L; m1 m2 M),
   // H N, and the k3 weights of the i = j != k shot-noise term per (i, j)
   int l1 = 0, l2 = 0, L = 0;
-  std::vector<int> sub;       // m1, m2, M per sub-configuration
+  std::vector<int> sub;       // m1, m2, M, symmetry flag per sub-configuration
   std::vector<double> subw;   // weight per sub-configuration
   double hn = 0.0;            // (l1 l2 L; 0 0 0) (2l1+1)(2l2+1)(2L+1)
   double* d_wq3 = nullptr;    // [nb][nb][next]

@@ -134,14 +134,25 @@ __global__ void __launch_bounds__(256) k_div_window(int n, int m, int assign, do
   }
 }
 
-// acc[i][j] += coef * C[pair (i, nb + j) of 2 nb shells]
-__global__ void k_sugi_accum(const double* __restrict__ C, int nb, double coef, double* __restrict__ acc) {
+__device__ __forceinline__ int pair_of(int a, int b, int ns) {  // a <= b
+  return a * ns - a * (a - 1) / 2 + (b - a);
+}
+
+// acc[i][j] += coef * (mode 0: C[pair (i, nb + j) of 2 nb shells];
+//   mode 1: the same plus its transpose C[pair (j, nb + i)];
+//   mode 2: C[pair (min(i, j), max(i, j)) of nb shells], one list for both legs)
+__global__ void k_sugi_accum(const double* __restrict__ C, int nb, int mode, double coef,
+                             double* __restrict__ acc) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nb * nb) return;
   const int i = t / nb, j = t - i * nb;
-  const int ns = 2 * nb, a = i, b = nb + j;
-  const int p = a * ns - a * (a - 1) / 2 + (b - a);
-  acc[t] += coef * C[p];
+  double v;
+  if (mode == 2) v = C[pair_of(i < j ? i : j, i < j ? j : i, nb)];
+  else {
+    v = C[pair_of(i, nb + j, 2 * nb)];
+    if (mode == 1) v += C[pair_of(j, nb + i, 2 * nb)];
+  }
+  acc[t] += coef * v;
 }
 
 struct SugiFin {
@@ -218,16 +229,28 @@ static cnpc_status sugi_plan_create(cnpc_bispec_plan** out, const cnpc_mesh_desc
   P->counts_ext = mode_counts(d, thr_ext, P->next);
   P->wq.resize(P->next);
   for (int c = 0; c < P->next; ++c) P->wq[c] = (double)P->counts_ext[c] / (b->kmin + (c + 0.5) * b->dk);
-  // paired sub-configurations: M < 0, or M = 0 with m1 <= 0; eta = 2 except (0, 0, 0)
+  // paired sub-configurations: M < 0, or M = 0 with m1 <= 0; eta = 2 except
+  // (0, 0, 0).  For l1 = l2 (section "Sugiyama estimator", symmetries between
+  // and within sub-configurations): (m2, m1, M) gives the transpose in (k1, k2)
+  // of (m1, m2, M) with the same 3j symbol (L even), so only m1 < m2 is kept
+  // and added with its transpose (flag 1); (m, -m, 0) is symmetric in (k1, k2)
+  // and needs the fields of one leg only (flag 2).
   for (int M = -L; M <= 0; ++M)
     for (int m1 = -l1; m1 <= l1; ++m1) {
       const int m2 = -m1 - M;
       if (std::abs(m2) > l2 || (M == 0 && m1 > 0)) continue;
       const double w = wigner3j_host(l1, l2, L, m1, m2, M);
       if (w == 0.0) continue;
+      int flag = 0;
+      if (l1 == l2) {
+        if (M == 0) flag = 2;
+        else if (m1 > m2) continue;
+        else if (m1 < m2) flag = 1;
+      }
       P->sub.push_back(m1);
       P->sub.push_back(m2);
       P->sub.push_back(M);
+      P->sub.push_back(flag);
       P->subw.push_back((m1 == 0 && m2 == 0 && M == 0) ? w : 2.0 * w);
     }
   P->hn = wigner3j_host(l1, l2, L, 0, 0, 0) * (2 * l1 + 1) * (2 * l2 + 1) * (2 * L + 1);
@@ -312,27 +335,31 @@ static cnpc_status sugi_run_t(const cnpc_bispec_plan* P, const cx<T>* F0, const 
     CNPC_HIP(hipGetLastError());
     return shell_c2r<T>(&dg, m, spec, P->thr.data(), nb + 1, 0, 1, false, slot, scr, s);
   };
-  auto contract_add = [&](int col, double coef) -> cnpc_status {
+  // mode 0 / 1: shells of P and Q (2 nb fields) with column g or h; mode 2:
+  // the shells of P alone with the column in the first Q slot
+  auto contract_add = [&](int col, double coef, int mode) -> cnpc_status {
     ContractCols cc;
     cc.ncols = 1;
-    cc.field[0] = 2 * nb + col;
+    const int nshell = mode == 2 ? nb : 2 * nb;
+    const int nf = mode == 2 ? nb + 1 : 2 * nb + 2;
+    cc.field[0] = mode == 2 ? nb : 2 * nb + col;
     if constexpr (sizeof(T) == 4) {
       if (P->prec == CNPC_PREC_BF16X3) {
-        CNPC_TRY(contract_mfma(fields, n3, 2 * nb + 2, 2 * nb, cc, partial, Cm, s));
+        CNPC_TRY(contract_mfma(fields, n3, nf, nshell, cc, partial, Cm, s));
       } else {
-        CNPC_TRY(contract_valu<T>(fields, n3, 2 * nb + 2, 2 * nb, cc, partial, Cm, s));
+        CNPC_TRY(contract_valu<T>(fields, n3, nf, nshell, cc, partial, Cm, s));
       }
     } else {
-      CNPC_TRY(contract_valu<T>(fields, n3, 2 * nb + 2, 2 * nb, cc, partial, Cm, s));
+      CNPC_TRY(contract_valu<T>(fields, n3, nf, nshell, cc, partial, Cm, s));
     }
-    hipLaunchKernelGGL(k_sugi_accum, dim3((nb * nb + 255) / 256), dim3(256), 0, s, Cm, nb, coef, acc);
+    hipLaunchKernelGGL(k_sugi_accum, dim3((nb * nb + 255) / 256), dim3(256), 0, s, Cm, nb, mode, coef, acc);
     CNPC_HIP(hipGetLastError());
     return CNPC_OK;
   };
   const int L = P->L;
   int curM = 1;  // no line-of-sight field loaded yet (loaded M are <= 0)
   for (size_t q = 0; q < P->subw.size(); ++q) {
-    const int m1 = P->sub[3 * q], m2 = P->sub[3 * q + 1], M = P->sub[3 * q + 2];
+    const int m1 = P->sub[4 * q], m2 = P->sub[4 * q + 1], M = P->sub[4 * q + 2], flag = P->sub[4 * q + 3];
     const double wgt = P->subw[q];
     if (M != curM) {
       // G^M = (-1)^M conj(G^|M|) for M < 0: g = (-1)^M c2r[A/W], h = (-1)^M c2r[B/W]
@@ -348,6 +375,20 @@ static cnpc_status sugi_run_t(const cnpc_bispec_plan* P, const cx<T>* F0, const 
       }
       curM = M;
     }
+    if (flag == 2) {
+      // F^m(k1) F^-m(k2) G_L^0 = (-1)^m [a(k1) a(k2) + b(k1) b(k2)] g (l even):
+      // the shells of one leg, contracted within the list
+      const double sgm = (m1 & 1) ? -wgt : wgt;
+      CNPC_HIP(hipMemcpyAsync(slotQ, slotG, sizeof(T) * (size_t)n3, hipMemcpyDeviceToDevice, s));
+      CNPC_TRY(load_leg(slotP, P->l1, m1, 0));
+      CNPC_TRY(contract_add(0, sgm, 2));
+      if (m1 != 0) {
+        CNPC_TRY(load_leg(slotP, P->l1, m1, 1));
+        CNPC_TRY(contract_add(0, sgm, 2));
+      }
+      continue;
+    }
+    const int mode = flag == 1 ? 1 : 0;
     // (a1 a2) g, then (a1 b2) h, (b1 b2) g, (b1 a2) h where present
     int pq[2][3] = {{-99, 0, 0}, {-99, 0, 0}};  // slot contents: (m, part) tags
     auto ensure = [&](int k, int ell, int em, int part) -> cnpc_status {
@@ -360,20 +401,20 @@ static cnpc_status sugi_run_t(const cnpc_bispec_plan* P, const cx<T>* F0, const 
     };
     CNPC_TRY(ensure(0, P->l1, m1, 0));
     CNPC_TRY(ensure(1, P->l2, m2, 0));
-    CNPC_TRY(contract_add(0, wgt));
+    CNPC_TRY(contract_add(0, wgt, mode));
     if (m2 != 0 && M != 0) {
       CNPC_TRY(ensure(1, P->l2, m2, 1));
-      CNPC_TRY(contract_add(1, -wgt));
+      CNPC_TRY(contract_add(1, -wgt, mode));
     }
     if (m1 != 0) {
       CNPC_TRY(ensure(0, P->l1, m1, 1));
       if (m2 != 0) {
         CNPC_TRY(ensure(1, P->l2, m2, 1));
-        CNPC_TRY(contract_add(0, -wgt));
+        CNPC_TRY(contract_add(0, -wgt, mode));
       }
       if (M != 0) {
         CNPC_TRY(ensure(1, P->l2, m2, 0));
-        CNPC_TRY(contract_add(1, -wgt));
+        CNPC_TRY(contract_add(1, -wgt, mode));
       }
     }
   }
