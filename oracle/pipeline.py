@@ -131,8 +131,9 @@ def measure_bk(gpos, gw, rpos, rw, cfg: MeshConfig, dk, nbins, ells=(0, 2),
     return out
 
 
-def measure_sugiyama(gpos, gw, rpos, rw, cfg: MeshConfig, dk, nbins, l1, l2, L):
-    """Sugiyama B_l1l2L(k_i, k_j) (all i, j) with its analytic shot noise (kmin = 0)."""
+def measure_sugiyama(gpos, gw, rpos, rw, cfg: MeshConfig, dk, nbins, l1, l2, L, fft_noise=False):
+    """Sugiyama B_l1l2L(k_i, k_j) (all i, j) with its analytic shot noise (kmin = 0);
+    fft_noise adds "shot_fft" and "value_fft" (the FFT-method i = j != k term)."""
     from . import sugiyama as sg
     obs = cfg.observer
     norms, W, F, FN = fkp_spectra(gpos, gw, rpos, rw, cfg, tuple(sorted({0, L})), noise_ells=(L,))
@@ -144,4 +145,12 @@ def measure_sugiyama(gpos, gw, rpos, rw, cfg: MeshConfig, dk, nbins, l1, l2, L):
     raw = sg.sugiyama_raw(F[0], dint, W, l1, l2, L, bins, norms.I33, cfg.boxsize, obs, cfg.los)
     Q, H, _ = noise_terms(F, FN, L, ext, norms, W, cfg)
     shot = sg.sugiyama_shot(l1, l2, L, nbins, Q, H, ext.counts(), ext.centres(), norms.I33, norms.Sbar)
-    return {"norms": norms, "raw": raw, "shot": shot, "value": raw - shot, "nmodes": bins.counts()}
+    out = {"norms": norms, "raw": raw, "shot": shot, "value": raw - shot, "nmodes": bins.counts()}
+    if fft_noise:
+        C = sn.c_shot(cfg.nmesh, cfg.assign, cfg.interlace)
+        term = sg.sugiyama_fft_term(dint, W, FN[0], C, norms.Sbar_lm, l1, l2, L, bins, norms.I33,
+                                    cfg.boxsize, obs, cfg.los)
+        out["fft_term"] = term
+        out["shot_fft"] = sg.sugiyama_shot_fft(l1, l2, L, nbins, term, H, norms.I33, norms.Sbar)
+        out["value_fft"] = raw - out["shot_fft"]
+    return out

@@ -32,7 +32,17 @@ compressed BB_000, realness, the pairing identity and the conjugation
 symmetries.  The shot noise is pinned by its (0, 0, 0) reduction to the
 compressed estimator's and by q_l0l = L_l (l 0 l; 0 0 0); beyond those special
 cases the i = j != k term of l1, l2 > 0 is parity unpinned (its associated
-Legendre sum follows the printed formula).
+Legendre sum follows the printed formula).  The FFT-method term is pinned by a
+direct sum over mode pairs and, for (0, 0, 0), by the compressed estimator's
+FFT-method noise.
+
+FFT method for the i = j != k term (the reference method of the section that
+validates the analytic noise; no thin-shell step):
+    S^FFT|i=j!=k = H N / I33 sum_{m1 m2 M} (l1 l2 L; m1 m2 M)
+                   1/N^3 sum_x Y_l1^m1(x; k1) Y_l2^m2(x; k2) P_L^M(x)
+    Y_l^m(x; k)  = 1/N_k sum_{q in shell k} e^{iq.x} y_l^m*(qhat)
+    P_L^M(x)     = sum_q e^{iq.x} [dn_L^M(q)/W(q) N_0(q)^*/W(q) - Sbar_L^M C(q)/W(q)^2]
+with N_0 the FFT of the N mesh, zero at q = 0 and on Nyquist-component modes.
 
 Readings (the paper leaves these open): I = I33; dn_L^M carries y_L^M* of
 the position (the conjugate of the printed weighting, so that
@@ -193,4 +203,63 @@ def sugiyama_shot(l1, l2, L, nbins, Q_ext, H, counts_ext, centres_ext, I33, Sbar
             qs = np.array([q_factor(l1, l2, L, centres_ext[i], centres_ext[j], centres_ext[c]) for c in cs])
             v += Hs * Nn * float(np.sum(wgt * qs * Q_ext[cs]) / np.sum(wgt))
             out[i, j] = v / I33
+    return out
+
+
+def harmonic_indicators(bins: Bins, ell: int, m: int, nmesh: int):
+    """Y_l^m(x; k) for every shell (complex), including the 1/N_k."""
+    ones = np.ones((nmesh,) * 3, dtype=np.complex128)
+    return shell_fields_lm(ones, bins, ell, m)
+
+
+def noise_los_field(delta_int, W, FN0, C, Sbar_lm, L, M, boxsize, observer, los=None):
+    """P_L^M(x) (complex N^3); FN0 = N_0 / W."""
+    n = delta_int.shape[0]
+    rvec = line_of_sight(n, boxsize, observer, los)
+    dn = np.fft.fftn(delta_int * np.conj(ylm_racah(L, M, rvec)))
+    spec = dn / W * np.conj(FN0) - Sbar_lm[(L, M)] * C / (W * W)
+    spec = np.where(nyquist_mask(n), 0.0, spec)
+    spec[0, 0, 0] = 0.0
+    return np.fft.ifftn(spec) * n ** 3
+
+
+def sugiyama_fft_term(delta_int, W, FN0, C, Sbar_lm, l1, l2, L, bins: Bins, I33, boxsize, observer,
+                      los=None, return_imag=False):
+    """S^FFT|i=j!=k (nbins x nbins), summed over every (m1, m2, M)."""
+    n = delta_int.shape[0]
+    H = wigner3j(l1, l2, L, 0, 0, 0)
+    Nn = (2 * l1 + 1) * (2 * l2 + 1) * (2 * L + 1)
+    nb = bins.nbins
+    acc = np.zeros((nb, nb), dtype=np.complex128)
+    cY, cP = {}, {}
+    for m1, m2, M, w in sub_configs(l1, l2, L):
+        for key in ((l1, m1), (l2, m2)):
+            if key not in cY:
+                cY[key] = harmonic_indicators(bins, key[0], key[1], n)
+        if M not in cP:
+            cP[M] = noise_los_field(delta_int, W, FN0, C, Sbar_lm, L, M, boxsize, observer, los)
+        A, B, Pm = cY[(l1, m1)], cY[(l2, m2)], cP[M]
+        for i in range(nb):
+            AP = A[i] * Pm
+            for j in range(nb):
+                acc[i, j] += w * np.sum(AP * B[j])
+    val = H * Nn / I33 * acc / float(n) ** 3
+    if return_imag:
+        return val.real, val.imag
+    return val.real
+
+
+def sugiyama_shot_fft(l1, l2, L, nbins, fft_term, H, I33, Sbar):
+    """S_l1l2L with the i = j != k term from the FFT method."""
+    out = np.array(fft_term, dtype=np.float64).copy()
+    for i in range(nbins):
+        for j in range(nbins):
+            v = 0.0
+            if l1 == 0 and l2 == 0 and L == 0:
+                v += Sbar
+            if l1 == L and l2 == 0:
+                v += (2 * L + 1) * H[i]
+            if l2 == L and l1 == 0:
+                v += (2 * L + 1) * H[j]
+            out[i, j] += v / I33
     return out

@@ -12,6 +12,9 @@
   (eq. sym_sugi and the boxed final form) reproduces it.
 * The symmetries of eq. sugi_F_and_G: F_l^-m = (-1)^(l+m) F_l^m*,
   G_L^-M = (-1)^M G_L^M*.
+* FFT-method i = j != k term: real, equal to the direct sum over mode pairs of
+  y*(q1hat) y*(q2hat) P_L^M(-q1 - q2), and for (0, 0, 0) the shot noise equals
+  the compressed estimator's FFT-method noise.
 * Shot noise: for (0, 0, 0) every term equals the compressed estimator's
   l = 0 noise; q_l0l = L_l(mu_13) (l 0 l; 0 0 0) (one n term); for (2, 2, 0)
   the i != j = k and i = k != j terms vanish.
@@ -188,3 +191,56 @@ def test_measure_sugiyama_runs_and_b000_shot_matches_compressed():
     for t, (i, j) in enumerate(bk.triposh_pairs(3)):
         assert math.isclose(out["raw"][i, j], ref["BB000_raw"][t], rel_tol=1e-11)
         assert math.isclose(out["shot"][i, j], ref["BB000_shot"][t], rel_tol=1e-11)
+
+
+def _noise_setup(n=12, nb=2):
+    g, gw, r, rw = synthcat.tiny_catalog(60, 300, seed=23)
+    obs = synthcat.observer_position()
+    cfg = MeshConfig(1000.0, n, ms.TSC, True, obs)
+    norms, W, F, FN = fkp_spectra(g, None, r, None, cfg, (0, 2), noise_ells=(2,))
+    delta, _ = ms.paint_fkp(g, None, r, None, norms.alpha, n, ms.TSC, True, noise=False)
+    _, dint = ms.deinterlace(delta[0], delta[1])
+    bins = sp.Bins(0.0, 2 * math.pi / 1000.0 * 1.3, nb, 1000.0, n)
+    C = sn.c_shot(n, ms.TSC, True)
+    return cfg, norms, W, F, FN, dint, bins, obs, C
+
+
+@pytest.mark.parametrize("l1,l2,L", [(2, 0, 2), (2, 2, 0), (0, 2, 2)])
+def test_fft_term_bruteforce_and_real(l1, l2, L):
+    cfg, norms, W, F, FN, dint, bins, obs, C = _noise_setup()
+    n = cfg.nmesh
+    re, im = sg.sugiyama_fft_term(dint, W, FN[0], C, norms.Sbar_lm, l1, l2, L, bins, norms.I33, cfg.boxsize, obs,
+                                  return_imag=True)
+    assert np.max(np.abs(im)) < 1e-10 * np.max(np.abs(re))
+    shells = bins.shell_index()
+    kf = 2 * math.pi / cfg.boxsize
+    H = sg.wigner3j(l1, l2, L, 0, 0, 0)
+    Nn = (2 * l1 + 1) * (2 * l2 + 1) * (2 * L + 1)
+    rvec = sp.line_of_sight(n, cfg.boxsize, obs)
+    nyq = ms.nyquist_mask(n)
+    for i in range(bins.nbins):
+        for j in range(bins.nbins):
+            qi, qj = np.argwhere(shells == i), np.argwhere(shells == j)
+            tot = 0.0 + 0.0j
+            for m1, m2, M, w in sg.sub_configs(l1, l2, L):
+                dn = np.fft.fftn(dint * np.conj(ylm_racah(L, M, rvec)))
+                P = dn / W * np.conj(FN[0]) - norms.Sbar_lm[(L, M)] * C / (W * W)
+                P = np.where(nyq, 0.0, P)
+                P[0, 0, 0] = 0.0
+                a = np.conj(ylm_racah(l1, m1, _signed(qi, n) * kf))
+                b = np.conj(ylm_racah(l2, m2, _signed(qj, n) * kf))
+                s3 = (-(qi[:, None, :] + qj[None, :, :])) % n
+                tot += w * np.sum(a[:, None] * b[None, :] * P[s3[..., 0], s3[..., 1], s3[..., 2]])
+            ref = H * Nn / norms.I33 * tot / (len(qi) * len(qj))
+            assert math.isclose(re[i, j], ref.real, rel_tol=1e-10, abs_tol=1e-12 * np.max(np.abs(re))), (i, j)
+
+
+def test_fft_term_000_equals_compressed_fft_noise():
+    g = synthcat.lognormal_catalog(8000, 1000.0, 15)
+    r = synthcat.random_catalog(40000, 16)
+    cfg = MeshConfig(1000.0, 32, ms.TSC, True, synthcat.observer_position())
+    out = measure_sugiyama(g, None, r, None, cfg, 0.012, 3, 0, 0, 0, fft_noise=True)
+    ref = measure_bk(g, None, r, None, cfg, 0.012, 3, ells=(0,), scoccimarro=(), triposh=(0,), fft_noise=True)
+    for t, (i, j) in enumerate(bk.triposh_pairs(3)):
+        assert math.isclose(out["shot_fft"][i, j], ref["BB000_shot_fft"][t], rel_tol=1e-11)
+        assert math.isclose(out["shot_fft"][j, i], ref["BB000_shot_fft"][t], rel_tol=1e-11)
