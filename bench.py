@@ -434,6 +434,13 @@ def single_config(args):
                 return run
             for l1, l2, Lm in ((0, 0, 0), (2, 0, 2), (2, 2, 0)):
                 jobs += [(f"Sugiyama_B{l1}{l2}{Lm}", f, sugi(dt, prec, l1, l2, Lm)) for f, dt, prec in forms]
+
+            def sugi_fft(dt, prec):
+                def run():
+                    res = pl.measure_sugiyama(descs[dt], gd, rd, bins, 2, 0, 2, precision=prec, noise="fft")
+                    return {"raw": res["raw"], "shot": res["shot"], "value": res["value"]}
+                return run
+            jobs += [("Sugiyama_B202_fft_noise", f, sugi_fft(dt, prec)) for f, dt, prec in forms]
     times, outs = {}, {}
     for name, form, run in jobs:
         outs[(name, form)] = {k: v.detach().cpu().numpy() for k, v in run().items()}  # warm: plans, scratch

@@ -343,12 +343,25 @@ cnpc_status cnpc_bispectrum(const cnpc_bispec_plan* plan, const void* F0, const 
  * self term L), or NULL for no shot noise; raw, shot, value: nbins x nbins
  * device FP64, row i = k_1 bin.  ws: cnpc_sugi_workspace_size bytes.  Errors:
  * CNPC_EINVAL (arguments, a plan of another estimator), CNPC_EWORKSPACE. */
+/* cnpc_sugiyama_fft_noise: as cnpc_sugiyama, with the i = j != k noise term by
+ * the FFT method (the reference of the section validating the analytic
+ * noise): H N / I33 sum eta (l1 l2 L; m1 m2 M) Re 1/G^3 sum_x Y_l1^m1(x; k_i)
+ * Y_l2^m2(x; k_j) P_L^M(x) / (N_i N_j), Y the harmonic shell indicators
+ * c2r[Phi conj(y)] and P_L^M = c2r[(FFT[delta conj(y_L^M)] / W) conj(N_0) / W
+ * - Sbar_L^M C / W^2]
+ * (zero at q = 0 and on Nyquist-component modes).  FN0: band spectrum of N_0
+ * (cnpc_assemble_F of the N mesh, l = 0); noise_means required (for the H_L
+ * terms).  A second pass over the sub-configurations: about twice the cost. */
 size_t cnpc_sugi_workspace_size(const cnpc_mesh_desc* desc, const cnpc_kbins* bins);
 cnpc_status cnpc_sugi_plan_create(cnpc_bispec_plan** plan, const cnpc_mesh_desc* desc, const cnpc_kbins* bins,
                                   int32_t l1, int32_t l2, int32_t L, int32_t precision);
 cnpc_status cnpc_sugiyama(const cnpc_bispec_plan* plan, const void* F0, const void* ylm,
                           const double* noise_means, const double* norms, double* raw, double* shot,
                           double* value, void* ws, size_t ws_bytes, void* stream);
+cnpc_status cnpc_sugiyama_fft_noise(const cnpc_bispec_plan* plan, const void* F0, const void* ylm,
+                                    const void* FN0, const double* noise_means, const double* norms,
+                                    double* raw, double* shot, double* value, void* ws, size_t ws_bytes,
+                                    void* stream);
 
 /* ---- FFT-method shot noise of the TripoSH BB_l0l (the reference method of
  * the section validating the analytic shot noise, applied to the i = j != k

@@ -102,6 +102,7 @@ _PROTOS = {
     "cnpc_sugi_workspace_size": (_sz, [_PD, _PB]),
     "cnpc_sugi_plan_create": (_i32, [C.POINTER(_vp), _PD, _PB, _i32, _i32, _i32, _i32]),
     "cnpc_sugiyama": (_i32, [_vp, _cvp, _cvp, _cvp, _cvp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "cnpc_sugiyama_fft_noise": (_i32, [_vp, _cvp, _cvp, _cvp, _cvp, _cvp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "cnpc_bispec_indicator_bytes": (_sz, [_vp]),
     "cnpc_bispec_indicators": (_i32, [_vp, _vp, _vp, _sz, _vp]),
     "cnpc_bispectrum_fft_noise": (_i32, [_vp, _cvp, _cvp, _cvp, _cvp, _cvp, _cvp, _vp, _vp, _vp, _vp, _sz,

@@ -134,6 +134,41 @@ __global__ void __launch_bounds__(256) k_div_window(int n, int m, int assign, do
   }
 }
 
+// Line-of-sight noise product of the FFT-method i = j != k term:
+// out = scale * [(src / W if div else src) * conj(FN0) - sgn * norms[sidx] * C / W^2]
+// on the band; zero at q = 0 and on modes with a Nyquist component
+template <typename T>
+__global__ void __launch_bounds__(256) k_los_noise(int n, int m, int assign, int interlace, int div,
+                                                   const cx<T>* __restrict__ src, const cx<T>* __restrict__ FN0,
+                                                   const double* __restrict__ norms, int sidx, double sgn,
+                                                   double scale, cx<T>* __restrict__ out) {
+  const int64_t bsz = (int64_t)4 * m * m * m;
+  const double sb = sgn * norms[sidx];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < bsz;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int kz = (int)(i % m);
+    const int jy = (int)((i / m) % (2 * m));
+    const int jx = (int)(i / ((int64_t)2 * m * m));
+    const int nx = band_freq(jx, m), ny = band_freq(jy, m), nz = kz;
+    const bool zero = (nx == 0 && ny == 0 && nz == 0) || nx == -(n / 2) || ny == -(n / 2) || nz == n / 2;
+    if (zero) {
+      out[i] = cx<T>{T(0), T(0)};
+      continue;
+    }
+    const double W = window_1d(nx, n, assign) * window_1d(ny, n, assign) * window_1d(nz, n, assign);
+    double cxs, ctx, cys, cty, czs, ctz;
+    alias_1d(nx, n, assign, &cxs, &ctx);
+    alias_1d(ny, n, assign, &cys, &cty);
+    alias_1d(nz, n, assign, &czs, &ctz);
+    const double C = interlace ? 0.5 * (cxs * cys * czs + ctx * cty * ctz) : cxs * cys * czs;
+    const cx<T> a = src[i], b = FN0[i];
+    const double ar = div ? (double)a.x / W : (double)a.x, ai = div ? (double)a.y / W : (double)a.y;
+    const double re = ar * (double)b.x + ai * (double)b.y - sb * C / (W * W);
+    const double im = ai * (double)b.x - ar * (double)b.y;
+    out[i] = cx<T>{T(scale * re), T(scale * im)};
+  }
+}
+
 __device__ __forceinline__ int pair_of(int a, int b, int ns) {  // a <= b
   return a * ns - a * (a - 1) / 2 + (b - a);
 }
@@ -162,7 +197,10 @@ struct SugiFin {
   const double* wq3;
 };
 
-__global__ void k_sugi_finalize(SugiFin f, const double* __restrict__ acc, const double* __restrict__ noise,
+// acc2 (optional): the FFT-method i = j != k sums, in place of the q-weighted
+// thin-shell term
+__global__ void k_sugi_finalize(SugiFin f, const double* __restrict__ acc, const double* __restrict__ acc2,
+                                const double* __restrict__ noise,
                                 const double* __restrict__ nm, double* __restrict__ raw,
                                 double* __restrict__ shot, double* __restrict__ value) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -180,10 +218,14 @@ __global__ void k_sugi_finalize(SugiFin f, const double* __restrict__ acc, const
     if (f.l1 == 0 && f.l2 == 0 && f.L == 0) v += Sbar;
     if (f.l1 == f.L && f.l2 == 0) v += (2.0 * f.L + 1.0) * (H[i] - S[i]);
     if (f.l2 == f.L && f.l1 == 0) v += (2.0 * f.L + 1.0) * (H[j] - S[j]);
-    const double* w = f.wq3 + (int64_t)t * ne;
-    double q = 0.0;
-    for (int c = 0; c < ne; ++c) q += w[c] * (Q[c] - S[c]);
-    v += f.hn * q;
+    if (acc2) {
+      v += f.hn * acc2[t] / (f.n3 * f.counts[i] * f.counts[j]);
+    } else {
+      const double* w = f.wq3 + (int64_t)t * ne;
+      double q = 0.0;
+      for (int c = 0; c < ne; ++c) q += w[c] * (Q[c] - S[c]);
+      v += f.hn * q;
+    }
     sh = v / I33;
   }
   raw[t] = r;
@@ -197,9 +239,9 @@ static size_t sugi_ws_bytes(const cnpc_mesh_desc* d, const cnpc_kbins* b) {
   const int nb = b->nbins, m = g.band;
   const size_t g3 = (size_t)g.grid * g.grid * g.grid, es = esize(d->dtype);
   const size_t npairs2 = (size_t)(2 * nb) * (2 * nb + 1) / 2;
-  return (size_t)(2 * nb + 2) * g3 * es + (size_t)4 * m * m * m * 2 * es +
+  return (size_t)(2 * nb + 2) * g3 * es + (size_t)2 * 4 * m * m * m * 2 * es +
          shell_c2r_ws_elems(g.grid, m, nb) * 2 * es +
-         (contract_partial_doubles(2 * nb, 1) + npairs2 + (size_t)nb * nb) * 8 + 8192;
+         (contract_partial_doubles(2 * nb, 1) + npairs2 + (size_t)2 * nb * nb) * 8 + 8192;
 }
 
 static cnpc_status sugi_plan_create(cnpc_bispec_plan** out, const cnpc_mesh_desc* d, const cnpc_kbins* b, int l1,
@@ -294,10 +336,13 @@ static cnpc_status sugi_plan_create(cnpc_bispec_plan** out, const cnpc_mesh_desc
 }
 
 // ------------------------------------------------------------------- run --
+// FN0 (optional): band spectrum of N_0 / W; with it the i = j != k noise
+// term is the FFT method's (a second pass over the sub-configurations with
+// harmonic shell indicators and the line-of-sight noise product)
 template <typename T>
-static cnpc_status sugi_run_t(const cnpc_bispec_plan* P, const cx<T>* F0, const cx<T>* ylm, const double* noise,
-                              const double* norms, double* raw, double* shot, double* value, void* ws,
-                              size_t ws_bytes, hipStream_t s) {
+static cnpc_status sugi_run_t(const cnpc_bispec_plan* P, const cx<T>* F0, const cx<T>* ylm, const cx<T>* FN0,
+                              const double* noise, const double* norms, double* raw, double* shot, double* value,
+                              void* ws, size_t ws_bytes, hipStream_t s) {
   cnpc_mesh_desc dg = P->desc;
   dg.n = P->grid;
   const int G = P->grid, m = P->band, nb = P->nb;
@@ -306,26 +351,30 @@ static cnpc_status sugi_run_t(const cnpc_bispec_plan* P, const cx<T>* F0, const 
   unsigned char* w = align256(reinterpret_cast<unsigned char*>(ws));
   T* fields = reinterpret_cast<T*>(w);  // [P: nb][Q: nb][g][h]
   cx<T>* spec = reinterpret_cast<cx<T>*>(align256(reinterpret_cast<unsigned char*>(fields + (int64_t)(2 * nb + 2) * n3)));
-  cx<T>* scr = reinterpret_cast<cx<T>*>(align256(reinterpret_cast<unsigned char*>(spec + bsz)));
+  cx<T>* ones = reinterpret_cast<cx<T>*>(align256(reinterpret_cast<unsigned char*>(spec + bsz)));
+  cx<T>* scr = reinterpret_cast<cx<T>*>(align256(reinterpret_cast<unsigned char*>(ones + bsz)));
   double* partial = reinterpret_cast<double*>(align256(reinterpret_cast<unsigned char*>(scr + shell_c2r_ws_elems(G, m, nb))));
   double* Cm = partial + contract_partial_doubles(2 * nb, 1);
   double* acc = Cm + npairs2;
-  const size_t need = reinterpret_cast<unsigned char*>(acc + (size_t)nb * nb) - reinterpret_cast<unsigned char*>(ws);
+  double* acc2 = acc + (size_t)nb * nb;
+  const size_t need = reinterpret_cast<unsigned char*>(acc2 + (size_t)nb * nb) - reinterpret_cast<unsigned char*>(ws);
   if (need > ws_bytes) {
     set_error("Sugiyama workspace too small: need %zu, got %zu", need, ws_bytes);
     return CNPC_EWORKSPACE;
   }
   CNPC_TRY(ensure_twiddles());
   const unsigned gb = (unsigned)std::min<int64_t>((bsz + 255) / 256, 65536);
-  hipLaunchKernelGGL(k_zero_f64, dim3(1), dim3(256), 0, s, acc, (int64_t)nb * nb);
+  hipLaunchKernelGGL(k_zero_f64, dim3(1), dim3(256), 0, s, acc, (int64_t)2 * nb * nb);
   CNPC_HIP(hipGetLastError());
   T* slotP = fields;
   T* slotQ = fields + (int64_t)nb * n3;
   T* slotG = fields + (int64_t)2 * nb * n3;
   T* slotH = slotG + n3;
-  // leg field (l, m, part) of every shell into a slot
+  // leg field (l, m, part) of every shell into a slot, from F_0 (signal) or
+  // from ones (harmonic shell indicators of the FFT-method noise)
+  const cx<T>* legsrc = F0;
   auto load_leg = [&](T* slot, int ell, int em, int part) -> cnpc_status {
-    hipLaunchKernelGGL((k_weight_ylm<T>), dim3(gb), dim3(256), 0, s, m, ell, em, part, F0, spec);
+    hipLaunchKernelGGL((k_weight_ylm<T>), dim3(gb), dim3(256), 0, s, m, ell, em, part, legsrc, spec);
     CNPC_HIP(hipGetLastError());
     return shell_c2r<T>(&dg, m, spec, P->thr.data(), nb + 1, 0, nb, true, slot, scr, s);
   };
@@ -337,6 +386,7 @@ static cnpc_status sugi_run_t(const cnpc_bispec_plan* P, const cx<T>* F0, const 
   };
   // mode 0 / 1: shells of P and Q (2 nb fields) with column g or h; mode 2:
   // the shells of P alone with the column in the first Q slot
+  double* accum = acc;
   auto contract_add = [&](int col, double coef, int mode) -> cnpc_status {
     ContractCols cc;
     cc.ncols = 1;
@@ -352,11 +402,21 @@ static cnpc_status sugi_run_t(const cnpc_bispec_plan* P, const cx<T>* F0, const 
     } else {
       CNPC_TRY(contract_valu<T>(fields, n3, nf, nshell, cc, partial, Cm, s));
     }
-    hipLaunchKernelGGL(k_sugi_accum, dim3((nb * nb + 255) / 256), dim3(256), 0, s, Cm, nb, mode, coef, acc);
+    hipLaunchKernelGGL(k_sugi_accum, dim3((nb * nb + 255) / 256), dim3(256), 0, s, Cm, nb, mode, coef, accum);
     CNPC_HIP(hipGetLastError());
     return CNPC_OK;
   };
   const int L = P->L;
+  const int sbase = CNPC_NORM_SBARLM + 2 * (L == 0 ? 0 : (L == 2 ? 1 : 4));
+  bool noise_pass = false;
+  // noise line-of-sight field: scale * [(src / W) N_0^* / W - sgn Sbar C / W^2]
+  auto load_los_noise = [&](T* slot, const cx<T>* src, int div, int sidx, double sgn, double scale) -> cnpc_status {
+    hipLaunchKernelGGL((k_los_noise<T>), dim3(gb), dim3(256), 0, s, P->desc.n, m, P->desc.assign,
+                       P->desc.interlace, div, src, FN0, norms, sidx, sgn, scale, spec);
+    CNPC_HIP(hipGetLastError());
+    return shell_c2r<T>(&dg, m, spec, P->thr.data(), nb + 1, 0, 1, false, slot, scr, s);
+  };
+  auto run_pass = [&]() -> cnpc_status {
   int curM = 1;  // no line-of-sight field loaded yet (loaded M are <= 0)
   for (size_t q = 0; q < P->subw.size(); ++q) {
     const int m1 = P->sub[4 * q], m2 = P->sub[4 * q + 1], M = P->sub[4 * q + 2], flag = P->sub[4 * q + 3];
@@ -366,7 +426,14 @@ static cnpc_status sugi_run_t(const cnpc_bispec_plan* P, const cx<T>* F0, const 
       const int am = -M;
       const double sg = (am & 1) ? -1.0 : 1.0;
       const cx<T>* A = L == 0 ? F0 : ylm + (am == 0 ? 0 : (int64_t)(2 * am - 1) * bsz);
-      if (L == 0) {
+      if (noise_pass) {
+        // P^M = (-1)^M conj(P^|M|) for M < 0, P^|M| = (A - i B)/W N_0^*/W - Sbar C/W^2:
+        // g = (-1)^M c2r[A N_0^*/W^2 - Re Sbar C/W^2], h = (-1)^M c2r[B N_0^*/W^2
+        // + Im Sbar C/W^2] (Sbar of (L, |M|)); M = 0: g only
+        const int si = sbase + 2 * am;
+        CNPC_TRY(load_los_noise(slotG, A, L == 0 ? 0 : 1, si, 1.0, am == 0 ? 1.0 : sg));
+        if (am > 0) CNPC_TRY(load_los_noise(slotH, ylm + (int64_t)(2 * am) * bsz, 1, si + 1, -1.0, sg));
+      } else if (L == 0) {
         // G_0^0 = c2r[F_0]: F_0 is already compensated
         CNPC_TRY(shell_c2r<T>(&dg, m, F0, P->thr.data(), nb + 1, 0, 1, false, slotG, scr, s));
       } else {
@@ -418,6 +485,17 @@ static cnpc_status sugi_run_t(const cnpc_bispec_plan* P, const cx<T>* F0, const 
       }
     }
   }
+  return CNPC_OK;
+  };
+  CNPC_TRY(run_pass());
+  if (FN0) {
+    hipLaunchKernelGGL(k_fill_ones<T>, dim3(256), dim3(256), 0, s, ones, bsz);
+    CNPC_HIP(hipGetLastError());
+    legsrc = ones;
+    accum = acc2;
+    noise_pass = true;
+    CNPC_TRY(run_pass());
+  }
   SugiFin f;
   f.l1 = P->l1;
   f.l2 = P->l2;
@@ -428,8 +506,8 @@ static cnpc_status sugi_run_t(const cnpc_bispec_plan* P, const cx<T>* F0, const 
   f.n3 = (double)n3;
   f.counts = P->d_counts;
   f.wq3 = P->d_wq3;
-  hipLaunchKernelGGL(k_sugi_finalize, dim3((nb * nb + 255) / 256), dim3(256), 0, s, f, acc, noise, norms, raw,
-                     shot, value);
+  hipLaunchKernelGGL(k_sugi_finalize, dim3((nb * nb + 255) / 256), dim3(256), 0, s, f, acc, FN0 ? acc2 : nullptr,
+                     noise, norms, raw, shot, value);
   CNPC_HIP(hipGetLastError());
   return CNPC_OK;
 }
@@ -472,10 +550,24 @@ cnpc_status cnpc_sugiyama(const cnpc_bispec_plan* p, const void* F0, const void*
   CNPC_REQUIRE(F0 && norms && raw && shot && value && ws, "null pointer argument");
   CNPC_REQUIRE(p->L == 0 || ylm != nullptr, "L > 0 needs the Y_L^M spectra of delta");
   if (p->desc.dtype == CNPC_F64)
-    return sugi_run_t<double>(p, (const cx<double>*)F0, (const cx<double>*)ylm, noise_means, norms, raw, shot,
-                              value, ws, ws_bytes, as_stream(stream));
-  return sugi_run_t<float>(p, (const cx<float>*)F0, (const cx<float>*)ylm, noise_means, norms, raw, shot, value,
-                           ws, ws_bytes, as_stream(stream));
+    return sugi_run_t<double>(p, (const cx<double>*)F0, (const cx<double>*)ylm, nullptr, noise_means, norms, raw,
+                              shot, value, ws, ws_bytes, as_stream(stream));
+  return sugi_run_t<float>(p, (const cx<float>*)F0, (const cx<float>*)ylm, nullptr, noise_means, norms, raw, shot,
+                           value, ws, ws_bytes, as_stream(stream));
+}
+
+cnpc_status cnpc_sugiyama_fft_noise(const cnpc_bispec_plan* p, const void* F0, const void* ylm, const void* FN0,
+                                    const double* noise_means, const double* norms, double* raw, double* shot,
+                                    double* value, void* ws, size_t ws_bytes, void* stream) {
+  API_BEGIN;
+  CNPC_REQUIRE(p != nullptr && p->est == CNPC_EST_SUGIYAMA, "need a plan of cnpc_sugi_plan_create");
+  CNPC_REQUIRE(F0 && FN0 && noise_means && norms && raw && shot && value && ws, "null pointer argument");
+  CNPC_REQUIRE(p->L == 0 || ylm != nullptr, "L > 0 needs the Y_L^M spectra of delta");
+  if (p->desc.dtype == CNPC_F64)
+    return sugi_run_t<double>(p, (const cx<double>*)F0, (const cx<double>*)ylm, (const cx<double>*)FN0,
+                              noise_means, norms, raw, shot, value, ws, ws_bytes, as_stream(stream));
+  return sugi_run_t<float>(p, (const cx<float>*)F0, (const cx<float>*)ylm, (const cx<float>*)FN0, noise_means,
+                           norms, raw, shot, value, ws, ws_bytes, as_stream(stream));
 }
 
 }  // extern "C"

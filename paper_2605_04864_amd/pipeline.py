@@ -417,10 +417,14 @@ def sugi_plan(desc, bins, l1, l2, L_, precision) -> SugiPlan:
 
 
 def measure_sugiyama(desc, gpos, rpos, bins, l1, l2, L_, precision=None, gw=None, rw=None,
-                     scratch: Optional[Scratch] = None, stream=None, shot_noise=True):
+                     scratch: Optional[Scratch] = None, stream=None, shot_noise=True, noise="analytic"):
     """Sugiyama B_l1l2L(k_i, k_j) for every pair of shells (nbins x nbins),
-    with its analytic shot noise."""
+    with its analytic shot noise; noise="fft" takes the i = j != k term by the
+    FFT method."""
     sc = scratch or Scratch()
+    if noise not in ("analytic", "fft") or (noise == "fft" and not shot_noise):
+        raise ValueError("noise must be 'analytic' or 'fft' (the latter with shot noise on)")
+    method = noise
     if precision is None:
         precision = L.PREC_F64 if desc.dtype == L.F64 else L.PREC_F32
     plan = sugi_plan(desc, bins, l1, l2, L_, precision)
@@ -446,8 +450,13 @@ def measure_sugiyama(desc, gpos, rpos, bins, l1, l2, L_, precision=None, gw=None
     shot = _empty((nb, nb), torch.float64)
     val = _empty((nb, nb), torch.float64)
     ws = sc.get(plan.ws_bytes)
-    L.check(L.lib.cnpc_sugiyama(plan.handle, L.ptr(F0), L.ptr(ylmL), L.ptr(rows), L.ptr(norms), L.ptr(raw),
-                                L.ptr(shot), L.ptr(val), L.ptr(ws), ws.numel(), _sh(stream)))
+    if method == "fft":
+        L.check(L.lib.cnpc_sugiyama_fft_noise(plan.handle, L.ptr(F0), L.ptr(ylmL), L.ptr(FN0), L.ptr(rows),
+                                              L.ptr(norms), L.ptr(raw), L.ptr(shot), L.ptr(val), L.ptr(ws),
+                                              ws.numel(), _sh(stream)))
+    else:
+        L.check(L.lib.cnpc_sugiyama(plan.handle, L.ptr(F0), L.ptr(ylmL), L.ptr(rows), L.ptr(norms), L.ptr(raw),
+                                    L.ptr(shot), L.ptr(val), L.ptr(ws), ws.numel(), _sh(stream)))
     return {"raw": raw, "shot": shot, "value": val, "norms": norms, "plan": plan}
 
 

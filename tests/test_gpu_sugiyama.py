@@ -1,8 +1,9 @@
 """Sugiyama bispectrum multipoles B_l1l2L against the FP64 oracle, through the
 C ABI: raw estimator, analytic shot noise and their difference for every
-pair of shells, in FP64 (1e-10), FP32 (1e-5) and split BF16 (1e-3), relative
-to the largest magnitude; B_000 also against the compressed TripoSH BB_000 of
-the library (the same estimator)."""
+pair of shells, and the same with the FFT-method i = j != k noise term, in
+FP64 (1e-10), FP32 (1e-5) and split BF16 (1e-3), relative to the largest
+magnitude; B_000 also against the compressed TripoSH BB_000 of the library
+(the same estimator), with both noise methods."""
 
 import numpy as np
 import pytest
@@ -29,8 +30,22 @@ def _oracle(l1, l2, Lm, n=32, nb=4, dk=0.012, seed=9):
     if key not in _ORA:
         g, r = P._cat(seed, 30_000, 150_000)
         cfg = MeshConfig(1000.0, n, L.TSC, True, P.OBS)
-        _ORA[key] = (g, r, measure_sugiyama(g, None, r, None, cfg, dk, nb, l1, l2, Lm))
+        _ORA[key] = (g, r, measure_sugiyama(g, None, r, None, cfg, dk, nb, l1, l2, Lm, fft_noise=True))
     return _ORA[key]
+
+
+@pytest.mark.parametrize("form", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("l1,l2,Lm", [(0, 0, 0), (2, 0, 2), (2, 2, 0), (2, 2, 2)])
+def test_sugiyama_fft_noise_vs_oracle(l1, l2, Lm, form):
+    n, nb, dk = 32, 4, 0.012
+    g, r, ora = _oracle(l1, l2, Lm)
+    dt, prec, tol = FORMS[form]
+    d = cn.mesh_desc(n, 1000.0, assign=L.TSC, interlace=True, dtype=dt, observer=P.OBS)
+    bins = cn.kbins(0.0, dk, nb)
+    res = pl.measure_sugiyama(d, P.dev(g), P.dev(r), bins, l1, l2, Lm, precision=prec, noise="fft")
+    assert P.rel(P.host(res["raw"]), ora["raw"]) < tol
+    assert P.rel(P.host(res["shot"]), ora["shot_fft"]) < tol
+    assert P.rel(P.host(res["value"]), ora["value_fft"]) < tol
 
 
 @pytest.mark.parametrize("form", ["f64", "f32", "bf16"])
@@ -52,15 +67,16 @@ def test_sugiyama_b000_equals_triposh_b000():
     d = cn.mesh_desc(n, 1000.0, assign=L.TSC, interlace=True, dtype=L.F64, observer=P.OBS)
     bins = cn.kbins(0.0, dk, nb)
     gd, rd = P.dev(g), P.dev(r)
-    sg = pl.measure_sugiyama(d, gd, rd, bins, 0, 0, 0)
-    tp = pl.measure_bk(d, gd, rd, bins, estimator=L.EST_TRIPOSH, ell=0)
-    cfg, _ = tp["plan"].configs()
-    S = {k: P.host(sg[k]) for k in ("raw", "shot", "value")}
-    for t, (i, j, _) in enumerate(cfg):
-        for k in ("raw", "shot", "value"):
-            ref = P.host(tp[k])[t]
-            assert abs(S[k][i, j] - ref) <= 1e-10 * abs(ref), (k, i, j)
-            assert abs(S[k][j, i] - ref) <= 1e-10 * abs(ref), (k, j, i)
+    for noise in ("analytic", "fft"):
+        sg = pl.measure_sugiyama(d, gd, rd, bins, 0, 0, 0, noise=noise)
+        tp = pl.measure_bk(d, gd, rd, bins, estimator=L.EST_TRIPOSH, ell=0, noise=noise)
+        cfg, _ = tp["plan"].configs()
+        S = {k: P.host(sg[k]) for k in ("raw", "shot", "value")}
+        for t, (i, j, _) in enumerate(cfg):
+            for k in ("raw", "shot", "value"):
+                ref = P.host(tp[k])[t]
+                assert abs(S[k][i, j] - ref) <= 1e-10 * abs(ref), (noise, k, i, j)
+                assert abs(S[k][j, i] - ref) <= 1e-10 * abs(ref), (noise, k, j, i)
 
 
 def test_sugiyama_many_shells_bf16_vs_fp64():
