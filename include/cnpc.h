@@ -352,6 +352,20 @@ cnpc_status cnpc_bispectrum(const cnpc_bispec_plan* plan, const void* F0, const 
  * (zero at q = 0 and on Nyquist-component modes).  FN0: band spectrum of N_0
  * (cnpc_assemble_F of the N mesh, l = 0); noise_means required (for the H_L
  * terms).  A second pass over the sub-configurations: about twice the cost. */
+/* Host utilities of the tripolar basis (no device work):
+ * cnpc_tripolar_real_coeffs: the coefficients A^{n1 n2 N}_{l1 l2 L} of the
+ * basis in real spherical harmonics (appendix on the real decomposition of
+ * bipolar and tripolar bases: 1/H sum_{m1 m2 M} U_m1n1 U_m2n2 U_MN
+ * (l1 l2 L; m1 m2 M), U the inverse of the real-harmonic matrix of the
+ * spherical-harmonics appendix), written to coeffs[(n1+l1)][(n2+l2)][(N+L)]
+ * when coeffs is not NULL (host array of (2l1+1)(2l2+1)(2L+1) doubles), and
+ * their number of non-zero entries to *nonzero.  l in [0, 8], triangle rule,
+ * even l1 + l2 + L; CNPC_EINVAL otherwise.
+ * cnpc_sugi_paired_count: the number of paired complex sub-configurations
+ * (m1, m2, M) with a non-zero 3j symbol (what cnpc_sugiyama evaluates before
+ * the l1 = l2 reductions); -1 for l outside [0, 8]. */
+cnpc_status cnpc_tripolar_real_coeffs(int32_t l1, int32_t l2, int32_t L, double* coeffs, int32_t* nonzero);
+int32_t cnpc_sugi_paired_count(int32_t l1, int32_t l2, int32_t L);
 size_t cnpc_sugi_workspace_size(const cnpc_mesh_desc* desc, const cnpc_kbins* bins);
 cnpc_status cnpc_sugi_plan_create(cnpc_bispec_plan** plan, const cnpc_mesh_desc* desc, const cnpc_kbins* bins,
                                   int32_t l1, int32_t l2, int32_t L, int32_t precision);

@@ -263,3 +263,43 @@ def sugiyama_shot_fft(l1, l2, L, nbins, fft_term, H, I33, Sbar):
                 v += (2 * L + 1) * H[j]
             out[i, j] += v / I33
     return out
+
+
+def real_harmonic_matrix(ell: int) -> np.ndarray:
+    """V^l of the real spherical harmonics X_lm = sum_n V_mn Y_l^n (appendix on
+    spherical harmonics: X for m < 0, m = 0, m > 0), rows and columns m, n =
+    -l..l."""
+    V = np.zeros((2 * ell + 1, 2 * ell + 1), dtype=np.complex128)
+    r2 = 1.0 / math.sqrt(2.0)
+    for m in range(-ell, ell + 1):
+        i = m + ell
+        if m < 0:
+            V[i, m + ell] = 1j * r2
+            V[i, -m + ell] = -1j * r2 * (-1) ** (m & 1)
+        elif m == 0:
+            V[i, ell] = 1.0
+        else:
+            V[i, -m + ell] = r2
+            V[i, m + ell] = r2 * (-1) ** (m & 1)
+    return V
+
+
+def tripolar_real_coeffs(l1: int, l2: int, L: int) -> np.ndarray:
+    """A^{n1 n2 N}_{l1 l2 L} of the real decomposition of the tripolar basis:
+    1/H sum_{m1 m2 M} U_m1n1 U_m2n2 U_MN (l1 l2 L; m1 m2 M), U = V^-1; indexed
+    [n1 + l1, n2 + l2, N + L] (complex array; real for an isotropic basis)."""
+    H = wigner3j(l1, l2, L, 0, 0, 0)
+    U1 = np.linalg.inv(real_harmonic_matrix(l1))
+    U2 = np.linalg.inv(real_harmonic_matrix(l2))
+    U3 = np.linalg.inv(real_harmonic_matrix(L))
+    A = np.zeros((2 * l1 + 1, 2 * l2 + 1, 2 * L + 1), dtype=np.complex128)
+    for m1 in range(-l1, l1 + 1):
+        for m2 in range(-l2, l2 + 1):
+            M = -m1 - m2
+            if abs(M) > L:
+                continue
+            w = wigner3j(l1, l2, L, m1, m2, M)
+            if w == 0.0:
+                continue
+            A += w * np.einsum("a,b,c->abc", U1[m1 + l1], U2[m2 + l2], U3[M + L])
+    return A / H

@@ -99,6 +99,8 @@ _PROTOS = {
                                   C.POINTER(_vp), C.POINTER(_i64), C.POINTER(_vp), C.POINTER(_vp), _vp, _sz]),
     "cnpc_batch_replay": (_i32, [_vp, _vp]),
     "cnpc_batch_destroy": (None, [_vp]),
+    "cnpc_tripolar_real_coeffs": (_i32, [_i32, _i32, _i32, C.POINTER(_d), C.POINTER(_i32)]),
+    "cnpc_sugi_paired_count": (_i32, [_i32, _i32, _i32]),
     "cnpc_sugi_workspace_size": (_sz, [_PD, _PB]),
     "cnpc_sugi_plan_create": (_i32, [C.POINTER(_vp), _PD, _PB, _i32, _i32, _i32, _i32]),
     "cnpc_sugiyama": (_i32, [_vp, _cvp, _cvp, _cvp, _cvp, _vp, _vp, _vp, _vp, _sz, _vp]),

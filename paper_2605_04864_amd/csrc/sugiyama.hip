@@ -516,7 +516,68 @@ static cnpc_status sugi_run_t(const cnpc_bispec_plan* P, const cx<T>* F0, const 
 
 using namespace cnpc;
 
+#include <complex>
+
+// Real decomposition of the tripolar basis (appendix on the real decomposition
+// of bipolar and tripolar bases): with X_lm = sum_n V_mn Y_l^n (the real
+// harmonics of the spherical-harmonics appendix) and U = V^-1 = V^dagger,
+// A^{n1 n2 N} = 1/H sum_{m1 m2 M} U_m1n1 U_m2n2 U_MN (l1 l2 L; m1 m2 M).
+static std::complex<double> real_v(int ell, int m, int n) {  // V^l_mn
+  const double r2 = 1.0 / std::sqrt(2.0), sg = (std::abs(m) & 1) ? -1.0 : 1.0;
+  if (m == 0) return n == 0 ? 1.0 : 0.0;
+  if (m < 0) {
+    if (n == m) return {0.0, r2};
+    if (n == -m) return {0.0, -r2 * sg};
+    return 0.0;
+  }
+  if (n == -m) return r2;
+  if (n == m) return r2 * sg;
+  return 0.0;
+}
+
 extern "C" {
+
+cnpc_status cnpc_tripolar_real_coeffs(int32_t l1, int32_t l2, int32_t L, double* coeffs, int32_t* nonzero) {
+  API_BEGIN;
+  for (int l : {l1, l2, L}) CNPC_REQUIRE(l >= 0 && l <= 8, "l1, l2, L must be in [0, 8]");
+  CNPC_REQUIRE(L >= std::abs(l1 - l2) && L <= l1 + l2 && (l1 + l2 + L) % 2 == 0,
+               "(l1, l2, L) must satisfy the triangle rule with an even sum");
+  const double H = wigner3j_host(l1, l2, L, 0, 0, 0);
+  int nz = 0;
+  for (int n1 = -l1; n1 <= l1; ++n1)
+    for (int n2 = -l2; n2 <= l2; ++n2)
+      for (int N = -L; N <= L; ++N) {
+        std::complex<double> a = 0.0;
+        for (int m1 = -l1; m1 <= l1; ++m1)
+          for (int m2 = -l2; m2 <= l2; ++m2) {
+            const int M = -m1 - m2;
+            if (std::abs(M) > L) continue;
+            const double w = wigner3j_host(l1, l2, L, m1, m2, M);
+            if (w == 0.0) continue;
+            // U_mn = conj(V_nm)
+            a += w * std::conj(real_v(l1, n1, m1)) * std::conj(real_v(l2, n2, m2)) * std::conj(real_v(L, N, M));
+          }
+        a /= H;
+        CNPC_REQUIRE(std::fabs(a.imag()) <= 1e-12, "non-real coefficient (internal error)");
+        const double v = std::fabs(a.real()) > 1e-12 ? a.real() : 0.0;
+        if (v != 0.0) ++nz;
+        if (coeffs) coeffs[((n1 + l1) * (2 * l2 + 1) + (n2 + l2)) * (2 * L + 1) + (N + L)] = v;
+      }
+  if (nonzero) *nonzero = nz;
+  return CNPC_OK;
+}
+
+int32_t cnpc_sugi_paired_count(int32_t l1, int32_t l2, int32_t L) {
+  if (l1 < 0 || l2 < 0 || L < 0 || l1 > 8 || l2 > 8 || L > 8) return -1;
+  int c = 0;
+  for (int M = -L; M <= 0; ++M)
+    for (int m1 = -l1; m1 <= l1; ++m1) {
+      const int m2 = -m1 - M;
+      if (std::abs(m2) > l2 || (M == 0 && m1 > 0)) continue;
+      if (wigner3j_host(l1, l2, L, m1, m2, M) != 0.0) ++c;
+    }
+  return c;
+}
 
 size_t cnpc_sugi_workspace_size(const cnpc_mesh_desc* d, const cnpc_kbins* b) {
   if (check_desc(d) != CNPC_OK || check_bins(d, b) != CNPC_OK) return 0;

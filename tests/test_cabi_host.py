@@ -177,3 +177,22 @@ def test_balanced_stream_assignment():
     for k in range(4):
         seq = [sizes[i] for i, q in mix if q == k]
         assert seq == sorted(seq, reverse=(k % 2 == 0))             # odd streams smallest first
+
+
+def test_tripolar_real_coeffs_match_oracle():
+    """Host utilities of the library against the oracle and the paper's counts."""
+    import ctypes as C
+    import numpy as np
+    from paper_2605_04864_amd import _lib as L
+    from oracle import sugiyama as sg
+    for (l1, l2, Lm), nz_paper, paired_paper in (((1, 1, 2), 11, 5), ((2, 2, 2), 25, 10), ((2, 2, 4), 37, 13)):
+        n = (2 * l1 + 1) * (2 * l2 + 1) * (2 * Lm + 1)
+        buf = (C.c_double * n)()
+        nz = C.c_int32()
+        L.check(L.lib.cnpc_tripolar_real_coeffs(l1, l2, Lm, buf, C.byref(nz)))
+        ref = sg.tripolar_real_coeffs(l1, l2, Lm).real.reshape(-1)
+        assert np.max(np.abs(np.frombuffer(buf, dtype=np.float64) - ref)) < 1e-13
+        assert nz.value == nz_paper
+        assert L.lib.cnpc_sugi_paired_count(l1, l2, Lm) == paired_paper
+    assert L.lib.cnpc_tripolar_real_coeffs(1, 1, 1, None, None) == -1  # odd l1 + l2 + L
+    assert L.lib.cnpc_tripolar_real_coeffs(2, 2, 5, None, None) == -1  # triangle rule

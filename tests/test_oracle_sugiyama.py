@@ -244,3 +244,51 @@ def test_fft_term_000_equals_compressed_fft_noise():
     for t, (i, j) in enumerate(bk.triposh_pairs(3)):
         assert math.isclose(out["shot_fft"][i, j], ref["BB000_shot_fft"][t], rel_tol=1e-11)
         assert math.isclose(out["shot_fft"][j, i], ref["BB000_shot_fft"][t], rel_tol=1e-11)
+
+
+def _golden_counts():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "special_values.txt")
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("#") or not line.strip():
+                continue
+            name, value = line.split()[:2]
+            vals[name] = value
+    return vals
+
+
+@pytest.mark.parametrize("lls", ["112", "222", "224"])
+def test_subconfiguration_counts_match_the_paper(lls):
+    """The appendix on the real decomposition prints the number of non-zero
+    sub-configurations of S_112, S_222, S_224: real form 11, 25, 37; complex
+    form with the pairing 5, 10, 13."""
+    g = _golden_counts()
+    l1, l2, L = (int(c) for c in lls)
+    A = sg.tripolar_real_coeffs(l1, l2, L)
+    assert int(np.sum(np.abs(A) > 1e-12)) == int(g[f"real_nonzero_{lls}"])
+    assert len(sg.sub_configs(l1, l2, L, paired=True)) == int(g[f"complex_paired_{lls}"])
+
+
+@pytest.mark.parametrize("l1,l2,L", [(1, 1, 2), (2, 2, 2), (2, 2, 4), (2, 0, 2), (3, 1, 2)])
+def test_real_decomposition_reproduces_the_basis(l1, l2, L):
+    """sum A x x x equals 1/H sum 3j y y y at random directions, and A is real."""
+    A = sg.tripolar_real_coeffs(l1, l2, L)
+    assert np.max(np.abs(A.imag)) < 1e-13
+    rng = np.random.default_rng(l1 * 100 + l2 * 10 + L)
+    H = sg.wigner3j(l1, l2, L, 0, 0, 0)
+
+    def xvec(ell, v):
+        y = np.array([ylm_racah(ell, m, v) for m in range(-ell, ell + 1)])
+        return sg.real_harmonic_matrix(ell) @ y  # Racah-normalised real harmonics
+
+    for _ in range(5):
+        k1, k2, nn = (rng.normal(size=3) for _ in range(3))
+        ref = sum(sg.wigner3j(l1, l2, L, m1, m2, -m1 - m2) * ylm_racah(l1, m1, k1) * ylm_racah(l2, m2, k2)
+                  * ylm_racah(L, -m1 - m2, nn)
+                  for m1 in range(-l1, l1 + 1) for m2 in range(-l2, l2 + 1) if abs(m1 + m2) <= L) / H
+        x1, x2, x3 = xvec(l1, k1), xvec(l2, k2), xvec(L, nn)
+        assert np.max(np.abs(x1.imag)) < 1e-12
+        got = np.einsum("abc,a,b,c->", A, x1, x2, x3)
+        assert abs(got - ref) < 1e-12 * max(1.0, abs(ref))
