@@ -331,7 +331,8 @@ cnpc_status cnpc_bispectrum(const cnpc_bispec_plan* plan, const void* F0, const 
  * (N_c/k_c) Q_L(k_c) / sum_c N_c/k_c, all over I33, with q of eq. q_ells
  * (Racah-normalised associated Legendre functions, cosines of the closed
  * triangle of bin centres) and c over the bins |i-j| .. i+j.
- * cnpc_sugi_plan_create: l1, l2, L in {0, 2, 4} with the triangle rule;
+ * cnpc_sugi_plan_create: l1, l2 in [0, 4] with l1 + l2 even, L in {0, 2, 4},
+ * the triangle rule;
  * kmin = 0 and (2 nbins - 1) dk below Nyquist; precision as for
  * cnpc_bispec_plan_create, split BF16 for at most 22 shells.  Destroy with
  * cnpc_bispec_plan_destroy; cnpc_bispec_band / _grid / _ext_bins /

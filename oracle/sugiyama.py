@@ -47,9 +47,8 @@ with N_0 the FFT of the N mesh, zero at q = 0 and on Nyquist-component modes.
 Readings (the paper leaves these open): I = I33; dn_L^M carries y_L^M* of
 the position (the conjugate of the printed weighting, so that
 sum_M y_L^M(khat) y_L^M*(xhat) is the Legendre kernel); the k3 weighting of
-the i = j != k term as for the compressed estimator (N_c / k_c); only even
-l1, l2, L are treated (plane-parallel symmetry makes L even; odd l1 = l2 is
-out of scope here).
+the i = j != k term as for the compressed estimator (N_c / k_c); L even
+(plane-parallel symmetry), so l1 + l2 even.
 """
 
 from __future__ import annotations

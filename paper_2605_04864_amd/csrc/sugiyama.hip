@@ -1,10 +1,11 @@
 // Sugiyama bispectrum multipoles B_l1l2L (tripolar spherical-harmonic
 // expansion; section "Sugiyama estimator", eq. sugi_estimator with eq. F_and_G,
 // the pairing of eq. sym_sugi, and the shot noise of eqs. S3_sugi_new, q_ells
-// and sugi_shot), for even l1, l2, L.
+// and sugi_shot), for l1, l2 <= 4 with l1 + l2 even and L in {0, 2, 4}.
 //
 // Fields on the contraction grid (all real, c2r of Hermitian band spectra):
 //   F_l^m(x; k) = a + i b,  a = c2r[Phi_k F_0 Re y_l^m],  b = c2r[Phi_k F_0 (-Im y_l^m)]
+//                 (l even; for l odd a = c2r[-i Phi_k F_0 Im y], b = c2r[-i Phi_k F_0 Re y])
 //   G_L^M(x)    = g + i h,  for M >= 0: g = c2r[A_M / W], h = -c2r[B_M / W]
 //                 (A_M, B_M: r2c of delta Re / Im y_L^M(xhat)); M < 0 by
 //                 G^M = (-1)^M conj(G^-M)
@@ -84,7 +85,11 @@ static double q_factor_host(int l1, int l2, int L, double k1, double k2, double 
 }
 
 // --------------------------------------------------------------- kernels --
-// out = F0(q) * (part == 0 ? Re y_l^m(qhat) : -Im y_l^m(qhat)) on the band
+// Band spectrum of the real (part 0) or imaginary (part 1) part of
+// F_l^m(x) = sum_q e^{iq.x} y_l^m*(qhat) F0(q) (F0 Hermitian):
+//   l even: F0 Re y (part 0), -F0 Im y (part 1)
+//   l odd:  -i F0 Im y (part 0), -i F0 Re y (part 1)
+// each Hermitian, so that a c2r gives the real field.
 template <typename T>
 __global__ void __launch_bounds__(256) k_weight_ylm(int m, int ell, int em, int part,
                                                     const cx<T>* __restrict__ F0, cx<T>* __restrict__ out) {
@@ -104,10 +109,13 @@ __global__ void __launch_bounds__(256) k_weight_ylm(int m, int ell, int em, int 
       double yr[5], yi[5];
       racah_ylm<double>(ell, nx / kn, ny / kn, nz / kn, yr, yi);
       const double re = sg * yr[am], im = (em < 0 ? -sg : sg) * yi[am];
-      wgt = part == 0 ? re : -im;
+      wgt = (ell & 1) ? (part == 0 ? im : re) : (part == 0 ? re : -im);
     }
     const cx<T> f = F0[i];
-    out[i] = cx<T>{T(wgt * (double)f.x), T(wgt * (double)f.y)};
+    if (ell & 1)  // times -i
+      out[i] = cx<T>{T(wgt * (double)f.y), T(-wgt * (double)f.x)};
+    else
+      out[i] = cx<T>{T(wgt * (double)f.x), T(wgt * (double)f.y)};
   }
 }
 
@@ -442,14 +450,18 @@ static cnpc_status sugi_run_t(const cnpc_bispec_plan* P, const cx<T>* F0, const 
       }
       curM = M;
     }
+    // the imaginary part b of F_l^m vanishes for even l and m = 0; the real
+    // part a for odd l and m = 0 (its contractions then add zero)
+    const bool b1 = m1 != 0 || (P->l1 & 1) == 1, b2 = m2 != 0 || (P->l2 & 1) == 1;
     if (flag == 2) {
-      // F^m(k1) F^-m(k2) G_L^0 = (-1)^m [a(k1) a(k2) + b(k1) b(k2)] g (l even):
-      // the shells of one leg, contracted within the list
-      const double sgm = (m1 & 1) ? -wgt : wgt;
+      // F^m(k1) F^-m(k2) G_L^0 = (-1)^(l+m) [a(k1) a(k2) + b(k1) b(k2)] g
+      // (F^-m = (-1)^(l+m) conj(F^m)): the shells of one leg, contracted
+      // within the list
+      const double sgm = ((P->l1 + m1) & 1) ? -wgt : wgt;
       CNPC_HIP(hipMemcpyAsync(slotQ, slotG, sizeof(T) * (size_t)n3, hipMemcpyDeviceToDevice, s));
       CNPC_TRY(load_leg(slotP, P->l1, m1, 0));
       CNPC_TRY(contract_add(0, sgm, 2));
-      if (m1 != 0) {
+      if (b1) {
         CNPC_TRY(load_leg(slotP, P->l1, m1, 1));
         CNPC_TRY(contract_add(0, sgm, 2));
       }
@@ -469,13 +481,13 @@ static cnpc_status sugi_run_t(const cnpc_bispec_plan* P, const cx<T>* F0, const 
     CNPC_TRY(ensure(0, P->l1, m1, 0));
     CNPC_TRY(ensure(1, P->l2, m2, 0));
     CNPC_TRY(contract_add(0, wgt, mode));
-    if (m2 != 0 && M != 0) {
+    if (b2 && M != 0) {
       CNPC_TRY(ensure(1, P->l2, m2, 1));
       CNPC_TRY(contract_add(1, -wgt, mode));
     }
-    if (m1 != 0) {
+    if (b1) {
       CNPC_TRY(ensure(0, P->l1, m1, 1));
-      if (m2 != 0) {
+      if (b2) {
         CNPC_TRY(ensure(1, P->l2, m2, 1));
         CNPC_TRY(contract_add(0, -wgt, mode));
       }
@@ -591,7 +603,9 @@ cnpc_status cnpc_sugi_plan_create(cnpc_bispec_plan** plan, const cnpc_mesh_desc*
   *plan = nullptr;
   CNPC_TRY(check_desc(d));
   CNPC_TRY(check_bins(d, b));
-  for (int l : {l1, l2, L}) CNPC_REQUIRE(l == 0 || l == 2 || l == 4, "l1, l2, L must be 0, 2 or 4");
+  for (int l : {l1, l2}) CNPC_REQUIRE(l >= 0 && l <= 4, "l1, l2 must be in [0, 4]");
+  CNPC_REQUIRE(L == 0 || L == 2 || L == 4, "L must be 0, 2 or 4");
+  CNPC_REQUIRE((l1 + l2) % 2 == 0, "l1 + l2 must be even");
   CNPC_REQUIRE(L >= std::abs(l1 - l2) && L <= l1 + l2, "(l1, l2, L) must satisfy the triangle rule");
   CNPC_REQUIRE(prec == CNPC_PREC_F64 || prec == CNPC_PREC_F32 || prec == CNPC_PREC_BF16X3, "unknown precision");
   CNPC_REQUIRE(!(prec == CNPC_PREC_F64 && d->dtype != CNPC_F64), "CNPC_PREC_F64 needs FP64 fields");

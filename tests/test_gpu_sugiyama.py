@@ -35,7 +35,7 @@ def _oracle(l1, l2, Lm, n=32, nb=4, dk=0.012, seed=9):
 
 
 @pytest.mark.parametrize("form", ["f64", "f32", "bf16"])
-@pytest.mark.parametrize("l1,l2,Lm", [(0, 0, 0), (2, 0, 2), (2, 2, 0), (2, 2, 2)])
+@pytest.mark.parametrize("l1,l2,Lm", [(0, 0, 0), (2, 0, 2), (2, 2, 0), (2, 2, 2), (1, 1, 2)])
 def test_sugiyama_fft_noise_vs_oracle(l1, l2, Lm, form):
     n, nb, dk = 32, 4, 0.012
     g, r, ora = _oracle(l1, l2, Lm)
@@ -49,7 +49,8 @@ def test_sugiyama_fft_noise_vs_oracle(l1, l2, Lm, form):
 
 
 @pytest.mark.parametrize("form", ["f64", "f32", "bf16"])
-@pytest.mark.parametrize("l1,l2,Lm", [(0, 0, 0), (2, 0, 2), (2, 2, 0), (2, 2, 2), (0, 2, 2)])
+@pytest.mark.parametrize("l1,l2,Lm", [(0, 0, 0), (2, 0, 2), (2, 2, 0), (2, 2, 2), (0, 2, 2), (1, 1, 0), (1, 1, 2),
+                                       (3, 1, 2), (4, 2, 2)])
 def test_sugiyama_vs_oracle(l1, l2, Lm, form):
     n, nb, dk = 32, 4, 0.012
     g, r, ora = _oracle(l1, l2, Lm)
@@ -100,6 +101,8 @@ def test_sugiyama_argument_errors():
     bins = cn.kbins(0.0, 0.012, 4)
     with pytest.raises(L.CnpcError):
         pl.SugiPlan(d, bins, 2, 2, 6, L.PREC_F32)  # L outside {0, 2, 4}
+    with pytest.raises(L.CnpcError):
+        pl.SugiPlan(d, bins, 2, 1, 2, L.PREC_F32)  # odd l1 + l2
     with pytest.raises(L.CnpcError):
         pl.SugiPlan(d, bins, 4, 0, 2, L.PREC_F32)  # triangle rule
     with pytest.raises(L.CnpcError):

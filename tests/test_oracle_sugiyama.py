@@ -85,7 +85,7 @@ def _signed(idx, n):
     return np.where(idx > n // 2, idx - n, idx)
 
 
-@pytest.mark.parametrize("l1,l2,L", [(0, 0, 0), (2, 0, 2), (2, 2, 0), (2, 2, 2)])
+@pytest.mark.parametrize("l1,l2,L", [(0, 0, 0), (2, 0, 2), (2, 2, 0), (2, 2, 2), (1, 1, 2), (3, 1, 2)])
 def test_sugiyama_bruteforce_mode_sums(l1, l2, L):
     cfg, norms, W, F0, dint, bins, obs = _tiny_setup()
     n = cfg.nmesh
@@ -124,7 +124,7 @@ def test_b000_equals_compressed_estimator():
         assert math.isclose(raw[j, i], comp[t], rel_tol=1e-11)
 
 
-@pytest.mark.parametrize("l1,l2,L", [(2, 0, 2), (2, 2, 0), (2, 2, 2), (4, 2, 2)])
+@pytest.mark.parametrize("l1,l2,L", [(2, 0, 2), (2, 2, 0), (2, 2, 2), (4, 2, 2), (1, 1, 0), (1, 1, 2)])
 def test_sum_is_real_and_pairing(l1, l2, L):
     cfg, norms, W, F0, dint, bins, obs = _tiny_setup(16)
     re, im = sg.sugiyama_raw(F0, dint, W, l1, l2, L, bins, norms.I33, cfg.boxsize, obs, return_imag=True)
@@ -147,7 +147,7 @@ def test_sum_is_real_and_pairing(l1, l2, L):
 
 def test_field_conjugation_symmetries():
     cfg, norms, W, F0, dint, bins, obs = _tiny_setup(16)
-    for l in (2, 4):
+    for l in (1, 2, 3, 4):
         for m in range(1, l + 1):
             Fp = sg.shell_fields_lm(F0, bins, l, m)
             Fm = sg.shell_fields_lm(F0, bins, l, -m)
