@@ -773,8 +773,6 @@ cnpc_status bispec_plan_create(cnpc_bispec_plan** out, const cnpc_mesh_desc* d, 
     }
   }
   // keep configurations with triangles (Scoccimarro) and fill per-config factors
-  const double* dummy = nullptr;
-  (void)dummy;
   for (int t = 0; t < ncand; ++t) {
     const int i = cfg[3 * t], j = cfg[3 * t + 1], k = cfg[3 * t + 2];
     if (est == CNPC_EST_SCOCCIMARRO && ntri[t] <= 0) continue;

@@ -8,6 +8,9 @@
 * c3 (256^3, 2e6 + 2e7, 20 bins): Scoccimarro B_0, B_2 and TripoSH B_202 in
   FP32 (1e-5) and split BF16 (1e-3) against FP64; triangle counts of sampled
   configurations against the oracle's indicator-field triple sums, bit-exact.
+* c4 (the benchmark's batch): its smallest, median and largest mocks through
+  the library's batch runner and its captured graph, FP32 / split BF16
+  against the FP64 path (1e-5 / 1e-3), configurations, N_T and mode counts.
 * c5 (512^3, L = 2000, 3e7 + 3e8, 40 bins of 0.005): TripoSH B_202 in split
   BF16 (1e-3) and FP32 (1e-5) against FP64.
 
@@ -130,3 +133,45 @@ def test_c5_full_triposh_precisions():
         assert np.all(np.isfinite(out["f64"][k]))
         assert P.rel(out["f32"][k], out["f64"][k]) < 1e-5, k
         assert P.rel(out["bf16"][k], out["f64"][k]) < 1e-3, k
+
+
+def test_c4_batch_graph_vs_fp64():
+    """c4 in the launch configuration of the benchmark: mocks of the c4 size
+    distribution (its smallest, median and largest: 1.0e6, 2.5e6, 7.9e6
+    galaxies with 10x randoms, the benchmark's seeds) through the library's
+    batch runner, captured as one graph and replayed, in FP32 fields with the
+    split-BF16 contraction; against the plain FP64 path mock by mock (P_l
+    within 1e-5, B_0 within 1e-3), identical configurations and N_T, and the
+    mode counts of the oracle's binning."""
+    sizes = synthcat.mock_sizes_c4(64)
+    pick = [63, 4, 54]
+    mocks = []
+    for k in pick:
+        ng = int(sizes[k])
+        g = synthcat.lognormal_catalog(ng, 1000.0, 4000 + 2 * k)
+        r = synthcat.random_catalog(10 * ng, 4000 + 2 * k + 1)
+        mocks.append((P.dev(g), P.dev(r)))
+        del g, r
+    bins = cn.kbins(0.0, 0.01, 20)
+    d32 = cn.mesh_desc(256, 1000.0, assign=L.TSC, interlace=True, dtype=L.F32, observer=OBS)
+    d64 = cn.mesh_desc(256, 1000.0, assign=L.TSC, interlace=True, dtype=L.F64, observer=OBS)
+    sc, sc64 = pl.Scratch(), pl.Scratch()
+    plan32 = pl.bispec_plan(d32, bins, L.EST_SCOCCIMARRO, 0, L.PREC_BF16X3, sc)
+    plan64 = pl.bispec_plan(d64, bins, L.EST_SCOCCIMARRO, 0, L.PREC_F64, sc64)
+    c32, c64 = plan32.configs(), plan64.configs()
+    assert np.array_equal(c32[0], c64[0]) and np.array_equal(c32[1], c64[1])
+    batch = pl.NativeBatch(d32, bins, plan32, nstreams=2, max_ngal=max(int(g.shape[1]) for g, _ in mocks),
+                           max_nran=max(int(r.shape[1]) for _, r in mocks))
+    outs = [{"pk": torch.empty((9, 20), dtype=torch.float64, device="cuda"),
+             "bk": torch.empty((3, plan32.nconf), dtype=torch.float64, device="cuda")} for _ in mocks]
+    batch.capture(mocks, outs)
+    batch.replay()
+    torch.cuda.synchronize()
+    ob = osp.Bins(0.0, 0.01, 20, 1000.0, 256)
+    for (g, r), o in zip(mocks, outs):
+        ref = pl.measure_pk_bk(d64, g, r, bins, plan64, scratch=sc64)
+        assert np.array_equal(P.host(ref["nmodes"]), ob.counts())
+        for row in range(3):  # P_0, P_2, P_4
+            assert P.rel(P.host(o["pk"][row]), P.host(ref["pk"][row])) < 1e-5, row
+        for row in range(3):  # raw, shot, value
+            assert P.rel(P.host(o["bk"][row]), P.host(ref["bk"][row])) < 1e-3, row
