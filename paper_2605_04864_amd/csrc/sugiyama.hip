@@ -10,9 +10,9 @@
 //                 (A_M, B_M: r2c of delta Re / Im y_L^M(xhat)); M < 0 by
 //                 G^M = (-1)^M conj(G^-M)
 // (the 1/N_k of F is applied at the end).  Each paired sub-configuration adds
-//   Re[F1 F2 G] = (a1 a2 - b1 b2) g - (a1 b2 + b1 a2) h
-// as up to four contractions sum_x P_i Q_j Z over the shell pairs (i, j),
-// with P, Q the k1 and k2 shell fields and Z = g or h.
+//   Re[F1 F2 G] = a1 (a2 g - b2 h) + b1 (-b2 g - a2 h)
+// as up to two GEMMs over grid points, sum_x P_i W_j with P = a1 or b1 (the
+// k1 shells) and W the pointwise products of the k2 shells with g and h.
 #include "bispec.h"
 
 namespace cnpc {
@@ -177,23 +177,48 @@ __global__ void __launch_bounds__(256) k_los_noise(int n, int m, int assign, int
   }
 }
 
+template <typename T>
+__global__ void k_fill_real(T* __restrict__ p, int64_t n, T v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// W_j = c1 X_j Z1 + c2 Y_j Z2 for the nb shells j (a term is left out when
+// its field pointer is null)
+template <typename T>
+__global__ void __launch_bounds__(256) k_sugi_w(int64_t n3, int nb, const T* __restrict__ X,
+                                                const T* __restrict__ Z1, double c1, const T* __restrict__ Y,
+                                                const T* __restrict__ Z2, double c2, T* __restrict__ W) {
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n3; x += (int64_t)gridDim.x * blockDim.x) {
+    const T z1 = X ? Z1[x] : T(0), z2 = Y ? Z2[x] : T(0);
+    for (int j = 0; j < nb; ++j) {
+      T v = T(0);
+      if (X) v += T(c1) * X[(int64_t)j * n3 + x] * z1;
+      if (Y) v += T(c2) * Y[(int64_t)j * n3 + x] * z2;
+      W[(int64_t)j * n3 + x] = v;
+    }
+  }
+}
+
 __device__ __forceinline__ int pair_of(int a, int b, int ns) {  // a <= b
   return a * ns - a * (a - 1) / 2 + (b - a);
 }
 
-// acc[i][j] += coef * (mode 0: C[pair (i, nb + j) of 2 nb shells];
-//   mode 1: the same plus its transpose C[pair (j, nb + i)];
-//   mode 2: C[pair (min(i, j), max(i, j)) of nb shells], one list for both legs)
+// acc[i][j] += coef * v_ij with (mode 0) v_ij = C_ij, the contraction of
+// field i of P (paired with the all-ones field nb of the nb + 1 shell fields)
+// against column j; (mode 1) C_ij + C_ji; (mode 2) the pair (min(i, j),
+// max(i, j)) of the nb shell fields of P against their one column
 __global__ void k_sugi_accum(const double* __restrict__ C, int nb, int mode, double coef,
                              double* __restrict__ acc) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nb * nb) return;
   const int i = t / nb, j = t - i * nb;
   double v;
-  if (mode == 2) v = C[pair_of(i < j ? i : j, i < j ? j : i, nb)];
-  else {
-    v = C[pair_of(i, nb + j, 2 * nb)];
-    if (mode == 1) v += C[pair_of(j, nb + i, 2 * nb)];
+  if (mode == 2) {
+    v = C[pair_of(i < j ? i : j, i < j ? j : i, nb)];
+  } else {
+    v = C[(int64_t)pair_of(i, nb, nb + 1) * nb + j];
+    if (mode == 1) v += C[(int64_t)pair_of(j, nb, nb + 1) * nb + i];
   }
   acc[t] += coef * v;
 }
@@ -246,10 +271,10 @@ static size_t sugi_ws_bytes(const cnpc_mesh_desc* d, const cnpc_kbins* b) {
   const BispecGeom g = bispec_geometry(d, b, CNPC_EST_TRIPOSH, 0);
   const int nb = b->nbins, m = g.band;
   const size_t g3 = (size_t)g.grid * g.grid * g.grid, es = esize(d->dtype);
-  const size_t npairs2 = (size_t)(2 * nb) * (2 * nb + 1) / 2;
-  return (size_t)(2 * nb + 2) * g3 * es + (size_t)2 * 4 * m * m * m * 2 * es +
+  const size_t np1 = (size_t)(nb + 1) * (nb + 2) / 2;
+  return (size_t)(4 * nb + 3) * g3 * es + (size_t)2 * 4 * m * m * m * 2 * es +
          shell_c2r_ws_elems(g.grid, m, nb) * 2 * es +
-         (contract_partial_doubles(2 * nb, 1) + npairs2 + (size_t)2 * nb * nb) * 8 + 8192;
+         (contract_partial_doubles(nb + 1, nb) + np1 * nb + (size_t)2 * nb * nb) * 8 + 8192;
 }
 
 static cnpc_status sugi_plan_create(cnpc_bispec_plan** out, const cnpc_mesh_desc* d, const cnpc_kbins* b, int l1,
@@ -355,15 +380,16 @@ static cnpc_status sugi_run_t(const cnpc_bispec_plan* P, const cx<T>* F0, const 
   dg.n = P->grid;
   const int G = P->grid, m = P->band, nb = P->nb;
   const int64_t n3 = (int64_t)G * G * G, bsz = (int64_t)4 * m * m * m;
-  const int npairs2 = (2 * nb) * (2 * nb + 1) / 2;
+  const int np1 = (nb + 1) * (nb + 2) / 2;
   unsigned char* w = align256(reinterpret_cast<unsigned char*>(ws));
-  T* fields = reinterpret_cast<T*>(w);  // [P: nb][Q: nb][g][h]
-  cx<T>* spec = reinterpret_cast<cx<T>*>(align256(reinterpret_cast<unsigned char*>(fields + (int64_t)(2 * nb + 2) * n3)));
+  // [P: nb][ones][W: nb] (the contraction's fields), then [Qa: nb][Qb: nb][g][h]
+  T* fields = reinterpret_cast<T*>(w);
+  cx<T>* spec = reinterpret_cast<cx<T>*>(align256(reinterpret_cast<unsigned char*>(fields + (int64_t)(4 * nb + 3) * n3)));
   cx<T>* ones = reinterpret_cast<cx<T>*>(align256(reinterpret_cast<unsigned char*>(spec + bsz)));
   cx<T>* scr = reinterpret_cast<cx<T>*>(align256(reinterpret_cast<unsigned char*>(ones + bsz)));
   double* partial = reinterpret_cast<double*>(align256(reinterpret_cast<unsigned char*>(scr + shell_c2r_ws_elems(G, m, nb))));
-  double* Cm = partial + contract_partial_doubles(2 * nb, 1);
-  double* acc = Cm + npairs2;
+  double* Cm = partial + contract_partial_doubles(nb + 1, nb);
+  double* acc = Cm + (size_t)np1 * nb;
   double* acc2 = acc + (size_t)nb * nb;
   const size_t need = reinterpret_cast<unsigned char*>(acc2 + (size_t)nb * nb) - reinterpret_cast<unsigned char*>(ws);
   if (need > ws_bytes) {
@@ -375,9 +401,15 @@ static cnpc_status sugi_run_t(const cnpc_bispec_plan* P, const cx<T>* F0, const 
   hipLaunchKernelGGL(k_zero_f64, dim3(1), dim3(256), 0, s, acc, (int64_t)2 * nb * nb);
   CNPC_HIP(hipGetLastError());
   T* slotP = fields;
-  T* slotQ = fields + (int64_t)nb * n3;
-  T* slotG = fields + (int64_t)2 * nb * n3;
+  T* slotOne = fields + (int64_t)nb * n3;
+  T* slotW = slotOne + n3;
+  T* slotQa = slotW + (int64_t)nb * n3;
+  T* slotQb = slotQa + (int64_t)nb * n3;
+  T* slotG = slotQb + (int64_t)nb * n3;
   T* slotH = slotG + n3;
+  hipLaunchKernelGGL((k_fill_real<T>), dim3(1024), dim3(256), 0, s, slotOne, n3, T(1));
+  CNPC_HIP(hipGetLastError());
+  const unsigned gw = (unsigned)std::min<int64_t>((n3 + 255) / 256, 8192);
   // leg field (l, m, part) of every shell into a slot, from F_0 (signal) or
   // from ones (harmonic shell indicators of the FFT-method noise)
   const cx<T>* legsrc = F0;
@@ -392,25 +424,48 @@ static cnpc_status sugi_run_t(const cnpc_bispec_plan* P, const cx<T>* F0, const 
     CNPC_HIP(hipGetLastError());
     return shell_c2r<T>(&dg, m, spec, P->thr.data(), nb + 1, 0, 1, false, slot, scr, s);
   };
-  // mode 0 / 1: shells of P and Q (2 nb fields) with column g or h; mode 2:
-  // the shells of P alone with the column in the first Q slot
+  // sum_x P_i W_j as a GEMM over grid points: the nb + 1 "shell" fields are
+  // P and the all-ones field, the nb columns W (W_j = c1 X_j Z1 + c2 Y_j Z2)
   double* accum = acc;
-  auto contract_add = [&](int col, double coef, int mode) -> cnpc_status {
+  auto contract_add = [&](const T* X, const T* Z1, double c1, const T* Y, const T* Z2, double c2, double coef,
+                          int transpose) -> cnpc_status {
+    hipLaunchKernelGGL((k_sugi_w<T>), dim3(gw), dim3(256), 0, s, n3, nb, X, Z1, c1, Y, Z2, c2, slotW);
+    CNPC_HIP(hipGetLastError());
     ContractCols cc;
-    cc.ncols = 1;
-    const int nshell = mode == 2 ? nb : 2 * nb;
-    const int nf = mode == 2 ? nb + 1 : 2 * nb + 2;
-    cc.field[0] = mode == 2 ? nb : 2 * nb + col;
+    cc.ncols = nb;
+    for (int j = 0; j < nb; ++j) cc.field[j] = nb + 1 + j;
     if constexpr (sizeof(T) == 4) {
       if (P->prec == CNPC_PREC_BF16X3) {
-        CNPC_TRY(contract_mfma(fields, n3, nf, nshell, cc, partial, Cm, s));
+        CNPC_TRY(contract_mfma(fields, n3, 2 * nb + 1, nb + 1, cc, partial, Cm, s));
       } else {
-        CNPC_TRY(contract_valu<T>(fields, n3, nf, nshell, cc, partial, Cm, s));
+        CNPC_TRY(contract_valu<T>(fields, n3, 2 * nb + 1, nb + 1, cc, partial, Cm, s));
       }
     } else {
-      CNPC_TRY(contract_valu<T>(fields, n3, nf, nshell, cc, partial, Cm, s));
+      CNPC_TRY(contract_valu<T>(fields, n3, 2 * nb + 1, nb + 1, cc, partial, Cm, s));
     }
-    hipLaunchKernelGGL(k_sugi_accum, dim3((nb * nb + 255) / 256), dim3(256), 0, s, Cm, nb, mode, coef, accum);
+    hipLaunchKernelGGL(k_sugi_accum, dim3((nb * nb + 255) / 256), dim3(256), 0, s, Cm, nb, transpose, coef, accum);
+    CNPC_HIP(hipGetLastError());
+    return CNPC_OK;
+  };
+  // sum_x P_i P_j g over the pairs i <= j of the nb fields of P, with g copied
+  // into the all-ones slot for the call (one column; restored afterwards)
+  auto contract_self = [&](double coef) -> cnpc_status {
+    CNPC_HIP(hipMemcpyAsync(slotOne, slotG, sizeof(T) * (size_t)n3, hipMemcpyDeviceToDevice, s));
+    ContractCols cc;
+    cc.ncols = 1;
+    cc.field[0] = nb;
+    if constexpr (sizeof(T) == 4) {
+      if (P->prec == CNPC_PREC_BF16X3) {
+        CNPC_TRY(contract_mfma(fields, n3, nb + 1, nb, cc, partial, Cm, s));
+      } else {
+        CNPC_TRY(contract_valu<T>(fields, n3, nb + 1, nb, cc, partial, Cm, s));
+      }
+    } else {
+      CNPC_TRY(contract_valu<T>(fields, n3, nb + 1, nb, cc, partial, Cm, s));
+    }
+    hipLaunchKernelGGL(k_sugi_accum, dim3((nb * nb + 255) / 256), dim3(256), 0, s, Cm, nb, 2, coef, accum);
+    CNPC_HIP(hipGetLastError());
+    hipLaunchKernelGGL((k_fill_real<T>), dim3(1024), dim3(256), 0, s, slotOne, n3, T(1));
     CNPC_HIP(hipGetLastError());
     return CNPC_OK;
   };
@@ -455,46 +510,26 @@ static cnpc_status sugi_run_t(const cnpc_bispec_plan* P, const cx<T>* F0, const 
     const bool b1 = m1 != 0 || (P->l1 & 1) == 1, b2 = m2 != 0 || (P->l2 & 1) == 1;
     if (flag == 2) {
       // F^m(k1) F^-m(k2) G_L^0 = (-1)^(l+m) [a(k1) a(k2) + b(k1) b(k2)] g
-      // (F^-m = (-1)^(l+m) conj(F^m)): the shells of one leg, contracted
-      // within the list
+      // (F^-m = (-1)^(l+m) conj(F^m)): one leg's shell fields contracted
+      // within the list (symmetric in k1, k2)
       const double sgm = ((P->l1 + m1) & 1) ? -wgt : wgt;
-      CNPC_HIP(hipMemcpyAsync(slotQ, slotG, sizeof(T) * (size_t)n3, hipMemcpyDeviceToDevice, s));
       CNPC_TRY(load_leg(slotP, P->l1, m1, 0));
-      CNPC_TRY(contract_add(0, sgm, 2));
+      CNPC_TRY(contract_self(sgm));
       if (b1) {
         CNPC_TRY(load_leg(slotP, P->l1, m1, 1));
-        CNPC_TRY(contract_add(0, sgm, 2));
+        CNPC_TRY(contract_self(sgm));
       }
       continue;
     }
-    const int mode = flag == 1 ? 1 : 0;
-    // (a1 a2) g, then (a1 b2) h, (b1 b2) g, (b1 a2) h where present
-    int pq[2][3] = {{-99, 0, 0}, {-99, 0, 0}};  // slot contents: (m, part) tags
-    auto ensure = [&](int k, int ell, int em, int part) -> cnpc_status {
-      if (pq[k][0] == 1 && pq[k][1] == em && pq[k][2] == part) return CNPC_OK;
-      CNPC_TRY(load_leg(k == 0 ? slotP : slotQ, ell, em, part));
-      pq[k][0] = 1;
-      pq[k][1] = em;
-      pq[k][2] = part;
-      return CNPC_OK;
-    };
-    CNPC_TRY(ensure(0, P->l1, m1, 0));
-    CNPC_TRY(ensure(1, P->l2, m2, 0));
-    CNPC_TRY(contract_add(0, wgt, mode));
-    if (b2 && M != 0) {
-      CNPC_TRY(ensure(1, P->l2, m2, 1));
-      CNPC_TRY(contract_add(1, -wgt, mode));
-    }
-    if (b1) {
-      CNPC_TRY(ensure(0, P->l1, m1, 1));
-      if (b2) {
-        CNPC_TRY(ensure(1, P->l2, m2, 1));
-        CNPC_TRY(contract_add(0, -wgt, mode));
-      }
-      if (M != 0) {
-        CNPC_TRY(ensure(1, P->l2, m2, 0));
-        CNPC_TRY(contract_add(1, -wgt, mode));
-      }
+    const int tr = flag == 1 ? 1 : 0;
+    // Re[F1 F2 G] = a1 (a2 g - b2 h) + b1 (-b2 g - a2 h)
+    CNPC_TRY(load_leg(slotQa, P->l2, m2, 0));
+    if (b2) CNPC_TRY(load_leg(slotQb, P->l2, m2, 1));
+    CNPC_TRY(load_leg(slotP, P->l1, m1, 0));
+    CNPC_TRY(contract_add(slotQa, slotG, 1.0, (b2 && M != 0) ? slotQb : nullptr, slotH, -1.0, wgt, tr));
+    if (b1 && (b2 || M != 0)) {
+      CNPC_TRY(load_leg(slotP, P->l1, m1, 1));
+      CNPC_TRY(contract_add(b2 ? slotQb : nullptr, slotG, -1.0, M != 0 ? slotQa : nullptr, slotH, -1.0, wgt, tr));
     }
   }
   return CNPC_OK;
@@ -614,6 +649,7 @@ cnpc_status cnpc_sugi_plan_create(cnpc_bispec_plan** plan, const cnpc_mesh_desc*
   const double kny = M_PI * d->n / d->boxsize;
   CNPC_REQUIRE((2 * b->nbins - 1) * b->dk <= kny, "the line-of-sight field needs bins up to 2 k_max below Nyquist");
   CNPC_REQUIRE(prec != CNPC_PREC_BF16X3 || b->nbins <= 22, "split-BF16 Sugiyama contraction: at most 22 shells");
+  CNPC_REQUIRE(b->nbins <= MAX_COLS, "Sugiyama contraction: at most %d shells", MAX_COLS);
   return sugi_plan_create(plan, d, b, l1, l2, L, prec);
 }
 
