@@ -141,9 +141,9 @@ def main():
         copy_probe(args.copy_probe_mib)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU; the mocks are independent and "
-                          "shard across GPUs without communication, but multi-GPU runs are not "
-                          "part of it", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "bench.py measures one GPU only; the mocks are independent and "
+                          "would shard across GPUs without communication, but no multi-GPU "
+                          "path is implemented", "n_gpus": args.gpus}))
         sys.exit(2)
     if args.config != 4:
         single_config(args)
