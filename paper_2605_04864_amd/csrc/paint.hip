@@ -677,7 +677,11 @@ __global__ void __launch_bounds__(512) k_fold_tiles(FoldArgs<T> fa, const double
                                                     T* __restrict__ delta, T* __restrict__ noise) {
   const int n = fa.n, nt = fa.nt, z2 = nt >= 2 ? 2 : 1;
   const int nzp = nt / z2;
+  // workgroups go to the 8 XCDs in turn (launch index mod 8); give each XCD a
+  // contiguous range of tile columns so that the halo rows shared by
+  // neighbouring tiles are fetched into one L2 (a bijection when 8 | grid)
   int b = blockIdx.x;
+  if ((gridDim.x & 7u) == 0) b = (int)((blockIdx.x & 7u) * (gridDim.x >> 3) + (blockIdx.x >> 3));
   const int tzp = b % nzp; b /= nzp;
   const int ty = b % nt; b /= nt;
   const int tx = b % nt;
