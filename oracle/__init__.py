@@ -21,11 +21,13 @@ paper prints, closed forms, identities and brute-force sums (see each test's
 docstring).  Functions without such a pin say "parity unpinned" in their
 docstring.
 
-Parity unpinned (partially): the l > 0 analytic shot-noise assembly
-(``shotnoise.scoccimarro_shot`` and ``shotnoise.triposh_shot`` for l = 2).  Its
-ingredients are pinned (g_l, the ring lemma, the alias sums, Q_l/H_l as shell
-means) and its l = 0 case is pinned statistically on Poisson catalogs, but no
-printed value or closed form fixes the l = 2 combination itself.
+The l > 0 analytic shot-noise assembly (``shotnoise.scoccimarro_shot_terms``,
+``shotnoise.triposh_shot_terms``) is pinned term by term against the exact
+closure sums of ``shotnoise_exact`` (the FFT method of the section validating
+the analytic noise, extended to every coincidence case), which are themselves
+pinned by a brute-force particle enumeration of each case
+(``tests/test_oracle_shot_exact.py``); the agreement holds within the stated
+thin-shell tolerances, and planted assembly mistakes fail them.
 """
 
-from . import catalog, mesh, ylm, spectra, bispectrum, shotnoise, pipeline  # noqa: F401
+from . import catalog, mesh, ylm, spectra, bispectrum, shotnoise, shotnoise_exact, pipeline  # noqa: F401

@@ -141,40 +141,59 @@ def self_term(ell: int, Sbar_lm, bins: Bins, W: np.ndarray, C: np.ndarray) -> np
     return bins.shell_mean(np.real(acc) * C / (W * W))
 
 
-def scoccimarro_shot(ell, configs, Q, H, centres, I33, Sbar):
-    """N^(l)(i; j, k) per configuration (see module docstring).
+def scoccimarro_shot_terms(ell, configs, Q, H, centres, Sbar):
+    """The four coincidence terms of N^(l)(i; j, k) per configuration, before the
+    (2l+1)/I33 factor: "jk" = Q_l(k_i) (the two l = 0 legs on one particle),
+    "ik" = L_l(mu_ij) H_l(k_j), "ij" = L_l(mu_ik) H_l(k_k) (the l leg shares a
+    particle with leg k or j; ring lemma, eq. I_l0l) and "ijk" = delta_l0 Sbar.
 
-    l = 0 is pinned statistically (Poisson catalogs); l > 0: parity unpinned
-    beyond its ingredients."""
-    out = np.empty(len(configs))
+    Pinned term by term against the exact closure sums of ``shotnoise_exact``
+    (thin-shell tolerance) and, for l = 0, statistically on Poisson catalogs."""
+    out = {key: np.empty(len(configs)) for key in ("jk", "ik", "ij", "ijk")}
     for t, (i, j, k) in enumerate(configs):
         ki, kj, kk = centres[i], centres[j], centres[k]
         mu_ij = np.clip((kk * kk - ki * ki - kj * kj) / (2 * ki * kj), -1.0, 1.0)
         mu_ik = np.clip((kj * kj - ki * ki - kk * kk) / (2 * ki * kk), -1.0, 1.0)
-        val = Q[i] + legendre(ell, mu_ij) * H[j] + legendre(ell, mu_ik) * H[k]
-        if ell == 0:
-            val += Sbar
-        out[t] = (2 * ell + 1) / I33 * val
+        out["jk"][t] = Q[i]
+        out["ik"][t] = legendre(ell, mu_ij) * H[j]
+        out["ij"][t] = legendre(ell, mu_ik) * H[k]
+        out["ijk"][t] = Sbar if ell == 0 else 0.0
+    return out
+
+
+def scoccimarro_shot(ell, configs, Q, H, centres, I33, Sbar):
+    """N^(l)(i; j, k) = (2l+1)/I33 (sum of ``scoccimarro_shot_terms``)."""
+    terms = scoccimarro_shot_terms(ell, configs, Q, H, centres, Sbar)
+    return (2 * ell + 1) / I33 * (terms["jk"] + terms["ik"] + terms["ij"] + terms["ijk"])
+
+
+def triposh_shot_terms(ell, pairs, Q_ext, H, counts_ext, centres_ext, Sbar):
+    """The four coincidence terms of N_l0l(k_i, k_j) per pair, before the 1/I33
+    factor: "12" = (2l+1) sum_c N_c Q_l(k_c)/k_c / sum_c N_c/k_c (the two l = 0
+    legs on one particle), "13" = (-1)^l (2l+1) g_l(1/t) H_l(k_j) and
+    "23" = (-1)^l (2l+1) g_l(t) H_l(k_i) with t = k_i/k_j (the l leg shares a
+    particle with the k1 or the k2 leg; Lemma 2, eq. g_ell), "123" = delta_l0 Sbar.
+
+    Pinned term by term against the exact closure sums of ``shotnoise_exact``
+    (thin-shell tolerance) and, for l = 0, statistically on Poisson catalogs."""
+    out = {key: np.empty(len(pairs)) for key in ("12", "13", "23", "123")}
+    sign = -1.0 if ell % 2 else 1.0
+    for t, (i, j) in enumerate(pairs):
+        tt = centres_ext[i] / centres_ext[j]
+        cs = np.arange(abs(i - j), i + j + 1)
+        wgt = counts_ext[cs] / centres_ext[cs]
+        out["12"][t] = (2 * ell + 1) * float(np.sum(wgt * Q_ext[cs]) / np.sum(wgt))
+        out["13"][t] = sign * (2 * ell + 1) * g_ell(ell, 1.0 / tt) * H[j]
+        out["23"][t] = sign * (2 * ell + 1) * g_ell(ell, tt) * H[i]
+        out["123"][t] = Sbar if ell == 0 else 0.0
     return out
 
 
 def triposh_shot(ell, pairs, Q_ext, H, counts_ext, centres_ext, I33, Sbar):
-    """N_l0l(k_i, k_j) per pair (i <= j); Q_ext etc. extend to bin 2 nbins - 2.
-
-    l = 0 is pinned statistically (Poisson catalogs); l > 0: parity unpinned
-    beyond its ingredients."""
-    out = np.empty(len(pairs))
-    sign = -1.0 if ell % 2 else 1.0
-    for t, (i, j) in enumerate(pairs):
-        tt = centres_ext[i] / centres_ext[j]
-        term = sign * (2 * ell + 1) * (g_ell(ell, tt) * H[i] + g_ell(ell, 1.0 / tt) * H[j])
-        cs = np.arange(abs(i - j), i + j + 1)
-        wgt = counts_ext[cs] / centres_ext[cs]
-        term += (2 * ell + 1) * float(np.sum(wgt * Q_ext[cs]) / np.sum(wgt))
-        if ell == 0:
-            term += Sbar
-        out[t] = term / I33
-    return out
+    """N_l0l(k_i, k_j) per pair (i <= j) = (sum of ``triposh_shot_terms``) / I33;
+    Q_ext etc. extend to bin 2 nbins - 2."""
+    terms = triposh_shot_terms(ell, pairs, Q_ext, H, counts_ext, centres_ext, Sbar)
+    return (terms["23"] + terms["13"] + terms["12"] + terms["123"]) / I33
 
 
 def self_term_modes(ell: int, Sbar_lm, nmesh: int, boxsize: float, W: np.ndarray,

@@ -15,7 +15,8 @@ Readings:
 * F_l(0) := 0 (khat undefined at k = 0).
 * k-bins are half-open [kmin + b dk, kmin + (b+1) dk); membership is decided on
   the integer n^2 = |n|^2 with thresholds T_b = ceil(((kmin + b dk)/kf)^2),
-  kf = 2 pi / L.  k = 0 and every mode with a Nyquist component are excluded.
+  kf = 2 pi / L, an edge within a relative 1e-9 of an integer n^2 counting as on
+  it.  k = 0 and every mode with a Nyquist component are excluded.
 * k_eff = mean |k| over the modes of a bin.
 """
 
@@ -43,12 +44,18 @@ class Bins:
         return 2.0 * math.pi / self.boxsize
 
     def thresholds(self) -> np.ndarray:
-        """Integer n^2 thresholds T_b, b = 0..nbins."""
+        """Integer n^2 thresholds T_b, b = 0..nbins: the smallest n^2 >= (edge/kf)^2.
+
+        An edge whose square lies within a relative 1e-9 of an integer is taken to
+        lie exactly on that integer: the rounding of dk and kf must not move a
+        whole lattice shell across a half-open edge."""
         kf = 2.0 * math.pi / self.boxsize
         out = []
         for b in range(self.nbins + 1):
             x = (self.kmin + b * self.dk) / kf
-            out.append(math.ceil(x * x))
+            v = x * x
+            r = round(v)
+            out.append(int(r) if abs(v - r) <= 1e-9 * max(1.0, v) else math.ceil(v))
         return np.array(out, dtype=np.int64)
 
     def centres(self) -> np.ndarray:

@@ -326,3 +326,34 @@ def test_cross_multipoles_self_and_symmetry():
     assert np.allclose(ab["P0"], ba["P0"], rtol=1e-12)
     assert np.isclose(ab["I22"], math.sqrt(auto["norms"].I22 *
                                            measure_pk(gB, None, rB, None, cfg, 0.0, 0.012, 6, ells=(0,))["norms"].I22))
+
+
+def _lattice_counts(nmesh, lo2, hi2):
+    """Number of wave vectors n (|n_i| < N/2) with lo2 <= |n|^2 < hi2, by integer enumeration."""
+    h = nmesh // 2
+    r = np.arange(-h + 1, h)
+    n2 = r[:, None, None] ** 2 + r[None, :, None] ** 2 + r[None, None, :] ** 2
+    return int(np.count_nonzero((n2 >= lo2) & (n2 < hi2) & (n2 > 0)))
+
+
+@pytest.mark.parametrize("kmin_f, dk_f", [(0, 1), (3, 2), (0, 2)])
+def test_mode_counts_on_integer_edges(kmin_f, dk_f):
+    """Half-open bins whose edges fall exactly on integer |n| (reading R6): a mode
+    with |n| on an edge belongs to the upper bin.  With dk = k_f the FP64 square of
+    edge 27, (27 dk / k_f)^2, rounds to 729.0000000000002; the counts must not move
+    the 30 modes of |n|^2 = 729 down a bin.  Reference counts by integer enumeration;
+    the first few by hand from the sums of three squares r3(n^2) = 6, 12, 8, 6, 24, 24,
+    0, 12, 30 for n^2 = 1..9: [0, 1) -> 0 modes, [1, 2) -> 6 + 12 + 8 = 26,
+    [2, 3) -> 6 + 24 + 24 + 12 = 66."""
+    n, box = 64, 1000.0
+    kf = 2 * math.pi / box
+    nb = 30 if dk_f == 1 else 14
+    bins = sp.Bins(kmin_f * kf, dk_f * kf, nb, box, n)
+    got = bins.counts()
+    for b in range(nb):
+        lo = (kmin_f + b * dk_f) ** 2
+        hi = (kmin_f + (b + 1) * dk_f) ** 2
+        assert got[b] == _lattice_counts(n, lo, hi), (b, got[b])
+    if (kmin_f, dk_f) == (0, 1):
+        assert list(got[:3]) == [0, 26, 66]
+        assert got[27] == _lattice_counts(n, 729, 784)
