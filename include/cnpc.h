@@ -82,9 +82,10 @@ typedef struct {
 
 /* k bins: half-open [kmin + b dk, kmin + (b+1) dk), b = 0..nbins-1.  Mode
  * membership is decided on the integer |n|^2 with thresholds
- * T_b = ceil(((kmin + b dk) / k_f)^2) computed in FP64 (this reading of the
- * binning mask of the Sugiyama section is documented in the design notes).
- * The k = 0 mode and modes with a Nyquist component are excluded.  The top
+ * T_b = ceil(((kmin + b dk) / k_f)^2) computed in FP64, an edge whose square is
+ * within a relative 1e-9 of an integer counting as exactly on it (a reading of
+ * the binning mask of the Sugiyama section, whose printed inequalities differ
+ * between its equations).  The k = 0 mode and modes with a Nyquist component are excluded.  The top
  * edge must not exceed the Nyquist wavenumber. */
 typedef struct {
   double kmin;

@@ -104,10 +104,15 @@ cnpc_status check_bins(const cnpc_mesh_desc* d, const cnpc_kbins* b) {
 }
 
 void bin_thresholds(const cnpc_mesh_desc* d, const cnpc_kbins* b, int64_t* out) {
+  // smallest integer n^2 at or above (edge / kf)^2; an edge whose square is
+  // within a relative 1e-9 of an integer sits on it, so that the rounding of
+  // dk and kf never moves a whole lattice shell across a half-open edge
   const double kf = 2.0 * M_PI / d->boxsize;
   for (int i = 0; i <= b->nbins; ++i) {
     const double x = (b->kmin + (double)i * b->dk) / kf;
-    out[i] = (int64_t)ceil(x * x);
+    const double v = x * x;
+    const double r = nearbyint(v);
+    out[i] = (int64_t)(fabs(v - r) <= 1e-9 * fmax(1.0, v) ? r : ceil(v));
   }
 }
 
@@ -296,7 +301,7 @@ int32_t cnpc_band_for(const cnpc_mesh_desc* d, double kmax) {
 
 size_t cnpc_deinterlace_workspace_size(const cnpc_mesh_desc* d) {
   if (check_desc(d) != CNPC_OK) return 0;
-  return deinterlace_ws_bytes(d);
+  return deinterlace_ws_max(d);
 }
 
 cnpc_status cnpc_deinterlace(const cnpc_mesh_desc* d, int32_t band, const void* meshes, void* spec_band,

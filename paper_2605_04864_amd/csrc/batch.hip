@@ -82,7 +82,7 @@ static void batch_layout(cnpc_batch* B) {
   B->o_nmodes = take(sizeof(int64_t) * nb);
   B->o_keff = take(sizeof(double) * nb);
   size_t call = paint_layout(d, B->max_ngal, B->max_nran, true).total;
-  call = std::max(call, deinterlace_ws_bytes(d));
+  call = std::max(call, deinterlace_ws_max(d));
   if (B->nhi) call = std::max(call, ylm_r2c_ws_bytes(d, B->nf, B->band));
   call = std::max(call, bin_ws_doubles(nb, B->nells + 1, 1) * sizeof(double));
   call = std::max(call, bispec_ws_bytes(d, &B->bins, CNPC_EST_SCOCCIMARRO, 0));

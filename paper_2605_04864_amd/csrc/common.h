@@ -53,7 +53,8 @@ cnpc_status check_bins(const cnpc_mesh_desc* d, const cnpc_kbins* b);
 inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 inline int ilog2_host(int n) { int l = 0; while ((1 << l) < n) ++l; return l; }
 inline size_t esize(int dtype) { return dtype == CNPC_F64 ? 8 : 4; }
-// FP64 bin thresholds T_b = ceil(((kmin + b dk)/kf)^2), b = 0..nbins (host)
+// FP64 bin thresholds T_b = ceil(((kmin + b dk)/kf)^2), b = 0..nbins (host);
+// an edge within a relative 1e-9 of an integer n^2 is taken to be on it
 void bin_thresholds(const cnpc_mesh_desc* d, const cnpc_kbins* b, int64_t* out);
 
 // ---------------------------------------------------------------- complex --

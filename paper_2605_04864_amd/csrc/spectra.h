@@ -31,6 +31,7 @@ cnpc_status launch_ylm_r2c(const cnpc_mesh_desc* d, int band, int nells, const i
 cnpc_status launch_ylm_fields(const cnpc_mesh_desc* d, int ell, const void* delta, void* out,
                               hipStream_t s);
 size_t deinterlace_ws_bytes(const cnpc_mesh_desc* d);
+size_t deinterlace_ws_max(const cnpc_mesh_desc* d);
 size_t deinterlace_band_ws_bytes(const cnpc_mesh_desc* d, int band);
 cnpc_status launch_deinterlace(const cnpc_mesh_desc* d, int band, const void* meshes, void* spec,
                                void* delta_int, void* ws, size_t ws_bytes, hipStream_t s);

@@ -484,6 +484,11 @@ size_t deinterlace_band_ws_bytes(const cnpc_mesh_desc* d, int band) {
   return (nb * bsz + fft_ws_elems(d->n, nb, band)) * 2 * esize(d->dtype);
 }
 
+// workspace that covers every band (the band-pruned path grows with the band)
+size_t deinterlace_ws_max(const cnpc_mesh_desc* d) {
+  return std::max(deinterlace_ws_bytes(d), deinterlace_band_ws_bytes(d, d->n / 2));
+}
+
 template <typename T>
 static cnpc_status deinterlace_t(const cnpc_mesh_desc* d, int band, const T* meshes, cx<T>* spec,
                                  T* delta_int, cx<T>* ws, hipStream_t s) {
