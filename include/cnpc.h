@@ -224,6 +224,22 @@ cnpc_status cnpc_bin_pk(const cnpc_mesh_desc* desc, const cnpc_kbins* bins, int3
                         double* means, double* selfterm, int64_t* nmodes, double* keff,
                         void* ws, size_t ws_bytes, void* stream);
 
+/* cnpc_bin_pk without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, outputs and limits as cnpc_bin_pk;
+ * the FP64 shell accumulators live in a static device array of
+ * 128 * (16 + 4 + 1) doubles (21.5 KiB, the largest binning cnpc_bin_pk
+ * accepts), one per GPU, held until the process ends; nbins * (npairs + nself
+ * + 1) above that is rejected with CNPC_EINVAL.  No call allocates or frees
+ * memory.  Every call on a GPU uses that GPU's one array (cleared by the call
+ * itself), so calls that overlap on one GPU, on any streams, race: serialise
+ * them.  The stream must belong to the current device. */
+cnpc_status cnpc_bin_pk_noalloc(const cnpc_mesh_desc* desc, const cnpc_kbins* bins, int32_t band,
+                                int32_t npairs, const void* const* pa, const void* const* pb,
+                                int32_t nself, const int32_t* self_ells, const double* norms,
+                                double* means, double* selfterm, int64_t* nmodes, double* keff,
+                                void* stream);
+
 /* Shell means of Im F_a(k) F_b(k)^* (odd multipoles: the imaginary-part form
  * of eq. pk_final).  Same arguments, limits and workspace as cnpc_bin_pk with
  * no self terms; for anti-Hermitian products (F_0 F_l^*, l odd) the half-grid

@@ -81,6 +81,8 @@ _PROTOS = {
     "cnpc_bin_pk_workspace_size": (_sz, [_PB, _i32, _i32]),
     "cnpc_bin_pk": (_i32, [_PD, _PB, _i32, _i32, C.POINTER(_vp), C.POINTER(_vp), _i32,
                            C.POINTER(_i32), _cvp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "cnpc_bin_pk_noalloc": (_i32, [_PD, _PB, _i32, _i32, C.POINTER(_vp), C.POINTER(_vp), _i32,
+                                   C.POINTER(_i32), _cvp, _vp, _vp, _vp, _vp, _vp]),
     "cnpc_pk_finalize": (_i32, [_PB, _cvp, _cvp, _cvp, _cvp, _cvp, _cvp, _cvp, _vp, _vp]),
     "cnpc_bispec_workspace_size": (_sz, [_PD, _PB, _i32, _i32]),
     "cnpc_bispec_plan_create": (_i32, [C.POINTER(_vp), _PD, _PB, _i32, _i32, _i32, _vp, _sz, _vp]),

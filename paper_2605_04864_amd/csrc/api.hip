@@ -400,6 +400,54 @@ cnpc_status cnpc_bin_pk(const cnpc_mesh_desc* d, const cnpc_kbins* b, int32_t ba
                        ws, ws_bytes, stream);
 }
 
+// Allocation-free bin_pk.  Its FP64 shell accumulators live in `scratch`, a
+// file-scope device array sized for the largest binning cnpc_bin_pk accepts;
+// each device holds its own copy, whose address is looked up once per device
+// with that device current and kept.  Host code only ever uses that address:
+// the array's name is a host-side stand-in, not a device pointer.
+constexpr size_t NOALLOC_BIN_DOUBLES = (size_t)MAX_BINS * (MAX_PAIRS + MAX_SELF + 1);
+static __device__ __align__(256) double scratch[NOALLOC_BIN_DOUBLES];
+
+static cnpc_status noalloc_scratch(double** out) {
+  static std::mutex mu;
+  static double* addr[64] = {nullptr};
+  int dev = 0;
+  CNPC_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) {
+    set_error("device index %d out of range", dev);
+    return CNPC_EUNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lk(mu);
+  if (addr[dev] == nullptr) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr) {
+      set_error("device %d: no address for the bin_pk scratch array (%s)", dev, hipGetErrorString(e));
+      return CNPC_EHIP;
+    }
+    addr[dev] = static_cast<double*>(p);
+  }
+  *out = addr[dev];
+  return CNPC_OK;
+}
+
+cnpc_status cnpc_bin_pk_noalloc(const cnpc_mesh_desc* d, const cnpc_kbins* b, int32_t band, int32_t npairs,
+                                const void* const* pa, const void* const* pb, int32_t nself,
+                                const int32_t* self_ells, const double* norms, double* means,
+                                double* selfterm, int64_t* nmodes, double* keff, void* stream) {
+  API_BEGIN;
+  CNPC_REQUIRE(b != nullptr, "null k-bins");
+  CNPC_REQUIRE(b->nbins >= 1 && npairs >= 0 && nself >= 0, "nbins must be >= 1, npairs and nself >= 0");
+  const size_t need = bin_ws_doubles(b->nbins, npairs, nself);
+  CNPC_REQUIRE(need <= NOALLOC_BIN_DOUBLES,
+               "bin_pk_noalloc: nbins * (npairs + nself + 1) = %zu exceeds the static scratch of %zu doubles",
+               need, NOALLOC_BIN_DOUBLES);
+  double* ws = nullptr;
+  CNPC_TRY(noalloc_scratch(&ws));
+  return bin_pk_common(d, b, band, npairs, pa, pb, 0u, nself, self_ells, norms, means, selfterm, nmodes, keff,
+                       ws, NOALLOC_BIN_DOUBLES * sizeof(double), stream);
+}
+
 cnpc_status cnpc_bin_pk_im(const cnpc_mesh_desc* d, const cnpc_kbins* b, int32_t band, int32_t npairs,
                            const void* const* pa, const void* const* pb, double* means, int64_t* nmodes,
                            double* keff, void* ws, size_t ws_bytes, void* stream) {

@@ -196,3 +196,15 @@ def test_tripolar_real_coeffs_match_oracle():
         assert L.lib.cnpc_sugi_paired_count(l1, l2, Lm) == paired_paper
     assert L.lib.cnpc_tripolar_real_coeffs(1, 1, 1, None, None) == -1  # odd l1 + l2 + L
     assert L.lib.cnpc_tripolar_real_coeffs(2, 2, 5, None, None) == -1  # triangle rule
+
+
+def test_bin_pk_noalloc_rejects_binning_beyond_static_scratch():
+    """The allocation-free bin_pk holds accumulators for at most 128 bins x (16
+    products + 4 self terms + 1); a larger binning is refused on the host."""
+    from paper_2605_04864_amd import _lib as L
+    d = L.mesh_desc(256, 1000.0, assign=L.TSC, interlace=True, dtype=L.F32)
+    b = L.kbins(0.0, 0.001, 129)
+    st = L.lib.cnpc_bin_pk_noalloc(C.byref(d), C.byref(b), 128, 16, None, None, 4, None, None, None, None,
+                                   None, None, None)
+    assert st != 0
+    assert "static scratch" in L.last_error()
