@@ -503,6 +503,12 @@ cnpc_status cnpc_ktimer_stop(double* ms_per_class, int64_t* launches_per_class);
  *   CNPC_TUNE_CONTRACT_KG  point groups per contraction workgroup (1, 2, 4).
  *   CNPC_TUNE_SORT_PER     particles per thread of the sort scatter (1, 2, 4).
  *   CNPC_TUNE_SORT_THREADS threads per sort-scatter workgroup (512, 1024).
+ *   CNPC_TUNE_SORT_FUSED   cnpc_paint_fkp on meshes of more than one tile
+ *                          bucket: 0 (default) takes the catalog sums, the
+ *                          tile histogram and the first sort step in one read
+ *                          of each catalog; 1 takes the sums and histogram in
+ *                          a read of their own (identical meshes up to the
+ *                          rounding of alpha, sums equal to a few ulp).
  * cnpc_tune_set rejects unknown knobs and values outside those ranges;
  * cnpc_tune_get returns the current value (-1 for an unknown knob). */
 #define CNPC_TUNE_FFT_PASSES 0
@@ -510,7 +516,8 @@ cnpc_status cnpc_ktimer_stop(double* ms_per_class, int64_t* launches_per_class);
 #define CNPC_TUNE_CONTRACT_KG 2
 #define CNPC_TUNE_SORT_PER 3
 #define CNPC_TUNE_SORT_THREADS 4
-#define CNPC_TUNE_COUNT 5
+#define CNPC_TUNE_SORT_FUSED 5
+#define CNPC_TUNE_COUNT 6
 cnpc_status cnpc_tune_set(int32_t knob, int32_t value);
 int32_t cnpc_tune_get(int32_t knob);
 

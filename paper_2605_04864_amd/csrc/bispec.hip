@@ -227,13 +227,24 @@ size_t contract_partial_doubles(int nshell, int ncols) {
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
 
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+
+// hi + lo split of 8 floats into packed bf16 by truncation: hi keeps the top 16
+// bits of each float (sign, exponent, 7 mantissa bits), lo = v - hi is exact in
+// FP32 and is truncated to bf16 in turn, so hi + lo is within 2^-16 |v| of v.
+// Two values per v_perm_b32 (the high halves of a pair of words).
 __device__ __forceinline__ void split_bf16(const float* v, bf16x8_t& hi, bf16x8_t& lo) {
+  u32x4_t h, l;
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const __bf16 h = (__bf16)v[e];
-    hi[e] = h;
-    lo[e] = (__bf16)(v[e] - (float)h);
+  for (int e = 0; e < 4; ++e) {
+    const uint32_t b0 = __float_as_uint(v[2 * e]), b1 = __float_as_uint(v[2 * e + 1]);
+    const float l0 = v[2 * e] - __uint_as_float(b0 & 0xffff0000u);
+    const float l1 = v[2 * e + 1] - __uint_as_float(b1 & 0xffff0000u);
+    h[e] = __builtin_amdgcn_perm(b1, b0, 0x07060302u);
+    l[e] = __builtin_amdgcn_perm(__float_as_uint(l1), __float_as_uint(l0), 0x07060302u);
   }
+  hi = __builtin_bit_cast(bf16x8_t, h);
+  lo = __builtin_bit_cast(bf16x8_t, l);
 }
 
 constexpr int MF_KC = 256;       // grid points per LDS chunk (= threads per workgroup)
@@ -312,6 +323,7 @@ __global__ void __launch_bounds__(256, 2) k_contract_mfma(const float* __restric
       for (int f = 0; f < MAXF; ++f)
         if (f < nf) pre[f] = ok ? src[(int64_t)f * npts + xn] : 0.f;
     }
+#pragma unroll
     for (int ks = kg * 16; ks < MF_KC; ks += 16 * KG) {
       bf16x8_t bhi[NT], blo[NT];
 #pragma unroll

@@ -26,6 +26,11 @@ struct PaintLayout {
   size_t off_partial, off_sums;  // catalog-sum partials and sums (fused entry point)
   size_t off_start, off_cursor, off_bcur;
   size_t off_blocks[4];
+  // fused bucket pass (entry point with catalog sums, more than one bucket):
+  // fixed-capacity bucket regions, the overflow records, the bucket
+  // reservation counters (+ one overflow counter)
+  uint32_t cap;
+  size_t off_region, off_ovf, off_bcnt;
   size_t total;
 };
 

@@ -394,6 +394,216 @@ __global__ void __launch_bounds__(NT) k_partition(const uint32_t* __restrict__ p
   }
 }
 
+// ------------------------------------------------------ fused bucket pass --
+// One read of a catalog does the FP64 catalog sums, the tile histogram and the
+// first counting-sort step.  Buckets have a fixed capacity `cap` (bucket b at
+// region + b cap): a workgroup reserves its run in bucket b with one atomic on
+// bcnt[b] and sends whatever would pass the capacity to the overflow region
+// (reserved on *ovf), which the tile pass takes as chunks of mixed buckets.
+// Persistent workgroups walk chunks of NT * PER particles, so the LDS tile
+// histogram is flushed with one atomic per non-empty tile per workgroup.
+struct BucketArgs {
+  TileGeom g;
+  int ntiles, nbuckets;
+  uint32_t cap;       // records per bucket region
+  uint32_t* bcnt;     // [nbuckets] reservations per bucket (may exceed cap)
+  uint32_t* ovf;      // overflow records reserved
+  uint32_t* tcount;   // [ntiles] tile histogram
+  double* partial;    // [gridDim.x][CNPC_SUMS_LEN] catalog-sum partials
+};
+
+// LDS bytes of k_bucket_pass
+__host__ __device__ constexpr size_t bucket_pass_lds(int per, int rs, int nbuckets, int nt, int ltiles) {
+  return (size_t)nt * per * (rs * 4 + 2) + (size_t)6 * nbuckets * 4 + 64 + (size_t)ltiles * 4;
+}
+
+template <int RS, int PER, int NT, int LMAX>
+__global__ void __launch_bounds__(NT) k_bucket_pass(const uint32_t* __restrict__ pos, const float* __restrict__ w,
+                                                    int64_t n, SumsArgs sa, BucketArgs ba,
+                                                    Rec<RS>* __restrict__ region, Rec<RS>* __restrict__ ovf_out) {
+  constexpr int CH = NT * PER;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  Rec<RS>* stage = reinterpret_cast<Rec<RS>*>(smem_raw);                        // [CH]
+  uint16_t* skey = reinterpret_cast<uint16_t*>(smem_raw + (size_t)CH * RS * 4);  // [CH]
+  uint32_t* hist = reinterpret_cast<uint32_t*>(smem_raw + (size_t)CH * (RS * 4 + 2));
+  uint32_t* lstart = hist + ba.nbuckets;
+  uint32_t* gbase = lstart + ba.nbuckets;
+  uint32_t* nin = gbase + ba.nbuckets;
+  uint32_t* obase = nin + ba.nbuckets;
+  uint32_t* wsum = obase + ba.nbuckets;  // 16 slots
+  uint32_t* ltile = wsum + 16;
+  const bool lds_tiles = ba.ntiles <= LDS_TILES_MAX;
+  if (lds_tiles)
+    for (int t = threadIdx.x; t < ba.ntiles; t += NT) ltile[t] = 0u;
+  double acc[CNPC_SUMS_LEN];
+#pragma unroll
+  for (int q = 0; q < CNPC_SUMS_LEN; ++q) acc[q] = 0.0;
+  const double scale = sa.boxsize / 4294967296.0;
+  const int bshift = 3 * ba.g.ls;
+  for (int64_t c0 = (int64_t)blockIdx.x * CH; c0 < n; c0 += (int64_t)gridDim.x * CH) {
+    Rec<RS> r[PER];
+    int key[PER];
+    __syncthreads();  // the previous chunk's LDS reads are done
+    for (int t = threadIdx.x; t < ba.nbuckets; t += NT) hist[t] = 0u;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int64_t i = c0 + (int64_t)k * NT + threadIdx.x;
+      key[k] = -1;
+      if (i < n) {
+        r[k].v[0] = pos[i];
+        r[k].v[1] = pos[n + i];
+        r[k].v[2] = pos[2 * n + i];
+        if constexpr (RS == 4) r[k].v[3] = __float_as_uint(w[i]);
+      }
+    }
+    __syncthreads();
+    uint32_t rank[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int64_t i = c0 + (int64_t)k * NT + threadIdx.x;
+      if (i < n) {
+        const int t = tile_key(r[k].v[0], r[k].v[1], r[k].v[2], ba.g);
+        key[k] = t >> bshift;
+        if (lds_tiles) atomicAdd(&ltile[t], 1u);
+        else atomicAdd(&ba.tcount[t], 1u);
+        rank[k] = atomicAdd(&hist[key[k]], 1u);
+        const double wi = RS == 4 ? (double)__uint_as_float(r[k].v[3]) : 1.0;
+        sums_add<LMAX>(acc, r[k].v[0], r[k].v[1], r[k].v[2], wi, scale, sa);
+      }
+    }
+    __syncthreads();
+    block_exclusive_scan<NT>(hist, ba.nbuckets, wsum, [&](int b, uint32_t v) {
+      lstart[b] = v;
+      const uint32_t c = hist[b];
+      uint32_t gb = 0u, ni = 0u, ob = 0u;
+      if (c) {
+        gb = atomicAdd(&ba.bcnt[b], c);
+        ni = gb >= ba.cap ? 0u : min(c, ba.cap - gb);
+        if (c > ni) ob = atomicAdd(ba.ovf, c - ni);
+      }
+      gbase[b] = gb;
+      nin[b] = ni;
+      obase[b] = ob;
+    });
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PER; ++k)
+      if (key[k] >= 0) {
+        const uint32_t slot = lstart[key[k]] + rank[k];
+        stage[slot] = r[k];
+        skey[slot] = (uint16_t)key[k];
+      }
+    __syncthreads();
+    const int cnt = (int)min((int64_t)CH, n - c0);
+    for (int j = threadIdx.x; j < cnt; j += NT) {
+      const int b = skey[j];
+      const uint32_t q = (uint32_t)j - lstart[b];
+      if (q < nin[b]) region[(int64_t)b * ba.cap + gbase[b] + q] = stage[j];
+      else ovf_out[obase[b] + (q - nin[b])] = stage[j];
+    }
+  }
+  // catalog-sum partial of the workgroup (fixed-order reduction)
+  __syncthreads();
+  double* red = reinterpret_cast<double*>(smem_raw);  // [NT / 64][CNPC_SUMS_LEN], over the stage
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < CNPC_SUMS_LEN; ++q) {
+    const double v = wave_sum(acc[q]);
+    if (lane == 0) red[wv * CNPC_SUMS_LEN + q] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < CNPC_SUMS_LEN) {
+    double v = 0.0;
+    for (int k = 0; k < NT / 64; ++k) v += red[k * CNPC_SUMS_LEN + threadIdx.x];
+    ba.partial[(int64_t)blockIdx.x * CNPC_SUMS_LEN + threadIdx.x] = v;
+  }
+  if (lds_tiles)
+    for (int t = threadIdx.x; t < ba.ntiles; t += NT) {
+      const uint32_t c = ltile[t];
+      if (c) atomicAdd(&ba.tcount[t], c);
+    }
+}
+
+// Second counting-sort step over the bucket regions: workgroup (b, j) sorts
+// records j CH .. of bucket b (its keys lie in bucket b); workgroups past the
+// last region chunk walk the overflow records (mixed buckets: one global slot
+// per particle).
+template <int RS, int PER, int NT>
+__global__ void __launch_bounds__(NT) k_tile_pass(const Rec<RS>* __restrict__ region,
+                                                  const Rec<RS>* __restrict__ ovf_in, const uint32_t* __restrict__ bcnt,
+                                                  const uint32_t* __restrict__ ovf, uint32_t cap, int chunks_per_bucket,
+                                                  int nbuckets, TileGeom g, uint32_t* __restrict__ cursor,
+                                                  Rec<RS>* __restrict__ rout) {
+  constexpr int CH = NT * PER;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int bshift = 3 * g.ls;
+  const int R = 1 << bshift;  // tiles per bucket
+  const int nreg = nbuckets * chunks_per_bucket;
+  if ((int)blockIdx.x >= nreg) {
+    const uint32_t no = *ovf;
+    for (int64_t c0 = (int64_t)(blockIdx.x - nreg) * CH; c0 < no; c0 += (int64_t)(gridDim.x - nreg) * CH) {
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        const int64_t i = c0 + (int64_t)k * NT + threadIdx.x;
+        if (i < no) {
+          const Rec<RS> rr = ovf_in[i];
+          rout[atomicAdd(&cursor[tile_key(rr.v[0], rr.v[1], rr.v[2], g)], 1u)] = rr;
+        }
+      }
+    }
+    return;
+  }
+  const int b = blockIdx.x / chunks_per_bucket, jc = blockIdx.x - b * chunks_per_bucket;
+  const uint32_t nb_ = min(bcnt[b], cap);
+  const int64_t c0 = (int64_t)jc * CH;
+  if (c0 >= nb_) return;
+  const int cnt = (int)min((int64_t)CH, (int64_t)nb_ - c0);
+  const Rec<RS>* rin = region + (int64_t)b * cap + c0;
+  Rec<RS>* stage = reinterpret_cast<Rec<RS>*>(smem_raw);                        // [CH]
+  uint16_t* skey = reinterpret_cast<uint16_t*>(smem_raw + (size_t)CH * RS * 4);  // [CH]
+  uint32_t* hist = reinterpret_cast<uint32_t*>(smem_raw + (size_t)CH * (RS * 4 + 2));
+  uint32_t* lstart = hist + R;
+  uint32_t* gbase = lstart + R;
+  uint32_t* wsum = gbase + R;  // 16 slots
+  const int klo = b << bshift;
+  Rec<RS> r[PER];
+  int key[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int i = k * NT + threadIdx.x;
+    key[k] = -1;
+    if (i < cnt) {
+      r[k] = rin[i];
+      key[k] = tile_key(r[k].v[0], r[k].v[1], r[k].v[2], g) - klo;
+    }
+  }
+  for (int t = threadIdx.x; t < R; t += NT) hist[t] = 0u;
+  __syncthreads();
+  uint32_t rank[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k)
+    if (key[k] >= 0) rank[k] = atomicAdd(&hist[key[k]], 1u);
+  __syncthreads();
+  block_exclusive_scan<NT>(hist, R, wsum, [&](int t, uint32_t v) {
+    lstart[t] = v;
+    const uint32_t c = hist[t];
+    gbase[t] = c ? atomicAdd(&cursor[klo + t], c) : 0u;
+  });
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < PER; ++k)
+    if (key[k] >= 0) {
+      const uint32_t slot = lstart[key[k]] + rank[k];
+      stage[slot] = r[k];
+      skey[slot] = (uint16_t)key[k];
+    }
+  __syncthreads();
+  for (int j = threadIdx.x; j < cnt; j += NT) {
+    const int kk = skey[j];
+    rout[gbase[kk] + (j - lstart[kk])] = stage[j];
+  }
+}
+
 // ------------------------------------------------------------------ paint --
 // 1-D stencil: node offsets relative to the base cell c = floor(u) and weights.
 template <typename T>
@@ -812,6 +1022,19 @@ static TileGeom tile_geom(const cnpc_mesh_desc* d) {
   return g;
 }
 
+// Bucket-pass geometry: chunk of BUCKET_NT * per particles, at most
+// BUCKET_BLOCKS_MAX persistent workgroups; a bucket region holds 1.5 times the
+// mean bucket count plus a chunk (more goes to the overflow region).
+constexpr int BUCKET_NT = 1024;
+constexpr int BUCKET_BLOCKS_MAX = 512;
+constexpr int OVF_BLOCKS = 256;  // tile-pass workgroups walking the overflow records
+static int bucket_per(int rs) { return rs == 3 ? 4 : 2; }
+static uint32_t bucket_cap(int64_t n, int nbuckets) {
+  const int64_t mean = (n + nbuckets - 1) / nbuckets;
+  const int64_t c = mean + mean / 2 + (int64_t)BUCKET_NT * 4;
+  return (uint32_t)((c + 63) / 64 * 64);
+}
+
 PaintLayout paint_layout(const cnpc_mesh_desc* d, int64_t ngal, int64_t nran, bool weighted) {
   PaintLayout L;
   const int nt = d->n / TILE;
@@ -829,7 +1052,7 @@ PaintLayout paint_layout(const cnpc_mesh_desc* d, int64_t ngal, int64_t nran, bo
   L.off_tmp = off; off = align_up(off + (L.nbuckets > 1 ? rec : 0));
   L.off_count[0] = off; off = align_up(off + (size_t)L.ntiles * 4);
   L.off_count[1] = off; off = align_up(off + (size_t)L.ntiles * 4);
-  L.off_partial = off; off = align_up(off + (size_t)SUMS_BLOCKS * CNPC_SUMS_LEN * 8);
+  L.off_partial = off; off = align_up(off + (size_t)BUCKET_BLOCKS_MAX * CNPC_SUMS_LEN * 8);
   L.off_sums = off; off = align_up(off + (size_t)2 * CNPC_SUMS_LEN * 8);
   L.off_start = off; off = align_up(off + (size_t)L.ntiles * 4);
   L.off_cursor = off; off = align_up(off + (size_t)L.ntiles * 4);
@@ -837,6 +1060,15 @@ PaintLayout paint_layout(const cnpc_mesh_desc* d, int64_t ngal, int64_t nran, bo
   for (int k = 0; k < L.nsets; ++k) {
     L.off_blocks[k] = off;
     off = align_up(off + (size_t)L.ntiles * L.nphase * BSTRIDE * es);
+  }
+  L.cap = 0;
+  L.off_region = L.off_ovf = L.off_bcnt = off;
+  if (L.nbuckets > 1) {
+    const size_t rs = weighted ? 16 : 12;
+    L.cap = bucket_cap(np, L.nbuckets);
+    L.off_region = off; off = align_up(off + (size_t)L.nbuckets * L.cap * rs);
+    L.off_ovf = off; off = align_up(off + (size_t)np * rs);
+    L.off_bcnt = off; off = align_up(off + (size_t)(L.nbuckets + 1) * 4);
   }
   L.total = off;
   return L;
@@ -903,38 +1135,14 @@ static cnpc_status launch_partition(const uint32_t* pos, const float* w, const R
   return CNPC_OK;
 }
 
+// Tile painting of tile-sorted records (rec, start, count of set set0).
 template <typename T, int RS>
-static cnpc_status sort_and_paint(const cnpc_mesh_desc* d, const uint32_t* pos, const float* w, int64_t n,
-                                  int set0, bool weighted, bool counted, unsigned char* ws,
-                                  const PaintLayout& L, hipStream_t s) {
+static cnpc_status paint_sorted(const cnpc_mesh_desc* d, bool weighted, int set0, unsigned char* ws,
+                                const PaintLayout& L, hipStream_t s) {
   const TileGeom g = tile_geom(d);
   uint32_t* count = reinterpret_cast<uint32_t*>(ws + L.off_count[set0]);
   uint32_t* start = reinterpret_cast<uint32_t*>(ws + L.off_start);
-  uint32_t* cursor = reinterpret_cast<uint32_t*>(ws + L.off_cursor);
-  uint32_t* bcur = reinterpret_cast<uint32_t*>(ws + L.off_bcur);
   Rec<RS>* rec = reinterpret_cast<Rec<RS>*>(ws + L.off_rec);
-  Rec<RS>* tmp = reinterpret_cast<Rec<RS>*>(ws + L.off_tmp);
-  if (!counted) {
-    hipLaunchKernelGGL(k_zero_u32, dim3(64), dim3(256), 0, s, count, (int64_t)L.ntiles);
-    CNPC_HIP(hipGetLastError());
-    const size_t lds_count = L.ntiles <= LDS_TILES_MAX ? (size_t)L.ntiles * 4 : 0;
-    const int64_t chunk = (int64_t)SORT_BLOCK * SORT_PER_THREAD;
-    const int64_t nblk = (n + chunk - 1) / chunk;
-    kt_begin(CNPC_KT_SORT, s);
-    hipLaunchKernelGGL(k_tile_count, dim3((unsigned)nblk), dim3(SORT_BLOCK), lds_count, s, pos, n, g, L.ntiles,
-                       count);
-    kt_end(CNPC_KT_SORT, s);
-    CNPC_HIP(hipGetLastError());
-  }
-  const int per_bucket = 1 << (3 * g.ls);
-  hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, count, L.ntiles, per_bucket, start, cursor, bcur);
-  CNPC_HIP(hipGetLastError());
-  if (L.nbuckets > 1) {
-    CNPC_TRY((launch_partition<true, false, RS>(pos, w, nullptr, n, g, L.nbuckets, bcur, tmp, s)));
-    CNPC_TRY((launch_partition<false, true, RS>(nullptr, nullptr, tmp, n, g, FINE_RCAP, cursor, rec, s)));
-  } else {
-    CNPC_TRY((launch_partition<true, true, RS>(pos, w, nullptr, n, g, L.ntiles, cursor, rec, s)));
-  }
   // phases per launch so that the 64-bit LDS blocks fit the workgroup limit
   const int nph = ((size_t)L.nphase * BVOL * 8 <= lds_limit()) ? L.nphase : 1;
   const size_t lds_paint = (size_t)nph * BVOL * 8;
@@ -968,11 +1176,141 @@ static cnpc_status sort_and_paint(const cnpc_mesh_desc* d, const uint32_t* pos, 
   return CNPC_OK;
 }
 
+template <typename T, int RS>
+static cnpc_status sort_and_paint(const cnpc_mesh_desc* d, const uint32_t* pos, const float* w, int64_t n,
+                                  int set0, bool weighted, bool counted, unsigned char* ws,
+                                  const PaintLayout& L, hipStream_t s) {
+  const TileGeom g = tile_geom(d);
+  uint32_t* count = reinterpret_cast<uint32_t*>(ws + L.off_count[set0]);
+  uint32_t* start = reinterpret_cast<uint32_t*>(ws + L.off_start);
+  uint32_t* cursor = reinterpret_cast<uint32_t*>(ws + L.off_cursor);
+  uint32_t* bcur = reinterpret_cast<uint32_t*>(ws + L.off_bcur);
+  Rec<RS>* rec = reinterpret_cast<Rec<RS>*>(ws + L.off_rec);
+  Rec<RS>* tmp = reinterpret_cast<Rec<RS>*>(ws + L.off_tmp);
+  if (!counted) {
+    hipLaunchKernelGGL(k_zero_u32, dim3(64), dim3(256), 0, s, count, (int64_t)L.ntiles);
+    CNPC_HIP(hipGetLastError());
+    const size_t lds_count = L.ntiles <= LDS_TILES_MAX ? (size_t)L.ntiles * 4 : 0;
+    const int64_t chunk = (int64_t)SORT_BLOCK * SORT_PER_THREAD;
+    const int64_t nblk = (n + chunk - 1) / chunk;
+    kt_begin(CNPC_KT_SORT, s);
+    hipLaunchKernelGGL(k_tile_count, dim3((unsigned)nblk), dim3(SORT_BLOCK), lds_count, s, pos, n, g, L.ntiles,
+                       count);
+    kt_end(CNPC_KT_SORT, s);
+    CNPC_HIP(hipGetLastError());
+  }
+  const int per_bucket = 1 << (3 * g.ls);
+  hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, count, L.ntiles, per_bucket, start, cursor, bcur);
+  CNPC_HIP(hipGetLastError());
+  if (L.nbuckets > 1) {
+    CNPC_TRY((launch_partition<true, false, RS>(pos, w, nullptr, n, g, L.nbuckets, bcur, tmp, s)));
+    CNPC_TRY((launch_partition<false, true, RS>(nullptr, nullptr, tmp, n, g, FINE_RCAP, cursor, rec, s)));
+  } else {
+    CNPC_TRY((launch_partition<true, true, RS>(pos, w, nullptr, n, g, L.ntiles, cursor, rec, s)));
+  }
+  return paint_sorted<T, RS>(d, weighted, set0, ws, L, s);
+}
+
+// Catalog sums, tile histogram and both sort steps from one read of the
+// catalog (fused bucket pass), then the tile painting.  sums: CNPC_SUMS_LEN
+// doubles (device).
+template <int RS, int LMAX>
+static void launch_bucket_pass(unsigned nblk, size_t lds, const uint32_t* pos, const float* w, int64_t n,
+                               const SumsArgs& sa, const BucketArgs& ba, Rec<RS>* region, Rec<RS>* ovf_out,
+                               hipStream_t s) {
+  if constexpr (RS == 3)
+    hipLaunchKernelGGL((k_bucket_pass<3, 4, BUCKET_NT, LMAX>), dim3(nblk), dim3(BUCKET_NT), lds, s, pos, w, n, sa, ba,
+                       region, ovf_out);
+  else
+    hipLaunchKernelGGL((k_bucket_pass<4, 2, BUCKET_NT, LMAX>), dim3(nblk), dim3(BUCKET_NT), lds, s, pos, w, n, sa, ba,
+                       region, ovf_out);
+}
+
+template <typename T, int RS>
+static cnpc_status fused_sort_and_paint(const cnpc_mesh_desc* d, const uint32_t* pos, const float* w, int64_t n,
+                                        int set0, bool weighted, int sums_lmax, double* sums, unsigned char* ws,
+                                        const PaintLayout& L, hipStream_t s) {
+  const TileGeom g = tile_geom(d);
+  uint32_t* count = reinterpret_cast<uint32_t*>(ws + L.off_count[set0]);
+  uint32_t* start = reinterpret_cast<uint32_t*>(ws + L.off_start);
+  uint32_t* cursor = reinterpret_cast<uint32_t*>(ws + L.off_cursor);
+  uint32_t* bcur = reinterpret_cast<uint32_t*>(ws + L.off_bcur);
+  uint32_t* bcnt = reinterpret_cast<uint32_t*>(ws + L.off_bcnt);
+  Rec<RS>* rec = reinterpret_cast<Rec<RS>*>(ws + L.off_rec);
+  Rec<RS>* region = reinterpret_cast<Rec<RS>*>(ws + L.off_region);
+  Rec<RS>* ovf_rec = reinterpret_cast<Rec<RS>*>(ws + L.off_ovf);
+  double* partial = reinterpret_cast<double*>(ws + L.off_partial);
+  const uint32_t cap = bucket_cap(n, L.nbuckets);  // <= L.cap
+  const int per = bucket_per(RS);
+  const int64_t ch = (int64_t)BUCKET_NT * per;
+  const unsigned nblk = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + ch - 1) / ch, BUCKET_BLOCKS_MAX));
+  const int ltiles = L.ntiles <= LDS_TILES_MAX ? L.ntiles : 0;
+  const size_t lds = bucket_pass_lds(per, RS, L.nbuckets, BUCKET_NT, ltiles);
+  if (lds > lds_limit()) {
+    set_error("bucket pass: %zu bytes of LDS exceed the workgroup limit", lds);
+    return CNPC_EUNSUPPORTED;
+  }
+  hipLaunchKernelGGL(k_zero_u32, dim3(64), dim3(256), 0, s, count, (int64_t)L.ntiles);
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(256), 0, s, bcnt, (int64_t)L.nbuckets + 1);
+  CNPC_HIP(hipGetLastError());
+  SumsArgs sa;
+  sa.lmax = sums_lmax;
+  sa.boxsize = d->boxsize;
+  for (int i = 0; i < 3; ++i) { sa.obs[i] = d->observer[i]; sa.los[i] = d->los[i]; }
+  sa.global_los = d->los_mode == CNPC_LOS_GLOBAL;
+  BucketArgs ba;
+  ba.g = g;
+  ba.ntiles = L.ntiles;
+  ba.nbuckets = L.nbuckets;
+  ba.cap = cap;
+  ba.bcnt = bcnt;
+  ba.ovf = bcnt + L.nbuckets;
+  ba.tcount = count;
+  ba.partial = partial;
+  kt_begin(CNPC_KT_SORT, s);
+  if (sums_lmax >= 4) launch_bucket_pass<RS, 4>(nblk, lds, pos, w, n, sa, ba, region, ovf_rec, s);
+  else if (sums_lmax >= 2) launch_bucket_pass<RS, 2>(nblk, lds, pos, w, n, sa, ba, region, ovf_rec, s);
+  else launch_bucket_pass<RS, 0>(nblk, lds, pos, w, n, sa, ba, region, ovf_rec, s);
+  kt_end(CNPC_KT_SORT, s);
+  CNPC_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_reduce_partials, dim3(CNPC_SUMS_LEN), dim3(64), 0, s, partial, (int)nblk, sums);
+  CNPC_HIP(hipGetLastError());
+  const int per_bucket = 1 << (3 * g.ls);
+  hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, count, L.ntiles, per_bucket, start, cursor, bcur);
+  CNPC_HIP(hipGetLastError());
+  // tile pass: one workgroup per region chunk, then OVF_BLOCKS over the overflow
+  const int tper = partition_per(RS, per_bucket, 1024);
+  if (tper == 0) {
+    set_error("tile pass: %d keys do not fit the LDS of a workgroup", per_bucket);
+    return CNPC_EINVAL;
+  }
+  const int64_t tch = (int64_t)1024 * tper;
+  const int cpb = (int)((cap + tch - 1) / tch);
+  const unsigned tgrid = (unsigned)(L.nbuckets * cpb + OVF_BLOCKS);
+  const size_t tlds = partition_lds(tper, RS, per_bucket, 1024);
+  kt_begin(CNPC_KT_SORT, s);
+  if (tper == 4)
+    hipLaunchKernelGGL((k_tile_pass<RS, 4, 1024>), dim3(tgrid), dim3(1024), tlds, s, region, ovf_rec, bcnt,
+                       bcnt + L.nbuckets, cap, cpb, L.nbuckets, g, cursor, rec);
+  else if (tper == 2)
+    hipLaunchKernelGGL((k_tile_pass<RS, 2, 1024>), dim3(tgrid), dim3(1024), tlds, s, region, ovf_rec, bcnt,
+                       bcnt + L.nbuckets, cap, cpb, L.nbuckets, g, cursor, rec);
+  else
+    hipLaunchKernelGGL((k_tile_pass<RS, 1, 1024>), dim3(tgrid), dim3(1024), tlds, s, region, ovf_rec, bcnt,
+                       bcnt + L.nbuckets, cap, cpb, L.nbuckets, g, cursor, rec);
+  kt_end(CNPC_KT_SORT, s);
+  CNPC_HIP(hipGetLastError());
+  return paint_sorted<T, RS>(d, weighted, set0, ws, L, s);
+}
+
+// fused: sums_lmax >= 0 selects the fused bucket pass (catalog sums into
+// gs / rs, norms formed after both catalogs); counted: tile counts already taken.
 template <typename T>
 static cnpc_status paint_t(const cnpc_mesh_desc* d, const uint32_t* gpos, const float* gw,
                            int64_t ngal, const uint32_t* rpos, const float* rw, int64_t nran,
                            const double* norms, T* delta, T* noise, unsigned char* ws,
-                           const PaintLayout& L, bool counted, hipStream_t s) {
+                           const PaintLayout& L, bool counted, hipStream_t s, int sums_lmax = -1,
+                           double* gs = nullptr, double* rs = nullptr) {
   const bool weighted = (gw != nullptr) || (rw != nullptr);
   const uint32_t* cpos[2] = {gpos, rpos};
   const float* cw[2] = {gw, rw};
@@ -985,11 +1323,17 @@ static cnpc_status paint_t(const cnpc_mesh_desc* d, const uint32_t* gpos, const 
   for (int c = 0; c < 2; ++c) {
     for (int pw = 0; pw < (weighted ? 2 : 1); ++pw)
       fa.blocks[c + 2 * pw] = reinterpret_cast<T*>(ws + L.off_blocks[c + 2 * pw]);
-    if (cw[c])
+    double* sums_c = c == 0 ? gs : rs;
+    if (sums_lmax >= 0 && cw[c])
+      CNPC_TRY((fused_sort_and_paint<T, 4>(d, cpos[c], cw[c], cn[c], c, weighted, sums_lmax, sums_c, ws, L, s)));
+    else if (sums_lmax >= 0)
+      CNPC_TRY((fused_sort_and_paint<T, 3>(d, cpos[c], nullptr, cn[c], c, weighted, sums_lmax, sums_c, ws, L, s)));
+    else if (cw[c])
       CNPC_TRY((sort_and_paint<T, 4>(d, cpos[c], cw[c], cn[c], c, weighted, counted, ws, L, s)));
     else
       CNPC_TRY((sort_and_paint<T, 3>(d, cpos[c], nullptr, cn[c], c, weighted, counted, ws, L, s)));
   }
+  if (sums_lmax >= 0) CNPC_TRY(launch_norms(d, gs, rs, ngal, const_cast<double*>(norms), s));
   const int z2 = L.nt >= 2 ? 2 : 1;
   const int64_t nb = (int64_t)L.nphase * L.nt * L.nt * (L.nt / z2);
   kt_begin(CNPC_KT_FOLD, s);
@@ -1028,6 +1372,15 @@ cnpc_status launch_paint_fkp(const cnpc_mesh_desc* d, const uint32_t* gpos, cons
     return CNPC_EWORKSPACE;
   }
   unsigned char* w = reinterpret_cast<unsigned char*>(ws);
+  double* gs_ = gsums ? gsums : reinterpret_cast<double*>(w + L.off_sums);
+  double* rs_ = rsums ? rsums : reinterpret_cast<double*>(w + L.off_sums) + CNPC_SUMS_LEN;
+  if (L.nbuckets > 1 && tune_value(CNPC_TUNE_SORT_FUSED) != 1) {
+    if (d->dtype == CNPC_F64)
+      return paint_t<double>(d, gpos, gw, ngal, rpos, rw, nran, norms, (double*)delta, (double*)noise, w, L,
+                             false, s, sums_lmax, gs_, rs_);
+    return paint_t<float>(d, gpos, gw, ngal, rpos, rw, nran, norms, (float*)delta, (float*)noise, w, L, false,
+                          s, sums_lmax, gs_, rs_);
+  }
   uint32_t* count0 = reinterpret_cast<uint32_t*>(w + L.off_count[0]);
   uint32_t* count1 = reinterpret_cast<uint32_t*>(w + L.off_count[1]);
   double* partial = reinterpret_cast<double*>(w + L.off_partial);
