@@ -172,13 +172,32 @@ int32_t cnpc_band_for(const cnpc_mesh_desc* desc, double kmax);
 /* ---- interlacing and de-aliasing (design reading; not in the paper) ----
  * From the painted meshes A (and B): D(k) = 1/2 [D_A(k) + exp(-i k.(1,1,1)H/2) D_B(k)]
  * with every Nyquist-component mode zeroed (without interlacing D = D_A).
- * Writes D in band layout (half-width `band`) to spec_band and, when
+ * Writes D in band layout (half-width `band`, the n = -band rows included) to
+ * spec_band and, when
  * delta_int != NULL, the de-aliased real mesh IDFT(D) / N^3 (without
  * interlacing: a copy of A). */
 size_t cnpc_deinterlace_workspace_size(const cnpc_mesh_desc* desc);
 cnpc_status cnpc_deinterlace(const cnpc_mesh_desc* desc, int32_t band, const void* meshes,
                              void* spec_band, void* delta_int, void* ws, size_t ws_bytes,
                              void* stream);
+
+/* ---- painting with de-interlacing (cnpc_paint_fkp followed by cnpc_deinterlace
+ * of the delta mesh with delta_int and of the N mesh, in one call) ----
+ * Interlaced meshes of side 256 (register FFT passes, the default) only;
+ * other meshes return CNPC_EUNSUPPORTED.  The tile sums of the painting are
+ * taken inside the z passes of the two de-interlacing transforms, so the
+ * delta and N meshes are never stored.  Arguments as in cnpc_paint_fkp and
+ * cnpc_deinterlace; outputs (device): the catalog sums (optional), norms, the
+ * band spectrum D and delta_int (N^3 reals) of delta, the band spectrum of N.
+ * Workspace: cnpc_paint_deinterlace_workspace_size (weighted: 1 if weights are
+ * given).  Results equal the two-step form within FP rounding. */
+size_t cnpc_paint_deinterlace_workspace_size(const cnpc_mesh_desc* desc, int64_t ngal, int64_t nran,
+                                             int32_t weighted, int32_t band);
+cnpc_status cnpc_paint_deinterlace(const cnpc_mesh_desc* desc, int32_t band, const uint32_t* gal_pos,
+                                   const float* gal_w, int64_t ngal, const uint32_t* ran_pos, const float* ran_w,
+                                   int64_t nran, int32_t sums_lmax, double* gal_sums, double* ran_sums,
+                                   double* norms, void* spec_band, void* delta_int, void* noise_spec_band,
+                                   void* ws, size_t ws_bytes, void* stream);
 
 /* ---- ylm_fields: Y_lm-weighted real fields (eq. key1, eq. hand, eq. F_lm_SIC) ----
  * Materialised form: out = (2l+1) real meshes delta(x) * [Re y_l^0, Re y_l^1,
@@ -509,6 +528,10 @@ cnpc_status cnpc_ktimer_stop(double* ms_per_class, int64_t* launches_per_class);
  *                          of each catalog; 1 takes the sums and histogram in
  *                          a read of their own (identical meshes up to the
  *                          rounding of alpha, sums equal to a few ulp).
+ *   CNPC_TUNE_FOLD_FUSED   cnpc_paint_deinterlace and the batch runner: 0
+ *                          (default) sums the tile blocks inside the z passes
+ *                          of the de-interlacing transforms; 1 writes the
+ *                          delta and N meshes and transforms them.
  * cnpc_tune_set rejects unknown knobs and values outside those ranges;
  * cnpc_tune_get returns the current value (-1 for an unknown knob). */
 #define CNPC_TUNE_FFT_PASSES 0
@@ -517,7 +540,8 @@ cnpc_status cnpc_ktimer_stop(double* ms_per_class, int64_t* launches_per_class);
 #define CNPC_TUNE_SORT_PER 3
 #define CNPC_TUNE_SORT_THREADS 4
 #define CNPC_TUNE_SORT_FUSED 5
-#define CNPC_TUNE_COUNT 6
+#define CNPC_TUNE_FOLD_FUSED 6
+#define CNPC_TUNE_COUNT 7
 cnpc_status cnpc_tune_set(int32_t knob, int32_t value);
 int32_t cnpc_tune_get(int32_t knob);
 

@@ -73,6 +73,9 @@ _PROTOS = {
     "cnpc_fft_c2r": (_i32, [_PD, _i32, _i32, _cvp, _vp, _vp, _sz, _vp]),
     "cnpc_band_for": (_i32, [_PD, _d]),
     "cnpc_deinterlace_workspace_size": (_sz, [_PD]),
+    "cnpc_paint_deinterlace_workspace_size": (_sz, [_PD, _i64, _i64, _i32, _i32]),
+    "cnpc_paint_deinterlace": (_i32, [_PD, _i32, _cvp, _cvp, _i64, _cvp, _cvp, _i64, _i32, _vp, _vp, _vp, _vp, _vp,
+                                      _vp, _vp, _sz, _vp]),
     "cnpc_deinterlace": (_i32, [_PD, _i32, _cvp, _vp, _vp, _vp, _sz, _vp]),
     "cnpc_ylm_fields": (_i32, [_PD, _i32, _cvp, _vp, _vp]),
     "cnpc_ylm_r2c_workspace_size": (_sz, [_PD, _i32, _i32]),
@@ -127,7 +130,7 @@ KT = {"paint": 1, "sort": 2, "fold": 3, "zr2c": 4, "col": 5, "zc2r": 6, "contrac
 # tuning knobs (cnpc_tune_set / cnpc_tune_get): name -> (index, allowed values)
 TUNE = {"fft_passes": (0, (0, 1)), "fft_col_w": (1, (0, 1, 2, 4, 8, 16, 32, 64)),
         "contract_kg": (2, (0, 1, 2, 4)), "sort_per": (3, (0, 1, 2, 4)),
-        "sort_threads": (4, (0, 512, 1024)), "sort_fused": (5, (0, 1))}
+        "sort_threads": (4, (0, 512, 1024)), "sort_fused": (5, (0, 1)), "fold_fused": (6, (0, 1))}
 
 EXPORTED = tuple(_PROTOS)
 

@@ -138,6 +138,7 @@ cnpc_status cnpc_tune_set(int32_t knob, int32_t value) {
     case CNPC_TUNE_SORT_PER: ok = ok || value == 1 || value == 2 || value == 4; break;
     case CNPC_TUNE_SORT_THREADS: ok = ok || value == 512 || value == 1024; break;
     case CNPC_TUNE_SORT_FUSED: ok = value == 0 || value == 1; break;
+    case CNPC_TUNE_FOLD_FUSED: ok = value == 0 || value == 1; break;
   }
   CNPC_REQUIRE(ok, "value %d out of range for tuning knob %d", value, knob);
   g_tune[knob].store(value, std::memory_order_relaxed);
@@ -313,6 +314,36 @@ cnpc_status cnpc_deinterlace(const cnpc_mesh_desc* d, int32_t band, const void* 
   CNPC_TRY(check_band(d, band));
   CNPC_REQUIRE(meshes && spec_band && ws, "null pointer argument");
   return launch_deinterlace(d, band, meshes, spec_band, delta_int, ws, ws_bytes, as_stream(stream));
+}
+
+size_t cnpc_paint_deinterlace_workspace_size(const cnpc_mesh_desc* d, int64_t ngal, int64_t nran, int32_t weighted,
+                                             int32_t band) {
+  if (check_desc(d) != CNPC_OK || band < 1 || ngal < 1 || nran < 1) return 0;
+  return paint_deinterlace_ws_bytes(d, ngal, nran, weighted != 0, band);
+}
+
+cnpc_status cnpc_paint_deinterlace(const cnpc_mesh_desc* d, int32_t band, const uint32_t* gpos, const float* gw,
+                                   int64_t ngal, const uint32_t* rpos, const float* rw, int64_t nran, int32_t sums_lmax,
+                                   double* gal_sums, double* ran_sums, double* norms, void* spec_band,
+                                   void* delta_int, void* noise_spec_band, void* ws, size_t ws_bytes, void* stream) {
+  API_BEGIN;
+  CNPC_TRY(check_desc(d));
+  CNPC_REQUIRE(band >= 1, "band must be >= 1");
+  CNPC_TRY(check_band(d, band));
+  CNPC_REQUIRE(gpos && rpos && norms && spec_band && delta_int && noise_spec_band && ws, "null pointer argument");
+  CNPC_REQUIRE(ngal >= 1 && nran >= 1, "empty catalog");
+  CNPC_REQUIRE(sums_lmax == 0 || sums_lmax == 2 || sums_lmax == 4, "sums_lmax must be 0, 2 or 4");
+  if (!has_fold_zr2c(d)) {
+    set_error("painting with de-interlacing needs an interlaced 256^3 mesh with the register FFT passes");
+    return CNPC_EUNSUPPORTED;
+  }
+  unsigned char* w = reinterpret_cast<unsigned char*>(ws);
+  // without caller arrays the sums go to the painting workspace's sums slots
+  const size_t off_sums = paint_layout(d, ngal, nran, gw || rw).off_sums;
+  double* gs = gal_sums ? gal_sums : reinterpret_cast<double*>(w + off_sums);
+  double* rs = ran_sums ? ran_sums : reinterpret_cast<double*>(w + off_sums) + CNPC_SUMS_LEN;
+  return launch_paint_deinterlace(d, band, gpos, gw, ngal, rpos, rw, nran, sums_lmax, gs, rs, norms, spec_band,
+                                  delta_int, noise_spec_band, ws, ws_bytes, as_stream(stream));
 }
 
 cnpc_status cnpc_ylm_fields(const cnpc_mesh_desc* d, int32_t ell, const void* delta, void* out,

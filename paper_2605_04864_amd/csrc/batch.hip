@@ -82,6 +82,8 @@ static void batch_layout(cnpc_batch* B) {
   B->o_nmodes = take(sizeof(int64_t) * nb);
   B->o_keff = take(sizeof(double) * nb);
   size_t call = paint_layout(d, B->max_ngal, B->max_nran, true).total;
+  if (has_fold_zr2c(d) && B->nhi)
+    call = std::max(call, paint_deinterlace_ws_bytes(d, B->max_ngal, B->max_nran, true, B->band));
   call = std::max(call, deinterlace_ws_max(d));
   if (B->nhi) call = std::max(call, ylm_r2c_ws_bytes(d, B->nf, B->band));
   call = std::max(call, bin_ws_doubles(nb, B->nells + 1, 1) * sizeof(double));
@@ -118,11 +120,18 @@ static cnpc_status batch_catalog(const cnpc_batch* B, const BatchArgs& a, int i,
   const size_t bsz = (size_t)4 * band * band * band * 2 * esize(d->dtype);
   const float* gw = a.gw ? a.gw[i] : nullptr;
   const float* rw = a.rw ? a.rw[i] : nullptr;
-  CNPC_TRY(launch_paint_fkp(d, a.gpos[i], gw, a.ngal[i], a.rpos[i], rw, a.nran[i], B->sums_lmax,
-                            reinterpret_cast<double*>(w + B->o_gs), reinterpret_cast<double*>(w + B->o_rs), norms,
-                            delta, noise, call, B->call_bytes, s));
-  CNPC_TRY(launch_deinterlace(d, band, delta, D, dint, call, B->call_bytes, s));
-  CNPC_TRY(launch_deinterlace(d, band, noise, DN, nullptr, call, B->call_bytes, s));
+  double* gs = reinterpret_cast<double*>(w + B->o_gs);
+  double* rs = reinterpret_cast<double*>(w + B->o_rs);
+  if (dint && has_fold_zr2c(d) && tune_value(CNPC_TUNE_FOLD_FUSED) != 1) {
+    // fold fused with the z passes of both de-interlacing transforms
+    CNPC_TRY(launch_paint_deinterlace(d, band, a.gpos[i], gw, a.ngal[i], a.rpos[i], rw, a.nran[i], B->sums_lmax, gs,
+                                      rs, norms, D, dint, DN, call, B->call_bytes, s));
+  } else {
+    CNPC_TRY(launch_paint_fkp(d, a.gpos[i], gw, a.ngal[i], a.rpos[i], rw, a.nran[i], B->sums_lmax, gs, rs, norms,
+                              delta, noise, call, B->call_bytes, s));
+    CNPC_TRY(launch_deinterlace(d, band, delta, D, dint, call, B->call_bytes, s));
+    CNPC_TRY(launch_deinterlace(d, band, noise, DN, nullptr, call, B->call_bytes, s));
+  }
   void* F[BATCH_MAX_ELLS] = {nullptr, nullptr, nullptr};
   for (int q = 0; q < nl; ++q) F[q] = w + B->o_F[q];
   void* FN0 = w + B->o_FN0;

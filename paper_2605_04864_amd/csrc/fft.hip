@@ -488,7 +488,7 @@ __global__ void __launch_bounds__(256) k_colpass_rr(const cx<T>* in, cx<T>* out,
 // (iy, kz) of both phase spectra (after their z and y passes, layout
 // [phase][x][y][kz < N/2]) the forward x transforms of A and B, the combination
 // D = 1/2 [A + e^{-i pi (nx + ny + kz) / N} B] (D = 0 on a Nyquist row or
-// column), the band copy of D (|nx|, |ny| < mb, kz < mb), and the inverse x
+// column), the band copy of D (-mb <= nx, ny < mb, kz < mb), and the inverse x
 // transform of scale * D, written to out (layout [x][y][kz]).
 template <typename T, int R>
 __global__ void __launch_bounds__(256) k_xpass_interlace_rr(const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
@@ -527,7 +527,7 @@ __global__ void __launch_bounds__(256) k_xpass_interlace_rr(const cx<T>* __restr
       else sincospi(-(double)(nx + ny + kz) / (double)N, &sn, &cs);
       d = cscale(cadd(va[k2], cmul(cx<T>{cs, sn}, vb[k2])), T(0.5));
     }
-    if (band_out && nx > -mb && nx < mb && ny > -mb && ny < mb && kz < mb) {
+    if (band_out && nx >= -mb && nx < mb && ny >= -mb && ny < mb && kz < mb) {
       const int bx = nx < 0 ? nx + 2 * mb : nx, by = ny < 0 ? ny + 2 * mb : ny;
       band_out[((int64_t)bx * 2 * mb + by) * mb + kz] = d;
     }

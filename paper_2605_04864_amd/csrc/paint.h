@@ -47,6 +47,16 @@ cnpc_status launch_paint_fkp(const cnpc_mesh_desc* d, const uint32_t* gpos, cons
                              int64_t ngal, const uint32_t* rpos, const float* rw, int64_t nran,
                              int sums_lmax, double* gsums, double* rsums, double* norms, void* delta,
                              void* noise, void* ws, size_t ws_bytes, hipStream_t s);
+// Painting into tile blocks (sums, sort, tile painting; no fold), then the
+// fold fused with the r2c z pass of both de-interlacing transforms: dsp gets
+// the delta z rows [phase][x][y][n/2] (complex), nw1 the N z rows
+// [phase][x][y][m].  Interlaced meshes of side 256 with the register FFT
+// passes (has_fold_zr2c); the blocks live in ws up to paint_layout().total.
+bool has_fold_zr2c(const cnpc_mesh_desc* d);
+cnpc_status launch_paint_blocks_zr2c(const cnpc_mesh_desc* d, const uint32_t* gpos, const float* gw, int64_t ngal,
+                                     const uint32_t* rpos, const float* rw, int64_t nran, int sums_lmax,
+                                     double* gsums, double* rsums, double* norms, void* dsp, void* nw1, int m,
+                                     void* ws, size_t ws_bytes, hipStream_t s);
 // per-workgroup LDS limit of the current device (bytes)
 size_t lds_limit();
 

@@ -6,6 +6,7 @@
 // LDS atomics, blocks are written out without atomics, and a fold pass sums
 // the <= 8 blocks covering every node while forming delta = n_g - alpha n_r and
 // N = n_g(w^2) + alpha^2 n_r(w^2).
+#include "fft.h"
 #include "paint.h"
 
 namespace cnpc {
@@ -963,6 +964,137 @@ __global__ void __launch_bounds__(512) k_fold_tiles(FoldArgs<T> fa, const double
   if (noise) store16<T>(noise + idx, q);
 }
 
+// Fold fused with the z pass of the de-interlacing transforms (N = 256: 16
+// z-tiles, one z-row = one row_fft_rr of 16 lanes).  A workgroup takes the 16
+// node rows (x, y = 16 ty + cy) of one x node x = 16 tx + cx of the tile
+// column (ph, tx, ty).  Load phase, lane (cy, tz): the block rows that hold
+// the 16 nodes of z-tile tz of row cy (own tile, the x / y neighbours' halo
+// rows; rows of consecutive cy are contiguous in a block, so 16 lanes read
+// 16 x 19 consecutive elements) are summed over the sources, and over both
+// weight sets into delta = sum cd v and N = sum cn v, then staged in LDS; the
+// row's z halo (positions 16, 17: nodes 0, 1 of z-tile tz + 1; position 18:
+// node 15 of z-tile tz - 1) is added after a barrier, one writer per node.
+// Transform phase: group g transforms row g (delta + i N) and the two-for-one
+// split gives the r2c z transforms of delta (kz < kz_d) and N (kz < kz_n).
+// Sources that a lane does not need are read from its own row and weighted by
+// zero, so no load sits in a divergent branch.  The meshes are never written.
+constexpr int FZ_RS = 273;  // staged row stride (complex): 256 nodes + 1 pad per 16
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_fold_zr2c(FoldArgs<T> fa, const double* __restrict__ norms,
+                                                   cx<T>* __restrict__ dsp, int kz_d, cx<T>* __restrict__ nw1,
+                                                   int kz_n) {
+  constexpr int R = 16, N = 256;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* stage = tw + N;  // [16][FZ_RS]; later the row_fft_rr buffers
+  load_twiddles<T, N, -1>(tw);
+  // workgroups go to the 8 XCDs in turn: each XCD takes a contiguous range of
+  // tile columns, so the blocks and halo rows they share meet in one L2
+  int b = blockIdx.x;
+  if ((gridDim.x & 7u) == 0) b = (int)((blockIdx.x & 7u) * (gridDim.x >> 3) + (blockIdx.x >> 3));
+  const int nt = fa.nt;
+  const int cx_ = b & 15;
+  b >>= 4;
+  const int ty = b % nt;
+  b /= nt;
+  const int tx = b % nt;
+  const int ph = b / nt;
+  const int tz = threadIdx.x >> 4, cy = threadIdx.x & 15;
+  const double alpha = norms[CNPC_NORM_ALPHA];
+  T cd[4] = {T(0), T(0), T(0), T(0)}, cn[4] = {T(0), T(0), T(0), T(0)};
+  if (fa.nsets == 2) {
+    cd[0] = T(1); cd[1] = T(-alpha); cn[0] = T(1); cn[1] = T(alpha * alpha);
+  } else {
+    cd[0] = T(1); cd[1] = T(-alpha); cn[2] = T(1); cn[3] = T(alpha * alpha);
+  }
+  // hx is uniform over the workgroup; a lane without a y halo reads its own
+  // row for the y-neighbour sources and weighs them by fy = 0
+  const bool hx = cx_ <= 1 || cx_ == 15, hy = cy <= 1 || cy == 15;
+  const int txn = cx_ <= 1 ? (tx - 1 + nt) % nt : (tx + 1) % nt;
+  const int tyn = cy <= 1 ? (ty - 1 + nt) % nt : (ty + 1) % nt;
+  const int lxn = cx_ <= 1 ? cx_ + 17 : 0, lyn = cy <= 1 ? cy + 17 : 0;
+  const int64_t bst = (int64_t)fa.nphase * BSTRIDE;
+  int64_t o[4];  // source k = 2 a + c (a: x neighbour, c: y neighbour)
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int a = k >> 1;
+    const bool c = (k & 1) && hy;
+    const int txs = a ? txn : tx, tys = c ? tyn : ty;
+    const int r = ((a ? lxn : cx_ + 1) * BW + (c ? lyn : cy + 1)) * BW;
+    o[k] = (((int64_t)txs * nt + tys) * nt + tz) * bst + (int64_t)ph * BSTRIDE + r;
+  }
+  const T fy = hy ? T(1) : T(0);
+  T d[19], q[19];
+#pragma unroll
+  for (int e = 0; e < 19; ++e) d[e] = q[e] = T(0);
+#pragma unroll
+  for (int sidx = 0; sidx < 4; ++sidx) {
+    if (sidx >= fa.nsets) break;
+    const T* __restrict__ bl = fa.blocks[sidx];
+    T v[19], u[19];
+    load16<T>(bl + o[0], v);
+    v[16] = bl[o[0] + 16]; v[17] = bl[o[0] + 17]; v[18] = bl[o[0] + 18];
+    load16<T>(bl + o[1], u);
+    u[16] = bl[o[1] + 16]; u[17] = bl[o[1] + 17]; u[18] = bl[o[1] + 18];
+#pragma unroll
+    for (int e = 0; e < 19; ++e) v[e] += fy * u[e];
+    if (hx) {
+      load16<T>(bl + o[2], u);
+      u[16] = bl[o[2] + 16]; u[17] = bl[o[2] + 17]; u[18] = bl[o[2] + 18];
+#pragma unroll
+      for (int e = 0; e < 19; ++e) v[e] += u[e];
+      load16<T>(bl + o[3], u);
+      u[16] = bl[o[3] + 16]; u[17] = bl[o[3] + 17]; u[18] = bl[o[3] + 18];
+#pragma unroll
+      for (int e = 0; e < 19; ++e) v[e] += fy * u[e];
+    }
+#pragma unroll
+    for (int e = 0; e < 19; ++e) {
+      d[e] += cd[sidx] * v[e];
+      q[e] += cn[sidx] * v[e];
+    }
+  }
+  // staged node (row, z) at row * FZ_RS + z + z / 16
+  cx<T>* srow = stage + cy * FZ_RS;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) srow[17 * tz + e] = cx<T>{d[e], q[e]};
+  __syncthreads();
+  {
+    cx<T>* up = srow + 17 * ((tz + 1) & 15);
+    cx<T>* lo = srow + 17 * ((tz + 15) & 15) + 15;
+    up[0] = cadd(up[0], cx<T>{d[16], q[16]});
+    up[1] = cadd(up[1], cx<T>{d[17], q[17]});
+    *lo = cadd(*lo, cx<T>{d[18], q[18]});
+  }
+  __syncthreads();
+  const int grp = threadIdx.x >> 4, rank = threadIdx.x & 15;
+  cx<T> v[R];
+#pragma unroll
+  for (int n2 = 0; n2 < R; ++n2) v[n2] = stage[grp * FZ_RS + 17 * n2 + rank];
+  __syncthreads();
+  row_fft_rr<T, R, -1>(v, rank, stage + grp * (R * (R + 1)), tw);
+  const int src = (R - rank) & (R - 1);
+  const int kzmax = kz_d > kz_n ? kz_d : kz_n;
+  const int K2 = (kzmax + R - 1) / R;
+  const int64_t row = ((int64_t)ph * N + 16 * tx + cx_) * N + 16 * ty + grp;
+  cx<T>* od = dsp + row * kz_d;
+  cx<T>* on = nw1 + row * kz_n;
+#pragma unroll
+  for (int k2 = 0; k2 < R / 2; ++k2) {
+    if (k2 < K2) {
+      const cx<T> a = v[R - 1 - k2];
+      const cx<T> sh = {__shfl(a.x, src, R), __shfl(a.y, src, R)};
+      const cx<T> zm = cconj(rank ? sh : v[(R - k2) & (R - 1)]);
+      const cx<T> zk = v[k2];
+      const int k = rank + R * k2;
+      const cx<T> dd = csub(zk, zm);
+      if (k < kz_d) od[k] = cscale(cadd(zk, zm), T(0.5));
+      if (k < kz_n) on[k] = cx<T>{T(0.5) * dd.y, T(-0.5) * dd.x};
+    }
+  }
+}
+
 // ------------------------------------------------------------------- host --
 static TileGeom tile_geom(const cnpc_mesh_desc* d);
 
@@ -1310,7 +1442,7 @@ static cnpc_status paint_t(const cnpc_mesh_desc* d, const uint32_t* gpos, const 
                            int64_t ngal, const uint32_t* rpos, const float* rw, int64_t nran,
                            const double* norms, T* delta, T* noise, unsigned char* ws,
                            const PaintLayout& L, bool counted, hipStream_t s, int sums_lmax = -1,
-                           double* gs = nullptr, double* rs = nullptr) {
+                           double* gs = nullptr, double* rs = nullptr, bool fold = true) {
   const bool weighted = (gw != nullptr) || (rw != nullptr);
   const uint32_t* cpos[2] = {gpos, rpos};
   const float* cw[2] = {gw, rw};
@@ -1334,6 +1466,7 @@ static cnpc_status paint_t(const cnpc_mesh_desc* d, const uint32_t* gpos, const 
       CNPC_TRY((sort_and_paint<T, 3>(d, cpos[c], nullptr, cn[c], c, weighted, counted, ws, L, s)));
   }
   if (sums_lmax >= 0) CNPC_TRY(launch_norms(d, gs, rs, ngal, const_cast<double*>(norms), s));
+  if (!fold) return CNPC_OK;
   const int z2 = L.nt >= 2 ? 2 : 1;
   const int64_t nb = (int64_t)L.nphase * L.nt * L.nt * (L.nt / z2);
   kt_begin(CNPC_KT_FOLD, s);
@@ -1359,6 +1492,74 @@ cnpc_status launch_paint(const cnpc_mesh_desc* d, const uint32_t* gpos, const fl
                            L, false, s);
   return paint_t<float>(d, gpos, gw, ngal, rpos, rw, nran, norms, (float*)delta, (float*)noise, w, L,
                         false, s);
+}
+
+bool has_fold_zr2c(const cnpc_mesh_desc* d) {
+  return d->interlace && d->n == 256 && fft_register_passes();
+}
+
+template <typename T>
+static cnpc_status fold_zr2c_t(const cnpc_mesh_desc* d, const PaintLayout& L, unsigned char* ws,
+                               const double* norms, cx<T>* dsp, cx<T>* nw1, int m, hipStream_t s) {
+  FoldArgs<T> fa;
+  fa.n = d->n;
+  fa.nt = L.nt;
+  fa.nphase = L.nphase;
+  fa.nsets = L.nsets;
+  for (int k = 0; k < L.nsets; ++k) fa.blocks[k] = reinterpret_cast<T*>(ws + L.off_blocks[k]);
+  // one workgroup per (phase, tile column, x node of the tile)
+  const int64_t grid = (int64_t)L.nphase * L.nt * L.nt * TILE;
+  const size_t lds = sizeof(cx<T>) * (256 + (size_t)16 * FZ_RS);
+  CNPC_TRY(ensure_twiddles());
+  kt_begin(CNPC_KT_FOLD, s);
+  hipLaunchKernelGGL((k_fold_zr2c<T>), dim3((unsigned)grid), dim3(256), lds, s, fa, norms, dsp, d->n / 2, nw1, m);
+  kt_end(CNPC_KT_FOLD, s);
+  CNPC_HIP(hipGetLastError());
+  return CNPC_OK;
+}
+
+cnpc_status launch_paint_blocks_zr2c(const cnpc_mesh_desc* d, const uint32_t* gpos, const float* gw, int64_t ngal,
+                                     const uint32_t* rpos, const float* rw, int64_t nran, int sums_lmax,
+                                     double* gsums, double* rsums, double* norms, void* dsp, void* nw1, int m,
+                                     void* ws, size_t ws_bytes, hipStream_t s) {
+  const bool weighted = (gw != nullptr) || (rw != nullptr);
+  PaintLayout L = paint_layout(d, ngal, nran, weighted);
+  if (ws_bytes < L.total) {
+    set_error("paint workspace too small: need %zu bytes, got %zu", L.total, ws_bytes);
+    return CNPC_EWORKSPACE;
+  }
+  if (!has_fold_zr2c(d)) {
+    set_error("fused fold and z pass: unsupported mesh");
+    return CNPC_EUNSUPPORTED;
+  }
+  unsigned char* w = reinterpret_cast<unsigned char*>(ws);
+  const bool fused = L.nbuckets > 1 && tune_value(CNPC_TUNE_SORT_FUSED) != 1;
+  if (!fused) {
+    // sums and tile counts in a pass of their own, norms before the painting
+    uint32_t* count0 = reinterpret_cast<uint32_t*>(w + L.off_count[0]);
+    uint32_t* count1 = reinterpret_cast<uint32_t*>(w + L.off_count[1]);
+    double* partial = reinterpret_cast<double*>(w + L.off_partial);
+    hipLaunchKernelGGL(k_zero_u32, dim3(64), dim3(256), 0, s, count0, (int64_t)L.ntiles);
+    hipLaunchKernelGGL(k_zero_u32, dim3(64), dim3(256), 0, s, count1, (int64_t)L.ntiles);
+    CNPC_HIP(hipGetLastError());
+    CountArgs ca;
+    ca.g = tile_geom(d);
+    ca.ntiles = L.ntiles;
+    ca.count = count0;
+    CNPC_TRY(sums_counted(d, gpos, gw, ngal, sums_lmax, gsums, partial, ca, s));
+    ca.count = count1;
+    CNPC_TRY(sums_counted(d, rpos, rw, nran, sums_lmax, rsums, partial, ca, s));
+    CNPC_TRY(launch_norms(d, gsums, rsums, ngal, norms, s));
+  }
+  const int lm = fused ? sums_lmax : -1;
+  if (d->dtype == CNPC_F64) {
+    CNPC_TRY(paint_t<double>(d, gpos, gw, ngal, rpos, rw, nran, norms, nullptr, nullptr, w, L, !fused, s, lm,
+                             gsums, rsums, false));
+    return fold_zr2c_t<double>(d, L, w, norms, (cx<double>*)dsp, (cx<double>*)nw1, m, s);
+  }
+  CNPC_TRY(paint_t<float>(d, gpos, gw, ngal, rpos, rw, nran, norms, nullptr, nullptr, w, L, !fused, s, lm, gsums,
+                          rsums, false));
+  return fold_zr2c_t<float>(d, L, w, norms, (cx<float>*)dsp, (cx<float>*)nw1, m, s);
 }
 
 cnpc_status launch_paint_fkp(const cnpc_mesh_desc* d, const uint32_t* gpos, const float* gw,

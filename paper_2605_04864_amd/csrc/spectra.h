@@ -32,6 +32,15 @@ cnpc_status launch_ylm_fields(const cnpc_mesh_desc* d, int ell, const void* delt
                               hipStream_t s);
 size_t deinterlace_ws_bytes(const cnpc_mesh_desc* d);
 size_t deinterlace_ws_max(const cnpc_mesh_desc* d);
+// Painting (sums, sort, tile painting) with the fold fused into the z passes
+// of the de-interlacing transforms (has_fold_zr2c meshes): the same outputs as
+// launch_paint_fkp followed by launch_deinterlace of delta (full, with
+// delta_int) and of N (band), without the delta and N meshes.
+size_t paint_deinterlace_ws_bytes(const cnpc_mesh_desc* d, int64_t ngal, int64_t nran, bool weighted, int band);
+cnpc_status launch_paint_deinterlace(const cnpc_mesh_desc* d, int band, const uint32_t* gpos, const float* gw,
+                                     int64_t ngal, const uint32_t* rpos, const float* rw, int64_t nran,
+                                     int sums_lmax, double* gsums, double* rsums, double* norms, void* spec,
+                                     void* delta_int, void* specN, void* ws, size_t ws_bytes, hipStream_t s);
 size_t deinterlace_band_ws_bytes(const cnpc_mesh_desc* d, int band);
 cnpc_status launch_deinterlace(const cnpc_mesh_desc* d, int band, const void* meshes, void* spec,
                                void* delta_int, void* ws, size_t ws_bytes, hipStream_t s);

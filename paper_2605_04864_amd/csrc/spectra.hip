@@ -466,7 +466,7 @@ __global__ void __launch_bounds__(256) k_interlace_combine(cx<T>* sa, const cx<T
       v = cscale(cadd(v, cmul(ph, b)), T(0.5));
     }
     sa[i] = cscale(v, scale_inplace);
-    if (band_out && nx > -mb && nx < mb && ny > -mb && ny < mb && kz < mb) {
+    if (band_out && nx >= -mb && nx < mb && ny >= -mb && ny < mb && kz < mb) {
       const int bx = nx < 0 ? nx + 2 * mb : nx, by = ny < 0 ? ny + 2 * mb : ny;
       band_out[((int64_t)bx * 2 * mb + by) * mb + kz] = v;
     }
@@ -535,6 +535,79 @@ static cnpc_status deinterlace_t(const cnpc_mesh_desc* d, int band, const T* mes
                      band, 1, T(1.0 / (double)n3));
   CNPC_HIP(hipGetLastError());
   return fft3d_c2r<T>(n, 1, 0, sp, delta_int, nullptr, s);
+}
+
+// ------------------------------------------- painting + de-interlacing --
+// The de-interlacing transforms continued from their z passes (done by the
+// fused fold): delta along the full path (y pass, fused x pass with the
+// interlace combination and band copy, inverse y and z passes into
+// delta_int), N along the band path (y and x band passes, combination).
+template <typename T>
+static cnpc_status deinterlace_from_z(const cnpc_mesh_desc* d, int band, cx<T>* sp, cx<T>* nw1, cx<T>* nw2,
+                                      cx<T>* nsp, cx<T>* spec, T* delta_int, cx<T>* specN, hipStream_t s) {
+  const int n = d->n, h = n / 2, m = band;
+  const int dt = sizeof(T) == 8 ? CNPC_F64 : CNPC_F32;
+  const int64_t nn = (int64_t)n * n, n3 = nn * n;
+  ColArgs ay = make_col(n, dt, (int64_t)n * h, (int64_t)n * h, h, h, h, 0, 0);
+  CNPC_TRY(colpass<T>(n, -1, sp, sp, ay, 2 * (int64_t)n, s));
+  cx<T>* o = reinterpret_cast<cx<T>*>(delta_int);
+  CNPC_TRY(xpass_interlace<T>(n, sp, o, spec, band, T(1.0 / (double)n3), s));
+  CNPC_TRY(colpass<T>(n, 1, o, o, ay, (int64_t)n, s));
+  CNPC_TRY(zpass_c2r<T>(n, o, delta_int, nn, h, s));
+  ColArgs by = make_col(n, dt, (int64_t)n * m, (int64_t)2 * m * m, m, m, m, 0, m);
+  CNPC_TRY(colpass<T>(n, -1, nw1, nw2, by, 2 * (int64_t)n, s));
+  ColArgs bx = make_col(n, dt, (int64_t)n * 2 * m * m, (int64_t)4 * m * m * m, (int64_t)2 * m * m,
+                        (int64_t)2 * m * m, 2 * m * m, 0, m);
+  CNPC_TRY(colpass<T>(n, -1, nw2, nsp, bx, 2, s));
+  const int64_t bsz = (int64_t)4 * m * m * m;
+  const unsigned g = (unsigned)std::min<int64_t>((bsz + 255) / 256, 65536);
+  hipLaunchKernelGGL((k_interlace_combine<T>), dim3(g), dim3(256), 0, s, nsp, nsp + bsz, n, band, specN, band, 1,
+                     T(1));
+  CNPC_HIP(hipGetLastError());
+  return CNPC_OK;
+}
+
+// bytes of the scratch that follows the paint workspace
+static size_t paint_deinterlace_extra(const cnpc_mesh_desc* d, int band) {
+  const size_t n = d->n, m = band, es = esize(d->dtype);
+  const size_t sp = 2 * n * n * (n / 2), w1 = 2 * n * n * m, w2 = 2 * n * 2 * m * m, nsp = 2 * 4 * m * m * m;
+  return (sp + w1 + w2 + nsp) * 2 * es + 4 * 256;
+}
+
+size_t paint_deinterlace_ws_bytes(const cnpc_mesh_desc* d, int64_t ngal, int64_t nran, bool weighted, int band) {
+  const size_t p = (paint_layout(d, ngal, nran, weighted).total + 255) & ~(size_t)255;
+  return p + paint_deinterlace_extra(d, band);
+}
+
+cnpc_status launch_paint_deinterlace(const cnpc_mesh_desc* d, int band, const uint32_t* gpos, const float* gw,
+                                     int64_t ngal, const uint32_t* rpos, const float* rw, int64_t nran,
+                                     int sums_lmax, double* gsums, double* rsums, double* norms, void* spec,
+                                     void* delta_int, void* specN, void* ws, size_t ws_bytes, hipStream_t s) {
+  const bool weighted = (gw != nullptr) || (rw != nullptr);
+  if (!has_fold_zr2c(d) || delta_int == nullptr) {
+    set_error("painting with fused de-interlacing: unsupported mesh");
+    return CNPC_EUNSUPPORTED;
+  }
+  if (ws_bytes < paint_deinterlace_ws_bytes(d, ngal, nran, weighted, band)) {
+    set_error("paint_deinterlace workspace too small");
+    return CNPC_EWORKSPACE;
+  }
+  const size_t ptot = (paint_layout(d, ngal, nran, weighted).total + 255) & ~(size_t)255;
+  unsigned char* w = reinterpret_cast<unsigned char*>(ws);
+  const size_t n = d->n, m = band, es = esize(d->dtype);
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  unsigned char* sp = w + ptot;
+  unsigned char* nw1 = sp + al(2 * n * n * (n / 2) * 2 * es);
+  unsigned char* nw2 = nw1 + al(2 * n * n * m * 2 * es);
+  unsigned char* nsp = nw2 + al(2 * n * 2 * m * m * 2 * es);
+  CNPC_TRY(launch_paint_blocks_zr2c(d, gpos, gw, ngal, rpos, rw, nran, sums_lmax, gsums, rsums, norms, sp, nw1, band,
+                                    ws, ptot, s));
+  if (d->dtype == CNPC_F64)
+    return deinterlace_from_z<double>(d, band, (cx<double>*)sp, (cx<double>*)nw1, (cx<double>*)nw2,
+                                      (cx<double>*)nsp, (cx<double>*)spec, (double*)delta_int,
+                                      (cx<double>*)specN, s);
+  return deinterlace_from_z<float>(d, band, (cx<float>*)sp, (cx<float>*)nw1, (cx<float>*)nw2, (cx<float>*)nsp,
+                                   (cx<float>*)spec, (float*)delta_int, (cx<float>*)specN, s);
 }
 
 cnpc_status launch_deinterlace(const cnpc_mesh_desc* d, int band, const void* meshes, void* spec,

@@ -99,6 +99,38 @@ def paint_fkp(desc, gpos, rpos, gw=None, rw=None, noise=True, sums_lmax=4,
     return norms, delta, nmesh, gs, rs
 
 
+def fold_fused_supported(desc) -> bool:
+    """cnpc_paint_deinterlace covers this mesh: interlaced 256^3 with the
+    register FFT passes, the fused form not switched off by its tuning knob."""
+    return (bool(desc.interlace) and desc.n == 256
+            and L.lib.cnpc_tune_get(L.TUNE["fft_passes"][0]) != 1
+            and L.lib.cnpc_tune_get(L.TUNE["fold_fused"][0]) != 1)
+
+
+def paint_deinterlace(desc, band, gpos, rpos, gw=None, rw=None, sums_lmax=4,
+                      scratch: Optional[Scratch] = None, stream=None):
+    """Painting and both de-interlacing transforms in one library call
+    (cnpc_paint_deinterlace).  Returns (norms, D, delta_int, DN, galaxy sums,
+    random sums)."""
+    sc = scratch or Scratch()
+    n = desc.n
+    dt = _TORCH_DT[desc.dtype]
+    norms = _empty(L.NORMS_LEN, torch.float64)
+    gs = _empty(L.SUMS_LEN, torch.float64)
+    rs = _empty(L.SUMS_LEN, torch.float64)
+    D = _empty((band_size(band), 2), dt)
+    DN = _empty((band_size(band), 2), dt)
+    dint = _empty((n, n, n), dt)
+    weighted = int(gw is not None or rw is not None)
+    ws = sc.get(L.lib.cnpc_paint_deinterlace_workspace_size(C.byref(desc), gpos.shape[1], rpos.shape[1],
+                                                             weighted, band))
+    L.check(L.lib.cnpc_paint_deinterlace(C.byref(desc), band, L.ptr(gpos), L.ptr(gw), gpos.shape[1],
+                                         L.ptr(rpos), L.ptr(rw), rpos.shape[1], int(sums_lmax), L.ptr(gs),
+                                         L.ptr(rs), L.ptr(norms), L.ptr(D), L.ptr(dint), L.ptr(DN), L.ptr(ws),
+                                         ws.numel(), _sh(stream)))
+    return norms, D, dint, DN, gs, rs
+
+
 def band_size(band: int) -> int:
     return 4 * band ** 3
 
@@ -467,6 +499,11 @@ def measure_pk_bk(desc, gpos, rpos, bins, plan: "BispecPlan", ells=(0, 2, 4), gw
     the shot-noise spectra.  `out` (optional): dict of preallocated result
     tensors to write into ("pk": [9, nbins], "bk": [3, nconf])."""
     sc = scratch or Scratch()
+    if any(l > 0 for l in ells) and fold_fused_supported(desc):
+        norms, D, dint, DN, _, _ = paint_deinterlace(desc, plan.band, gpos, rpos, gw, rw,
+                                                     sums_lmax=_pk_bk_lmax(plan), scratch=sc, stream=stream)
+        return _spectra_stage(desc, bins, plan, (norms, None, None), ells, sc, stream, out,
+                              deinterlaced=(D, dint, DN))
     painted = paint_fkp(desc, gpos, rpos, gw, rw, noise=True, sums_lmax=_pk_bk_lmax(plan), scratch=sc,
                         stream=stream)
     return _spectra_stage(desc, bins, plan, painted, ells, sc, stream, out)
@@ -477,13 +514,17 @@ def _pk_bk_lmax(plan) -> int:
     return 0 if plan.ell == 0 else 4
 
 
-def _spectra_stage(desc, bins, plan, painted, ells, sc: Scratch, stream, out):
-    """Everything of measure_pk_bk after the painting."""
+def _spectra_stage(desc, bins, plan, painted, ells, sc: Scratch, stream, out, deinterlaced=None):
+    """Everything of measure_pk_bk after the painting (after the de-interlacing
+    too when `deinterlaced` = (D, delta_int, DN) is given)."""
     norms, delta, nmesh = painted[0], painted[1], painted[2]
     band = plan.band
     hi = [l for l in ells if l > 0]
-    D, dint = deinterlace(desc, band, delta, want_real=len(hi) > 0, scratch=sc, stream=stream)
-    DN, _ = deinterlace(desc, band, nmesh, want_real=False, scratch=sc, stream=stream)
+    if deinterlaced is not None:
+        D, dint, DN = deinterlaced
+    else:
+        D, dint = deinterlace(desc, band, delta, want_real=len(hi) > 0, scratch=sc, stream=stream)
+        DN, _ = deinterlace(desc, band, nmesh, want_real=False, scratch=sc, stream=stream)
     F = {0: assemble(desc, band, 0, spec0=D, stream=stream)}
     FN0 = assemble(desc, band, 0, spec0=DN, stream=stream)
     if hi:

@@ -208,3 +208,16 @@ def test_bin_pk_noalloc_rejects_binning_beyond_static_scratch():
                                    None, None, None)
     assert st != 0
     assert "static scratch" in L.last_error()
+
+
+def test_paint_deinterlace_rejects_other_meshes():
+    """The painting with fused de-interlacing covers interlaced 256^3 meshes; a
+    64^3 or non-interlaced mesh is refused on the host with CNPC_EUNSUPPORTED."""
+    from paper_2605_04864_amd import _lib as L
+    p = C.c_void_p(16)
+    for n, il in ((64, True), (256, False)):
+        d = L.mesh_desc(n, 1000.0, assign=L.TSC, interlace=il, dtype=L.F32)
+        st = L.lib.cnpc_paint_deinterlace(C.byref(d), 16, p, None, 10, p, None, 100, 4, None, None, p, p, p, p,
+                                          p, 1 << 30, None)
+        assert st == -4, (n, il, st)
+        assert "256^3" in L.last_error()

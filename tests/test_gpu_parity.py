@@ -464,3 +464,32 @@ def test_graph_replay_matches_eager(nstreams, staged):
             assert rel(host(o["pk"]), pk) < 1e-5
             assert rel(host(o["bk"]), bk) < 1e-5
         _ = torch.randn(1000, device="cuda").sum().item()  # eager work between replays
+
+
+@pytest.mark.parametrize("weights,dtype,band", [(False, L.F32, 32), (True, L.F32, 16), (True, L.F64, 32),
+                                                (False, L.F64, 64)])
+def test_paint_deinterlace_matches_two_steps(weights, dtype, band):
+    """cnpc_paint_deinterlace (tile sums taken inside the z passes of the
+    de-interlacing transforms) against cnpc_paint_fkp + cnpc_deinterlace of
+    delta (band spectrum and delta_int) and of N (band spectrum), every band
+    slot included."""
+    n = 256
+    if weights:
+        g, gw, r, rw = _tiny(15, 60000, 300000, True)
+    else:
+        g = synthcat.lognormal_catalog(300_000, 1000.0, 17)
+        r = synthcat.random_catalog(10 * g.shape[1], 18)
+        gw = rw = None
+    d = cn.mesh_desc(n, 1000.0, assign=L.TSC, interlace=True, dtype=dtype, observer=OBS)
+    gt, rt = dev(g), dev(r)
+    gwt = dev(gw) if gw is not None else None
+    rwt = dev(rw) if rw is not None else None
+    sc = pl.Scratch()
+    norms, delta, nmesh, gs, rs = pl.paint_fkp(d, gt, rt, gwt, rwt, noise=True, scratch=sc)
+    D, dint = pl.deinterlace(d, band, delta, want_real=True, scratch=sc)
+    DN, _ = pl.deinterlace(d, band, nmesh, want_real=False, scratch=sc)
+    norms2, D2, dint2, DN2, gs2, rs2 = pl.paint_deinterlace(d, band, gt, rt, gwt, rwt, scratch=sc)
+    assert np.allclose(host(norms2), host(norms), rtol=1e-14, atol=0)
+    tol = 1e-12 if dtype == L.F64 else 2e-6
+    for a, b in ((D2, D), (dint2, dint), (DN2, DN)):
+        assert rel(host(a), host(b)) < tol
