@@ -57,6 +57,11 @@ def parse():
                     help="only run a plain device copy of this many MiB (calibrates HBM counters)")
     ap.add_argument("--fp64-mocks", type=int, default=2, help="mocks timed on the plain FP64 path")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-workers", type=int, default=0,
+                    help="processes of the all-core oracle sample (0: min(cpu count, 16))")
+    ap.add_argument("--cpu-whole", action="store_true",
+                    help="only time the oracle on whole mocks (CPU only; takes about an hour)")
+    ap.add_argument("--cpu-sample-worker", default=None, help=argparse.SUPPRESS)
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--config", type=int, default=4, choices=[1, 2, 3, 4, 5],
                     help="4: the batched headline; 1, 2, 3, 5: one catalog of that configuration "
@@ -93,33 +98,26 @@ def pipeline_bytes(ng, nr, es=4, n=256):
     return 12 * (ng + nr) + 50 * R + 34 * Cb
 
 
-def class_model(ng, nr, n=256, es=4, band=32, grid=128, nb=20, nfields=14, nphase=2):
-    """Algorithmic HBM bytes (or MFMA flops) of one mock per kernel class of the
-    path: every array read or written once by the kernels of that class."""
-    ntiles, bvol = (n // 16) ** 3, 19 ** 3
-    npart = ng + nr
-    blocks = ntiles * nphase * bvol * es            # one catalog's tile blocks
-    mesh = n ** 3 * es                               # one real mesh
-    half = n * n * (n // 2) * 2 * es                 # one half-layout spectrum
-    zb = n * n * band * 2 * es                       # one z-pruned band plane stack
-    yb = n * 2 * band * band * 2 * es                # after the y pass
-    xb = 4 * band ** 3 * 2 * es                      # band spectrum
-    g3 = grid ** 3 * es
-    gz = grid * grid * band * 2 * es
-    gy = grid * 2 * band * band * 2 * es
-    npairs = nb * (nb + 1) // 2
-    return {
-        "sums": 12 * npart,
-        "sort": 2 * 24 * npart,
-        "paint": 12 * npart + 2 * blocks,
-        "fold": 2 * blocks + 2 * nphase * mesh,
-        "zr2c": nphase * (mesh + half) + nphase * (mesh + zb) + (mesh + nfields * zb),
-        "col": (nphase * 4 * half + nphase * (zb + 2 * yb + xb) + nfields * (zb + 2 * yb + xb)
-                + 4 * half + nb * (xb + 2 * gy + gz)),
-        "zc2r": (half + mesh) + nb * (gz + g3),
-        "bin": (nfields + 4) * xb,
-        "contract": 3 * 2.0 * npairs * nb * grid ** 3,   # MFMA flops (split bf16: 3 products)
-    }
+def stage_model(ng, nr, n=256, es=4, grid=128, rows=110, cols=20):
+    """Algorithmic HBM bytes of one mock per stage of the byte model (every
+    stage reads its inputs and writes its outputs once; R: real mesh, C:
+    half-complex spectrum) and the contraction's MFMA flops.  The stages sum to
+    pipeline_bytes: paint 12 (N_g + N_r) + 4R; the transforms 26R + 18C
+    (interlaced r2c x4 4R + 2C, de-alias c2r C + R, Y_lm r2c x14 R + 14C, 20
+    shell c2r C + 20R); binning 16C; contraction 20R.  MFMA flops: the 32 x 32
+    output tiles over the contraction's pair rows and columns, three split
+    products, 2 flops per multiply-add, over the grid^3 points."""
+    R = n ** 3 * es
+    Cb = n * n * (n // 2 + 1) * 2 * es
+    tiles = -(-rows // 32) * 32 * -(-cols // 32) * 32
+    return {"paint": 12 * (ng + nr) + 4 * R, "fft": 26 * R + 18 * Cb, "bin": 16 * Cb,
+            "contract": 20 * R, "contract_flops": 3 * 2.0 * tiles * grid ** 3}
+
+
+# kernel-timer classes behind each stage of the byte model; sums and sort are
+# intermediates of this design (the particle reads are counted once, in paint)
+STAGE_CLASSES = {"paint": ("paint",), "fft": ("fold", "zr2c", "col", "zc2r"), "bin": ("bin",),
+                 "contract": ("contract",), "intermediate": ("sums", "sort")}
 
 
 def copy_probe(mib: int):
@@ -137,6 +135,12 @@ def copy_probe(mib: int):
 
 def main():
     args = parse()
+    if args.cpu_sample_worker:
+        _sample_worker(args.cpu_sample_worker)
+        return
+    if args.cpu_whole:
+        cpu_whole(args)
+        return
     if args.copy_probe_mib > 0:
         copy_probe(args.copy_probe_mib)
         return
@@ -204,8 +208,9 @@ def main():
     eager = [(o["pk"].clone(), o["bk"].clone()) for o in outs]
 
     ntot = int(np.sum(sizes[: args.mocks]) * 11)
-    models = [class_model(int(sz), 10 * int(sz), band=plan.band, grid=plan.grid)
-              for sz in sizes[: args.mocks]]
+    # contraction rows: the shell pairs (j, k) of the kept configurations
+    rows = len({(int(c[1]), int(c[2])) for c in plan.configs()[0]})
+    models = [stage_model(int(sz), 10 * int(sz), grid=plan.grid, rows=rows) for sz in sizes[: args.mocks]]
     model = {k: float(np.sum([m[k] for m in models])) for k in models[0]}  # per step
 
     run = step
@@ -282,7 +287,8 @@ def main():
         fp64 = {"catalogs_per_s": 1.0 / per, "mocks_timed": [int(sizes[k]) for k in pick],
                 "speedup_fp32_batched": value * per}
         del sc64
-    cpu = None if args.no_cpu else cpu_baseline(mocks, sizes, log=lambda *m: log(args, *m))
+    cpu = None if args.no_cpu else cpu_baseline(mocks, sizes, log=lambda *m: log(args, *m),
+                                                workers=args.cpu_workers or None)
 
     # kernel times: the batch once more, eagerly on a single stream (kernels
     # unshared, so each launch's time is that kernel's own), every launch of the
@@ -300,13 +306,13 @@ def main():
     e1.record()
     kern = ktimer_read(L)
     ms_instr = e0.elapsed_time(e1)
-    dom = max(kern, key=lambda k: kern[k]["ms"])
-    classes = {name: class_roofline(name, kv, model) for name, kv in kern.items()
-               if kv["launches"] > 0 and kv["ms"] > 0}
-    roof = dict(classes[dom])
-    roof["kernel"] = KERNEL_OF_CLASS.get(dom, dom)
-    roof["launches"] = kern[dom]["launches"]
+    stages = stage_roofline(model, kern)
+    roof = paint_roofline(model, kern["paint"])
+    roof["kernel"] = KERNEL_OF_CLASS["paint"]
+    roof["launches"] = kern["paint"]["launches"]
     roof["traffic"] = measured_traffic(roof["kernel"])
+    if roof["traffic"] is not None:
+        roof["traffic_over_algorithmic"] = roof["traffic"] / roof["per_launch"]
     roof["durations_from"] = (f"HIP events around each launch of a single-stream eager pass of the "
                               f"batch run last ({ms_instr:.1f} ms for the batch)")
     kern_ms = {k: round(v["ms"], 3) for k, v in kern.items()}
@@ -341,8 +347,8 @@ def main():
         "pipeline_hbm_frac": (hbm_bytes / (ms_step / 1e3)) / (HBM_PEAK_GBS * 1e9),
         "kernels_ms_per_step": kern_ms,
         "roofline": roof,
-        "roofline_by_class": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv)
-                                  for kk, vv in v.items()} for k, v in classes.items()},
+        "roofline_by_stage": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv)
+                                  for kk, vv in v.items()} for k, v in stages.items()},
         "fp64_plain": fp64,
         "cpu_baseline": cpu,
     }
@@ -480,22 +486,50 @@ def ktimer_read(L):
     return {k: {"ms": ms_cls[v], "launches": n_cls[v]} for k, v in L.KT.items()}
 
 
-def class_roofline(name, kv, model):
-    """Achieved rate of one kernel class: algorithmic bytes (or MFMA flops) per
-    launch from the per-step model over the average launch duration."""
-    per_launch = model[name] / kv["launches"]
+def stage_roofline(model, kern):
+    """Achieved rate of every stage over the summed time of its kernel classes
+    in one step: algorithmic bytes (contraction: MFMA flops) of the byte model
+    over that time."""
+    out = {}
+    for st, cls in STAGE_CLASSES.items():
+        ms = sum(kern[c]["ms"] for c in cls if c in kern)
+        launches = sum(kern[c]["launches"] for c in cls if c in kern)
+        if ms <= 0:
+            continue
+        if st == "intermediate":
+            out[st] = {"classes": list(cls), "ms": ms, "launches": launches, "algorithmic": 0.0}
+            continue
+        if st == "contract":
+            ach = model["contract_flops"] / (ms * 1e-3) / 1e12
+            out[st] = {"bound": "mfma", "achieved": ach, "peak": PEAKS_TFLOPS["bf16"], "unit": "TFLOP/s",
+                       "frac": ach / PEAKS_TFLOPS["bf16"], "ms": ms, "launches": launches}
+            continue
+        if st == "bin":
+            # the byte model reads 16 full half-complex spectra; the design bins
+            # band spectra (|n_i| < band), far fewer bytes: no rate is claimed
+            out[st] = {"ms": ms, "launches": launches, "model_bytes": model[st],
+                       "note": "band-pruned: reads less than the model's 16C"}
+            continue
+        ach = model[st] / (ms * 1e-3) / 1e9
+        out[st] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                   "frac": ach / HBM_PEAK_GBS, "ms": ms, "launches": launches, "classes": list(cls)}
+    return out
+
+
+def paint_roofline(model, kv):
+    """The dominant kernel, the particle painter: one launch paints one catalog
+    (both interlacing phases), algorithmic bytes 12 per particle of the launch
+    plus its half of the mock's 4R mesh writes; per launch the step's paint
+    bytes over its launches, over the average launch duration."""
+    per_launch = model["paint"] / kv["launches"]
     avg_ms = kv["ms"] / kv["launches"]
-    if name == "contract":
-        ach = per_launch / (avg_ms * 1e-3) / 1e12
-        return {"bound": "mfma", "achieved": ach, "peak": PEAKS_TFLOPS["bf16"], "unit": "TFLOP/s",
-                "frac": ach / PEAKS_TFLOPS["bf16"], "avg_launch_ms": avg_ms, "per_launch": per_launch}
     ach = per_launch / (avg_ms * 1e-3) / 1e9
-    return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": ach / HBM_PEAK_GBS, "avg_launch_ms": avg_ms, "per_launch": per_launch}
+    return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+            "avg_launch_ms": avg_ms, "per_launch": per_launch}
 
 
-# kernel behind each timer class (the dominant one is named in the roofline)
-KERNEL_OF_CLASS = {"paint": "k_paint_tiles_u32", "sort": "k_partition", "fold": "k_fold_tiles",
+# kernel behind each timer class
+KERNEL_OF_CLASS = {"paint": "k_paint_tiles_u32", "sort": "k_bucket_pass", "fold": "k_fold_zr2c",
                    "zr2c": "k_zpass_ylm_rr", "col": "k_colpass_rr", "zc2r": "k_zpass_c2r",
                    "contract": "k_contract_mfma", "bin": "k_bin", "sums": "k_catalog_sums"}
 
@@ -524,76 +558,205 @@ def measured_traffic(kernel):
     return float(vals["bytes_per_launch"])
 
 
-def cpu_baseline(mocks, sizes, log=print):
-    """FP64 oracle on a bounded sample of the smallest mock, extrapolated to the mean mock.
+CPU_SLICE = 64  # the bounded sample paints and sums 1/64 of each picked mock
 
-    Each oracle step is timed on a slice and scaled by the number of times the
-    whole computation repeats it; the sum estimates seconds per catalog."""
+
+def cpu_picks(sizes):
+    """The mocks the oracle is timed on: smallest, the two medians, largest."""
+    order = np.argsort(sizes)
+    m = len(order)
+    return [int(order[0]), int(order[(m - 1) // 2]), int(order[m // 2]), int(order[-1])]
+
+
+def oracle_sample(slices, n=256, box=1000.0):
+    """One bounded, single-threaded sample of the FP64 oracle on the headline
+    workload (P_0,2,4 by measure_pk and B_0 by measure_bk, as the oracle runs
+    them: each sums and paints the catalogs itself; 12 single-catalog paintings
+    of 6 (N_g + N_r) particles per mock in all).
+
+    Per picked mock: the catalog sums of both calls and one painting of its
+    random catalog, on a slice.  Once: the 9 de-interlacing FFTs, 14 Y_lm-
+    weighted FFTs, 40 shell / indicator inverse FFTs, 2 x 825 triple sums and
+    the binnings, one instance each, scaled by its repeat count."""
     import synthcat
     from oracle import bispectrum as obk
     from oracle import mesh as oms
     from oracle import spectra as osp
     from oracle.catalog import catalog_norms
     from oracle.ylm import Ylm
-    k = int(np.argmin(sizes))
-    g, r = mocks[k]
-    ng, nr = g.shape[1], r.shape[1]
-    n, box = 256, 1000.0
     obs = synthcat.observer_position()
-    parts = {}
-    frac = 50
-    t = time.perf_counter()
-    catalog_norms(g[:, : ng // frac], None, r[:, : nr // frac], None, box, obs, (0, 2, 4))
-    parts["catalog_sums"] = (time.perf_counter() - t) * frac
-    t = time.perf_counter()
-    oms.paint(r[:, : nr // 20], None, n, oms.TSC, 0.0)
-    # 8 paintings (2 catalogs x 2 interlacing phases x {w, w^2}) of all particles
-    parts["paint"] = (time.perf_counter() - t) * 20 * 8 * (ng + nr) / nr
+    sums_s, paint_s, paint_n = [], [], []
+    for g, r in slices:
+        t = time.perf_counter()
+        catalog_norms(g, None, r, None, box, obs, (0, 2, 4))
+        catalog_norms(g, None, r, None, box, obs, (0,))
+        sums_s.append(time.perf_counter() - t)
+        t = time.perf_counter()
+        oms.paint(r, None, n, oms.TSC, 0.5)
+        paint_s.append(time.perf_counter() - t)
+        paint_n.append(int(r.shape[1]))
     mesh = np.random.default_rng(0).normal(size=(n, n, n))
+    parts = {}
     t = time.perf_counter()
     D = np.fft.fftn(mesh)
-    one_fft = time.perf_counter() - t
-    parts["deinterlace_ffts"] = one_fft * 6  # (A, B, inverse) for delta and N
+    parts["deinterlace_ffts"] = (time.perf_counter() - t) * 9
     rvec = osp.line_of_sight(n, box, obs)
     kvec = osp.kvectors(n, box)
     t = time.perf_counter()
     S = np.fft.fftn(mesh * Ylm(2, 1, rvec))
-    acc = np.conj(Ylm(2, 1, kvec)) * S
-    one_m = time.perf_counter() - t
-    parts["ylm_weighted_ffts"] = one_m * 14  # 5 (l=2) + 9 (l=4) m values
-    del S, acc, rvec, kvec
+    np.conj(Ylm(2, 1, kvec)) * S
+    parts["ylm_weighted_ffts"] = (time.perf_counter() - t) * 14
+    del S, rvec, kvec
     bins = osp.Bins(0.0, 0.01, 20, box, n)
     t = time.perf_counter()
-    shells = bins.shell_index()
-    X = obk.shell_field(D, shells, 10)
-    one_shell = time.perf_counter() - t
-    parts["shell_and_indicator_iffts"] = one_shell * 40
+    X = obk.shell_field(D, bins.shell_index(), 10)
+    parts["shell_and_indicator_iffts"] = (time.perf_counter() - t) * 40
     t = time.perf_counter()
     for _ in range(8):
         obk.triple_sum(X, X, X)
-    parts["triple_sums"] = (time.perf_counter() - t) / 8 * 825 * 2  # signal + triangle counts
+    parts["triple_sums"] = (time.perf_counter() - t) / 8 * 825 * 2
     t = time.perf_counter()
     bins.shell_mean(np.real(D * np.conj(D)))
-    parts["binning"] = (time.perf_counter() - t) * 6
-    # particle-proportional steps scaled from the sampled mock to the mean mock
-    scale = float(np.mean(sizes)) / float(sizes[k])
-    parts["catalog_sums"] *= scale
-    parts["paint"] *= scale
-    total = sum(parts.values())
-    threads = int(os.environ.get("OMP_NUM_THREADS", "1"))
-    log(f"cpu oracle estimate {total:.1f}s per catalog: " +
-        ", ".join(f"{k}={v:.1f}" for k, v in parts.items()))
-    return {"value": 1.0 / total, "unit": "catalogs/s", "cores": 1, "kind": "oracle",
-            "sample": f"smallest mock (N_g={ng}, N_r={nr}), 256^3: each oracle step timed on a "
-                      f"slice (1/50 of the catalog sums, 1/20 of one painting, one 256^3 FFT, one "
-                      f"Y_lm-weighted FFT, one shell inverse FFT, 8 triple sums) and scaled by its "
-                      f"repeat count; sums and painting then scaled to the mean mock "
-                      f"(N_g={float(np.mean(sizes)):.3g}); numpy FFT single-threaded",
-            "seconds_per_catalog": total, "parts_s": {k: round(v, 2) for k, v in parts.items()},
-            "omp_threads_env": threads, "host_cpus": os.cpu_count(), "cpu_model": _cpu_model()}
+    parts["binning"] = (time.perf_counter() - t) * 8
+    return {"particles": [int(g.shape[1] + r.shape[1]) for g, r in slices], "sums_s": sums_s,
+            "paint_particles": paint_n, "paint_s": paint_s, "mesh_parts_s": parts}
+
+
+def fit_line(x, y):
+    """Least-squares a, b of y = a x + b."""
+    A = np.vstack([np.asarray(x, float), np.ones(len(x))]).T
+    a, b = np.linalg.lstsq(A, np.asarray(y, float), rcond=None)[0]
+    return float(a), float(b)
+
+
+def sample_estimate(res, sizes):
+    """Seconds per catalog of every mock from one oracle sample, as the line
+    a (N_g + N_r) + b: a = 6 a_paint + a_sums, b = 12 b_paint + b_sums + the
+    mesh stages (a_paint, b_paint: the painting's per-particle and per-call
+    cost; a_sums, b_sums: the two catalog sums'), N_r = 10 N_g."""
+    ap, bp = fit_line(res["paint_particles"], res["paint_s"])
+    asum, bsum = fit_line(res["particles"], res["sums_s"])
+    mesh_s = float(sum(res["mesh_parts_s"].values()))
+    a = 6 * ap + asum
+    b = 12 * bp + bsum + mesh_s
+    per = [a * 11 * float(sz) + b for sz in sizes]
+    return per, {"a_s_per_particle": a, "b_s": b, "paint_a_s": ap, "paint_b_s": bp, "sums_a_s": asum,
+                 "mesh_s": mesh_s}
+
+
+def _sample_worker(path):
+    """Child process of the all-core sample: one oracle sample on the slices in
+    `path` (an .npz the parent wrote), result as one JSON line."""
+    z = np.load(path)
+    slices = [(z[f"g{i}"], z[f"r{i}"]) for i in range(len([k for k in z.files if k.startswith("g")]))]
+    print(json.dumps(oracle_sample(slices)))
+
+
+def cpu_baseline(mocks, sizes, log=print, workers=None):
+    """The FP64 oracle on the host cores, on a bounded sample of the workload.
+
+    Mocks: smallest, two medians, largest.  The particle stages run on 1/64 of
+    each (the slope a of seconds = a (N_g + N_r) + b comes from these four
+    sizes), the mesh stages once; the line gives every mock's seconds and the
+    64-mock total.  Single-threaded (FFT and BLAS threads = 1), then the same
+    sample in `workers` concurrent processes (all cores of the GPU's share of
+    the host): the all-core throughput is workers / the mean per-process
+    seconds per catalog."""
+    import subprocess
+    import tempfile
+    picks = cpu_picks(sizes)
+    slices = [(np.ascontiguousarray(mocks[k][0][:, : mocks[k][0].shape[1] // CPU_SLICE]),
+               np.ascontiguousarray(mocks[k][1][:, : mocks[k][1].shape[1] // CPU_SLICE])) for k in picks]
+    t = time.perf_counter()
+    single = oracle_sample(slices)
+    t_single = time.perf_counter() - t
+    per, fit = sample_estimate(single, sizes)
+    total = float(np.sum(per))
+    log(f"cpu oracle, one thread: {total / len(sizes):.1f} s per mean catalog "
+        f"({t_single:.1f} s sample); fit a={fit['a_s_per_particle']:.3e} s/particle, b={fit['b_s']:.1f} s")
+    workers = workers or min(os.cpu_count() or 1, 16)
+    allcore = None
+    if workers > 1:
+        with tempfile.TemporaryDirectory(dir="/tmp") as td:
+            path = os.path.join(td, "slices.npz")
+            np.savez(path, **{f"g{i}": g for i, (g, _) in enumerate(slices)},
+                     **{f"r{i}": r for i, (_, r) in enumerate(slices)})
+            env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+            cmd = [sys.executable, os.path.abspath(__file__), "--cpu-sample-worker", path]
+            t = time.perf_counter()
+            procs = [subprocess.Popen(cmd, stdout=subprocess.PIPE, env=env, text=True) for _ in range(workers)]
+            outs = [p.communicate()[0] for p in procs]
+            t_all = time.perf_counter() - t
+            if all(p.returncode == 0 for p in procs):
+                ests = [float(np.sum(sample_estimate(json.loads(o.strip().splitlines()[-1]), sizes)[0]))
+                        for o in outs]
+                mean_total = float(np.mean(ests))
+                allcore = {"value": workers * len(sizes) / mean_total, "cores": workers,
+                           "seconds_per_mean_catalog_per_process": mean_total / len(sizes),
+                           "sample_wall_s": round(t_all, 1)}
+                log(f"cpu oracle, {workers} processes: {allcore['value']:.4f} catalogs/s")
+            else:
+                log("cpu oracle all-core sample failed: " + str([p.returncode for p in procs]))
+    one = {"value": len(sizes) / total, "cores": 1, "seconds_per_mean_catalog": total / len(sizes),
+           "sample_wall_s": round(t_single, 1)}
+    best = allcore or one
+    return {"value": best["value"], "unit": "catalogs/s", "cores": best["cores"], "kind": "oracle",
+            "sample": (f"oracle measure_pk (P_0,2,4) + measure_bk (B_0) as they stand, 256^3 TSC + interlacing; "
+                       f"mocks {[int(sizes[k]) for k in picks]} (N_g: smallest, two medians, largest of the "
+                       f"{len(sizes)}); catalog sums and one painting timed on 1/{CPU_SLICE} of each (their "
+                       f"per-particle and per-call costs fitted over the four sizes), FFT / shell / triple-sum / "
+                       f"binning stages timed once each and scaled by their repeat counts; seconds per mock "
+                       f"a (N_g + N_r) + b, summed over all {len(sizes)} mocks"),
+            "single_thread": one, "all_cores": allcore, "fit": fit,
+            "parts_s": {k: round(v, 2) for k, v in single["mesh_parts_s"].items()},
+            "host_cpus": os.cpu_count(), "cpu_model": _cpu_model()}
+
+
+def cpu_whole(args):
+    """The oracle on whole mocks (smallest, two medians, largest), one thread,
+    against the bounded sample's estimate for the same mocks on the same host."""
+    import synthcat
+    from oracle.pipeline import MeshConfig, measure_bk, measure_pk
+    from oracle import mesh as oms
+    sizes = synthcat.mock_sizes_c4(64)
+    picks = cpu_picks(sizes)
+    cfg = MeshConfig(1000.0, 256, oms.TSC, True, synthcat.observer_position())
+    whole = []
+    slices = []
+    for k in picks:
+        ng = int(sizes[k])
+        g = synthcat.lognormal_catalog(ng, 1000.0, 4000 + 2 * k)
+        r = synthcat.random_catalog(10 * ng, 4000 + 2 * k + 1)
+        slices.append((np.ascontiguousarray(g[:, : ng // CPU_SLICE]),
+                       np.ascontiguousarray(r[:, : r.shape[1] // CPU_SLICE])))
+        t = time.perf_counter()
+        measure_pk(g, None, r, None, cfg, 0.0, 0.01, 20, ells=(0, 2, 4))
+        measure_bk(g, None, r, None, cfg, 0.01, 20, ells=(0,), scoccimarro=(0,), triposh=())
+        whole.append(time.perf_counter() - t)
+        log(args, f"whole mock N_g={ng}: {whole[-1]:.1f} s")
+        del g, r
+    npart = [11 * int(sizes[k]) for k in picks]
+    a, b = fit_line(npart, whole)
+    est, fit = sample_estimate(oracle_sample(slices), sizes)
+    print(json.dumps({"kind": "oracle whole mocks, one thread", "mocks_ng": [int(sizes[k]) for k in picks],
+                      "seconds": [round(x, 1) for x in whole], "fit_a_s_per_particle": a, "fit_b_s": b,
+                      "total_64_mocks_s": float(a * 11 * np.sum(sizes) + 64 * b),
+                      "catalogs_per_s": 64 / float(a * 11 * np.sum(sizes) + 64 * b),
+                      "sample_estimate_same_mocks_s": [round(est[k], 1) for k in picks],
+                      "sample_total_64_mocks_s": float(np.sum(est)), "sample_fit": fit,
+                      "host_cpus": os.cpu_count(), "cpu_model": _cpu_model()}))
 
 
 def _cpu_model():
+    """The lscpu model name (else /proc/cpuinfo's)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.strip().startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
     try:
         with open("/proc/cpuinfo") as fh:
             for line in fh:

@@ -18,6 +18,7 @@ struct FinArgs {
   int est, ell, nb, next, ncols, nconf;
   double n3;
   const int* cfg;
+  const int* prow;       // per config: its row of the contraction output
   const int64_t* ntri;
   const double* aux;     // per config: L(mu_ij), L(mu_ik) (Scoccimarro) or g(t), g(1/t)
   const double* counts;  // N_mode per shell
@@ -34,9 +35,17 @@ struct BispecGeom {
 double g_ell_host(int l, double t);
 BispecGeom bispec_geometry(const cnpc_mesh_desc* d, const cnpc_kbins* b, int est, int ell);
 size_t bispec_ws_bytes(const cnpc_mesh_desc* d, const cnpc_kbins* b, int est, int ell);
+// out[r][c] = sum_x X_a(x) X_b(x) Y_c(x) over the npts grid points, fields
+// [nf][npts]: row r is the pair (a, b) = pairs[r] (a | b << 16, nlist rows)
+// or, without a list, the r-th pair a <= b of the nshell first fields in
+// (a, b) lexicographic order; column c is field cc.field[c].
 template <typename T>
 cnpc_status contract_valu(const T* fields, int64_t npts, int nf, int nshell, const ContractCols& cc,
-                          double* partial, double* out, hipStream_t s);
+                          double* partial, double* out, hipStream_t s, const uint32_t* pairs = nullptr,
+                          int nlist = 0);
+cnpc_status contract_mfma(const float* fields, int64_t npts, int nf, int nshell, const ContractCols& cc,
+                          double* partial, double* out, hipStream_t s, const uint32_t* pairs = nullptr,
+                          int nlist = 0);
 
 }  // namespace cnpc
 
@@ -49,6 +58,12 @@ struct cnpc_bispec_plan {
   std::vector<int64_t> thr, counts, counts_ext, ntri;
   std::vector<int> cfg;
   std::vector<double> aux, wq;
+  // contraction rows: the shell pairs the configurations use (a | b << 16), and
+  // the row of each configuration
+  std::vector<uint32_t> pairs;
+  std::vector<int> prow;
+  uint32_t* d_pairs = nullptr;
+  int* d_prow = nullptr;
   int* d_cfg = nullptr;
   int64_t* d_ntri = nullptr;
   double* d_aux = nullptr;

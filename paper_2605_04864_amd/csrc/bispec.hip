@@ -103,13 +103,17 @@ static inline int pair_index(int a, int b, int nb) {  // a <= b
 template <typename T>
 __global__ void __launch_bounds__(256) k_contract(const T* __restrict__ fields, int64_t npts, int nf,
                                                   int nshell, int npairs, int p0, ContractCols cc,
+                                                  const uint32_t* __restrict__ pairs,
                                                   double* __restrict__ partial) {
   constexpr int KT = 128;  // points per LDS tile
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* tile = reinterpret_cast<T*>(smem_raw);  // [nf][KT]
   const int p = p0 + threadIdx.x;
   int fa = 0, fb = 0;
-  if (p < npairs) {  // decode pair index -> (a, b), a <= b
+  if (p < npairs && pairs) {  // listed pair: a | b << 16
+    fa = (int)(pairs[p] & 0xffffu);
+    fb = (int)(pairs[p] >> 16);
+  } else if (p < npairs) {  // decode pair index -> (a, b), a <= b
     int a = 0, rem = p;
     while (rem >= nshell - a) { rem -= nshell - a; ++a; }
     fa = a;
@@ -193,8 +197,8 @@ constexpr int CONTRACT_BLOCKS = 512;
 
 template <typename T>
 cnpc_status contract_valu(const T* fields, int64_t npts, int nf, int nshell, const ContractCols& cc,
-                          double* partial, double* out, hipStream_t s) {
-  const int npairs = nshell * (nshell + 1) / 2;
+                          double* partial, double* out, hipStream_t s, const uint32_t* pairs, int nlist) {
+  const int npairs = pairs ? nlist : nshell * (nshell + 1) / 2;
   const size_t lds = (size_t)nf * 128 * sizeof(T);
   if (lds > lds_limit()) {
     set_error("too many fields for the contraction tile (%d)", nf);
@@ -204,7 +208,7 @@ cnpc_status contract_valu(const T* fields, int64_t npts, int nf, int nshell, con
     // each launch covers 256 pairs; partials of all launches share the layout
     kt_begin(CNPC_KT_CONTRACT, s);
     hipLaunchKernelGGL((k_contract<T>), dim3(CONTRACT_BLOCKS), dim3(256), lds, s, fields, npts, nf,
-                       nshell, npairs, p0, cc, partial);
+                       nshell, npairs, p0, cc, pairs, partial);
     kt_end(CNPC_KT_CONTRACT, s);
     CNPC_HIP(hipGetLastError());
   }
@@ -260,6 +264,7 @@ constexpr int MF_ROW = MF_KC + MF_PAD;
 template <int MTW, int NT, int KG, int MAXF>
 __global__ void __launch_bounds__(256, 2) k_contract_mfma(const float* __restrict__ fields, int64_t npts,
                                                        int nf, int nshell, int npairs, ContractCols cc,
+                                                       const uint32_t* __restrict__ pairs,
                                                        double* __restrict__ partial) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   float* tile = reinterpret_cast<float*>(smem_raw);  // [nf + 1][MF_ROW]
@@ -273,7 +278,10 @@ __global__ void __launch_bounds__(256, 2) k_contract_mfma(const float* __restric
   for (int i = 0; i < MTW; ++i) {
     const int p = (mg * MTW + i) * 32 + row;
     int a = zero_row, bb = zero_row;
-    if (p < npairs) {
+    if (p < npairs && pairs) {
+      a = (int)(pairs[p] & 0xffffu);
+      bb = (int)(pairs[p] >> 16);
+    } else if (p < npairs) {
       int x = 0, rem = p;
       while (rem >= nshell - x) { rem -= nshell - x; ++x; }
       a = x;
@@ -402,13 +410,14 @@ __global__ void __launch_bounds__(256, 2) k_contract_mfma(const float* __restric
 
 template <int MTW, int NT, int KG>
 static cnpc_status launch_mfma(const float* fields, int64_t npts, int nf, int nshell, int npairs,
-                               const ContractCols& cc, double* partial, size_t lds, hipStream_t s) {
+                               const ContractCols& cc, const uint32_t* pairs, double* partial, size_t lds,
+                               hipStream_t s) {
   if (nf <= 24)
     hipLaunchKernelGGL((k_contract_mfma<MTW, NT, KG, 24>), dim3(CONTRACT_BLOCKS), dim3(256), lds, s,
-                       fields, npts, nf, nshell, npairs, cc, partial);
+                       fields, npts, nf, nshell, npairs, cc, pairs, partial);
   else if (nf <= 48)
     hipLaunchKernelGGL((k_contract_mfma<MTW, NT, KG, 48>), dim3(CONTRACT_BLOCKS), dim3(256), lds, s,
-                       fields, npts, nf, nshell, npairs, cc, partial);
+                       fields, npts, nf, nshell, npairs, cc, pairs, partial);
   else {
     set_error("split-BF16 contraction supports at most 48 fields");
     return CNPC_EUNSUPPORTED;
@@ -425,17 +434,18 @@ size_t contract_mfma_partial_doubles(int nshell, int ncols) {
 // dispatch of launch_mfma over MTW = 1..MAXMTW for fixed NT, KG
 template <int NT, int KG, int MTW>
 static cnpc_status launch_mfma_mtw(int mtw, const float* fields, int64_t npts, int nf, int nshell, int npairs,
-                                   const ContractCols& cc, double* partial, size_t lds, hipStream_t s) {
-  if (mtw == MTW) return launch_mfma<MTW, NT, KG>(fields, npts, nf, nshell, npairs, cc, partial, lds, s);
+                                   const ContractCols& cc, const uint32_t* pairs, double* partial, size_t lds,
+                                   hipStream_t s) {
+  if (mtw == MTW) return launch_mfma<MTW, NT, KG>(fields, npts, nf, nshell, npairs, cc, pairs, partial, lds, s);
   if constexpr (MTW > 1)
-    return launch_mfma_mtw<NT, KG, MTW - 1>(mtw, fields, npts, nf, nshell, npairs, cc, partial, lds, s);
+    return launch_mfma_mtw<NT, KG, MTW - 1>(mtw, fields, npts, nf, nshell, npairs, cc, pairs, partial, lds, s);
   set_error("split-BF16 contraction: no kernel for %d tiles per wave", mtw);
   return CNPC_EUNSUPPORTED;
 }
 
 cnpc_status contract_mfma(const float* fields, int64_t npts, int nf, int nshell, const ContractCols& cc,
-                          double* partial, double* out, hipStream_t s) {
-  const int npairs = nshell * (nshell + 1) / 2;
+                          double* partial, double* out, hipStream_t s, const uint32_t* pairs, int nlist) {
+  const int npairs = pairs ? nlist : nshell * (nshell + 1) / 2;
   const int mtiles = (npairs + 31) / 32, ntiles = (cc.ncols + 31) / 32;
   if (ntiles > 2 || mtiles > 32) {
     set_error("split-BF16 contraction supports at most 64 columns and 1024 pairs");
@@ -464,13 +474,13 @@ cnpc_status contract_mfma(const float* fields, int64_t npts, int nf, int nshell,
   cnpc_status st;
   kt_begin(CNPC_KT_CONTRACT, s);
   if (ntiles == 1) {
-    if (kg == 4) st = launch_mfma_mtw<1, 4, 8>(mtw, fields, npts, nf, nshell, npairs, cc, partial, lds, s);
-    else if (kg == 2) st = launch_mfma_mtw<1, 2, 8>(mtw, fields, npts, nf, nshell, npairs, cc, partial, lds, s);
-    else st = launch_mfma_mtw<1, 1, 8>(mtw, fields, npts, nf, nshell, npairs, cc, partial, lds, s);
+    if (kg == 4) st = launch_mfma_mtw<1, 4, 8>(mtw, fields, npts, nf, nshell, npairs, cc, pairs, partial, lds, s);
+    else if (kg == 2) st = launch_mfma_mtw<1, 2, 8>(mtw, fields, npts, nf, nshell, npairs, cc, pairs, partial, lds, s);
+    else st = launch_mfma_mtw<1, 1, 8>(mtw, fields, npts, nf, nshell, npairs, cc, pairs, partial, lds, s);
   } else {
-    if (kg == 4) st = launch_mfma_mtw<2, 4, 4>(mtw, fields, npts, nf, nshell, npairs, cc, partial, lds, s);
-    else if (kg == 2) st = launch_mfma_mtw<2, 2, 4>(mtw, fields, npts, nf, nshell, npairs, cc, partial, lds, s);
-    else st = launch_mfma_mtw<2, 1, 4>(mtw, fields, npts, nf, nshell, npairs, cc, partial, lds, s);
+    if (kg == 4) st = launch_mfma_mtw<2, 4, 4>(mtw, fields, npts, nf, nshell, npairs, cc, pairs, partial, lds, s);
+    else if (kg == 2) st = launch_mfma_mtw<2, 2, 4>(mtw, fields, npts, nf, nshell, npairs, cc, pairs, partial, lds, s);
+    else st = launch_mfma_mtw<2, 1, 4>(mtw, fields, npts, nf, nshell, npairs, cc, pairs, partial, lds, s);
   }
   kt_end(CNPC_KT_CONTRACT, s);
   if (st != CNPC_OK) return st;
@@ -521,8 +531,8 @@ __global__ void k_finalize(FinArgs f, const double* __restrict__ C, const double
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < f.nconf; t += gridDim.x * blockDim.x) {
     const int i = f.cfg[3 * t], j = f.cfg[3 * t + 1], k = f.cfg[3 * t + 2];
     double r, sh = 0.0;
+    const int p = f.prow[t];
     if (f.est == CNPC_EST_SCOCCIMARRO) {
-      const int p = j * f.nb - j * (j - 1) / 2 + (k - j);
       const double c = C[(int64_t)p * f.ncols + i];
       r = pre * c / (f.n3 * (double)f.ntri[t]);
       if (noise) {
@@ -534,7 +544,6 @@ __global__ void k_finalize(FinArgs f, const double* __restrict__ C, const double
         sh = pre * v;
       }
     } else {
-      const int p = i * f.nb - i * (i - 1) / 2 + (j - i);
       const double c = C[(int64_t)p * f.ncols + 0];
       r = pre * c / (f.n3 * f.counts[i] * f.counts[j]);
       if (noise) {
@@ -568,6 +577,9 @@ __global__ void k_finalize(FinArgs f, const double* __restrict__ C, const double
 // ---------------------------------------------------------------- plan --
 static cnpc_status device_tables(cnpc_bispec_plan* P) {
   const int nc = P->nconf;
+  const size_t npl = P->pairs.size();
+  CNPC_HIP(hipMalloc(&P->d_pairs, sizeof(uint32_t) * (npl > 0 ? npl : 1)));
+  CNPC_HIP(hipMalloc(&P->d_prow, sizeof(int) * (nc > 0 ? nc : 1)));
   CNPC_HIP(hipMalloc(&P->d_cfg, sizeof(int) * 3 * (nc > 0 ? nc : 1)));
   CNPC_HIP(hipMalloc(&P->d_ntri, sizeof(int64_t) * (nc > 0 ? nc : 1)));
   CNPC_HIP(hipMalloc(&P->d_aux, sizeof(double) * 2 * (nc > 0 ? nc : 1)));
@@ -580,6 +592,8 @@ static cnpc_status upload_tables(cnpc_bispec_plan* P) {
   const int nc = P->nconf;
   std::vector<double> cnt(P->nb);
   for (int b = 0; b < P->nb; ++b) cnt[b] = (double)P->counts[b];
+  CNPC_HIP(hipMemcpy(P->d_pairs, P->pairs.data(), sizeof(uint32_t) * P->pairs.size(), hipMemcpyHostToDevice));
+  CNPC_HIP(hipMemcpy(P->d_prow, P->prow.data(), sizeof(int) * nc, hipMemcpyHostToDevice));
   CNPC_HIP(hipMemcpy(P->d_cfg, P->cfg.data(), sizeof(int) * 3 * nc, hipMemcpyHostToDevice));
   CNPC_HIP(hipMemcpy(P->d_ntri, P->ntri.data(), sizeof(int64_t) * nc, hipMemcpyHostToDevice));
   CNPC_HIP(hipMemcpy(P->d_aux, P->aux.data(), sizeof(double) * 2 * nc, hipMemcpyHostToDevice));
@@ -806,6 +820,28 @@ cnpc_status bispec_plan_create(cnpc_bispec_plan** out, const cnpc_mesh_desc* d, 
     }
   }
   P->nconf = (int)P->ntri.size();
+  // contraction rows: the pairs (j, k) (Scoccimarro, column i) or (i, j)
+  // (TripoSH) the kept configurations use, in lexicographic order; for
+  // Scoccimarro l = 0 these are the pairs with k <= 2j, about half of all
+  {
+    std::vector<int> row_of((size_t)nb * (nb + 1) / 2, -1);
+    for (int t = 0; t < P->nconf; ++t) {
+      const int a = est == CNPC_EST_TRIPOSH ? P->cfg[3 * t] : P->cfg[3 * t + 1];
+      const int bb = est == CNPC_EST_TRIPOSH ? P->cfg[3 * t + 1] : P->cfg[3 * t + 2];
+      row_of[pair_index(a, bb, nb)] = -2;  // used
+    }
+    for (int a = 0; a < nb; ++a)
+      for (int bb = a; bb < nb; ++bb)
+        if (row_of[pair_index(a, bb, nb)] == -2) {
+          row_of[pair_index(a, bb, nb)] = (int)P->pairs.size();
+          P->pairs.push_back((uint32_t)a | ((uint32_t)bb << 16));
+        }
+    for (int t = 0; t < P->nconf; ++t) {
+      const int a = est == CNPC_EST_TRIPOSH ? P->cfg[3 * t] : P->cfg[3 * t + 1];
+      const int bb = est == CNPC_EST_TRIPOSH ? P->cfg[3 * t + 1] : P->cfg[3 * t + 2];
+      P->prow.push_back(row_of[pair_index(a, bb, nb)]);
+    }
+  }
   cnpc_status st = device_tables(P);
   if (st == CNPC_OK) st = upload_tables(P);
   if (st != CNPC_OK) {
@@ -818,6 +854,8 @@ cnpc_status bispec_plan_create(cnpc_bispec_plan** out, const cnpc_mesh_desc* d, 
 
 void bispec_plan_destroy(cnpc_bispec_plan* P) {
   if (!P) return;
+  if (P->d_pairs) (void)hipFree(P->d_pairs);
+  if (P->d_prow) (void)hipFree(P->d_prow);
   if (P->d_cfg) (void)hipFree(P->d_cfg);
   if (P->d_ntri) (void)hipFree(P->d_ntri);
   if (P->d_aux) (void)hipFree(P->d_aux);
@@ -831,9 +869,10 @@ template <typename T>
 static cnpc_status contract_any(const cnpc_bispec_plan* P, const T* fields, int64_t n3, double* partial,
                                 double* out, hipStream_t s) {
   if constexpr (sizeof(T) == 4) {
-    if (P->prec == CNPC_PREC_BF16X3) return contract_mfma(fields, n3, P->nfields, P->nb, P->cc, partial, out, s);
+    if (P->prec == CNPC_PREC_BF16X3)
+      return contract_mfma(fields, n3, P->nfields, P->nb, P->cc, partial, out, s, P->d_pairs, (int)P->pairs.size());
   }
-  return contract_valu<T>(fields, n3, P->nfields, P->nb, P->cc, partial, out, s);
+  return contract_valu<T>(fields, n3, P->nfields, P->nb, P->cc, partial, out, s, P->d_pairs, (int)P->pairs.size());
 }
 
 // FN0 / ind (TripoSH, both or neither): band spectrum of N and the shell
@@ -894,6 +933,7 @@ static cnpc_status bispec_run_t(const cnpc_bispec_plan* P, const cx<T>* F0, cons
   f.nconf = P->nconf;
   f.n3 = (double)n3;
   f.cfg = P->d_cfg;
+  f.prow = P->d_prow;
   f.ntri = P->d_ntri;
   f.aux = P->d_aux;
   f.counts = P->d_counts;

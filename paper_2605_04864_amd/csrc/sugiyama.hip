@@ -204,10 +204,10 @@ __device__ __forceinline__ int pair_of(int a, int b, int ns) {  // a <= b
   return a * ns - a * (a - 1) / 2 + (b - a);
 }
 
-// acc[i][j] += coef * v_ij with (mode 0) v_ij = C_ij, the contraction of
-// field i of P (paired with the all-ones field nb of the nb + 1 shell fields)
-// against column j; (mode 1) C_ij + C_ji; (mode 2) the pair (min(i, j),
-// max(i, j)) of the nb shell fields of P against their one column
+// acc[i][j] += coef * v_ij with (mode 0) v_ij = C_ij, row i (the pair of
+// field i of P with the all-ones field nb) against column j; (mode 1) C_ij +
+// C_ji; (mode 2) the pair (min(i, j), max(i, j)) of the nb shell fields of P
+// (all pairs, lexicographic rows) against their one column
 __global__ void k_sugi_accum(const double* __restrict__ C, int nb, int mode, double coef,
                              double* __restrict__ acc) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -216,9 +216,9 @@ __global__ void k_sugi_accum(const double* __restrict__ C, int nb, int mode, dou
   double v;
   if (mode == 2) {
     v = C[pair_of(i < j ? i : j, i < j ? j : i, nb)];
-  } else {
-    v = C[(int64_t)pair_of(i, nb, nb + 1) * nb + j];
-    if (mode == 1) v += C[(int64_t)pair_of(j, nb, nb + 1) * nb + i];
+  } else {  // rows of the pairs (i, nb): row i
+    v = C[(int64_t)i * nb + j];
+    if (mode == 1) v += C[(int64_t)j * nb + i];
   }
   acc[t] += coef * v;
 }
@@ -351,6 +351,10 @@ static cnpc_status sugi_plan_create(cnpc_bispec_plan** out, const cnpc_mesh_desc
         wq3[((size_t)i * nb + j) * P->next + c] = q_factor_host(l1, l2, L, ki, kj, kc) * P->wq[c] / den;
       }
     }
+  // rows of the cross-leg contraction: the pairs (i, nb), shell field i times
+  // the all-ones field
+  for (int i = 0; i < nb; ++i) P->pairs.push_back((uint32_t)i | ((uint32_t)nb << 16));
+  P->prow.assign(P->nconf, 0);
   cnpc_status st = device_tables(P);
   if (st == CNPC_OK) st = upload_tables(P);
   if (st == CNPC_OK) {
@@ -436,12 +440,12 @@ static cnpc_status sugi_run_t(const cnpc_bispec_plan* P, const cx<T>* F0, const 
     for (int j = 0; j < nb; ++j) cc.field[j] = nb + 1 + j;
     if constexpr (sizeof(T) == 4) {
       if (P->prec == CNPC_PREC_BF16X3) {
-        CNPC_TRY(contract_mfma(fields, n3, 2 * nb + 1, nb + 1, cc, partial, Cm, s));
+        CNPC_TRY(contract_mfma(fields, n3, 2 * nb + 1, nb + 1, cc, partial, Cm, s, P->d_pairs, nb));
       } else {
-        CNPC_TRY(contract_valu<T>(fields, n3, 2 * nb + 1, nb + 1, cc, partial, Cm, s));
+        CNPC_TRY(contract_valu<T>(fields, n3, 2 * nb + 1, nb + 1, cc, partial, Cm, s, P->d_pairs, nb));
       }
     } else {
-      CNPC_TRY(contract_valu<T>(fields, n3, 2 * nb + 1, nb + 1, cc, partial, Cm, s));
+      CNPC_TRY(contract_valu<T>(fields, n3, 2 * nb + 1, nb + 1, cc, partial, Cm, s, P->d_pairs, nb));
     }
     hipLaunchKernelGGL(k_sugi_accum, dim3((nb * nb + 255) / 256), dim3(256), 0, s, Cm, nb, transpose, coef, accum);
     CNPC_HIP(hipGetLastError());
