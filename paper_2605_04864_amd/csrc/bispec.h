@@ -46,6 +46,11 @@ cnpc_status contract_valu(const T* fields, int64_t npts, int nf, int nshell, con
 cnpc_status contract_mfma(const float* fields, int64_t npts, int nf, int nshell, const ContractCols& cc,
                           double* partial, double* out, hipStream_t s, const uint32_t* pairs = nullptr,
                           int nlist = 0);
+// the same in the field type (FP32 or FP64) on the matrix cores
+template <typename T>
+cnpc_status contract_mfma_fp(const T* fields, int64_t npts, int nf, int nshell, const ContractCols& cc,
+                             double* partial, double* out, hipStream_t s, const uint32_t* pairs = nullptr,
+                             int nlist = 0);
 
 }  // namespace cnpc
 

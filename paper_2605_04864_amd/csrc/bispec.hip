@@ -488,6 +488,220 @@ cnpc_status contract_mfma(const float* fields, int64_t npts, int nf, int nshell,
                        out, s);
 }
 
+// ------------------------------------------ FP32 / FP64 MFMA contraction --
+// The same C[r, c] = sum_x X_a X_b Y_c on the matrix cores in the field type:
+// FP32 with v_mfma_f32_32x32x2_f32 (32 x 32 output tiles, 2 points per
+// instruction), FP64 with v_mfma_f64_16x16x4_f64 (16 x 16 tiles, 4 points).
+// Operand layout (TM x TK = 64 lanes): lane l holds A[l % TM][l / TM] and
+// B[l / TM][l % TM]; the K index is any bijection onto the points shared by A
+// and B, here lane group q = l / TM takes the S consecutive points
+// ks + q S .. ks + q S + S - 1 of each step, one per instruction.  Output
+// register v of lane l is D[row(v, l)][l % TM]: FP32 32 x 32 row 8 (v / 4) +
+// 4 (l / 32) + v % 4, FP64 16 x 16 row 4 v + l / 16.  The pair products X_a X_b are
+// formed in the field type; the FP32 accumulators are added into FP64 ones
+// every chunk of points, so no FP32 sum runs over more than MP_KC / KG points.
+template <typename T>
+struct MfmaFp;
+template <>
+struct MfmaFp<float> {
+  static constexpr int TM = 32, TK = 2, NACC = 16;
+  typedef float acc_t __attribute__((ext_vector_type(16)));
+  static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int v, int l) { return 8 * (v / 4) + 4 * (l / 32) + (v % 4); }
+};
+template <>
+struct MfmaFp<double> {
+  static constexpr int TM = 16, TK = 4, NACC = 4;
+  typedef double acc_t __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int v, int l) { return 4 * v + l / 16; }
+};
+
+constexpr int MP_KC = 256;  // grid points per LDS chunk (= threads per workgroup)
+constexpr int MP_S = 8;     // consecutive points per lane per step
+
+// Wave w of the 4 is point group kg = w % KG of pair group mg = w / KG: it
+// owns the MTW m-tiles mg MTW .. and all NT n-tiles, for the steps kg, kg +
+// KG, ... of every chunk; one FP64 partial per (workgroup, point group).
+template <typename T, int MTW, int NT>
+__global__ void __launch_bounds__(256, 2) k_contract_mfma_fp(const T* __restrict__ fields, int64_t npts, int nf,
+                                                          int nshell, int npairs, int kg_n, ContractCols cc,
+                                                          const uint32_t* __restrict__ pairs,
+                                                          double* __restrict__ partial) {
+  using M = MfmaFp<T>;
+  constexpr int TM = M::TM, TK = M::TK, NACC = M::NACC, STEP = TK * MP_S;
+  constexpr int ROW = MP_KC + (sizeof(T) == 4 ? 4 : 2);  // padded row (elements)
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* tile = reinterpret_cast<T*>(smem_raw);  // [nf + 1][ROW]
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int mg = wave / kg_n, kg = wave - mg * kg_n;
+  const int zero_row = nf;
+  for (int i = threadIdx.x; i < ROW; i += blockDim.x) tile[zero_row * ROW + i] = T(0);
+  const int q = lane / TM, r = lane % TM;
+  int offa[MTW], offb[MTW];
+#pragma unroll
+  for (int i = 0; i < MTW; ++i) {
+    const int p = (mg * MTW + i) * TM + r;
+    int a = zero_row, bb = zero_row;
+    if (p < npairs && pairs) {
+      a = (int)(pairs[p] & 0xffffu);
+      bb = (int)(pairs[p] >> 16);
+    } else if (p < npairs) {
+      int x = 0, rem = p;
+      while (rem >= nshell - x) { rem -= nshell - x; ++x; }
+      a = x;
+      bb = x + rem;
+    }
+    offa[i] = a * ROW + q * MP_S;
+    offb[i] = bb * ROW + q * MP_S;
+  }
+  int offc[NT];
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) {
+    const int j = nt * TM + r;
+    int f = zero_row;
+#pragma unroll
+    for (int c = 0; c < MAX_COLS; ++c)
+      if (c == j && c < cc.ncols) f = cc.field[c];
+    offc[nt] = f * ROW + q * MP_S;
+  }
+  typename M::acc_t acc[MTW][NT];
+  double tot[MTW][NT][NACC];
+#pragma unroll
+  for (int i = 0; i < MTW; ++i)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+      for (int v = 0; v < NACC; ++v) {
+        acc[i][nt][v] = T(0);
+        tot[i][nt][v] = 0.0;
+      }
+  const int64_t per_block = ((npts + gridDim.x - 1) / gridDim.x + MP_KC - 1) / MP_KC * MP_KC;
+  const int64_t x0 = (int64_t)blockIdx.x * per_block;
+  const int64_t x1 = min(npts, x0 + per_block);
+  for (int64_t xb = x0; xb < x1; xb += MP_KC) {
+    __syncthreads();
+    {
+      const bool ok = xb + threadIdx.x < x1;
+#pragma unroll 8
+      for (int f = 0; f < nf; ++f)
+        tile[f * ROW + threadIdx.x] = ok ? fields[(int64_t)f * npts + xb + threadIdx.x] : T(0);
+    }
+    __syncthreads();
+    for (int ks = kg * STEP; ks < MP_KC; ks += STEP * kg_n) {
+      T bv[NT][MP_S];
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+        for (int e = 0; e < MP_S; ++e) bv[nt][e] = tile[offc[nt] + ks + e];
+#pragma unroll
+      for (int i = 0; i < MTW; ++i) {
+        T av[MP_S];
+#pragma unroll
+        for (int e = 0; e < MP_S; ++e) av[e] = tile[offa[i] + ks + e] * tile[offb[i] + ks + e];
+#pragma unroll
+        for (int e = 0; e < MP_S; ++e)
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) acc[i][nt] = M::mma(av[e], bv[nt][e], acc[i][nt]);
+      }
+    }
+    if constexpr (sizeof(T) == 4) {
+#pragma unroll
+      for (int i = 0; i < MTW; ++i)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+          for (int v = 0; v < NACC; ++v) {
+            tot[i][nt][v] += (double)acc[i][nt][v];
+            acc[i][nt][v] = T(0);
+          }
+    }
+  }
+  double* out = partial + ((int64_t)blockIdx.x * kg_n + kg) * npairs * cc.ncols;
+#pragma unroll
+  for (int i = 0; i < MTW; ++i) {
+    const int mt = mg * MTW + i;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int j = nt * TM + r;
+#pragma unroll
+      for (int v = 0; v < NACC; ++v) {
+        const int p = mt * TM + M::row(v, lane);
+        const double val = sizeof(T) == 4 ? tot[i][nt][v] : (double)acc[i][nt][v];
+        if (p < npairs && j < cc.ncols) out[(int64_t)p * cc.ncols + j] = val;
+      }
+    }
+  }
+}
+
+// MTW in {1, 2, 4, 8} (FP32: at most 4 accumulator tiles per wave; FP64: 16)
+template <typename T, int NT, int MTW>
+static cnpc_status launch_mfma_fp_mtw(int mtw, int kg, const T* fields, int64_t npts, int nf, int nshell,
+                                      int npairs, const ContractCols& cc, const uint32_t* pairs, double* partial,
+                                      size_t lds, hipStream_t s) {
+  if (mtw <= MTW) {
+    hipLaunchKernelGGL((k_contract_mfma_fp<T, MTW, NT>), dim3(CONTRACT_BLOCKS), dim3(256), lds, s, fields, npts,
+                       nf, nshell, npairs, kg, cc, pairs, partial);
+    CNPC_HIP(hipGetLastError());
+    return CNPC_OK;
+  }
+  if constexpr (MTW < 8 && (sizeof(T) == 8 ? MTW * 2 * NT <= 16 : MTW * 2 * NT <= 4))
+    return launch_mfma_fp_mtw<T, NT, MTW * 2>(mtw, kg, fields, npts, nf, nshell, npairs, cc, pairs, partial,
+                                              lds, s);
+  set_error("MFMA contraction: no kernel for %d tiles per wave", mtw);
+  return CNPC_EUNSUPPORTED;
+}
+
+template <typename T>
+cnpc_status contract_mfma_fp(const T* fields, int64_t npts, int nf, int nshell, const ContractCols& cc,
+                             double* partial, double* out, hipStream_t s, const uint32_t* pairs, int nlist) {
+  constexpr int TM = MfmaFp<T>::TM;
+  constexpr int MAXT = sizeof(T) == 8 ? 16 : 4;  // accumulator tiles per wave
+  const int npairs = pairs ? nlist : nshell * (nshell + 1) / 2;
+  const int mtiles = (npairs + TM - 1) / TM, ntiles = (cc.ncols + TM - 1) / TM;
+  if (ntiles > (sizeof(T) == 8 ? 3 : 2)) {
+    set_error("MFMA contraction: too many columns (%d)", cc.ncols);
+    return CNPC_EUNSUPPORTED;
+  }
+  // the most point groups KG whose pair groups fit MAXT tiles per wave; the
+  // m-tiles per wave rounded up to a power of two (at most 8)
+  int kg = 4, mtw = 0;
+  for (; kg >= 1; kg >>= 1) {
+    const int need = (mtiles + (4 / kg) - 1) / (4 / kg);
+    mtw = 1;
+    while (mtw < need) mtw <<= 1;
+    if (mtw <= 8 && mtw * ntiles <= MAXT) break;
+  }
+  if (kg < 1) {
+    set_error("MFMA contraction: %d pair tiles x %d column tiles do not fit", mtiles, ntiles);
+    return CNPC_EUNSUPPORTED;
+  }
+  const size_t lds = sizeof(T) * (size_t)(nf + 1) * (MP_KC + (sizeof(T) == 4 ? 4 : 2));
+  if (lds > lds_limit()) {
+    set_error("too many fields for the MFMA contraction tile (%d)", nf);
+    return CNPC_EUNSUPPORTED;
+  }
+  cnpc_status st;
+  kt_begin(CNPC_KT_CONTRACT, s);
+  if (ntiles == 1) {
+    st = launch_mfma_fp_mtw<T, 1, 1>(mtw, kg, fields, npts, nf, nshell, npairs, cc, pairs, partial, lds, s);
+  } else if (ntiles == 2) {
+    st = launch_mfma_fp_mtw<T, 2, 1>(mtw, kg, fields, npts, nf, nshell, npairs, cc, pairs, partial, lds, s);
+  } else {
+    if constexpr (sizeof(T) == 8)
+      st = launch_mfma_fp_mtw<T, 3, 1>(mtw, kg, fields, npts, nf, nshell, npairs, cc, pairs, partial, lds, s);
+    else
+      st = CNPC_EUNSUPPORTED;
+  }
+  kt_end(CNPC_KT_CONTRACT, s);
+  if (st != CNPC_OK) return st;
+  return reduce_blocks(partial, CONTRACT_BLOCKS * kg, (int64_t)npairs * cc.ncols, out, s);
+}
+
 // --------------------------------------------------- shell-filtered c2r --
 // X_b = c2r[Phi_b F] for the shells b0..b0+nsh-1 (mask != 0), or G = c2r[F]
 // (mask == 0, nsh = 1).  F: band spectrum (half-width m).
@@ -872,7 +1086,8 @@ static cnpc_status contract_any(const cnpc_bispec_plan* P, const T* fields, int6
     if (P->prec == CNPC_PREC_BF16X3)
       return contract_mfma(fields, n3, P->nfields, P->nb, P->cc, partial, out, s, P->d_pairs, (int)P->pairs.size());
   }
-  return contract_valu<T>(fields, n3, P->nfields, P->nb, P->cc, partial, out, s, P->d_pairs, (int)P->pairs.size());
+  return contract_mfma_fp<T>(fields, n3, P->nfields, P->nb, P->cc, partial, out, s, P->d_pairs,
+                             (int)P->pairs.size());
 }
 
 // FN0 / ind (TripoSH, both or neither): band spectrum of N and the shell

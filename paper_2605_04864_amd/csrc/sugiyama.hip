@@ -442,10 +442,10 @@ static cnpc_status sugi_run_t(const cnpc_bispec_plan* P, const cx<T>* F0, const 
       if (P->prec == CNPC_PREC_BF16X3) {
         CNPC_TRY(contract_mfma(fields, n3, 2 * nb + 1, nb + 1, cc, partial, Cm, s, P->d_pairs, nb));
       } else {
-        CNPC_TRY(contract_valu<T>(fields, n3, 2 * nb + 1, nb + 1, cc, partial, Cm, s, P->d_pairs, nb));
+        CNPC_TRY(contract_mfma_fp<T>(fields, n3, 2 * nb + 1, nb + 1, cc, partial, Cm, s, P->d_pairs, nb));
       }
     } else {
-      CNPC_TRY(contract_valu<T>(fields, n3, 2 * nb + 1, nb + 1, cc, partial, Cm, s, P->d_pairs, nb));
+      CNPC_TRY(contract_mfma_fp<T>(fields, n3, 2 * nb + 1, nb + 1, cc, partial, Cm, s, P->d_pairs, nb));
     }
     hipLaunchKernelGGL(k_sugi_accum, dim3((nb * nb + 255) / 256), dim3(256), 0, s, Cm, nb, transpose, coef, accum);
     CNPC_HIP(hipGetLastError());
@@ -462,10 +462,10 @@ static cnpc_status sugi_run_t(const cnpc_bispec_plan* P, const cx<T>* F0, const 
       if (P->prec == CNPC_PREC_BF16X3) {
         CNPC_TRY(contract_mfma(fields, n3, nb + 1, nb, cc, partial, Cm, s));
       } else {
-        CNPC_TRY(contract_valu<T>(fields, n3, nb + 1, nb, cc, partial, Cm, s));
+        CNPC_TRY(contract_mfma_fp<T>(fields, n3, nb + 1, nb, cc, partial, Cm, s));
       }
     } else {
-      CNPC_TRY(contract_valu<T>(fields, n3, nb + 1, nb, cc, partial, Cm, s));
+      CNPC_TRY(contract_mfma_fp<T>(fields, n3, nb + 1, nb, cc, partial, Cm, s));
     }
     hipLaunchKernelGGL(k_sugi_accum, dim3((nb * nb + 255) / 256), dim3(256), 0, s, Cm, nb, 2, coef, accum);
     CNPC_HIP(hipGetLastError());
