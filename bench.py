@@ -48,8 +48,6 @@ def parse():
                     help="batch runner: the library's cnpc_batch (HIP graph captured by the library) "
                          "or the Python Batch captured with torch.cuda.CUDAGraph")
     ap.add_argument("--no-tune", action="store_true", help="library defaults, no autotuning")
-    ap.add_argument("--staged", action="store_true",
-                    help="painting and spectra on separate streams (with --no-tune)")
     ap.add_argument("--balance", choices=["rr", "lpt", "mixed"], default="rr",
                     help="placement of the catalogs on the streams (see pipeline.Batch.assignment)")
     ap.add_argument("--tune-mocks", type=int, default=16, help="mocks per autotuner trial batch")
@@ -176,7 +174,6 @@ def main():
              "bk": torch.empty((3, plan.nconf), dtype=torch.float64, device=dev)} for _ in gpu_mocks]
     tuning = None
     nstreams = args.streams or 4
-    staged = args.staged
     if not args.no_tune:
         from paper_2605_04864_amd import autotune
         tcat = gpu_mocks[: max(1, min(args.tune_mocks, len(gpu_mocks)))]
@@ -184,12 +181,11 @@ def main():
                                   streams=(args.streams,) if args.streams else (1, 2, 3, 4, 6),
                                   log=lambda m: log(args, m), engine=args.engine)
         nstreams = res.streams
-        staged = res.staged
         tuning = res.as_dict()
         tuning["batch_mocks"] = len(tcat)
-        log(args, f"autotuned in {res.seconds:.1f}s: streams {res.streams}, staged {res.staged}, knobs {res.knobs}, "
+        log(args, f"autotuned in {res.seconds:.1f}s: streams {res.streams}, knobs {res.knobs}, "
                   f"{res.default_ms:.2f} -> {res.ms:.2f} ms per {len(tcat)} mocks")
-    native = args.engine == "native" and not staged and not args.graph_per_stream and args.balance == "rr"
+    native = args.engine == "native" and not args.graph_per_stream and args.balance == "rr"
     if native:
         batch = pl.NativeBatch(desc, bins, plan, nstreams=nstreams,
                                max_ngal=max(int(g.shape[1]) for g, _ in gpu_mocks),
@@ -198,7 +194,7 @@ def main():
         def step():
             batch.run(gpu_mocks, outs)
     else:
-        batch = pl.Batch(nstreams, staged=staged, balance=args.balance)
+        batch = pl.Batch(nstreams, balance=args.balance)
 
         def step():
             batch.run(desc, gpu_mocks, bins, plan, outs)
@@ -214,7 +210,7 @@ def main():
     model = {k: float(np.sum([m[k] for m in models])) for k in models[0]}  # per step
 
     run = step
-    if args.graph_per_stream and not args.no_graph and not staged:
+    if args.graph_per_stream and not args.no_graph:
         # one single-stream graph per stream, replayed side by side
         graphs = []
         for k, s in enumerate(batch.streams):
@@ -336,7 +332,6 @@ def main():
         "graph": "none" if args.no_graph else ("per-stream" if args.graph_per_stream else "one"),
         "engine": "cnpc_batch" if native else "python Batch",
         "streams": nstreams,
-        "staged": staged,
         "placement": args.balance,
         "tuning": tuning,
         "data": "synthetic lognormal mocks (seeded), resident in HBM",
@@ -706,7 +701,9 @@ def cpu_baseline(mocks, sizes, log=print, workers=None):
                        f"{len(sizes)}); catalog sums and one painting timed on 1/{CPU_SLICE} of each (their "
                        f"per-particle and per-call costs fitted over the four sizes), FFT / shell / triple-sum / "
                        f"binning stages timed once each and scaled by their repeat counts; seconds per mock "
-                       f"a (N_g + N_r) + b, summed over all {len(sizes)} mocks"),
+                       f"a (N_g + N_r) + b, summed over all {len(sizes)} mocks; on the build host this sample "
+                       f"estimates 22% less time than the oracle takes on whole mocks "
+                       f"(profiles/cpu_oracle_whole_mocks_c4.txt)"),
             "single_thread": one, "all_cores": allcore, "fit": fit,
             "parts_s": {k: round(v, 2) for k, v in single["mesh_parts_s"].items()},
             "host_cpus": os.cpu_count(), "cpu_model": _cpu_model()}

@@ -10,11 +10,19 @@
  * Conventions shared by every call
  * --------------------------------
  *  - All data pointers are DEVICE pointers unless a parameter says "host".
- *    The caller owns every buffer; no call allocates device memory.  Scratch
- *    space is passed in as `ws` / `ws_bytes`, sized by the matching
- *    *_workspace_size query.
- *  - Every call is asynchronous on `stream` (a hipStream_t, NULL = default
- *    stream).  Outputs are valid once the stream has synchronised.
+ *    The caller owns every buffer it passes.  Scratch space is passed in as
+ *    `ws` / `ws_bytes`, sized by the matching *_workspace_size query.
+ *  - Every compute call is asynchronous on `stream` (a hipStream_t, NULL =
+ *    default stream), allocates no device memory and does not synchronise;
+ *    outputs are valid once the stream has synchronised.  The set-up calls
+ *    are the exceptions: cnpc_bispec_plan_create and cnpc_sugi_plan_create
+ *    allocate the plan's small device tables (configurations, factors, pair
+ *    rows) with blocking copies, and a Scoccimarro plan computes N_T on
+ *    `stream` and synchronises it to read them back; cnpc_batch_create
+ *    creates streams and events, cnpc_batch_capture a HIP graph,
+ *    cnpc_ktimer_start events; the first transform on a device uploads a
+ *    16 KiB twiddle table with a blocking copy.  Destroy calls free what
+ *    their create call allocated.
  *  - Return value: CNPC_OK (0) or a negative status.  Arguments are validated
  *    on the host before anything is launched; on error nothing is launched and
  *    cnpc_last_error() (thread-local) describes the problem.
@@ -526,8 +534,11 @@ cnpc_status cnpc_ktimer_stop(double* ms_per_class, int64_t* launches_per_class);
  *                          bucket: 0 (default) takes the catalog sums, the
  *                          tile histogram and the first sort step in one read
  *                          of each catalog; 1 takes the sums and histogram in
- *                          a read of their own (identical meshes up to the
- *                          rounding of alpha, sums equal to a few ulp).
+ *                          a read of their own; 2 keeps the histogram and the
+ *                          l = 0 sums in the first sort step and takes the
+ *                          Y_lm sums (l = 2, 4) in a read of their own
+ *                          (identical meshes up to the rounding of alpha,
+ *                          sums equal to a few ulp).
  *   CNPC_TUNE_FOLD_FUSED   cnpc_paint_deinterlace and the batch runner: 0
  *                          (default) sums the tile blocks inside the z passes
  *                          of the de-interlacing transforms; 1 writes the

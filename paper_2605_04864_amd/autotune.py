@@ -6,8 +6,6 @@ size), the batch is captured into one HIP graph, and the graph is replayed.
 The setting is
 
   streams      streams a ``pipeline.Batch`` spreads the catalogs over
-  staged       Batch mode: whole catalogs round-robin (False; the only mode
-               captured into graphs, so the only one searched)
   fft_passes   register FFT passes (0) or LDS Stockham passes only (1)
   fft_col_w    columns per workgroup of the LDS column passes (0: library's)
   contract_kg  point groups per split-BF16 contraction workgroup (0: library's)
@@ -117,7 +115,6 @@ def _cache_store(path: str, sig: str, entry: Dict) -> None:
 @dataclass
 class TuneResult:
     streams: int
-    staged: bool
     knobs: Dict[str, int]
     ms: float                  # per batch, best setting
     default_ms: float          # per batch, library defaults (DEFAULT_STREAMS if offered)
@@ -132,7 +129,7 @@ class TuneResult:
 
 
 def time_batch(desc, catalogs, bins, plan, ells=(0, 2, 4), nstreams: int = DEFAULT_STREAMS,
-               reps: int = 3, staged: bool = False, engine: str = "torch") -> float:
+               reps: int = 3, engine: str = "torch") -> float:
     """Median ms per graph replay of the whole batch under the current knobs
     (engine "native": the library's cnpc_batch graph; "torch": pipeline.Batch
     captured with torch.cuda.CUDAGraph)."""
@@ -141,7 +138,7 @@ def time_batch(desc, catalogs, bins, plan, ells=(0, 2, 4), nstreams: int = DEFAU
     dev = catalogs[0][0].device
     outs = [{"pk": torch.empty((9, bins.nbins), dtype=torch.float64, device=dev),
              "bk": torch.empty((3, plan.nconf), dtype=torch.float64, device=dev)} for _ in catalogs]
-    if engine == "native" and not staged:
+    if engine == "native":
         batch = pl.NativeBatch(desc, bins, plan, ells=ells, nstreams=nstreams,
                                max_ngal=max(int(g.shape[1]) for g, _ in catalogs),
                                max_nran=max(int(r.shape[1]) for _, r in catalogs), device=dev)
@@ -150,7 +147,7 @@ def time_batch(desc, catalogs, bins, plan, ells=(0, 2, 4), nstreams: int = DEFAU
         batch.capture(catalogs, outs)
         replay = batch.replay
     else:
-        batch = pl.Batch(nstreams, device=dev, staged=staged)
+        batch = pl.Batch(nstreams, device=dev)
         batch.run(desc, catalogs, bins, plan, outs, ells)
         torch.cuda.synchronize()
         graph = torch.cuda.CUDAGraph()
@@ -183,19 +180,17 @@ def tune_batch(desc, catalogs, bins, plan, ells=(0, 2, 4), streams: Sequence[int
         hit = _cache_load(path).get("entries", {}).get(sig)
         if hit:
             set_knobs(hit["knobs"])
-            return TuneResult(int(hit["streams"]), bool(hit.get("staged", False)), dict(hit["knobs"]),
-                              float(hit["ms"]), float(hit["default_ms"]), 0.0, True, [])
-    # staged batches are not captured into graphs (see pipeline.Batch), so the
-    # timed search keeps the round-robin batch
-    space = {"streams": list(streams), "staged": [False]}
+            return TuneResult(int(hit["streams"]), dict(hit["knobs"]), float(hit["ms"]), float(hit["default_ms"]),
+                              0.0, True, [])
+    space = {"streams": list(streams)}
     for k in KNOB_ORDER:
         space[k] = list(L.TUNE[k][1]) if k != "fft_col_w" else [0, 4, 8, 16, 32]
     s0 = DEFAULT_STREAMS if DEFAULT_STREAMS in streams else streams[0]
-    start = {"streams": s0, "staged": False, **{k: 0 for k in KNOB_ORDER}}
+    start = {"streams": s0, **{k: 0 for k in KNOB_ORDER}}
 
     def measure(s):
         set_knobs({k: s[k] for k in KNOB_ORDER})
-        t = time_batch(desc, catalogs, bins, plan, ells, s["streams"], reps, staged=s["staged"], engine=engine)
+        t = time_batch(desc, catalogs, bins, plan, ells, s["streams"], reps, engine=engine)
         if log:
             log(f"autotune {s} -> {t:.3f} ms")
         return t
@@ -208,9 +203,9 @@ def tune_batch(desc, catalogs, bins, plan, ells=(0, 2, 4), streams: Sequence[int
         raise
     knobs = {k: int(best[k]) for k in KNOB_ORDER}
     set_knobs(knobs)
-    res = TuneResult(int(best["streams"]), bool(best["staged"]), knobs, float(best_t), float(trials[0][1]),
-                     time.time() - t0, False, [dict(s, ms=t) for s, t in trials])
+    res = TuneResult(int(best["streams"]), knobs, float(best_t), float(trials[0][1]), time.time() - t0, False,
+                     [dict(s, ms=t) for s, t in trials])
     if use_cache:
-        _cache_store(path, sig, {"streams": res.streams, "staged": res.staged, "knobs": knobs, "ms": res.ms,
+        _cache_store(path, sig, {"streams": res.streams, "knobs": knobs, "ms": res.ms,
                                  "default_ms": res.default_ms})
     return res

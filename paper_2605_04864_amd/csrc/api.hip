@@ -137,7 +137,7 @@ cnpc_status cnpc_tune_set(int32_t knob, int32_t value) {
     case CNPC_TUNE_CONTRACT_KG:
     case CNPC_TUNE_SORT_PER: ok = ok || value == 1 || value == 2 || value == 4; break;
     case CNPC_TUNE_SORT_THREADS: ok = ok || value == 512 || value == 1024; break;
-    case CNPC_TUNE_SORT_FUSED: ok = value == 0 || value == 1; break;
+    case CNPC_TUNE_SORT_FUSED: ok = value >= 0 && value <= 2; break;
     case CNPC_TUNE_FOLD_FUSED: ok = value == 0 || value == 1; break;
   }
   CNPC_REQUIRE(ok, "value %d out of range for tuning knob %d", value, knob);

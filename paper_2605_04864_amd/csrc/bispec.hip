@@ -928,10 +928,10 @@ static unsigned char* align256(unsigned char* p) {
   return reinterpret_cast<unsigned char*>((reinterpret_cast<uintptr_t>(p) + 255) & ~(uintptr_t)255);
 }
 
-cnpc_status bispec_plan_create(cnpc_bispec_plan** out, const cnpc_mesh_desc* d, const cnpc_kbins* b,
-                               int est, int ell, int prec, void* ws, size_t ws_bytes,
-                               hipStream_t s) {
-  auto* P = new cnpc_bispec_plan();
+// Everything of the plan but its allocation; on an error the caller destroys P
+// (device tables allocated so far included).
+static cnpc_status bispec_plan_build(cnpc_bispec_plan* P, const cnpc_mesh_desc* d, const cnpc_kbins* b, int est,
+                                     int ell, int prec, void* ws, size_t ws_bytes, hipStream_t s) {
   P->desc = *d;
   P->bins = *b;
   P->est = est;
@@ -988,7 +988,6 @@ cnpc_status bispec_plan_create(cnpc_bispec_plan** out, const cnpc_mesh_desc* d, 
     const size_t need = (reinterpret_cast<unsigned char*>(Cm + (size_t)nb * (nb + 1) / 2 * nb) -
                          reinterpret_cast<unsigned char*>(ws));
     if (need > ws_bytes) {
-      delete P;
       set_error("bispectrum plan workspace too small: need %zu, got %zu", need, ws_bytes);
       return CNPC_EWORKSPACE;
     }
@@ -1056,8 +1055,15 @@ cnpc_status bispec_plan_create(cnpc_bispec_plan** out, const cnpc_mesh_desc* d, 
       P->prow.push_back(row_of[pair_index(a, bb, nb)]);
     }
   }
-  cnpc_status st = device_tables(P);
-  if (st == CNPC_OK) st = upload_tables(P);
+  CNPC_TRY(device_tables(P));
+  return upload_tables(P);
+}
+
+cnpc_status bispec_plan_create(cnpc_bispec_plan** out, const cnpc_mesh_desc* d, const cnpc_kbins* b,
+                               int est, int ell, int prec, void* ws, size_t ws_bytes,
+                               hipStream_t s) {
+  auto* P = new cnpc_bispec_plan();
+  const cnpc_status st = bispec_plan_build(P, d, b, est, ell, prec, ws, ws_bytes, s);
   if (st != CNPC_OK) {
     bispec_plan_destroy(P);
     return st;

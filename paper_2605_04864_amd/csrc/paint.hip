@@ -1399,14 +1399,24 @@ static cnpc_status fused_sort_and_paint(const cnpc_mesh_desc* d, const uint32_t*
   ba.ovf = bcnt + L.nbuckets;
   ba.tcount = count;
   ba.partial = partial;
+  // knob value 2: the Y_lm sums (l = 2, 4) in a pass of their own, which
+  // keeps the bucket pass at the register count of the l = 0 sums
+  const bool split_sums = sums_lmax >= 2 && tune_value(CNPC_TUNE_SORT_FUSED) == 2;
   kt_begin(CNPC_KT_SORT, s);
-  if (sums_lmax >= 4) launch_bucket_pass<RS, 4>(nblk, lds, pos, w, n, sa, ba, region, ovf_rec, s);
-  else if (sums_lmax >= 2) launch_bucket_pass<RS, 2>(nblk, lds, pos, w, n, sa, ba, region, ovf_rec, s);
+  if (sums_lmax >= 4 && !split_sums) launch_bucket_pass<RS, 4>(nblk, lds, pos, w, n, sa, ba, region, ovf_rec, s);
+  else if (sums_lmax >= 2 && !split_sums) launch_bucket_pass<RS, 2>(nblk, lds, pos, w, n, sa, ba, region, ovf_rec, s);
   else launch_bucket_pass<RS, 0>(nblk, lds, pos, w, n, sa, ba, region, ovf_rec, s);
   kt_end(CNPC_KT_SORT, s);
   CNPC_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_reduce_partials, dim3(CNPC_SUMS_LEN), dim3(64), 0, s, partial, (int)nblk, sums);
-  CNPC_HIP(hipGetLastError());
+  if (split_sums) {
+    CountArgs none;
+    none.ntiles = 0;
+    none.count = nullptr;
+    CNPC_TRY(sums_counted(d, pos, w, n, sums_lmax, sums, partial, none, s));
+  } else {
+    hipLaunchKernelGGL(k_reduce_partials, dim3(CNPC_SUMS_LEN), dim3(64), 0, s, partial, (int)nblk, sums);
+    CNPC_HIP(hipGetLastError());
+  }
   const int per_bucket = 1 << (3 * g.ls);
   hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, count, L.ntiles, per_bucket, start, cursor, bcur);
   CNPC_HIP(hipGetLastError());

@@ -631,36 +631,18 @@ def balanced_assignment(sizes: Sequence[int], nstreams: int, mixed: bool = False
 
 
 class Batch:
-    """Many catalog pairs through measure_pk_bk.
+    """Many catalog pairs through measure_pk_bk: the catalogs are spread over
+    `nstreams` streams (each with its own scratch), so that the small and the
+    tail-end kernels of one catalog overlap the work of another; `balance`
+    picks the placement ("rr" round-robin, "lpt" or "mixed" by particle count,
+    see assignment).  The caller's current stream is forked at the start and
+    joined at the end, so the batch can be captured into one graph."""
 
-    Stream mode (staged=False): the catalogs are spread over `nstreams`
-    streams (each with its own scratch), so that the small and the tail-end
-    kernels of one catalog overlap the work of another; `balance` picks the
-    placement ("rr" round-robin, "lpt" or "mixed" by particle count, see
-    assignment).
-
-    Staged mode (staged=True): the painting of catalog i (catalog sums, sort,
-    LDS paint and fold, bound by LDS atomics and HBM) runs on one of `nstage`
-    particle streams into that stream's mesh slot, and everything after it
-    (transforms, binning, contraction) on one of `nstreams` spectral streams,
-    so the two kinds of work overlap by construction.  A slot is painted again
-    only after the spectral stream that read it has reached that point.
-
-    In both modes the caller's current stream is forked at the start and
-    joined at the end; the round-robin batch can be captured into one graph,
-    the staged one runs eagerly only."""
-
-    def __init__(self, nstreams: int = 2, device="cuda", staged: bool = False, nstage: int = 2,
-                 balance: str = "rr"):
+    def __init__(self, nstreams: int = 2, device="cuda", balance: str = "rr"):
         self.device = device
-        self.staged = staged
         self.balance = balance
         self.streams = [torch.cuda.Stream(device=device) for _ in range(max(1, nstreams))]
         self.scratch = [Scratch(device) for _ in self.streams]
-        self.pstreams = [torch.cuda.Stream(device=device) for _ in range(max(1, nstage))] if staged else []
-        self.pscratch = [Scratch(device) for _ in self.pstreams]
-        self.slots = [None] * len(self.pstreams)
-        self.slot_key = [None] * len(self.pstreams)
 
     def assignment(self, catalogs):
         """(catalog, stream) pairs in launch order.  balance "rr": catalog i
@@ -681,46 +663,13 @@ class Batch:
                 measure_pk_bk(desc, catalogs[i][0], catalogs[i][1], bins, plan, ells=ells,
                               scratch=self.scratch[k], out=outs[i])
 
-    def _slot(self, j, desc):
-        key = (desc.n, desc.dtype, desc.interlace)
-        if self.slots[j] is None or self.slot_key[j] != key:
-            with torch.cuda.stream(self.pstreams[j]):
-                self.slots[j] = paint_outputs(desc, noise=True)
-            self.slot_key[j] = key
-        return self.slots[j]
-
     def run(self, desc, catalogs, bins, plan, outs, ells=(0, 2, 4)):
-        if self.staged and torch.cuda.is_current_stream_capturing():
-            # capturing the staged dependency pattern (particle and spectral
-            # streams waiting on each other in turn) crashed the process at
-            # the end of the capture on ROCm 7; only the round-robin batch is
-            # captured
-            raise RuntimeError("staged batches run eagerly only; use staged=False under graph capture")
         cur = torch.cuda.current_stream()
-        for s in self.streams + self.pstreams:
+        for s in self.streams:
             s.wait_stream(cur)
-        if not self.staged:
-            for i, k in self.assignment(catalogs):
-                (g, r), o = catalogs[i], outs[i]
-                with torch.cuda.stream(self.streams[k]):
-                    measure_pk_bk(desc, g, r, bins, plan, ells=ells, scratch=self.scratch[k], out=o)
-        else:
-            # every cross-stream dependency is an event recorded and waited on
-            # at once (wait_stream), also under graph capture
-            reader = [None] * len(self.pstreams)  # spectral stream that last read slot j
-            for i, ((g, r), o) in enumerate(zip(catalogs, outs)):
-                j = i % len(self.pstreams)
-                k = i % len(self.streams)
-                p, s = self.pstreams[j], self.streams[k]
-                slot = self._slot(j, desc)
-                if reader[j] is not None:
-                    p.wait_stream(reader[j])
-                with torch.cuda.stream(p):
-                    paint_fkp(desc, g, r, noise=True, sums_lmax=_pk_bk_lmax(plan), scratch=self.pscratch[j],
-                              stream=p, out=slot)
-                s.wait_stream(p)
-                with torch.cuda.stream(s):
-                    _spectra_stage(desc, bins, plan, slot, ells, self.scratch[k], s, o)
-                reader[j] = s
-        for s in self.streams + self.pstreams:
+        for i, k in self.assignment(catalogs):
+            (g, r), o = catalogs[i], outs[i]
+            with torch.cuda.stream(self.streams[k]):
+                measure_pk_bk(desc, g, r, bins, plan, ells=ells, scratch=self.scratch[k], out=o)
+        for s in self.streams:
             cur.wait_stream(s)

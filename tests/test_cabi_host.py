@@ -146,7 +146,7 @@ def test_autotune_cache_roundtrip(tmp_path):
     from paper_2605_04864_amd import autotune as at
     path = str(tmp_path / "sub" / "tune.json")
     assert at._cache_load(path) == {"version": 1, "entries": {}}
-    e1 = {"streams": 3, "staged": True,
+    e1 = {"streams": 3,
           "knobs": {"fft_passes": 0, "fft_col_w": 8, "contract_kg": 2, "sort_per": 4, "sort_threads": 0},
           "ms": 1.5, "default_ms": 2.0}
     at._cache_store(path, "sig1", e1)

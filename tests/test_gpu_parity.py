@@ -241,6 +241,15 @@ def test_paint_fkp_matches_separate_calls(n, weights, dtype):
             autotune.reset_knobs()
         for a, b in ((norms, norms3), (gs, gs3), (rs, rs3), (delta, delta3), (nmesh, nmesh3)):
             assert np.array_equal(host(a), host(b))
+        # l = 0 sums in the bucket pass, Y_lm sums in their own pass: the sums of
+        # that pass equal the separate calls' bit for bit
+        autotune.set_knobs({"sort_fused": 2})
+        try:
+            norms4, delta4, nmesh4, gs4, rs4 = pl.paint_fkp(d, gt, rt, gwt, rwt, noise=True)
+        finally:
+            autotune.reset_knobs()
+        for a, b in ((norms, norms4), (gs, gs4), (rs, rs4), (delta, delta4), (nmesh, nmesh4)):
+            assert np.array_equal(host(a), host(b))
     # l = 0 sums only: the same w sums, meshes and l = 0 normalisations, zero Y_lm sums
     norms0, delta0, nmesh0, gs0, rs0 = pl.paint_fkp(d, gt, rt, gwt, rwt, noise=True, sums_lmax=0)
     for a, b in ((delta2, delta0), (nmesh2, nmesh0)):
@@ -419,16 +428,16 @@ def test_measure_bk_reduced_grid_vs_oracle(est, ell, prec):
     assert rel(host(res["value"]), ora[key]) < tol
 
 
-_STAGED_SKIP = pytest.mark.skip(reason="capturing a staged batch crashed the process at the end of the "
-                                        "capture; Batch.run now refuses staged batches under capture")
+_STAGED_SKIP = pytest.mark.skip(reason="the staged batch mode (painting and spectra on separate streams) was "
+                                        "removed: never faster than the round-robin batch, and capturing it "
+                                        "crashed the process at the end of the capture (cause not found)")
 
 
 @pytest.mark.parametrize("nstreams,staged", [(1, False), (3, False), pytest.param(2, True, marks=_STAGED_SKIP),
                                              pytest.param(1, True, marks=_STAGED_SKIP)])
 def test_graph_replay_matches_eager(nstreams, staged):
-    """The batch captured as one graph (catalogs spread over nstreams streams,
-    or painting and spectra on separate streams) gives the eager single-stream
-    results on every replay."""
+    """The batch captured as one graph (catalogs spread over nstreams streams)
+    gives the eager single-stream results on every replay."""
     n, box = 32, 1000.0
     bins = cn.kbins(0.0, 0.012, 4)
     d = cn.mesh_desc(n, box, assign=L.TSC, interlace=True, dtype=L.F32, observer=OBS)
@@ -440,7 +449,8 @@ def test_graph_replay_matches_eager(nstreams, staged):
              "bk": torch.empty((3, plan.nconf), dtype=torch.float64, device="cuda")} for _ in cats]
     for (g, r), o in zip(cats, outs):
         pl.measure_pk_bk(d, g, r, bins, plan, scratch=sc, out=o)
-    batch = pl.Batch(nstreams, staged=staged)
+    assert not staged
+    batch = pl.Batch(nstreams)
 
     def step():
         batch.run(d, cats, bins, plan, outs)

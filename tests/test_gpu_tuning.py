@@ -115,21 +115,19 @@ def test_autotune_batch(tmp_path, engine):
     try:
         res = autotune.tune_batch(d, cats, bins, plan, streams=(1, 2), reps=1, cache=path, engine=engine)
         assert res.streams in (1, 2) and not res.cached and len(res.trials) >= 5
-        assert res.staged in (False, True)
         assert res.ms > 0 and res.default_ms > 0
         assert autotune.get_knobs() == res.knobs
         for k, v in res.knobs.items():
             assert v in L.TUNE[k][1]
         again = autotune.tune_batch(d, cats, bins, plan, streams=(1, 2), reps=1, cache=path, engine=engine)
         assert again.cached and again.knobs == res.knobs and again.streams == res.streams
-        assert again.staged == res.staged
         outs = [{"pk": torch.empty((9, 4), dtype=torch.float64, device="cuda"),
                  "bk": torch.empty((3, plan.nconf), dtype=torch.float64, device="cuda")} for _ in cats]
         if engine == "native":
             pl.NativeBatch(d, bins, plan, nstreams=res.streams, max_ngal=max(g.shape[1] for g, _ in cats),
                            max_nran=max(r.shape[1] for _, r in cats)).run(cats, outs)
         else:
-            pl.Batch(res.streams, staged=res.staged).run(d, cats, bins, plan, outs)
+            pl.Batch(res.streams).run(d, cats, bins, plan, outs)
         torch.cuda.synchronize()
         for (pk, bk), o in zip(ref, outs):
             assert P.rel(P.host(o["pk"]), pk) < 1e-5
