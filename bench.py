@@ -374,6 +374,11 @@ def single_config(args):
     t0 = time.time()
     g = synthcat.lognormal_catalog(spec.ngal, spec.boxsize, 1000 * args.config)
     r = synthcat.random_catalog(spec.nran, 1000 * args.config + 1)
+    import hashlib
+    hs = hashlib.sha256()
+    hs.update(np.ascontiguousarray(g).tobytes())
+    hs.update(np.ascontiguousarray(r).tobytes())
+    g_sha = hs.hexdigest()
     log(args, f"generated c{args.config} catalogs in {time.time() - t0:.1f}s")
     gd, rd = torch.from_numpy(g).to(dev), torch.from_numpy(r).to(dev)
     del g, r
@@ -460,6 +465,7 @@ def single_config(args):
             continue
         ref = outs[(name, "f64")]
         errors.setdefault(name, {})[form] = {k: rel_err(o[k], ref[k]) for k in o}
+    oracle_err = oracle_fixture_errors(args.config, g_sha, outs)
     line = {
         "metric": "seconds per catalog",
         "config": {"workload": spec.name, "ngal": spec.ngal, "nran": spec.nran, "nmesh": spec.nmesh,
@@ -469,8 +475,32 @@ def single_config(args):
         "reps": args.reps,
         "seconds_per_catalog": times,
         "rel_error_vs_fp64": errors,
+        "rel_error_vs_oracle": oracle_err,
     }
     print(json.dumps(line))
+
+
+def oracle_fixture_errors(config, sha, outs):
+    """Errors of every form against the stored FP64 oracle outputs of this
+    catalog (tests/golden/oracle_c2.json, oracle_c3.json, written by the
+    oracle alone), when they exist and their catalog digest matches."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden", f"oracle_c{config}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        fx = json.load(fh)
+    if fx.get("catalog_sha256") != sha:
+        return {"error": "catalog digest differs from the fixture's"}
+    res = {}
+    for (name, form), o in outs.items():
+        if name == "pk" and "pk" in fx:
+            res.setdefault(name, {})[form] = {k: rel_err(o[k], fx["pk"][k]) for k in o if k in fx["pk"]}
+        key = {"B0": "B0", "B2": "B2", "B202": "BB202"}.get(name)
+        if key and key in fx:
+            raw, shot = np.asarray(fx[key]["raw"]), np.asarray(fx[key]["shot"])
+            res.setdefault(name, {})[form] = {"raw": rel_err(o["raw"], raw), "shot": rel_err(o["shot"], shot),
+                                              "value": rel_err(o["value"], raw - shot)}
+    return res
 
 
 def ktimer_read(L):

@@ -542,10 +542,11 @@ __global__ void __launch_bounds__(256, 2) k_contract_mfma_fp(const T* __restrict
   const int zero_row = nf;
   for (int i = threadIdx.x; i < ROW; i += blockDim.x) tile[zero_row * ROW + i] = T(0);
   const int q = lane / TM, r = lane % TM;
+  const int mbase = (int)blockIdx.y * (4 / kg_n) * MTW;  // first m-tile of this workgroup row
   int offa[MTW], offb[MTW];
 #pragma unroll
   for (int i = 0; i < MTW; ++i) {
-    const int p = (mg * MTW + i) * TM + r;
+    const int p = (mbase + mg * MTW + i) * TM + r;
     int a = zero_row, bb = zero_row;
     if (p < npairs && pairs) {
       a = (int)(pairs[p] & 0xffffu);
@@ -624,7 +625,7 @@ __global__ void __launch_bounds__(256, 2) k_contract_mfma_fp(const T* __restrict
   double* out = partial + ((int64_t)blockIdx.x * kg_n + kg) * npairs * cc.ncols;
 #pragma unroll
   for (int i = 0; i < MTW; ++i) {
-    const int mt = mg * MTW + i;
+    const int mt = mbase + mg * MTW + i;
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
       const int j = nt * TM + r;
@@ -638,19 +639,20 @@ __global__ void __launch_bounds__(256, 2) k_contract_mfma_fp(const T* __restrict
   }
 }
 
-// MTW in {1, 2, 4, 8} (FP32: at most 4 accumulator tiles per wave; FP64: 16)
+// MTW a power of two with MTW x NT <= 4 (FP32) or 16 (FP64) accumulator tiles
+// per wave; ny workgroup rows split the m-tiles when one row cannot hold them
 template <typename T, int NT, int MTW>
-static cnpc_status launch_mfma_fp_mtw(int mtw, int kg, const T* fields, int64_t npts, int nf, int nshell,
+static cnpc_status launch_mfma_fp_mtw(int mtw, int kg, int ny, const T* fields, int64_t npts, int nf, int nshell,
                                       int npairs, const ContractCols& cc, const uint32_t* pairs, double* partial,
                                       size_t lds, hipStream_t s) {
   if (mtw <= MTW) {
-    hipLaunchKernelGGL((k_contract_mfma_fp<T, MTW, NT>), dim3(CONTRACT_BLOCKS), dim3(256), lds, s, fields, npts,
-                       nf, nshell, npairs, kg, cc, pairs, partial);
+    hipLaunchKernelGGL((k_contract_mfma_fp<T, MTW, NT>), dim3(CONTRACT_BLOCKS, (unsigned)ny), dim3(256), lds, s,
+                       fields, npts, nf, nshell, npairs, kg, cc, pairs, partial);
     CNPC_HIP(hipGetLastError());
     return CNPC_OK;
   }
-  if constexpr (MTW < 8 && (sizeof(T) == 8 ? MTW * 2 * NT <= 16 : MTW * 2 * NT <= 4))
-    return launch_mfma_fp_mtw<T, NT, MTW * 2>(mtw, kg, fields, npts, nf, nshell, npairs, cc, pairs, partial,
+  if constexpr (sizeof(T) == 8 ? MTW * 2 * NT <= 16 : MTW * 2 * NT <= 4)
+    return launch_mfma_fp_mtw<T, NT, MTW * 2>(mtw, kg, ny, fields, npts, nf, nshell, npairs, cc, pairs, partial,
                                               lds, s);
   set_error("MFMA contraction: no kernel for %d tiles per wave", mtw);
   return CNPC_EUNSUPPORTED;
@@ -667,18 +669,21 @@ cnpc_status contract_mfma_fp(const T* fields, int64_t npts, int nf, int nshell, 
     set_error("MFMA contraction: too many columns (%d)", cc.ncols);
     return CNPC_EUNSUPPORTED;
   }
-  // the most point groups KG whose pair groups fit MAXT tiles per wave; the
-  // m-tiles per wave rounded up to a power of two (at most 8)
-  int kg = 4, mtw = 0;
+  // the most point groups KG whose pair groups fit MAXT tiles per wave (m-tiles
+  // per wave rounded up to a power of two); when even KG = 1 does not fit,
+  // ny workgroup rows of 4 pair groups x the largest MTW share the m-tiles
+  int kg = 4, mtw = 0, ny = 1;
   for (; kg >= 1; kg >>= 1) {
     const int need = (mtiles + (4 / kg) - 1) / (4 / kg);
     mtw = 1;
     while (mtw < need) mtw <<= 1;
-    if (mtw <= 8 && mtw * ntiles <= MAXT) break;
+    if (mtw * ntiles <= MAXT) break;
   }
   if (kg < 1) {
-    set_error("MFMA contraction: %d pair tiles x %d column tiles do not fit", mtiles, ntiles);
-    return CNPC_EUNSUPPORTED;
+    kg = 1;
+    mtw = 1;
+    while (2 * mtw * ntiles <= MAXT) mtw <<= 1;
+    ny = (mtiles + 4 * mtw - 1) / (4 * mtw);
   }
   const size_t lds = sizeof(T) * (size_t)(nf + 1) * (MP_KC + (sizeof(T) == 4 ? 4 : 2));
   if (lds > lds_limit()) {
@@ -688,12 +693,12 @@ cnpc_status contract_mfma_fp(const T* fields, int64_t npts, int nf, int nshell, 
   cnpc_status st;
   kt_begin(CNPC_KT_CONTRACT, s);
   if (ntiles == 1) {
-    st = launch_mfma_fp_mtw<T, 1, 1>(mtw, kg, fields, npts, nf, nshell, npairs, cc, pairs, partial, lds, s);
+    st = launch_mfma_fp_mtw<T, 1, 1>(mtw, kg, ny, fields, npts, nf, nshell, npairs, cc, pairs, partial, lds, s);
   } else if (ntiles == 2) {
-    st = launch_mfma_fp_mtw<T, 2, 1>(mtw, kg, fields, npts, nf, nshell, npairs, cc, pairs, partial, lds, s);
+    st = launch_mfma_fp_mtw<T, 2, 1>(mtw, kg, ny, fields, npts, nf, nshell, npairs, cc, pairs, partial, lds, s);
   } else {
     if constexpr (sizeof(T) == 8)
-      st = launch_mfma_fp_mtw<T, 3, 1>(mtw, kg, fields, npts, nf, nshell, npairs, cc, pairs, partial, lds, s);
+      st = launch_mfma_fp_mtw<T, 3, 1>(mtw, kg, ny, fields, npts, nf, nshell, npairs, cc, pairs, partial, lds, s);
     else
       st = CNPC_EUNSUPPORTED;
   }
