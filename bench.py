@@ -202,6 +202,7 @@ def main():
     step()  # eager pass: plans, twiddles and scratch reach their final size
     torch.cuda.synchronize()
     eager = [(o["pk"].clone(), o["bk"].clone()) for o in outs]
+    vs_oracle = smallest_mock_vs_oracle(mocks, sizes, eager, args.mocks)
 
     ntot = int(np.sum(sizes[: args.mocks]) * 11)
     # contraction rows: the shell pairs (j, k) of the kept configurations
@@ -275,13 +276,19 @@ def main():
         pl.measure_pk_bk(d64, g, r, bins, plan64, scratch=sc64)  # warm
         torch.cuda.synchronize()
         t = time.perf_counter()
+        res64 = {}
         for k in pick:
             g, r = gpu_mocks[k]
-            pl.measure_pk_bk(d64, g, r, bins, plan64, scratch=sc64)
+            res64[k] = pl.measure_pk_bk(d64, g, r, bins, plan64, scratch=sc64)
         torch.cuda.synchronize()
         per = (time.perf_counter() - t) / len(pick)
         fp64 = {"catalogs_per_s": 1.0 / per, "mocks_timed": [int(sizes[k]) for k in pick],
                 "speedup_fp32_batched": value * per}
+        kmin = int(np.argmin(sizes[: args.mocks]))
+        if kmin in res64:
+            e64 = smallest_mock_vs_oracle(mocks, sizes, {kmin: (res64[kmin]["pk"], res64[kmin]["bk"])},
+                                          args.mocks)
+            fp64["rel_error_vs_oracle"] = e64
         del sc64
     cpu = None if args.no_cpu else cpu_baseline(mocks, sizes, log=lambda *m: log(args, *m),
                                                 workers=args.cpu_workers or None)
@@ -344,10 +351,34 @@ def main():
         "roofline": roof,
         "roofline_by_stage": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv)
                                   for kk, vv in v.items()} for k, v in stages.items()},
+        "rel_error_vs_oracle": vs_oracle,
         "fp64_plain": fp64,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))
+
+
+def smallest_mock_vs_oracle(mocks, sizes, eager, nmocks):
+    """Errors of the batch's outputs for its smallest mock against the stored
+    FP64 oracle outputs of that catalog (tests/golden/oracle_c4min.json,
+    written by the oracle alone), when the catalog digest matches."""
+    import hashlib
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden", "oracle_c4min.json")
+    k = int(np.argmin(sizes[:nmocks]))
+    if not os.path.exists(path) or k != int(np.argmin(sizes)):
+        return None
+    with open(path) as fh:
+        fx = json.load(fh)
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(mocks[k][0]).tobytes())
+    h.update(np.ascontiguousarray(mocks[k][1]).tobytes())
+    if h.hexdigest() != fx["catalog_sha256"]:
+        return {"error": "catalog digest differs from the fixture's"}
+    pk, bk = eager[k][0].cpu().numpy(), eager[k][1].cpu().numpy()
+    raw, shot = np.asarray(fx["B0"]["raw"]), np.asarray(fx["B0"]["shot"])
+    out = {f"P{l}": rel_err(pk[row], fx["pk"][f"P{l}"]) for row, l in enumerate((0, 2, 4))}
+    out.update({"B0_raw": rel_err(bk[0], raw), "B0_shot": rel_err(bk[1], shot), "B0": rel_err(bk[2], raw - shot)})
+    return {"mock_ng": int(sizes[k]), "errors": out}
 
 
 def rel_err(a, b):
