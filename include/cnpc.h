@@ -543,6 +543,10 @@ cnpc_status cnpc_ktimer_stop(double* ms_per_class, int64_t* launches_per_class);
  *                          (default) sums the tile blocks inside the z passes
  *                          of the de-interlacing transforms; 1 writes the
  *                          delta and N meshes and transforms them.
+ *   CNPC_TUNE_BUCKET       shape of the first sort step of unweighted catalogs
+ *                          (0: 1024 threads x 4 particles; 1: 1024 x 2 with
+ *                          the next chunk loaded during the current one; 2:
+ *                          512 x 4, likewise).
  * cnpc_tune_set rejects unknown knobs and values outside those ranges;
  * cnpc_tune_get returns the current value (-1 for an unknown knob). */
 #define CNPC_TUNE_FFT_PASSES 0
@@ -552,7 +556,8 @@ cnpc_status cnpc_ktimer_stop(double* ms_per_class, int64_t* launches_per_class);
 #define CNPC_TUNE_SORT_THREADS 4
 #define CNPC_TUNE_SORT_FUSED 5
 #define CNPC_TUNE_FOLD_FUSED 6
-#define CNPC_TUNE_COUNT 7
+#define CNPC_TUNE_BUCKET 7
+#define CNPC_TUNE_COUNT 8
 cnpc_status cnpc_tune_set(int32_t knob, int32_t value);
 int32_t cnpc_tune_get(int32_t knob);
 

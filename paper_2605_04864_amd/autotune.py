@@ -11,8 +11,11 @@ The setting is
   contract_kg  point groups per split-BF16 contraction workgroup (0: library's)
   sort_per     particles per thread of the sort scatter (0: library's)
   sort_threads threads per sort-scatter workgroup (0: library's)
+  sort_fused   how the catalog sums and the first sort step share reads (0, 1, 2)
+  fold_fused   fold inside the de-interlacing z passes (0) or meshes written (1)
+  bucket       shape of the first sort step (0, 1, 2)
 
-The last five are the library's tuning knobs (``cnpc_tune_set``); the search
+All but the stream count are the library's tuning knobs (``cnpc_tune_set``); the search
 is one coordinate-descent sweep in that order, each value timed with the
 others held at the best found so far, and a value replaces the incumbent only
 when it is faster by more than ``min_gain``.  Every setting gives results
@@ -32,7 +35,8 @@ from typing import Callable, Dict, List, Optional, Sequence, Tuple
 
 from . import _lib as L
 
-KNOB_ORDER = ("fft_passes", "fft_col_w", "contract_kg", "sort_per", "sort_threads", "sort_fused", "fold_fused")
+KNOB_ORDER = ("fft_passes", "fft_col_w", "contract_kg", "sort_per", "sort_threads", "sort_fused", "fold_fused",
+              "bucket")
 DEFAULT_STREAMS = 4
 
 

@@ -499,7 +499,7 @@ cnpc_status contract_mfma(const float* fields, int64_t npts, int nf, int nshell,
 // register v of lane l is D[row(v, l)][l % TM]: FP32 32 x 32 row 8 (v / 4) +
 // 4 (l / 32) + v % 4, FP64 16 x 16 row 4 v + l / 16.  The pair products X_a X_b are
 // formed in the field type; the FP32 accumulators are added into FP64 ones
-// every chunk of points, so no FP32 sum runs over more than MP_KC / KG points.
+// every chunk of points, so no FP32 sum runs over more than KC / KG points.
 template <typename T>
 struct MfmaFp;
 template <>
@@ -521,20 +521,22 @@ struct MfmaFp<double> {
   static __device__ __forceinline__ int row(int v, int l) { return 4 * v + l / 16; }
 };
 
-constexpr int MP_KC = 256;  // grid points per LDS chunk (= threads per workgroup)
+// KC: grid points per LDS chunk, 256 or (many FP64 fields: three workgroups per
+// CU instead of one) 128; the 256 threads stage 256 / KC fields per point
 constexpr int MP_S = 8;     // consecutive points per lane per step
 
 // Wave w of the 4 is point group kg = w % KG of pair group mg = w / KG: it
 // owns the MTW m-tiles mg MTW .. and all NT n-tiles, for the steps kg, kg +
 // KG, ... of every chunk; one FP64 partial per (workgroup, point group).
-template <typename T, int MTW, int NT>
+template <typename T, int MTW, int NT, int KC>
 __global__ void __launch_bounds__(256, 2) k_contract_mfma_fp(const T* __restrict__ fields, int64_t npts, int nf,
                                                           int nshell, int npairs, int kg_n, ContractCols cc,
                                                           const uint32_t* __restrict__ pairs,
                                                           double* __restrict__ partial) {
   using M = MfmaFp<T>;
   constexpr int TM = M::TM, TK = M::TK, NACC = M::NACC, STEP = TK * MP_S;
-  constexpr int ROW = MP_KC + (sizeof(T) == 4 ? 4 : 2);  // padded row (elements)
+  constexpr int ROW = KC + (sizeof(T) == 4 ? 4 : 2);  // padded row (elements)
+  constexpr int FS = 256 / KC;                            // fields staged per thread and pass
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* tile = reinterpret_cast<T*>(smem_raw);  // [nf + 1][ROW]
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -581,19 +583,20 @@ __global__ void __launch_bounds__(256, 2) k_contract_mfma_fp(const T* __restrict
         acc[i][nt][v] = T(0);
         tot[i][nt][v] = 0.0;
       }
-  const int64_t per_block = ((npts + gridDim.x - 1) / gridDim.x + MP_KC - 1) / MP_KC * MP_KC;
+  const int64_t per_block = ((npts + gridDim.x - 1) / gridDim.x + KC - 1) / KC * KC;
   const int64_t x0 = (int64_t)blockIdx.x * per_block;
   const int64_t x1 = min(npts, x0 + per_block);
-  for (int64_t xb = x0; xb < x1; xb += MP_KC) {
+  const int sp = threadIdx.x % KC, sf = threadIdx.x / KC;  // staged point, first field
+  for (int64_t xb = x0; xb < x1; xb += KC) {
     __syncthreads();
     {
-      const bool ok = xb + threadIdx.x < x1;
+      const bool ok = xb + sp < x1;
 #pragma unroll 8
-      for (int f = 0; f < nf; ++f)
-        tile[f * ROW + threadIdx.x] = ok ? fields[(int64_t)f * npts + xb + threadIdx.x] : T(0);
+      for (int f = sf; f < nf; f += FS)
+        tile[f * ROW + sp] = ok ? fields[(int64_t)f * npts + xb + sp] : T(0);
     }
     __syncthreads();
-    for (int ks = kg * STEP; ks < MP_KC; ks += STEP * kg_n) {
+    for (int ks = kg * STEP; ks < KC; ks += STEP * kg_n) {
       T bv[NT][MP_S];
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt)
@@ -642,18 +645,22 @@ __global__ void __launch_bounds__(256, 2) k_contract_mfma_fp(const T* __restrict
 // MTW a power of two with MTW x NT <= 4 (FP32) or 16 (FP64) accumulator tiles
 // per wave; ny workgroup rows split the m-tiles when one row cannot hold them
 template <typename T, int NT, int MTW>
-static cnpc_status launch_mfma_fp_mtw(int mtw, int kg, int ny, const T* fields, int64_t npts, int nf, int nshell,
-                                      int npairs, const ContractCols& cc, const uint32_t* pairs, double* partial,
-                                      size_t lds, hipStream_t s) {
+static cnpc_status launch_mfma_fp_mtw(int mtw, int kg, int ny, int kc, const T* fields, int64_t npts, int nf,
+                                      int nshell, int npairs, const ContractCols& cc, const uint32_t* pairs,
+                                      double* partial, size_t lds, hipStream_t s) {
   if (mtw <= MTW) {
-    hipLaunchKernelGGL((k_contract_mfma_fp<T, MTW, NT>), dim3(CONTRACT_BLOCKS, (unsigned)ny), dim3(256), lds, s,
-                       fields, npts, nf, nshell, npairs, kg, cc, pairs, partial);
+    if (kc == 128)
+      hipLaunchKernelGGL((k_contract_mfma_fp<T, MTW, NT, 128>), dim3(CONTRACT_BLOCKS, (unsigned)ny), dim3(256), lds,
+                         s, fields, npts, nf, nshell, npairs, kg, cc, pairs, partial);
+    else
+      hipLaunchKernelGGL((k_contract_mfma_fp<T, MTW, NT, 256>), dim3(CONTRACT_BLOCKS, (unsigned)ny), dim3(256), lds,
+                         s, fields, npts, nf, nshell, npairs, kg, cc, pairs, partial);
     CNPC_HIP(hipGetLastError());
     return CNPC_OK;
   }
   if constexpr (sizeof(T) == 8 ? MTW * 2 * NT <= 16 : MTW * 2 * NT <= 4)
-    return launch_mfma_fp_mtw<T, NT, MTW * 2>(mtw, kg, ny, fields, npts, nf, nshell, npairs, cc, pairs, partial,
-                                              lds, s);
+    return launch_mfma_fp_mtw<T, NT, MTW * 2>(mtw, kg, ny, kc, fields, npts, nf, nshell, npairs, cc, pairs,
+                                              partial, lds, s);
   set_error("MFMA contraction: no kernel for %d tiles per wave", mtw);
   return CNPC_EUNSUPPORTED;
 }
@@ -685,7 +692,9 @@ cnpc_status contract_mfma_fp(const T* fields, int64_t npts, int nf, int nshell, 
     while (2 * mtw * ntiles <= MAXT) mtw <<= 1;
     ny = (mtiles + 4 * mtw - 1) / (4 * mtw);
   }
-  const size_t lds = sizeof(T) * (size_t)(nf + 1) * (MP_KC + (sizeof(T) == 4 ? 4 : 2));
+  // the 256-point chunk unless its staging tile would keep a CU to one workgroup
+  const int kc = sizeof(T) * (size_t)(nf + 1) * (256 + 2) > 56 * 1024 ? 128 : 256;
+  const size_t lds = sizeof(T) * (size_t)(nf + 1) * (kc + (sizeof(T) == 4 ? 4 : 2));
   if (lds > lds_limit()) {
     set_error("too many fields for the MFMA contraction tile (%d)", nf);
     return CNPC_EUNSUPPORTED;
@@ -693,12 +702,12 @@ cnpc_status contract_mfma_fp(const T* fields, int64_t npts, int nf, int nshell, 
   cnpc_status st;
   kt_begin(CNPC_KT_CONTRACT, s);
   if (ntiles == 1) {
-    st = launch_mfma_fp_mtw<T, 1, 1>(mtw, kg, ny, fields, npts, nf, nshell, npairs, cc, pairs, partial, lds, s);
+    st = launch_mfma_fp_mtw<T, 1, 1>(mtw, kg, ny, kc, fields, npts, nf, nshell, npairs, cc, pairs, partial, lds, s);
   } else if (ntiles == 2) {
-    st = launch_mfma_fp_mtw<T, 2, 1>(mtw, kg, ny, fields, npts, nf, nshell, npairs, cc, pairs, partial, lds, s);
+    st = launch_mfma_fp_mtw<T, 2, 1>(mtw, kg, ny, kc, fields, npts, nf, nshell, npairs, cc, pairs, partial, lds, s);
   } else {
     if constexpr (sizeof(T) == 8)
-      st = launch_mfma_fp_mtw<T, 3, 1>(mtw, kg, ny, fields, npts, nf, nshell, npairs, cc, pairs, partial, lds, s);
+      st = launch_mfma_fp_mtw<T, 3, 1>(mtw, kg, ny, kc, fields, npts, nf, nshell, npairs, cc, pairs, partial, lds, s);
     else
       st = CNPC_EUNSUPPORTED;
   }

@@ -418,7 +418,8 @@ __host__ __device__ constexpr size_t bucket_pass_lds(int per, int rs, int nbucke
   return (size_t)nt * per * (rs * 4 + 2) + (size_t)6 * nbuckets * 4 + 64 + (size_t)ltiles * 4;
 }
 
-template <int RS, int PER, int NT, int LMAX>
+// PF: the next chunk's particles are loaded while the current one is sorted
+template <int RS, int PER, int NT, int LMAX, bool PF>
 __global__ void __launch_bounds__(NT) k_bucket_pass(const uint32_t* __restrict__ pos, const float* __restrict__ w,
                                                     int64_t n, SumsArgs sa, BucketArgs ba,
                                                     Rec<RS>* __restrict__ region, Rec<RS>* __restrict__ ovf_out) {
@@ -441,21 +442,34 @@ __global__ void __launch_bounds__(NT) k_bucket_pass(const uint32_t* __restrict__
   for (int q = 0; q < CNPC_SUMS_LEN; ++q) acc[q] = 0.0;
   const double scale = sa.boxsize / 4294967296.0;
   const int bshift = 3 * ba.g.ls;
-  for (int64_t c0 = (int64_t)blockIdx.x * CH; c0 < n; c0 += (int64_t)gridDim.x * CH) {
+  const int64_t stride = (int64_t)gridDim.x * CH;
+  auto load_chunk = [&](int64_t c, Rec<RS>* dst) {
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int64_t i = c + (int64_t)k * NT + threadIdx.x;
+      if (i < n) {
+        dst[k].v[0] = pos[i];
+        dst[k].v[1] = pos[n + i];
+        dst[k].v[2] = pos[2 * n + i];
+        if constexpr (RS == 4) dst[k].v[3] = __float_as_uint(w[i]);
+      }
+    }
+  };
+  Rec<RS> rn[PF ? PER : 1];
+  if constexpr (PF) load_chunk((int64_t)blockIdx.x * CH, rn);
+  for (int64_t c0 = (int64_t)blockIdx.x * CH; c0 < n; c0 += stride) {
     Rec<RS> r[PER];
     int key[PER];
     __syncthreads();  // the previous chunk's LDS reads are done
     for (int t = threadIdx.x; t < ba.nbuckets; t += NT) hist[t] = 0u;
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      const int64_t i = c0 + (int64_t)k * NT + threadIdx.x;
-      key[k] = -1;
-      if (i < n) {
-        r[k].v[0] = pos[i];
-        r[k].v[1] = pos[n + i];
-        r[k].v[2] = pos[2 * n + i];
-        if constexpr (RS == 4) r[k].v[3] = __float_as_uint(w[i]);
-      }
+    for (int k = 0; k < PER; ++k) key[k] = -1;
+    if constexpr (PF) {
+#pragma unroll
+      for (int k = 0; k < PER; ++k) r[k] = rn[k];
+      if (c0 + stride < n) load_chunk(c0 + stride, rn);
+    } else {
+      load_chunk(c0, r);
     }
     __syncthreads();
     uint32_t rank[PER];
@@ -1346,16 +1360,46 @@ static cnpc_status sort_and_paint(const cnpc_mesh_desc* d, const uint32_t* pos, 
 // Catalog sums, tile histogram and both sort steps from one read of the
 // catalog (fused bucket pass), then the tile painting.  sums: CNPC_SUMS_LEN
 // doubles (device).
+// Bucket-pass shape: CNPC_TUNE_BUCKET 0 (default) 1024 threads, 4 (RS 3) or 2
+// (RS 4) particles per thread; 1: 1024 threads, 2 particles, next chunk
+// prefetched; 2: 512 threads, 4 particles, prefetched.  The prefetching forms
+// exist for unweighted catalogs with l = 0 or l <= 4 sums; the rest take 0.
+struct BucketShape {
+  int nt, per;
+  bool pf;
+};
+static BucketShape bucket_shape(int rs, int lmax) {
+  const int v = tune_value(CNPC_TUNE_BUCKET);
+  if (rs == 3 && (lmax == 0 || lmax >= 4)) {
+    if (v == 1) return {1024, 2, true};
+    if (v == 2) return {512, 4, true};
+  }
+  return {BUCKET_NT, bucket_per(rs), false};
+}
+
 template <int RS, int LMAX>
-static void launch_bucket_pass(unsigned nblk, size_t lds, const uint32_t* pos, const float* w, int64_t n,
-                               const SumsArgs& sa, const BucketArgs& ba, Rec<RS>* region, Rec<RS>* ovf_out,
-                               hipStream_t s) {
-  if constexpr (RS == 3)
-    hipLaunchKernelGGL((k_bucket_pass<3, 4, BUCKET_NT, LMAX>), dim3(nblk), dim3(BUCKET_NT), lds, s, pos, w, n, sa, ba,
-                       region, ovf_out);
-  else
-    hipLaunchKernelGGL((k_bucket_pass<4, 2, BUCKET_NT, LMAX>), dim3(nblk), dim3(BUCKET_NT), lds, s, pos, w, n, sa, ba,
-                       region, ovf_out);
+static void launch_bucket_pass(const BucketShape& b, unsigned nblk, size_t lds, const uint32_t* pos, const float* w,
+                               int64_t n, const SumsArgs& sa, const BucketArgs& ba, Rec<RS>* region,
+                               Rec<RS>* ovf_out, hipStream_t s) {
+  if constexpr (RS == 3) {
+    if constexpr (LMAX != 2) {
+      if (b.pf && b.nt == 1024) {
+        hipLaunchKernelGGL((k_bucket_pass<3, 2, 1024, LMAX, true>), dim3(nblk), dim3(1024), lds, s, pos, w, n, sa,
+                           ba, region, ovf_out);
+        return;
+      }
+      if (b.pf) {
+        hipLaunchKernelGGL((k_bucket_pass<3, 4, 512, LMAX, true>), dim3(nblk), dim3(512), lds, s, pos, w, n, sa, ba,
+                           region, ovf_out);
+        return;
+      }
+    }
+    hipLaunchKernelGGL((k_bucket_pass<3, 4, BUCKET_NT, LMAX, false>), dim3(nblk), dim3(BUCKET_NT), lds, s, pos, w, n,
+                       sa, ba, region, ovf_out);
+  } else {
+    hipLaunchKernelGGL((k_bucket_pass<4, 2, BUCKET_NT, LMAX, false>), dim3(nblk), dim3(BUCKET_NT), lds, s, pos, w, n,
+                       sa, ba, region, ovf_out);
+  }
 }
 
 template <typename T, int RS>
@@ -1373,11 +1417,16 @@ static cnpc_status fused_sort_and_paint(const cnpc_mesh_desc* d, const uint32_t*
   Rec<RS>* ovf_rec = reinterpret_cast<Rec<RS>*>(ws + L.off_ovf);
   double* partial = reinterpret_cast<double*>(ws + L.off_partial);
   const uint32_t cap = bucket_cap(n, L.nbuckets);  // <= L.cap
-  const int per = bucket_per(RS);
-  const int64_t ch = (int64_t)BUCKET_NT * per;
+  // knob value 2 of CNPC_TUNE_SORT_FUSED: the Y_lm sums (l = 2, 4) in a pass
+  // of their own, which keeps the bucket pass at the register count of the
+  // l = 0 sums
+  const bool split_sums = sums_lmax >= 2 && tune_value(CNPC_TUNE_SORT_FUSED) == 2;
+  const int lm = split_sums ? 0 : (sums_lmax >= 4 ? 4 : (sums_lmax >= 2 ? 2 : 0));
+  const BucketShape bs = bucket_shape(RS, lm);
+  const int64_t ch = (int64_t)bs.nt * bs.per;
   const unsigned nblk = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + ch - 1) / ch, BUCKET_BLOCKS_MAX));
   const int ltiles = L.ntiles <= LDS_TILES_MAX ? L.ntiles : 0;
-  const size_t lds = bucket_pass_lds(per, RS, L.nbuckets, BUCKET_NT, ltiles);
+  const size_t lds = bucket_pass_lds(bs.per, RS, L.nbuckets, bs.nt, ltiles);
   if (lds > lds_limit()) {
     set_error("bucket pass: %zu bytes of LDS exceed the workgroup limit", lds);
     return CNPC_EUNSUPPORTED;
@@ -1399,13 +1448,10 @@ static cnpc_status fused_sort_and_paint(const cnpc_mesh_desc* d, const uint32_t*
   ba.ovf = bcnt + L.nbuckets;
   ba.tcount = count;
   ba.partial = partial;
-  // knob value 2: the Y_lm sums (l = 2, 4) in a pass of their own, which
-  // keeps the bucket pass at the register count of the l = 0 sums
-  const bool split_sums = sums_lmax >= 2 && tune_value(CNPC_TUNE_SORT_FUSED) == 2;
   kt_begin(CNPC_KT_SORT, s);
-  if (sums_lmax >= 4 && !split_sums) launch_bucket_pass<RS, 4>(nblk, lds, pos, w, n, sa, ba, region, ovf_rec, s);
-  else if (sums_lmax >= 2 && !split_sums) launch_bucket_pass<RS, 2>(nblk, lds, pos, w, n, sa, ba, region, ovf_rec, s);
-  else launch_bucket_pass<RS, 0>(nblk, lds, pos, w, n, sa, ba, region, ovf_rec, s);
+  if (lm == 4) launch_bucket_pass<RS, 4>(bs, nblk, lds, pos, w, n, sa, ba, region, ovf_rec, s);
+  else if (lm == 2) launch_bucket_pass<RS, 2>(bs, nblk, lds, pos, w, n, sa, ba, region, ovf_rec, s);
+  else launch_bucket_pass<RS, 0>(bs, nblk, lds, pos, w, n, sa, ba, region, ovf_rec, s);
   kt_end(CNPC_KT_SORT, s);
   CNPC_HIP(hipGetLastError());
   if (split_sums) {
