@@ -546,7 +546,8 @@ cnpc_status cnpc_ktimer_stop(double* ms_per_class, int64_t* launches_per_class);
  *   CNPC_TUNE_BUCKET       shape of the first sort step of unweighted catalogs
  *                          (0: 1024 threads x 4 particles; 1: 1024 x 2 with
  *                          the next chunk loaded during the current one; 2:
- *                          512 x 4, likewise).
+ *                          512 x 4, likewise; 3: as 0 with at most half the
+ *                          persistent workgroups).
  * cnpc_tune_set rejects unknown knobs and values outside those ranges;
  * cnpc_tune_get returns the current value (-1 for an unknown knob). */
 #define CNPC_TUNE_FFT_PASSES 0

@@ -1362,19 +1362,22 @@ static cnpc_status sort_and_paint(const cnpc_mesh_desc* d, const uint32_t* pos, 
 // doubles (device).
 // Bucket-pass shape: CNPC_TUNE_BUCKET 0 (default) 1024 threads, 4 (RS 3) or 2
 // (RS 4) particles per thread; 1: 1024 threads, 2 particles, next chunk
-// prefetched; 2: 512 threads, 4 particles, prefetched.  The prefetching forms
-// exist for unweighted catalogs with l = 0 or l <= 4 sums; the rest take 0.
+// prefetched; 2: 512 threads, 4 particles, prefetched; 3: as 0 with at most
+// half the persistent workgroups.  The prefetching forms exist for unweighted
+// catalogs with l = 0 or l <= 4 sums; the rest take 0.
 struct BucketShape {
   int nt, per;
   bool pf;
+  int maxblk;  // persistent workgroups at most
 };
 static BucketShape bucket_shape(int rs, int lmax) {
   const int v = tune_value(CNPC_TUNE_BUCKET);
   if (rs == 3 && (lmax == 0 || lmax >= 4)) {
-    if (v == 1) return {1024, 2, true};
-    if (v == 2) return {512, 4, true};
+    if (v == 1) return {1024, 2, true, BUCKET_BLOCKS_MAX};
+    if (v == 2) return {512, 4, true, BUCKET_BLOCKS_MAX};
   }
-  return {BUCKET_NT, bucket_per(rs), false};
+  // 3: half the workgroups (half the tile-histogram flushes)
+  return {BUCKET_NT, bucket_per(rs), false, v == 3 ? BUCKET_BLOCKS_MAX / 2 : BUCKET_BLOCKS_MAX};
 }
 
 template <int RS, int LMAX>
@@ -1424,7 +1427,7 @@ static cnpc_status fused_sort_and_paint(const cnpc_mesh_desc* d, const uint32_t*
   const int lm = split_sums ? 0 : (sums_lmax >= 4 ? 4 : (sums_lmax >= 2 ? 2 : 0));
   const BucketShape bs = bucket_shape(RS, lm);
   const int64_t ch = (int64_t)bs.nt * bs.per;
-  const unsigned nblk = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + ch - 1) / ch, BUCKET_BLOCKS_MAX));
+  const unsigned nblk = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + ch - 1) / ch, bs.maxblk));
   const int ltiles = L.ntiles <= LDS_TILES_MAX ? L.ntiles : 0;
   const size_t lds = bucket_pass_lds(bs.per, RS, L.nbuckets, bs.nt, ltiles);
   if (lds > lds_limit()) {
