@@ -443,16 +443,17 @@ __global__ void __launch_bounds__(NT) k_bucket_pass(const uint32_t* __restrict__
   const double scale = sa.boxsize / 4294967296.0;
   const int bshift = 3 * ba.g.ls;
   const int64_t stride = (int64_t)gridDim.x * CH;
+  // c < n: indices past the end are clamped to the last particle, so the
+  // loads form straight-line code and are all in flight before the first use
+  // (a load under a branch is waited for before the next one is issued)
   auto load_chunk = [&](int64_t c, Rec<RS>* dst) {
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-      const int64_t i = c + (int64_t)k * NT + threadIdx.x;
-      if (i < n) {
-        dst[k].v[0] = pos[i];
-        dst[k].v[1] = pos[n + i];
-        dst[k].v[2] = pos[2 * n + i];
-        if constexpr (RS == 4) dst[k].v[3] = __float_as_uint(w[i]);
-      }
+      const int64_t i = min(c + (int64_t)k * NT + threadIdx.x, n - 1);
+      dst[k].v[0] = pos[i];
+      dst[k].v[1] = pos[n + i];
+      dst[k].v[2] = pos[2 * n + i];
+      if constexpr (RS == 4) dst[k].v[3] = __float_as_uint(w[i]);
     }
   };
   Rec<RS> rn[PF ? PER : 1];
@@ -583,15 +584,12 @@ __global__ void __launch_bounds__(NT) k_tile_pass(const Rec<RS>* __restrict__ re
   const int klo = b << bshift;
   Rec<RS> r[PER];
   int key[PER];
+  // cnt >= 1: clamped straight-line loads, all in flight before the first use
 #pragma unroll
-  for (int k = 0; k < PER; ++k) {
-    const int i = k * NT + threadIdx.x;
-    key[k] = -1;
-    if (i < cnt) {
-      r[k] = rin[i];
-      key[k] = tile_key(r[k].v[0], r[k].v[1], r[k].v[2], g) - klo;
-    }
-  }
+  for (int k = 0; k < PER; ++k) r[k] = rin[min(k * NT + (int)threadIdx.x, cnt - 1)];
+#pragma unroll
+  for (int k = 0; k < PER; ++k)
+    key[k] = k * NT + (int)threadIdx.x < cnt ? tile_key(r[k].v[0], r[k].v[1], r[k].v[2], g) - klo : -1;
   for (int t = threadIdx.x; t < R; t += NT) hist[t] = 0u;
   __syncthreads();
   uint32_t rank[PER];
