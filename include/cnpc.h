@@ -548,6 +548,11 @@ cnpc_status cnpc_ktimer_stop(double* ms_per_class, int64_t* launches_per_class);
  *                          the next chunk loaded during the current one; 2:
  *                          512 x 4, likewise; 3: as 0 with at most half the
  *                          persistent workgroups).
+ *   CNPC_TUNE_YLM_BASIS    FP32 Y_lm z passes of bands kz < 4 R (N = R^2 of
+ *                          the register passes): 0 (default) transforms
+ *                          delta R^-l r_z^j, j = 0..l, and forms every field
+ *                          of that l from these l + 1 spectra; 1 transforms
+ *                          each field (2l + 1 per l).
  * cnpc_tune_set rejects unknown knobs and values outside those ranges;
  * cnpc_tune_get returns the current value (-1 for an unknown knob). */
 #define CNPC_TUNE_FFT_PASSES 0
@@ -558,7 +563,8 @@ cnpc_status cnpc_ktimer_stop(double* ms_per_class, int64_t* launches_per_class);
 #define CNPC_TUNE_SORT_FUSED 5
 #define CNPC_TUNE_FOLD_FUSED 6
 #define CNPC_TUNE_BUCKET 7
-#define CNPC_TUNE_COUNT 8
+#define CNPC_TUNE_YLM_BASIS 8
+#define CNPC_TUNE_COUNT 9
 cnpc_status cnpc_tune_set(int32_t knob, int32_t value);
 int32_t cnpc_tune_get(int32_t knob);
 

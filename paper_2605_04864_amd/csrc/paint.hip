@@ -735,9 +735,10 @@ constexpr int PAINT32_THREADS = 1024;
 constexpr int PAINT32_OWN = (2 * BVOL + PAINT32_THREADS - 1) / PAINT32_THREADS;  // nodes per thread
 
 // 1-D stencil in 32-bit integer arithmetic (shift <= 28): same nodes and
-// weights as stencil_1d<float>.
+// weights as stencil_1d<float>, times `scale`, a power of two (scaling by it
+// is exact, so a scaled weight is bit for bit the scaled unscaled weight).
 template <int ASSIGN>
-__device__ __forceinline__ int stencil32(uint32_t p, int shift, int phase, float* wt) {
+__device__ __forceinline__ int stencil32(uint32_t p, int shift, int phase, float* wt, float scale = 1.0f) {
   const uint32_t one = 1u << shift, half = one >> 1;
   const int f = (int)(p & (one - 1u));
   const float inv = 1.0f / (float)one;
@@ -753,23 +754,23 @@ __device__ __forceinline__ int stencil32(uint32_t p, int shift, int phase, float
     }
     const float d = (float)dfix * inv;
     const float a = 0.5f - d, b = 0.5f + d;
-    wt[0] = 0.5f * a * a;
-    wt[1] = 0.75f - d * d;
-    wt[2] = 0.5f * b * b;
+    wt[0] = (0.5f * scale) * a * a;
+    wt[1] = __builtin_fmaf(-d, d * scale, 0.75f * scale);
+    wt[2] = (0.5f * scale) * b * b;
     return off - 1;
   } else {
     if (phase == 0) {
       const float d = (float)f * inv;
-      wt[0] = 1.0f - d;
-      wt[1] = d;
+      wt[0] = __builtin_fmaf(-d, scale, scale);
+      wt[1] = d * scale;
       return 0;
     }
     const bool up = f >= (int)half;
     const int off = up ? 0 : -1;
     const int dfix = up ? f - (int)half : f + (int)half;
     const float d = (float)dfix * inv;
-    wt[0] = 1.0f - d;
-    wt[1] = d;
+    wt[0] = __builtin_fmaf(-d, scale, scale);
+    wt[1] = d * scale;
     return off;
   }
 }
@@ -805,7 +806,7 @@ __global__ void __launch_bounds__(PAINT32_THREADS, 8) k_paint_tiles_u32(const Re
       const int bz = ((int)(pz >> shift) & 15) + 1;
       for (int ph = 0; ph < nphase; ++ph) {
         float wx[3], wy[3], wz[3];
-        const int ox = stencil32<ASSIGN>(px, shift, ph, wx);
+        const int ox = stencil32<ASSIGN>(px, shift, ph, wx, SCALE);  // x weights carry the 2^21 units
         const int oy = stencil32<ASSIGN>(py, shift, ph, wy);
         const int oz = stencil32<ASSIGN>(pz, shift, ph, wz);
         // node lz = bz + oz + iz sits at lz - 1 in its row, lz = 0 at 18
@@ -815,7 +816,7 @@ __global__ void __launch_bounds__(PAINT32_THREADS, 8) k_paint_tiles_u32(const Re
         for (int ix = 0; ix < NP; ++ix)
 #pragma unroll
           for (int iy = 0; iy < NP; ++iy) {
-            const float vxy = wx[ix] * wy[iy] * SCALE;
+            const float vxy = wx[ix] * wy[iy];
             const int o = ix * BW * BW + iy * BW;
 #pragma unroll
             for (int iz = 0; iz < NP; ++iz)

@@ -322,14 +322,183 @@ __global__ void __launch_bounds__(256, 3) k_zpass_ylm_rr(const T* __restrict__ d
   }
 }
 
+// r_z^J for a compile-time power J
+template <typename T, int J>
+__device__ __forceinline__ T zpow(T z) {
+  if constexpr (J == 0) return T(1);
+  else if constexpr (J == 1) return z;
+  else if constexpr (J == 2) return z * z;
+  else if constexpr (J == 3) return z * z * z;
+  else { const T z2 = z * z; return z2 * z2; }
+}
+
+// basis J of the row pair: transform of (d0, d1) r_z^J, split per row at the
+// kept kz = rank + R k2 (k2 < K2M): row 0 into g0[k2], row 1 into g1[k2]
+template <typename T, int R, int K2M, int J>
+__device__ __forceinline__ void zbasis(const T* d0, const T* d1, T rz0, T dz, int rank, int src, cx<T>* buf,
+                                       const cx<T>* tw, cx<T>* g0, cx<T>* g1) {
+  cx<T> v[R];
+#pragma unroll
+  for (int n2 = 0; n2 < R; ++n2) {
+    T za = rz0 + T(n2) * dz;
+    asm volatile("" : "+v"(za));
+    const T w = zpow<T, J>(za);
+    v[n2] = J == 0 ? cx<T>{d0[n2], d1[n2]} : cx<T>{d0[n2] * w, d1[n2] * w};
+  }
+  row_fft_rr<T, R, -1>(v, rank, buf, tw);
+  // lane k1 holds Z[k1 + R k2]; Z[N - k] sits in lane (R - k1) & (R - 1),
+  // register R - 1 - k2 (k1 > 0) or in this lane, register (R - k2) & (R - 1)
+#pragma unroll
+  for (int k2 = 0; k2 < K2M; ++k2) {
+    const cx<T> a = v[R - 1 - k2];
+    const cx<T> sh = {__shfl(a.x, src, R), __shfl(a.y, src, R)};
+    const cx<T> zm = cconj(rank ? sh : v[(R - k2) & (R - 1)]);
+    const cx<T> zk = v[k2];
+    const cx<T> dd = csub(zk, zm);
+    g0[k2] = cscale(cadd(zk, zm), T(0.5));
+    g1[k2] = cx<T>{T(0.5) * dd.y, T(-0.5) * dd.x};
+  }
+}
+
+// c0 g[b0] + c2 g[b0 + 2] + c4 g[b0 + 4] at one kz (bases past 4 have c = 0)
+template <typename T, int K2M, int B0>
+__device__ __forceinline__ cx<T> zcombine(const cx<T> (*g)[K2M], int k2, T c0, T c2, T c4) {
+  cx<T> r = cscale(g[B0][k2], c0);
+  r = cx<T>{r.x + c2 * g[B0 + 2][k2].x, r.y + c2 * g[B0 + 2][k2].y};
+  if constexpr (B0 + 4 <= 4) r = cx<T>{r.x + c4 * g[B0 + 4][k2].x, r.y + c4 * g[B0 + 4][k2].y};
+  return r;
+}
+
+// Register z-pass by powers of r_z (N = R^2, l <= 4, kz_keep <= K2M R).  Along
+// a row the weight of field (l, m, part) is the row constant times a
+// polynomial in r_z of degree l - m (ZPoly: c4 z^4 + c2 z^2 + c0, times z when
+// Q_lm is odd), and the transform is linear, so the field's row spectrum is
+// c4 G_{odd+4} + c2 G_{odd+2} + c0 G_odd with G_j the spectrum of
+// delta R^-l r_z^j.  Per l the l + 1 bases are transformed (two rows as one
+// complex sequence, split per row at the kept kz) and every field of that l is
+// formed from them: l + 1 transforms in place of 2l + 1 (local line of sight),
+// one transform for all fields (global line of sight, G_0 of delta itself).
+// Same outputs as k_zpass_ylm_rr up to rounding.
+template <typename T, int R, int K2M>
+__global__ void __launch_bounds__(256, 2) k_zpass_ylm_basis(const T* __restrict__ delta, cx<T>* __restrict__ out,
+                                                         FieldTable ft, int kz_keep, int64_t fstride, Geo g) {
+  constexpr int N = R * R;
+  constexpr int GR = 256 / R;  // row pairs per workgroup
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
+  load_twiddles<T, N, -1>(tw);
+  const int grp = threadIdx.x / R, rank = threadIdx.x % R;
+  cx<T>* buf = tw + N + grp * (R * (R + 1));
+  const int q = blockIdx.x * GR + grp;
+  const int ix = q / (N / 2), iy0 = 2 * (q - ix * (N / 2));
+  const T* r0 = delta + ((int64_t)ix * N + iy0) * N;
+  T d0[R], d1[R];
+  int pw = 0;
+#pragma unroll
+  for (int n2 = 0; n2 < R; ++n2) {
+    const int z = rank + R * n2;
+    d0[n2] = r0[z];
+    d1[n2] = r0[N + z];
+  }
+  const T rz0 = T(rank * g.h - g.obs[2]), dz = T(R * g.h);
+  const T rx = T(ix * g.h - g.obs[0]);
+  const T ry0 = T(iy0 * g.h - g.obs[1]), ry1 = T((iy0 + 1) * g.h - g.obs[1]);
+  const T rho0 = rx * rx + ry0 * ry0, rho1 = rx * rx + ry1 * ry1;
+  __syncthreads();
+  const int src = (R - rank) & (R - 1);
+  cx<T>* orow = out + ((int64_t)ix * N + iy0) * kz_keep;
+  cx<T> g0[5][K2M], g1[5][K2M];
+#pragma unroll
+  for (int j = 0; j < 5; ++j)
+#pragma unroll
+    for (int k2 = 0; k2 < K2M; ++k2) g0[j][k2] = g1[j][k2] = cx<T>{T(0), T(0)};
+  int have = -1;  // l of the bases held (a global line of sight needs G_0 once)
+  for (int f0 = 0; f0 < ft.nf;) {
+    const int l = ft.ell[f0];
+    int f1 = f0 + 1;
+    while (f1 < ft.nf && ft.ell[f1] == l) ++f1;
+    if (g.global_los ? have < 0 : have != l) {
+      if (!g.global_los && l != pw) {
+        if (l < pw) {
+#pragma unroll
+          for (int n2 = 0; n2 < R; ++n2) {
+            const int z = rank + R * n2;
+            d0[n2] = r0[z];
+            d1[n2] = r0[N + z];
+          }
+          pw = 0;
+        }
+        switch (l - pw) {
+          case 1: scale_rows<T, R, 1>(d0, d1, rz0, dz, rho0, rho1); break;
+          case 2: scale_rows<T, R, 2>(d0, d1, rz0, dz, rho0, rho1); break;
+          case 3: scale_rows<T, R, 3>(d0, d1, rz0, dz, rho0, rho1); break;
+          case 4: scale_rows<T, R, 4>(d0, d1, rz0, dz, rho0, rho1); break;
+          default: break;
+        }
+        pw = l;
+      }
+      const int jmax = g.global_los ? 0 : l;
+      zbasis<T, R, K2M, 0>(d0, d1, rz0, dz, rank, src, buf, tw, g0[0], g1[0]);
+      if (jmax >= 1) zbasis<T, R, K2M, 1>(d0, d1, rz0, dz, rank, src, buf, tw, g0[1], g1[1]);
+      if (jmax >= 2) zbasis<T, R, K2M, 2>(d0, d1, rz0, dz, rank, src, buf, tw, g0[2], g1[2]);
+      if (jmax >= 3) zbasis<T, R, K2M, 3>(d0, d1, rz0, dz, rank, src, buf, tw, g0[3], g1[3]);
+      if (jmax >= 4) zbasis<T, R, K2M, 4>(d0, d1, rz0, dz, rank, src, buf, tw, g0[4], g1[4]);
+      have = l;
+    }
+    for (int f = f0; f < f1; ++f) {
+      const int m = ft.m[f], p = ft.part[f];
+      ZPoly<T> a, b;
+      bool odd = false;
+      if (g.global_los) {
+        const T w = ylm_one<T>(l, m, p, T(g.los[0]), T(g.los[1]), T(g.los[2]));
+        a = b = ZPoly<T>{T(0), T(0), w};
+      } else {
+        const T s0 = cpow_part<T>(rx, ry0, m, p), s1 = cpow_part<T>(rx, ry1, m, p);
+        const SolidQ qc = solid_coef(l, m);
+        a = zpoly<T>(qc, rho0, s0);
+        b = zpoly<T>(qc, rho1, s1);
+        odd = qc.odd != 0;
+      }
+      cx<T>* o = orow + (int64_t)f * fstride;
+#pragma unroll
+      for (int k2 = 0; k2 < K2M; ++k2) {
+        const int k = rank + R * k2;
+        if (k < kz_keep) {
+          if (odd) {
+            o[k] = zcombine<T, K2M, 1>(g0, k2, a.c0, a.c2, a.c4);
+            o[kz_keep + k] = zcombine<T, K2M, 1>(g1, k2, b.c0, b.c2, b.c4);
+          } else {
+            o[k] = zcombine<T, K2M, 0>(g0, k2, a.c0, a.c2, a.c4);
+            o[kz_keep + k] = zcombine<T, K2M, 0>(g1, k2, b.c0, b.c2, b.c4);
+          }
+        }
+      }
+    }
+    f0 = f1;
+  }
+}
+
 template <typename T, int R>
 static cnpc_status zylm_rr(const T* delta, cx<T>* out, const FieldTable& ft, int kz, int64_t fstride,
                            const Geo& g, hipStream_t s) {
   constexpr int N = R * R, GR = 256 / R;
   const size_t lds = sizeof(cx<T>) * (N + (size_t)GR * R * (R + 1));
+  const dim3 grid(N * (N / 2) / GR);
+  // FP32 with kz_keep <= 4 R: powers of r_z (CNPC_TUNE_YLM_BASIS 1: one
+  // transform per field); FP64 and wider bands: one transform per field
+  const bool basis = kz <= 4 * R && tune_value(CNPC_TUNE_YLM_BASIS) != 1;
   kt_begin(CNPC_KT_ZR2C, s);
-  hipLaunchKernelGGL((k_zpass_ylm_rr<T, R>), dim3(N * (N / 2) / GR), dim3(256), lds, s, delta, out, ft, kz,
-                     fstride, g);
+  if constexpr (sizeof(T) == 4) {
+    if (basis && kz <= 2 * R)
+      hipLaunchKernelGGL((k_zpass_ylm_basis<T, R, 2>), grid, dim3(256), lds, s, delta, out, ft, kz, fstride, g);
+    else if (basis)
+      hipLaunchKernelGGL((k_zpass_ylm_basis<T, R, 4>), grid, dim3(256), lds, s, delta, out, ft, kz, fstride, g);
+    else
+      hipLaunchKernelGGL((k_zpass_ylm_rr<T, R>), grid, dim3(256), lds, s, delta, out, ft, kz, fstride, g);
+  } else {
+    (void)basis;
+    hipLaunchKernelGGL((k_zpass_ylm_rr<T, R>), grid, dim3(256), lds, s, delta, out, ft, kz, fstride, g);
+  }
   kt_end(CNPC_KT_ZR2C, s);
   CNPC_HIP(hipGetLastError());
   return CNPC_OK;

@@ -304,19 +304,29 @@ def test_ylm_fields(ell, dtype):
         assert rel(got[f], ref) < 10 * TOL[dtype] + 1e-7 * (dtype == L.F32)
 
 
-@pytest.mark.parametrize("n,band,dtype", [(64, 16, L.F64), (128, 32, L.F32), (256, 32, L.F32), (256, 64, L.F64)])
-def test_ylm_r2c_band(n, band, dtype):
+YLM_LOS = (0.3, -0.5, 0.812403840463596)
+
+
+# FP32 at N = 64 and 256 with bands kz < 2R and < 4R take the z-power-basis z
+# pass (l + 1 transforms per l); FP64, N = 128 and the band 128 at 256 take one
+# transform per field
+@pytest.mark.parametrize("n,band,dtype,ells,los", [
+    (64, 16, L.F64, (2, 4), None), (128, 32, L.F32, (2, 4), None), (256, 32, L.F32, (2, 4), None),
+    (256, 64, L.F64, (2, 4), None), (64, 16, L.F32, (1, 2, 3, 4), None), (256, 64, L.F32, (2, 4), None),
+    (256, 128, L.F32, (2, 4), None), (64, 16, L.F32, (1, 2, 3, 4), YLM_LOS),
+    (256, 32, L.F32, (2, 4), YLM_LOS)])
+def test_ylm_r2c_band(n, band, dtype, ells, los):
     """Y_lm-weighted band transforms (fused prologue z-pass + band column
     passes) against numpy FFTs of the explicitly weighted fields."""
     from oracle.ylm import ylm_racah
     box = 1000.0
-    d = cn.mesh_desc(n, box, dtype=dtype, observer=OBS)
+    d = cn.mesh_desc(n, box, dtype=dtype, observer=OBS, los=los)
     tdt = torch.float64 if dtype == L.F64 else torch.float32
     delta = np.random.default_rng(n + band).normal(size=(n, n, n))
-    got = pl.ylm_spectra(d, band, (2, 4), dev(delta, tdt))
-    rvec = osp.line_of_sight(n, box, OBS)
+    got = pl.ylm_spectra(d, band, ells, dev(delta, tdt))
+    rvec = osp.line_of_sight(n, box, OBS, los)
     idx = np.r_[0:band, n - band:n]
-    for ell in (2, 4):
+    for ell in ells:
         fields = [ylm_racah(ell, 0, rvec).real]
         for m in range(1, ell + 1):
             y = ylm_racah(ell, m, rvec)

@@ -54,7 +54,21 @@ def test_fft_band_knobs(n, band, setting):
 @pytest.mark.parametrize("n,band,dtype", [(64, 16, L.F64), (256, 32, L.F32)])
 def test_ylm_band_stockham_only(n, band, dtype):
     with knobs(fft_passes=1):
-        P.test_ylm_r2c_band(n, band, dtype)
+        P.test_ylm_r2c_band(n, band, dtype, (2, 4), None)
+
+
+@pytest.mark.parametrize("n,band,ells,los", [(256, 32, (2, 4), None), (64, 16, (1, 2, 3, 4), None),
+                                             (256, 32, (2, 4), P.YLM_LOS)])
+def test_ylm_band_per_field(n, band, ells, los):
+    """CNPC_TUNE_YLM_BASIS 1: one z transform per field in place of the
+    z-power bases."""
+    with knobs(ylm_basis=1):
+        P.test_ylm_r2c_band(n, band, L.F32, ells, los)
+
+
+def test_measure_pk_ylm_per_field():
+    with knobs(ylm_basis=1):
+        P.test_measure_pk_vs_oracle(64, L.TSC, True, L.F32)
 
 
 def test_measure_pk_stockham_only():
