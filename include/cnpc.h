@@ -550,9 +550,10 @@ cnpc_status cnpc_ktimer_stop(double* ms_per_class, int64_t* launches_per_class);
  *                          persistent workgroups).
  *   CNPC_TUNE_YLM_BASIS    FP32 Y_lm z passes of bands kz < 4 R (N = R^2 of
  *                          the register passes): 0 (default) transforms
- *                          delta R^-l r_z^j, j = 0..l, and forms every field
- *                          of that l from these l + 1 spectra; 1 transforms
- *                          each field (2l + 1 per l).
+ *                          delta R^-L r_z^j, j = 0..L, per parity class of l
+ *                          (L its largest l) and forms every field of the
+ *                          class from these L + 1 spectra (5 for l = 2, 4);
+ *                          1 transforms each field (2l + 1 per l).
  * cnpc_tune_set rejects unknown knobs and values outside those ranges;
  * cnpc_tune_get returns the current value (-1 for an unknown knob). */
 #define CNPC_TUNE_FFT_PASSES 0

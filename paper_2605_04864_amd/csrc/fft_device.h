@@ -151,22 +151,36 @@ __device__ __forceinline__ void dft_reg(cx<T>* v) {
   }
 }
 
+// Orders the LDS accesses of one wavefront around an exchange among its own
+// lanes: the LDS executes a wavefront's operations in issue order, so only the
+// compiler has to be kept from moving accesses across this point.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Length N = R * R transform of one sequence by a group of R lanes (rank =
 // lane within the group): on entry lane n1 holds x[n1 + R n2] in v[n2]; on
 // exit it holds X[n1 + R k2] in v[k2].  Two register DFTs with one LDS
 // transpose in between (buffer of R (R + 1) elements per group, padded so that
 // both the row writes and the column reads are bank-conflict free); tw is the
-// N-entry table W_N^t.  Contains two workgroup barriers: every lane of the
-// workgroup must call it.
-template <typename T, int R, int DIR>
+// N-entry table W_N^t.  WAVE = false: two workgroup barriers, every lane of the
+// workgroup must call it; WAVE = true: the group's buffer is its own and the
+// group lies within one wavefront (R divides 64), and the transpose is ordered
+// by wavefront-level syncs only (the caller has made tw visible).
+template <typename T, int R, int DIR, bool WAVE = false>
 __device__ __forceinline__ void row_fft_rr(cx<T>* v, int rank, cx<T>* buf, const cx<T>* tw) {
+  static_assert(!WAVE || 64 % R == 0, "a wavefront-synchronised group lies within one wavefront");
   dft_reg<T, R, DIR>(v);  // lane n1: Y[n1][k1] in v[k1]
 #pragma unroll
   for (int k1 = 0; k1 < R; ++k1) buf[k1 * (R + 1) + rank] = k1 == 0 ? v[k1] : cmul(v[k1], tw[rank * k1]);
-  __syncthreads();
+  if constexpr (WAVE) wave_lds_sync();
+  else __syncthreads();
 #pragma unroll
   for (int n1 = 0; n1 < R; ++n1) v[n1] = buf[rank * (R + 1) + n1];
-  __syncthreads();
+  if constexpr (WAVE) wave_lds_sync();
+  else __syncthreads();
   dft_reg<T, R, DIR>(v);
 }
 

@@ -345,7 +345,11 @@ __device__ __forceinline__ void zbasis(const T* d0, const T* d1, T rz0, T dz, in
     const T w = zpow<T, J>(za);
     v[n2] = J == 0 ? cx<T>{d0[n2], d1[n2]} : cx<T>{d0[n2] * w, d1[n2] * w};
   }
-  row_fft_rr<T, R, -1>(v, rank, buf, tw);
+  // an opaque lane index per call: keeps the twiddle reads of the bases from
+  // being merged into one register copy held across all of them
+  int lane = rank;
+  asm volatile("" : "+v"(lane));
+  row_fft_rr<T, R, -1, true>(v, lane, buf, tw);
   // lane k1 holds Z[k1 + R k2]; Z[N - k] sits in lane (R - k1) & (R - 1),
   // register R - 1 - k2 (k1 > 0) or in this lane, register (R - k2) & (R - 1)
 #pragma unroll
@@ -369,18 +373,20 @@ __device__ __forceinline__ cx<T> zcombine(const cx<T> (*g)[K2M], int k2, T c0, T
   return r;
 }
 
-// Register z-pass by powers of r_z (N = R^2, l <= 4, kz_keep <= K2M R).  Along
-// a row the weight of field (l, m, part) is the row constant times a
-// polynomial in r_z of degree l - m (ZPoly: c4 z^4 + c2 z^2 + c0, times z when
-// Q_lm is odd), and the transform is linear, so the field's row spectrum is
-// c4 G_{odd+4} + c2 G_{odd+2} + c0 G_odd with G_j the spectrum of
-// delta R^-l r_z^j.  Per l the l + 1 bases are transformed (two rows as one
-// complex sequence, split per row at the kept kz) and every field of that l is
-// formed from them: l + 1 transforms in place of 2l + 1 (local line of sight),
-// one transform for all fields (global line of sight, G_0 of delta itself).
-// Same outputs as k_zpass_ylm_rr up to rounding.
+// Register z-pass by powers of r_z (N = R^2, l <= 4, kz_keep <= K2M R).  With
+// R^2 = rho^2 + r_z^2 (rho^2 = r_x^2 + r_y^2, fixed along a z row), the
+// weight y_l^m = Q_lm(r_z, R^2) s^m / R^l of a field is, over the common
+// R^-L of its parity class (L the largest l of that parity in the table),
+// the row constant times the polynomial Q_lm R^(L - l) in r_z of degree
+// L - m <= 4 (R^(L - l) = (rho^2 + r_z^2)^((L - l) / 2) for even L - l).  The
+// transform is linear, so every field's row spectrum is sum_j e_j G_j with G_j
+// the spectrum of delta R^-L r_z^j, j = 0..L: L + 1 transforms per parity
+// class (two rows as one complex sequence, split per row at the kept kz) in
+// place of 2l + 1 per l, e.g. 5 for l = 2, 4 against 14; one transform for all
+// fields with a global line of sight (G_0 of delta itself).  Same outputs as
+// k_zpass_ylm_rr up to rounding.
 template <typename T, int R, int K2M>
-__global__ void __launch_bounds__(256, 2) k_zpass_ylm_basis(const T* __restrict__ delta, cx<T>* __restrict__ out,
+__global__ void __launch_bounds__(256, K2M == 2 ? 3 : 2) k_zpass_ylm_basis(const T* __restrict__ delta, cx<T>* __restrict__ out,
                                                          FieldTable ft, int kz_keep, int64_t fstride, Geo g) {
   constexpr int N = R * R;
   constexpr int GR = 256 / R;  // row pairs per workgroup
@@ -404,7 +410,7 @@ __global__ void __launch_bounds__(256, 2) k_zpass_ylm_basis(const T* __restrict_
   const T rx = T(ix * g.h - g.obs[0]);
   const T ry0 = T(iy0 * g.h - g.obs[1]), ry1 = T((iy0 + 1) * g.h - g.obs[1]);
   const T rho0 = rx * rx + ry0 * ry0, rho1 = rx * rx + ry1 * ry1;
-  __syncthreads();
+  __syncthreads();  // twiddles
   const int src = (R - rank) & (R - 1);
   cx<T>* orow = out + ((int64_t)ix * N + iy0) * kz_keep;
   cx<T> g0[5][K2M], g1[5][K2M];
@@ -412,14 +418,15 @@ __global__ void __launch_bounds__(256, 2) k_zpass_ylm_basis(const T* __restrict_
   for (int j = 0; j < 5; ++j)
 #pragma unroll
     for (int k2 = 0; k2 < K2M; ++k2) g0[j][k2] = g1[j][k2] = cx<T>{T(0), T(0)};
-  int have = -1;  // l of the bases held (a global line of sight needs G_0 once)
-  for (int f0 = 0; f0 < ft.nf;) {
-    const int l = ft.ell[f0];
-    int f1 = f0 + 1;
-    while (f1 < ft.nf && ft.ell[f1] == l) ++f1;
-    if (g.global_los ? have < 0 : have != l) {
-      if (!g.global_los && l != pw) {
-        if (l < pw) {
+  bool have = false;  // a global line of sight needs G_0 once
+  for (int par = 1; par >= 0; --par) {  // odd l, then even l
+    int L = -1;
+    for (int f = 0; f < ft.nf; ++f)
+      if ((ft.ell[f] & 1) == par && ft.ell[f] > L) L = ft.ell[f];
+    if (L < 0) continue;
+    if (!g.global_los) {
+      if (L != pw) {
+        if (L < pw) {
 #pragma unroll
           for (int n2 = 0; n2 < R; ++n2) {
             const int z = rank + R * n2;
@@ -428,36 +435,45 @@ __global__ void __launch_bounds__(256, 2) k_zpass_ylm_basis(const T* __restrict_
           }
           pw = 0;
         }
-        switch (l - pw) {
+        switch (L - pw) {
           case 1: scale_rows<T, R, 1>(d0, d1, rz0, dz, rho0, rho1); break;
           case 2: scale_rows<T, R, 2>(d0, d1, rz0, dz, rho0, rho1); break;
           case 3: scale_rows<T, R, 3>(d0, d1, rz0, dz, rho0, rho1); break;
           case 4: scale_rows<T, R, 4>(d0, d1, rz0, dz, rho0, rho1); break;
           default: break;
         }
-        pw = l;
+        pw = L;
       }
-      const int jmax = g.global_los ? 0 : l;
       zbasis<T, R, K2M, 0>(d0, d1, rz0, dz, rank, src, buf, tw, g0[0], g1[0]);
-      if (jmax >= 1) zbasis<T, R, K2M, 1>(d0, d1, rz0, dz, rank, src, buf, tw, g0[1], g1[1]);
-      if (jmax >= 2) zbasis<T, R, K2M, 2>(d0, d1, rz0, dz, rank, src, buf, tw, g0[2], g1[2]);
-      if (jmax >= 3) zbasis<T, R, K2M, 3>(d0, d1, rz0, dz, rank, src, buf, tw, g0[3], g1[3]);
-      if (jmax >= 4) zbasis<T, R, K2M, 4>(d0, d1, rz0, dz, rank, src, buf, tw, g0[4], g1[4]);
-      have = l;
+      if (L >= 1) zbasis<T, R, K2M, 1>(d0, d1, rz0, dz, rank, src, buf, tw, g0[1], g1[1]);
+      if (L >= 2) zbasis<T, R, K2M, 2>(d0, d1, rz0, dz, rank, src, buf, tw, g0[2], g1[2]);
+      if (L >= 3) zbasis<T, R, K2M, 3>(d0, d1, rz0, dz, rank, src, buf, tw, g0[3], g1[3]);
+      if (L >= 4) zbasis<T, R, K2M, 4>(d0, d1, rz0, dz, rank, src, buf, tw, g0[4], g1[4]);
+    } else if (!have) {
+      zbasis<T, R, K2M, 0>(d0, d1, rz0, dz, rank, src, buf, tw, g0[0], g1[0]);
+      have = true;
     }
-    for (int f = f0; f < f1; ++f) {
+    for (int f = 0; f < ft.nf; ++f) {
+      const int l = ft.ell[f];
+      if ((l & 1) != par) continue;
       const int m = ft.m[f], p = ft.part[f];
-      ZPoly<T> a, b;
+      // coefficients of r_z^(odd + 2i), i = 0..2, for row 0 (a) and row 1 (b)
+      T a0, a2, a4, b0, b2, b4;
       bool odd = false;
       if (g.global_los) {
-        const T w = ylm_one<T>(l, m, p, T(g.los[0]), T(g.los[1]), T(g.los[2]));
-        a = b = ZPoly<T>{T(0), T(0), w};
+        a0 = b0 = ylm_one<T>(l, m, p, T(g.los[0]), T(g.los[1]), T(g.los[2]));
+        a2 = a4 = b2 = b4 = T(0);
       } else {
         const T s0 = cpow_part<T>(rx, ry0, m, p), s1 = cpow_part<T>(rx, ry1, m, p);
         const SolidQ qc = solid_coef(l, m);
-        a = zpoly<T>(qc, rho0, s0);
-        b = zpoly<T>(qc, rho1, s1);
+        const ZPoly<T> a = zpoly<T>(qc, rho0, s0), b = zpoly<T>(qc, rho1, s1);
         odd = qc.odd != 0;
+        a0 = a.c0; a2 = a.c2; a4 = a.c4;
+        b0 = b.c0; b2 = b.c2; b4 = b.c4;
+        for (int k = l; k < L; k += 2) {  // times rho^2 + r_z^2 (the degree stays <= 4)
+          a4 = a4 * rho0 + a2; a2 = a2 * rho0 + a0; a0 = a0 * rho0;
+          b4 = b4 * rho1 + b2; b2 = b2 * rho1 + b0; b0 = b0 * rho1;
+        }
       }
       cx<T>* o = orow + (int64_t)f * fstride;
 #pragma unroll
@@ -465,16 +481,15 @@ __global__ void __launch_bounds__(256, 2) k_zpass_ylm_basis(const T* __restrict_
         const int k = rank + R * k2;
         if (k < kz_keep) {
           if (odd) {
-            o[k] = zcombine<T, K2M, 1>(g0, k2, a.c0, a.c2, a.c4);
-            o[kz_keep + k] = zcombine<T, K2M, 1>(g1, k2, b.c0, b.c2, b.c4);
+            o[k] = zcombine<T, K2M, 1>(g0, k2, a0, a2, a4);
+            o[kz_keep + k] = zcombine<T, K2M, 1>(g1, k2, b0, b2, b4);
           } else {
-            o[k] = zcombine<T, K2M, 0>(g0, k2, a.c0, a.c2, a.c4);
-            o[kz_keep + k] = zcombine<T, K2M, 0>(g1, k2, b.c0, b.c2, b.c4);
+            o[k] = zcombine<T, K2M, 0>(g0, k2, a0, a2, a4);
+            o[kz_keep + k] = zcombine<T, K2M, 0>(g1, k2, b0, b2, b4);
           }
         }
       }
     }
-    f0 = f1;
   }
 }
 
