@@ -184,6 +184,26 @@ __device__ __forceinline__ void row_fft_rr(cx<T>* v, int rank, cx<T>* buf, const
   dft_reg<T, R, DIR>(v);
 }
 
+// Length N = R^2 transform of W = 256 / R columns by a workgroup: lane (c,
+// rank) holds rows rank + R n2 of column c in v[n2] on entry and rows
+// rank + R k2 of the transform in v[k2] on exit.  One LDS exchange (layout
+// [k1][n1][c], 16 elements of padding per k1 block, conflict free for the
+// stage-1 writes and the stage-2 reads of a half wavefront); contains one
+// workgroup barrier before the exchange reads and one after them.
+template <typename T, int R, int DIR>
+__device__ __forceinline__ void col_fft_rr(cx<T>* v, int c, int rank, cx<T>* buf, const cx<T>* tw) {
+  constexpr int W = 256 / R;
+  dft_reg<T, R, DIR>(v);
+#pragma unroll
+  for (int k1 = 0; k1 < R; ++k1)
+    buf[(k1 * R + rank) * W + c + 16 * k1] = k1 == 0 ? v[k1] : cmul(v[k1], tw[rank * k1]);
+  __syncthreads();
+#pragma unroll
+  for (int n1 = 0; n1 < R; ++n1) v[n1] = buf[(rank * R + n1) * W + c + 16 * rank];
+  __syncthreads();
+  dft_reg<T, R, DIR>(v);
+}
+
 // Length N = R1 R2 transform (R2 = Q R1) of one sequence by a group of R1
 // lanes: on entry lane n1 holds x[n1 + R1 n2] in v[n2] (n2 < R2); on exit it
 // holds X[(n1 + R1 i) + R2 k2] in v[i R1 + k2] (i < Q, k2 < R1).  R2-point

@@ -493,6 +493,241 @@ __global__ void __launch_bounds__(256, K2M == 2 ? 3 : 2) k_zpass_ylm_basis(const
   }
 }
 
+// ---------------------------------- z-power bases combined in the y pass --
+// Bases of a field table: per parity class of l (odd first) the spectra of
+// delta R^-L r_z^j, j = 0..L (L the class's largest l), at basis indices
+// off[c] + j; a global line of sight has the one basis delta.  Field f is
+// sum_i e_i B[bo[f] + 2 i] over i < nt[f] (bo = class offset + parity of
+// l - m, nt = 1 + (L - m - that parity) / 2).
+struct YlmBases {
+  int nclass, nb;
+  int L[2], off[2];
+  signed char bo[32], nt[32];
+};
+
+static YlmBases ylm_bases(const FieldTable& ft, bool global_los) {
+  YlmBases yb{};
+  int Lp[2] = {-1, -1};  // by parity of l
+  for (int f = 0; f < ft.nf; ++f) Lp[ft.ell[f] & 1] = std::max(Lp[ft.ell[f] & 1], (int)ft.ell[f]);
+  if (global_los) {
+    yb.nclass = 1;
+    yb.L[0] = 0;
+    yb.off[0] = 0;
+    yb.nb = 1;
+    for (int f = 0; f < ft.nf; ++f) { yb.bo[f] = 0; yb.nt[f] = 1; }
+    return yb;
+  }
+  int off[2] = {0, 0}, nb = 0;
+  for (int par = 1; par >= 0; --par) {
+    if (Lp[par] < 0) continue;
+    yb.L[yb.nclass] = Lp[par];
+    yb.off[yb.nclass] = nb;
+    off[par] = nb;
+    nb += Lp[par] + 1;
+    ++yb.nclass;
+  }
+  yb.nb = nb;
+  for (int f = 0; f < ft.nf; ++f) {
+    const int l = ft.ell[f], m = ft.m[f], odd = (l - m) & 1, L = Lp[l & 1];
+    yb.bo[f] = (signed char)(off[l & 1] + odd);
+    yb.nt[f] = (signed char)(1 + (L - m - odd) / 2);
+  }
+  return yb;
+}
+
+// Coefficients e_0, e_2, e_4 of the fields' polynomials in r_z on every z row:
+// coef[f][ix][iy] = (e_0, e_2, e_4, 0), the row constant of y_l^m times
+// Q_lm R^(L - l) (ZPoly times (rho^2 + r_z^2)^((L - l) / 2)); the weight
+// itself for a global line of sight.
+template <typename T>
+__global__ void __launch_bounds__(256) k_ylm_coef(FieldTable ft, YlmBases yb, int n, Geo g, T* __restrict__ coef) {
+  const int64_t nn = (int64_t)n * n;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= ft.nf * nn) return;
+  const int f = (int)(i / nn);
+  const int ix = (int)((i - f * nn) / n), iy = (int)(i % n);
+  const int l = ft.ell[f], m = ft.m[f], p = ft.part[f];
+  T e0, e2 = T(0), e4 = T(0);
+  if (g.global_los) {
+    e0 = ylm_one<T>(l, m, p, T(g.los[0]), T(g.los[1]), T(g.los[2]));
+  } else {
+    const T rx = T(ix * g.h - g.obs[0]), ry = T(iy * g.h - g.obs[1]);
+    const T rho = rx * rx + ry * ry;
+    const ZPoly<T> a = zpoly<T>(solid_coef(l, m), rho, cpow_part<T>(rx, ry, m, p));
+    e0 = a.c0;
+    e2 = a.c2;
+    e4 = a.c4;
+    const int L = yb.L[0] % 2 == l % 2 ? yb.L[0] : yb.L[1];
+    for (int k = l; k < L; k += 2) {  // times rho^2 + r_z^2 (the degree stays <= 4)
+      e4 = e4 * rho + e2;
+      e2 = e2 * rho + e0;
+      e0 = e0 * rho;
+    }
+  }
+  T* o = coef + 4 * i;
+  o[0] = e0;
+  o[1] = e2;
+  o[2] = e4;
+  o[3] = T(0);
+}
+
+// Register z pass of the bases alone (N = R^2): per row pair the spectra of
+// delta R^-L r_z^j (both rows as one complex sequence, split per row) at
+// kz < kz_keep, written as planes [basis][x][y][kz] (layout of the fields of
+// k_zpass_ylm_rr).
+template <typename T, int R>
+__global__ void __launch_bounds__(256, 3) k_zpass_ylm_bases(const T* __restrict__ delta, cx<T>* __restrict__ out,
+                                                         YlmBases yb, int kz_keep, int64_t bstride, Geo g) {
+  constexpr int N = R * R;
+  constexpr int GR = 256 / R;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
+  load_twiddles<T, N, -1>(tw);
+  const int grp = threadIdx.x / R, rank = threadIdx.x % R;
+  cx<T>* buf = tw + N + grp * (R * (R + 1));
+  const int q = blockIdx.x * GR + grp;
+  const int ix = q / (N / 2), iy0 = 2 * (q - ix * (N / 2));
+  const T* r0 = delta + ((int64_t)ix * N + iy0) * N;
+  T d0[R], d1[R];
+  int pw = 0;
+#pragma unroll
+  for (int n2 = 0; n2 < R; ++n2) {
+    const int z = rank + R * n2;
+    d0[n2] = r0[z];
+    d1[n2] = r0[N + z];
+  }
+  const T rz0 = T(rank * g.h - g.obs[2]), dz = T(R * g.h);
+  const T rx = T(ix * g.h - g.obs[0]);
+  const T ry0 = T(iy0 * g.h - g.obs[1]), ry1 = T((iy0 + 1) * g.h - g.obs[1]);
+  const T rho0 = rx * rx + ry0 * ry0, rho1 = rx * rx + ry1 * ry1;
+  __syncthreads();  // twiddles
+  const int src = (R - rank) & (R - 1);
+  const int K2 = (kz_keep + R - 1) / R;
+  cx<T>* orow = out + ((int64_t)ix * N + iy0) * kz_keep;
+  for (int cl = 0; cl < yb.nclass; ++cl) {
+    const int L = yb.L[cl];
+    if (!g.global_los && L != pw) {
+      if (L < pw) {
+#pragma unroll
+        for (int n2 = 0; n2 < R; ++n2) {
+          const int z = rank + R * n2;
+          d0[n2] = r0[z];
+          d1[n2] = r0[N + z];
+        }
+        pw = 0;
+      }
+      switch (L - pw) {
+        case 1: scale_rows<T, R, 1>(d0, d1, rz0, dz, rho0, rho1); break;
+        case 2: scale_rows<T, R, 2>(d0, d1, rz0, dz, rho0, rho1); break;
+        case 3: scale_rows<T, R, 3>(d0, d1, rz0, dz, rho0, rho1); break;
+        case 4: scale_rows<T, R, 4>(d0, d1, rz0, dz, rho0, rho1); break;
+        default: break;
+      }
+      pw = L;
+    }
+#pragma unroll
+    for (int j = 0; j <= 4; ++j) {
+      if (j > L) break;
+      cx<T> v[R];
+#pragma unroll
+      for (int n2 = 0; n2 < R; ++n2) {
+        T za = rz0 + T(n2) * dz;
+        asm volatile("" : "+v"(za));
+        T w = T(1);
+#pragma unroll
+        for (int e = 0; e < j; ++e) w *= za;
+        v[n2] = cx<T>{d0[n2] * w, d1[n2] * w};
+      }
+      row_fft_rr<T, R, -1, true>(v, rank, buf, tw);
+      cx<T>* o = orow + (int64_t)(yb.off[cl] + j) * bstride;
+#pragma unroll
+      for (int k2 = 0; k2 < R / 2; ++k2) {
+        if (k2 < K2) {
+          const cx<T> a = v[R - 1 - k2];
+          const cx<T> sh = {__shfl(a.x, src, R), __shfl(a.y, src, R)};
+          const cx<T> zm = cconj(rank ? sh : v[(R - k2) & (R - 1)]);
+          const cx<T> zk = v[k2];
+          const int k = rank + R * k2;
+          if (k < kz_keep) {
+            const cx<T> dd = csub(zk, zm);
+            o[k] = cscale(cadd(zk, zm), T(0.5));
+            o[kz_keep + k] = cx<T>{T(0.5) * dd.y, T(-0.5) * dd.x};
+          }
+        }
+      }
+    }
+  }
+}
+
+// rows rank + R n2 of column kz of a field with NT terms: sum_i e_i B[bo + 2i]
+// (bases from global memory, all loads issued before the first use;
+// coefficients e from the workgroup's copy in LDS)
+template <typename T, int R, int NT>
+__device__ __forceinline__ void ylm_combine(cx<T>* v, const cx<T>* __restrict__ b0, const T* ecf, int rank,
+                                            int64_t bstride, int m) {
+  cx<T> u[NT][R];
+#pragma unroll
+  for (int i = 0; i < NT; ++i)
+#pragma unroll
+    for (int n2 = 0; n2 < R; ++n2) u[i][n2] = b0[(int64_t)(2 * i) * bstride + (int64_t)(rank + R * n2) * m];
+#pragma unroll
+  for (int n2 = 0; n2 < R; ++n2) {
+    const T* e = ecf + 4 * (rank + R * n2);
+    cx<T> a = cscale(u[0][n2], e[0]);
+#pragma unroll
+    for (int i = 1; i < NT; ++i) a = cx<T>{a.x + e[i] * u[i][n2].x, a.y + e[i] * u[i][n2].y};
+    v[n2] = a;
+  }
+}
+
+// Forward y pass of the band z spectra of the Y_lm fields formed from the
+// bases (N = R^2, W = 256 / R kz columns per workgroup): workgroup (ix, f, tile)
+// reads at each of its rows y and columns kz the bases of field f, combines
+// them with coef[f][ix][y], transforms along y and writes the band rows
+// ky = -(m-1) .. m-1 (n = -m as zero) of plane (f, ix), layout [f][x][2m][m].
+// Workgroups of one x plane run on one XCD (workgroup index mod 8 picks the
+// XCD), so the fields of a plane read its bases from that XCD's L2.
+template <typename T, int R>
+__global__ void __launch_bounds__(256) k_colpass_ylm_rr(const cx<T>* __restrict__ bases, const T* __restrict__ coef,
+                                                     cx<T>* __restrict__ out, YlmBases yb, int nf, int m) {
+  constexpr int N = R * R, W = 256 / R, LOGW = (W == 8 ? 3 : W == 16 ? 4 : W == 32 ? 5 : 6);
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* buf = tw + N;
+  T* ecf = reinterpret_cast<T*>(buf + (size_t)N * W + 16 * R);  // [N][4] coefficients of the plane
+  load_twiddles<T, N, -1>(tw);
+  const int c = threadIdx.x & (W - 1), rank = threadIdx.x >> LOGW;
+  const int tiles = m / W;
+  const unsigned per = gridDim.x / 8;  // gridDim.x is a multiple of 8
+  const unsigned lb = (blockIdx.x & 7u) * per + (blockIdx.x >> 3);
+  const int t = (int)(lb % (unsigned)tiles);
+  const int pf = (int)(lb / (unsigned)tiles);
+  const int ix = pf / nf, f = pf - ix * nf;
+  const int kz = t * W + c;
+  const int bo = yb.bo[f], nt = yb.nt[f];
+  const int64_t bstride = (int64_t)N * N * m;
+  const cx<T>* b0 = bases + (int64_t)bo * bstride + (int64_t)ix * N * m + kz;
+  const T* cf = coef + (((int64_t)f * N + ix) * N) * 4;
+  for (int i = threadIdx.x; i < N; i += 256)
+    reinterpret_cast<float4*>(ecf)[i] = reinterpret_cast<const float4*>(cf)[i];  // T = float
+  __syncthreads();  // twiddles, coefficients
+  cx<T> v[R];
+  if (nt == 1) ylm_combine<T, R, 1>(v, b0, ecf, rank, bstride, m);
+  else if (nt == 2) ylm_combine<T, R, 2>(v, b0, ecf, rank, bstride, m);
+  else ylm_combine<T, R, 3>(v, b0, ecf, rank, bstride, m);
+  col_fft_rr<T, R, -1>(v, c, rank, buf, tw);
+  cx<T>* dst = out + ((int64_t)f * N + ix) * 2 * m * m + kz;
+#pragma unroll
+  for (int k2 = 0; k2 < R; ++k2) {
+    const int r = rank + R * k2;
+    int j;
+    if (r < m) j = r;
+    else if (r >= N - m) j = r - N + 2 * m;
+    else continue;
+    dst[(int64_t)j * m] = v[k2];
+  }
+}
+
 template <typename T, int R>
 static cnpc_status zylm_rr(const T* delta, cx<T>* out, const FieldTable& ft, int kz, int64_t fstride,
                            const Geo& g, hipStream_t s) {
@@ -575,6 +810,17 @@ template cnpc_status band_forward_yx<float>(int, int, int, int, const cx<float>*
 template cnpc_status band_forward_yx<double>(int, int, int, int, const cx<double>*, cx<double>*,
                                              cx<double>*, hipStream_t);
 
+// FP32 at N = 256 with register passes, a band of whole 16-column tiles and
+// CNPC_TUNE_YLM_BASIS 0: the z pass writes the z-power bases, the y pass forms
+// the fields from them (coefficient table next to the bases in w1)
+template <typename T>
+static bool ylm_bases_route(int n, int m, const FieldTable& ft, const YlmBases& yb) {
+  if (sizeof(T) != 4 || n != 256 || m % 16 != 0 || !fft_register_passes()) return false;
+  if (tune_value(CNPC_TUNE_YLM_BASIS) == 1) return false;
+  const size_t nn = (size_t)n * n;
+  return yb.nb * nn * m * sizeof(cx<T>) + ft.nf * nn * 4 * sizeof(T) <= ft.nf * nn * m * sizeof(cx<T>);
+}
+
 template <typename T>
 static cnpc_status ylm_r2c_t(const cnpc_mesh_desc* d, int band, const FieldTable& ft,
                              const T* delta, cx<T>* out, cx<T>* ws, hipStream_t s) {
@@ -583,7 +829,33 @@ static cnpc_status ylm_r2c_t(const cnpc_mesh_desc* d, int band, const FieldTable
   const int64_t nn = (int64_t)n * n;
   cx<T>* w1 = ws;
   cx<T>* w2 = ws + (int64_t)ft.nf * nn * m;
-  CNPC_TRY(zpass_ylm<T>(n, delta, w1, ft, m, nn * m, make_geo(d), s));
+  const Geo g = make_geo(d);
+  const YlmBases yb = ylm_bases(ft, g.global_los != 0);
+  if constexpr (sizeof(T) == 4) {
+    if (ylm_bases_route<T>(n, m, ft, yb)) {
+      constexpr int R = 16, N = 256, GR = 256 / R;
+      T* coef = reinterpret_cast<T*>(w1 + (int64_t)yb.nb * nn * m);
+      const int64_t ncoef = ft.nf * nn;
+      kt_begin(CNPC_KT_ZR2C, s);
+      hipLaunchKernelGGL((k_ylm_coef<T>), dim3((unsigned)((ncoef + 255) / 256)), dim3(256), 0, s, ft, yb, n, g,
+                         coef);
+      const size_t zlds = sizeof(cx<T>) * (N + (size_t)GR * R * (R + 1));
+      hipLaunchKernelGGL((k_zpass_ylm_bases<T, R>), dim3(N * (N / 2) / GR), dim3(256), zlds, s, delta, w1, yb, m,
+                         nn * m, g);
+      kt_end(CNPC_KT_ZR2C, s);
+      CNPC_HIP(hipGetLastError());
+      const unsigned blocks = (unsigned)(ft.nf * n * (m / 16));  // a multiple of 8 (n = 256)
+      const size_t clds = sizeof(cx<T>) * (N + (size_t)N * 16 + 16 * R) + sizeof(T) * 4 * N;
+      kt_begin(CNPC_KT_COL, s);
+      hipLaunchKernelGGL((k_colpass_ylm_rr<T, R>), dim3(blocks), dim3(256), clds, s, w1, coef, w2, yb, ft.nf, m);
+      kt_end(CNPC_KT_COL, s);
+      CNPC_HIP(hipGetLastError());
+      ColArgs ax = make_col(n, d->dtype, (int64_t)n * 2 * m * m, (int64_t)4 * m * m * m, (int64_t)2 * m * m,
+                            (int64_t)2 * m * m, 2 * m * m, 0, m);
+      return colpass<T>(n, -1, w2, out, ax, ft.nf, s);
+    }
+  }
+  CNPC_TRY(zpass_ylm<T>(n, delta, w1, ft, m, nn * m, g, s));
   return band_forward_yx<T>(n, d->dtype, ft.nf, m, w1, w2, out, s);
 }
 

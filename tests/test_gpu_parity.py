@@ -307,14 +307,14 @@ def test_ylm_fields(ell, dtype):
 YLM_LOS = (0.3, -0.5, 0.812403840463596)
 
 
-# FP32 at N = 64 and 256 with bands kz < 2R and < 4R take the z-power-basis z
-# pass (l + 1 transforms per l); FP64, N = 128 and the band 128 at 256 take one
-# transform per field
+# FP32 at N = 256 (bands of whole 16-column tiles) writes the z-power bases and
+# forms the fields in the y pass; FP32 at N = 64 forms them in the z pass from
+# bases held in registers; FP64 and N = 128 take one transform per field
 @pytest.mark.parametrize("n,band,dtype,ells,los", [
     (64, 16, L.F64, (2, 4), None), (128, 32, L.F32, (2, 4), None), (256, 32, L.F32, (2, 4), None),
     (256, 64, L.F64, (2, 4), None), (64, 16, L.F32, (1, 2, 3, 4), None), (256, 64, L.F32, (2, 4), None),
     (256, 128, L.F32, (2, 4), None), (64, 16, L.F32, (1, 2, 3, 4), YLM_LOS),
-    (256, 32, L.F32, (2, 4), YLM_LOS)])
+    (256, 32, L.F32, (2, 4), YLM_LOS), (256, 32, L.F32, (1, 2, 3, 4), None), (256, 16, L.F32, (2,), None)])
 def test_ylm_r2c_band(n, band, dtype, ells, los):
     """Y_lm-weighted band transforms (fused prologue z-pass + band column
     passes) against numpy FFTs of the explicitly weighted fields."""
