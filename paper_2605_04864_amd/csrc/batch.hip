@@ -32,6 +32,7 @@ struct cnpc_batch {
   // slab layout (bytes from the slab start)
   size_t o_norms, o_gs, o_rs, o_delta, o_noise, o_D, o_DN, o_dint, o_ylm, o_F[cnpc::BATCH_MAX_ELLS], o_FN0,
       o_means, o_nmodes, o_keff, o_call, call_bytes, slab;
+  size_t shared = 0;  // bytes before the slabs: the Y_lm coefficient table shared by every catalog
   std::vector<hipStream_t> streams;
   hipStream_t origin = nullptr;
   hipEvent_t fork = nullptr;
@@ -91,6 +92,7 @@ static void batch_layout(cnpc_batch* B) {
   B->call_bytes = call;
   B->o_call = take(call);
   B->slab = o;
+  B->shared = B->nhi ? al256(ylm_coef_bytes(d, B->nhi, B->his, B->band)) : 0;
 }
 
 struct BatchArgs {
@@ -107,7 +109,7 @@ struct BatchArgs {
 };
 
 static cnpc_status batch_catalog(const cnpc_batch* B, const BatchArgs& a, int i, unsigned char* w,
-                                 hipStream_t s) {
+                                 const void* coef, hipStream_t s) {
   const cnpc_mesh_desc* d = &B->desc;
   const int nb = B->bins.nbins, band = B->band, nl = B->nells;
   double* norms = reinterpret_cast<double*>(w + B->o_norms);
@@ -142,7 +144,7 @@ static cnpc_status batch_catalog(const cnpc_batch* B, const BatchArgs& a, int i,
   CNPC_TRY(launch_assemble(d, band, 0, DN, nullptr, FN0, s));
   if (B->nhi) {
     unsigned char* ylm = w + B->o_ylm;
-    CNPC_TRY(launch_ylm_r2c(d, band, B->nhi, B->his, dint, ylm, call, B->call_bytes, s));
+    CNPC_TRY(launch_ylm_r2c(d, band, B->nhi, B->his, dint, ylm, call, B->call_bytes, s, coef));
     size_t f = 0;
     for (int h = 0; h < B->nhi; ++h) {
       const int l = B->his[h];
@@ -173,14 +175,21 @@ static cnpc_status batch_catalog(const cnpc_batch* B, const BatchArgs& a, int i,
                     bk + 2 * (size_t)nc, call, B->call_bytes, s);
 }
 
-// fork the batch streams from s0, enqueue every catalog, join them back into s0
+// form the shared tables on s0, fork the batch streams from s0, enqueue every
+// catalog, join them back into s0
 static cnpc_status batch_enqueue(const cnpc_batch* B, const BatchArgs& a, hipStream_t s0) {
+  const void* coef = nullptr;
+  const size_t cb = B->shared ? ylm_coef_bytes(&B->desc, B->nhi, B->his, B->band) : 0;  // 0: another route now
+  if (cb > 0 && cb <= B->shared) {
+    CNPC_TRY(launch_ylm_coef(&B->desc, B->nhi, B->his, B->band, a.ws, s0));
+    coef = a.ws;
+  }
   CNPC_HIP(hipEventRecord(B->fork, s0));
   for (hipStream_t s : B->streams) CNPC_HIP(hipStreamWaitEvent(s, B->fork, 0));
   cnpc_status st = CNPC_OK;
   for (int i = 0; i < a.ncat && st == CNPC_OK; ++i) {
     const int k = i % B->nstreams;
-    st = batch_catalog(B, a, i, a.ws + (size_t)k * B->slab, B->streams[k]);
+    st = batch_catalog(B, a, i, a.ws + B->shared + (size_t)k * B->slab, coef, B->streams[k]);
   }
   // join even after a failed enqueue, so that a capture can end cleanly
   for (int k = 0; k < B->nstreams; ++k) {
@@ -198,8 +207,8 @@ static cnpc_status batch_check_args(const cnpc_batch* B, const BatchArgs& a, siz
   CNPC_REQUIRE(a.ncat >= 1, "need at least one catalog");
   CNPC_REQUIRE(a.gpos && a.ngal && a.rpos && a.nran && a.pk && a.bk && a.ws, "null pointer argument");
   CNPC_REQUIRE((a.gw == nullptr) == (a.rw == nullptr), "give weight arrays for both catalogs or for neither");
-  if (ws_bytes < (size_t)B->nstreams * B->slab) {
-    set_error("batch workspace too small: need %zu, got %zu", (size_t)B->nstreams * B->slab, ws_bytes);
+  if (ws_bytes < B->shared + (size_t)B->nstreams * B->slab) {
+    set_error("batch workspace too small: need %zu, got %zu", B->shared + (size_t)B->nstreams * B->slab, ws_bytes);
     return CNPC_EWORKSPACE;
   }
   for (int i = 0; i < a.ncat; ++i) {
@@ -293,7 +302,7 @@ cnpc_status cnpc_batch_create(cnpc_batch** out, const cnpc_mesh_desc* d, const c
   return CNPC_OK;
 }
 
-size_t cnpc_batch_workspace_size(const cnpc_batch* B) { return B ? (size_t)B->nstreams * B->slab : 0; }
+size_t cnpc_batch_workspace_size(const cnpc_batch* B) { return B ? B->shared + (size_t)B->nstreams * B->slab : 0; }
 
 void cnpc_batch_destroy(cnpc_batch* B) { batch_free(B); }
 

@@ -26,8 +26,16 @@ template <typename T>
 cnpc_status band_forward_yx(int n, int dt, int batch, int m, const cx<T>* w1, cx<T>* w2, cx<T>* out,
                             hipStream_t s);
 size_t ylm_r2c_ws_bytes(const cnpc_mesh_desc* d, int nfields, int band);
+// coef: the table of launch_ylm_coef for the same mesh, ells and band, or
+// nullptr (the call forms it in its workspace)
 cnpc_status launch_ylm_r2c(const cnpc_mesh_desc* d, int band, int nells, const int32_t* ells,
-                           const void* delta, void* out, void* ws, size_t ws_bytes, hipStream_t s);
+                           const void* delta, void* out, void* ws, size_t ws_bytes, hipStream_t s,
+                           const void* coef = nullptr);
+// Per-row coefficient table of the FP32 z-power-bases route of launch_ylm_r2c:
+// its bytes (0 when that route does not apply) and a kernel that fills it.
+size_t ylm_coef_bytes(const cnpc_mesh_desc* d, int nells, const int32_t* ells, int band);
+cnpc_status launch_ylm_coef(const cnpc_mesh_desc* d, int nells, const int32_t* ells, int band, void* coef,
+                            hipStream_t s);
 cnpc_status launch_ylm_fields(const cnpc_mesh_desc* d, int ell, const void* delta, void* out,
                               hipStream_t s);
 size_t deinterlace_ws_bytes(const cnpc_mesh_desc* d);

@@ -823,7 +823,7 @@ static bool ylm_bases_route(int n, int m, const FieldTable& ft, const YlmBases& 
 
 template <typename T>
 static cnpc_status ylm_r2c_t(const cnpc_mesh_desc* d, int band, const FieldTable& ft,
-                             const T* delta, cx<T>* out, cx<T>* ws, hipStream_t s) {
+                             const T* delta, cx<T>* out, cx<T>* ws, const T* coef_in, hipStream_t s) {
   CNPC_TRY(ensure_twiddles());
   const int n = d->n, m = band;
   const int64_t nn = (int64_t)n * n;
@@ -834,11 +834,14 @@ static cnpc_status ylm_r2c_t(const cnpc_mesh_desc* d, int band, const FieldTable
   if constexpr (sizeof(T) == 4) {
     if (ylm_bases_route<T>(n, m, ft, yb)) {
       constexpr int R = 16, N = 256, GR = 256 / R;
-      T* coef = reinterpret_cast<T*>(w1 + (int64_t)yb.nb * nn * m);
-      const int64_t ncoef = ft.nf * nn;
+      const T* coef = coef_in;
       kt_begin(CNPC_KT_ZR2C, s);
-      hipLaunchKernelGGL((k_ylm_coef<T>), dim3((unsigned)((ncoef + 255) / 256)), dim3(256), 0, s, ft, yb, n, g,
-                         coef);
+      if (!coef) {
+        T* c = reinterpret_cast<T*>(w1 + (int64_t)yb.nb * nn * m);
+        const int64_t ncoef = ft.nf * nn;
+        hipLaunchKernelGGL((k_ylm_coef<T>), dim3((unsigned)((ncoef + 255) / 256)), dim3(256), 0, s, ft, yb, n, g, c);
+        coef = c;
+      }
       const size_t zlds = sizeof(cx<T>) * (N + (size_t)GR * R * (R + 1));
       hipLaunchKernelGGL((k_zpass_ylm_bases<T, R>), dim3(N * (N / 2) / GR), dim3(256), zlds, s, delta, w1, yb, m,
                          nn * m, g);
@@ -865,7 +868,8 @@ size_t ylm_r2c_ws_bytes(const cnpc_mesh_desc* d, int nfields, int band) {
 }
 
 cnpc_status launch_ylm_r2c(const cnpc_mesh_desc* d, int band, int nells, const int32_t* ells,
-                           const void* delta, void* out, void* ws, size_t ws_bytes, hipStream_t s) {
+                           const void* delta, void* out, void* ws, size_t ws_bytes, hipStream_t s,
+                           const void* coef) {
   FieldTable ft;
   const int nf = field_table(nells, ells, &ft);
   CNPC_REQUIRE(nf > 0, "too many Y_lm fields (max 32)");
@@ -874,8 +878,31 @@ cnpc_status launch_ylm_r2c(const cnpc_mesh_desc* d, int band, int nells, const i
     return CNPC_EWORKSPACE;
   }
   if (d->dtype == CNPC_F64)
-    return ylm_r2c_t<double>(d, band, ft, (const double*)delta, (cx<double>*)out, (cx<double>*)ws, s);
-  return ylm_r2c_t<float>(d, band, ft, (const float*)delta, (cx<float>*)out, (cx<float>*)ws, s);
+    return ylm_r2c_t<double>(d, band, ft, (const double*)delta, (cx<double>*)out, (cx<double>*)ws, nullptr, s);
+  return ylm_r2c_t<float>(d, band, ft, (const float*)delta, (cx<float>*)out, (cx<float>*)ws, (const float*)coef,
+                          s);
+}
+
+size_t ylm_coef_bytes(const cnpc_mesh_desc* d, int nells, const int32_t* ells, int band) {
+  FieldTable ft;
+  if (d->dtype != CNPC_F32 || field_table(nells, ells, &ft) <= 0) return 0;
+  const YlmBases yb = ylm_bases(ft, d->los_mode == CNPC_LOS_GLOBAL);
+  if (!ylm_bases_route<float>(d->n, band, ft, yb)) return 0;
+  return (size_t)ft.nf * d->n * d->n * 4 * sizeof(float);
+}
+
+cnpc_status launch_ylm_coef(const cnpc_mesh_desc* d, int nells, const int32_t* ells, int band, void* coef,
+                            hipStream_t s) {
+  FieldTable ft;
+  CNPC_REQUIRE(field_table(nells, ells, &ft) > 0, "too many Y_lm fields (max 32)");
+  CNPC_REQUIRE(ylm_coef_bytes(d, nells, ells, band) > 0, "no coefficient table for this transform");
+  const Geo g = make_geo(d);
+  const YlmBases yb = ylm_bases(ft, g.global_los != 0);
+  const int64_t ncoef = (int64_t)ft.nf * d->n * d->n;
+  hipLaunchKernelGGL((k_ylm_coef<float>), dim3((unsigned)((ncoef + 255) / 256)), dim3(256), 0, s, ft, yb, d->n, g,
+                     (float*)coef);
+  CNPC_HIP(hipGetLastError());
+  return CNPC_OK;
 }
 
 cnpc_status launch_ylm_fields(const cnpc_mesh_desc* d, int ell, const void* delta, void* out,
