@@ -544,10 +544,11 @@ cnpc_status cnpc_ktimer_stop(double* ms_per_class, int64_t* launches_per_class);
  *                          of the de-interlacing transforms; 1 writes the
  *                          delta and N meshes and transforms them.
  *   CNPC_TUNE_BUCKET       shape of the first sort step of unweighted catalogs
- *                          (0: 1024 threads x 4 particles; 1: 1024 x 2 with
- *                          the next chunk loaded during the current one; 2:
- *                          512 x 4, likewise; 3: as 0 with at most half the
- *                          persistent workgroups).
+ *                          (0: 1024 threads x 8 particles on one workgroup per
+ *                          CU with the l = 0 sums, x 4 with Y_lm sums; 1: 1024
+ *                          x 2 with the next chunk loaded during the current
+ *                          one; 2: 512 x 4, likewise; 3: 1024 x 4 on two
+ *                          workgroups per CU).
  *   CNPC_TUNE_YLM_BASIS    FP32 Y_lm z passes of bands kz < 4 R (N = R^2 of
  *                          the register passes): 0 (default) transforms
  *                          delta R^-L r_z^j, j = 0..L, per parity class of l

@@ -1167,16 +1167,15 @@ static TileGeom tile_geom(const cnpc_mesh_desc* d) {
   return g;
 }
 
-// Bucket-pass geometry: chunk of BUCKET_NT * per particles, at most
+// Bucket-pass geometry: chunk of BUCKET_NT * per particles (per <= 8), at most
 // BUCKET_BLOCKS_MAX persistent workgroups; a bucket region holds 1.5 times the
-// mean bucket count plus a chunk (more goes to the overflow region).
+// mean bucket count plus the largest chunk (more goes to the overflow region).
 constexpr int BUCKET_NT = 1024;
 constexpr int BUCKET_BLOCKS_MAX = 512;
 constexpr int OVF_BLOCKS = 256;  // tile-pass workgroups walking the overflow records
-static int bucket_per(int rs) { return rs == 3 ? 4 : 2; }
 static uint32_t bucket_cap(int64_t n, int nbuckets) {
   const int64_t mean = (n + nbuckets - 1) / nbuckets;
-  const int64_t c = mean + mean / 2 + (int64_t)BUCKET_NT * 4;
+  const int64_t c = mean + mean / 2 + (int64_t)BUCKET_NT * 8;
   return (uint32_t)((c + 63) / 64 * 64);
 }
 
@@ -1359,11 +1358,13 @@ static cnpc_status sort_and_paint(const cnpc_mesh_desc* d, const uint32_t* pos, 
 // Catalog sums, tile histogram and both sort steps from one read of the
 // catalog (fused bucket pass), then the tile painting.  sums: CNPC_SUMS_LEN
 // doubles (device).
-// Bucket-pass shape: CNPC_TUNE_BUCKET 0 (default) 1024 threads, 4 (RS 3) or 2
-// (RS 4) particles per thread; 1: 1024 threads, 2 particles, next chunk
-// prefetched; 2: 512 threads, 4 particles, prefetched; 3: as 0 with at most
-// half the persistent workgroups.  The prefetching forms exist for unweighted
-// catalogs with l = 0 or l <= 4 sums; the rest take 0.
+// Bucket-pass shape: CNPC_TUNE_BUCKET 0 (default) 1024 threads; unweighted
+// catalogs with the l = 0 sums 8 particles per thread on at most 256
+// workgroups (one per CU: 130 KB of LDS), with Y_lm sums 4 on at most 512;
+// weighted catalogs 2 on at most 512.  1: 1024 threads, 2 particles, next
+// chunk prefetched; 2: 512 threads, 4 particles, prefetched; 3: 1024 threads,
+// 4 particles on at most 512 workgroups.  The prefetching forms exist for
+// unweighted catalogs with l = 0 or l <= 4 sums; the rest take 0.
 struct BucketShape {
   int nt, per;
   bool pf;
@@ -1375,8 +1376,9 @@ static BucketShape bucket_shape(int rs, int lmax) {
     if (v == 1) return {1024, 2, true, BUCKET_BLOCKS_MAX};
     if (v == 2) return {512, 4, true, BUCKET_BLOCKS_MAX};
   }
-  // 3: half the workgroups (half the tile-histogram flushes)
-  return {BUCKET_NT, bucket_per(rs), false, v == 3 ? BUCKET_BLOCKS_MAX / 2 : BUCKET_BLOCKS_MAX};
+  if (rs == 4) return {BUCKET_NT, 2, false, BUCKET_BLOCKS_MAX};
+  if (v == 3 || lmax > 0) return {BUCKET_NT, 4, false, BUCKET_BLOCKS_MAX};
+  return {BUCKET_NT, 8, false, BUCKET_BLOCKS_MAX / 2};
 }
 
 template <int RS, int LMAX>
@@ -1393,6 +1395,13 @@ static void launch_bucket_pass(const BucketShape& b, unsigned nblk, size_t lds, 
       if (b.pf) {
         hipLaunchKernelGGL((k_bucket_pass<3, 4, 512, LMAX, true>), dim3(nblk), dim3(512), lds, s, pos, w, n, sa, ba,
                            region, ovf_out);
+        return;
+      }
+    }
+    if constexpr (LMAX == 0) {
+      if (b.per == 8) {
+        hipLaunchKernelGGL((k_bucket_pass<3, 8, BUCKET_NT, 0, false>), dim3(nblk), dim3(BUCKET_NT), lds, s, pos, w,
+                           n, sa, ba, region, ovf_out);
         return;
       }
     }
@@ -1424,11 +1433,15 @@ static cnpc_status fused_sort_and_paint(const cnpc_mesh_desc* d, const uint32_t*
   // l = 0 sums
   const bool split_sums = sums_lmax >= 2 && tune_value(CNPC_TUNE_SORT_FUSED) == 2;
   const int lm = split_sums ? 0 : (sums_lmax >= 4 ? 4 : (sums_lmax >= 2 ? 2 : 0));
-  const BucketShape bs = bucket_shape(RS, lm);
+  BucketShape bs = bucket_shape(RS, lm);
+  const int ltiles = L.ntiles <= LDS_TILES_MAX ? L.ntiles : 0;
+  size_t lds = bucket_pass_lds(bs.per, RS, L.nbuckets, bs.nt, ltiles);
+  if (bs.per == 8 && lds > lds_limit()) {  // many buckets (N >= 1024): 4 per thread
+    bs = {BUCKET_NT, 4, false, BUCKET_BLOCKS_MAX};
+    lds = bucket_pass_lds(bs.per, RS, L.nbuckets, bs.nt, ltiles);
+  }
   const int64_t ch = (int64_t)bs.nt * bs.per;
   const unsigned nblk = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + ch - 1) / ch, bs.maxblk));
-  const int ltiles = L.ntiles <= LDS_TILES_MAX ? L.ntiles : 0;
-  const size_t lds = bucket_pass_lds(bs.per, RS, L.nbuckets, bs.nt, ltiles);
   if (lds > lds_limit()) {
     set_error("bucket pass: %zu bytes of LDS exceed the workgroup limit", lds);
     return CNPC_EUNSUPPORTED;
