@@ -124,10 +124,14 @@ static cnpc_status batch_catalog(const cnpc_batch* B, const BatchArgs& a, int i,
   const float* rw = a.rw ? a.rw[i] : nullptr;
   double* gs = reinterpret_cast<double*>(w + B->o_gs);
   double* rs = reinterpret_cast<double*>(w + B->o_rs);
+  // FP32 z-power-bases route of the Y_lm transforms: the de-aliased mesh stays
+  // as z half spectra and its inverse z pass runs inside the Y_lm z pass
+  bool zspec = false;
   if (dint && has_fold_zr2c(d) && tune_value(CNPC_TUNE_FOLD_FUSED) != 1) {
     // fold fused with the z passes of both de-interlacing transforms
+    zspec = B->nhi && ylm_coef_bytes(d, B->nhi, B->his, band) > 0;
     CNPC_TRY(launch_paint_deinterlace(d, band, a.gpos[i], gw, a.ngal[i], a.rpos[i], rw, a.nran[i], B->sums_lmax, gs,
-                                      rs, norms, D, dint, DN, call, B->call_bytes, s));
+                                      rs, norms, D, dint, DN, call, B->call_bytes, s, zspec));
   } else {
     CNPC_TRY(launch_paint_fkp(d, a.gpos[i], gw, a.ngal[i], a.rpos[i], rw, a.nran[i], B->sums_lmax, gs, rs, norms,
                               delta, noise, call, B->call_bytes, s));
@@ -144,7 +148,7 @@ static cnpc_status batch_catalog(const cnpc_batch* B, const BatchArgs& a, int i,
   CNPC_TRY(launch_assemble(d, band, 0, DN, nullptr, FN0, s));
   if (B->nhi) {
     unsigned char* ylm = w + B->o_ylm;
-    CNPC_TRY(launch_ylm_r2c(d, band, B->nhi, B->his, dint, ylm, call, B->call_bytes, s, coef));
+    CNPC_TRY(launch_ylm_r2c(d, band, B->nhi, B->his, dint, ylm, call, B->call_bytes, s, coef, zspec));
     size_t f = 0;
     for (int h = 0; h < B->nhi; ++h) {
       const int l = B->his[h];

@@ -27,10 +27,12 @@ cnpc_status band_forward_yx(int n, int dt, int batch, int m, const cx<T>* w1, cx
                             hipStream_t s);
 size_t ylm_r2c_ws_bytes(const cnpc_mesh_desc* d, int nfields, int band);
 // coef: the table of launch_ylm_coef for the same mesh, ells and band, or
-// nullptr (the call forms it in its workspace)
+// nullptr (the call forms it in its workspace).  delta_zspec: delta holds the
+// z half spectra that launch_paint_deinterlace leaves with delta_int_zspec
+// (the real mesh is then never stored); only where ylm_coef_bytes > 0.
 cnpc_status launch_ylm_r2c(const cnpc_mesh_desc* d, int band, int nells, const int32_t* ells,
                            const void* delta, void* out, void* ws, size_t ws_bytes, hipStream_t s,
-                           const void* coef = nullptr);
+                           const void* coef = nullptr, bool delta_zspec = false);
 // Per-row coefficient table of the FP32 z-power-bases route of launch_ylm_r2c:
 // its bytes (0 when that route does not apply) and a kernel that fills it.
 size_t ylm_coef_bytes(const cnpc_mesh_desc* d, int nells, const int32_t* ells, int band);
@@ -48,7 +50,8 @@ size_t paint_deinterlace_ws_bytes(const cnpc_mesh_desc* d, int64_t ngal, int64_t
 cnpc_status launch_paint_deinterlace(const cnpc_mesh_desc* d, int band, const uint32_t* gpos, const float* gw,
                                      int64_t ngal, const uint32_t* rpos, const float* rw, int64_t nran,
                                      int sums_lmax, double* gsums, double* rsums, double* norms, void* spec,
-                                     void* delta_int, void* specN, void* ws, size_t ws_bytes, hipStream_t s);
+                                     void* delta_int, void* specN, void* ws, size_t ws_bytes, hipStream_t s,
+                                     bool delta_int_zspec = false);
 size_t deinterlace_band_ws_bytes(const cnpc_mesh_desc* d, int band);
 cnpc_status launch_deinterlace(const cnpc_mesh_desc* d, int band, const void* meshes, void* spec,
                                void* delta_int, void* ws, size_t ws_bytes, hipStream_t s);

@@ -518,7 +518,9 @@ static YlmBases ylm_bases(const FieldTable& ft, bool global_los) {
     return yb;
   }
   int off[2] = {0, 0}, nb = 0;
-  for (int par = 1; par >= 0; --par) {
+  // classes by ascending L, so that the R^-L scaling of delta only grows
+  const int first = Lp[1] >= 0 && (Lp[0] < 0 || Lp[1] < Lp[0]) ? 1 : 0;
+  for (int par : {first, 1 - first}) {
     if (Lp[par] < 0) continue;
     yb.L[yb.nclass] = Lp[par];
     yb.off[yb.nclass] = nb;
@@ -574,27 +576,57 @@ __global__ void __launch_bounds__(256) k_ylm_coef(FieldTable ft, YlmBases yb, in
 // Register z pass of the bases alone (N = R^2): per row pair the spectra of
 // delta R^-L r_z^j (both rows as one complex sequence, split per row) at
 // kz < kz_keep, written as planes [basis][x][y][kz] (layout of the fields of
-// k_zpass_ylm_rr).
-template <typename T, int R>
-__global__ void __launch_bounds__(256, 3) k_zpass_ylm_bases(const T* __restrict__ delta, cx<T>* __restrict__ out,
-                                                         YlmBases yb, int kz_keep, int64_t bstride, Geo g) {
-  constexpr int N = R * R;
+// k_zpass_ylm_rr).  ZIN = false: delta is the real mesh; ZIN = true: delta is
+// given as its z half spectra (rows of N/2 complex values, kz < N/2, Nyquist
+// zero; the layout k_zpass_c2r_rr takes), inverse-transformed here first, so
+// that the real mesh is never stored (the classes then have ascending L and
+// delta is never re-read).
+template <typename T, int R, bool ZIN>
+__global__ void __launch_bounds__(256, 3) k_zpass_ylm_bases(const void* __restrict__ delta_in,
+                                                         cx<T>* __restrict__ out, YlmBases yb, int kz_keep,
+                                                         int64_t bstride, Geo g) {
+  constexpr int N = R * R, H = N / 2;
   constexpr int GR = 256 / R;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* twi = tw + N;  // inverse twiddles (ZIN)
   load_twiddles<T, N, -1>(tw);
+  if constexpr (ZIN) load_twiddles<T, N, 1>(twi);
   const int grp = threadIdx.x / R, rank = threadIdx.x % R;
-  cx<T>* buf = tw + N + grp * (R * (R + 1));
+  cx<T>* buf = tw + (ZIN ? 2 : 1) * N + grp * (R * (R + 1));
   const int q = blockIdx.x * GR + grp;
   const int ix = q / (N / 2), iy0 = 2 * (q - ix * (N / 2));
-  const T* r0 = delta + ((int64_t)ix * N + iy0) * N;
+  const T* r0 = reinterpret_cast<const T*>(delta_in) + ((int64_t)ix * N + iy0) * N;
   T d0[R], d1[R];
   int pw = 0;
+  if constexpr (ZIN) {
+    // both rows as one complex sequence A + i B from their half spectra A, B
+    // (clamped straight-line loads; k = N/2 is the zero Nyquist term)
+    const cx<T>* z0 = reinterpret_cast<const cx<T>*>(delta_in) + (int64_t)2 * q * H;
+    cx<T> v[R];
 #pragma unroll
-  for (int n2 = 0; n2 < R; ++n2) {
-    const int z = rank + R * n2;
-    d0[n2] = r0[z];
-    d1[n2] = r0[N + z];
+    for (int n2 = 0; n2 < R; ++n2) {
+      const int k = rank + R * n2;
+      const int kk = k < H ? k : N - k;  // <= H
+      const int kc = kk < H ? kk : H - 1;
+      const cx<T> a = z0[kc], b = z0[H + kc];
+      cx<T> zv = k < H ? cx<T>{a.x - b.y, a.y + b.x} : cx<T>{a.x + b.y, b.x - a.y};
+      v[n2] = kk < H ? zv : cx<T>{T(0), T(0)};
+    }
+    __syncthreads();  // twiddles
+    row_fft_rr<T, R, 1, true>(v, rank, buf, twi);
+#pragma unroll
+    for (int n2 = 0; n2 < R; ++n2) {
+      d0[n2] = v[n2].x;
+      d1[n2] = v[n2].y;
+    }
+  } else {
+#pragma unroll
+    for (int n2 = 0; n2 < R; ++n2) {
+      const int z = rank + R * n2;
+      d0[n2] = r0[z];
+      d1[n2] = r0[N + z];
+    }
   }
   const T rz0 = T(rank * g.h - g.obs[2]), dz = T(R * g.h);
   const T rx = T(ix * g.h - g.obs[0]);
@@ -607,7 +639,7 @@ __global__ void __launch_bounds__(256, 3) k_zpass_ylm_bases(const T* __restrict_
   for (int cl = 0; cl < yb.nclass; ++cl) {
     const int L = yb.L[cl];
     if (!g.global_los && L != pw) {
-      if (L < pw) {
+      if (!ZIN && L < pw) {
 #pragma unroll
         for (int n2 = 0; n2 < R; ++n2) {
           const int z = rank + R * n2;
@@ -821,9 +853,10 @@ static bool ylm_bases_route(int n, int m, const FieldTable& ft, const YlmBases& 
   return yb.nb * nn * m * sizeof(cx<T>) + ft.nf * nn * 4 * sizeof(T) <= ft.nf * nn * m * sizeof(cx<T>);
 }
 
+// zspec: delta holds the z half spectra of the real mesh (bases route only)
 template <typename T>
 static cnpc_status ylm_r2c_t(const cnpc_mesh_desc* d, int band, const FieldTable& ft,
-                             const T* delta, cx<T>* out, cx<T>* ws, const T* coef_in, hipStream_t s) {
+                             const T* delta, cx<T>* out, cx<T>* ws, const T* coef_in, bool zspec, hipStream_t s) {
   CNPC_TRY(ensure_twiddles());
   const int n = d->n, m = band;
   const int64_t nn = (int64_t)n * n;
@@ -842,9 +875,13 @@ static cnpc_status ylm_r2c_t(const cnpc_mesh_desc* d, int band, const FieldTable
         hipLaunchKernelGGL((k_ylm_coef<T>), dim3((unsigned)((ncoef + 255) / 256)), dim3(256), 0, s, ft, yb, n, g, c);
         coef = c;
       }
-      const size_t zlds = sizeof(cx<T>) * (N + (size_t)GR * R * (R + 1));
-      hipLaunchKernelGGL((k_zpass_ylm_bases<T, R>), dim3(N * (N / 2) / GR), dim3(256), zlds, s, delta, w1, yb, m,
-                         nn * m, g);
+      const size_t zlds = sizeof(cx<T>) * ((zspec ? 2 : 1) * N + (size_t)GR * R * (R + 1));
+      if (zspec)
+        hipLaunchKernelGGL((k_zpass_ylm_bases<T, R, true>), dim3(N * (N / 2) / GR), dim3(256), zlds, s,
+                           (const void*)delta, w1, yb, m, nn * m, g);
+      else
+        hipLaunchKernelGGL((k_zpass_ylm_bases<T, R, false>), dim3(N * (N / 2) / GR), dim3(256), zlds, s,
+                           (const void*)delta, w1, yb, m, nn * m, g);
       kt_end(CNPC_KT_ZR2C, s);
       CNPC_HIP(hipGetLastError());
       const unsigned blocks = (unsigned)(ft.nf * n * (m / 16));  // a multiple of 8 (n = 256)
@@ -858,6 +895,10 @@ static cnpc_status ylm_r2c_t(const cnpc_mesh_desc* d, int band, const FieldTable
       return colpass<T>(n, -1, w2, out, ax, ft.nf, s);
     }
   }
+  if (zspec) {
+    set_error("Y_lm transform of z spectra: only the FP32 z-power-bases route takes them");
+    return CNPC_EUNSUPPORTED;
+  }
   CNPC_TRY(zpass_ylm<T>(n, delta, w1, ft, m, nn * m, g, s));
   return band_forward_yx<T>(n, d->dtype, ft.nf, m, w1, w2, out, s);
 }
@@ -869,7 +910,7 @@ size_t ylm_r2c_ws_bytes(const cnpc_mesh_desc* d, int nfields, int band) {
 
 cnpc_status launch_ylm_r2c(const cnpc_mesh_desc* d, int band, int nells, const int32_t* ells,
                            const void* delta, void* out, void* ws, size_t ws_bytes, hipStream_t s,
-                           const void* coef) {
+                           const void* coef, bool delta_zspec) {
   FieldTable ft;
   const int nf = field_table(nells, ells, &ft);
   CNPC_REQUIRE(nf > 0, "too many Y_lm fields (max 32)");
@@ -878,9 +919,10 @@ cnpc_status launch_ylm_r2c(const cnpc_mesh_desc* d, int band, int nells, const i
     return CNPC_EWORKSPACE;
   }
   if (d->dtype == CNPC_F64)
-    return ylm_r2c_t<double>(d, band, ft, (const double*)delta, (cx<double>*)out, (cx<double>*)ws, nullptr, s);
+    return ylm_r2c_t<double>(d, band, ft, (const double*)delta, (cx<double>*)out, (cx<double>*)ws, nullptr,
+                             delta_zspec, s);
   return ylm_r2c_t<float>(d, band, ft, (const float*)delta, (cx<float>*)out, (cx<float>*)ws, (const float*)coef,
-                          s);
+                          delta_zspec, s);
 }
 
 size_t ylm_coef_bytes(const cnpc_mesh_desc* d, int nells, const int32_t* ells, int band) {
@@ -1027,7 +1069,8 @@ static cnpc_status deinterlace_t(const cnpc_mesh_desc* d, int band, const T* mes
 // delta_int), N along the band path (y and x band passes, combination).
 template <typename T>
 static cnpc_status deinterlace_from_z(const cnpc_mesh_desc* d, int band, cx<T>* sp, cx<T>* nw1, cx<T>* nw2,
-                                      cx<T>* nsp, cx<T>* spec, T* delta_int, cx<T>* specN, hipStream_t s) {
+                                      cx<T>* nsp, cx<T>* spec, T* delta_int, cx<T>* specN, bool zspec_out,
+                                      hipStream_t s) {
   const int n = d->n, h = n / 2, m = band;
   const int dt = sizeof(T) == 8 ? CNPC_F64 : CNPC_F32;
   const int64_t nn = (int64_t)n * n, n3 = nn * n;
@@ -1036,7 +1079,7 @@ static cnpc_status deinterlace_from_z(const cnpc_mesh_desc* d, int band, cx<T>* 
   cx<T>* o = reinterpret_cast<cx<T>*>(delta_int);
   CNPC_TRY(xpass_interlace<T>(n, sp, o, spec, band, T(1.0 / (double)n3), s));
   CNPC_TRY(colpass<T>(n, 1, o, o, ay, (int64_t)n, s));
-  CNPC_TRY(zpass_c2r<T>(n, o, delta_int, nn, h, s));
+  if (!zspec_out) CNPC_TRY(zpass_c2r<T>(n, o, delta_int, nn, h, s));
   ColArgs by = make_col(n, dt, (int64_t)n * m, (int64_t)2 * m * m, m, m, m, 0, m);
   CNPC_TRY(colpass<T>(n, -1, nw1, nw2, by, 2 * (int64_t)n, s));
   ColArgs bx = make_col(n, dt, (int64_t)n * 2 * m * m, (int64_t)4 * m * m * m, (int64_t)2 * m * m,
@@ -1065,7 +1108,8 @@ size_t paint_deinterlace_ws_bytes(const cnpc_mesh_desc* d, int64_t ngal, int64_t
 cnpc_status launch_paint_deinterlace(const cnpc_mesh_desc* d, int band, const uint32_t* gpos, const float* gw,
                                      int64_t ngal, const uint32_t* rpos, const float* rw, int64_t nran,
                                      int sums_lmax, double* gsums, double* rsums, double* norms, void* spec,
-                                     void* delta_int, void* specN, void* ws, size_t ws_bytes, hipStream_t s) {
+                                     void* delta_int, void* specN, void* ws, size_t ws_bytes, hipStream_t s,
+                                     bool delta_int_zspec) {
   const bool weighted = (gw != nullptr) || (rw != nullptr);
   if (!has_fold_zr2c(d) || delta_int == nullptr) {
     set_error("painting with fused de-interlacing: unsupported mesh");
@@ -1088,9 +1132,9 @@ cnpc_status launch_paint_deinterlace(const cnpc_mesh_desc* d, int band, const ui
   if (d->dtype == CNPC_F64)
     return deinterlace_from_z<double>(d, band, (cx<double>*)sp, (cx<double>*)nw1, (cx<double>*)nw2,
                                       (cx<double>*)nsp, (cx<double>*)spec, (double*)delta_int,
-                                      (cx<double>*)specN, s);
+                                      (cx<double>*)specN, delta_int_zspec, s);
   return deinterlace_from_z<float>(d, band, (cx<float>*)sp, (cx<float>*)nw1, (cx<float>*)nw2, (cx<float>*)nsp,
-                                   (cx<float>*)spec, (float*)delta_int, (cx<float>*)specN, s);
+                                   (cx<float>*)spec, (float*)delta_int, (cx<float>*)specN, delta_int_zspec, s);
 }
 
 cnpc_status launch_deinterlace(const cnpc_mesh_desc* d, int band, const void* meshes, void* spec,
