@@ -298,14 +298,25 @@ def main():
     # timed classes bracketed by HIP events on its launch stream.  This is the
     # last GPU work of the run: the roofline kernel's launches are the last ones
     # of that kernel in a rocprofv3 trace of the same command.
+    # (the same engine as the timed replays, on one stream)
     mask = sum(1 << v for v in L.KT.values())
-    single = pl.Batch(1)
-    single.run(desc, gpu_mocks, bins, plan, outs)  # scratch of the single stream
+    if native:
+        single = pl.NativeBatch(desc, bins, plan, nstreams=1, max_ngal=max(int(g.shape[1]) for g, _ in gpu_mocks),
+                                max_nran=max(int(r.shape[1]) for _, r in gpu_mocks))
+
+        def single_run():
+            single.run(gpu_mocks, outs)
+    else:
+        single = pl.Batch(1)
+
+        def single_run():
+            single.run(desc, gpu_mocks, bins, plan, outs)
+    single_run()  # scratch of the single stream
     torch.cuda.synchronize()
     L.check(L.lib.cnpc_ktimer_start(mask, 1 << 16))
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
-    single.run(desc, gpu_mocks, bins, plan, outs)
+    single_run()
     e1.record()
     kern = ktimer_read(L)
     ms_instr = e0.elapsed_time(e1)
