@@ -555,6 +555,11 @@ cnpc_status cnpc_ktimer_stop(double* ms_per_class, int64_t* launches_per_class);
  *                          (L its largest l) and forms every field of the
  *                          class from these L + 1 spectra (5 for l = 2, 4);
  *                          1 transforms each field (2l + 1 per l).
+ *   CNPC_TUNE_SHELL_FUSED  split-BF16 bispectrum contraction on a 128^3 grid
+ *                          (at most 24 fields, 128 shell pairs, 32 columns):
+ *                          0 (default) runs the shells' c2r z pass inside the
+ *                          contraction, from their z half spectra; 1 writes
+ *                          the real shell fields first.
  * cnpc_tune_set rejects unknown knobs and values outside those ranges;
  * cnpc_tune_get returns the current value (-1 for an unknown knob). */
 #define CNPC_TUNE_FFT_PASSES 0
@@ -566,7 +571,8 @@ cnpc_status cnpc_ktimer_stop(double* ms_per_class, int64_t* launches_per_class);
 #define CNPC_TUNE_FOLD_FUSED 6
 #define CNPC_TUNE_BUCKET 7
 #define CNPC_TUNE_YLM_BASIS 8
-#define CNPC_TUNE_COUNT 9
+#define CNPC_TUNE_SHELL_FUSED 9
+#define CNPC_TUNE_COUNT 10
 cnpc_status cnpc_tune_set(int32_t knob, int32_t value);
 int32_t cnpc_tune_get(int32_t knob);
 

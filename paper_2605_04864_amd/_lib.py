@@ -131,7 +131,7 @@ KT = {"paint": 1, "sort": 2, "fold": 3, "zr2c": 4, "col": 5, "zc2r": 6, "contrac
 TUNE = {"fft_passes": (0, (0, 1)), "fft_col_w": (1, (0, 1, 2, 4, 8, 16, 32, 64)),
         "contract_kg": (2, (0, 1, 2, 4)), "sort_per": (3, (0, 1, 2, 4)),
         "sort_threads": (4, (0, 512, 1024)), "sort_fused": (5, (0, 1, 2)), "fold_fused": (6, (0, 1)),
-        "bucket": (7, (0, 1, 2, 3)), "ylm_basis": (8, (0, 1))}
+        "bucket": (7, (0, 1, 2, 3)), "ylm_basis": (8, (0, 1)), "shell_fused": (9, (0, 1))}
 
 EXPORTED = tuple(_PROTOS)
 

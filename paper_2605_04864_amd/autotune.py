@@ -36,7 +36,7 @@ from typing import Callable, Dict, List, Optional, Sequence, Tuple
 from . import _lib as L
 
 KNOB_ORDER = ("fft_passes", "fft_col_w", "contract_kg", "sort_per", "sort_threads", "sort_fused", "fold_fused",
-              "bucket", "ylm_basis")
+              "bucket", "ylm_basis", "shell_fused")
 DEFAULT_STREAMS = 4
 
 

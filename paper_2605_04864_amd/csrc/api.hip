@@ -141,6 +141,7 @@ cnpc_status cnpc_tune_set(int32_t knob, int32_t value) {
     case CNPC_TUNE_FOLD_FUSED: ok = value == 0 || value == 1; break;
     case CNPC_TUNE_BUCKET: ok = value >= 0 && value <= 3; break;
     case CNPC_TUNE_YLM_BASIS: ok = value == 0 || value == 1; break;
+    case CNPC_TUNE_SHELL_FUSED: ok = value == 0 || value == 1; break;
   }
   CNPC_REQUIRE(ok, "value %d out of range for tuning knob %d", value, knob);
   g_tune[knob].store(value, std::memory_order_relaxed);

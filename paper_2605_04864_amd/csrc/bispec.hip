@@ -255,17 +255,50 @@ constexpr int MF_KC = 256;       // grid points per LDS chunk (= threads per wor
 constexpr int MF_PAD = 4;        // row padding (floats) against bank conflicts
 constexpr int MF_ROW = MF_KC + MF_PAD;
 
+// ZIN: the fields are given on a 128^3 grid as their z half spectra (rows of
+// zm complex values, kz < zm <= 64, layout [field][x][y][kz]); each 256-point
+// chunk is the two z rows of one row pair, and its c2r z transform (R1 = 8
+// lanes per field, two-for-one) runs in the workgroup before the contraction,
+// so the real fields are never stored.
+constexpr int MFZ_N = 128, MFZ_R1 = 8, MFZ_R2 = 16, MFZ_MAXF = 24;
+// LDS bytes of the c2r staging of ZIN (twiddles + one exchange buffer per field)
+constexpr size_t mfz_lds = sizeof(cx<float>) * (MFZ_N + (size_t)MFZ_MAXF * MFZ_R2 * (MFZ_R1 + 1));
+
+// row_fft_q<float, MFZ_R1, MFZ_R2, +1> of the lanes with `active` set; every
+// lane of the workgroup passes its two barriers
+__device__ __forceinline__ void zrow_c2r(cx<float>* v, int rank, cx<float>* buf, const cx<float>* tw,
+                                         bool active) {
+  constexpr int R1 = MFZ_R1, R2 = MFZ_R2, Q = R2 / R1;
+  if (active) {
+    dft_reg<float, R2, 1>(v);
+#pragma unroll
+    for (int k1 = 0; k1 < R2; ++k1) buf[k1 * (R1 + 1) + rank] = k1 == 0 ? v[k1] : cmul(v[k1], tw[rank * k1]);
+  }
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+#pragma unroll
+      for (int n1 = 0; n1 < R1; ++n1) v[i * R1 + n1] = buf[(rank + R1 * i) * (R1 + 1) + n1];
+  }
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) dft_reg<float, R1, 1>(v + i * R1);
+  }
+}
+
 // The 4 waves of a workgroup form MG = 4 / KG pair groups x KG point groups:
 // wave (mg, kg) owns the m-tiles mg*MTW .. mg*MTW+MTW-1 (32 pairs each) and all
 // NT n-tiles (32 columns each) for the points kg, kg + KG, ... (16-point steps)
 // of every 256-point chunk staged in LDS; the next chunk is prefetched into
 // registers meanwhile.  Splitting the points (KG > 1) keeps each operand split
 // computed once; splitting the pairs (KG = 1) bounds the accumulators per wave.
-template <int MTW, int NT, int KG, int MAXF>
-__global__ void __launch_bounds__(256, 2) k_contract_mfma(const float* __restrict__ fields, int64_t npts,
+template <int MTW, int NT, int KG, int MAXF, bool ZIN = false>
+__global__ void __launch_bounds__(256, ZIN ? 3 : 2) k_contract_mfma(const float* __restrict__ fields, int64_t npts,
                                                        int nf, int nshell, int npairs, ContractCols cc,
                                                        const uint32_t* __restrict__ pairs,
-                                                       double* __restrict__ partial) {
+                                                       double* __restrict__ partial, int zm = 0) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   float* tile = reinterpret_cast<float*>(smem_raw);  // [nf + 1][MF_ROW]
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -312,7 +345,33 @@ __global__ void __launch_bounds__(256, 2) k_contract_mfma(const float* __restric
   const int64_t x1 = min(npts, x0 + per_block);
   const float* src = fields + threadIdx.x;
   float pre[MAXF];
-  {
+  // ZIN: lane group zg (8 lanes) stages field zg; its 16 inputs of the next
+  // row pair wait in registers
+  constexpr int ZH = MFZ_N / 2;
+  const int zg = threadIdx.x / MFZ_R1, zr = threadIdx.x % MFZ_R1;
+  cx<float>* ztw = reinterpret_cast<cx<float>*>(smem_raw + sizeof(float) * (nf + 1) * MF_ROW);
+  cx<float>* zbuf = ztw + MFZ_N + min(zg, MFZ_MAXF - 1) * (MFZ_R2 * (MFZ_R1 + 1));
+  const cx<float>* zsrc =
+      reinterpret_cast<const cx<float>*>(fields) + (int64_t)min(zg, nf - 1) * (npts / MFZ_N) * zm;
+  cx<float> zv[MFZ_R2];
+  // the row pair of chunk xb as one complex sequence A + i B from the half
+  // spectra A, B of its rows (clamped straight-line loads; kz >= zm and the
+  // Nyquist term are zero)
+  auto zload = [&](int64_t xb) {
+    const cx<float>* r0 = zsrc + (xb / MFZ_N) * zm;
+#pragma unroll
+    for (int n2 = 0; n2 < MFZ_R2; ++n2) {
+      const int k = zr + MFZ_R1 * n2;
+      const int kk = k < ZH ? k : MFZ_N - k;
+      const int kc = kk < zm ? kk : zm - 1;
+      const cx<float> a = r0[kc], b = r0[zm + kc];
+      const cx<float> z = k < ZH ? cx<float>{a.x - b.y, a.y + b.x} : cx<float>{a.x + b.y, b.x - a.y};
+      zv[n2] = kk < zm ? z : cx<float>{0.f, 0.f};
+    }
+  };
+  if constexpr (ZIN) {
+    load_twiddles<float, MFZ_N, 1>(ztw);
+  } else {
     const bool ok = x0 + threadIdx.x < x1;
 #pragma unroll
     for (int f = 0; f < MAXF; ++f)
@@ -320,16 +379,34 @@ __global__ void __launch_bounds__(256, 2) k_contract_mfma(const float* __restric
   }
   for (int64_t xb = x0; xb < x1; xb += MF_KC) {
     __syncthreads();
+    if constexpr (ZIN) {
+      zload(xb);  // issued here, not ahead: the registers stay free during the contraction
+      zrow_c2r(zv, zr, zbuf, ztw, zg < nf);  // two workgroup barriers
+      if (zg < nf) {
+        float* t = tile + zg * MF_ROW;
 #pragma unroll
-    for (int f = 0; f < MAXF; ++f)
-      if (f < nf) tile[f * MF_ROW + threadIdx.x] = pre[f];
+        for (int i = 0; i < MFZ_R2 / MFZ_R1; ++i)
+#pragma unroll
+          for (int k2 = 0; k2 < MFZ_R1; ++k2) {
+            const int e = zr + MFZ_R1 * i + MFZ_R2 * k2;
+            t[e] = zv[i * MFZ_R1 + k2].x;
+            t[MFZ_N + e] = zv[i * MFZ_R1 + k2].y;
+          }
+      }
+    } else {
+#pragma unroll
+      for (int f = 0; f < MAXF; ++f)
+        if (f < nf) tile[f * MF_ROW + threadIdx.x] = pre[f];
+    }
     __syncthreads();
     if (xb + MF_KC < x1) {
       const int64_t xn = xb + MF_KC;
-      const bool ok = xn + threadIdx.x < x1;
+      if constexpr (!ZIN) {
+        const bool ok = xn + threadIdx.x < x1;
 #pragma unroll
-      for (int f = 0; f < MAXF; ++f)
-        if (f < nf) pre[f] = ok ? src[(int64_t)f * npts + xn] : 0.f;
+        for (int f = 0; f < MAXF; ++f)
+          if (f < nf) pre[f] = ok ? src[(int64_t)f * npts + xn] : 0.f;
+      }
     }
 #pragma unroll
     for (int ks = kg * 16; ks < MF_KC; ks += 16 * KG) {
@@ -424,6 +501,47 @@ static cnpc_status launch_mfma(const float* fields, int64_t npts, int nf, int ns
   }
   CNPC_HIP(hipGetLastError());
   return CNPC_OK;
+}
+
+// The split-BF16 contraction of fields given as z half spectra on a 128^3 grid
+// (kernel flag ZIN): the default shapes of at most 24 fields, one column tile
+// and 4 point groups per workgroup (MTW <= 4).  Returns false (nothing
+// launched) where that does not apply.
+static bool contract_mfma_z_ok(int nf, int nshell, const ContractCols& cc, int nlist, const uint32_t* pairs) {
+  const int npairs = pairs ? nlist : nshell * (nshell + 1) / 2;
+  const int mtiles = (npairs + 31) / 32, ntiles = (cc.ncols + 31) / 32;
+  const int kg = tune_value(CNPC_TUNE_CONTRACT_KG);
+  return nf <= 24 && ntiles == 1 && (kg == 0 || kg == 4) && mtiles <= 4 && fft_register_passes();
+}
+
+template <int MTW>
+static void launch_mfma_z(const cx<float>* zin, int zm, int64_t npts, int nf, int nshell, int npairs,
+                          const ContractCols& cc, const uint32_t* pairs, double* partial, size_t lds,
+                          hipStream_t s) {
+  hipLaunchKernelGGL((k_contract_mfma<MTW, 1, 4, 24, true>), dim3(CONTRACT_BLOCKS), dim3(256), lds, s,
+                     reinterpret_cast<const float*>(zin), npts, nf, nshell, npairs, cc, pairs, partial, zm);
+}
+
+static cnpc_status contract_mfma_z(const cx<float>* zin, int zm, int nf, int nshell, const ContractCols& cc,
+                                   double* partial, double* out, hipStream_t s, const uint32_t* pairs, int nlist) {
+  if (!contract_mfma_z_ok(nf, nshell, cc, nlist, pairs) || zm < 1 || zm > MFZ_N / 2 || nf > MFZ_MAXF) {
+    set_error("fused c2r contraction: unsupported shape");
+    return CNPC_EUNSUPPORTED;
+  }
+  const int64_t npts = (int64_t)MFZ_N * MFZ_N * MFZ_N;
+  const int npairs = pairs ? nlist : nshell * (nshell + 1) / 2;
+  const int mtw = (npairs + 31) / 32;
+  const size_t lds_tile = sizeof(float) * (nf + 1) * MF_ROW + mfz_lds;
+  const size_t lds_red = (size_t)mtw * 16 * 64 * sizeof(double);
+  const size_t lds = lds_tile > lds_red ? lds_tile : lds_red;
+  kt_begin(CNPC_KT_CONTRACT, s);
+  if (mtw == 1) launch_mfma_z<1>(zin, zm, npts, nf, nshell, npairs, cc, pairs, partial, lds, s);
+  else if (mtw == 2) launch_mfma_z<2>(zin, zm, npts, nf, nshell, npairs, cc, pairs, partial, lds, s);
+  else if (mtw == 3) launch_mfma_z<3>(zin, zm, npts, nf, nshell, npairs, cc, pairs, partial, lds, s);
+  else launch_mfma_z<4>(zin, zm, npts, nf, nshell, npairs, cc, pairs, partial, lds, s);
+  kt_end(CNPC_KT_CONTRACT, s);
+  CNPC_HIP(hipGetLastError());
+  return reduce_blocks(partial, CONTRACT_BLOCKS, (int64_t)npairs * cc.ncols, out, s);
 }
 
 // partial doubles needed by contract_mfma (4 point groups per workgroup at most)
@@ -738,6 +856,24 @@ cnpc_status shell_c2r(const cnpc_mesh_desc* d, int m, const cx<T>* F, const int6
   CNPC_TRY(colpass<T>(n, 1, w2, w1, ay, (int64_t)nsh * n, s));
   CNPC_TRY(zpass_c2r<T>(n, w1, out, (int64_t)nsh * nn, m, s));
   return CNPC_OK;
+}
+
+// the x and y passes of shell_c2r alone: X_b's z half spectra into out
+// [nsh][n][n][m]; w2: scratch of nsh n 2m m elements
+template <typename T>
+static cnpc_status shell_xy(const cnpc_mesh_desc* d, int m, const cx<T>* F, const int64_t* thr, int nthr,
+                           int b0, int nsh, bool mask, cx<T>* out, cx<T>* w2, hipStream_t s) {
+  const int n = d->n, dt = d->dtype;
+  ColArgs ax = make_col(n, dt, 0, (int64_t)n * 2 * m * m, (int64_t)2 * m * m, (int64_t)2 * m * m,
+                        2 * m * m, m, 0);
+  if (mask) {
+    ax.mask_m = m;
+    ax.mask_b0 = b0;
+    for (int i = 0; i < nthr; ++i) ax.thr[i] = thr[i];
+  }
+  CNPC_TRY(colpass<T>(n, 1, F, w2, ax, nsh, s));
+  ColArgs ay = make_col(n, dt, (int64_t)2 * m * m, (int64_t)n * m, m, m, m, m, 0);
+  return colpass<T>(n, 1, w2, out, ay, (int64_t)nsh * n, s);
 }
 
 size_t shell_c2r_ws_elems(int n, int m, int nsh) {
@@ -1138,12 +1274,33 @@ static cnpc_status bispec_run_t(const cnpc_bispec_plan* P, const cx<T>* F0, cons
   }
   CNPC_TRY(ensure_twiddles());
   const int nthr = nb + 1;
-  CNPC_TRY(shell_c2r<T>(d, m, F0, P->thr.data(), nthr, 0, nb, true, fields, scr, s));
-  if (P->est == CNPC_EST_SCOCCIMARRO && P->ell > 0)
-    CNPC_TRY(shell_c2r<T>(d, m, Fl, P->thr.data(), nthr, 0, nb, true, fields + (int64_t)nb * n3, scr, s));
-  if (P->est == CNPC_EST_TRIPOSH)
-    CNPC_TRY(shell_c2r<T>(d, m, Fl, P->thr.data(), nthr, 0, 1, false, fields + (int64_t)nb * n3, scr, s));
-  CNPC_TRY(contract_any<T>(P, fields, n3, partial, Cm, s));
+  // split BF16 on a 128^3 grid (CNPC_TUNE_SHELL_FUSED 0): the shells' z c2r
+  // runs inside the contraction, from their z half spectra in scr
+  bool fused = false;
+  if constexpr (sizeof(T) == 4)
+    fused = P->prec == CNPC_PREC_BF16X3 && n == MFZ_N && m <= MFZ_N / 2 &&
+            tune_value(CNPC_TUNE_SHELL_FUSED) != 1 &&
+            contract_mfma_z_ok(P->nfields, P->nb, P->cc, (int)P->pairs.size(), P->d_pairs);
+  if (fused) {
+    if constexpr (sizeof(T) == 4) {
+      const int64_t zplane = (int64_t)n * n * m;
+      cx<T>* w2 = scr + (int64_t)P->nfields * zplane;
+      CNPC_TRY(shell_xy<T>(d, m, F0, P->thr.data(), nthr, 0, nb, true, scr, w2, s));
+      if (P->est == CNPC_EST_SCOCCIMARRO && P->ell > 0)
+        CNPC_TRY(shell_xy<T>(d, m, Fl, P->thr.data(), nthr, 0, nb, true, scr + (int64_t)nb * zplane, w2, s));
+      if (P->est == CNPC_EST_TRIPOSH)
+        CNPC_TRY(shell_xy<T>(d, m, Fl, P->thr.data(), nthr, 0, 1, false, scr + (int64_t)nb * zplane, w2, s));
+      CNPC_TRY(contract_mfma_z(scr, m, P->nfields, P->nb, P->cc, partial, Cm, s, P->d_pairs,
+                               (int)P->pairs.size()));
+    }
+  } else {
+    CNPC_TRY(shell_c2r<T>(d, m, F0, P->thr.data(), nthr, 0, nb, true, fields, scr, s));
+    if (P->est == CNPC_EST_SCOCCIMARRO && P->ell > 0)
+      CNPC_TRY(shell_c2r<T>(d, m, Fl, P->thr.data(), nthr, 0, nb, true, fields + (int64_t)nb * n3, scr, s));
+    if (P->est == CNPC_EST_TRIPOSH)
+      CNPC_TRY(shell_c2r<T>(d, m, Fl, P->thr.data(), nthr, 0, 1, false, fields + (int64_t)nb * n3, scr, s));
+    CNPC_TRY(contract_any<T>(P, fields, n3, partial, Cm, s));
+  }
   const bool exact = ind != nullptr;
   if (exact) {
     // the signal fields are consumed: P(q) goes to the start of the field

@@ -148,3 +148,21 @@ def test_autotune_batch(tmp_path, engine):
             assert P.rel(P.host(o["bk"]), bk) < 1e-3
     finally:
         autotune.reset_knobs()
+
+
+@pytest.mark.parametrize("est,ell", [(L.EST_SCOCCIMARRO, 0), (L.EST_TRIPOSH, 2)])
+def test_shell_c2r_inside_contraction(est, ell):
+    """CNPC_TUNE_SHELL_FUSED: the split-BF16 contraction on the 128^3 grid of a
+    256^3 mesh that runs the shells' c2r z pass itself gives the results of
+    the real shell fields written first (same transforms, same contraction)."""
+    n, box = 256, 1000.0
+    bins = cn.kbins(0.0, 0.01, 20)
+    g, r = P._cat(41, 200_000, 800_000)
+    d = cn.mesh_desc(n, box, assign=L.TSC, interlace=True, dtype=L.F32, observer=P.OBS)
+    res = {}
+    for v in (0, 1):
+        with knobs(shell_fused=v):
+            o = pl.measure_bk(d, P.dev(g), P.dev(r), bins, estimator=est, ell=ell, precision=L.PREC_BF16X3)
+            res[v] = {k: P.host(o[k]) for k in ("raw", "shot", "value")}
+    for k in ("raw", "shot", "value"):
+        assert P.rel(res[0][k], res[1][k]) < 1e-12, k
