@@ -479,9 +479,14 @@ __global__ void __launch_bounds__(256) k_xpass_interlace_rr(const cx<T>* __restr
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* twf = reinterpret_cast<cx<T>*>(smem_raw);
   cx<T>* twi = twf + N;
-  cx<T>* buf = twi + N;
+  cx<T>* tph = twi + N;  // [2N]: exp(-i pi s / N), the interlacing phase of nx + ny + kz = s (mod 2N)
+  cx<T>* buf = tph + 2 * N;
   load_twiddles<T, N, -1>(twf);
   load_twiddles<T, N, 1>(twi);
+  for (int t = threadIdx.x; t < 2 * N; t += blockDim.x) {
+    const cx<double> w = g_twiddle1024[t * (512 / N)];
+    tph[t] = cx<T>{T(w.x), T(w.y)};
+  }
   const int c = threadIdx.x & (W - 1), rank = threadIdx.x >> LOGW;
   const int col = blockIdx.x * W + c;
   cx<T> va[R], vb[R];
@@ -501,12 +506,7 @@ __global__ void __launch_bounds__(256) k_xpass_interlace_rr(const cx<T>* __restr
     const int row = rank + R * k2;
     const int nx = row < H ? row : row - N;
     cx<T> d = {T(0), T(0)};
-    if (nx != -H && ny != -H) {
-      T sn, cs;
-      if constexpr (sizeof(T) == 4) sincospif(-(float)(nx + ny + kz) / (float)N, &sn, &cs);
-      else sincospi(-(double)(nx + ny + kz) / (double)N, &sn, &cs);
-      d = cscale(cadd(va[k2], cmul(cx<T>{cs, sn}, vb[k2])), T(0.5));
-    }
+    if (nx != -H && ny != -H) d = cscale(cadd(va[k2], cmul(tph[(nx + ny + kz) & (2 * N - 1)], vb[k2])), T(0.5));
     if (band_out && nx >= -mb && nx < mb && ny >= -mb && ny < mb && kz < mb) {
       const int bx = nx < 0 ? nx + 2 * mb : nx, by = ny < 0 ? ny + 2 * mb : ny;
       band_out[((int64_t)bx * 2 * mb + by) * mb + kz] = d;
@@ -524,7 +524,7 @@ cnpc_status xpass_interlace(int n, const cx<T>* in, cx<T>* out, cx<T>* band_out,
   auto go = [&](auto rc) -> cnpc_status {
     constexpr int R = decltype(rc)::value, N = R * R, W = 256 / R;
     const int64_t cols = (int64_t)N * (N / 2);
-    const size_t lds = sizeof(cx<T>) * (2 * N + (size_t)N * W + 16 * R);
+    const size_t lds = sizeof(cx<T>) * (4 * N + (size_t)N * W + 16 * R);
     kt_begin(CNPC_KT_COL, s);
     hipLaunchKernelGGL((k_xpass_interlace_rr<T, R>), dim3((unsigned)(cols / W)), dim3(256), lds, s, in, out,
                        band_out, mb, scale);
