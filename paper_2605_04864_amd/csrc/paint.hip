@@ -301,6 +301,39 @@ __global__ void __launch_bounds__(1024) k_tile_scan(const uint32_t* __restrict__
   });
 }
 
+// k_tile_scan (workgroup 0) and, in workgroups 1 .. CNPC_SUMS_LEN, the
+// fixed-order column sums of k_reduce_partials (first wavefront): the two
+// steps between the first and the second sort step of a fused sort, one launch.
+__global__ void __launch_bounds__(1024) k_tile_scan_sums(const uint32_t* __restrict__ count, int ntiles,
+                                                         int per_bucket, uint32_t* __restrict__ start,
+                                                         uint32_t* __restrict__ cursor, uint32_t* __restrict__ bcur,
+                                                         const double* __restrict__ partial, int nblocks,
+                                                         double* __restrict__ sums) {
+  __shared__ uint32_t wsum[16];
+  if (blockIdx.x == 0) {
+    block_exclusive_scan<1024>(count, ntiles, wsum, [&](int t, uint32_t v) {
+      start[t] = v;
+      cursor[t] = v;
+      if (t % per_bucket == 0) bcur[t / per_bucket] = v;
+    });
+    return;
+  }
+  if (threadIdx.x >= 64) return;
+  const int q = blockIdx.x - 1;
+  double v = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += 64) v += partial[(int64_t)b * CNPC_SUMS_LEN + q];
+  v = wave_sum(v);
+  if (threadIdx.x == 0) sums[q] = v;
+}
+
+// zeroes p[0, n) and q[0, m) in one launch
+__global__ void k_zero2_u32(uint32_t* p, int64_t n, uint32_t* q, int64_t m) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n + m; i += (int64_t)gridDim.x * blockDim.x) {
+    if (i < n) p[i] = 0u;
+    else q[i - n] = 0u;
+  }
+}
+
 // Size in bytes of the LDS layout of k_partition with nt threads.
 __host__ __device__ constexpr size_t partition_lds(int per, int rs, int rcap, int nt) {
   return (size_t)nt * per * (rs * 4 + 2) + (size_t)3 * rcap * 4 + 64;
@@ -1446,8 +1479,8 @@ static cnpc_status fused_sort_and_paint(const cnpc_mesh_desc* d, const uint32_t*
     set_error("bucket pass: %zu bytes of LDS exceed the workgroup limit", lds);
     return CNPC_EUNSUPPORTED;
   }
-  hipLaunchKernelGGL(k_zero_u32, dim3(64), dim3(256), 0, s, count, (int64_t)L.ntiles);
-  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(256), 0, s, bcnt, (int64_t)L.nbuckets + 1);
+  hipLaunchKernelGGL(k_zero2_u32, dim3(64), dim3(256), 0, s, count, (int64_t)L.ntiles, bcnt,
+                     (int64_t)L.nbuckets + 1);
   CNPC_HIP(hipGetLastError());
   SumsArgs sa;
   sa.lmax = sums_lmax;
@@ -1469,17 +1502,18 @@ static cnpc_status fused_sort_and_paint(const cnpc_mesh_desc* d, const uint32_t*
   else launch_bucket_pass<RS, 0>(bs, nblk, lds, pos, w, n, sa, ba, region, ovf_rec, s);
   kt_end(CNPC_KT_SORT, s);
   CNPC_HIP(hipGetLastError());
+  const int per_bucket = 1 << (3 * g.ls);
   if (split_sums) {
     CountArgs none;
     none.ntiles = 0;
     none.count = nullptr;
     CNPC_TRY(sums_counted(d, pos, w, n, sums_lmax, sums, partial, none, s));
+    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, count, L.ntiles, per_bucket, start, cursor, bcur);
   } else {
-    hipLaunchKernelGGL(k_reduce_partials, dim3(CNPC_SUMS_LEN), dim3(64), 0, s, partial, (int)nblk, sums);
-    CNPC_HIP(hipGetLastError());
+    // tile scan and the column sums of the bucket pass's partials in one launch
+    hipLaunchKernelGGL(k_tile_scan_sums, dim3(1 + CNPC_SUMS_LEN), dim3(1024), 0, s, count, L.ntiles, per_bucket,
+                       start, cursor, bcur, partial, (int)nblk, sums);
   }
-  const int per_bucket = 1 << (3 * g.ls);
-  hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, count, L.ntiles, per_bucket, start, cursor, bcur);
   CNPC_HIP(hipGetLastError());
   // tile pass: one workgroup per region chunk, then OVF_BLOCKS over the overflow
   const int tper = partition_per(RS, per_bucket, 1024);
