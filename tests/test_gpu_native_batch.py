@@ -54,6 +54,29 @@ def test_native_batch_matches_single_calls(nstreams, ells):
         assert P.rel(P.host(o["bk"]), bk) < 1e-12
 
 
+@pytest.mark.parametrize("ells", [(0, 2, 4), (0, 2)])
+def test_native_batch_256_matches_single_calls(ells):
+    """At 256^3 with the benchmark's bins the batch takes its own routes: the
+    de-aliased mesh handed to the Y_lm bases pass as z half spectra, the row
+    coefficient table formed once, the shells' c2r inside the contraction;
+    the single calls store the real mesh and form their own table.  Same
+    transforms in differently compiled kernels, so the results agree to FP32
+    rounding (a mistake in the hand-over would show at order one)."""
+    d, bins, sc, plan, cats = _setup(n=256, ncat=2, nb=20)
+    ref = []
+    for g, r in cats:
+        o = pl.measure_pk_bk(d, g, r, bins, plan, ells=ells, scratch=sc)
+        ref.append((P.host(o["pk"]).copy(), P.host(o["bk"]).copy()))
+    b = pl.NativeBatch(d, bins, plan, ells=ells, nstreams=2,
+                       max_ngal=max(g.shape[1] for g, _ in cats), max_nran=max(r.shape[1] for _, r in cats))
+    outs = _outs(cats, plan, bins.nbins)
+    b.run(cats, outs)
+    torch.cuda.synchronize()
+    for (pk, bk), o in zip(ref, outs):
+        assert P.rel(P.host(o["pk"]), pk) < 1e-6
+        assert P.rel(P.host(o["bk"]), bk) < 1e-6
+
+
 @pytest.mark.parametrize("dtype,prec", [(L.F32, L.PREC_BF16X3), (L.F64, L.PREC_F64)])
 def test_native_batch_graph_replays(dtype, prec):
     d, bins, sc, plan, cats = _setup(dtype=dtype, prec=prec, ncat=4)
