@@ -457,8 +457,11 @@ cnpc_status cnpc_bispectrum_fft_noise(const cnpc_bispec_plan* plan, const void* 
  * transforms of the l > 0 multipoles in ells, F_l assembly, the shell means of
  * F_0 F_l^* and F_0 N^* with the l = 0 self term, P_l (cnpc_pk_finalize rows)
  * and the Scoccimarro B_0 of plan with its analytic shot noise (cnpc_bispectrum
- * rows) -- the same calls, in the same order, as the single-catalog entry
- * points.  Catalog i runs on batch stream i mod nstreams; each stream owns a
+ * rows) -- the steps of the single-catalog entry points, in their order, with
+ * two hand-overs of its own on FP32 256^3 meshes: the de-aliased mesh stays as
+ * z half spectra for the Y_lm pass (never stored as a real mesh), and the Y_lm
+ * row coefficients are formed once per run (results equal to FP32 rounding).
+ * Catalog i runs on batch stream i mod nstreams; each stream owns a
  * slab of the caller's workspace for its intermediates, so catalogs on
  * different streams overlap.
  * cnpc_batch_create: plan must be a Scoccimarro l = 0 plan made for desc and
@@ -466,7 +469,9 @@ cnpc_status cnpc_bispectrum_fft_noise(const cnpc_bispec_plan* plan, const void* 
  * [1, 16]; max_ngal / max_nran bound every later catalog (they size the
  * painting scratch).  The batch owns its streams (default priority), events
  * and a captured graph; it keeps a pointer to plan, which must outlive it.
- * cnpc_batch_workspace_size: bytes of device workspace a run needs.
+ * cnpc_batch_workspace_size: bytes of device workspace a run needs (one slab
+ * per stream, and ahead of them the FP32 Y_lm row-coefficient table that every
+ * catalog of a run shares, formed on `stream` before the batch streams fork).
  * cnpc_batch_run: enqueues ncat catalogs.  Host arrays of ncat device
  * pointers: gpos / rpos (3 x n uint32 positions), pk_out (9 x nbins FP64, the
  * cnpc_pk_finalize rows), bk_out (3 x nconf FP64: raw, shot, value); host
