@@ -259,6 +259,66 @@ def test_paint_fkp_matches_separate_calls(n, weights, dtype):
     assert np.array_equal(host(norms2)[:L.NORM_SBARLM + 2], host(norms0)[:L.NORM_SBARLM + 2])
 
 
+_OVF = {}
+
+
+def _overflow_case(weights):
+    """Catalogs that overflow the fixed-capacity bucket regions of the fused
+    bucket pass on a 256^3 mesh (64 buckets of 4^3 tiles): half of each catalog
+    in one bucket's 64^3-node cube, a fifth in one 16^3-node tile, the rest
+    uniform (a survey footprint inside its box is of this kind).  The oracle's
+    norms and meshes are cached per weighting."""
+    if weights in _OVF:
+        return _OVF[weights]
+    rng = np.random.default_rng(31)
+
+    def mix(n, tile_corner):
+        a, b = n // 2, n // 5
+        cube = rng.integers(0, 2 ** 30, size=(3, a), dtype=np.uint32)
+        tile = rng.integers(0, 2 ** 28, size=(3, b), dtype=np.uint32) + np.uint32(tile_corner)
+        rest = rng.integers(0, 2 ** 32, size=(3, n - a - b), dtype=np.uint32)
+        p = np.concatenate([cube, tile, rest], axis=1)
+        return np.ascontiguousarray(p[:, rng.permutation(n)])
+
+    g, r = mix(150_000, 2 ** 31), mix(600_000, 3 * 2 ** 30)
+    gw = rng.uniform(0.5, 1.5, g.shape[1]).astype(np.float32) if weights else None
+    rw = rng.uniform(0.5, 1.5, r.shape[1]).astype(np.float32) if weights else None
+    ora = catalog_norms(g, gw, r, rw, 1000.0, OBS, (0, 2, 4))
+    od, onm = oms.paint_fkp(g, gw, r, rw, ora.alpha, 256, L.TSC, True, noise=True)
+    _OVF[weights] = (g, gw, r, rw, ora, od, onm)
+    return _OVF[weights]
+
+
+@pytest.mark.parametrize("bucket,sums_lmax,weights", [(0, 0, False), (0, 4, False), (1, 0, False),
+                                                      (2, 4, False), (3, 0, False), (0, 4, True)])
+def test_paint_fkp_bucket_overflow(bucket, sums_lmax, weights):
+    """The fused bucket pass when most records overflow their bucket regions
+    (the tile pass then walks the overflow records with one slot per record),
+    for every bucket-pass shape: meshes against the oracle's and against the
+    separate calls, whose sort has no capacity limit."""
+    from paper_2605_04864_amd import autotune
+    g, gw, r, rw, ora, od, onm = _overflow_case(weights)
+    d = cn.mesh_desc(256, 1000.0, assign=L.TSC, interlace=True, dtype=L.F32, observer=OBS)
+    gt, rt = dev(g), dev(r)
+    gwt = dev(gw) if weights else None
+    rwt = dev(rw) if weights else None
+    autotune.set_knobs({"bucket": bucket})
+    try:
+        norms, delta, nmesh, _, _ = pl.paint_fkp(d, gt, rt, gwt, rwt, noise=True, sums_lmax=sums_lmax)
+        hn, hd, hnm = host(norms), host(delta), host(nmesh)
+    finally:
+        autotune.reset_knobs()
+    for k, v in ((L.NORM_ALPHA, ora.alpha), (L.NORM_I22, ora.I22), (L.NORM_N0, ora.N0)):
+        assert math.isclose(hn[k], v, rel_tol=1e-12)
+    for ph in range(2):
+        assert rel(hd[ph], od[ph]) < 20 * TOL[L.F32]
+        assert rel(hnm[ph], onm[ph]) < 20 * TOL[L.F32]
+    norms2, _, _ = pl.catalog_norms(d, gt, rt, gwt, rwt)
+    delta2, nmesh2 = pl.paint(d, gt, rt, norms2, gwt, rwt, noise=True)
+    assert rel(hd, host(delta2)) < 1e-6
+    assert rel(hnm, host(nmesh2)) < 1e-6
+
+
 def test_paint_single_particle_cells_bit_exact():
     n, box = 32, 100.0
     rng = np.random.default_rng(9)
