@@ -30,9 +30,14 @@ Racah-normalised associated Legendre functions, y_l^n(theta, phi = 0).
 Pins: the estimator against a direct sum over mode pairs, B_000 against the
 compressed BB_000, realness, the pairing identity and the conjugation
 symmetries.  The shot noise is pinned by its (0, 0, 0) reduction to the
-compressed estimator's and by q_l0l = L_l (l 0 l; 0 0 0); beyond those special
-cases the i = j != k term of l1, l2 > 0 is parity unpinned (its associated
-Legendre sum follows the printed formula).  The FFT-method term is pinned by a
+compressed estimator's, by q_l0l = L_l (l 0 l; 0 0 0), by q_l1l2L equal to the
+frame-free invariant of the three closed-triangle directions (spherical
+harmonics from scipy, any orientation, l1, l2 > 0 included), and for (0, 0, 0),
+(2, 0, 2) and (4, 0, 4) by the FFT method on a Poisson catalog (thin-shell
+tolerance, lowest bins aside for (0, 0, 0) and (4, 0, 4)); for l1, l2 > 0 the
+i = j != k term is a small residual that the FFT method does not resolve on
+such catalogs, so its bin sum over c is pinned only through the l2 = 0 cases,
+which share it.  The FFT-method term is pinned by a
 direct sum over mode pairs and, for (0, 0, 0), by the compressed estimator's
 FFT-method noise.
 
