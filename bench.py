@@ -131,6 +131,29 @@ def copy_probe(mib: int):
     print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4, "launches": 5}))
 
 
+def copy_rate_gbs(mib: int = 2048, reps: int = 10) -> float:
+    """Achievable HBM rate of a plain streaming copy, b = 1 * a through torch's
+    elementwise kernel (6.1-6.2 TB/s on MI355X, where its blit copy b.copy_(a)
+    reaches 4.3-5.0), on arrays far larger than the 256 MB last-level cache:
+    bytes read plus written per second, median of `reps` copies timed with HIP
+    events."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.rand(n, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        torch.mul(a, 1.0, out=b)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    ev[0].record()
+    for k in range(reps):
+        torch.mul(a, 1.0, out=b)
+        ev[k + 1].record()
+    torch.cuda.synchronize()
+    ms = float(np.median([ev[k].elapsed_time(ev[k + 1]) for k in range(reps)]))
+    del a, b
+    return 2.0 * n * 4 / (ms / 1e3) / 1e9
+
+
 def main():
     args = parse()
     if args.cpu_sample_worker:
@@ -292,6 +315,8 @@ def main():
         del sc64
     cpu = None if args.no_cpu else cpu_baseline(mocks, sizes, log=lambda *m: log(args, *m),
                                                 workers=args.cpu_workers or None)
+    copy_gbs = copy_rate_gbs()
+    log(args, f"plain streaming copy: {copy_gbs:.0f} GB/s")
 
     # kernel times: the batch once more, eagerly on a single stream (kernels
     # unshared, so each launch's time is that kernel's own), every launch of the
@@ -327,6 +352,8 @@ def main():
     roof["traffic"] = measured_traffic(roof["kernel"])
     if roof["traffic"] is not None:
         roof["traffic_over_algorithmic"] = roof["traffic"] / roof["per_launch"]
+    roof["copy_gbs"] = copy_gbs
+    roof["frac_of_copy"] = roof["achieved"] / copy_gbs
     roof["durations_from"] = (f"HIP events around each launch of a single-stream eager pass of the "
                               f"batch run last ({ms_instr:.1f} ms for the batch)")
     kern_ms = {k: round(v["ms"], 3) for k, v in kern.items()}
@@ -358,6 +385,8 @@ def main():
                                "dk=0.01) with analytic shot noise",
                    "global_batch": args.mocks, "nmesh": 256, "particles_total": ntot},
         "pipeline_hbm_frac": (hbm_bytes / (ms_step / 1e3)) / (HBM_PEAK_GBS * 1e9),
+        "hbm_copy_gbs": copy_gbs,
+        "pipeline_copy_frac": (hbm_bytes / (ms_step / 1e3)) / (copy_gbs * 1e9),
         "kernels_ms_per_step": kern_ms,
         "roofline": roof,
         "roofline_by_stage": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv)
