@@ -184,15 +184,21 @@ def main():
     t0 = time.time()
     mocks, sizes = make_mocks(args.mocks)
     log(args, f"generated {args.mocks} mocks in {time.time() - t0:.1f}s")
+    t_up = time.perf_counter()
     gpu_mocks = [(torch.from_numpy(g).to(dev), torch.from_numpy(r).to(dev)) for g, r in mocks]
     torch.cuda.synchronize()
+    t_up = time.perf_counter() - t_up
+    up_bytes = float(sum(g.nbytes + r.nbytes for g, r in mocks))
     log(args, f"uploaded in {time.time() - t0:.1f}s")
     obs = synthcat.observer_position()
     bins = cn.kbins(0.0, 0.01, 20)
     prec = L.PREC_BF16X3 if args.precision == "bf16x3" else L.PREC_F32
     desc = cn.mesh_desc(256, 1000.0, assign=L.TSC, interlace=True, dtype=L.F32, observer=obs)
     sc = pl.Scratch()
+    t_plan = time.perf_counter()
     plan = pl.bispec_plan(desc, bins, L.EST_SCOCCIMARRO, 0, prec, sc)
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t_plan
     outs = [{"pk": torch.empty((9, 20), dtype=torch.float64, device=dev),
              "bk": torch.empty((3, plan.nconf), dtype=torch.float64, device=dev)} for _ in gpu_mocks]
     tuning = None
@@ -222,8 +228,10 @@ def main():
         def step():
             batch.run(desc, gpu_mocks, bins, plan, outs)
 
+    t_eager = time.perf_counter()
     step()  # eager pass: plans, twiddles and scratch reach their final size
     torch.cuda.synchronize()
+    t_eager = time.perf_counter() - t_eager
     eager = [(o["pk"].clone(), o["bk"].clone()) for o in outs]
     vs_oracle = smallest_mock_vs_oracle(mocks, sizes, eager, args.mocks)
 
@@ -234,6 +242,7 @@ def main():
     model = {k: float(np.sum([m[k] for m in models])) for k in models[0]}  # per step
 
     run = step
+    t_cap = None
     if args.graph_per_stream and not args.no_graph:
         # one single-stream graph per stream, replayed side by side
         graphs = []
@@ -254,7 +263,10 @@ def main():
                 cur.wait_stream(s)
         log(args, f"captured {len(graphs)} single-stream graphs")
     elif not args.no_graph and native:
+        t_cap = time.perf_counter()
         batch.capture(gpu_mocks, outs)
+        torch.cuda.synchronize()
+        t_cap = time.perf_counter() - t_cap
         run = batch.replay
         log(args, "captured the batch as one graph (cnpc_batch_capture)")
     elif not args.no_graph:
@@ -379,6 +391,9 @@ def main():
         "streams": nstreams,
         "placement": args.balance,
         "tuning": tuning,
+        "setup_s": {"upload": round(t_up, 3), "upload_gbs_pcie": round(up_bytes / t_up / 1e9, 2),
+                    "bispec_plan": round(t_plan, 3), "first_eager_batch": round(t_eager, 3),
+                    "graph_capture": None if t_cap is None else round(t_cap, 3)},
         "data": "synthetic lognormal mocks (seeded), resident in HBM",
         "config": {"workload": "64 uneven lognormal mocks (N_g 1e6-8e6 log-uniform, 10x randoms), "
                                "256^3 TSC + interlacing, L=1000, P_0,2,4 + Scoccimarro B_0 (20 bins, "
