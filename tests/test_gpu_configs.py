@@ -12,7 +12,8 @@
   the library's batch runner and its captured graph, FP32 / split BF16
   against the FP64 path (1e-5 / 1e-3), configurations, N_T and mode counts.
 * c5 (512^3, L = 2000, 3e7 + 3e8, 40 bins of 0.005): TripoSH B_202 in split
-  BF16 (1e-3) and FP32 (1e-5) against FP64.
+  BF16 (1e-3) and FP32 (1e-5) against FP64; mode counts and k_eff against the
+  oracle's binning of the whole 512^3 grid.
 
 Catalogs follow the benchmark recipe (seed 1000 * config for galaxies, + 1 for
 randoms).
@@ -133,6 +134,21 @@ def test_c5_full_triposh_precisions():
         assert np.all(np.isfinite(out["f64"][k]))
         assert P.rel(out["f32"][k], out["f64"][k]) < 1e-5, k
         assert P.rel(out["bf16"][k], out["f64"][k]) < 1e-3, k
+
+
+def test_c5_mode_counts_vs_oracle():
+    """c5's binning at full size (512^3, L = 2000, 40 bins of 0.005): the mode
+    counts of every bin bit-exact and k_eff within 1e-12 against the oracle's
+    integer-n^2 binning of the whole grid (FP32 and FP64 paths)."""
+    spec, g, r, gd, rd = catalogs(5)
+    ds = descs(spec)
+    bins = cn.kbins(0.0, spec.dk, spec.nbins)
+    ob = osp.Bins(0.0, spec.dk, spec.nbins, spec.boxsize, spec.nmesh)
+    counts, keff = ob.counts(), ob.k_eff()
+    for dt in (L.F32, L.F64):
+        res = pl.measure_pk(ds[dt], gd, rd, bins, ells=(0, 2))
+        assert np.array_equal(P.host(res["nmodes"]), counts)
+        assert P.rel(P.host(res["k_eff"]), keff) < 1e-12
 
 
 def test_c4_batch_graph_vs_fp64():
