@@ -1,7 +1,8 @@
 // Catalog sums, normalisations and FKP mass assignment (CIC / TSC, interlacing).
 //
 // Painting: particles are counting-sorted by 16^3-node tile (two LDS-staged
-// steps: by bucket of tiles, then by tile), each tile's particles are
+// steps: by bucket of tiles, then by tile; for the FP32 painter the second step
+// writes 8-byte tile-relative records), each tile's particles are
 // accumulated into a 19^3-node LDS block (the tile plus the stencil halo) with
 // LDS atomics, blocks are written out without atomics, and a fold pass sums
 // the <= 8 blocks covering every node while forming delta = n_g - alpha n_r and
@@ -41,6 +42,30 @@ template <int RS>
 struct Rec {
   uint32_t v[RS];
 };
+
+// Tile-sorted record of the FP32 painter (unweighted catalogs): the 21 bits of
+// each coordinate below the tile index, i.e. the 4 node bits inside the
+// 16-node tile and the top 17 fraction bits, in 8 bytes (x | y << 21 | z << 42).
+// Positions keep a 2^-17 cell grid, finer than FP32 coordinates of a 256-cell
+// box resolve; needs shift >= 17 (meshes up to 2^15 per side).
+__device__ __forceinline__ uint64_t pack_rec(const Rec<3>& r, int shift) {
+  const uint32_t m = shift + 4 >= 32 ? 0xffffffffu : ((1u << (shift + 4)) - 1u);
+  const int down = shift - 17;
+  return (uint64_t)((r.v[0] & m) >> down) | ((uint64_t)((r.v[1] & m) >> down) << 21) |
+         ((uint64_t)((r.v[2] & m) >> down) << 42);
+}
+
+// a tile-sorted record out: in full, or packed (pack_rec) for the FP32 painter
+template <int RS>
+__device__ __forceinline__ void put_rec(Rec<RS>* out, uint32_t o, const Rec<RS>& r, bool pack, int shift) {
+  if constexpr (RS == 3) {
+    if (pack) {
+      reinterpret_cast<uint64_t*>(out)[o] = pack_rec(r, shift);
+      return;
+    }
+  }
+  out[o] = r;
+}
 
 // catalog positions read once by the sums pass: non-temporal loads
 __device__ __forceinline__ uint32_t ld_stream(const uint32_t* p) { return __builtin_nontemporal_load(p); }
@@ -353,7 +378,7 @@ __global__ void __launch_bounds__(NT) k_partition(const uint32_t* __restrict__ p
                                                             const Rec<RS>* __restrict__ rin,
                                                             int64_t n, TileGeom g, int rcap,
                                                             uint32_t* __restrict__ cursor,
-                                                            Rec<RS>* __restrict__ rout) {
+                                                            Rec<RS>* __restrict__ rout, bool pack) {
   constexpr int CH = NT * PER;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   Rec<RS>* stage = reinterpret_cast<Rec<RS>*>(smem_raw);                        // [CH]
@@ -397,7 +422,7 @@ __global__ void __launch_bounds__(NT) k_partition(const uint32_t* __restrict__ p
     // wide key range: one global slot per particle
 #pragma unroll
     for (int k = 0; k < PER; ++k)
-      if (key[k] >= 0) rout[atomicAdd(&cursor[klo + key[k]], 1u)] = r[k];
+      if (key[k] >= 0) put_rec(rout, atomicAdd(&cursor[klo + key[k]], 1u), r[k], FINE && pack, g.shift);
     return;
   }
   for (int t = threadIdx.x; t < R; t += NT) hist[t] = 0u;
@@ -424,7 +449,7 @@ __global__ void __launch_bounds__(NT) k_partition(const uint32_t* __restrict__ p
   const int cnt = (int)min((int64_t)CH, n - c0);
   for (int j = threadIdx.x; j < cnt; j += NT) {
     const int kk = skey[j];
-    rout[gbase[kk] + (j - lstart[kk])] = stage[j];
+    put_rec(rout, gbase[kk] + (j - lstart[kk]), stage[j], FINE && pack, g.shift);
   }
 }
 
@@ -582,7 +607,7 @@ __global__ void __launch_bounds__(NT) k_tile_pass(const Rec<RS>* __restrict__ re
                                                   const Rec<RS>* __restrict__ ovf_in, const uint32_t* __restrict__ bcnt,
                                                   const uint32_t* __restrict__ ovf, uint32_t cap, int chunks_per_bucket,
                                                   int nbuckets, TileGeom g, uint32_t* __restrict__ cursor,
-                                                  Rec<RS>* __restrict__ rout) {
+                                                  Rec<RS>* __restrict__ rout, bool pack) {
   constexpr int CH = NT * PER;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int bshift = 3 * g.ls;
@@ -596,7 +621,7 @@ __global__ void __launch_bounds__(NT) k_tile_pass(const Rec<RS>* __restrict__ re
         const int64_t i = c0 + (int64_t)k * NT + threadIdx.x;
         if (i < no) {
           const Rec<RS> rr = ovf_in[i];
-          rout[atomicAdd(&cursor[tile_key(rr.v[0], rr.v[1], rr.v[2], g)], 1u)] = rr;
+          put_rec(rout, atomicAdd(&cursor[tile_key(rr.v[0], rr.v[1], rr.v[2], g)], 1u), rr, pack, g.shift);
         }
       }
     }
@@ -646,7 +671,7 @@ __global__ void __launch_bounds__(NT) k_tile_pass(const Rec<RS>* __restrict__ re
   __syncthreads();
   for (int j = threadIdx.x; j < cnt; j += NT) {
     const int kk = skey[j];
-    rout[gbase[kk] + (j - lstart[kk])] = stage[j];
+    put_rec(rout, gbase[kk] + (j - lstart[kk]), stage[j], pack, g.shift);
   }
 }
 
@@ -763,7 +788,9 @@ __global__ void __launch_bounds__(1024) k_paint_tiles(const Rec<RS>* __restrict_
 // 1024 * 1 * 2^21), so the 32-bit sums are exact.  After every interval each
 // thread moves the nodes it owns into 64-bit registers and clears them.  The
 // result equals the 64-bit fixed-point sum of the contributions rounded to
-// 2^-21 (half up), independent of the order of the additions.
+// 2^-21 (half up), independent of the order of the additions.  The particles
+// come as packed 8-byte records (pack_rec): positions inside the tile on a
+// 2^-17 cell grid.
 constexpr int PAINT32_THREADS = 1024;
 constexpr int PAINT32_OWN = (2 * BVOL + PAINT32_THREADS - 1) / PAINT32_THREADS;  // nodes per thread
 
@@ -832,8 +859,12 @@ __global__ void __launch_bounds__(PAINT32_THREADS, 8) k_paint_tiles_u32(const Re
   for (uint32_t base = 0; base < cnt; base += PAINT32_THREADS) {
     const uint32_t k = base + threadIdx.x;
     if (k < cnt) {
-      const Rec<3> p = rec[(int64_t)s0 + k];
-      const uint32_t px = p.v[0], py = p.v[1], pz = p.v[2];
+      // packed record (pack_rec): tile-relative positions on the 2^-17 cell grid
+      const uint64_t q = reinterpret_cast<const uint64_t*>(rec)[(int64_t)s0 + k];
+      const int up = shift - 17;
+      const uint32_t px = (uint32_t)(q & 0x1fffffu) << up;
+      const uint32_t py = (uint32_t)((q >> 21) & 0x1fffffu) << up;
+      const uint32_t pz = (uint32_t)((q >> 42) & 0x1fffffu) << up;
       const int bx = ((int)(px >> shift) & 15) + 1;
       const int by = ((int)(py >> shift) & 15) + 1;
       const int bz = ((int)(pz >> shift) & 15) + 1;
@@ -1277,21 +1308,21 @@ static int partition_per(int rs, int rcap, int nt) {
 template <bool SOA, bool FINE, int RS, int NT>
 static void launch_partition_nt(int per, unsigned nblk, size_t lds, const uint32_t* pos, const float* w,
                                 const Rec<RS>* rin, int64_t n, const TileGeom& g, int rcap, uint32_t* cursor,
-                                Rec<RS>* rout, hipStream_t s) {
+                                Rec<RS>* rout, bool pack, hipStream_t s) {
   if (per == 4)
     hipLaunchKernelGGL((k_partition<SOA, FINE, RS, 4, NT>), dim3(nblk), dim3(NT), lds, s, pos, w, rin, n, g,
-                       rcap, cursor, rout);
+                       rcap, cursor, rout, pack);
   else if (per == 2)
     hipLaunchKernelGGL((k_partition<SOA, FINE, RS, 2, NT>), dim3(nblk), dim3(NT), lds, s, pos, w, rin, n, g,
-                       rcap, cursor, rout);
+                       rcap, cursor, rout, pack);
   else
     hipLaunchKernelGGL((k_partition<SOA, FINE, RS, 1, NT>), dim3(nblk), dim3(NT), lds, s, pos, w, rin, n, g,
-                       rcap, cursor, rout);
+                       rcap, cursor, rout, pack);
 }
 
 template <bool SOA, bool FINE, int RS>
 static cnpc_status launch_partition(const uint32_t* pos, const float* w, const Rec<RS>* rin, int64_t n,
-                                    const TileGeom& g, int rcap, uint32_t* cursor, Rec<RS>* rout,
+                                    const TileGeom& g, int rcap, uint32_t* cursor, Rec<RS>* rout, bool pack,
                                     hipStream_t s) {
   const int nt = tune_value(CNPC_TUNE_SORT_THREADS) == 512 ? 512 : 1024;
   const int per = partition_per(RS, rcap, nt);
@@ -1304,9 +1335,9 @@ static cnpc_status launch_partition(const uint32_t* pos, const float* w, const R
   const size_t lds = partition_lds(per, RS, rcap, nt);
   kt_begin(CNPC_KT_SORT, s);
   if (nt == 512)
-    launch_partition_nt<SOA, FINE, RS, 512>(per, nblk, lds, pos, w, rin, n, g, rcap, cursor, rout, s);
+    launch_partition_nt<SOA, FINE, RS, 512>(per, nblk, lds, pos, w, rin, n, g, rcap, cursor, rout, pack, s);
   else
-    launch_partition_nt<SOA, FINE, RS, 1024>(per, nblk, lds, pos, w, rin, n, g, rcap, cursor, rout, s);
+    launch_partition_nt<SOA, FINE, RS, 1024>(per, nblk, lds, pos, w, rin, n, g, rcap, cursor, rout, pack, s);
   kt_end(CNPC_KT_SORT, s);
   CNPC_HIP(hipGetLastError());
   return CNPC_OK;
@@ -1379,11 +1410,12 @@ static cnpc_status sort_and_paint(const cnpc_mesh_desc* d, const uint32_t* pos, 
   const int per_bucket = 1 << (3 * g.ls);
   hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, count, L.ntiles, per_bucket, start, cursor, bcur);
   CNPC_HIP(hipGetLastError());
+  const bool pack = sizeof(T) == 4 && RS == 3;  // records of the FP32 painter
   if (L.nbuckets > 1) {
-    CNPC_TRY((launch_partition<true, false, RS>(pos, w, nullptr, n, g, L.nbuckets, bcur, tmp, s)));
-    CNPC_TRY((launch_partition<false, true, RS>(nullptr, nullptr, tmp, n, g, FINE_RCAP, cursor, rec, s)));
+    CNPC_TRY((launch_partition<true, false, RS>(pos, w, nullptr, n, g, L.nbuckets, bcur, tmp, false, s)));
+    CNPC_TRY((launch_partition<false, true, RS>(nullptr, nullptr, tmp, n, g, FINE_RCAP, cursor, rec, pack, s)));
   } else {
-    CNPC_TRY((launch_partition<true, true, RS>(pos, w, nullptr, n, g, L.ntiles, cursor, rec, s)));
+    CNPC_TRY((launch_partition<true, true, RS>(pos, w, nullptr, n, g, L.ntiles, cursor, rec, pack, s)));
   }
   return paint_sorted<T, RS>(d, weighted, set0, ws, L, s);
 }
@@ -1523,18 +1555,19 @@ static cnpc_status fused_sort_and_paint(const cnpc_mesh_desc* d, const uint32_t*
   }
   const int64_t tch = (int64_t)1024 * tper;
   const int cpb = (int)((cap + tch - 1) / tch);
+  const bool pack = sizeof(T) == 4 && RS == 3;  // records of the FP32 painter
   const unsigned tgrid = (unsigned)(L.nbuckets * cpb + OVF_BLOCKS);
   const size_t tlds = partition_lds(tper, RS, per_bucket, 1024);
   kt_begin(CNPC_KT_SORT, s);
   if (tper == 4)
     hipLaunchKernelGGL((k_tile_pass<RS, 4, 1024>), dim3(tgrid), dim3(1024), tlds, s, region, ovf_rec, bcnt,
-                       bcnt + L.nbuckets, cap, cpb, L.nbuckets, g, cursor, rec);
+                       bcnt + L.nbuckets, cap, cpb, L.nbuckets, g, cursor, rec, pack);
   else if (tper == 2)
     hipLaunchKernelGGL((k_tile_pass<RS, 2, 1024>), dim3(tgrid), dim3(1024), tlds, s, region, ovf_rec, bcnt,
-                       bcnt + L.nbuckets, cap, cpb, L.nbuckets, g, cursor, rec);
+                       bcnt + L.nbuckets, cap, cpb, L.nbuckets, g, cursor, rec, pack);
   else
     hipLaunchKernelGGL((k_tile_pass<RS, 1, 1024>), dim3(tgrid), dim3(1024), tlds, s, region, ovf_rec, bcnt,
-                       bcnt + L.nbuckets, cap, cpb, L.nbuckets, g, cursor, rec);
+                       bcnt + L.nbuckets, cap, cpb, L.nbuckets, g, cursor, rec, pack);
   kt_end(CNPC_KT_SORT, s);
   CNPC_HIP(hipGetLastError());
   return paint_sorted<T, RS>(d, weighted, set0, ws, L, s);
