@@ -1,8 +1,9 @@
 // Catalog sums, normalisations and FKP mass assignment (CIC / TSC, interlacing).
 //
 // Painting: particles are counting-sorted by 16^3-node tile (two LDS-staged
-// steps: by bucket of tiles, then by tile; for the FP32 painter the second step
-// writes 8-byte tile-relative records), each tile's particles are
+// steps: by bucket of tiles, then by tile; for the FP32 painter on meshes of
+// 256^3 and more the second step writes 8-byte tile-relative records), each
+// tile's particles are
 // accumulated into a 19^3-node LDS block (the tile plus the stencil halo) with
 // LDS atomics, blocks are written out without atomics, and a fold pass sums
 // the <= 8 blocks covering every node while forming delta = n_g - alpha n_r and
@@ -43,11 +44,16 @@ struct Rec {
   uint32_t v[RS];
 };
 
-// Tile-sorted record of the FP32 painter (unweighted catalogs): the 21 bits of
-// each coordinate below the tile index, i.e. the 4 node bits inside the
-// 16-node tile and the top 17 fraction bits, in 8 bytes (x | y << 21 | z << 42).
-// Positions keep a 2^-17 cell grid, finer than FP32 coordinates of a 256-cell
-// box resolve; needs shift >= 17 (meshes up to 2^15 per side).
+// Tile-sorted record of the FP32 painter (unweighted catalogs, meshes of 256^3
+// and more): the 21 bits of each coordinate below the tile index, i.e. the 4
+// node bits inside the 16-node tile and the top 17 fraction bits, in 8 bytes
+// (x | y << 21 | z << 42).  Positions keep a 2^-17 cell grid, finer than FP32
+// coordinates of a 256-cell box resolve; needs shift >= 17 (meshes up to 2^15
+// per side).  The grid's jitter scales with the cell size, so coarser meshes,
+// whose binned k reach closer to their Nyquist wavenumber, keep full records.
+__host__ __device__ constexpr bool packs_records(bool f32, int rs, int shift) {
+  return f32 && rs == 3 && shift <= 24;
+}
 __device__ __forceinline__ uint64_t pack_rec(const Rec<3>& r, int shift) {
   const uint32_t m = shift + 4 >= 32 ? 0xffffffffu : ((1u << (shift + 4)) - 1u);
   const int down = shift - 17;
@@ -788,9 +794,9 @@ __global__ void __launch_bounds__(1024) k_paint_tiles(const Rec<RS>* __restrict_
 // 1024 * 1 * 2^21), so the 32-bit sums are exact.  After every interval each
 // thread moves the nodes it owns into 64-bit registers and clears them.  The
 // result equals the 64-bit fixed-point sum of the contributions rounded to
-// 2^-21 (half up), independent of the order of the additions.  The particles
-// come as packed 8-byte records (pack_rec): positions inside the tile on a
-// 2^-17 cell grid.
+// 2^-21 (half up), independent of the order of the additions.  From 256^3 up
+// the particles come as packed 8-byte records (pack_rec): positions inside the
+// tile on a 2^-17 cell grid.
 constexpr int PAINT32_THREADS = 1024;
 constexpr int PAINT32_OWN = (2 * BVOL + PAINT32_THREADS - 1) / PAINT32_THREADS;  // nodes per thread
 
@@ -839,7 +845,7 @@ template <int ASSIGN>
 __global__ void __launch_bounds__(PAINT32_THREADS, 8) k_paint_tiles_u32(const Rec<3>* __restrict__ rec,
                                                                      const uint32_t* __restrict__ start,
                                                                      const uint32_t* __restrict__ count,
-                                                                     TileGeom g, int nphase,
+                                                                     TileGeom g, int nphase, bool packed,
                                                                      float* __restrict__ blocks) {
   constexpr float SCALE = 2097152.0f;  // 2^21
   constexpr int ROUNDS_PER_FLUSH = ASSIGN == CNPC_TSC ? 4 : 1;
@@ -859,12 +865,19 @@ __global__ void __launch_bounds__(PAINT32_THREADS, 8) k_paint_tiles_u32(const Re
   for (uint32_t base = 0; base < cnt; base += PAINT32_THREADS) {
     const uint32_t k = base + threadIdx.x;
     if (k < cnt) {
-      // packed record (pack_rec): tile-relative positions on the 2^-17 cell grid
-      const uint64_t q = reinterpret_cast<const uint64_t*>(rec)[(int64_t)s0 + k];
-      const int up = shift - 17;
-      const uint32_t px = (uint32_t)(q & 0x1fffffu) << up;
-      const uint32_t py = (uint32_t)((q >> 21) & 0x1fffffu) << up;
-      const uint32_t pz = (uint32_t)((q >> 42) & 0x1fffffu) << up;
+      uint32_t px, py, pz;
+      if (packed) {  // pack_rec: tile-relative positions on the 2^-17 cell grid
+        const uint64_t q = reinterpret_cast<const uint64_t*>(rec)[(int64_t)s0 + k];
+        const int up = shift - 17;
+        px = (uint32_t)(q & 0x1fffffu) << up;
+        py = (uint32_t)((q >> 21) & 0x1fffffu) << up;
+        pz = (uint32_t)((q >> 42) & 0x1fffffu) << up;
+      } else {
+        const Rec<3> p = rec[(int64_t)s0 + k];
+        px = p.v[0];
+        py = p.v[1];
+        pz = p.v[2];
+      }
       const int bx = ((int)(px >> shift) & 15) + 1;
       const int by = ((int)(py >> shift) & 15) + 1;
       const int bz = ((int)(pz >> shift) & 15) + 1;
@@ -1361,10 +1374,10 @@ static cnpc_status paint_sorted(const cnpc_mesh_desc* d, bool weighted, int set0
       kt_begin(CNPC_KT_PAINT, s);
       if (d->assign == CNPC_TSC)
         hipLaunchKernelGGL((k_paint_tiles_u32<CNPC_TSC>), dim3(L.ntiles), dim3(PAINT32_THREADS), 0, s, rec, start,
-                           count, g, L.nphase, reinterpret_cast<float*>(blocks));
+                           count, g, L.nphase, packs_records(true, 3, g.shift), reinterpret_cast<float*>(blocks));
       else
         hipLaunchKernelGGL((k_paint_tiles_u32<CNPC_CIC>), dim3(L.ntiles), dim3(PAINT32_THREADS), 0, s, rec, start,
-                           count, g, L.nphase, reinterpret_cast<float*>(blocks));
+                           count, g, L.nphase, packs_records(true, 3, g.shift), reinterpret_cast<float*>(blocks));
       kt_end(CNPC_KT_PAINT, s);
       CNPC_HIP(hipGetLastError());
       continue;
@@ -1410,7 +1423,7 @@ static cnpc_status sort_and_paint(const cnpc_mesh_desc* d, const uint32_t* pos, 
   const int per_bucket = 1 << (3 * g.ls);
   hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, count, L.ntiles, per_bucket, start, cursor, bcur);
   CNPC_HIP(hipGetLastError());
-  const bool pack = sizeof(T) == 4 && RS == 3;  // records of the FP32 painter
+  const bool pack = packs_records(sizeof(T) == 4, RS, g.shift);  // records of the FP32 painter
   if (L.nbuckets > 1) {
     CNPC_TRY((launch_partition<true, false, RS>(pos, w, nullptr, n, g, L.nbuckets, bcur, tmp, false, s)));
     CNPC_TRY((launch_partition<false, true, RS>(nullptr, nullptr, tmp, n, g, FINE_RCAP, cursor, rec, pack, s)));
@@ -1555,7 +1568,7 @@ static cnpc_status fused_sort_and_paint(const cnpc_mesh_desc* d, const uint32_t*
   }
   const int64_t tch = (int64_t)1024 * tper;
   const int cpb = (int)((cap + tch - 1) / tch);
-  const bool pack = sizeof(T) == 4 && RS == 3;  // records of the FP32 painter
+  const bool pack = packs_records(sizeof(T) == 4, RS, g.shift);  // records of the FP32 painter
   const unsigned tgrid = (unsigned)(L.nbuckets * cpb + OVF_BLOCKS);
   const size_t tlds = partition_lds(tper, RS, per_bucket, 1024);
   kt_begin(CNPC_KT_SORT, s);
