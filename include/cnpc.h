@@ -142,7 +142,10 @@ cnpc_status cnpc_norms(const cnpc_mesh_desc* desc, const double* gal_sums, const
  * delta and noise each hold (1 + interlace) N^3 elements of desc->dtype.
  * Particles are counting-sorted by 16^3-node tiles and accumulated in LDS as
  * integer fixed point (2^-40 units; 2^-21 for unit-weight FP32), so the
- * meshes do not depend on the order of the additions.
+ * meshes do not depend on the order of the additions.  Unit-weight FP32
+ * meshes of 256^3 and more take the positions truncated to a 2^-17 cell grid
+ * inside their tile (8-byte sort records); the FP64 path, weighted catalogs,
+ * coarser meshes and the catalog sums use the full 32-bit positions.
  * Workspace: cnpc_paint_workspace_size bytes (an upper bound for weighted and
  * unweighted catalogs), owned by the caller, not retained after the call. */
 size_t cnpc_paint_workspace_size(const cnpc_mesh_desc* desc, int64_t ngal, int64_t nran);
