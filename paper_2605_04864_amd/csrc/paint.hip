@@ -2,8 +2,9 @@
 //
 // Painting: particles are counting-sorted by 16^3-node tile (two LDS-staged
 // steps: by bucket of tiles, then by tile; for the FP32 painter on meshes of
-// 256^3 and more the second step writes 8-byte tile-relative records), each
-// tile's particles are
+// 256^3 and more the records are 8-byte tile-relative ones from the first step
+// on, with a 16-bit tile index beside them up to 2^16 tiles), each tile's
+// particles are
 // accumulated into a 19^3-node LDS block (the tile plus the stencil halo) with
 // LDS atomics, blocks are written out without atomics, and a fold pass sums
 // the <= 8 blocks covering every node while forming delta = n_g - alpha n_r and
@@ -466,7 +467,12 @@ __global__ void __launch_bounds__(NT) k_partition(const uint32_t* __restrict__ p
 // bcnt[b] and sends whatever would pass the capacity to the overflow region
 // (reserved on *ovf), which the tile pass takes as chunks of mixed buckets.
 // Persistent workgroups walk chunks of NT * PER particles, so the LDS tile
-// histogram is flushed with one atomic per non-empty tile per workgroup.
+// histogram is flushed with one atomic per non-empty tile per workgroup.  With
+// `pack` (FP32 painter, unweighted, 256^3 and more, at most 2^16 tiles) a
+// record goes out as pack_rec in 8 bytes and its tile index in 2 more, in an
+// array after the 8-byte records of its region (both fit the 12-byte records'
+// room); the LDS then also stages each record's tile index after the tile
+// histogram.
 struct BucketArgs {
   TileGeom g;
   int ntiles, nbuckets;
@@ -475,6 +481,9 @@ struct BucketArgs {
   uint32_t* ovf;      // overflow records reserved
   uint32_t* tcount;   // [ntiles] tile histogram
   double* partial;    // [gridDim.x][CNPC_SUMS_LEN] catalog-sum partials
+  bool pack;          // records out as pack_rec + a 16-bit tile index (rkey / okey)
+  uint16_t* rkey;     // [nbuckets * cap] tile index of each region record (pack)
+  uint16_t* okey;     // [n] tile index of each overflow record (pack)
 };
 
 // LDS bytes of k_bucket_pass
@@ -520,6 +529,7 @@ __global__ void __launch_bounds__(NT) k_bucket_pass(const uint32_t* __restrict__
       if constexpr (RS == 4) dst[k].v[3] = __float_as_uint(w[i]);
     }
   };
+  uint16_t* stile = reinterpret_cast<uint16_t*>(ltile + (lds_tiles ? ba.ntiles : 0));  // [CH] (pack)
   Rec<RS> rn[PF ? PER : 1];
   if constexpr (PF) load_chunk((int64_t)blockIdx.x * CH, rn);
   for (int64_t c0 = (int64_t)blockIdx.x * CH; c0 < n; c0 += stride) {
@@ -538,11 +548,14 @@ __global__ void __launch_bounds__(NT) k_bucket_pass(const uint32_t* __restrict__
     }
     __syncthreads();
     uint32_t rank[PER];
+    int tk[PER];
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
       const int64_t i = c0 + (int64_t)k * NT + threadIdx.x;
+      tk[k] = 0;
       if (i < n) {
         const int t = tile_key(r[k].v[0], r[k].v[1], r[k].v[2], ba.g);
+        tk[k] = t;
         key[k] = t >> bshift;
         if (lds_tiles) atomicAdd(&ltile[t], 1u);
         else atomicAdd(&ba.tcount[t], 1u);
@@ -572,14 +585,32 @@ __global__ void __launch_bounds__(NT) k_bucket_pass(const uint32_t* __restrict__
         const uint32_t slot = lstart[key[k]] + rank[k];
         stage[slot] = r[k];
         skey[slot] = (uint16_t)key[k];
+        if (ba.pack) stile[slot] = (uint16_t)tk[k];
       }
     __syncthreads();
     const int cnt = (int)min((int64_t)CH, n - c0);
-    for (int j = threadIdx.x; j < cnt; j += NT) {
-      const int b = skey[j];
-      const uint32_t q = (uint32_t)j - lstart[b];
-      if (q < nin[b]) region[(int64_t)b * ba.cap + gbase[b] + q] = stage[j];
-      else ovf_out[obase[b] + (q - nin[b])] = stage[j];
+    if (RS == 3 && ba.pack) {
+      for (int j = threadIdx.x; j < cnt; j += NT) {
+        const int b = skey[j];
+        const uint32_t q = (uint32_t)j - lstart[b];
+        const uint64_t v = pack_rec(*reinterpret_cast<const Rec<3>*>(&stage[j]), ba.g.shift);
+        if (q < nin[b]) {
+          const int64_t o = (int64_t)b * ba.cap + gbase[b] + q;
+          reinterpret_cast<uint64_t*>(region)[o] = v;
+          ba.rkey[o] = stile[j];
+        } else {
+          const int64_t o = obase[b] + (q - nin[b]);
+          reinterpret_cast<uint64_t*>(ovf_out)[o] = v;
+          ba.okey[o] = stile[j];
+        }
+      }
+    } else {
+      for (int j = threadIdx.x; j < cnt; j += NT) {
+        const int b = skey[j];
+        const uint32_t q = (uint32_t)j - lstart[b];
+        if (q < nin[b]) region[(int64_t)b * ba.cap + gbase[b] + q] = stage[j];
+        else ovf_out[obase[b] + (q - nin[b])] = stage[j];
+      }
     }
   }
   // catalog-sum partial of the workgroup (fixed-order reduction)
@@ -678,6 +709,85 @@ __global__ void __launch_bounds__(NT) k_tile_pass(const Rec<RS>* __restrict__ re
   for (int j = threadIdx.x; j < cnt; j += NT) {
     const int kk = skey[j];
     put_rec(rout, gbase[kk] + (j - lstart[kk]), stage[j], pack, g.shift);
+  }
+}
+
+// k_tile_pass over records the bucket pass wrote packed (pack_rec + 16-bit tile
+// index, for the FP32 painter): the tile index comes from its own array and the
+// packed records are moved as they are
+template <int PER, int NT>
+__global__ void __launch_bounds__(NT) k_tile_pass_packed(const uint64_t* __restrict__ region,
+                                                         const uint16_t* __restrict__ rkey,
+                                                         const uint64_t* __restrict__ ovf_in,
+                                                         const uint16_t* __restrict__ okey,
+                                                         const uint32_t* __restrict__ bcnt,
+                                                         const uint32_t* __restrict__ ovf, uint32_t cap,
+                                                         int chunks_per_bucket, int nbuckets, TileGeom g,
+                                                         uint32_t* __restrict__ cursor, uint64_t* __restrict__ rout) {
+  constexpr int CH = NT * PER;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int bshift = 3 * g.ls;
+  const int R = 1 << bshift;
+  const int nreg = nbuckets * chunks_per_bucket;
+  if ((int)blockIdx.x >= nreg) {
+    const uint32_t no = *ovf;
+    for (int64_t c0 = (int64_t)(blockIdx.x - nreg) * CH; c0 < no; c0 += (int64_t)(gridDim.x - nreg) * CH) {
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        const int64_t i = c0 + (int64_t)k * NT + threadIdx.x;
+        if (i < no) rout[atomicAdd(&cursor[okey[i]], 1u)] = ovf_in[i];
+      }
+    }
+    return;
+  }
+  const int b = blockIdx.x / chunks_per_bucket, jc = blockIdx.x - b * chunks_per_bucket;
+  const uint32_t nb_ = min(bcnt[b], cap);
+  const int64_t c0 = (int64_t)jc * CH;
+  if (c0 >= nb_) return;
+  const int cnt = (int)min((int64_t)CH, (int64_t)nb_ - c0);
+  const uint64_t* rin = region + (int64_t)b * cap + c0;
+  const uint16_t* kin = rkey + (int64_t)b * cap + c0;
+  uint64_t* stage = reinterpret_cast<uint64_t*>(smem_raw);                  // [CH]
+  uint16_t* skey = reinterpret_cast<uint16_t*>(smem_raw + (size_t)CH * 8);  // [CH]
+  uint32_t* hist = reinterpret_cast<uint32_t*>(smem_raw + (size_t)CH * 10);
+  uint32_t* lstart = hist + R;
+  uint32_t* gbase = lstart + R;
+  uint32_t* wsum = gbase + R;  // 16 slots
+  const int klo = b << bshift;
+  uint64_t r[PER];
+  int key[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int ii = min(k * NT + (int)threadIdx.x, cnt - 1);
+    r[k] = rin[ii];
+    key[k] = (int)kin[ii];
+  }
+#pragma unroll
+  for (int k = 0; k < PER; ++k) key[k] = k * NT + (int)threadIdx.x < cnt ? key[k] - klo : -1;
+  for (int t = threadIdx.x; t < R; t += NT) hist[t] = 0u;
+  __syncthreads();
+  uint32_t rank[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k)
+    if (key[k] >= 0) rank[k] = atomicAdd(&hist[key[k]], 1u);
+  __syncthreads();
+  block_exclusive_scan<NT>(hist, R, wsum, [&](int t, uint32_t v) {
+    lstart[t] = v;
+    const uint32_t c = hist[t];
+    gbase[t] = c ? atomicAdd(&cursor[klo + t], c) : 0u;
+  });
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < PER; ++k)
+    if (key[k] >= 0) {
+      const uint32_t slot = lstart[key[k]] + rank[k];
+      stage[slot] = r[k];
+      skey[slot] = (uint16_t)key[k];
+    }
+  __syncthreads();
+  for (int j = threadIdx.x; j < cnt; j += NT) {
+    const int kk = skey[j];
+    rout[gbase[kk] + (j - lstart[kk])] = stage[j];
   }
 }
 
@@ -1513,10 +1623,15 @@ static cnpc_status fused_sort_and_paint(const cnpc_mesh_desc* d, const uint32_t*
   const int lm = split_sums ? 0 : (sums_lmax >= 4 ? 4 : (sums_lmax >= 2 ? 2 : 0));
   BucketShape bs = bucket_shape(RS, lm);
   const int ltiles = L.ntiles <= LDS_TILES_MAX ? L.ntiles : 0;
-  size_t lds = bucket_pass_lds(bs.per, RS, L.nbuckets, bs.nt, ltiles);
+  const bool pack = packs_records(sizeof(T) == 4, RS, g.shift);  // records of the FP32 painter
+  const bool packb = pack && L.ntiles <= 65536;                  // bucket records packed too
+  auto blds = [&](const BucketShape& b) {
+    return bucket_pass_lds(b.per, RS, L.nbuckets, b.nt, ltiles) + (packb ? (size_t)b.nt * b.per * 2 : 0);
+  };
+  size_t lds = blds(bs);
   if (bs.per == 8 && lds > lds_limit()) {  // many buckets (N >= 1024): 4 per thread
     bs = {BUCKET_NT, 4, false, BUCKET_BLOCKS_MAX};
-    lds = bucket_pass_lds(bs.per, RS, L.nbuckets, bs.nt, ltiles);
+    lds = blds(bs);
   }
   const int64_t ch = (int64_t)bs.nt * bs.per;
   const unsigned nblk = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + ch - 1) / ch, bs.maxblk));
@@ -1541,6 +1656,9 @@ static cnpc_status fused_sort_and_paint(const cnpc_mesh_desc* d, const uint32_t*
   ba.ovf = bcnt + L.nbuckets;
   ba.tcount = count;
   ba.partial = partial;
+  ba.pack = packb;
+  ba.rkey = reinterpret_cast<uint16_t*>(reinterpret_cast<uint64_t*>(region) + (int64_t)L.nbuckets * cap);
+  ba.okey = reinterpret_cast<uint16_t*>(reinterpret_cast<uint64_t*>(ovf_rec) + n);
   kt_begin(CNPC_KT_SORT, s);
   if (lm == 4) launch_bucket_pass<RS, 4>(bs, nblk, lds, pos, w, n, sa, ba, region, ovf_rec, s);
   else if (lm == 2) launch_bucket_pass<RS, 2>(bs, nblk, lds, pos, w, n, sa, ba, region, ovf_rec, s);
@@ -1568,10 +1686,27 @@ static cnpc_status fused_sort_and_paint(const cnpc_mesh_desc* d, const uint32_t*
   }
   const int64_t tch = (int64_t)1024 * tper;
   const int cpb = (int)((cap + tch - 1) / tch);
-  const bool pack = packs_records(sizeof(T) == 4, RS, g.shift);  // records of the FP32 painter
   const unsigned tgrid = (unsigned)(L.nbuckets * cpb + OVF_BLOCKS);
   const size_t tlds = partition_lds(tper, RS, per_bucket, 1024);
   kt_begin(CNPC_KT_SORT, s);
+  if (packb) {
+    const size_t plds = (size_t)1024 * tper * 10 + (size_t)3 * per_bucket * 4 + 64;
+    const uint64_t* r64 = reinterpret_cast<const uint64_t*>(region);
+    const uint64_t* o64 = reinterpret_cast<const uint64_t*>(ovf_rec);
+    uint64_t* out64 = reinterpret_cast<uint64_t*>(rec);
+    if (tper == 4)
+      hipLaunchKernelGGL((k_tile_pass_packed<4, 1024>), dim3(tgrid), dim3(1024), plds, s, r64, ba.rkey, o64, ba.okey,
+                         bcnt, bcnt + L.nbuckets, cap, cpb, L.nbuckets, g, cursor, out64);
+    else if (tper == 2)
+      hipLaunchKernelGGL((k_tile_pass_packed<2, 1024>), dim3(tgrid), dim3(1024), plds, s, r64, ba.rkey, o64, ba.okey,
+                         bcnt, bcnt + L.nbuckets, cap, cpb, L.nbuckets, g, cursor, out64);
+    else
+      hipLaunchKernelGGL((k_tile_pass_packed<1, 1024>), dim3(tgrid), dim3(1024), plds, s, r64, ba.rkey, o64, ba.okey,
+                         bcnt, bcnt + L.nbuckets, cap, cpb, L.nbuckets, g, cursor, out64);
+    kt_end(CNPC_KT_SORT, s);
+    CNPC_HIP(hipGetLastError());
+    return paint_sorted<T, RS>(d, weighted, set0, ws, L, s);
+  }
   if (tper == 4)
     hipLaunchKernelGGL((k_tile_pass<RS, 4, 1024>), dim3(tgrid), dim3(1024), tlds, s, region, ovf_rec, bcnt,
                        bcnt + L.nbuckets, cap, cpb, L.nbuckets, g, cursor, rec, pack);
